@@ -1,0 +1,165 @@
+"""Float64 CPU oracle for the straightest-geodesic exponential map.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the GPU library never does.  The
+tracer is plain C (sg_oracle.c) following the paper's extrinsic algorithms
+(geodesic_step, transport_over_edge, transport_over_vertex, Alg. gpu_parallel)
+and its two backward schemes (eq. proxy_func, eqs. jv/jp).  This module only
+marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+RAY_OK, RAY_MAXSTEPS, RAY_BOUNDARY, RAY_BADINPUT = 0, 1, 2, 3
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        P = C.c_void_p
+        L.or_mesh_build.argtypes = [P, C.c_int64, P, C.c_int64, C.POINTER(C.c_void_p)]
+        L.or_mesh_build.restype = C.c_int
+        L.or_mesh_free.argtypes = [P]
+        L.or_mesh_mean_edge.argtypes = [P]
+        L.or_mesh_mean_edge.restype = C.c_double
+        L.or_mesh_theta.argtypes = [P, P]
+        L.or_last_error.restype = C.c_char_p
+        L.or_exp_batch.argtypes = [P, C.c_int64, P, P, P, C.c_int32, P, P] + [P] * 11 + [C.c_int32]
+        L.or_exp_batch.restype = C.c_int
+        L.or_exp_trace.argtypes = [P, C.c_int32, P, P, P, C.c_int32] + [P] * 8
+        L.or_exp_trace.restype = C.c_int32
+        L.or_ep_batch.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, C.c_int32]
+        L.or_ep_batch.restype = C.c_int
+        L.or_gfd_batch.argtypes = [P, C.c_int64, P, P, P, P, C.c_double, C.c_double, P, P, P, P, P, C.c_int32]
+        L.or_gfd_batch.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class Opts(C.Structure):
+    _fields_ = [("max_steps", C.c_int32), ("vertex_snap", C.c_double)]
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"oracle error {code}: {msg}")
+        self.code = code
+
+
+class Mesh:
+    """Oracle mesh built from the canonical float32 (X, F)."""
+
+    def __init__(self, X, F):
+        L = lib()
+        self.X = np.ascontiguousarray(X, dtype=np.float32)
+        self.F = np.ascontiguousarray(F, dtype=np.int32)
+        h = C.c_void_p()
+        rc = L.or_mesh_build(_p(self.X), self.X.shape[0], _p(self.F), self.F.shape[0], C.byref(h))
+        if rc != 0:
+            raise OracleError(rc, L.or_last_error().decode())
+        self._h = h
+        self.nv, self.nf = self.X.shape[0], self.F.shape[0]
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().or_mesh_free(self._h)
+            self._h = None
+
+    @property
+    def mean_edge(self):
+        return lib().or_mesh_mean_edge(self._h)
+
+    def theta(self):
+        t = np.zeros(self.nv)
+        lib().or_mesh_theta(self._h, _p(t))
+        return t
+
+    @staticmethod
+    def opts(max_steps=1 << 20, vertex_snap=1e-10):
+        return Opts(max_steps, vertex_snap)
+
+    def exp(self, f, b, v, W=None, max_steps=1 << 20, vertex_snap=1e-10, nthreads=0):
+        f = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
+        n = f.shape[0]
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(n, 3)
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(n, 3)
+        if W is None:
+            W = np.zeros((n, 0, 3))
+        W = np.ascontiguousarray(W, dtype=np.float64).reshape(n, -1, 3)
+        K = W.shape[1]
+        out = dict(
+            f=np.zeros(n, np.int32), b=np.zeros((n, 3)), p=np.zeros((n, 3)), v=np.zeros((n, 3)),
+            W=np.zeros((n, K, 3)), status=np.zeros(n, np.int32), n_cross=np.zeros(n, np.int32),
+            hash=np.zeros(n, np.uint64), min_vdist=np.zeros(n), traced=np.zeros(n),
+            sigma=np.zeros(n, np.int8))
+        o = Opts(max_steps, vertex_snap)
+        rc = lib().or_exp_batch(
+            self._h, n, _p(f), _p(b), _p(v), K, _p(W) if K else None, C.byref(o),
+            _p(out["f"]), _p(out["b"]), _p(out["p"]), _p(out["v"]), _p(out["W"]) if K else None,
+            _p(out["status"]), _p(out["n_cross"]), _p(out["hash"]), _p(out["min_vdist"]),
+            _p(out["traced"]), _p(out["sigma"]), nthreads)
+        if rc != 0:
+            raise OracleError(rc, lib().or_last_error().decode())
+        return out
+
+    def trace(self, f, b, v, cap=100000, max_steps=1 << 20, vertex_snap=1e-10):
+        kind = np.zeros(cap, np.int8)
+        face = np.zeros(cap, np.int32)
+        e0 = np.zeros(cap, np.int32)
+        e1 = np.zeros(cap, np.int32)
+        pt = np.zeros((cap, 3))
+        fo = C.c_int32()
+        st = C.c_int32()
+        po = np.zeros(3)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        o = Opts(max_steps, vertex_snap)
+        k = lib().or_exp_trace(self._h, int(f), _p(b), _p(v), C.byref(o), cap, _p(kind), _p(face),
+                               _p(e0), _p(e1), _p(pt), C.byref(fo), _p(po), C.byref(st))
+        return dict(kind=kind[:k], face=face[:k], e0=e0[:k], e1=e1[:k], point=pt[:k],
+                    f=fo.value, p=po, status=st.value)
+
+    def ep(self, f, b, v, g, max_steps=1 << 20, vertex_snap=1e-10, nthreads=0):
+        f = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
+        n = f.shape[0]
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(n, 3)
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(n, 3)
+        g = np.ascontiguousarray(g, dtype=np.float64).reshape(n, 3)
+        gv = np.zeros((n, 3))
+        gb = np.zeros((n, 3))
+        o = Opts(max_steps, vertex_snap)
+        rc = lib().or_ep_batch(self._h, n, _p(f), _p(b), _p(v), C.byref(o), _p(g), _p(gv), _p(gb), nthreads)
+        if rc != 0:
+            raise OracleError(rc, lib().or_last_error().decode())
+        return gv, gb
+
+    def gfd(self, f, b, v, g, eps_v, eps_p, max_steps=1 << 20, vertex_snap=1e-10, nthreads=0):
+        f = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
+        n = f.shape[0]
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(n, 3)
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(n, 3)
+        g = np.ascontiguousarray(g, dtype=np.float64).reshape(n, 3)
+        gv = np.zeros((n, 3))
+        gb = np.zeros((n, 3))
+        Jv = np.zeros((n, 2, 2))
+        Jp = np.zeros((n, 2, 2))
+        o = Opts(max_steps, vertex_snap)
+        rc = lib().or_gfd_batch(self._h, n, _p(f), _p(b), _p(v), C.byref(o), float(eps_v), float(eps_p),
+                                _p(g), _p(gv), _p(gb), _p(Jv), _p(Jp), nthreads)
+        if rc != 0:
+            raise OracleError(rc, lib().or_last_error().decode())
+        return dict(grad_v=gv, grad_b=gb, Jv=Jv, Jp=Jp)

@@ -1,0 +1,774 @@
+/*
+ * sg_oracle.c -- float64 CPU oracle for straightest geodesics on triangle meshes.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the GPU library.  It shares no code
+ * with the GPU path.
+ *
+ * What it follows (Verninas et al., "Parallelised Differentiable Straightest
+ * Geodesics for 3D Meshes"):
+ *   - Sec. 4 "Straightest geodesics": a point is (face, barycentric); the
+ *     straightest rule keeps equal left/right angles, total angle 2 pi on faces
+ *     and edges and theta(x) = sum of corner angles at a vertex.
+ *   - Appendix, algorithm geodesic_step: barycentric rate of the direction,
+ *     exit parameter lambda = min{-b_i / b^v_i > 0}, advance.
+ *   - Appendix, algorithm transport_over_edge: rotate the direction about the
+ *     shared edge so that the two faces are unfolded into one plane (written
+ *     orientation-free, so meshes need not be orientable; Sec. "Main
+ *     differences with SotA implementation").
+ *   - Appendix, algorithm transport_over_vertex: walk the fan around the vertex
+ *     accumulating corner angles from the reversed incoming direction until half
+ *     of theta(x) is reached; leave along the fan edge rotated by the residual.
+ *   - Sec. 4 "Parallel Transport": a transported vector keeps its angle to the
+ *     geodesic tangent; across an edge it is rotated with the unfolding.
+ *   - Alg. gpu_parallel: loop until the traced length reaches |v| or MAX_STEPS.
+ *   - Eq. proxy_func (extrinsic proxy) and eqs. jv, jp (geodesic finite
+ *     differences) for the backward.
+ * Readings where the paper is silent or garbled:
+ *   - the exact tests b_k = 1 / b_k = 0 of geodesic_step are replaced by
+ *     classifying exits by the sign of the barycentric rate, and a vertex is
+ *     passed when the exit point lies within `vertex_snap` (edge-parameter
+ *     units) of an edge endpoint;
+ *   - the last in-face step is clamped to the remaining length;
+ *   - v is first projected onto the start face's plane (initialise_trace);
+ *   - the outgoing direction at a vertex is the fan edge rotated inside its face
+ *     by the residual angle (the vector rotation printed in
+ *     transport_over_vertex is garbled);
+ *   - extra vectors keep their signed angle to the tangent through a vertex;
+ *   - the proxy's rotation is R = M_{p'} M_p^T (frame axes as columns), so that
+ *     R^T carries the upstream gradient back from p' to p;
+ *   - the tracer stops at a boundary edge or boundary vertex (Sec. 4, original
+ *     behaviour); the hole-avoiding variant is not modelled.
+ */
+#define _GNU_SOURCE
+#include "sg_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+struct or_mesh {
+    int64_t nv, nf;
+    double* X;      /* nv*3, exact upcast of the float32 mesh */
+    int32_t* F;     /* nf*3 */
+    double* N;      /* nf*3 unit face normals (x1-x0) x (x2-x0) */
+    int64_t* nbr;   /* nf*3: face across local edge k = (F[k], F[k+1]), or -1 */
+    int8_t* nbr_k;  /* nf*3: local index of that edge in the neighbour */
+    double* theta;  /* nv: total angle */
+    uint8_t* vbnd;  /* nv: vertex lies on a boundary edge */
+    double mean_edge;
+};
+
+static __thread char g_err[256];
+static void set_err(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+const char* or_last_error(void) { return g_err; }
+
+/* ---------------------------------------------------------------- vectors */
+static inline double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static inline void sub3(const double* a, const double* b, double* r) { r[0] = a[0] - b[0]; r[1] = a[1] - b[1]; r[2] = a[2] - b[2]; }
+static inline void cross3(const double* a, const double* b, double* r) {
+    double x = a[1] * b[2] - a[2] * b[1], y = a[2] * b[0] - a[0] * b[2], z = a[0] * b[1] - a[1] * b[0];
+    r[0] = x; r[1] = y; r[2] = z;
+}
+static inline double norm3(const double* a) { return sqrt(dot3(a, a)); }
+static inline void scale3(double* a, double s) { a[0] *= s; a[1] *= s; a[2] *= s; }
+static inline void unit3(double* a) { scale3(a, 1.0 / norm3(a)); }
+/* component of a orthogonal to the unit vector u */
+static inline void perp3(const double* a, const double* u, double* r) {
+    double t = dot3(a, u);
+    r[0] = a[0] - t * u[0]; r[1] = a[1] - t * u[1]; r[2] = a[2] - t * u[2];
+}
+static inline double angle3(const double* a, const double* c) {
+    double x[3];
+    cross3(a, c, x);
+    return atan2(norm3(x), dot3(a, c));
+}
+static inline const double* VX(const or_mesh* m, int64_t v) { return m->X + 3 * v; }
+static inline const double* FX(const or_mesh* m, int64_t f, int k) { return m->X + 3 * (int64_t)m->F[3 * f + k]; }
+
+/* ------------------------------------------------------------ mesh build */
+typedef struct { int32_t lo, hi; int64_t he; } edge_rec;
+static int edge_cmp(const void* a, const void* b) {
+    const edge_rec* x = a; const edge_rec* y = b;
+    if (x->lo != y->lo) return x->lo < y->lo ? -1 : 1;
+    if (x->hi != y->hi) return x->hi < y->hi ? -1 : 1;
+    return x->he < y->he ? -1 : (x->he > y->he);
+}
+
+void or_mesh_free(or_mesh* m) {
+    if (!m) return;
+    free(m->X); free(m->F); free(m->N); free(m->nbr); free(m->nbr_k); free(m->theta); free(m->vbnd);
+    free(m);
+}
+
+int or_mesh_build(const float* X, int64_t nv, const int32_t* F, int64_t nf, or_mesh** out) {
+    *out = NULL;
+    if (!X || !F || nv <= 0 || nf <= 0) { set_err("empty mesh"); return OR_E_ARG; }
+    or_mesh* m = calloc(1, sizeof *m);
+    if (!m) return OR_E_OOM;
+    m->nv = nv; m->nf = nf;
+    m->X = malloc(sizeof(double) * 3 * nv);
+    m->F = malloc(sizeof(int32_t) * 3 * nf);
+    m->N = malloc(sizeof(double) * 3 * nf);
+    m->nbr = malloc(sizeof(int64_t) * 3 * nf);
+    m->nbr_k = malloc(sizeof(int8_t) * 3 * nf);
+    m->theta = calloc(nv, sizeof(double));
+    m->vbnd = calloc(nv, 1);
+    edge_rec* E = malloc(sizeof(edge_rec) * 3 * nf);
+    if (!m->X || !m->F || !m->N || !m->nbr || !m->nbr_k || !m->theta || !m->vbnd || !E) {
+        free(E); or_mesh_free(m); return OR_E_OOM;
+    }
+    for (int64_t i = 0; i < 3 * nv; i++) {
+        if (!isfinite(X[i])) { set_err("non-finite vertex coordinate"); free(E); or_mesh_free(m); return OR_E_ARG; }
+        m->X[i] = (double)X[i];
+    }
+    for (int64_t f = 0; f < nf; f++) {
+        for (int k = 0; k < 3; k++) {
+            int32_t v = F[3 * f + k];
+            if (v < 0 || v >= nv) { set_err("face %lld: vertex index out of range", (long long)f); free(E); or_mesh_free(m); return OR_E_ARG; }
+            m->F[3 * f + k] = v;
+        }
+        const int32_t* t = m->F + 3 * f;
+        if (t[0] == t[1] || t[1] == t[2] || t[0] == t[2]) { set_err("face %lld repeats a vertex", (long long)f); free(E); or_mesh_free(m); return OR_E_DEGENERATE; }
+        double e1[3], e2[3], n[3];
+        sub3(FX(m, f, 1), FX(m, f, 0), e1);
+        sub3(FX(m, f, 2), FX(m, f, 0), e2);
+        cross3(e1, e2, n);
+        double a = norm3(n);
+        if (!(a > 0.0)) { set_err("face %lld has zero area", (long long)f); free(E); or_mesh_free(m); return OR_E_DEGENERATE; }
+        scale3(n, 1.0 / a);
+        memcpy(m->N + 3 * f, n, sizeof n);
+        for (int k = 0; k < 3; k++) {
+            int32_t a0 = t[k], a1 = t[(k + 1) % 3];
+            E[3 * f + k].lo = a0 < a1 ? a0 : a1;
+            E[3 * f + k].hi = a0 < a1 ? a1 : a0;
+            E[3 * f + k].he = 3 * f + k;
+            /* corner angle at t[k] */
+            double p[3], q[3];
+            sub3(FX(m, f, (k + 1) % 3), FX(m, f, k), p);
+            sub3(FX(m, f, (k + 2) % 3), FX(m, f, k), q);
+            m->theta[t[k]] += angle3(p, q);
+        }
+    }
+    qsort(E, 3 * nf, sizeof(edge_rec), edge_cmp);
+    double esum = 0.0;
+    int64_t ecount = 0;
+    for (int64_t s = 0; s < 3 * nf;) {
+        int64_t e = s + 1;
+        while (e < 3 * nf && E[e].lo == E[s].lo && E[e].hi == E[s].hi) e++;
+        int64_t cnt = e - s;
+        double d[3];
+        sub3(VX(m, E[s].hi), VX(m, E[s].lo), d);
+        esum += norm3(d);
+        ecount++;
+        if (cnt > 2) { set_err("edge (%d,%d) has %lld faces", E[s].lo, E[s].hi, (long long)cnt); free(E); or_mesh_free(m); return OR_E_NONMANIFOLD; }
+        if (cnt == 1) {
+            m->nbr[E[s].he] = -1; m->nbr_k[E[s].he] = -1;
+            m->vbnd[E[s].lo] = 1; m->vbnd[E[s].hi] = 1;
+        } else {
+            int64_t h0 = E[s].he, h1 = E[s + 1].he;
+            if (h0 / 3 == h1 / 3) { set_err("face %lld uses an edge twice", (long long)(h0 / 3)); free(E); or_mesh_free(m); return OR_E_DEGENERATE; }
+            m->nbr[h0] = h1 / 3; m->nbr_k[h0] = (int8_t)(h1 % 3);
+            m->nbr[h1] = h0 / 3; m->nbr_k[h1] = (int8_t)(h0 % 3);
+        }
+        s = e;
+    }
+    free(E);
+    m->mean_edge = esum / (double)ecount;
+
+    /* every vertex fan must be a single connected fan (manifold condition) */
+    int64_t* start = calloc(nv + 1, sizeof(int64_t));
+    int64_t* inc = malloc(sizeof(int64_t) * 3 * nf);
+    uint8_t* seen = calloc(nf, 1);
+    int64_t* stack = malloc(sizeof(int64_t) * 3 * nf);
+    if (!start || !inc || !seen || !stack) { free(start); free(inc); free(seen); free(stack); or_mesh_free(m); return OR_E_OOM; }
+    for (int64_t i = 0; i < 3 * nf; i++) start[m->F[i] + 1]++;
+    for (int64_t v = 0; v < nv; v++) start[v + 1] += start[v];
+    int64_t* fill = malloc(sizeof(int64_t) * (nv + 1));
+    memcpy(fill, start, sizeof(int64_t) * (nv + 1));
+    for (int64_t i = 0; i < 3 * nf; i++) inc[fill[m->F[i]]++] = i / 3;
+    free(fill);
+    int rc = OR_OK;
+    for (int64_t v = 0; v < nv && rc == OR_OK; v++) {
+        int64_t deg = start[v + 1] - start[v];
+        if (deg == 0) continue;
+        int64_t sp = 0, visited = 0;
+        stack[sp++] = inc[start[v]];
+        seen[inc[start[v]]] = 1;
+        while (sp) {
+            int64_t f = stack[--sp];
+            visited++;
+            for (int k = 0; k < 3; k++) {
+                if (m->F[3 * f + k] != v && m->F[3 * f + (k + 1) % 3] != v) continue;
+                int64_t g = m->nbr[3 * f + k];
+                if (g >= 0 && !seen[g]) { seen[g] = 1; stack[sp++] = g; }
+            }
+        }
+        if (visited != deg) { set_err("vertex %lld: faces do not form one fan", (long long)v); rc = OR_E_NONMANIFOLD; }
+        for (int64_t i = start[v]; i < start[v + 1]; i++) seen[inc[i]] = 0;
+    }
+    free(start); free(inc); free(seen); free(stack);
+    if (rc != OR_OK) { or_mesh_free(m); return rc; }
+    *out = m;
+    return OR_OK;
+}
+
+double or_mesh_mean_edge(const or_mesh* m) { return m->mean_edge; }
+void or_mesh_theta(const or_mesh* m, double* theta) { memcpy(theta, m->theta, sizeof(double) * m->nv); }
+
+/* ------------------------------------------------------------ tracing */
+typedef struct {
+    int32_t cap, n;
+    int8_t* kind; int32_t* face; int32_t* ev0; int32_t* ev1; double* pt;
+} trace_buf;
+
+typedef struct {
+    int32_t f, status, n_cross;
+    double b[3], p[3], v[3];
+    uint64_t hash;
+    double min_vdist, traced;
+    int8_t sigma;
+    double d0[3], L;          /* start tangent (unit) and length, for the backward */
+} ray_out;
+
+static inline uint64_t fnv_face(uint64_t h, int32_t f) {
+    uint32_t u = (uint32_t)f;
+    for (int i = 0; i < 4; i++) { h ^= (u >> (8 * i)) & 0xffu; h *= 1099511628211ull; }
+    return h;
+}
+
+static inline void bary_pos(const or_mesh* m, int64_t f, const double* b, double* p) {
+    const double *x0 = FX(m, f, 0), *x1 = FX(m, f, 1), *x2 = FX(m, f, 2);
+    for (int c = 0; c < 3; c++) p[c] = b[0] * x0[c] + b[1] * x1[c] + b[2] * x2[c];
+}
+
+/* barycentric representation of a tangent vector d in face f (rates sum to 0) */
+static void bary_rate(const or_mesh* m, int64_t f, const double* d, double* bd) {
+    double e1[3], e2[3];
+    sub3(FX(m, f, 1), FX(m, f, 0), e1);
+    sub3(FX(m, f, 2), FX(m, f, 0), e2);
+    double g11 = dot3(e1, e1), g12 = dot3(e1, e2), g22 = dot3(e2, e2);
+    double r1 = dot3(d, e1), r2 = dot3(d, e2);
+    double det = g11 * g22 - g12 * g12;
+    bd[1] = (g22 * r1 - g12 * r2) / det;
+    bd[2] = (g11 * r2 - g12 * r1) / det;
+    bd[0] = -bd[1] - bd[2];
+}
+
+static void clamp_renorm(double* b) {
+    for (int k = 0; k < 3; k++) if (b[k] < 0.0) b[k] = 0.0;
+    double s = b[0] + b[1] + b[2];
+    b[0] /= s; b[1] /= s; b[2] /= s;
+}
+
+static double seg_point_dist(const double* a, const double* c, const double* x) {
+    double ac[3], ax[3];
+    sub3(c, a, ac);
+    sub3(x, a, ax);
+    double l2 = dot3(ac, ac);
+    double t = l2 > 0 ? dot3(ax, ac) / l2 : 0.0;
+    if (t < 0) t = 0;
+    if (t > 1) t = 1;
+    double q[3] = {a[0] + t * ac[0] - x[0], a[1] + t * ac[1] - x[1], a[2] + t * ac[2] - x[2]};
+    return norm3(q);
+}
+
+static void seg_update(const or_mesh* m, int64_t f, const double* a, const double* c, double* best) {
+    for (int k = 0; k < 3; k++) {
+        double d = seg_point_dist(a, c, FX(m, f, k));
+        if (d < *best) *best = d;
+    }
+}
+
+static int local_index(const or_mesh* m, int64_t f, int32_t v) {
+    for (int k = 0; k < 3; k++) if (m->F[3 * f + k] == v) return k;
+    return -1;
+}
+
+static void trace_push(trace_buf* tb, int8_t kind, int32_t face, int32_t v0, int32_t v1, const double* p) {
+    if (!tb || tb->n >= tb->cap) return;
+    int i = tb->n++;
+    tb->kind[i] = kind; tb->face[i] = face; tb->ev0[i] = v0; tb->ev1[i] = v1;
+    memcpy(tb->pt + 3 * i, p, 3 * sizeof(double));
+}
+
+/* One exponential map.  K extra vectors W (K*3) are transported into Wout. */
+static void exp_one(const or_mesh* m, int32_t f0, const double* b0, const double* v0, int K,
+                    const double* W0, const or_opts* o, ray_out* out, double* Wout, trace_buf* tb) {
+    memset(out, 0, sizeof *out);
+    out->f = f0;
+    out->sigma = 1;
+    out->min_vdist = INFINITY;
+    out->hash = 14695981039346656037ull;
+    double wn[64];
+    double snap = o ? o->vertex_snap : 1e-10;
+    int32_t max_steps = o ? o->max_steps : (1 << 20);
+
+    int bad = (f0 < 0 || f0 >= m->nf);
+    double b[3] = {0, 0, 0};
+    if (!bad) {
+        double s = 0.0;
+        for (int k = 0; k < 3; k++) {
+            b[k] = b0[k];
+            if (!isfinite(b[k]) || b[k] < 0.0) bad = 1;
+            s += b[k];
+        }
+        if (!(s > 0.0) || !isfinite(s)) bad = 1;
+        else for (int k = 0; k < 3; k++) b[k] /= s;
+        for (int c = 0; c < 3; c++) if (!isfinite(v0[c])) bad = 1;
+        for (int i = 0; i < 3 * K; i++) if (!isfinite(W0[i])) bad = 1;
+    }
+    if (bad || K > 64) {
+        out->status = OR_RAY_BADINPUT;
+        for (int k = 0; k < 3; k++) { out->b[k] = b0[k]; out->p[k] = NAN; out->v[k] = NAN; }
+        for (int i = 0; i < 3 * K; i++) Wout[i] = NAN;
+        return;
+    }
+    int64_t f = f0;
+    const double* n = m->N + 3 * f;
+    double d[3];
+    perp3(v0, n, d);
+    double L = norm3(d);
+    for (int k = 0; k < K; k++) {
+        perp3(W0 + 3 * k, n, Wout + 3 * k);
+        wn[k] = norm3(Wout + 3 * k);
+    }
+    out->hash = fnv_face(out->hash, (int32_t)f);
+    if (!(L > 0.0)) {
+        memcpy(out->b, b, sizeof b);
+        bary_pos(m, f, b, out->p);
+        out->L = 0.0;
+        return;
+    }
+    scale3(d, 1.0 / L);
+    memcpy(out->d0, d, sizeof d);
+    out->L = L;
+
+    int atv = -1, skip = -1, sigma = 1;
+    int nz = (b[0] == 0.0) + (b[1] == 0.0) + (b[2] == 0.0);
+    double bd[3];
+    if (nz == 2) {
+        atv = b[0] != 0.0 ? 0 : (b[1] != 0.0 ? 1 : 2);
+        bary_rate(m, f, d, bd);
+        for (int k = 0; k < 3; k++)
+            if (k != atv && bd[k] < 0.0) {   /* direction leaves the given face's corner */
+                out->status = OR_RAY_BADINPUT;
+                memcpy(out->b, b, sizeof b);
+                bary_pos(m, f, b, out->p);
+                return;
+            }
+    }
+    double rem = L, traced = 0.0;
+    int32_t steps = 0;
+    double p_prev[3], p_new[3];
+    int status = OR_RAY_OK;
+    for (;;) {
+        bary_rate(m, f, d, bd);
+        int ks = -1;
+        double ts = INFINITY;
+        if (atv >= 0) {
+            if (bd[atv] < 0.0) { ks = atv; ts = b[atv] / -bd[atv]; }
+        } else {
+            for (int k = 0; k < 3; k++) {
+                if (k == skip || !(bd[k] < 0.0)) continue;
+                double t = b[k] / -bd[k];
+                if (t < ts) { ts = t; ks = k; }
+            }
+        }
+        bary_pos(m, f, b, p_prev);
+        if (ks < 0) { status = OR_RAY_BADINPUT; break; }
+        if (rem <= ts) {
+            for (int k = 0; k < 3; k++) b[k] += rem * bd[k];
+            clamp_renorm(b);
+            traced += rem;
+            bary_pos(m, f, b, p_new);
+            seg_update(m, f, p_prev, p_new, &out->min_vdist);
+            rem = 0.0;
+            break;
+        }
+        if (steps >= max_steps) { status = OR_RAY_MAXSTEPS; break; }
+        for (int k = 0; k < 3; k++) b[k] += ts * bd[k];
+        b[ks] = 0.0;
+        clamp_renorm(b);
+        rem -= ts;
+        traced += ts;
+        steps++;
+        bary_pos(m, f, b, p_new);
+        seg_update(m, f, p_prev, p_new, &out->min_vdist);
+        int e = (ks + 1) % 3, i = e, j = (e + 1) % 3;
+
+        int vloc = -1;
+        if (b[j] <= snap) vloc = i;
+        else if (b[i] <= snap) vloc = j;
+
+        if (vloc < 0) {
+            /* ---- transport_over_edge: unfold f' into the plane of f about the shared edge */
+            int64_t g = m->nbr[3 * f + e];
+            if (g < 0) { status = OR_RAY_BOUNDARY; break; }
+            int ge = m->nbr_k[3 * f + e];
+            const double *xi = FX(m, f, i), *xj = FX(m, f, j), *xk = FX(m, f, ks), *z = FX(m, g, (ge + 2) % 3);
+            double u[3], mf[3], mg[3], cf[3], cg[3], t1[3], t2[3];
+            sub3(xj, xi, u); unit3(u);
+            sub3(xk, xi, t1); perp3(t1, u, mf); unit3(mf);
+            sub3(z, xi, t2); perp3(t2, u, mg); unit3(mg);
+            cross3(u, mf, cf);
+            cross3(u, mg, cg);
+            /* rotation about u taking f's inward edge normal to g's outward one */
+#define QROT(w, r) do { double a_ = dot3(w, u), b_ = dot3(w, mf), c_ = dot3(w, cf); \
+            for (int q_ = 0; q_ < 3; q_++) (r)[q_] = a_ * u[q_] - b_ * mg[q_] - c_ * cg[q_]; } while (0)
+            const double* ng = m->N + 3 * g;
+            double r[3];
+            QROT(d, r);
+            perp3(r, ng, d); unit3(d);
+            for (int k = 0; k < K; k++) {
+                double* w = Wout + 3 * k;
+                QROT(w, r);
+                perp3(r, ng, w);
+                double nw = norm3(w);
+                if (nw > 0) scale3(w, wn[k] / nw);
+            }
+            QROT(m->N + 3 * f, r);
+            if (dot3(r, ng) < 0) sigma = -sigma;
+#undef QROT
+            double bg[3];
+            int32_t vi = m->F[3 * f + i];
+            if (m->F[3 * g + ge] == vi) { bg[ge] = b[i]; bg[(ge + 1) % 3] = b[j]; }
+            else { bg[ge] = b[j]; bg[(ge + 1) % 3] = b[i]; }
+            bg[(ge + 2) % 3] = 0.0;
+            trace_push(tb, 0, (int32_t)g, m->F[3 * f + i], m->F[3 * f + j], p_new);
+            f = g;
+            memcpy(b, bg, sizeof b);
+            skip = (ge + 2) % 3;
+            atv = -1;
+        } else {
+            /* ---- transport_over_vertex: fan walk to half the total angle */
+            int32_t x0id = m->F[3 * f + vloc];
+            const double* x0 = VX(m, x0id);
+            out->min_vdist = 0.0;
+            if (m->vbnd[x0id]) {
+                status = OR_RAY_BOUNDARY;
+                b[0] = b[1] = b[2] = 0.0; b[vloc] = 1.0;
+                break;
+            }
+            double nsig[3] = {sigma * m->N[3 * f], sigma * m->N[3 * f + 1], sigma * m->N[3 * f + 2]};
+            double psi[64];
+            for (int k = 0; k < K; k++) {
+                double c[3];
+                cross3(d, Wout + 3 * k, c);
+                psi[k] = atan2(dot3(c, nsig), dot3(d, Wout + 3 * k));
+            }
+            double rdir[3] = {-d[0], -d[1], -d[2]};
+            int32_t ynext = m->F[3 * f + (sigma > 0 ? (vloc + 2) % 3 : (vloc + 1) % 3)];
+            double p1[3], p2[3], ydir[3];
+            sub3(FX(m, f, (vloc + 1) % 3), x0, p1);
+            sub3(FX(m, f, (vloc + 2) % 3), x0, p2);
+            double corner = angle3(p1, p2);
+            sub3(VX(m, ynext), x0, ydir);
+            double acc = angle3(rdir, ydir);
+            if (acc > corner) acc = corner;
+            double half = 0.5 * m->theta[x0id];
+            double outd[3];
+            int64_t cur = f;
+            int sig = sigma;
+            if (acc >= half) {
+                double w[3];
+                perp3(ydir, rdir, w); unit3(w);
+                for (int c = 0; c < 3; c++) outd[c] = cos(half) * rdir[c] + sin(half) * w[c];
+            } else {
+                int guard = 0;
+                for (;;) {
+                    int e2 = -1;
+                    for (int k = 0; k < 3; k++) {
+                        int32_t a0 = m->F[3 * cur + k], a1 = m->F[3 * cur + (k + 1) % 3];
+                        if ((a0 == x0id && a1 == ynext) || (a1 == x0id && a0 == ynext)) { e2 = k; break; }
+                    }
+                    int64_t g = m->nbr[3 * cur + e2];
+                    if (g < 0 || ++guard > 4096) { status = OR_RAY_BOUNDARY; break; }
+                    int ge = m->nbr_k[3 * cur + e2];
+                    if (m->F[3 * g + ge] == m->F[3 * cur + e2]) sig = -sig;   /* orientation flips */
+                    int lx = local_index(m, g, x0id);
+                    int lz = 3 - lx - local_index(m, g, ynext);
+                    int32_t zid = m->F[3 * g + lz];
+                    double u[3], zz[3];
+                    sub3(VX(m, ynext), x0, u);
+                    sub3(VX(m, zid), x0, zz);
+                    double cg = angle3(u, zz);
+                    if (acc + cg >= half) {
+                        double beta = half - acc, w[3];
+                        unit3(u);
+                        perp3(zz, u, w); unit3(w);
+                        for (int c = 0; c < 3; c++) outd[c] = cos(beta) * u[c] + sin(beta) * w[c];
+                        cur = g;
+                        break;
+                    }
+                    acc += cg;
+                    ynext = zid;
+                    cur = g;
+                }
+                if (status != OR_RAY_OK) {
+                    b[0] = b[1] = b[2] = 0.0; b[vloc] = 1.0;
+                    break;
+                }
+            }
+            f = cur;
+            sigma = sig;
+            memcpy(d, outd, sizeof d);
+            const double* nn = m->N + 3 * f;
+            double nsig2[3] = {sigma * nn[0], sigma * nn[1], sigma * nn[2]}, dperp[3];
+            cross3(nsig2, d, dperp);
+            for (int k = 0; k < K; k++)
+                for (int c = 0; c < 3; c++) Wout[3 * k + c] = wn[k] * (cos(psi[k]) * d[c] + sin(psi[k]) * dperp[c]);
+            atv = local_index(m, f, x0id);
+            b[0] = b[1] = b[2] = 0.0;
+            b[atv] = 1.0;
+            skip = -1;
+            trace_push(tb, 1, (int32_t)f, x0id, -1, x0);
+        }
+        out->n_cross++;
+        out->hash = fnv_face(out->hash, (int32_t)f);
+    }
+    out->f = (int32_t)f;
+    out->status = status;
+    memcpy(out->b, b, sizeof b);
+    bary_pos(m, f, b, out->p);
+    for (int c = 0; c < 3; c++) out->v[c] = L * d[c];
+    out->traced = traced;
+    out->sigma = (int8_t)sigma;
+}
+
+/* ------------------------------------------------------------ batching */
+typedef struct {
+    const or_mesh* m;
+    int64_t n;
+    const int32_t* f; const double* b; const double* v; int32_t K; const double* W; const or_opts* o;
+    int32_t* f_out; double* b_out; double* p_out; double* v_out; double* W_out;
+    int32_t* status; int32_t* n_cross; uint64_t* seq_hash; double* min_vdist; double* traced; int8_t* sigma_end;
+    /* backward */
+    int mode;   /* 0 forward, 1 EP, 2 GFD */
+    double eps_v, eps_p;
+    const double* g; double* grad_v; double* grad_b; double* Jv; double* Jp;
+    int64_t next;
+} job_t;
+
+static void ep_one(const job_t* J, int64_t i);
+static void gfd_one(const job_t* J, int64_t i);
+
+static void fwd_one(const job_t* J, int64_t i) {
+    ray_out r;
+    double Wtmp[3 * 64];
+    double* Wo = J->W_out ? J->W_out + 3 * J->K * i : Wtmp;
+    exp_one(J->m, J->f[i], J->b + 3 * i, J->v + 3 * i, J->K, J->W ? J->W + 3 * J->K * i : NULL, J->o, &r, Wo, NULL);
+    J->f_out[i] = r.f;
+    memcpy(J->b_out + 3 * i, r.b, sizeof r.b);
+    memcpy(J->p_out + 3 * i, r.p, sizeof r.p);
+    memcpy(J->v_out + 3 * i, r.v, sizeof r.v);
+    J->status[i] = r.status;
+    if (J->n_cross) J->n_cross[i] = r.n_cross;
+    if (J->seq_hash) J->seq_hash[i] = r.hash;
+    if (J->min_vdist) J->min_vdist[i] = r.min_vdist;
+    if (J->traced) J->traced[i] = r.traced;
+    if (J->sigma_end) J->sigma_end[i] = r.sigma;
+}
+
+static void* worker(void* arg) {
+    job_t* J = arg;
+    const int64_t chunk = 4096;
+    for (;;) {
+        int64_t s = __atomic_fetch_add(&J->next, chunk, __ATOMIC_RELAXED);
+        if (s >= J->n) break;
+        int64_t e = s + chunk < J->n ? s + chunk : J->n;
+        for (int64_t i = s; i < e; i++) {
+            if (J->mode == 0) fwd_one(J, i);
+            else if (J->mode == 1) ep_one(J, i);
+            else gfd_one(J, i);
+        }
+    }
+    return NULL;
+}
+
+static int run_job(job_t* J, int32_t nthreads) {
+    if (nthreads <= 0) nthreads = (int32_t)sysconf(_SC_NPROCESSORS_ONLN);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    J->next = 0;
+    if (nthreads == 1 || J->n < 4096) { worker(J); return OR_OK; }
+    pthread_t th[256];
+    int started = 0;
+    for (int t = 0; t < nthreads; t++)
+        if (pthread_create(&th[t], NULL, worker, J) == 0) started++;
+        else break;
+    if (!started) worker(J);
+    for (int t = 0; t < started; t++) pthread_join(th[t], NULL);
+    return OR_OK;
+}
+
+int or_exp_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b, const double* v,
+                 int32_t K, const double* W, const or_opts* o, int32_t* f_out, double* b_out,
+                 double* p_out, double* v_out, double* W_out, int32_t* status, int32_t* n_cross,
+                 uint64_t* seq_hash, double* min_vdist, double* traced, int8_t* sigma_end, int32_t nthreads) {
+    if (!m || n < 0 || K < 0 || K > 64 || (n > 0 && (!f || !b || !v || !f_out || !b_out || !p_out || !v_out || !status)) ||
+        (K > 0 && n > 0 && (!W || !W_out))) {
+        set_err("bad arguments");
+        return OR_E_ARG;
+    }
+    job_t J = {0};
+    J.m = m; J.n = n; J.f = f; J.b = b; J.v = v; J.K = K; J.W = W; J.o = o;
+    J.f_out = f_out; J.b_out = b_out; J.p_out = p_out; J.v_out = v_out; J.W_out = W_out;
+    J.status = status; J.n_cross = n_cross; J.seq_hash = seq_hash; J.min_vdist = min_vdist;
+    J.traced = traced; J.sigma_end = sigma_end;
+    return run_job(&J, nthreads);
+}
+
+int32_t or_exp_trace(const or_mesh* m, int32_t f, const double* b, const double* v, const or_opts* o,
+                     int32_t cap, int8_t* kind, int32_t* face, int32_t* ev0, int32_t* ev1, double* point,
+                     int32_t* f_out, double* p_out, int32_t* status) {
+    trace_buf tb = {cap, 0, kind, face, ev0, ev1, point};
+    ray_out r;
+    exp_one(m, f, b, v, 0, NULL, o, &r, NULL, &tb);
+    *f_out = r.f;
+    memcpy(p_out, r.p, sizeof r.p);
+    *status = r.status;
+    return tb.n;
+}
+
+/* ------------------------------------------------------------ backward */
+/* Extrinsic proxy (eq. proxy_func): J^v = R = M_{p'} M_p^T, J^p = 0. */
+static void ep_one(const job_t* J, int64_t i) {
+    const or_mesh* m = J->m;
+    ray_out r;
+    exp_one(m, J->f[i], J->b + 3 * i, J->v + 3 * i, 0, NULL, J->o, &r, NULL, NULL);
+    const double* g = J->g + 3 * i;
+    double* gv = J->grad_v + 3 * i;
+    for (int c = 0; c < 3; c++) J->grad_b[3 * i + c] = 0.0;
+    if (r.status == OR_RAY_BADINPUT) { for (int c = 0; c < 3; c++) gv[c] = NAN; return; }
+    if (!(r.L > 0.0)) { memcpy(gv, g, 3 * sizeof(double)); return; }
+    double Mp[3][3], Mq[3][3];   /* rows: e_par, e_perp, n */
+    const double* n0 = m->N + 3 * (int64_t)J->f[i];
+    memcpy(Mp[0], r.d0, sizeof r.d0);
+    memcpy(Mp[2], n0, 3 * sizeof(double));
+    cross3(Mp[2], Mp[0], Mp[1]);
+    for (int c = 0; c < 3; c++) { Mq[0][c] = r.v[c] / r.L; Mq[2][c] = r.sigma * m->N[3 * (int64_t)r.f + c]; }
+    unit3(Mq[0]);
+    cross3(Mq[2], Mq[0], Mq[1]);
+    /* R^T g = M_p (M_{p'}^T g) */
+    double c3[3] = {dot3(Mq[0], g), dot3(Mq[1], g), dot3(Mq[2], g)};
+    for (int c = 0; c < 3; c++) gv[c] = c3[0] * Mp[0][c] + c3[1] * Mp[1][c] + c3[2] * Mp[2][c];
+}
+
+/* projection of an ambient vector onto face f's non-orthogonal (e_u, e_v) frame */
+static void pinv_face(const or_mesh* m, int64_t f, const double* w, double* c) {
+    double eu[3], ev[3];
+    sub3(FX(m, f, 1), FX(m, f, 0), eu); unit3(eu);
+    sub3(FX(m, f, 2), FX(m, f, 0), ev); unit3(ev);
+    double a = dot3(eu, eu), bb = dot3(eu, ev), d = dot3(ev, ev);
+    double r1 = dot3(eu, w), r2 = dot3(ev, w), det = a * d - bb * bb;
+    c[0] = (d * r1 - bb * r2) / det;
+    c[1] = (a * r2 - bb * r1) / det;
+}
+
+/* Geodesic finite differences, eqs. jv and jp, chained with g (eq. chain). */
+static void gfd_one(const job_t* J, int64_t i) {
+    const or_mesh* m = J->m;
+    const int32_t f = J->f[i];
+    const double* b = J->b + 3 * i;
+    const double* g = J->g + 3 * i;
+    double ev = J->eps_v, ep = J->eps_p;
+    ray_out r0, r1, r2, ru, rv, r3, r4;
+    exp_one(m, f, b, J->v + 3 * i, 0, NULL, J->o, &r0, NULL, NULL);
+    double* gv = J->grad_v + 3 * i;
+    double* gb = J->grad_b + 3 * i;
+    if (r0.status == OR_RAY_BADINPUT) {
+        for (int c = 0; c < 3; c++) gv[c] = gb[c] = NAN;
+        return;
+    }
+    double eu[3], evv[3];
+    sub3(FX(m, f, 1), FX(m, f, 0), eu); unit3(eu);
+    sub3(FX(m, f, 2), FX(m, f, 0), evv); unit3(evv);
+    const double* n0 = m->N + 3 * (int64_t)f;
+    double epar[3], eperp[3], dend[3];
+    if (r0.L > 0.0) {
+        memcpy(epar, r0.d0, sizeof epar);
+        for (int c = 0; c < 3; c++) dend[c] = r0.v[c] / r0.L;
+    } else {           /* |v| = 0: the tangent frame starts on e_u */
+        memcpy(epar, eu, sizeof epar);
+        memcpy(dend, eu, sizeof dend);
+    }
+    cross3(n0, epar, eperp);
+    double vt[3];
+    perp3(J->v + 3 * i, n0, vt);
+    /* column e_par: short trace from p' along the transported tangent */
+    double w[3];
+    for (int c = 0; c < 3; c++) w[c] = ev * dend[c];
+    exp_one(m, r0.f, r0.b, w, 0, NULL, J->o, &r1, NULL, NULL);
+    /* column e_perp */
+    for (int c = 0; c < 3; c++) w[c] = vt[c] + ev * eperp[c];
+    exp_one(m, f, b, w, 0, NULL, J->o, &r2, NULL, NULL);
+    /* start-point perturbations with v transported along them */
+    double vu[3], vv[3];
+    for (int c = 0; c < 3; c++) w[c] = ep * eu[c];
+    exp_one(m, f, b, w, 1, vt, J->o, &ru, vu, NULL);
+    for (int c = 0; c < 3; c++) w[c] = ep * evv[c];
+    exp_one(m, f, b, w, 1, vt, J->o, &rv, vv, NULL);
+    exp_one(m, ru.f, ru.b, vu, 0, NULL, J->o, &r3, NULL, NULL);
+    exp_one(m, rv.f, rv.b, vv, 0, NULL, J->o, &r4, NULL, NULL);
+    double col[4][3];
+    for (int c = 0; c < 3; c++) {
+        col[0][c] = (r1.p[c] - r0.p[c]) / ev;
+        col[1][c] = (r2.p[c] - r0.p[c]) / ev;
+        col[2][c] = (r3.p[c] - r0.p[c]) / ep;
+        col[3][c] = (r4.p[c] - r0.p[c]) / ep;
+    }
+    double jv[2][2], jp[2][2], t[2];   /* jv[row][col] */
+    pinv_face(m, r0.f, col[0], t); jv[0][0] = t[0]; jv[1][0] = t[1];
+    pinv_face(m, r0.f, col[1], t); jv[0][1] = t[0]; jv[1][1] = t[1];
+    pinv_face(m, r0.f, col[2], t); jp[0][0] = t[0]; jp[1][0] = t[1];
+    pinv_face(m, r0.f, col[3], t); jp[0][1] = t[0]; jp[1][1] = t[1];
+    if (J->Jv) { J->Jv[4 * i] = jv[0][0]; J->Jv[4 * i + 1] = jv[0][1]; J->Jv[4 * i + 2] = jv[1][0]; J->Jv[4 * i + 3] = jv[1][1]; }
+    if (J->Jp) { J->Jp[4 * i] = jp[0][0]; J->Jp[4 * i + 1] = jp[0][1]; J->Jp[4 * i + 2] = jp[1][0]; J->Jp[4 * i + 3] = jp[1][1]; }
+    /* M_{p'}^T g */
+    double eu2[3], ev2[3];
+    sub3(FX(m, r0.f, 1), FX(m, r0.f, 0), eu2); unit3(eu2);
+    sub3(FX(m, r0.f, 2), FX(m, r0.f, 0), ev2); unit3(ev2);
+    double h[2] = {dot3(eu2, g), dot3(ev2, g)};
+    double cv[2] = {jv[0][0] * h[0] + jv[1][0] * h[1], jv[0][1] * h[0] + jv[1][1] * h[1]};
+    double cp[2] = {jp[0][0] * h[0] + jp[1][0] * h[1], jp[0][1] * h[0] + jp[1][1] * h[1]};
+    for (int c = 0; c < 3; c++) gv[c] = cv[0] * epar[c] + cv[1] * eperp[c];
+    /* start-point gradient G in the face plane with M_p^T G = cp, M_p = [e_u e_v] */
+    double a = dot3(eu, eu), bb = dot3(eu, evv), d = dot3(evv, evv), det = a * d - bb * bb;
+    double y0 = (d * cp[0] - bb * cp[1]) / det, y1 = (a * cp[1] - bb * cp[0]) / det;
+    double G[3];
+    for (int c = 0; c < 3; c++) G[c] = y0 * eu[c] + y1 * evv[c];
+    for (int k = 0; k < 3; k++) gb[k] = dot3(G, FX(m, f, k));
+}
+
+int or_ep_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b, const double* v,
+                const or_opts* o, const double* g, double* grad_v, double* grad_b, int32_t nthreads) {
+    if (!m || n < 0 || (n > 0 && (!f || !b || !v || !g || !grad_v || !grad_b))) { set_err("bad arguments"); return OR_E_ARG; }
+    job_t J = {0};
+    J.m = m; J.n = n; J.f = f; J.b = b; J.v = v; J.o = o; J.mode = 1;
+    J.g = g; J.grad_v = grad_v; J.grad_b = grad_b;
+    return run_job(&J, nthreads);
+}
+
+int or_gfd_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b, const double* v,
+                 const or_opts* o, double eps_v, double eps_p, const double* g, double* grad_v,
+                 double* grad_b, double* Jv, double* Jp, int32_t nthreads) {
+    if (!m || n < 0 || !(eps_v > 0) || !(eps_p > 0) || (n > 0 && (!f || !b || !v || !g || !grad_v || !grad_b))) {
+        set_err("bad arguments");
+        return OR_E_ARG;
+    }
+    job_t J = {0};
+    J.m = m; J.n = n; J.f = f; J.b = b; J.v = v; J.o = o; J.mode = 2;
+    J.eps_v = eps_v; J.eps_p = eps_p;
+    J.g = g; J.grad_v = grad_v; J.grad_b = grad_b; J.Jv = Jv; J.Jp = Jp;
+    return run_job(&J, nthreads);
+}

@@ -1,0 +1,79 @@
+/*
+ * sg_oracle.h -- float64 CPU oracle for the straightest-geodesic exponential
+ * map on triangle meshes (Verninas et al., "Parallelised Differentiable
+ * Straightest Geodesics for 3D Meshes", Sec. 4 and the appendix algorithms
+ * geodesic_step / transport_over_edge / transport_over_vertex).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant with the GPU library.
+ */
+#ifndef SG_ORACLE_H
+#define SG_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_OK = 0, OR_E_ARG = -1, OR_E_NONMANIFOLD = -2, OR_E_DEGENERATE = -3, OR_E_OOM = -5 };
+enum { OR_RAY_OK = 0, OR_RAY_MAXSTEPS = 1, OR_RAY_BOUNDARY = 2, OR_RAY_BADINPUT = 3 };
+
+typedef struct or_mesh or_mesh;
+
+typedef struct {
+    int32_t max_steps;     /* cap on edge crossings + vertex passages */
+    double vertex_snap;    /* exit point within this edge-parameter distance of an
+                              edge endpoint counts as passing through that vertex */
+} or_opts;
+
+/* Builds adjacency, normals and vertex total angles from the canonical float32
+ * mesh (upcast exactly).  Returns OR_OK or a negative error code. */
+int or_mesh_build(const float* X, int64_t nv, const int32_t* F, int64_t nf, or_mesh** out);
+void or_mesh_free(or_mesh* m);
+double or_mesh_mean_edge(const or_mesh* m);
+void or_mesh_theta(const or_mesh* m, double* theta /* [nv] */);
+const char* or_last_error(void);
+
+/* Batched exponential map with parallel transport of K extra vectors.
+ * Inputs: f[n], b[n*3] (renormalised to sum 1), v[n*3] (projected onto the
+ * start face), W[n*K*3].  Outputs (all caller-owned, float64 unless noted):
+ * f_out, b_out, p_out, v_out = |v_t| * end tangent, W_out, status,
+ * n_cross (edge crossings + vertex passages), seq_hash (FNV-1a 64 of the
+ * visited face ids), min_vdist (closest approach of the path to a vertex of
+ * the face it was in), traced (total traced length), sigma_end (+1/-1, the
+ * end face's normal relative to the orientation carried along the path).
+ * Any output pointer except f_out/b_out/p_out/v_out/status may be NULL.
+ * nthreads <= 0 uses every online core. */
+int or_exp_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
+                 const double* v, int32_t K, const double* W, const or_opts* o,
+                 int32_t* f_out, double* b_out, double* p_out, double* v_out,
+                 double* W_out, int32_t* status, int32_t* n_cross, uint64_t* seq_hash,
+                 double* min_vdist, double* traced, int8_t* sigma_end, int32_t nthreads);
+
+/* One ray with its event list: for each edge crossing or vertex passage,
+ * kind (0 edge, 1 vertex), the face entered and the 3D point of the event.
+ * Returns the number of events written (at most cap). */
+int32_t or_exp_trace(const or_mesh* m, int32_t f, const double* b, const double* v,
+                     const or_opts* o, int32_t cap, int8_t* kind, int32_t* face,
+                     int32_t* edge_v0, int32_t* edge_v1, double* point,
+                     int32_t* f_out, double* p_out, int32_t* status);
+
+/* Extrinsic-proxy backward (eq. proxy_func): grad_v = R^T g with
+ * R = M_{p'} M_p^T, frames [e_par, e_perp, n]; the start-point gradient is zero. */
+int or_ep_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
+                const double* v, const or_opts* o, const double* g,
+                double* grad_v, double* grad_b, int32_t nthreads);
+
+/* Geodesic finite differences (eqs. jv, jp) at step sizes eps_v, eps_p, chained
+ * with the upstream gradient g = dL/dp'.  Also returns the 2x2 Jacobians
+ * (row-major, may be NULL) in the paper's local frames. */
+int or_gfd_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
+                 const double* v, const or_opts* o, double eps_v, double eps_p,
+                 const double* g, double* grad_v, double* grad_b,
+                 double* Jv, double* Jp, int32_t nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
