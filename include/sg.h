@@ -1,0 +1,130 @@
+/*
+ * sg.h -- C ABI of the MI355X straightest-geodesic library.
+ *
+ * Computes the discrete exponential map Exp_p(v) on triangle meshes by
+ * straightest geodesics (Verninas et al., "Parallelised Differentiable
+ * Straightest Geodesics for 3D Meshes": Sec. 3 eq. ivp for the definition,
+ * Sec. 4 "Straightest geodesics" for the straightest rule, Alg. gpu_parallel
+ * for one geodesic per GPU lane), the parallel transport of extra tangent
+ * vectors along it (Sec. 4 "Parallel Transport"), and the backward schemes of
+ * Sec. 4 (extrinsic proxy, eq. proxy_func; geodesic finite differences, eqs.
+ * jv and jp), chained with an upstream gradient as in eq. chain.
+ *
+ * Conventions shared by every call:
+ *  - Array arguments named in the comments as [n,3] are row-major float32 or
+ *    int32 arrays in *device* memory (hipMalloc / torch CUDA tensors) unless
+ *    the comment says host.  The caller owns them; the library never frees
+ *    caller memory and keeps no pointer after the call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call except sg_mesh_create / sg_mesh_destroy / sg_mesh_info is
+ *    asynchronous on that stream.
+ *  - Return values: SG_OK or a negative SG_E_* code.  Argument and shape
+ *    problems are found before anything is launched; a HIP failure maps to
+ *    SG_E_HIP.  No C++ exception crosses this boundary.  sg_last_error()
+ *    returns a message for the last failure on the calling thread.
+ *  - Per-ray problems never fail a call: they go to the optional per-ray
+ *    `status` array (SG_RAY_*).
+ *  - A surface point is (face id, barycentric b) with p = sum_k b_k x_{F[f][k]}
+ *    (Sec. 4); b is renormalised to sum 1 and must be non-negative.  Face ids
+ *    are global over all meshes of a handle.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sg_mesh_s* sg_mesh;
+
+enum {
+    SG_OK = 0,
+    SG_E_ARG = -1,          /* null pointer, bad size, bad option */
+    SG_E_NONMANIFOLD = -2,  /* an edge with more than two faces, or a vertex whose faces form several fans (Sec. 4) */
+    SG_E_DEGENERATE = -3,   /* a face repeating a vertex or with zero area */
+    SG_E_HIP = -4,          /* a HIP runtime call failed */
+    SG_E_OOM = -5           /* host or device allocation failed */
+};
+
+enum {
+    SG_RAY_OK = 0,          /* traced the full length */
+    SG_RAY_MAXSTEPS = 1,    /* stopped after max_steps crossings (Alg. gpu_parallel's MAX_STEPS) */
+    SG_RAY_BOUNDARY = 2,    /* reached a boundary edge or boundary vertex and stopped there (Sec. 4) */
+    SG_RAY_BADINPUT = 3     /* face id out of range, non-finite or negative input, or a vertex start whose
+                               direction leaves the given face */
+};
+
+enum { SG_BWD_EP = 0, SG_BWD_GFD = 1 };
+enum { SG_KERNEL_AUTO = 0, SG_KERNEL_PLAIN = 1, SG_KERNEL_PERSISTENT = 2 };
+
+typedef struct {
+    int32_t max_steps;     /* cap on crossings per ray (edge crossings + vertex passages); <= 0: 1 << 20 */
+    float vertex_snap;     /* an exit point within this edge-parameter distance of an edge endpoint passes
+                              through that vertex (straightest rule at vertices); <= 0: 2^-18 */
+    float eps_v, eps_p;    /* GFD step sizes (absolute lengths); <= 0: 5e-3 * mean edge of the handle */
+    int32_t kernel;        /* SG_KERNEL_*: which forward kernel runs the walk */
+    uint32_t debug;        /* bit 0: fill n_cross; bit 1: fill seq_hash (FNV-1a 64 of the visited face ids) */
+} sg_opts;
+
+/* Fills *o with the defaults above. */
+void sg_opts_default(sg_opts* o);
+
+/*
+ * Builds a mesh handle from host arrays (Sec. 4: M = {X, F}; several meshes
+ * may be batched by offsets, Sec. 4 "Parallelisation on the GPU").
+ *   X_host [n_verts,3] float32 host, F_host [n_faces,3] int32 host.
+ *   vert_offsets / face_offsets: host int64 arrays of n_meshes+1 entries
+ *   (prefix sums), or both NULL with n_meshes = 1.  Vertex indices in F are
+ *   local to their mesh; the library adds the vertex offset.  Rays name faces
+ *   by global id (face_offsets[m] + local id).
+ * Validates the manifold condition of Sec. 4, packs per-half-edge records in
+ * float64 on the host (rounded once to float32 / fixed-point angles) and
+ * uploads them.  Synchronous.  On success *out owns device memory until
+ * sg_mesh_destroy.
+ */
+int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, int64_t n_faces,
+                   const int64_t* vert_offsets, const int64_t* face_offsets, int32_t n_meshes,
+                   sg_mesh* out);
+void sg_mesh_destroy(sg_mesh mesh);
+
+/* Host outputs, each nullable: mean undirected edge length, number of
+ * half-edge records, device bytes held by the handle. */
+int sg_mesh_info(sg_mesh mesh, double* mean_edge, int64_t* n_half_edges, size_t* device_bytes);
+
+/*
+ * Exponential map (Sec. 3 eq. ivp; Alg. gpu_parallel).  For each ray i:
+ *   in : f[n] int32, b[n,3] float32, v[n,3] float32 (projected onto the start
+ *        face's plane; |v_t| is the length to trace).
+ *   out: f_out[n] int32 end face, b_out[n,3] end barycentrics, p_out[n,3] end
+ *        point, v_out[n,3] = |v_t| * end tangent (v transported to p').
+ *   optional (NULL to skip): status[n] int32, n_cross[n] int32 (needs
+ *        debug bit 0), seq_hash[n] uint64 (needs debug bit 1).
+ * opts may be NULL (defaults).  n = 0 is a no-op.
+ */
+int sg_exp(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v,
+           int32_t* f_out, float* b_out, float* p_out, float* v_out,
+           int32_t* status, int32_t* n_cross, uint64_t* seq_hash,
+           const sg_opts* opts, void* stream);
+
+/*
+ * sg_exp plus parallel transport (Sec. 4 "Parallel Transport") of K extra
+ * vectors per ray: W[n,K,3] float32 in (projected onto the start face),
+ * W_out[n,K,3] float32 out.  Each vector keeps its norm and its signed angle
+ * to the geodesic's tangent.  K in [0, 64].
+ */
+int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v,
+                     int32_t K, const float* W,
+                     int32_t* f_out, float* b_out, float* p_out, float* v_out, float* W_out,
+                     int32_t* status, int32_t* n_cross, uint64_t* seq_hash,
+                     const sg_opts* opts, void* stream);
+
+/* Message describing the last non-OK return on the calling thread. */
+const char* sg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

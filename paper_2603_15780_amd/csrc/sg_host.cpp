@@ -1,0 +1,376 @@
+// sg_host.cpp -- mesh packer and C ABI of the straightest-geodesic library.
+//
+// The packer runs once per mesh on the host in float64 from the float32
+// vertex positions: manifold validation (Sec. 4: every edge on one or two
+// faces, each vertex fan connected), face adjacency (the only connectivity
+// the walk uses, so non-orientable meshes are accepted), per-half-edge chart
+// records and theta(x) = sum of corner angles at each vertex (Sec. 4), all
+// rounded once to float32 or fixed-point angles and uploaded.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "sg.h"
+#include "sg_internal.h"
+#include "sg_launch.h"
+
+using sg::HalfEdgeRec;
+
+struct sg_mesh_s {
+    int device = 0;
+    int64_t n_verts = 0, n_faces = 0;
+    int32_t n_meshes = 1;
+    double mean_edge = 0.0;
+    HalfEdgeRec* d_rec = nullptr;
+    int32_t* d_F = nullptr;
+    float* d_X = nullptr;
+    int64_t* d_half = nullptr;
+    size_t bytes = 0;
+    sg::DevMesh dev() const {
+        return sg::DevMesh{d_rec, d_F, d_X, d_half, n_faces, n_verts};
+    }
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(SG_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct V3 {
+    double x, y, z;
+};
+inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline double len(V3 a) { return std::sqrt(dot(a, a)); }
+inline V3 mul(V3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+
+// angle between two vectors, robust for small angles
+inline double angle_between(V3 a, V3 b) { return std::atan2(len(cross(a, b)), dot(a, b)); }
+
+inline uint32_t to_fx(double rad) {
+    const double u = std::nearbyint(rad * sg::kFxPerRad);
+    return (uint32_t)(int64_t)u;
+}
+
+// union-find over face corners, used for the one-fan-per-vertex check
+struct DSU {
+    std::vector<int64_t> p;
+    explicit DSU(int64_t n) : p(n) { std::iota(p.begin(), p.end(), 0); }
+    int64_t find(int64_t x) {
+        while (p[x] != x) {
+            p[x] = p[p[x]];
+            x = p[x];
+        }
+        return x;
+    }
+    void unite(int64_t a, int64_t b) {
+        a = find(a);
+        b = find(b);
+        if (a != b) p[std::max(a, b)] = std::min(a, b);
+    }
+};
+
+template <class T>
+int upload(T** dptr, const std::vector<T>& h, size_t& bytes) {
+    const size_t nb = h.size() * sizeof(T);
+    hipError_t e = hipMalloc((void**)dptr, nb ? nb : sizeof(T));
+    if (e != hipSuccess) return fail(SG_E_OOM, "hipMalloc(%zu): %s", nb, hipGetErrorString(e));
+    bytes += nb;
+    if (nb) {
+        e = hipMemcpy(*dptr, h.data(), nb, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    }
+    return SG_OK;
+}
+
+void free_mesh(sg_mesh_s* m) {
+    if (!m) return;
+    (void)hipFree(m->d_rec);
+    (void)hipFree(m->d_F);
+    (void)hipFree(m->d_X);
+    (void)hipFree(m->d_half);
+    delete m;
+}
+
+int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
+    sg_opts_default(&o);
+    if (in) o = *in;
+    if (o.max_steps <= 0) o.max_steps = 1 << 20;
+    if (!(o.vertex_snap > 0.f)) o.vertex_snap = 1.0f / 262144.0f;
+    if (!(o.vertex_snap < 0.25f)) return fail(SG_E_ARG, "vertex_snap must be below 0.25");
+    if (!(o.eps_v > 0.f)) o.eps_v = (float)(5e-3 * m->mean_edge);
+    if (!(o.eps_p > 0.f)) o.eps_p = (float)(5e-3 * m->mean_edge);
+    if (o.kernel < SG_KERNEL_AUTO || o.kernel > SG_KERNEL_PERSISTENT) return fail(SG_E_ARG, "unknown kernel %d", o.kernel);
+    return SG_OK;
+}
+
+}  // namespace
+
+namespace sg {
+
+int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64_t n_faces,
+              const int64_t* vert_offsets, const int64_t* face_offsets, int32_t n_meshes, PackedMesh& out) {
+    try {
+        if (!X_host || !F_host || n_verts <= 0 || n_faces <= 0) return fail(SG_E_ARG, "empty mesh");
+        if (n_faces > ((int64_t)1 << 29) || n_verts > ((int64_t)1 << 31) - 1)
+            return fail(SG_E_ARG, "mesh too large for 32-bit half-edge ids (%lld faces)", (long long)n_faces);
+        if (n_meshes < 1) return fail(SG_E_ARG, "n_meshes must be >= 1");
+        if ((vert_offsets == nullptr) != (face_offsets == nullptr))
+            return fail(SG_E_ARG, "vert_offsets and face_offsets must both be given or both be NULL");
+        if (!vert_offsets && n_meshes != 1) return fail(SG_E_ARG, "offsets are required for several meshes");
+        std::vector<int64_t> vo{0, n_verts}, fo{0, n_faces};
+        if (vert_offsets) {
+            vo.assign(vert_offsets, vert_offsets + n_meshes + 1);
+            fo.assign(face_offsets, face_offsets + n_meshes + 1);
+            if (vo[0] != 0 || fo[0] != 0 || vo[n_meshes] != n_verts || fo[n_meshes] != n_faces)
+                return fail(SG_E_ARG, "offsets must start at 0 and end at the totals");
+            for (int32_t m = 0; m < n_meshes; ++m)
+                if (vo[m + 1] < vo[m] || fo[m + 1] < fo[m]) return fail(SG_E_ARG, "offsets must be non-decreasing");
+        }
+        // global vertex ids and float64 positions
+        std::vector<int32_t> F(3 * n_faces);
+        for (int32_t m = 0; m < n_meshes; ++m) {
+            const int64_t nvm = vo[m + 1] - vo[m];
+            for (int64_t f = fo[m]; f < fo[m + 1]; ++f)
+                for (int k = 0; k < 3; ++k) {
+                    const int64_t v = F_host[3 * f + k];
+                    if (v < 0 || v >= nvm)
+                        return fail(SG_E_ARG, "face %lld: vertex index %lld out of range", (long long)f, (long long)v);
+                    F[3 * f + k] = (int32_t)(v + vo[m]);
+                }
+        }
+        std::vector<V3> X(n_verts);
+        for (int64_t v = 0; v < n_verts; ++v) {
+            const float* p = X_host + 3 * v;
+            if (!std::isfinite(p[0]) || !std::isfinite(p[1]) || !std::isfinite(p[2]))
+                return fail(SG_E_ARG, "vertex %lld is not finite", (long long)v);
+            X[v] = {(double)p[0], (double)p[1], (double)p[2]};
+        }
+        for (int64_t f = 0; f < n_faces; ++f) {
+            const int32_t* t = &F[3 * f];
+            if (t[0] == t[1] || t[1] == t[2] || t[0] == t[2])
+                return fail(SG_E_DEGENERATE, "face %lld repeats a vertex", (long long)f);
+            if (!(len(cross(X[t[1]] - X[t[0]], X[t[2]] - X[t[0]])) > 0.0))
+                return fail(SG_E_DEGENERATE, "face %lld has zero area", (long long)f);
+        }
+        // undirected edges: sort half-edges by (min, max) vertex key
+        const int64_t nh = 3 * n_faces;
+        std::vector<uint64_t> key(nh);
+        std::vector<int64_t> order(nh);
+        for (int64_t h = 0; h < nh; ++h) {
+            const uint32_t a = (uint32_t)F[h], b = (uint32_t)F[(h / 3) * 3 + (h % 3 + 1) % 3];
+            key[h] = ((uint64_t)std::min(a, b) << 32) | std::max(a, b);
+            order[h] = h;
+        }
+        std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return key[x] < key[y] || (key[x] == key[y] && x < y); });
+        std::vector<int64_t> twin(nh, -1);
+        std::vector<uint8_t> vbnd(n_verts, 0);
+        double esum = 0.0;
+        int64_t ecount = 0;
+        for (int64_t i = 0; i < nh;) {
+            int64_t j = i + 1;
+            while (j < nh && key[order[j]] == key[order[i]]) ++j;
+            const int64_t h0 = order[i];
+            const int32_t a = F[h0], b = F[(h0 / 3) * 3 + (h0 % 3 + 1) % 3];
+            esum += len(X[b] - X[a]);
+            ++ecount;
+            if (j - i > 2)
+                return fail(SG_E_NONMANIFOLD, "edge (%d,%d) has %lld faces", std::min(a, b), std::max(a, b), (long long)(j - i));
+            if (j - i == 2) {
+                const int64_t h1 = order[i + 1];
+                if (h0 / 3 == h1 / 3) return fail(SG_E_DEGENERATE, "face %lld uses an edge twice", (long long)(h0 / 3));
+                twin[h0] = h1;
+                twin[h1] = h0;
+            } else {
+                vbnd[a] = vbnd[b] = 1;
+            }
+            i = j;
+        }
+        // one fan per vertex: corners at the same vertex are joined across shared edges
+        {
+            DSU dsu(nh);
+            for (int64_t h = 0; h < nh; ++h) {
+                const int64_t g = twin[h];
+                if (g < h) continue;
+                const int64_t f = h / 3, k = h % 3, fg = g / 3, kg = g % 3;
+                const int32_t a = F[h], b = F[3 * f + (k + 1) % 3];
+                // corner of f at a is h; corner of fg at a is whichever end of g equals a
+                const int64_t ga = F[g] == a ? g : 3 * fg + (kg + 1) % 3;
+                const int64_t gb = F[g] == b ? g : 3 * fg + (kg + 1) % 3;
+                dsu.unite(h, ga);
+                dsu.unite(3 * f + (k + 1) % 3, gb);
+            }
+            std::vector<int64_t> root(n_verts, -1);
+            for (int64_t h = 0; h < nh; ++h) {
+                const int32_t v = F[h];
+                const int64_t r = dsu.find(h);
+                if (root[v] < 0) root[v] = r;
+                else if (root[v] != r) return fail(SG_E_NONMANIFOLD, "vertex %d: faces do not form one fan", v);
+            }
+        }
+        // chart records and vertex total angles
+        std::vector<HalfEdgeRec>& rec = out.rec;
+        rec.assign(nh, HalfEdgeRec{});
+        std::vector<double> theta(n_verts, 0.0);
+        for (int64_t h = 0; h < nh; ++h) {
+            const int64_t f = h / 3;
+            const int k = (int)(h % 3);
+            const int32_t ia = F[3 * f + k], ib = F[3 * f + (k + 1) % 3], ic = F[3 * f + (k + 2) % 3];
+            const V3 ab = X[ib] - X[ia], ac = X[ic] - X[ia], bc = X[ic] - X[ib];
+            const double l = len(ab);
+            const V3 ex = mul(ab, 1.0 / l);
+            V3 n = cross(ab, ac);
+            n = mul(n, 1.0 / len(n));
+            const V3 ey = cross(n, ex);
+            const double A = angle_between(ab, ac);
+            const double B = angle_between(mul(ab, -1.0), bc);
+            theta[ia] += A;
+            HalfEdgeRec& r = rec[h];
+            r.cx = (float)dot(ac, ex);
+            r.cy = (float)dot(ac, ey);
+            r.lac = (float)len(ac);
+            r.lbc = (float)len(bc);
+            r.A = to_fx(A);
+            r.B = to_fx(B);
+            auto link = [&](int64_t he) -> int32_t {
+                const int64_t g = twin[he];
+                if (g < 0) return -1;
+                const int32_t start_he = F[he];
+                const int32_t start_g = F[g];
+                const uint32_t flip = start_he == start_g ? 1u : 0u;   // same direction: orientations disagree
+                return (int32_t)(((uint32_t)g << 1) | flip);
+            };
+            r.nca = link(3 * f + (k + 2) % 3);
+            r.nbc = link(3 * f + (k + 1) % 3);
+        }
+        std::vector<int64_t>& half = out.half;
+        half.assign(n_verts, 0);
+        for (int64_t v = 0; v < n_verts; ++v)
+            half[v] = vbnd[v] ? -1 : (int64_t)std::llround(0.5 * theta[v] * sg::kFxPerRad);
+        out.X.assign(X_host, X_host + 3 * n_verts);
+        out.F = std::move(F);
+        out.n_verts = n_verts;
+        out.n_faces = n_faces;
+        out.mean_edge = esum / (double)ecount;
+        return SG_OK;
+
+    } catch (const std::bad_alloc&) {
+        return fail(SG_E_OOM, "out of host memory");
+    } catch (...) {
+        return fail(SG_E_ARG, "unexpected error while packing the mesh");
+    }
+}
+
+}  // namespace sg
+
+extern "C" {
+
+const char* sg_last_error(void) { return g_err.c_str(); }
+
+void sg_opts_default(sg_opts* o) {
+    if (!o) return;
+    o->max_steps = 1 << 20;
+    o->vertex_snap = 1.0f / 262144.0f;
+    o->eps_v = 0.f;
+    o->eps_p = 0.f;
+    o->kernel = SG_KERNEL_AUTO;
+    o->debug = 0u;
+}
+
+int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, int64_t n_faces,
+                   const int64_t* vert_offsets, const int64_t* face_offsets, int32_t n_meshes, sg_mesh* out) {
+    if (!out) return fail(SG_E_ARG, "out is NULL");
+    *out = nullptr;
+    sg::PackedMesh pm;
+    int rc = sg::pack_mesh(X_host, n_verts, F_host, n_faces, vert_offsets, face_offsets, n_meshes, pm);
+    if (rc != SG_OK) return rc;
+    auto* m = new (std::nothrow) sg_mesh_s();
+    if (!m) return fail(SG_E_OOM, "out of host memory");
+    hipError_t e = hipGetDevice(&m->device);
+    if (e != hipSuccess) {
+        delete m;
+        return hip_fail(e, "hipGetDevice");
+    }
+    m->n_verts = n_verts;
+    m->n_faces = n_faces;
+    m->n_meshes = n_meshes;
+    m->mean_edge = pm.mean_edge;
+    rc = upload(&m->d_rec, pm.rec, m->bytes);
+    if (rc == SG_OK) rc = upload(&m->d_F, pm.F, m->bytes);
+    if (rc == SG_OK) rc = upload(&m->d_X, pm.X, m->bytes);
+    if (rc == SG_OK) rc = upload(&m->d_half, pm.half, m->bytes);
+    if (rc != SG_OK) {
+        free_mesh(m);
+        return rc;
+    }
+    *out = m;
+    return SG_OK;
+}
+
+void sg_mesh_destroy(sg_mesh mesh) { free_mesh(mesh); }
+
+int sg_mesh_info(sg_mesh mesh, double* mean_edge, int64_t* n_half_edges, size_t* device_bytes) {
+    if (!mesh) return fail(SG_E_ARG, "mesh is NULL");
+    if (mean_edge) *mean_edge = mesh->mean_edge;
+    if (n_half_edges) *n_half_edges = 3 * mesh->n_faces;
+    if (device_bytes) *device_bytes = mesh->bytes;
+    return SG_OK;
+}
+
+int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v, int32_t K,
+                     const float* W, int32_t* f_out, float* b_out, float* p_out, float* v_out, float* W_out,
+                     int32_t* status, int32_t* n_cross, uint64_t* seq_hash, const sg_opts* opts, void* stream) {
+    if (!mesh) return fail(SG_E_ARG, "mesh is NULL");
+    if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
+    if (K < 0 || K > 64) return fail(SG_E_ARG, "K must be in [0, 64]");
+    sg_opts o;
+    int rc = check_opts(opts, o, mesh);
+    if (rc != SG_OK) return rc;
+    if (n == 0) return SG_OK;
+    if (!f || !b || !v || !f_out || !b_out || !p_out || !v_out) return fail(SG_E_ARG, "a required array is NULL");
+    if (K > 0 && (!W || !W_out)) return fail(SG_E_ARG, "W and W_out are required when K > 0");
+    if ((o.debug & 2u) && !seq_hash) return fail(SG_E_ARG, "debug bit 1 needs seq_hash");
+    sg::ExpArgs a{};
+    a.n = n;
+    a.f = f; a.b = b; a.v = v;
+    a.K = K; a.W = W;
+    a.f_out = f_out; a.b_out = b_out; a.p_out = p_out; a.v_out = v_out; a.W_out = W_out;
+    a.status = status; a.n_cross = n_cross; a.seq_hash = seq_hash;
+    a.max_steps = o.max_steps;
+    a.snap = o.vertex_snap;
+    a.debug = o.debug;
+    hipError_t e = sg::launch_exp_plain(mesh->dev(), a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return SG_OK;
+}
+
+int sg_exp(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v, int32_t* f_out, float* b_out,
+           float* p_out, float* v_out, int32_t* status, int32_t* n_cross, uint64_t* seq_hash, const sg_opts* opts,
+           void* stream) {
+    return sg_exp_transport(mesh, n, f, b, v, 0, nullptr, f_out, b_out, p_out, v_out, nullptr, status, n_cross,
+                            seq_hash, opts, stream);
+}
+
+}  // extern "C"

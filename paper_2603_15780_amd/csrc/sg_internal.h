@@ -1,0 +1,46 @@
+// sg_internal.h -- data layout shared by the host packer and the gfx950 kernels.
+//
+// The walk is intrinsic: a ray inside a face is described in the chart of
+// the half-edge it entered through.  For half-edge h = 3 f + k of face f the
+// entry edge runs from a = F[f][k] to b = F[f][k+1]; the apex is
+// c = F[f][k+2].  The chart puts a at the origin, b on the +x axis and the
+// face in y > 0.  Unfolding across an edge (Sec. 4: the neighbourhood of an
+// edge point is isometric to a plane) is then an exact change of chart, and
+// the direction is carried as a fixed-point angle to the entry edge, so the
+// angle-preserving transition is an integer add of a corner angle.
+#pragma once
+#include <stdint.h>
+
+namespace sg {
+
+// Fixed-point angles: 2^32 units = 2 pi.  Corner angles are rounded once from
+// float64; their sums are exact integer arithmetic.
+constexpr uint32_t kPiFx = 0x80000000u;
+constexpr uint32_t kHalfPiFx = 0x40000000u;
+constexpr double kFxPerRad = 4294967296.0 / 6.283185307179586476925286766559;
+constexpr float kRadPerFx = 1.4629180792671596e-09f;   // 2 pi / 2^32
+
+// One record per half-edge (32 bytes, one aligned sector): everything a ray
+// entering face f through edge k needs to find its exit and the next chart.
+struct alignas(32) HalfEdgeRec {
+    float cx, cy;     // apex c in the entry chart
+    float lac, lbc;   // lengths |ac| and |bc|
+    uint32_t A, B;    // corner angles at a and b (fixed point)
+    int32_t nca;      // half-edge entered when crossing edge c-a: (id << 1) | flip, or -1 (boundary)
+    int32_t nbc;      // half-edge entered when crossing edge b-c, same encoding
+};
+static_assert(sizeof(HalfEdgeRec) == 32, "record must be one 32-byte sector");
+
+// Device view of a packed mesh handle.
+struct DevMesh {
+    const HalfEdgeRec* rec;   // [3 n_faces]
+    const int32_t* F;         // [n_faces, 3] global vertex ids
+    const float* X;           // [n_verts, 3]
+    const int64_t* half_theta;// [n_verts] theta(x)/2 in fixed point, -1 on boundary vertices
+    int64_t n_faces;
+    int64_t n_verts;
+};
+
+enum RayStatus : int32_t { kRayOk = 0, kRayMaxSteps = 1, kRayBoundary = 2, kRayBadInput = 3 };
+
+}  // namespace sg

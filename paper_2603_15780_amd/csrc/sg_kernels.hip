@@ -1,0 +1,469 @@
+// sg_kernels.hip -- gfx950 kernels of the straightest-geodesic exponential map.
+//
+// One ray per lane (Alg. gpu_parallel).  A ray is held in the chart of the
+// half-edge it entered through (see sg_internal.h):
+//   h        current half-edge record (face f = h / 3, entry edge k = h % 3)
+//   s, t     distance of the entry point from the edge's start a and end b
+//   phi      direction angle to the entry edge, fixed point, in [0, pi]
+//   Lhi+Llo  remaining length, compensated sum
+// Per crossing the lane gathers one 32-byte record, finds the exit edge
+// (geodesic_step's lambda, restricted to the two non-entry edges), and
+// changes chart.  Unfolding keeps the angle to the crossed edge, so the new
+// direction is phi - A or phi + B (transport_over_edge), an exact integer add;
+// only the position is rounded, once per crossing, in the local chart.
+// Passing a vertex applies the straightest rule of Sec. 4 (equal angles
+// theta(x)/2 on both sides, transport_over_vertex) by walking the fan with
+// the same records.  Extra vectors keep their signed angle to the tangent
+// (Sec. 4 "Parallel Transport"), so they are reconstructed at the end.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sg_internal.h"
+#include "sg_launch.h"
+
+namespace sg {
+
+#define SG_HD __host__ __device__
+
+namespace {
+
+constexpr uint32_t kForceBC = 2u;   // leave a vertex through the edge opposite it (vertex at a)
+constexpr uint32_t kForceCA = 4u;   // (vertex at b)
+constexpr uint32_t kForceMask = 6u;
+constexpr uint32_t kParity = 1u;    // orientation flipped an odd number of times
+
+// sin(x)/x and cos(x) as polynomials in u = x^2 on |x| <= pi/2 (least-squares
+// minimax fits, max error about 1.4e-7 in float32).
+SG_HD __forceinline__ float poly_sinc(float u) {
+    float r = 2.579398596935789e-06f;
+    r = fmaf(r, u, -1.9794619583990425e-04f);
+    r = fmaf(r, u, 8.332779631018639e-03f);
+    r = fmaf(r, u, -1.6666638851165771e-01f);
+    return fmaf(r, u, 9.999999403953552e-01f);
+}
+SG_HD __forceinline__ float poly_cos(float u) {
+    float r = -2.596159447421087e-07f;
+    r = fmaf(r, u, 2.4754535843385383e-05f);
+    r = fmaf(r, u, -1.3888237299397588e-03f);
+    r = fmaf(r, u, 4.166662320494652e-02f);
+    r = fmaf(r, u, -0.5f);
+    return fmaf(r, u, 1.0f);
+}
+
+// sin and cos of a fixed-point angle in [0, pi] (evaluated about pi/2).
+SG_HD __forceinline__ void sincos_fx(uint32_t phi, float& sn, float& cs) {
+    const float x = (float)(int32_t)(phi - kHalfPiFx) * kRadPerFx;
+    const float u = x * x;
+    sn = poly_cos(u);
+    cs = -x * poly_sinc(u);
+}
+
+// Full-circle fixed-point angle of the 2D vector (x, y), reduced to one octant
+// so the float32 arctangent only sees [0, 1].
+SG_HD uint32_t angle_fx(float x, float y) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const bool sw = ay > ax;
+    const float q = sw ? ax / ay : (ax > 0.f ? ay / ax : 0.f);
+    const float a = atanf(q);
+    // a * 2^32 / (2 pi) with the constant split in two floats
+    const float khi = 683565248.0f, klo = 27.576362f;
+    const float p = a * khi;
+    const float e = fmaf(a, khi, -p) + a * klo;
+    const float pr = rintf(p);
+    uint32_t fx = (uint32_t)(int32_t)pr + (uint32_t)(int32_t)rintf((p - pr) + e);
+    if (sw) fx = kHalfPiFx - fx;
+    if (x < 0.f) fx = kPiFx - fx;
+    if (y < 0.f) fx = 0u - fx;
+    return fx;
+}
+
+SG_HD __forceinline__ uint64_t fnv_face(uint64_t h, uint32_t f) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        h ^= (f >> (8 * i)) & 0xffu;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+struct Ray {
+    int32_t h;
+    float s, t;
+    uint32_t phi;
+    float Lhi, Llo;
+    uint32_t flags;
+    int32_t ncross;
+    uint64_t hash;
+};
+
+SG_HD __forceinline__ float3 ld3(const float* p) { return make_float3(p[0], p[1], p[2]); }
+SG_HD __forceinline__ float3 sub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+SG_HD __forceinline__ float dot(float3 a, float3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+SG_HD __forceinline__ float3 crs(float3 a, float3 b) {
+    return make_float3(fmaf(a.y, b.z, -a.z * b.y), fmaf(a.z, b.x, -a.x * b.z), fmaf(a.x, b.y, -a.y * b.x));
+}
+SG_HD __forceinline__ float3 scl(float3 a, float s) { return make_float3(a.x * s, a.y * s, a.z * s); }
+SG_HD __forceinline__ float3 nrm(float3 a) { return scl(a, 1.0f / sqrtf(dot(a, a))); }
+
+enum InitResult { kInitOk = 0, kInitZero = 1, kInitBad = 2 };
+
+// initialise_trace (Alg. gpu_parallel): project v onto the start face, then
+// extend the ray backwards to the edge it would have entered through, so the
+// walk always starts on an entry edge with remaining length |v_t| + tau.
+SG_HD int ray_init(const DevMesh& M, int32_t f, const float* bp, const float* vp, Ray& st, float& L) {
+    if (f < 0 || (int64_t)f >= M.n_faces) return kInitBad;
+    float b0 = bp[0], b1 = bp[1], b2 = bp[2];
+    if (!(b0 >= 0.f && b1 >= 0.f && b2 >= 0.f)) return kInitBad;
+    const float bs = b0 + b1 + b2;
+    if (!(bs > 0.f) || !__builtin_isfinite(bs)) return kInitBad;
+    const float3 v = ld3(vp);
+    if (!__builtin_isfinite(v.x) || !__builtin_isfinite(v.y) || !__builtin_isfinite(v.z)) return kInitBad;
+    b0 /= bs; b1 /= bs; b2 /= bs;
+    const int64_t f3 = 3 * (int64_t)f;
+    const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
+    const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
+    const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+    const float3 e1 = sub(x1, x0), e2 = sub(x2, x0);
+    const float l0 = sqrtf(dot(e1, e1));
+    const float3 n = nrm(crs(e1, e2));
+    const float3 ex = scl(e1, 1.0f / l0);
+    const float3 ey = crs(n, ex);
+    const float vx = dot(v, ex), vy = dot(v, ey);
+    L = sqrtf(fmaf(vx, vx, vy * vy));
+    if (!(L > 0.f)) return kInitZero;
+    const HalfEdgeRec r0 = M.rec[f3];
+    const uint32_t phi0 = angle_fx(vx, vy);
+    const float dx = vx / L, dy = vy / L;
+    // barycentric rates of the direction in the chart of edge 0
+    const float icy = 1.0f / r0.cy, il0 = 1.0f / l0;
+    const float rc = dy * icy;
+    const float rb = fmaf(dx, il0, -dy * r0.cx * icy * il0);
+    const float ra = -(rb + rc);
+    // a start on a vertex must point into this face's corner there
+    if ((b0 == 0.f) + (b1 == 0.f) + (b2 == 0.f) == 2) {
+        if ((b0 == 0.f && ra < 0.f) || (b1 == 0.f && rb < 0.f) || (b2 == 0.f && rc < 0.f)) return kInitBad;
+    }
+    // backward exit: the first barycentric that reaches 0 going along -d
+    int ie = -1;
+    float tau = 0.f;
+    if (ra > 0.f) { tau = b0 / ra; ie = 0; }
+    if (rb > 0.f) { const float ti = b1 / rb; if (ie < 0 || ti < tau) { tau = ti; ie = 1; } }
+    if (rc > 0.f) { const float ti = b2 / rc; if (ie < 0 || ti < tau) { tau = ti; ie = 2; } }
+    if (ie < 0) return kInitBad;
+    const int k = ie == 2 ? 0 : ie + 1;   // entry edge (F[k], F[k+1]) is opposite vertex ie
+    // barycentrics of the entry point at the two ends of edge k
+    const float bk = k == 0 ? b0 : (k == 1 ? b1 : b2);
+    const float rk = k == 0 ? ra : (k == 1 ? rb : rc);
+    const float bk1 = k == 0 ? b1 : (k == 1 ? b2 : b0);
+    const float rk1 = k == 0 ? rb : (k == 1 ? rc : ra);
+    const float wk = fmaxf(fmaf(-tau, rk, bk), 0.f);
+    const float wk1 = fmaxf(fmaf(-tau, rk1, bk1), 0.f);
+    const float ell = k == 0 ? l0 : (k == 1 ? r0.lbc : r0.lac);
+    const float iw = 1.0f / (wk + wk1);
+    st.s = wk1 * iw * ell;
+    st.t = wk * iw * ell;
+    const uint32_t th = k == 0 ? 0u : (k == 1 ? kPiFx - r0.B : kPiFx + r0.A);
+    uint32_t phi = phi0 - th;
+    if (st.s == 0.f || st.t == 0.f) {
+        // start on a vertex: the direction must point into this face's corner there
+        const uint32_t C0 = kPiFx - r0.A - r0.B;
+        const uint32_t cA = k == 0 ? r0.A : (k == 1 ? r0.B : C0);   // corner at F[k]
+        const uint32_t cB = k == 0 ? r0.B : (k == 1 ? C0 : r0.A);   // corner at F[k+1]
+        if (phi > kPiFx) return kInitBad;
+        if (st.s == 0.f && phi > cA) return kInitBad;
+        if (st.t == 0.f && phi < kPiFx - cB) return kInitBad;
+    } else if (phi > kPiFx) {
+        // a grazing interior start can round just outside [0, pi]
+        phi = phi >= kPiFx + kHalfPiFx ? 0u : kPiFx;
+    }
+    st.phi = phi;
+    st.h = (int32_t)(f3 + k);
+    // remaining length L + tau as a compensated pair (TwoSum)
+    const float sum = L + tau;
+    const float bv = sum - L;
+    st.Lhi = sum;
+    st.Llo = (L - (sum - bv)) + (tau - bv);
+    st.flags = 0u;
+    if (st.s == 0.f) st.flags |= kForceBC;
+    else if (st.t == 0.f) st.flags |= kForceCA;
+    st.ncross = 0;
+    st.hash = fnv_face(14695981039346656037ull, (uint32_t)f);
+    return kInitOk;
+}
+
+enum VertexResult { kVertexDone = 0, kVertexNoSnap = 1, kVertexBoundary = 2 };
+
+// transport_over_vertex: the ray reached vertex x0 of face h/3.  Walk the fan
+// from the reversed incoming direction, adding corner angles, until half the
+// vertex's total angle is reached; leave along the fan edge of that face
+// rotated by the residual.  `at_apex` says x0 is the apex c of the current
+// chart (else x0 is a for a c-a exit, b for a b-c exit).
+SG_HD __forceinline__ int vertex_rule(const DevMesh& M, Ray& st, const HalfEdgeRec& r, bool via_ca,
+                                         bool at_apex, int32_t& x0_out) {
+    const int32_t f = st.h / 3, k = st.h - 3 * (st.h / 3);
+    int xl, hv, roleA;
+    int64_t acc;
+    float ell;
+    if (at_apex) {
+        xl = (k + 2) % 3;
+        if (via_ca) {   // walk from -d towards c->a; virtual entry across b-c, x0 is that chart's b
+            hv = 3 * f + (k + 1) % 3; roleA = 0;
+            acc = (int64_t)(int32_t)(st.phi + r.B - kPiFx);
+            ell = r.lbc;
+        } else {        // walk from -d towards c->b; virtual entry across c-a, x0 is that chart's a
+            hv = 3 * f + (k + 2) % 3; roleA = 1;
+            acc = (int64_t)(int32_t)(r.A - st.phi);
+            ell = r.lac;
+        }
+    } else if (via_ca) {   // passing vertex a: -d points back across a-b
+        xl = k; hv = st.h; roleA = 1;
+        acc = (int64_t)(kPiFx - st.phi);
+        ell = st.s + st.t;
+    } else {               // passing vertex b
+        xl = (k + 1) % 3; hv = st.h; roleA = 0;
+        acc = (int64_t)st.phi;
+        ell = st.s + st.t;
+    }
+    const int32_t x0 = M.F[3 * (int64_t)f + xl];
+    x0_out = x0;
+    const int64_t half = M.half_theta[x0];
+    if (half < 0) return kVertexBoundary;
+    if (!at_apex && acc >= half) return kVertexNoSnap;
+    uint32_t par = st.flags & kParity;
+    for (int guard = 0; guard < 4096; ++guard) {
+        const HalfEdgeRec q = M.rec[hv];
+        const uint32_t corner = roleA ? q.A : q.B;
+        if (acc + (int64_t)corner >= half) {
+            const uint32_t beta = (uint32_t)(half - acc);
+            st.h = hv;
+            st.phi = roleA ? beta : kPiFx - beta;
+            st.s = roleA ? 0.f : ell;
+            st.t = roleA ? ell : 0.f;
+            st.flags = par | (roleA ? kForceBC : kForceCA);
+            return kVertexDone;
+        }
+        acc += corner;
+        const int32_t nx = roleA ? q.nca : q.nbc;
+        ell = roleA ? q.lac : q.lbc;
+        if (nx < 0) return kVertexBoundary;
+        hv = nx >> 1;
+        const uint32_t flip = (uint32_t)nx & 1u;
+        roleA ^= (int)flip;
+        par ^= flip;
+    }
+    return kVertexBoundary;
+}
+
+// Barycentric coordinates of chart point (ex, ey) in face h/3, rotated from
+// chart order (a, b, c) into face vertex order by the entry edge index k.
+SG_HD __forceinline__ void chart_bary(const HalfEdgeRec& r, float ell, float ex, float ey, int k, float& o0,
+                                           float& o1, float& o2) {
+    float bc = ey / r.cy;
+    float bb = (ex - bc * r.cx) / ell;
+    float ba = 1.0f - bb - bc;
+    ba = fmaxf(ba, 0.f); bb = fmaxf(bb, 0.f); bc = fmaxf(bc, 0.f);
+    const float is = 1.0f / (ba + bb + bc);
+    ba *= is; bb *= is; bc *= is;
+    o0 = k == 0 ? ba : (k == 1 ? bc : bb);
+    o1 = k == 0 ? bb : (k == 1 ? ba : bc);
+    o2 = k == 0 ? bc : (k == 1 ? bb : ba);
+}
+
+template <bool kHash>
+SG_HD void exp_ray(const DevMesh& M, const ExpArgs& a, int64_t i) {
+    const int32_t f0 = a.f[i];
+    Ray st;
+    float L = 0.f;
+    const int ir = ray_init(M, f0, a.b + 3 * i, a.v + 3 * i, st, L);
+    if (ir != kInitOk) {
+        const bool bad = ir == kInitBad;
+        a.f_out[i] = f0;
+        float bo[3] = {a.b[3 * i], a.b[3 * i + 1], a.b[3 * i + 2]};
+        float3 p = make_float3(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
+        float3 n = make_float3(0.f, 0.f, 0.f);
+        if (!bad) {
+            const float s = bo[0] + bo[1] + bo[2];
+            bo[0] /= s; bo[1] /= s; bo[2] /= s;
+            const int64_t f3 = 3 * (int64_t)f0;
+            const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
+            const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
+            const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+            p = make_float3(bo[0] * x0.x + bo[1] * x1.x + bo[2] * x2.x, bo[0] * x0.y + bo[1] * x1.y + bo[2] * x2.y,
+                            bo[0] * x0.z + bo[1] * x1.z + bo[2] * x2.z);
+            n = nrm(crs(sub(x1, x0), sub(x2, x0)));
+        }
+        for (int c = 0; c < 3; ++c) a.b_out[3 * i + c] = bo[c];
+        a.p_out[3 * i] = p.x; a.p_out[3 * i + 1] = p.y; a.p_out[3 * i + 2] = p.z;
+        const float vz = bad ? __builtin_nanf("") : 0.f;
+        a.v_out[3 * i] = vz; a.v_out[3 * i + 1] = vz; a.v_out[3 * i + 2] = vz;
+        for (int kk = 0; kk < a.K; ++kk) {
+            const float3 w = ld3(a.W + 3 * (i * a.K + kk));
+            const float3 wt = bad ? make_float3(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""))
+                                  : sub(w, scl(n, dot(w, n)));
+            float* o = a.W_out + 3 * (i * a.K + kk);
+            o[0] = wt.x; o[1] = wt.y; o[2] = wt.z;
+        }
+        if (a.status) a.status[i] = bad ? kRayBadInput : kRayOk;
+        if (a.n_cross) a.n_cross[i] = 0;
+        if (a.seq_hash) a.seq_hash[i] = bad ? 0ull : fnv_face(14695981039346656037ull, (uint32_t)f0);
+        return;
+    }
+
+    int32_t status = kRayOk;
+    float ex = 0.f, ey = 0.f;   // stop point in the final chart
+    HalfEdgeRec r;
+    for (;;) {
+        r = M.rec[st.h];
+        float sn, cs;
+        sincos_fx(st.phi, sn, cs);
+        const float cross = fmaf(cs, r.cy, -sn * (r.cx - st.s));
+        const uint32_t force = st.flags & kForceMask;
+        const bool via_ca = force ? (force == kForceCA) : (cross < 0.f);
+        const float w = via_ca ? st.s : st.t;
+        const float acr = fabsf(cross);
+        const float D = fmaf(w, sn, acr);
+        const float rD = 1.0f / D;
+        const float lam = w * r.cy * rD;
+        const float Lr = st.Lhi + st.Llo;
+        if (!(lam < Lr)) {   // the ray ends inside this face (ties stay in the face)
+            ex = fmaf(Lr, cs, st.s);
+            ey = Lr * sn;
+            break;
+        }
+        if (st.ncross >= a.max_steps) {
+            status = kRayMaxSteps;
+            ex = st.s;
+            ey = 0.f;
+            break;
+        }
+        const float mu = w * sn * rD;     // exit point: fraction from the edge's non-apex end
+        const float omu = acr * rD;       // 1 - mu: fraction from the apex
+        const int32_t nx = via_ca ? r.nca : r.nbc;
+        if (omu < a.snap || mu < a.snap) {
+            int32_t x0;
+            Ray cand = st;
+            const int vr = vertex_rule(M, cand, r, via_ca, omu < a.snap, x0);
+            if (vr == kVertexBoundary) {
+                status = kRayBoundary;
+                const bool at_apex = omu < a.snap;
+                ex = at_apex ? r.cx : (via_ca ? 0.f : st.s + st.t);
+                ey = at_apex ? r.cy : 0.f;
+                break;
+            }
+            if (vr == kVertexDone) {
+                // the vertex lies lam along the ray; consume it exactly as an edge crossing would
+                const float nh = st.Lhi - lam;
+                cand.Llo = st.Llo + ((st.Lhi - nh) - lam);
+                cand.Lhi = nh;
+                cand.ncross = st.ncross + 1;
+                cand.hash = kHash ? fnv_face(st.hash, (uint32_t)(cand.h / 3)) : 0ull;
+                st = cand;
+                continue;
+            }
+        }
+        if (nx < 0) {   // boundary edge: stop on it (Sec. 4, original behaviour)
+            status = kRayBoundary;
+            ex = fmaf(lam, cs, st.s);
+            ey = lam * sn;
+            break;
+        }
+        {
+            const float nh = st.Lhi - lam;
+            st.Llo += (st.Lhi - nh) - lam;
+            st.Lhi = nh;
+        }
+        const uint32_t flip = (uint32_t)nx & 1u;
+        const float len = via_ca ? r.lac : r.lbc;
+        const float dm = mu * len, dom = omu * len;
+        float sn2 = via_ca ? dm : dom;
+        float tn2 = via_ca ? dom : dm;
+        uint32_t ph = via_ca ? st.phi - r.A : st.phi + r.B;
+        if (flip) {
+            const float tmp = sn2; sn2 = tn2; tn2 = tmp;
+            ph = kPiFx - ph;
+        }
+        // keep the direction inside [0, pi] against rounding of grazing exits
+        const int32_t phs = (int32_t)ph;
+        st.phi = (uint32_t)(phs < 0 ? 0 : phs);
+        st.s = sn2;
+        st.t = tn2;
+        st.h = nx >> 1;
+        st.flags = (st.flags & kParity) ^ flip;
+        st.ncross += 1;
+        if (kHash) st.hash = fnv_face(st.hash, (uint32_t)(st.h / 3));
+    }
+
+    // ---- epilogue: end face, barycentrics, 3D point and transported vectors
+    const int32_t fe = st.h / 3;
+    const int ke = st.h - 3 * fe;
+    const float ell = st.s + st.t;
+    float bo[3];
+    chart_bary(r, ell, ex, ey, ke, bo[0], bo[1], bo[2]);
+    const int64_t f3 = 3 * (int64_t)fe;
+    const float3 y0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
+    const float3 y1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
+    const float3 y2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+    a.f_out[i] = fe;
+    a.b_out[3 * i] = bo[0]; a.b_out[3 * i + 1] = bo[1]; a.b_out[3 * i + 2] = bo[2];
+    a.p_out[3 * i] = fmaf(bo[0], y0.x, fmaf(bo[1], y1.x, bo[2] * y2.x));
+    a.p_out[3 * i + 1] = fmaf(bo[0], y0.y, fmaf(bo[1], y1.y, bo[2] * y2.y));
+    a.p_out[3 * i + 2] = fmaf(bo[0], y0.z, fmaf(bo[1], y1.z, bo[2] * y2.z));
+    // 3D tangent frame of the final chart
+    const float3 ya = ke == 0 ? y0 : (ke == 1 ? y1 : y2);
+    const float3 yb = ke == 0 ? y1 : (ke == 1 ? y2 : y0);
+    const float3 yc = ke == 0 ? y2 : (ke == 1 ? y0 : y1);
+    const float3 eab = sub(yb, ya);
+    const float3 ex3 = nrm(eab);
+    const float3 n3 = nrm(crs(eab, sub(yc, ya)));
+    const float3 ey3 = crs(n3, ex3);
+    float sn, cs;
+    sincos_fx(st.phi, sn, cs);
+    const float3 d3 = make_float3(fmaf(cs, ex3.x, sn * ey3.x), fmaf(cs, ex3.y, sn * ey3.y), fmaf(cs, ex3.z, sn * ey3.z));
+    a.v_out[3 * i] = L * d3.x; a.v_out[3 * i + 1] = L * d3.y; a.v_out[3 * i + 2] = L * d3.z;
+    if (a.K > 0) {
+        // signed angle of each extra vector to the start tangent, about the start normal
+        const int64_t g3 = 3 * (int64_t)f0;
+        const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[g3]);
+        const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[g3 + 1]);
+        const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[g3 + 2]);
+        const float3 n0 = nrm(crs(sub(x1, x0), sub(x2, x0)));
+        const float3 v = ld3(a.v + 3 * i);
+        const float3 d0 = nrm(sub(v, scl(n0, dot(v, n0))));
+        const float3 q0 = crs(n0, d0);
+        const float sg = (st.flags & kParity) ? -1.0f : 1.0f;
+        const float3 q3 = scl(crs(n3, d3), sg);
+        for (int kk = 0; kk < a.K; ++kk) {
+            const float3 w = ld3(a.W + 3 * (i * a.K + kk));
+            const float wx = dot(w, d0), wy = dot(w, q0);
+            float* o = a.W_out + 3 * (i * a.K + kk);
+            o[0] = fmaf(wx, d3.x, wy * q3.x);
+            o[1] = fmaf(wx, d3.y, wy * q3.y);
+            o[2] = fmaf(wx, d3.z, wy * q3.z);
+        }
+    }
+    if (a.status) a.status[i] = status;
+    if (a.n_cross) a.n_cross[i] = st.ncross;
+    if (a.seq_hash) a.seq_hash[i] = kHash ? st.hash : 0ull;
+}
+
+template <bool kHash>
+__global__ __launch_bounds__(256) void k_exp_plain(DevMesh M, ExpArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    exp_ray<kHash>(M, a, i);
+}
+
+}  // namespace
+
+hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    const int block = 256;
+    const int64_t grid = (a.n + block - 1) / block;
+    if (a.debug & 2u)
+        hipLaunchKernelGGL(k_exp_plain<true>, dim3((unsigned)grid), dim3(block), 0, s, M, a);
+    else
+        hipLaunchKernelGGL(k_exp_plain<false>, dim3((unsigned)grid), dim3(block), 0, s, M, a);
+    return hipGetLastError();
+}
+
+}  // namespace sg

@@ -1,0 +1,49 @@
+// sg_launch.h -- launch interface between the C ABI (host) and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "sg_internal.h"
+
+namespace sg {
+
+struct ExpArgs {
+    int64_t n;
+    const int32_t* f;
+    const float* b;
+    const float* v;
+    int32_t K;
+    const float* W;
+    int32_t* f_out;
+    float* b_out;
+    float* p_out;
+    float* v_out;
+    float* W_out;
+    int32_t* status;
+    int32_t* n_cross;
+    uint64_t* seq_hash;
+    int32_t max_steps;
+    float snap;
+    uint32_t debug;
+};
+
+// Host-side result of packing a mesh (float64 work, rounded once).
+struct PackedMesh {
+    std::vector<HalfEdgeRec> rec;
+    std::vector<int32_t> F;
+    std::vector<float> X;
+    std::vector<int64_t> half;
+    int64_t n_verts = 0, n_faces = 0;
+    double mean_edge = 0.0;
+};
+
+// Validates and packs a mesh on the host; returns SG_OK or an SG_E_* code.
+int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64_t n_faces,
+              const int64_t* vert_offsets, const int64_t* face_offsets, int32_t n_meshes, PackedMesh& out);
+
+// Plain forward: one ray per lane, run to completion (Alg. gpu_parallel).
+hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s);
+
+}  // namespace sg

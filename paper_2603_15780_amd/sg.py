@@ -1,0 +1,156 @@
+"""Python binding of libsg.so (include/sg.h): argument marshalling only.
+
+Every step of the exponential map runs in the library's gfx950 kernels.
+PyTorch supplies device memory and the current HIP stream.  If the library
+is missing this module raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+SG_OK = 0
+SG_E_ARG, SG_E_NONMANIFOLD, SG_E_DEGENERATE, SG_E_HIP, SG_E_OOM = -1, -2, -3, -4, -5
+RAY_OK, RAY_MAXSTEPS, RAY_BOUNDARY, RAY_BADINPUT = 0, 1, 2, 3
+KERNEL_AUTO, KERNEL_PLAIN, KERNEL_PERSISTENT = 0, 1, 2
+BWD_EP, BWD_GFD = 0, 1
+
+_lib = None
+
+
+class SgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sg error {code}: {msg}")
+        self.code = code
+
+
+class Opts(C.Structure):
+    _fields_ = [("max_steps", C.c_int32), ("vertex_snap", C.c_float), ("eps_v", C.c_float),
+                ("eps_p", C.c_float), ("kernel", C.c_int32), ("debug", C.c_uint32)]
+
+
+def lib_path() -> str:
+    return _build.LIB
+
+
+def lib():
+    """Loads libsg.so; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            raise ImportError(f"libsg.so not built at {_build.LIB}; run __graft_entry__.build()")
+        L = C.CDLL(_build.LIB)
+        P, I64, I32 = C.c_void_p, C.c_int64, C.c_int32
+        L.sg_last_error.restype = C.c_char_p
+        L.sg_opts_default.argtypes = [C.POINTER(Opts)]
+        L.sg_mesh_create.argtypes = [P, I64, P, I64, P, P, I32, C.POINTER(C.c_void_p)]
+        L.sg_mesh_create.restype = C.c_int
+        L.sg_mesh_destroy.argtypes = [P]
+        L.sg_mesh_info.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]
+        L.sg_mesh_info.restype = C.c_int
+        L.sg_exp.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P, C.POINTER(Opts), P]
+        L.sg_exp.restype = C.c_int
+        L.sg_exp_transport.argtypes = [P, I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, C.POINTER(Opts), P]
+        L.sg_exp_transport.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != SG_OK:
+        raise SgError(rc, lib().sg_last_error().decode())
+
+
+def opts(**kw) -> Opts:
+    o = Opts()
+    lib().sg_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Mesh:
+    """A packed mesh handle (one or several meshes batched by offsets)."""
+
+    def __init__(self, X, F, vert_offsets=None, face_offsets=None):
+        L = lib()
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        F = np.ascontiguousarray(F, dtype=np.int32)
+        h = C.c_void_p()
+        if vert_offsets is None:
+            rc = L.sg_mesh_create(_np_ptr(X), X.shape[0], _np_ptr(F), F.shape[0], None, None, 1, C.byref(h))
+        else:
+            vo = np.ascontiguousarray(vert_offsets, dtype=np.int64)
+            fo = np.ascontiguousarray(face_offsets, dtype=np.int64)
+            rc = L.sg_mesh_create(_np_ptr(X), X.shape[0], _np_ptr(F), F.shape[0], _np_ptr(vo), _np_ptr(fo),
+                                  vo.shape[0] - 1, C.byref(h))
+        _check(rc)
+        self._h = h
+        self.n_verts, self.n_faces = X.shape[0], F.shape[0]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sg_mesh_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def info(self):
+        me = C.c_double()
+        nh = C.c_int64()
+        nb = C.c_size_t()
+        _check(lib().sg_mesh_info(self._h, C.byref(me), C.byref(nh), C.byref(nb)))
+        return dict(mean_edge=me.value, n_half_edges=nh.value, device_bytes=nb.value)
+
+    def exp(self, f, b, v, W=None, *, out=None, want_status=True, want_cross=False, want_hash=False,
+            o: Opts | None = None, **kw):
+        """Exp_p(v) for torch CUDA tensors f[n] int32, b[n,3], v[n,3] (float32), W[n,K,3]."""
+        import torch
+        n = f.shape[0]
+        dev = f.device
+        assert f.dtype == torch.int32 and b.dtype == torch.float32 and v.dtype == torch.float32
+        assert f.is_contiguous() and b.is_contiguous() and v.is_contiguous()
+        assert b.shape == (n, 3) and v.shape == (n, 3)
+        K = 0 if W is None else W.shape[1]
+        if W is not None:
+            assert W.dtype == torch.float32 and W.is_contiguous() and W.shape == (n, K, 3)
+        if o is None:
+            o = opts(**kw)
+        if want_cross:
+            o.debug |= 1
+        if want_hash:
+            o.debug |= 2
+        if out is None:
+            out = dict(
+                f=torch.empty(n, dtype=torch.int32, device=dev),
+                b=torch.empty(n, 3, dtype=torch.float32, device=dev),
+                p=torch.empty(n, 3, dtype=torch.float32, device=dev),
+                v=torch.empty(n, 3, dtype=torch.float32, device=dev),
+                W=torch.empty(n, K, 3, dtype=torch.float32, device=dev) if K else None,
+                status=torch.empty(n, dtype=torch.int32, device=dev) if want_status else None,
+                n_cross=torch.empty(n, dtype=torch.int32, device=dev) if want_cross else None,
+                hash=torch.empty(n, dtype=torch.int64, device=dev) if want_hash else None,
+            )
+        rc = lib().sg_exp_transport(
+            self._h, n, _dptr(f), _dptr(b), _dptr(v), K, _dptr(W), _dptr(out["f"]), _dptr(out["b"]),
+            _dptr(out["p"]), _dptr(out["v"]), _dptr(out.get("W")), _dptr(out.get("status")),
+            _dptr(out.get("n_cross")), _dptr(out.get("hash")), C.byref(o), _stream())
+        _check(rc)
+        return out

@@ -1,0 +1,67 @@
+"""Parity criteria between the GPU float32 walk and the float64 oracle.
+
+Tolerances (endpoint 1e-4 x mean edge for at least 99.9% of rays; face and
+face-sequence divergence only where the float64 path passes within 1e-6 of a
+vertex; transported-vector angle 1e-4 rad) are the spec bar for the
+float32 tracer.  Where several answers are correct (an endpoint on a shared
+edge may be reported in either face; paths through a vertex neighbourhood may
+split) the unique part is compared and the rest is checked for validity.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+NEAR_VERTEX = 1e-6
+
+
+def _angle(a, b):
+    """Angle between vectors along the last axis, float64, accurate near 0."""
+    c = np.cross(a, b)
+    return np.arctan2(np.linalg.norm(c, axis=-1), np.einsum("...c,...c->...", a, b))
+
+
+def report(o, g, me, K=0):
+    """Returns a dict of parity statistics (o: oracle dict, g: GPU dict of numpy arrays)."""
+    err = np.linalg.norm(g["p"].astype(np.float64) - o["p"], axis=1)
+    tol = 1e-4 * me
+    near = o["min_vdist"] < NEAR_VERTEX
+    bad = err > tol
+    face_mis = g["f"] != o["f"]
+    # an endpoint within tolerance of an edge may be reported in either face
+    on_edge = (np.min(o["b"], axis=1) * me < 2 * tol) | (np.min(g["b"], axis=1) * me < 2 * tol)
+    out = dict(n=len(err), tol=tol, frac_ok=1.0 - bad.mean(), bad_not_near=int(np.sum(bad & ~near)),
+               face_mis_unexplained=int(np.sum(face_mis & ~near & ~(on_edge & ~bad))),
+               status_mis=int(np.sum((g["status"] != o["status"]) & ~near)),
+               err_max_far=float(err[~near].max()) if np.any(~near) else 0.0,
+               err_p999=float(np.percentile(err, 99.9)), err_median=float(np.median(err)))
+    if "n_cross" in g and g["n_cross"] is not None:
+        out["cross_mis_far"] = int(np.sum((g["n_cross"] != o["n_cross"]) & ~near))
+    if "hash" in g and g["hash"] is not None:
+        out["hash_mis_far"] = int(np.sum((g["hash"].astype(np.uint64) != o["hash"]) & ~near))
+    if K:
+        same = (g["f"] == o["f"]) & ~near
+        gw, ow = g["W"].astype(np.float64), o["W"]
+        ang = _angle(gw, ow)
+        out["W_angle_max"] = float(ang[same].max()) if same.any() else 0.0
+        out["W_norm_err"] = float(np.abs(np.linalg.norm(gw, axis=2) - np.linalg.norm(ow, axis=2))[same].max()) if same.any() else 0.0
+    vang = _angle(g["v"].astype(np.float64), o["v"])
+    sel = (g["f"] == o["f"]) & ~near & (np.linalg.norm(o["v"], axis=1) > 0)
+    out["v_angle_max"] = float(vang[sel].max()) if sel.any() else 0.0
+    return out
+
+
+def assert_parity(o, g, me, K=0, label=""):
+    s = report(o, g, me, K)
+    msg = f"{label}: {s}"
+    assert s["frac_ok"] >= 0.999, msg
+    assert s["bad_not_near"] == 0, msg
+    assert s["face_mis_unexplained"] == 0, msg
+    assert s["status_mis"] == 0, msg
+    if "hash_mis_far" in s:
+        assert s["hash_mis_far"] == 0, msg
+    if "cross_mis_far" in s:
+        assert s["cross_mis_far"] == 0, msg
+    if K:
+        assert s["W_angle_max"] <= 1e-4, msg
+    assert s["v_angle_max"] <= 1e-4, msg
+    return s

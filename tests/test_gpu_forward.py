@@ -1,0 +1,240 @@
+"""GPU parity of the forward walk (sg_exp / sg_exp_transport) against the oracle.
+
+Runs through the C ABI (ctypes binding) on cuda:0.  Sizes span several
+256-lane blocks with ragged tails; the config-2 case runs the full
+1,048,576-ray batch in the benchmark's launch configuration and checks a
+sample of rows against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from parity import assert_parity, report
+from workloads import configs as CF
+from workloads import meshes as M
+from workloads.rays import random_rays, uniform_len
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU test needs a HIP device"
+    return T
+
+
+def run(torch, mesh, r, K=None, **kw):
+    dev = torch.device("cuda:0")
+    f = torch.from_numpy(np.ascontiguousarray(r["f"], np.int32)).to(dev)
+    b = torch.from_numpy(np.ascontiguousarray(r["b"], np.float32)).to(dev)
+    v = torch.from_numpy(np.ascontiguousarray(r["v"], np.float32)).to(dev)
+    W = None
+    if r.get("W") is not None and r["W"].shape[1] > 0:
+        W = torch.from_numpy(np.ascontiguousarray(r["W"], np.float32)).to(dev)
+    out = mesh.exp(f, b, v, W, want_cross=True, want_hash=True, **kw)
+    torch.cuda.synchronize()
+    g = {k: (t.cpu().numpy() if t is not None else None) for k, t in out.items()}
+    g["hash"] = g["hash"].view(np.uint64)
+    return g
+
+
+def both(torch, X, F, r, **kw):
+    from paper_2603_15780_amd import sg
+    om = oracle.Mesh(X, F)
+    gm = sg.Mesh(X, F)
+    o = om.exp(r["f"], r["b"], r["v"], r["W"] if r["W"].shape[1] else None)
+    g = run(torch, gm, r, **kw)
+    return om, gm, o, g
+
+
+def test_config1_parity(torch):
+    X, F = CF.mesh_config(1)
+    r = CF.rays_config(1, X, F)
+    om, gm, o, g = both(torch, X, F, r)
+    assert abs(gm.info()["mean_edge"] - om.mean_edge) < 1e-12
+    s = assert_parity(o, g, om.mean_edge, K=1, label="config1")
+    assert s["hash_mis_far"] == 0
+
+
+@pytest.mark.parametrize("n", [1, 63, 255, 257, 1000, 4097])
+def test_ragged_sizes(torch, n):
+    X, F = CF.mesh_config(1)
+    r = random_rays(X, F, n, np.random.default_rng(n), uniform_len(0.0, 2.0), K=2)
+    om, gm, o, g = both(torch, X, F, r)
+    s = report(o, g, om.mean_edge, K=2)
+    assert s["bad_not_near"] == 0 and s["face_mis_unexplained"] == 0, s
+
+
+def test_config2_full_batch_sampled(torch):
+    """1,048,576 rays on the 327,680-face displaced icosphere, K = 2, sampled rows vs oracle."""
+    X, F = CF.mesh_config(2)
+    r = CF.rays_config(2, X, F)
+    from paper_2603_15780_amd import sg
+    gm = sg.Mesh(X, F)
+    g = run(torch, gm, r)
+    rows = np.arange(0, r["f"].shape[0], 8)   # 131,072 sampled rays
+    om = oracle.Mesh(X, F)
+    o = om.exp(r["f"][rows], r["b"][rows], r["v"][rows], r["W"][rows])
+    gs = {k: (a[rows] if a is not None else None) for k, a in g.items()}
+    s = assert_parity(o, gs, om.mean_edge, K=2, label="config2")
+    print("config2", s)
+    # the rest of the batch: properties that hold at any size
+    L = np.linalg.norm(r["v"].astype(np.float64), axis=1)
+    assert np.all(g["status"] == 0)
+    assert np.abs(np.linalg.norm(g["v"], axis=1) - L).max() < 1e-5
+    assert np.abs(np.linalg.norm(g["W"], axis=2) - 1.0).max() < 1e-5
+    assert np.all((g["b"] >= 0) & (g["b"] <= 1))
+    assert np.abs(g["b"].sum(1) - 1).max() < 1e-5
+
+
+def test_displaced_and_torus(torch):
+    X, F = M.icosphere(4)
+    X, F = M.canonical(M.sh_displace(X, 8, 0.15, np.random.default_rng(11)), F)
+    r = random_rays(X, F, 20000, np.random.default_rng(12), uniform_len(0.0, 2.0), K=2)
+    om, gm, o, g = both(torch, X, F, r)
+    assert_parity(o, g, om.mean_edge, K=2, label="displaced")
+    X, F = M.canonical(*M.torus_grid(120, 40, 0.2, np.random.default_rng(13)))
+    r = random_rays(X, F, 20000, np.random.default_rng(14), uniform_len(0.0, 3.0), K=1)
+    om, gm, o, g = both(torch, X, F, r)
+    assert_parity(o, g, om.mean_edge, K=1, label="torus")
+
+
+def test_flat_plane_closed_form(torch):
+    """Sec. 4: theta = 2 pi, so Exp_p(v) = p + v, also for rays aimed through vertices."""
+    from paper_2603_15780_amd import sg
+    X, F = M.canonical(*M.flat_grid(24, 0.3, np.random.default_rng(1), size=24.0))
+    Xd = X.astype(np.float64)
+    inner = [f for f in range(F.shape[0]) if np.all(np.abs(Xd[F[f]][:, :2] - 12.0).max(1) < 5)]
+    r = random_rays(X, F, 3000, np.random.default_rng(2), uniform_len(0.0, 6.0), K=1, faces=inner)
+    b = r["b"].astype(np.float64)
+    p0 = (b[:, :, None] * Xd[F[r["f"]]]).sum(1) / b.sum(1)[:, None]
+    vids = np.resize([i for i in range(X.shape[0]) if np.abs(Xd[i, :2] - 12.0).max() < 4.0], 500)
+    r["v"][:500] = ((Xd[vids] - p0[:500]) * 1.3).astype(np.float32)
+    g = run(torch, sg.Mesh(X, F), r)
+    pe = p0 + r["v"].astype(np.float64)
+    me = M.mean_edge(X, F)
+    assert np.all(g["status"] == 0)
+    assert np.abs(g["p"] - pe).max() < 1e-4 * me
+    assert np.abs(g["W"] - r["W"]).max() < 1e-5
+
+
+@pytest.mark.parametrize("a", [0.1, 0.4, 0.7, 1.2, 1.45])
+def test_cube_corner_closed_form(torch, a):
+    """Vertex rule on a cone (theta = 3 pi / 2): the ray leaves 3 pi / 4 from -d."""
+    from paper_2603_15780_amd import sg
+    X, F = M.canonical(*M.cube_grid(2, 1.0))
+    Xd = X.astype(np.float64)
+    c = np.array([1.0, 1.0, 1.0])
+    d = np.array([np.cos(a), np.sin(a), 0.0])
+    D, rr = 0.8, 0.6
+    p = c - D * d
+    best = None
+    for f in range(F.shape[0]):
+        if not np.all(Xd[F[f], 2] == 1.0):
+            continue
+        x0, x1, x2 = Xd[F[f]]
+        l = np.linalg.lstsq(np.column_stack([x1 - x0, x2 - x0]), p - x0, rcond=None)[0]
+        bb = np.array([1 - l.sum(), l[0], l[1]])
+        if bb.min() >= -1e-12:
+            best = (f, np.clip(bb, 0, None))
+            break
+    f, bb = best
+    r = dict(f=np.array([f], np.int32), b=bb[None].astype(np.float32), v=((D + rr) * d)[None].astype(np.float32),
+             W=np.zeros((1, 0, 3), np.float32))
+    g = run(torch, sg.Mesh(X, F), r)
+    if a <= np.pi / 4:
+        out = np.cos(np.pi / 4 + a) * np.array([0, -1.0, 0]) + np.sin(np.pi / 4 + a) * np.array([0, 0, -1.0])
+    else:
+        out = np.cos(3 * np.pi / 4 - a) * np.array([-1.0, 0, 0]) + np.sin(3 * np.pi / 4 - a) * np.array([0, 0, -1.0])
+    assert g["status"][0] == 0
+    assert np.abs(g["p"][0] - (c + rr * out)).max() < 1e-5
+
+
+def test_edge_cases(torch):
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    gm = sg.Mesh(X, F)
+    om = oracle.Mesh(X, F)
+    r = random_rays(X, F, 64, np.random.default_rng(3), uniform_len(0.5, 1.5), K=1)
+    # empty batch is a no-op
+    e = dict(f=r["f"][:0], b=r["b"][:0], v=r["v"][:0], W=r["W"][:0])
+    g = run(torch, gm, e)
+    assert g["f"].shape == (0,)
+    # bad inputs and zero length
+    rb = {k: v.copy() for k, v in r.items() if k in ("f", "b", "v", "W")}
+    rb["f"][0] = F.shape[0]
+    rb["f"][1] = -1
+    rb["b"][2] = [np.nan, 0.5, 0.5]
+    rb["b"][3] = [-0.1, 0.6, 0.5]
+    rb["v"][4] = [np.inf, 0, 0]
+    rb["v"][5] = 0.0
+    g = run(torch, gm, rb)
+    o = om.exp(rb["f"], rb["b"], rb["v"], rb["W"])
+    assert list(g["status"][:5]) == [3, 3, 3, 3, 3] and list(o["status"][:5]) == [3, 3, 3, 3, 3]
+    assert g["status"][5] == 0 and g["n_cross"][5] == 0 and g["f"][5] == rb["f"][5]
+    assert np.abs(g["p"][5] - o["p"][5]).max() < 1e-6
+    assert np.all(g["v"][5] == 0)
+    # max_steps: stop after one crossing
+    g = run(torch, gm, r, max_steps=1)
+    o = om.exp(r["f"], r["b"], r["v"], max_steps=1)
+    assert np.array_equal(g["status"], o["status"]) and np.any(g["status"] == 1)
+    assert np.array_equal(g["f"], o["f"])
+    assert np.abs(g["p"] - o["p"]).max() < 1e-5
+    # vertex starts: into the corner is traced, out of the face is rejected
+    rv = {k: v[:2].copy() for k, v in r.items() if k in ("f", "b", "v", "W")}
+    x0, x1, x2 = X[F[rv["f"][0]]].astype(np.float64)
+    rv["b"][:] = [1.0, 0.0, 0.0]
+    inside = 0.5 * ((x1 - x0) / np.linalg.norm(x1 - x0) + (x2 - x0) / np.linalg.norm(x2 - x0))
+    rv["v"][0] = (0.3 * inside / np.linalg.norm(inside)).astype(np.float32)
+    rv["v"][1] = (-rv["v"][0]).astype(np.float32)
+    rv["f"][1] = rv["f"][0]
+    g = run(torch, gm, rv)
+    o = om.exp(rv["f"], rv["b"], rv["v"])
+    assert list(o["status"]) == [0, 3] and list(g["status"]) == [0, 3]
+    assert np.abs(g["p"][0] - o["p"][0]).max() < 1e-5
+
+
+def test_boundary_stop(torch):
+    from paper_2603_15780_amd import sg
+    X, F = M.icosphere(3)
+    X, F = M.remove_faces(X, F, np.where((F == 0).any(1) | (F == 7).any(1) | (F == 100).any(1))[0])
+    X, F = M.canonical(X, F)
+    r = random_rays(X, F, 5000, np.random.default_rng(4), uniform_len(0.5, 3.0), K=1)
+    om, gm, o, g = both(torch, X, F, r)
+    assert np.any(o["status"] == 2)
+    assert_parity(o, g, om.mean_edge, K=1, label="holes")
+
+
+def test_multi_mesh_offsets(torch):
+    from paper_2603_15780_amd import sg
+    X1, F1 = CF.mesh_config(1)
+    X2, F2 = M.canonical(*M.torus_grid(60, 20, 0.2, np.random.default_rng(5)))
+    X = np.concatenate([X1, X2])
+    F = np.concatenate([F1, F2])
+    vo = np.array([0, X1.shape[0], X.shape[0]])
+    fo = np.array([0, F1.shape[0], F.shape[0]])
+    gm = sg.Mesh(X, F, vo, fo)
+    r1 = random_rays(X1, F1, 3000, np.random.default_rng(6), uniform_len(0.0, 1.5), K=1)
+    r2 = random_rays(X2, F2, 3000, np.random.default_rng(7), uniform_len(0.0, 2.0), K=1)
+    r = {k: np.concatenate([r1[k], r2[k] + (F1.shape[0] if k == "f" else 0)]) for k in ("f", "b", "v", "W")}
+    g = run(torch, gm, r)
+    o1 = oracle.Mesh(X1, F1).exp(r1["f"], r1["b"], r1["v"], r1["W"])
+    o2 = oracle.Mesh(X2, F2).exp(r2["f"], r2["b"], r2["v"], r2["W"])
+    g1 = {k: (a[:3000] if a is not None else None) for k, a in g.items()}
+    g2 = {k: (a[3000:] if a is not None else None) for k, a in g.items()}
+    g2["f"] = g2["f"] - F1.shape[0]
+    g2["hash"] = None
+    assert_parity(o1, g1, M.mean_edge(X1, F1), K=1, label="mesh1")
+    assert_parity(o2, g2, M.mean_edge(X2, F2), K=1, label="mesh2")
+
+
+def test_deterministic(torch):
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    gm = sg.Mesh(X, F)
+    r = CF.rays_config(1, X, F)
+    a = run(torch, gm, r)
+    b = run(torch, gm, r)
+    for k in ("f", "b", "p", "v", "W", "status", "n_cross", "hash"):
+        assert np.array_equal(a[k], b[k]), k
