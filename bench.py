@@ -97,7 +97,8 @@ def main():
         import oracle
         nc = args.cpu_rays or n
         om = oracle.Mesh(X, F)
-        cores = os.cpu_count()
+        # the machine's CPU share is given by OMP_NUM_THREADS when set
+        cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
         c0 = time.perf_counter()
         oo = om.exp(r["f"][:nc], r["b"][:nc], r["v"][:nc], r["W"][:nc], nthreads=cores)
         c1 = time.perf_counter()
