@@ -41,6 +41,8 @@ def main():
     ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 plain, 2 persistent")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=0, help="oracle sample size (0: whole batch)")
+    ap.add_argument("--no-plain", action="store_true", help="skip timing the plain kernel for comparison")
+    ap.add_argument("--calib-copy", type=int, default=0, help="MiB copied once to calibrate byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -66,30 +68,44 @@ def main():
         p=torch.empty(n, 3, device=dev), v=torch.empty(n, 3, device=dev),
         W=torch.empty(n, K, 3, device=dev), status=torch.empty(n, dtype=torch.int32, device=dev),
         n_cross=torch.empty(n, dtype=torch.int32, device=dev), hash=None)
-    o = sg.opts(kernel=args.kernel, debug=1)
+    def timed(kernel, steps, warmup):
+        """(wall ms per call, event ms per call, walk-kernel event ms per launch or None)."""
+        o = sg.opts(kernel=kernel, debug=1 | (4 if kernel != 1 else 0))
+        for _ in range(warmup):
+            mesh.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=o)
+        torch.cuda.synchronize()
+        mesh.walk_time()   # drop the warm-up launches
+        stream = torch.cuda.current_stream()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(steps):
+            mesh.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=o)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        w1 = time.perf_counter()
+        wms, wn = mesh.walk_time()
+        return (w1 - w0) * 1e3 / steps, ev0.elapsed_time(ev1) / steps, (wms / wn if wn else None)
 
-    def step():
-        mesh.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=o)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    w1 = time.perf_counter()
-    ms_step = (w1 - w0) * 1e3 / args.steps
-    ms_kernel = ev0.elapsed_time(ev1) / args.steps
+    ms_step, ms_call, ms_walk = timed(args.kernel, args.steps, args.warmup)
+    # dominant kernel: the persistent walk (events the library records around it), or the plain kernel
+    ms_kernel = ms_walk if ms_walk is not None else ms_call
     gpu_cross = int(out["n_cross"].sum().item())
     n_ok = int((out["status"] == 0).sum().item())
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step (events {ms_kernel:.3f} ms), "
+    log(f"timed {args.steps} steps (kernel {args.kernel}): {ms_step:.3f} ms/step (events {ms_kernel:.3f} ms), "
         f"GPU crossings {gpu_cross}, status ok {n_ok}/{n}")
+    plain = None
+    if args.kernel != 1 and not args.no_plain:
+        ms_p, ms_pk, _ = timed(1, max(3, args.steps // 4), 1)
+        plain = {"ms_per_call": ms_p, "events_ms": ms_pk}
+        log(f"plain one-ray-per-lane kernel: {ms_p:.3f} ms/call")
+    if args.calib_copy:
+        # a plain copy of known size, profiled beside the walk to scale the HBM byte counters
+        src = torch.empty(args.calib_copy << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy} MiB read + {args.calib_copy} MiB written")
 
     cross = gpu_cross
     cpu = None
@@ -111,7 +127,12 @@ def main():
         log(f"oracle: {ocross} crossings in {c1 - c0:.2f}s on {cores} threads; GPU/oracle crossing ratio "
             f"{gpu_cross / max(ocross, 1) if nc == n else float('nan'):.6f}")
 
-    algo_bytes = cross * BYTES_PER_CROSSING + n * (144 + 24 * K)
+    # algorithmic bytes: 16 per crossing (next face's shape in the crossed edge's frame and its two
+    # onward links); per ray the walk kernel reads and writes a 32-byte chart state, while the whole
+    # forward call reads the query and writes the answer (144 + 24 K bytes)
+    walk_bytes = cross * BYTES_PER_CROSSING + n * 64
+    call_bytes = cross * BYTES_PER_CROSSING + n * (144 + 24 * K)
+    algo_bytes = walk_bytes if ms_walk is not None else call_bytes
     achieved = algo_bytes / (ms_kernel * 1e-3) / 1e9
     res = {
         "metric": METRIC,
@@ -131,12 +152,17 @@ def main():
                          "|v|~U[0,pi/2], K=2 transported; forward only" if args.config == 2 else
                          "icosphere level 3 (1,280 faces); 8,192 rays, |v|~U[0,pi/2], K=1; forward only"),
             "faces": int(F.shape[0]), "rays": n, "K": K, "crossings": cross,
-            "kernel": ["auto", "plain", "persistent"][args.kernel],
+            "kernel": ["persistent (auto)", "plain", "persistent"][args.kernel],
         },
+        "plain_kernel": plain,
+        "speedup_over_plain": (plain["ms_per_call"] / ms_step) if plain else None,
         "queries_per_s": n / (ms_step * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": algo_bytes, "kernel_ms": ms_kernel},
+                     "kernel": "k_walk (persistent walk)" if ms_walk is not None else "k_exp_plain",
+                     "algorithmic_bytes_per_launch": algo_bytes, "kernel_ms": ms_kernel,
+                     "whole_call": {"ms": ms_call, "algorithmic_bytes": call_bytes,
+                                    "achieved_GBs": call_bytes / (ms_call * 1e-3) / 1e9}},
         "cpu_baseline": cpu,
         "mesh_device_bytes": info["device_bytes"],
     }

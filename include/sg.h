@@ -65,8 +65,12 @@ typedef struct {
     float vertex_snap;     /* an exit point within this edge-parameter distance of an edge endpoint passes
                               through that vertex (straightest rule at vertices); <= 0: 2^-18 */
     float eps_v, eps_p;    /* GFD step sizes (absolute lengths); <= 0: 5e-3 * mean edge of the handle */
-    int32_t kernel;        /* SG_KERNEL_*: which forward kernel runs the walk */
-    uint32_t debug;        /* bit 0: fill n_cross; bit 1: fill seq_hash (FNV-1a 64 of the visited face ids) */
+    int32_t kernel;        /* SG_KERNEL_*: which forward kernel runs the walk (AUTO = PERSISTENT) */
+    uint32_t debug;        /* bit 0: fill n_cross; bit 1: fill seq_hash (FNV-1a 64 of the visited face ids);
+                              bit 2: time the walk kernel with HIP events (read with sg_mesh_walk_time) */
+    int32_t refill_min;    /* persistent kernel: a wave refetches rays once this many of its 64 lanes are
+                              idle; <= 0: tuned default */
+    int32_t walk_blocks;   /* persistent kernel: 256-lane blocks launched; <= 0: fill every CU */
 } sg_opts;
 
 /* Fills *o with the defaults above. */
@@ -120,6 +124,15 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
                      int32_t* f_out, float* b_out, float* p_out, float* v_out, float* W_out,
                      int32_t* status, int32_t* n_cross, uint64_t* seq_hash,
                      const sg_opts* opts, void* stream);
+
+/*
+ * Walk-kernel timing (profiling aid).  Calls made with opts->debug bit 2
+ * record a HIP event pair around their walk kernel on the call's stream.
+ * This synchronizes those events, returns the summed elapsed milliseconds
+ * and the number of timed launches (host outputs, nullable), and clears the
+ * list.  Not thread-safe with concurrent timed calls on the same handle.
+ */
+int sg_mesh_walk_time(sg_mesh mesh, double* total_ms, int64_t* launches);
 
 /* Message describing the last non-OK return on the calling thread. */
 const char* sg_last_error(void);

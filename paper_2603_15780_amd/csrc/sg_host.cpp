@@ -26,6 +26,8 @@ using sg::HalfEdgeRec;
 
 struct sg_mesh_s {
     int device = 0;
+    int cu_count = 0;
+    int walk_blocks_per_cu = 0;
     int64_t n_verts = 0, n_faces = 0;
     int32_t n_meshes = 1;
     double mean_edge = 0.0;
@@ -34,6 +36,7 @@ struct sg_mesh_s {
     float* d_X = nullptr;
     int64_t* d_half = nullptr;
     size_t bytes = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare;   // walk-kernel event pairs
     sg::DevMesh dev() const {
         return sg::DevMesh{d_rec, d_F, d_X, d_half, n_faces, n_verts};
     }
@@ -107,6 +110,8 @@ int upload(T** dptr, const std::vector<T>& h, size_t& bytes) {
 
 void free_mesh(sg_mesh_s* m) {
     if (!m) return;
+    for (auto& pr : m->timed) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+    for (auto& pr : m->spare) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     (void)hipFree(m->d_rec);
     (void)hipFree(m->d_F);
     (void)hipFree(m->d_X);
@@ -123,6 +128,10 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     if (!(o.eps_v > 0.f)) o.eps_v = (float)(5e-3 * m->mean_edge);
     if (!(o.eps_p > 0.f)) o.eps_p = (float)(5e-3 * m->mean_edge);
     if (o.kernel < SG_KERNEL_AUTO || o.kernel > SG_KERNEL_PERSISTENT) return fail(SG_E_ARG, "unknown kernel %d", o.kernel);
+    if (o.kernel == SG_KERNEL_AUTO) o.kernel = SG_KERNEL_PERSISTENT;
+    if (o.refill_min <= 0) o.refill_min = 16;
+    if (o.refill_min > 64) return fail(SG_E_ARG, "refill_min must be at most 64");
+    if (o.walk_blocks <= 0) o.walk_blocks = m->cu_count * m->walk_blocks_per_cu;
     return SG_OK;
 }
 
@@ -297,6 +306,8 @@ void sg_opts_default(sg_opts* o) {
     o->eps_p = 0.f;
     o->kernel = SG_KERNEL_AUTO;
     o->debug = 0u;
+    o->refill_min = 0;
+    o->walk_blocks = 0;
 }
 
 int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, int64_t n_faces,
@@ -313,6 +324,10 @@ int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, 
         delete m;
         return hip_fail(e, "hipGetDevice");
     }
+    if (hipDeviceGetAttribute(&m->cu_count, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess ||
+        m->cu_count <= 0)
+        m->cu_count = 256;
+    m->walk_blocks_per_cu = sg::walk_blocks_per_cu();
     m->n_verts = n_verts;
     m->n_faces = n_faces;
     m->n_meshes = n_meshes;
@@ -339,6 +354,25 @@ int sg_mesh_info(sg_mesh mesh, double* mean_edge, int64_t* n_half_edges, size_t*
     return SG_OK;
 }
 
+int sg_mesh_walk_time(sg_mesh mesh, double* total_ms, int64_t* launches) {
+    if (!mesh) return fail(SG_E_ARG, "mesh is NULL");
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (auto& pr : mesh->timed) {
+        hipError_t e = hipEventSynchronize(pr.second);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+        if (e != hipSuccess) return hip_fail(e, "walk timing");
+        tot += ms;
+        ++cnt;
+        mesh->spare.push_back(pr);
+    }
+    mesh->timed.clear();
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = cnt;
+    return SG_OK;
+}
+
 int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v, int32_t K,
                      const float* W, int32_t* f_out, float* b_out, float* p_out, float* v_out, float* W_out,
                      int32_t* status, int32_t* n_cross, uint64_t* seq_hash, const sg_opts* opts, void* stream) {
@@ -361,8 +395,31 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
     a.max_steps = o.max_steps;
     a.snap = o.vertex_snap;
     a.debug = o.debug;
-    hipError_t e = sg::launch_exp_plain(mesh->dev(), a, (hipStream_t)stream);
+    const hipStream_t st = (hipStream_t)stream;
+    if (o.kernel == SG_KERNEL_PLAIN) {
+        hipError_t e = sg::launch_exp_plain(mesh->dev(), a, st);
+        if (e != hipSuccess) return hip_fail(e, "forward launch");
+        return SG_OK;
+    }
+    // persistent form: per-ray chart states live in a stream-ordered workspace
+    void* ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, sg::exp_persistent_workspace(n), st);
+    if (e != hipSuccess) return fail(SG_E_OOM, "workspace allocation: %s", hipGetErrorString(e));
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (o.debug & 4u) {
+        if (!mesh->spare.empty()) {
+            ev = mesh->spare.back();
+            mesh->spare.pop_back();
+        } else if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
+            (void)hipFreeAsync(ws, st);
+            return fail(SG_E_HIP, "hipEventCreate failed");
+        }
+    }
+    e = sg::launch_exp_persistent(mesh->dev(), a, ws, o.walk_blocks, o.refill_min, st, ev.first, ev.second);
+    if (ev.first) mesh->timed.push_back(ev);
+    const hipError_t e2 = hipFreeAsync(ws, st);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
+    if (e2 != hipSuccess) return hip_fail(e2, "workspace release");
     return SG_OK;
 }
 

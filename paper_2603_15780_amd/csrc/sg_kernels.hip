@@ -96,6 +96,15 @@ struct Ray {
     uint64_t hash;
 };
 
+// hardware reciprocal (about 1 ulp); the walk only needs local accuracy
+SG_HD __forceinline__ float rcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
 SG_HD __forceinline__ float3 ld3(const float* p) { return make_float3(p[0], p[1], p[2]); }
 SG_HD __forceinline__ float3 sub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
 SG_HD __forceinline__ float dot(float3 a, float3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
@@ -269,159 +278,183 @@ SG_HD __forceinline__ void chart_bary(const HalfEdgeRec& r, float ell, float ex,
     o2 = k == 0 ? bc : (k == 1 ? bb : ba);
 }
 
+
+// Stop point of a finished walk, in the chart of the last half-edge.
+struct Final {
+    int32_t h;
+    float ex, ey;
+    uint32_t phi;
+    uint32_t flags;   // bit 0 parity, bits 8..15 status
+    int32_t ncross;
+    uint64_t hash;
+};
+static_assert(sizeof(Final) == 32, "final state is one 32-byte sector");
+
+enum StepEvent { kStepContinue = 0, kStepDone = 1 };
+
+// One geodesic_step: find the exit of the current face, then either stop in
+// the face, stop on the boundary, pass a vertex, or cross the edge into the
+// next chart (transport_over_edge).
 template <bool kHash>
-SG_HD void exp_ray(const DevMesh& M, const ExpArgs& a, int64_t i) {
-    const int32_t f0 = a.f[i];
-    Ray st;
-    float L = 0.f;
-    const int ir = ray_init(M, f0, a.b + 3 * i, a.v + 3 * i, st, L);
-    if (ir != kInitOk) {
-        const bool bad = ir == kInitBad;
-        a.f_out[i] = f0;
-        float bo[3] = {a.b[3 * i], a.b[3 * i + 1], a.b[3 * i + 2]};
-        float3 p = make_float3(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
-        float3 n = make_float3(0.f, 0.f, 0.f);
-        if (!bad) {
-            const float s = bo[0] + bo[1] + bo[2];
-            bo[0] /= s; bo[1] /= s; bo[2] /= s;
-            const int64_t f3 = 3 * (int64_t)f0;
-            const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
-            const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
-            const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
-            p = make_float3(bo[0] * x0.x + bo[1] * x1.x + bo[2] * x2.x, bo[0] * x0.y + bo[1] * x1.y + bo[2] * x2.y,
-                            bo[0] * x0.z + bo[1] * x1.z + bo[2] * x2.z);
-            n = nrm(crs(sub(x1, x0), sub(x2, x0)));
-        }
-        for (int c = 0; c < 3; ++c) a.b_out[3 * i + c] = bo[c];
-        a.p_out[3 * i] = p.x; a.p_out[3 * i + 1] = p.y; a.p_out[3 * i + 2] = p.z;
-        const float vz = bad ? __builtin_nanf("") : 0.f;
-        a.v_out[3 * i] = vz; a.v_out[3 * i + 1] = vz; a.v_out[3 * i + 2] = vz;
-        for (int kk = 0; kk < a.K; ++kk) {
-            const float3 w = ld3(a.W + 3 * (i * a.K + kk));
-            const float3 wt = bad ? make_float3(__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""))
-                                  : sub(w, scl(n, dot(w, n)));
-            float* o = a.W_out + 3 * (i * a.K + kk);
-            o[0] = wt.x; o[1] = wt.y; o[2] = wt.z;
-        }
-        if (a.status) a.status[i] = bad ? kRayBadInput : kRayOk;
-        if (a.n_cross) a.n_cross[i] = 0;
-        if (a.seq_hash) a.seq_hash[i] = bad ? 0ull : fnv_face(14695981039346656037ull, (uint32_t)f0);
-        return;
+SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps, float snap, Final& fin) {
+    const HalfEdgeRec r = M.rec[st.h];
+    float sn, cs;
+    sincos_fx(st.phi, sn, cs);
+    const float cross = fmaf(cs, r.cy, -sn * (r.cx - st.s));
+    const uint32_t force = st.flags & kForceMask;
+    const bool via_ca = force ? (force == kForceCA) : (cross < 0.f);
+    const float w = via_ca ? st.s : st.t;
+    const float acr = fabsf(cross);
+    const float D = fmaf(w, sn, acr);
+    const float rD = rcp(D);
+    const float lam = w * r.cy * rD;
+    const float Lr = st.Lhi + st.Llo;
+    if (!(lam < Lr)) {   // the ray ends inside this face (ties stay in the face)
+        fin.ex = fmaf(Lr, cs, st.s);
+        fin.ey = Lr * sn;
+        fin.flags = (st.flags & kParity) | ((uint32_t)kRayOk << 8);
+        return kStepDone;
     }
-
-    int32_t status = kRayOk;
-    float ex = 0.f, ey = 0.f;   // stop point in the final chart
-    HalfEdgeRec r;
-    for (;;) {
-        r = M.rec[st.h];
-        float sn, cs;
-        sincos_fx(st.phi, sn, cs);
-        const float cross = fmaf(cs, r.cy, -sn * (r.cx - st.s));
-        const uint32_t force = st.flags & kForceMask;
-        const bool via_ca = force ? (force == kForceCA) : (cross < 0.f);
-        const float w = via_ca ? st.s : st.t;
-        const float acr = fabsf(cross);
-        const float D = fmaf(w, sn, acr);
-        const float rD = 1.0f / D;
-        const float lam = w * r.cy * rD;
-        const float Lr = st.Lhi + st.Llo;
-        if (!(lam < Lr)) {   // the ray ends inside this face (ties stay in the face)
-            ex = fmaf(Lr, cs, st.s);
-            ey = Lr * sn;
-            break;
+    if (st.ncross >= max_steps) {
+        fin.ex = st.s;
+        fin.ey = 0.f;
+        fin.flags = (st.flags & kParity) | ((uint32_t)kRayMaxSteps << 8);
+        return kStepDone;
+    }
+    const float mu = w * sn * rD;   // exit point: fraction from the edge's non-apex end
+    const float omu = acr * rD;     // 1 - mu: fraction from the apex
+    const int32_t nx = via_ca ? r.nca : r.nbc;
+    if (omu < snap || mu < snap) {
+        int32_t x0;
+        Ray cand = st;
+        const bool at_apex = omu < snap;
+        const int vr = vertex_rule(M, cand, r, via_ca, at_apex, x0);
+        if (vr == kVertexBoundary) {
+            fin.ex = at_apex ? r.cx : (via_ca ? 0.f : st.s + st.t);
+            fin.ey = at_apex ? r.cy : 0.f;
+            fin.flags = (st.flags & kParity) | ((uint32_t)kRayBoundary << 8);
+            return kStepDone;
         }
-        if (st.ncross >= a.max_steps) {
-            status = kRayMaxSteps;
-            ex = st.s;
-            ey = 0.f;
-            break;
-        }
-        const float mu = w * sn * rD;     // exit point: fraction from the edge's non-apex end
-        const float omu = acr * rD;       // 1 - mu: fraction from the apex
-        const int32_t nx = via_ca ? r.nca : r.nbc;
-        if (omu < a.snap || mu < a.snap) {
-            int32_t x0;
-            Ray cand = st;
-            const int vr = vertex_rule(M, cand, r, via_ca, omu < a.snap, x0);
-            if (vr == kVertexBoundary) {
-                status = kRayBoundary;
-                const bool at_apex = omu < a.snap;
-                ex = at_apex ? r.cx : (via_ca ? 0.f : st.s + st.t);
-                ey = at_apex ? r.cy : 0.f;
-                break;
-            }
-            if (vr == kVertexDone) {
-                // the vertex lies lam along the ray; consume it exactly as an edge crossing would
-                const float nh = st.Lhi - lam;
-                cand.Llo = st.Llo + ((st.Lhi - nh) - lam);
-                cand.Lhi = nh;
-                cand.ncross = st.ncross + 1;
-                cand.hash = kHash ? fnv_face(st.hash, (uint32_t)(cand.h / 3)) : 0ull;
-                st = cand;
-                continue;
-            }
-        }
-        if (nx < 0) {   // boundary edge: stop on it (Sec. 4, original behaviour)
-            status = kRayBoundary;
-            ex = fmaf(lam, cs, st.s);
-            ey = lam * sn;
-            break;
-        }
-        {
+        if (vr == kVertexDone) {
+            // the vertex lies lam along the ray; consume it as an edge crossing would
             const float nh = st.Lhi - lam;
-            st.Llo += (st.Lhi - nh) - lam;
-            st.Lhi = nh;
+            cand.Llo = st.Llo + ((st.Lhi - nh) - lam);
+            cand.Lhi = nh;
+            cand.ncross = st.ncross + 1;
+            cand.hash = kHash ? fnv_face(st.hash, (uint32_t)(cand.h / 3)) : 0ull;
+            st = cand;
+            return kStepContinue;
         }
-        const uint32_t flip = (uint32_t)nx & 1u;
-        const float len = via_ca ? r.lac : r.lbc;
-        const float dm = mu * len, dom = omu * len;
-        float sn2 = via_ca ? dm : dom;
-        float tn2 = via_ca ? dom : dm;
-        uint32_t ph = via_ca ? st.phi - r.A : st.phi + r.B;
-        if (flip) {
-            const float tmp = sn2; sn2 = tn2; tn2 = tmp;
-            ph = kPiFx - ph;
-        }
-        // keep the direction inside [0, pi] against rounding of grazing exits
-        const int32_t phs = (int32_t)ph;
-        st.phi = (uint32_t)(phs < 0 ? 0 : phs);
-        st.s = sn2;
-        st.t = tn2;
-        st.h = nx >> 1;
-        st.flags = (st.flags & kParity) ^ flip;
-        st.ncross += 1;
-        if (kHash) st.hash = fnv_face(st.hash, (uint32_t)(st.h / 3));
     }
+    if (nx < 0) {   // boundary edge: stop on it (Sec. 4, original behaviour)
+        fin.ex = fmaf(lam, cs, st.s);
+        fin.ey = lam * sn;
+        fin.flags = (st.flags & kParity) | ((uint32_t)kRayBoundary << 8);
+        return kStepDone;
+    }
+    const float nh = st.Lhi - lam;
+    st.Llo += (st.Lhi - nh) - lam;
+    st.Lhi = nh;
+    const uint32_t flip = (uint32_t)nx & 1u;
+    const float len = via_ca ? r.lac : r.lbc;
+    const float dm = mu * len, dom = omu * len;
+    float sn2 = via_ca ? dm : dom;
+    float tn2 = via_ca ? dom : dm;
+    uint32_t ph = via_ca ? st.phi - r.A : st.phi + r.B;
+    if (flip) {
+        const float tmp = sn2;
+        sn2 = tn2;
+        tn2 = tmp;
+        ph = kPiFx - ph;
+    }
+    // keep the direction inside [0, pi] against rounding of grazing exits
+    const int32_t phs = (int32_t)ph;
+    st.phi = (uint32_t)(phs < 0 ? 0 : phs);
+    st.s = sn2;
+    st.t = tn2;
+    st.h = nx >> 1;
+    st.flags = (st.flags & kParity) ^ flip;
+    st.ncross += 1;
+    if (kHash) st.hash = fnv_face(st.hash, (uint32_t)(st.h / 3));
+    return kStepContinue;
+}
 
-    // ---- epilogue: end face, barycentrics, 3D point and transported vectors
-    const int32_t fe = st.h / 3;
-    const int ke = st.h - 3 * fe;
-    const float ell = st.s + st.t;
-    float bo[3];
-    chart_bary(r, ell, ex, ey, ke, bo[0], bo[1], bo[2]);
+template <bool kHash>
+SG_HD __forceinline__ void walk_to_end(const DevMesh& M, Ray& st, int32_t max_steps, float snap, Final& fin) {
+    while (walk_step<kHash>(M, st, max_steps, snap, fin) == kStepContinue) {
+    }
+    fin.h = st.h;
+    fin.phi = st.phi;
+    fin.ncross = st.ncross;
+    fin.hash = st.hash;
+}
+
+// Outputs of a ray that never walked: bad input (NaN outputs) or |v_t| = 0
+// (the identity: start point, zero vector, projected extra vectors).
+SG_HD void write_unwalked(const DevMesh& M, const ExpArgs& a, int64_t i, bool bad) {
+    const int32_t f0 = a.f[i];
+    a.f_out[i] = f0;
+    float bo[3] = {a.b[3 * i], a.b[3 * i + 1], a.b[3 * i + 2]};
+    const float nan = __builtin_nanf("");
+    float3 p = make_float3(nan, nan, nan);
+    float3 n = make_float3(0.f, 0.f, 0.f);
+    if (!bad) {
+        const float s = bo[0] + bo[1] + bo[2];
+        bo[0] /= s; bo[1] /= s; bo[2] /= s;
+        const int64_t f3 = 3 * (int64_t)f0;
+        const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
+        const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
+        const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+        p = make_float3(bo[0] * x0.x + bo[1] * x1.x + bo[2] * x2.x, bo[0] * x0.y + bo[1] * x1.y + bo[2] * x2.y,
+                        bo[0] * x0.z + bo[1] * x1.z + bo[2] * x2.z);
+        n = nrm(crs(sub(x1, x0), sub(x2, x0)));
+    }
+    a.b_out[3 * i] = bo[0]; a.b_out[3 * i + 1] = bo[1]; a.b_out[3 * i + 2] = bo[2];
+    a.p_out[3 * i] = p.x; a.p_out[3 * i + 1] = p.y; a.p_out[3 * i + 2] = p.z;
+    const float vz = bad ? nan : 0.f;
+    a.v_out[3 * i] = vz; a.v_out[3 * i + 1] = vz; a.v_out[3 * i + 2] = vz;
+    for (int kk = 0; kk < a.K; ++kk) {
+        const float3 w = ld3(a.W + 3 * (i * a.K + kk));
+        const float3 wt = bad ? make_float3(nan, nan, nan) : sub(w, scl(n, dot(w, n)));
+        float* o = a.W_out + 3 * (i * a.K + kk);
+        o[0] = wt.x; o[1] = wt.y; o[2] = wt.z;
+    }
+    if (a.status) a.status[i] = bad ? kRayBadInput : kRayOk;
+    if (a.n_cross) a.n_cross[i] = 0;
+    if (a.seq_hash) a.seq_hash[i] = bad ? 0ull : fnv_face(14695981039346656037ull, (uint32_t)f0);
+}
+
+// Epilogue: end face, barycentrics, 3D point, transported tangent and vectors.
+SG_HD void write_final(const DevMesh& M, const ExpArgs& a, int64_t i, const Final& fin, float L) {
+    const int32_t fe = fin.h / 3;
+    const int ke = fin.h - 3 * fe;
+    const HalfEdgeRec r = M.rec[fin.h];
     const int64_t f3 = 3 * (int64_t)fe;
     const float3 y0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
     const float3 y1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
     const float3 y2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+    const float3 ya = ke == 0 ? y0 : (ke == 1 ? y1 : y2);
+    const float3 yb = ke == 0 ? y1 : (ke == 1 ? y2 : y0);
+    const float3 yc = ke == 0 ? y2 : (ke == 1 ? y0 : y1);
+    const float3 eab = sub(yb, ya);
+    const float ell = sqrtf(dot(eab, eab));
+    float bo[3];
+    chart_bary(r, ell, fin.ex, fin.ey, ke, bo[0], bo[1], bo[2]);
     a.f_out[i] = fe;
     a.b_out[3 * i] = bo[0]; a.b_out[3 * i + 1] = bo[1]; a.b_out[3 * i + 2] = bo[2];
     a.p_out[3 * i] = fmaf(bo[0], y0.x, fmaf(bo[1], y1.x, bo[2] * y2.x));
     a.p_out[3 * i + 1] = fmaf(bo[0], y0.y, fmaf(bo[1], y1.y, bo[2] * y2.y));
     a.p_out[3 * i + 2] = fmaf(bo[0], y0.z, fmaf(bo[1], y1.z, bo[2] * y2.z));
-    // 3D tangent frame of the final chart
-    const float3 ya = ke == 0 ? y0 : (ke == 1 ? y1 : y2);
-    const float3 yb = ke == 0 ? y1 : (ke == 1 ? y2 : y0);
-    const float3 yc = ke == 0 ? y2 : (ke == 1 ? y0 : y1);
-    const float3 eab = sub(yb, ya);
-    const float3 ex3 = nrm(eab);
+    const float3 ex3 = scl(eab, 1.0f / ell);
     const float3 n3 = nrm(crs(eab, sub(yc, ya)));
     const float3 ey3 = crs(n3, ex3);
     float sn, cs;
-    sincos_fx(st.phi, sn, cs);
+    sincos_fx(fin.phi, sn, cs);
     const float3 d3 = make_float3(fmaf(cs, ex3.x, sn * ey3.x), fmaf(cs, ex3.y, sn * ey3.y), fmaf(cs, ex3.z, sn * ey3.z));
     a.v_out[3 * i] = L * d3.x; a.v_out[3 * i + 1] = L * d3.y; a.v_out[3 * i + 2] = L * d3.z;
     if (a.K > 0) {
-        // signed angle of each extra vector to the start tangent, about the start normal
+        // components of each extra vector in the start frame (tangent, normal x tangent)
+        const int32_t f0 = a.f[i];
         const int64_t g3 = 3 * (int64_t)f0;
         const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[g3]);
         const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[g3 + 1]);
@@ -430,7 +463,7 @@ SG_HD void exp_ray(const DevMesh& M, const ExpArgs& a, int64_t i) {
         const float3 v = ld3(a.v + 3 * i);
         const float3 d0 = nrm(sub(v, scl(n0, dot(v, n0))));
         const float3 q0 = crs(n0, d0);
-        const float sg = (st.flags & kParity) ? -1.0f : 1.0f;
+        const float sg = (fin.flags & kParity) ? -1.0f : 1.0f;
         const float3 q3 = scl(crs(n3, d3), sg);
         for (int kk = 0; kk < a.K; ++kk) {
             const float3 w = ld3(a.W + 3 * (i * a.K + kk));
@@ -441,9 +474,40 @@ SG_HD void exp_ray(const DevMesh& M, const ExpArgs& a, int64_t i) {
             o[2] = fmaf(wx, d3.z, wy * q3.z);
         }
     }
-    if (a.status) a.status[i] = status;
-    if (a.n_cross) a.n_cross[i] = st.ncross;
-    if (a.seq_hash) a.seq_hash[i] = kHash ? st.hash : 0ull;
+    if (a.status) a.status[i] = (int32_t)((fin.flags >> 8) & 0xffu);
+    if (a.n_cross) a.n_cross[i] = fin.ncross;
+    if (a.seq_hash) a.seq_hash[i] = fin.hash;
+}
+
+// |v_t| of ray i (projection of v onto the start face), recomputed where the
+// walk state did not keep it.
+SG_HD __forceinline__ float tangent_length(const DevMesh& M, const ExpArgs& a, int64_t i) {
+    const int64_t f3 = 3 * (int64_t)a.f[i];
+    const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
+    const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
+    const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+    const float3 e1 = sub(x1, x0), e2 = sub(x2, x0);
+    const float l0 = sqrtf(dot(e1, e1));   // same arithmetic as ray_init
+    const float3 n = nrm(crs(e1, e2));
+    const float3 ex = scl(e1, 1.0f / l0);
+    const float3 ey = crs(n, ex);
+    const float3 v = ld3(a.v + 3 * i);
+    const float vx = dot(v, ex), vy = dot(v, ey);
+    return sqrtf(fmaf(vx, vx, vy * vy));
+}
+
+template <bool kHash>
+SG_HD void exp_ray(const DevMesh& M, const ExpArgs& a, int64_t i) {
+    Ray st;
+    float L = 0.f;
+    const int ir = ray_init(M, a.f[i], a.b + 3 * i, a.v + 3 * i, st, L);
+    if (ir != kInitOk) {
+        write_unwalked(M, a, i, ir == kInitBad);
+        return;
+    }
+    Final fin;
+    walk_to_end<kHash>(M, st, a.max_steps, a.snap, fin);
+    write_final(M, a, i, fin, L);
 }
 
 template <bool kHash>
@@ -451,6 +515,105 @@ __global__ __launch_bounds__(256) void k_exp_plain(DevMesh M, ExpArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     exp_ray<kHash>(M, a, i);
+}
+
+// ---------------------------------------------------------------- persistent form
+// 32-byte walk state in the workspace: the initial chart state written by
+// k_init, overwritten in place by the Final record when the walk ends.
+struct alignas(32) StateRec {
+    int32_t h;        // < 0: the ray needs no walk (its outputs are already written)
+    float s, t;
+    uint32_t phi;
+    float Lhi, Llo;
+    uint32_t flags;
+    int32_t pad;
+};
+static_assert(sizeof(StateRec) == 32, "state record is one 32-byte sector");
+
+__global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* states, unsigned long long* counter) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *counter = 0ull;
+    if (i >= a.n) return;
+    Ray st;
+    float L = 0.f;
+    const int ir = ray_init(M, a.f[i], a.b + 3 * i, a.v + 3 * i, st, L);
+    StateRec rec;
+    if (ir != kInitOk) {
+        write_unwalked(M, a, i, ir == kInitBad);
+        rec.h = -1;
+        rec.s = rec.t = rec.Lhi = rec.Llo = 0.f;
+        rec.phi = rec.flags = 0u;
+    } else {
+        rec.h = st.h;
+        rec.s = st.s;
+        rec.t = st.t;
+        rec.phi = st.phi;
+        rec.Lhi = st.Lhi;
+        rec.Llo = st.Llo;
+        rec.flags = st.flags;
+    }
+    rec.pad = 0;
+    states[i] = rec;
+}
+
+// Persistent walk: each wave keeps 64 rays in flight and refills finished
+// lanes from a global queue (one atomic per wave per refill, ballot for the
+// lane ranks), so short and long rays share lanes instead of idling behind
+// the longest ray of a fixed batch.
+template <bool kHash>
+__global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
+                                              int32_t max_steps, float snap, int refill_min) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    bool active = false;
+    bool exhausted = false;
+    int64_t q = 0;
+    Ray st;
+    st.h = 0; st.s = st.t = st.Lhi = st.Llo = 0.f; st.phi = st.flags = 0u; st.ncross = 0; st.hash = 0ull;
+    for (;;) {
+        const uint64_t idle = __ballot(!active);
+        const int nidle = __popcll(idle);
+        if (!exhausted && nidle >= refill_min) {
+            unsigned long long base = 0ull;
+            if (lane == 0) base = atomicAdd(counter, (unsigned long long)nidle);
+            base = __shfl(base, 0);
+            if (base + (unsigned long long)nidle >= (unsigned long long)n) exhausted = true;
+            if (!active) {
+                q = (int64_t)base + __popcll(idle & below);
+                if (q < n) {
+                    const StateRec rec = states[q];
+                    if (rec.h >= 0) {
+                        st.h = rec.h; st.s = rec.s; st.t = rec.t; st.phi = rec.phi;
+                        st.Lhi = rec.Lhi; st.Llo = rec.Llo; st.flags = rec.flags;
+                        st.ncross = 0;
+                        st.hash = kHash ? fnv_face(14695981039346656037ull, (uint32_t)(rec.h / 3)) : 0ull;
+                        active = true;
+                    }
+                }
+            }
+            continue;
+        }
+        if (nidle == 64 && exhausted) break;
+        if (active) {
+            Final fin;
+            if (walk_step<kHash>(M, st, max_steps, snap, fin) == kStepDone) {
+                fin.h = st.h;
+                fin.phi = st.phi;
+                fin.ncross = st.ncross;
+                fin.hash = st.hash;
+                *reinterpret_cast<Final*>(&states[q]) = fin;
+                active = false;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_finish(DevMesh M, ExpArgs a, const StateRec* states) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const Final fin = *reinterpret_cast<const Final*>(&states[i]);
+    if (fin.h < 0) return;
+    write_final(M, a, i, fin, tangent_length(M, a, i));
 }
 
 }  // namespace
@@ -464,6 +627,34 @@ hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s) {
     else
         hipLaunchKernelGGL(k_exp_plain<false>, dim3((unsigned)grid), dim3(block), 0, s, M, a);
     return hipGetLastError();
+}
+
+size_t exp_persistent_workspace(int64_t n) { return (size_t)n * sizeof(StateRec) + 256; }
+
+hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, int grid_blocks, int refill_min,
+                                 hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (a.n <= 0) return hipSuccess;
+    const int block = 256;
+    const int64_t grid = (a.n + block - 1) / block;
+    auto* states = reinterpret_cast<StateRec*>(ws);
+    auto* counter = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(ws) + (size_t)a.n * sizeof(StateRec));
+    hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, counter);
+    if (ev0) (void)hipEventRecord(ev0, s);
+    if (a.debug & 2u)
+        hipLaunchKernelGGL(k_walk<true>, dim3((unsigned)grid_blocks), dim3(block), 0, s, M, states, a.n, counter,
+                           a.max_steps, a.snap, refill_min);
+    else
+        hipLaunchKernelGGL(k_walk<false>, dim3((unsigned)grid_blocks), dim3(block), 0, s, M, states, a.n, counter,
+                           a.max_steps, a.snap, refill_min);
+    if (ev1) (void)hipEventRecord(ev1, s);
+    hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states);
+    return hipGetLastError();
+}
+
+int walk_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk<false>, 256, 0) != hipSuccess || nb <= 0) nb = 1;
+    return nb;
 }
 
 }  // namespace sg

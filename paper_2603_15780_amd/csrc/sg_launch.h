@@ -46,4 +46,12 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
 // Plain forward: one ray per lane, run to completion (Alg. gpu_parallel).
 hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s);
 
+// Persistent forward: init kernel, persistent work-queue walk, finish kernel.
+// ws must hold exp_persistent_workspace(n) bytes of device memory.
+size_t exp_persistent_workspace(int64_t n);
+// ev0/ev1 (nullable) are recorded on s around the walk kernel.
+hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, int grid_blocks, int refill_min,
+                                 hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+int walk_blocks_per_cu();
+
 }  // namespace sg

@@ -30,7 +30,8 @@ class SgError(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("vertex_snap", C.c_float), ("eps_v", C.c_float),
-                ("eps_p", C.c_float), ("kernel", C.c_int32), ("debug", C.c_uint32)]
+                ("eps_p", C.c_float), ("kernel", C.c_int32), ("debug", C.c_uint32),
+                ("refill_min", C.c_int32), ("walk_blocks", C.c_int32)]
 
 
 def lib_path() -> str:
@@ -56,6 +57,8 @@ def lib():
         L.sg_exp.restype = C.c_int
         L.sg_exp_transport.argtypes = [P, I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, C.POINTER(Opts), P]
         L.sg_exp_transport.restype = C.c_int
+        L.sg_mesh_walk_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.sg_mesh_walk_time.restype = C.c_int
         _lib = L
     return _lib
 
@@ -118,6 +121,13 @@ class Mesh:
         nb = C.c_size_t()
         _check(lib().sg_mesh_info(self._h, C.byref(me), C.byref(nh), C.byref(nb)))
         return dict(mean_edge=me.value, n_half_edges=nh.value, device_bytes=nb.value)
+
+    def walk_time(self):
+        """(summed ms, launches) of walk kernels timed with debug bit 2 since the last call."""
+        ms = C.c_double()
+        cnt = C.c_int64()
+        _check(lib().sg_mesh_walk_time(self._h, C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value
 
     def exp(self, f, b, v, W=None, *, out=None, want_status=True, want_cross=False, want_hash=False,
             o: Opts | None = None, **kw):

@@ -48,31 +48,34 @@ def both(torch, X, F, r, **kw):
     return om, gm, o, g
 
 
-def test_config1_parity(torch):
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_config1_parity(torch, kernel):
     X, F = CF.mesh_config(1)
     r = CF.rays_config(1, X, F)
-    om, gm, o, g = both(torch, X, F, r)
+    om, gm, o, g = both(torch, X, F, r, kernel=kernel)
     assert abs(gm.info()["mean_edge"] - om.mean_edge) < 1e-12
     s = assert_parity(o, g, om.mean_edge, K=1, label="config1")
     assert s["hash_mis_far"] == 0
 
 
+@pytest.mark.parametrize("kernel", [1, 2])
 @pytest.mark.parametrize("n", [1, 63, 255, 257, 1000, 4097])
-def test_ragged_sizes(torch, n):
+def test_ragged_sizes(torch, n, kernel):
     X, F = CF.mesh_config(1)
     r = random_rays(X, F, n, np.random.default_rng(n), uniform_len(0.0, 2.0), K=2)
-    om, gm, o, g = both(torch, X, F, r)
+    om, gm, o, g = both(torch, X, F, r, kernel=kernel)
     s = report(o, g, om.mean_edge, K=2)
     assert s["bad_not_near"] == 0 and s["face_mis_unexplained"] == 0, s
 
 
-def test_config2_full_batch_sampled(torch):
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_config2_full_batch_sampled(torch, kernel):
     """1,048,576 rays on the 327,680-face displaced icosphere, K = 2, sampled rows vs oracle."""
     X, F = CF.mesh_config(2)
     r = CF.rays_config(2, X, F)
     from paper_2603_15780_amd import sg
     gm = sg.Mesh(X, F)
-    g = run(torch, gm, r)
+    g = run(torch, gm, r, kernel=kernel)
     rows = np.arange(0, r["f"].shape[0], 8)   # 131,072 sampled rays
     om = oracle.Mesh(X, F)
     o = om.exp(r["f"][rows], r["b"][rows], r["v"][rows], r["W"][rows])
@@ -151,7 +154,8 @@ def test_cube_corner_closed_form(torch, a):
     assert np.abs(g["p"][0] - (c + rr * out)).max() < 1e-5
 
 
-def test_edge_cases(torch):
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_edge_cases(torch, kernel):
     from paper_2603_15780_amd import sg
     X, F = CF.mesh_config(1)
     gm = sg.Mesh(X, F)
@@ -159,7 +163,7 @@ def test_edge_cases(torch):
     r = random_rays(X, F, 64, np.random.default_rng(3), uniform_len(0.5, 1.5), K=1)
     # empty batch is a no-op
     e = dict(f=r["f"][:0], b=r["b"][:0], v=r["v"][:0], W=r["W"][:0])
-    g = run(torch, gm, e)
+    g = run(torch, gm, e, kernel=kernel)
     assert g["f"].shape == (0,)
     # bad inputs and zero length
     rb = {k: v.copy() for k, v in r.items() if k in ("f", "b", "v", "W")}
@@ -169,14 +173,14 @@ def test_edge_cases(torch):
     rb["b"][3] = [-0.1, 0.6, 0.5]
     rb["v"][4] = [np.inf, 0, 0]
     rb["v"][5] = 0.0
-    g = run(torch, gm, rb)
+    g = run(torch, gm, rb, kernel=kernel)
     o = om.exp(rb["f"], rb["b"], rb["v"], rb["W"])
     assert list(g["status"][:5]) == [3, 3, 3, 3, 3] and list(o["status"][:5]) == [3, 3, 3, 3, 3]
     assert g["status"][5] == 0 and g["n_cross"][5] == 0 and g["f"][5] == rb["f"][5]
     assert np.abs(g["p"][5] - o["p"][5]).max() < 1e-6
     assert np.all(g["v"][5] == 0)
     # max_steps: stop after one crossing
-    g = run(torch, gm, r, max_steps=1)
+    g = run(torch, gm, r, max_steps=1, kernel=kernel)
     o = om.exp(r["f"], r["b"], r["v"], max_steps=1)
     assert np.array_equal(g["status"], o["status"]) and np.any(g["status"] == 1)
     assert np.array_equal(g["f"], o["f"])
@@ -189,19 +193,19 @@ def test_edge_cases(torch):
     rv["v"][0] = (0.3 * inside / np.linalg.norm(inside)).astype(np.float32)
     rv["v"][1] = (-rv["v"][0]).astype(np.float32)
     rv["f"][1] = rv["f"][0]
-    g = run(torch, gm, rv)
+    g = run(torch, gm, rv, kernel=kernel)
     o = om.exp(rv["f"], rv["b"], rv["v"])
     assert list(o["status"]) == [0, 3] and list(g["status"]) == [0, 3]
     assert np.abs(g["p"][0] - o["p"][0]).max() < 1e-5
 
 
-def test_boundary_stop(torch):
-    from paper_2603_15780_amd import sg
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_boundary_stop(torch, kernel):
     X, F = M.icosphere(3)
     X, F = M.remove_faces(X, F, np.where((F == 0).any(1) | (F == 7).any(1) | (F == 100).any(1))[0])
     X, F = M.canonical(X, F)
     r = random_rays(X, F, 5000, np.random.default_rng(4), uniform_len(0.5, 3.0), K=1)
-    om, gm, o, g = both(torch, X, F, r)
+    om, gm, o, g = both(torch, X, F, r, kernel=kernel)
     assert np.any(o["status"] == 2)
     assert_parity(o, g, om.mean_edge, K=1, label="holes")
 
@@ -229,12 +233,28 @@ def test_multi_mesh_offsets(torch):
     assert_parity(o2, g2, M.mean_edge(X2, F2), K=1, label="mesh2")
 
 
-def test_deterministic(torch):
+def test_deterministic_and_kernels_agree(torch):
+    """Bitwise repeatable, and the plain and persistent forms compute identical rays."""
     from paper_2603_15780_amd import sg
     X, F = CF.mesh_config(1)
     gm = sg.Mesh(X, F)
     r = CF.rays_config(1, X, F)
-    a = run(torch, gm, r)
-    b = run(torch, gm, r)
+    a = run(torch, gm, r, kernel=2)
+    b = run(torch, gm, r, kernel=2)
+    c = run(torch, gm, r, kernel=1)
+    for k in ("f", "b", "p", "v", "W", "status", "n_cross", "hash"):
+        assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], c[k]), k
+
+
+@pytest.mark.parametrize("refill_min,walk_blocks", [(1, 0), (64, 0), (16, 3), (8, 1)])
+def test_persistent_schedules(torch, refill_min, walk_blocks):
+    """Every refill threshold and grid size gives the same rays (queue drains fully)."""
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    gm = sg.Mesh(X, F)
+    r = random_rays(X, F, 5000, np.random.default_rng(9), uniform_len(0.0, 3.0), K=1)
+    a = run(torch, gm, r, kernel=1)
+    b = run(torch, gm, r, kernel=2, refill_min=refill_min, walk_blocks=walk_blocks)
     for k in ("f", "b", "p", "v", "W", "status", "n_cross", "hash"):
         assert np.array_equal(a[k], b[k]), k
