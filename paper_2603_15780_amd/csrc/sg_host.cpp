@@ -35,10 +35,11 @@ struct sg_mesh_s {
     int32_t* d_F = nullptr;
     float* d_X = nullptr;
     int64_t* d_half = nullptr;
+    int32_t has_flip = 0;
     size_t bytes = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare;   // walk-kernel event pairs
     sg::DevMesh dev() const {
-        return sg::DevMesh{d_rec, d_F, d_X, d_half, n_faces, n_verts};
+        return sg::DevMesh{d_rec, d_F, d_X, d_half, n_faces, n_verts, has_flip};
     }
 };
 
@@ -143,8 +144,10 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
               const int64_t* vert_offsets, const int64_t* face_offsets, int32_t n_meshes, PackedMesh& out) {
     try {
         if (!X_host || !F_host || n_verts <= 0 || n_faces <= 0) return fail(SG_E_ARG, "empty mesh");
-        if (n_faces > ((int64_t)1 << 29) || n_verts > ((int64_t)1 << 31) - 1)
-            return fail(SG_E_ARG, "mesh too large for 32-bit half-edge ids (%lld faces)", (long long)n_faces);
+        // half-edge records are addressed with 32-bit byte offsets: 3 n_faces * 32 < 2^32
+        if (3 * n_faces * 32 >= ((int64_t)1 << 32))
+            return fail(SG_E_ARG, "mesh too large: %lld faces (at most 44,739,242)", (long long)n_faces);
+        if (n_verts > ((int64_t)1 << 31) - 1) return fail(SG_E_ARG, "too many vertices");
         if (n_meshes < 1) return fail(SG_E_ARG, "n_meshes must be >= 1");
         if ((vert_offsets == nullptr) != (face_offsets == nullptr))
             return fail(SG_E_ARG, "vert_offsets and face_offsets must both be given or both be NULL");
@@ -278,6 +281,9 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
         half.assign(n_verts, 0);
         for (int64_t v = 0; v < n_verts; ++v)
             half[v] = vbnd[v] ? -1 : (int64_t)std::llround(0.5 * theta[v] * sg::kFxPerRad);
+        out.has_flip = 0;
+        for (const HalfEdgeRec& r : rec)
+            if ((r.nca >= 0 && (r.nca & 1)) || (r.nbc >= 0 && (r.nbc & 1))) out.has_flip = 1;
         out.X.assign(X_host, X_host + 3 * n_verts);
         out.F = std::move(F);
         out.n_verts = n_verts;
@@ -332,6 +338,7 @@ int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, 
     m->n_faces = n_faces;
     m->n_meshes = n_meshes;
     m->mean_edge = pm.mean_edge;
+    m->has_flip = pm.has_flip;
     rc = upload(&m->d_rec, pm.rec, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_F, pm.F, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_X, pm.X, m->bytes);

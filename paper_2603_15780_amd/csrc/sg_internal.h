@@ -39,6 +39,7 @@ struct DevMesh {
     const int64_t* half_theta;// [n_verts] theta(x)/2 in fixed point, -1 on boundary vertices
     int64_t n_faces;
     int64_t n_verts;
+    int32_t has_flip;         // some adjacent faces disagree in orientation (non-orientable or mixed)
 };
 
 enum RayStatus : int32_t { kRayOk = 0, kRayMaxSteps = 1, kRayBoundary = 2, kRayBadInput = 3 };

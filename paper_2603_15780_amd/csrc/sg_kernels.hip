@@ -27,9 +27,12 @@ namespace sg {
 
 namespace {
 
-constexpr uint32_t kForceBC = 2u;   // leave a vertex through the edge opposite it (vertex at a)
-constexpr uint32_t kForceCA = 4u;   // (vertex at b)
-constexpr uint32_t kForceMask = 6u;
+// A ray that starts on a vertex must leave through the edge opposite it; the
+// exit test (sign of `cross`) is biased to force that choice.
+constexpr float kBig = 1.0e30f;
+constexpr float kForceBC = kBig;    // vertex at a: leave through b-c
+constexpr float kForceCA = -kBig;   // vertex at b: leave through c-a
+constexpr uint32_t kForceBCBit = 2u, kForceCABit = 4u;   // the same, in a stored state record
 constexpr uint32_t kParity = 1u;    // orientation flipped an odd number of times
 
 // sin(x)/x and cos(x) as polynomials in u = x^2 on |x| <= pi/2 (least-squares
@@ -91,10 +94,16 @@ struct Ray {
     float s, t;
     uint32_t phi;
     float Lhi, Llo;
-    uint32_t flags;
+    float bias;      // 0, or kForceBC / kForceCA right after a vertex
+    uint32_t par;    // kParity if the orientation flipped an odd number of times
     int32_t ncross;
     uint64_t hash;
 };
+
+// Record gather with a 32-bit byte offset from the table base (h < 2^27).
+SG_HD __forceinline__ HalfEdgeRec rec_at(const DevMesh& M, int32_t h) {
+    return *reinterpret_cast<const HalfEdgeRec*>(reinterpret_cast<const char*>(M.rec) + ((uint32_t)h << 5));
+}
 
 // hardware reciprocal (about 1 ulp); the walk only needs local accuracy
 SG_HD __forceinline__ float rcp(float x) {
@@ -192,9 +201,8 @@ SG_HD int ray_init(const DevMesh& M, int32_t f, const float* bp, const float* vp
     const float bv = sum - L;
     st.Lhi = sum;
     st.Llo = (L - (sum - bv)) + (tau - bv);
-    st.flags = 0u;
-    if (st.s == 0.f) st.flags |= kForceBC;
-    else if (st.t == 0.f) st.flags |= kForceCA;
+    st.par = 0u;
+    st.bias = st.s == 0.f ? kForceBC : (st.t == 0.f ? kForceCA : 0.f);
     st.ncross = 0;
     st.hash = fnv_face(14695981039346656037ull, (uint32_t)f);
     return kInitOk;
@@ -238,9 +246,9 @@ SG_HD __forceinline__ int vertex_rule(const DevMesh& M, Ray& st, const HalfEdgeR
     const int64_t half = M.half_theta[x0];
     if (half < 0) return kVertexBoundary;
     if (!at_apex && acc >= half) return kVertexNoSnap;
-    uint32_t par = st.flags & kParity;
+    uint32_t par = st.par;
     for (int guard = 0; guard < 4096; ++guard) {
-        const HalfEdgeRec q = M.rec[hv];
+        const HalfEdgeRec q = rec_at(M, hv);
         const uint32_t corner = roleA ? q.A : q.B;
         if (acc + (int64_t)corner >= half) {
             const uint32_t beta = (uint32_t)(half - acc);
@@ -248,7 +256,8 @@ SG_HD __forceinline__ int vertex_rule(const DevMesh& M, Ray& st, const HalfEdgeR
             st.phi = roleA ? beta : kPiFx - beta;
             st.s = roleA ? 0.f : ell;
             st.t = roleA ? ell : 0.f;
-            st.flags = par | (roleA ? kForceBC : kForceCA);
+            st.par = par;
+            st.bias = roleA ? kForceBC : kForceCA;
             return kVertexDone;
         }
         acc += corner;
@@ -292,101 +301,119 @@ static_assert(sizeof(Final) == 32, "final state is one 32-byte sector");
 
 enum StepEvent { kStepContinue = 0, kStepDone = 1 };
 
-// One geodesic_step: find the exit of the current face, then either stop in
-// the face, stop on the boundary, pass a vertex, or cross the edge into the
-// next chart (transport_over_edge).
-template <bool kHash>
+SG_HD __forceinline__ void set_final(Final& fin, const Ray& st, float ex, float ey, int32_t status) {
+    fin.h = st.h;
+    fin.ex = ex;
+    fin.ey = ey;
+    fin.phi = st.phi;
+    fin.flags = (st.par & kParity) | ((uint32_t)status << 8);
+    fin.ncross = st.ncross;
+    fin.hash = st.hash;
+}
+
+// One geodesic_step: find the exit of the current face (the smallest positive
+// barycentric exit parameter over the two non-entry edges), then cross the
+// edge into the next chart (transport_over_edge).  The crossing is computed
+// for every lane and committed with selects; stopping in the face, at the
+// step cap, at a vertex or on the boundary is one rarely taken branch.
+template <bool kHash, bool kFlip>
 SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps, float snap, Final& fin) {
-    const HalfEdgeRec r = M.rec[st.h];
+    const HalfEdgeRec r = rec_at(M, st.h);
     float sn, cs;
     sincos_fx(st.phi, sn, cs);
-    const float cross = fmaf(cs, r.cy, -sn * (r.cx - st.s));
-    const uint32_t force = st.flags & kForceMask;
-    const bool via_ca = force ? (force == kForceCA) : (cross < 0.f);
+    const float cross = fmaf(cs, r.cy, -sn * (r.cx - st.s));   // > 0: apex left of the ray
+    const bool via_ca = (cross + st.bias) < 0.f;
     const float w = via_ca ? st.s : st.t;
     const float acr = fabsf(cross);
-    const float D = fmaf(w, sn, acr);
-    const float rD = rcp(D);
-    const float lam = w * r.cy * rD;
+    const float rD = rcp(fmaf(w, sn, acr));
+    const float lam = w * r.cy * rD;   // distance to the exit point
     const float Lr = st.Lhi + st.Llo;
-    if (!(lam < Lr)) {   // the ray ends inside this face (ties stay in the face)
-        fin.ex = fmaf(Lr, cs, st.s);
-        fin.ey = Lr * sn;
-        fin.flags = (st.flags & kParity) | ((uint32_t)kRayOk << 8);
-        return kStepDone;
-    }
-    if (st.ncross >= max_steps) {
-        fin.ex = st.s;
-        fin.ey = 0.f;
-        fin.flags = (st.flags & kParity) | ((uint32_t)kRayMaxSteps << 8);
-        return kStepDone;
-    }
-    const float mu = w * sn * rD;   // exit point: fraction from the edge's non-apex end
-    const float omu = acr * rD;     // 1 - mu: fraction from the apex
+    const float mu = w * sn * rD;      // exit point: fraction from the edge's non-apex end
+    const float omu = acr * rD;        // 1 - mu: fraction from the apex
     const int32_t nx = via_ca ? r.nca : r.nbc;
-    if (omu < snap || mu < snap) {
+    // the next chart: the crossed edge keeps its points and angles
+    const float len = via_ca ? r.lac : r.lbc;
+    const float dm = mu * len, dom = omu * len;
+    float s2 = via_ca ? dm : dom;
+    float t2 = via_ca ? dom : dm;
+    uint32_t ph = via_ca ? st.phi - r.A : st.phi + r.B;
+    uint32_t par = st.par;
+    if (kFlip) {   // neighbour traverses the edge the same way: mirror the chart
+        const uint32_t flip = (uint32_t)nx & 1u;
+        const float tmp = s2;
+        s2 = flip ? t2 : s2;
+        t2 = flip ? tmp : t2;
+        ph = flip ? kPiFx - ph : ph;
+        par ^= flip;
+    }
+    const int32_t phs = (int32_t)ph;   // keep [0, pi] against rounding of grazing exits
+    ph = (uint32_t)(phs < 0 ? 0 : phs);
+    const float nh = st.Lhi - lam;                    // compensated remaining length
+    const float lo = st.Llo + ((st.Lhi - nh) - lam);
+    const bool rare = !(lam < Lr) || (st.ncross >= max_steps) || (mu < snap) || (omu < snap) || (nx < 0);
+    const Ray old = st;
+    st.s = rare ? st.s : s2;
+    st.t = rare ? st.t : t2;
+    st.phi = rare ? st.phi : ph;
+    st.Lhi = rare ? st.Lhi : nh;
+    st.Llo = rare ? st.Llo : lo;
+    st.h = rare ? st.h : (nx >> 1);
+    st.par = rare ? st.par : par;
+    st.bias = rare ? st.bias : 0.f;
+    st.ncross += rare ? 0 : 1;
+    if (kHash && !rare) st.hash = fnv_face(st.hash, (uint32_t)(st.h / 3));
+    if (!rare) return kStepContinue;
+
+    // ---- rare events, in priority order
+    if (!(lam < Lr)) {   // the ray ends inside this face (ties stay in the face)
+        set_final(fin, old, fmaf(Lr, cs, old.s), Lr * sn, kRayOk);
+        return kStepDone;
+    }
+    if (old.ncross >= max_steps) {
+        set_final(fin, old, old.s, 0.f, kRayMaxSteps);
+        return kStepDone;
+    }
+    if (mu < snap || omu < snap) {   // passing a vertex (transport_over_vertex)
         int32_t x0;
-        Ray cand = st;
+        Ray cand = old;
         const bool at_apex = omu < snap;
         const int vr = vertex_rule(M, cand, r, via_ca, at_apex, x0);
         if (vr == kVertexBoundary) {
-            fin.ex = at_apex ? r.cx : (via_ca ? 0.f : st.s + st.t);
-            fin.ey = at_apex ? r.cy : 0.f;
-            fin.flags = (st.flags & kParity) | ((uint32_t)kRayBoundary << 8);
+            set_final(fin, old, at_apex ? r.cx : (via_ca ? 0.f : old.s + old.t), at_apex ? r.cy : 0.f, kRayBoundary);
             return kStepDone;
         }
-        if (vr == kVertexDone) {
-            // the vertex lies lam along the ray; consume it as an edge crossing would
-            const float nh = st.Lhi - lam;
-            cand.Llo = st.Llo + ((st.Lhi - nh) - lam);
+        if (vr == kVertexDone) {   // the vertex lies lam along the ray: consume it like a crossing
             cand.Lhi = nh;
-            cand.ncross = st.ncross + 1;
-            cand.hash = kHash ? fnv_face(st.hash, (uint32_t)(cand.h / 3)) : 0ull;
+            cand.Llo = lo;
+            cand.ncross = old.ncross + 1;
+            cand.hash = kHash ? fnv_face(old.hash, (uint32_t)(cand.h / 3)) : 0ull;
             st = cand;
             return kStepContinue;
         }
     }
     if (nx < 0) {   // boundary edge: stop on it (Sec. 4, original behaviour)
-        fin.ex = fmaf(lam, cs, st.s);
-        fin.ey = lam * sn;
-        fin.flags = (st.flags & kParity) | ((uint32_t)kRayBoundary << 8);
+        set_final(fin, old, fmaf(lam, cs, old.s), lam * sn, kRayBoundary);
         return kStepDone;
     }
-    const float nh = st.Lhi - lam;
-    st.Llo += (st.Lhi - nh) - lam;
+    // a vertex passed too far away to snap: an ordinary crossing
+    st = old;
+    st.s = s2;
+    st.t = t2;
+    st.phi = ph;
     st.Lhi = nh;
-    const uint32_t flip = (uint32_t)nx & 1u;
-    const float len = via_ca ? r.lac : r.lbc;
-    const float dm = mu * len, dom = omu * len;
-    float sn2 = via_ca ? dm : dom;
-    float tn2 = via_ca ? dom : dm;
-    uint32_t ph = via_ca ? st.phi - r.A : st.phi + r.B;
-    if (flip) {
-        const float tmp = sn2;
-        sn2 = tn2;
-        tn2 = tmp;
-        ph = kPiFx - ph;
-    }
-    // keep the direction inside [0, pi] against rounding of grazing exits
-    const int32_t phs = (int32_t)ph;
-    st.phi = (uint32_t)(phs < 0 ? 0 : phs);
-    st.s = sn2;
-    st.t = tn2;
+    st.Llo = lo;
     st.h = nx >> 1;
-    st.flags = (st.flags & kParity) ^ flip;
-    st.ncross += 1;
-    if (kHash) st.hash = fnv_face(st.hash, (uint32_t)(st.h / 3));
+    st.par = par;
+    st.bias = 0.f;
+    st.ncross = old.ncross + 1;
+    if (kHash) st.hash = fnv_face(old.hash, (uint32_t)(st.h / 3));
     return kStepContinue;
 }
 
-template <bool kHash>
+template <bool kHash, bool kFlip>
 SG_HD __forceinline__ void walk_to_end(const DevMesh& M, Ray& st, int32_t max_steps, float snap, Final& fin) {
-    while (walk_step<kHash>(M, st, max_steps, snap, fin) == kStepContinue) {
+    while (walk_step<kHash, kFlip>(M, st, max_steps, snap, fin) == kStepContinue) {
     }
-    fin.h = st.h;
-    fin.phi = st.phi;
-    fin.ncross = st.ncross;
-    fin.hash = st.hash;
 }
 
 // Outputs of a ray that never walked: bad input (NaN outputs) or |v_t| = 0
@@ -496,7 +523,7 @@ SG_HD __forceinline__ float tangent_length(const DevMesh& M, const ExpArgs& a, i
     return sqrtf(fmaf(vx, vx, vy * vy));
 }
 
-template <bool kHash>
+template <bool kHash, bool kFlip>
 SG_HD void exp_ray(const DevMesh& M, const ExpArgs& a, int64_t i) {
     Ray st;
     float L = 0.f;
@@ -506,15 +533,15 @@ SG_HD void exp_ray(const DevMesh& M, const ExpArgs& a, int64_t i) {
         return;
     }
     Final fin;
-    walk_to_end<kHash>(M, st, a.max_steps, a.snap, fin);
+    walk_to_end<kHash, kFlip>(M, st, a.max_steps, a.snap, fin);
     write_final(M, a, i, fin, L);
 }
 
-template <bool kHash>
+template <bool kHash, bool kFlip>
 __global__ __launch_bounds__(256) void k_exp_plain(DevMesh M, ExpArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
-    exp_ray<kHash>(M, a, i);
+    exp_ray<kHash, kFlip>(M, a, i);
 }
 
 // ---------------------------------------------------------------- persistent form
@@ -550,7 +577,7 @@ __global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* st
         rec.phi = st.phi;
         rec.Lhi = st.Lhi;
         rec.Llo = st.Llo;
-        rec.flags = st.flags;
+        rec.flags = st.bias > 0.f ? kForceBCBit : (st.bias < 0.f ? kForceCABit : 0u);
     }
     rec.pad = 0;
     states[i] = rec;
@@ -559,8 +586,9 @@ __global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* st
 // Persistent walk: each wave keeps 64 rays in flight and refills finished
 // lanes from a global queue (one atomic per wave per refill, ballot for the
 // lane ranks), so short and long rays share lanes instead of idling behind
-// the longest ray of a fixed batch.
-template <bool kHash>
+// the longest ray of a fixed batch.  Between refills the wave runs a tight
+// loop of walk steps and re-ballots only to see whether enough lanes are idle.
+template <bool kHash, bool kFlip>
 __global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
                                               int32_t max_steps, float snap, int refill_min) {
     const int lane = (int)(threadIdx.x & 63u);
@@ -569,10 +597,11 @@ __global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, int64
     bool exhausted = false;
     int64_t q = 0;
     Ray st;
-    st.h = 0; st.s = st.t = st.Lhi = st.Llo = 0.f; st.phi = st.flags = 0u; st.ncross = 0; st.hash = 0ull;
+    st.h = 0; st.s = st.t = st.Lhi = st.Llo = st.bias = 0.f; st.phi = st.par = 0u; st.ncross = 0; st.hash = 0ull;
     for (;;) {
         const uint64_t idle = __ballot(!active);
         const int nidle = __popcll(idle);
+        if (nidle == 64 && exhausted) break;
         if (!exhausted && nidle >= refill_min) {
             unsigned long long base = 0ull;
             if (lane == 0) base = atomicAdd(counter, (unsigned long long)nidle);
@@ -584,26 +613,27 @@ __global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, int64
                     const StateRec rec = states[q];
                     if (rec.h >= 0) {
                         st.h = rec.h; st.s = rec.s; st.t = rec.t; st.phi = rec.phi;
-                        st.Lhi = rec.Lhi; st.Llo = rec.Llo; st.flags = rec.flags;
+                        st.Lhi = rec.Lhi; st.Llo = rec.Llo;
+                        st.bias = (rec.flags & kForceBCBit) ? kForceBC : ((rec.flags & kForceCABit) ? kForceCA : 0.f);
+                        st.par = 0u;
                         st.ncross = 0;
                         st.hash = kHash ? fnv_face(14695981039346656037ull, (uint32_t)(rec.h / 3)) : 0ull;
                         active = true;
                     }
                 }
             }
-            continue;
         }
-        if (nidle == 64 && exhausted) break;
-        if (active) {
-            Final fin;
-            if (walk_step<kHash>(M, st, max_steps, snap, fin) == kStepDone) {
-                fin.h = st.h;
-                fin.phi = st.phi;
-                fin.ncross = st.ncross;
-                fin.hash = st.hash;
-                *reinterpret_cast<Final*>(&states[q]) = fin;
-                active = false;
+        // walk until enough lanes are idle to refill (all of them once the queue is empty)
+        const int stop_at = exhausted ? 64 : refill_min;
+        for (;;) {
+            if (active) {
+                Final fin;
+                if (walk_step<kHash, kFlip>(M, st, max_steps, snap, fin) == kStepDone) {
+                    *reinterpret_cast<Final*>(&states[q]) = fin;
+                    active = false;
+                }
             }
+            if (__popcll(__ballot(!active)) >= stop_at) break;
         }
     }
 }
@@ -618,14 +648,23 @@ __global__ __launch_bounds__(256) void k_finish(DevMesh M, ExpArgs a, const Stat
 
 }  // namespace
 
+// Launches the kernel instance for the (hash, orientation-flip) combination in use.
+#define SG_DISPATCH(KERNEL, HASH, FLIP, GRID, BLOCK, STREAM, ...)                          \
+    do {                                                                                   \
+        if (HASH) {                                                                        \
+            if (FLIP) KERNEL<true, true><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);   \
+            else KERNEL<true, false><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);       \
+        } else {                                                                           \
+            if (FLIP) KERNEL<false, true><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);  \
+            else KERNEL<false, false><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);      \
+        }                                                                                  \
+    } while (0)
+
 hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
     const int block = 256;
     const int64_t grid = (a.n + block - 1) / block;
-    if (a.debug & 2u)
-        hipLaunchKernelGGL(k_exp_plain<true>, dim3((unsigned)grid), dim3(block), 0, s, M, a);
-    else
-        hipLaunchKernelGGL(k_exp_plain<false>, dim3((unsigned)grid), dim3(block), 0, s, M, a);
+    SG_DISPATCH(k_exp_plain, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)grid), dim3(block), s, M, a);
     return hipGetLastError();
 }
 
@@ -640,12 +679,8 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, i
     auto* counter = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(ws) + (size_t)a.n * sizeof(StateRec));
     hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, counter);
     if (ev0) (void)hipEventRecord(ev0, s);
-    if (a.debug & 2u)
-        hipLaunchKernelGGL(k_walk<true>, dim3((unsigned)grid_blocks), dim3(block), 0, s, M, states, a.n, counter,
-                           a.max_steps, a.snap, refill_min);
-    else
-        hipLaunchKernelGGL(k_walk<false>, dim3((unsigned)grid_blocks), dim3(block), 0, s, M, states, a.n, counter,
-                           a.max_steps, a.snap, refill_min);
+    SG_DISPATCH(k_walk, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)grid_blocks), dim3(block), s, M, states,
+                a.n, counter, a.max_steps, a.snap, refill_min);
     if (ev1) (void)hipEventRecord(ev1, s);
     hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states);
     return hipGetLastError();
@@ -653,7 +688,7 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, i
 
 int walk_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk<false>, 256, 0) != hipSuccess || nb <= 0) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk<false, false>, 256, 0) != hipSuccess || nb <= 0) nb = 1;
     return nb;
 }
 

@@ -37,6 +37,7 @@ struct PackedMesh {
     std::vector<int64_t> half;
     int64_t n_verts = 0, n_faces = 0;
     double mean_edge = 0.0;
+    int32_t has_flip = 0;
 };
 
 // Validates and packs a mesh on the host; returns SG_OK or an SG_E_* code.

@@ -258,3 +258,18 @@ def test_persistent_schedules(torch, refill_min, walk_blocks):
     b = run(torch, gm, r, kernel=2, refill_min=refill_min, walk_blocks=walk_blocks)
     for k in ("f", "b", "p", "v", "W", "status", "n_cross", "hash"):
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_mixed_orientation(torch):
+    """Faces listed with inconsistent orientation: the walk only uses adjacency, so the
+    orientation-flip charts must give the oracle's answer (Sec. 4, non-orientable meshes)."""
+    from paper_2603_15780_amd import sg
+    X, F = M.icosphere(4)
+    X, F = M.canonical(M.sh_displace(X, 6, 0.1, np.random.default_rng(3)), F)
+    flip = np.random.default_rng(5).random(F.shape[0]) < 0.3
+    F2 = F.copy()
+    F2[flip] = F2[flip][:, [0, 2, 1]]
+    r = random_rays(X, F2, 20000, np.random.default_rng(4), uniform_len(0.0, 2.0), K=2)
+    for kernel in (1, 2):
+        om, gm, o, g = both(torch, X, F2, r, kernel=kernel)
+        assert_parity(o, g, om.mean_edge, K=2, label=f"mixed orientation, kernel {kernel}")

@@ -473,3 +473,23 @@ def test_gfd_sphere_jacobian_sanity():
         gv -= np.dot(gv, p[i]) * p[i]
         cos.append(np.dot(gv, out["grad_v"][i]) / np.linalg.norm(gv) / np.linalg.norm(out["grad_v"][i]))
     assert np.median(cos) > 0.98
+
+
+def test_orientation_invariance(rng):
+    """Reversing the vertex order of some faces describes the same surface: the
+    orientation-free unfolding must return the same points and vectors."""
+    X, F = M.icosphere(3)
+    X, F = M.canonical(M.sh_displace(X, 6, 0.1, np.random.default_rng(3)), F)
+    r = random_rays(X, F, 3000, rng, uniform_len(0.0, 2.0), K=2)
+    flip = np.random.default_rng(5).random(F.shape[0]) < 0.4
+    F2 = F.copy()
+    F2[flip] = F2[flip][:, [0, 2, 1]]
+    b2 = r["b"].astype(np.float64).copy()
+    sel = flip[r["f"]]
+    b2[sel] = b2[sel][:, [0, 2, 1]]
+    o = oracle.Mesh(X, F).exp(r["f"], r["b"], r["v"], r["W"])
+    o2 = oracle.Mesh(X, F2).exp(r["f"], b2, r["v"], r["W"])
+    far = o["min_vdist"] > 1e-9
+    assert np.abs(o2["p"] - o["p"])[far].max() < 1e-12
+    assert np.abs(o2["v"] - o["v"])[far].max() < 1e-12
+    assert np.abs(o2["W"] - o["W"])[far].max() < 1e-12
