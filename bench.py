@@ -42,6 +42,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=0, help="oracle sample size (0: whole batch)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain kernel for comparison")
+    ap.add_argument("--refill", type=int, default=0, help="persistent kernel refill threshold (0: library default)")
+    ap.add_argument("--walk-blocks", type=int, default=0, help="persistent kernel blocks (0: fill the GPU)")
     ap.add_argument("--calib-copy", type=int, default=0, help="MiB copied once to calibrate byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -70,7 +72,8 @@ def main():
         n_cross=torch.empty(n, dtype=torch.int32, device=dev), hash=None)
     def timed(kernel, steps, warmup):
         """(wall ms per call, event ms per call, walk-kernel event ms per launch or None)."""
-        o = sg.opts(kernel=kernel, debug=1 | (4 if kernel != 1 else 0))
+        o = sg.opts(kernel=kernel, debug=1 | (4 if kernel != 1 else 0), refill_min=args.refill,
+                    walk_blocks=args.walk_blocks)
         for _ in range(warmup):
             mesh.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=o)
         torch.cuda.synchronize()

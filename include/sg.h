@@ -58,14 +58,19 @@ enum {
 };
 
 enum { SG_BWD_EP = 0, SG_BWD_GFD = 1 };
-enum { SG_KERNEL_AUTO = 0, SG_KERNEL_PLAIN = 1, SG_KERNEL_PERSISTENT = 2 };
+enum {
+    SG_KERNEL_AUTO = 0,         /* = SG_KERNEL_PARTITIONED */
+    SG_KERNEL_PLAIN = 1,        /* one ray per lane, run to completion (Alg. gpu_parallel) */
+    SG_KERNEL_PERSISTENT = 2,   /* persistent waves refilled from one global ray queue */
+    SG_KERNEL_PARTITIONED = 3   /* persistent waves per XCD, each walking the rays inside its part of the mesh */
+};
 
 typedef struct {
     int32_t max_steps;     /* cap on crossings per ray (edge crossings + vertex passages); <= 0: 1 << 20 */
     float vertex_snap;     /* an exit point within this edge-parameter distance of an edge endpoint passes
                               through that vertex (straightest rule at vertices); <= 0: 2^-18 */
     float eps_v, eps_p;    /* GFD step sizes (absolute lengths); <= 0: 5e-3 * mean edge of the handle */
-    int32_t kernel;        /* SG_KERNEL_*: which forward kernel runs the walk (AUTO = PERSISTENT) */
+    int32_t kernel;        /* SG_KERNEL_*: which forward kernel runs the walk */
     uint32_t debug;        /* bit 0: fill n_cross; bit 1: fill seq_hash (FNV-1a 64 of the visited face ids);
                               bit 2: time the walk kernel with HIP events (read with sg_mesh_walk_time) */
     int32_t refill_min;    /* persistent kernel: a wave refetches rays once this many of its 64 lanes are

@@ -28,6 +28,7 @@ struct sg_mesh_s {
     int device = 0;
     int cu_count = 0;
     int walk_blocks_per_cu = 0;
+    int part_blocks_per_cu = 0;
     int64_t n_verts = 0, n_faces = 0;
     int32_t n_meshes = 1;
     double mean_edge = 0.0;
@@ -35,11 +36,16 @@ struct sg_mesh_s {
     int32_t* d_F = nullptr;
     float* d_X = nullptr;
     int64_t* d_half = nullptr;
+    int32_t* d_perm = nullptr;
+    int32_t* d_order = nullptr;
+    int32_t part_he[sg::kParts + 1] = {};
     int32_t has_flip = 0;
     size_t bytes = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare;   // walk-kernel event pairs
     sg::DevMesh dev() const {
-        return sg::DevMesh{d_rec, d_F, d_X, d_half, n_faces, n_verts, has_flip};
+        sg::DevMesh d{d_rec, d_F, d_X, d_half, d_perm, d_order, n_faces, n_verts, has_flip, {}};
+        for (int p = 0; p <= sg::kParts; ++p) d.part_he[p] = part_he[p];
+        return d;
     }
 };
 
@@ -117,6 +123,8 @@ void free_mesh(sg_mesh_s* m) {
     (void)hipFree(m->d_F);
     (void)hipFree(m->d_X);
     (void)hipFree(m->d_half);
+    (void)hipFree(m->d_perm);
+    (void)hipFree(m->d_order);
     delete m;
 }
 
@@ -128,11 +136,12 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     if (!(o.vertex_snap < 0.25f)) return fail(SG_E_ARG, "vertex_snap must be below 0.25");
     if (!(o.eps_v > 0.f)) o.eps_v = (float)(5e-3 * m->mean_edge);
     if (!(o.eps_p > 0.f)) o.eps_p = (float)(5e-3 * m->mean_edge);
-    if (o.kernel < SG_KERNEL_AUTO || o.kernel > SG_KERNEL_PERSISTENT) return fail(SG_E_ARG, "unknown kernel %d", o.kernel);
-    if (o.kernel == SG_KERNEL_AUTO) o.kernel = SG_KERNEL_PERSISTENT;
+    if (o.kernel < SG_KERNEL_AUTO || o.kernel > SG_KERNEL_PARTITIONED) return fail(SG_E_ARG, "unknown kernel %d", o.kernel);
+    if (o.kernel == SG_KERNEL_AUTO) o.kernel = SG_KERNEL_PARTITIONED;
     if (o.refill_min <= 0) o.refill_min = 16;
     if (o.refill_min > 64) return fail(SG_E_ARG, "refill_min must be at most 64");
-    if (o.walk_blocks <= 0) o.walk_blocks = m->cu_count * m->walk_blocks_per_cu;
+    if (o.walk_blocks <= 0)
+        o.walk_blocks = m->cu_count * (o.kernel == SG_KERNEL_PARTITIONED ? m->part_blocks_per_cu : m->walk_blocks_per_cu);
     return SG_OK;
 }
 
@@ -187,6 +196,54 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
             if (!(len(cross(X[t[1]] - X[t[0]], X[t[2]] - X[t[0]])) > 0.0))
                 return fail(SG_E_DEGENERATE, "face %lld has zero area", (long long)f);
         }
+        // Spatial face order: recursive coordinate bisection of the face centroids
+        // (median split along the longest box axis).  The first three levels cut
+        // the faces into 8 contiguous parts of equal count, one per XCD; deeper
+        // levels keep neighbouring faces close in memory.  Everything below works
+        // on internal ids; perm / order map user ids to internal ids and back.
+        {
+            std::vector<V3> cen(n_faces);
+            for (int64_t f = 0; f < n_faces; ++f) {
+                const V3 a = X[F[3 * f]], b = X[F[3 * f + 1]], c = X[F[3 * f + 2]];
+                cen[f] = {(a.x + b.x + c.x) / 3.0, (a.y + b.y + c.y) / 3.0, (a.z + b.z + c.z) / 3.0};
+            }
+            std::vector<int64_t>& order = out.order;
+            order.resize(n_faces);
+            std::iota(order.begin(), order.end(), 0);
+            struct Span { int64_t lo, hi; };
+            std::vector<Span> stack{{0, n_faces}};
+            while (!stack.empty()) {
+                const Span sp = stack.back();
+                stack.pop_back();
+                if (sp.hi - sp.lo <= 16) continue;
+                V3 mn = cen[order[sp.lo]], mx = mn;
+                for (int64_t i = sp.lo; i < sp.hi; ++i) {
+                    const V3 c = cen[order[i]];
+                    mn = {std::min(mn.x, c.x), std::min(mn.y, c.y), std::min(mn.z, c.z)};
+                    mx = {std::max(mx.x, c.x), std::max(mx.y, c.y), std::max(mx.z, c.z)};
+                }
+                const double ex_ = mx.x - mn.x, ey_ = mx.y - mn.y, ez_ = mx.z - mn.z;
+                const int ax = ex_ >= ey_ && ex_ >= ez_ ? 0 : (ey_ >= ez_ ? 1 : 2);
+                const int64_t mid = sp.lo + (sp.hi - sp.lo) / 2;
+                std::nth_element(order.begin() + sp.lo, order.begin() + mid, order.begin() + sp.hi,
+                                 [&](int64_t u, int64_t w) {
+                                     const double cu = ax == 0 ? cen[u].x : (ax == 1 ? cen[u].y : cen[u].z);
+                                     const double cw = ax == 0 ? cen[w].x : (ax == 1 ? cen[w].y : cen[w].z);
+                                     return cu < cw || (cu == cw && u < w);
+                                 });
+                stack.push_back({sp.lo, mid});
+                stack.push_back({mid, sp.hi});
+            }
+            std::vector<int32_t> Fi(3 * n_faces);
+            out.perm.resize(n_faces);
+            for (int64_t i = 0; i < n_faces; ++i) {
+                out.perm[order[i]] = (int32_t)i;
+                for (int k = 0; k < 3; ++k) Fi[3 * i + k] = F[3 * order[i] + k];
+            }
+            F.swap(Fi);
+            // the 8 parts: ranges [n_faces * p / 8, n_faces * (p + 1) / 8) of the bisection order
+            for (int p = 0; p <= kParts; ++p) out.part_start[p] = n_faces * p / kParts;
+        }
         // undirected edges: sort half-edges by (min, max) vertex key
         const int64_t nh = 3 * n_faces;
         std::vector<uint64_t> key(nh);
@@ -212,7 +269,8 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
                 return fail(SG_E_NONMANIFOLD, "edge (%d,%d) has %lld faces", std::min(a, b), std::max(a, b), (long long)(j - i));
             if (j - i == 2) {
                 const int64_t h1 = order[i + 1];
-                if (h0 / 3 == h1 / 3) return fail(SG_E_DEGENERATE, "face %lld uses an edge twice", (long long)(h0 / 3));
+                if (h0 / 3 == h1 / 3)
+                    return fail(SG_E_DEGENERATE, "face %lld uses an edge twice", (long long)out.order[h0 / 3]);
                 twin[h0] = h1;
                 twin[h1] = h0;
             } else {
@@ -334,15 +392,20 @@ int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, 
         m->cu_count <= 0)
         m->cu_count = 256;
     m->walk_blocks_per_cu = sg::walk_blocks_per_cu();
+    m->part_blocks_per_cu = sg::part_blocks_per_cu();
     m->n_verts = n_verts;
     m->n_faces = n_faces;
     m->n_meshes = n_meshes;
     m->mean_edge = pm.mean_edge;
     m->has_flip = pm.has_flip;
+    for (int p = 0; p <= sg::kParts; ++p) m->part_he[p] = (int32_t)(3 * pm.part_start[p]);
+    std::vector<int32_t> order32(pm.order.begin(), pm.order.end());
     rc = upload(&m->d_rec, pm.rec, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_F, pm.F, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_X, pm.X, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_half, pm.half, m->bytes);
+    if (rc == SG_OK) rc = upload(&m->d_perm, pm.perm, m->bytes);
+    if (rc == SG_OK) rc = upload(&m->d_order, order32, m->bytes);
     if (rc != SG_OK) {
         free_mesh(m);
         return rc;
@@ -408,9 +471,11 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
         if (e != hipSuccess) return hip_fail(e, "forward launch");
         return SG_OK;
     }
-    // persistent form: per-ray chart states live in a stream-ordered workspace
+    // persistent forms: per-ray chart states and queues live in a stream-ordered workspace
+    const bool part = o.kernel == SG_KERNEL_PARTITIONED;
+    const size_t wsb = part ? sg::exp_partitioned_workspace(n, (o.debug & 2u) != 0u) : sg::exp_persistent_workspace(n);
     void* ws = nullptr;
-    hipError_t e = hipMallocAsync(&ws, sg::exp_persistent_workspace(n), st);
+    hipError_t e = hipMallocAsync(&ws, wsb, st);
     if (e != hipSuccess) return fail(SG_E_OOM, "workspace allocation: %s", hipGetErrorString(e));
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     if (o.debug & 4u) {
@@ -422,7 +487,8 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
             return fail(SG_E_HIP, "hipEventCreate failed");
         }
     }
-    e = sg::launch_exp_persistent(mesh->dev(), a, ws, o.walk_blocks, o.refill_min, st, ev.first, ev.second);
+    e = part ? sg::launch_exp_partitioned(mesh->dev(), a, ws, o.walk_blocks, o.refill_min, st, ev.first, ev.second)
+             : sg::launch_exp_persistent(mesh->dev(), a, ws, o.walk_blocks, o.refill_min, st, ev.first, ev.second);
     if (ev.first) mesh->timed.push_back(ev);
     const hipError_t e2 = hipFreeAsync(ws, st);
     if (e != hipSuccess) return hip_fail(e, "forward launch");

@@ -31,15 +31,23 @@ struct alignas(32) HalfEdgeRec {
 };
 static_assert(sizeof(HalfEdgeRec) == 32, "record must be one 32-byte sector");
 
-// Device view of a packed mesh handle.
+// Faces are stored in a spatial (bisection) order cut into kParts contiguous
+// parts, one per XCD of the MI355X, so that a part's records fit that XCD's L2.
+constexpr int kParts = 8;
+
+// Device view of a packed mesh handle.  Face ids inside the library are
+// internal (bisection order); rays name faces by user id.
 struct DevMesh {
-    const HalfEdgeRec* rec;   // [3 n_faces]
-    const int32_t* F;         // [n_faces, 3] global vertex ids
-    const float* X;           // [n_verts, 3]
-    const int64_t* half_theta;// [n_verts] theta(x)/2 in fixed point, -1 on boundary vertices
+    const HalfEdgeRec* rec;     // [3 n_faces], internal order
+    const int32_t* F;           // [n_faces, 3] global vertex ids, internal order
+    const float* X;             // [n_verts, 3]
+    const int64_t* half_theta;  // [n_verts] theta(x)/2 in fixed point, -1 on boundary vertices
+    const int32_t* perm;        // [n_faces] user face id -> internal id
+    const int32_t* order;       // [n_faces] internal face id -> user id
     int64_t n_faces;
     int64_t n_verts;
-    int32_t has_flip;         // some adjacent faces disagree in orientation (non-orientable or mixed)
+    int32_t has_flip;           // some adjacent faces disagree in orientation (non-orientable or mixed)
+    int32_t part_he[kParts + 1];// half-edge id ranges of the parts
 };
 
 enum RayStatus : int32_t { kRayOk = 0, kRayMaxSteps = 1, kRayBoundary = 2, kRayBadInput = 3 };

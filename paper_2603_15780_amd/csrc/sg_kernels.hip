@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "sg_internal.h"
 #include "sg_launch.h"
 
@@ -34,6 +36,7 @@ constexpr float kForceBC = kBig;    // vertex at a: leave through b-c
 constexpr float kForceCA = -kBig;   // vertex at b: leave through c-a
 constexpr uint32_t kForceBCBit = 2u, kForceCABit = 4u;   // the same, in a stored state record
 constexpr uint32_t kParity = 1u;    // orientation flipped an odd number of times
+constexpr uint32_t kDoneBit = 1u << 16;   // a Final record: the walk reached its end
 
 // sin(x)/x and cos(x) as polynomials in u = x^2 on |x| <= pi/2 (least-squares
 // minimax fits, max error about 1.4e-7 in float32).
@@ -128,8 +131,9 @@ enum InitResult { kInitOk = 0, kInitZero = 1, kInitBad = 2 };
 // initialise_trace (Alg. gpu_parallel): project v onto the start face, then
 // extend the ray backwards to the edge it would have entered through, so the
 // walk always starts on an entry edge with remaining length |v_t| + tau.
-SG_HD int ray_init(const DevMesh& M, int32_t f, const float* bp, const float* vp, Ray& st, float& L) {
-    if (f < 0 || (int64_t)f >= M.n_faces) return kInitBad;
+SG_HD int ray_init(const DevMesh& M, int32_t fu, const float* bp, const float* vp, Ray& st, float& L) {
+    if (fu < 0 || (int64_t)fu >= M.n_faces) return kInitBad;
+    const int32_t f = M.perm[fu];   // internal face id
     float b0 = bp[0], b1 = bp[1], b2 = bp[2];
     if (!(b0 >= 0.f && b1 >= 0.f && b2 >= 0.f)) return kInitBad;
     const float bs = b0 + b1 + b2;
@@ -204,7 +208,7 @@ SG_HD int ray_init(const DevMesh& M, int32_t f, const float* bp, const float* vp
     st.par = 0u;
     st.bias = st.s == 0.f ? kForceBC : (st.t == 0.f ? kForceCA : 0.f);
     st.ncross = 0;
-    st.hash = fnv_face(14695981039346656037ull, (uint32_t)f);
+    st.hash = fnv_face(14695981039346656037ull, (uint32_t)fu);
     return kInitOk;
 }
 
@@ -293,7 +297,7 @@ struct Final {
     int32_t h;
     float ex, ey;
     uint32_t phi;
-    uint32_t flags;   // bit 0 parity, bits 8..15 status
+    uint32_t flags;   // bit 0 parity, bits 8..15 status, bit 16 done
     int32_t ncross;
     uint64_t hash;
 };
@@ -306,7 +310,7 @@ SG_HD __forceinline__ void set_final(Final& fin, const Ray& st, float ex, float 
     fin.ex = ex;
     fin.ey = ey;
     fin.phi = st.phi;
-    fin.flags = (st.par & kParity) | ((uint32_t)status << 8);
+    fin.flags = (st.par & kParity) | ((uint32_t)status << 8) | kDoneBit;
     fin.ncross = st.ncross;
     fin.hash = st.hash;
 }
@@ -361,7 +365,7 @@ SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps
     st.par = rare ? st.par : par;
     st.bias = rare ? st.bias : 0.f;
     st.ncross += rare ? 0 : 1;
-    if (kHash && !rare) st.hash = fnv_face(st.hash, (uint32_t)(st.h / 3));
+    if (kHash && !rare) st.hash = fnv_face(st.hash, (uint32_t)M.order[st.h / 3]);
     if (!rare) return kStepContinue;
 
     // ---- rare events, in priority order
@@ -386,7 +390,7 @@ SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps
             cand.Lhi = nh;
             cand.Llo = lo;
             cand.ncross = old.ncross + 1;
-            cand.hash = kHash ? fnv_face(old.hash, (uint32_t)(cand.h / 3)) : 0ull;
+            cand.hash = kHash ? fnv_face(old.hash, (uint32_t)M.order[cand.h / 3]) : 0ull;
             st = cand;
             return kStepContinue;
         }
@@ -406,7 +410,7 @@ SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps
     st.par = par;
     st.bias = 0.f;
     st.ncross = old.ncross + 1;
-    if (kHash) st.hash = fnv_face(old.hash, (uint32_t)(st.h / 3));
+    if (kHash) st.hash = fnv_face(old.hash, (uint32_t)M.order[st.h / 3]);
     return kStepContinue;
 }
 
@@ -428,7 +432,7 @@ SG_HD void write_unwalked(const DevMesh& M, const ExpArgs& a, int64_t i, bool ba
     if (!bad) {
         const float s = bo[0] + bo[1] + bo[2];
         bo[0] /= s; bo[1] /= s; bo[2] /= s;
-        const int64_t f3 = 3 * (int64_t)f0;
+        const int64_t f3 = 3 * (int64_t)M.perm[f0];
         const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
         const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
         const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
@@ -467,7 +471,7 @@ SG_HD void write_final(const DevMesh& M, const ExpArgs& a, int64_t i, const Fina
     const float ell = sqrtf(dot(eab, eab));
     float bo[3];
     chart_bary(r, ell, fin.ex, fin.ey, ke, bo[0], bo[1], bo[2]);
-    a.f_out[i] = fe;
+    a.f_out[i] = M.order[fe];
     a.b_out[3 * i] = bo[0]; a.b_out[3 * i + 1] = bo[1]; a.b_out[3 * i + 2] = bo[2];
     a.p_out[3 * i] = fmaf(bo[0], y0.x, fmaf(bo[1], y1.x, bo[2] * y2.x));
     a.p_out[3 * i + 1] = fmaf(bo[0], y0.y, fmaf(bo[1], y1.y, bo[2] * y2.y));
@@ -481,8 +485,7 @@ SG_HD void write_final(const DevMesh& M, const ExpArgs& a, int64_t i, const Fina
     a.v_out[3 * i] = L * d3.x; a.v_out[3 * i + 1] = L * d3.y; a.v_out[3 * i + 2] = L * d3.z;
     if (a.K > 0) {
         // components of each extra vector in the start frame (tangent, normal x tangent)
-        const int32_t f0 = a.f[i];
-        const int64_t g3 = 3 * (int64_t)f0;
+        const int64_t g3 = 3 * (int64_t)M.perm[a.f[i]];
         const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[g3]);
         const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[g3 + 1]);
         const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[g3 + 2]);
@@ -509,7 +512,7 @@ SG_HD void write_final(const DevMesh& M, const ExpArgs& a, int64_t i, const Fina
 // |v_t| of ray i (projection of v onto the start face), recomputed where the
 // walk state did not keep it.
 SG_HD __forceinline__ float tangent_length(const DevMesh& M, const ExpArgs& a, int64_t i) {
-    const int64_t f3 = 3 * (int64_t)a.f[i];
+    const int64_t f3 = 3 * (int64_t)M.perm[a.f[i]];
     const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
     const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
     const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
@@ -552,9 +555,24 @@ struct alignas(32) StateRec {
     float s, t;
     uint32_t phi;
     float Lhi, Llo;
-    uint32_t flags;
-    int32_t pad;
+    uint32_t flags;   // force-exit bits and parity
+    int32_t ncross;
 };
+
+SG_HD __forceinline__ StateRec pack_state(const Ray& st) {
+    StateRec r;
+    r.h = st.h; r.s = st.s; r.t = st.t; r.phi = st.phi; r.Lhi = st.Lhi; r.Llo = st.Llo;
+    r.flags = (st.par & kParity) | (st.bias > 0.f ? kForceBCBit : (st.bias < 0.f ? kForceCABit : 0u));
+    r.ncross = st.ncross;
+    return r;
+}
+
+SG_HD __forceinline__ void unpack_state(const StateRec& r, Ray& st) {
+    st.h = r.h; st.s = r.s; st.t = r.t; st.phi = r.phi; st.Lhi = r.Lhi; st.Llo = r.Llo;
+    st.bias = (r.flags & kForceBCBit) ? kForceBC : ((r.flags & kForceCABit) ? kForceCA : 0.f);
+    st.par = r.flags & kParity;
+    st.ncross = r.ncross;
+}
 static_assert(sizeof(StateRec) == 32, "state record is one 32-byte sector");
 
 __global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* states, unsigned long long* counter) {
@@ -570,16 +588,10 @@ __global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* st
         rec.h = -1;
         rec.s = rec.t = rec.Lhi = rec.Llo = 0.f;
         rec.phi = rec.flags = 0u;
+        rec.ncross = 0;
     } else {
-        rec.h = st.h;
-        rec.s = st.s;
-        rec.t = st.t;
-        rec.phi = st.phi;
-        rec.Lhi = st.Lhi;
-        rec.Llo = st.Llo;
-        rec.flags = st.bias > 0.f ? kForceBCBit : (st.bias < 0.f ? kForceCABit : 0u);
+        rec = pack_state(st);
     }
-    rec.pad = 0;
     states[i] = rec;
 }
 
@@ -612,12 +624,8 @@ __global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, int64
                 if (q < n) {
                     const StateRec rec = states[q];
                     if (rec.h >= 0) {
-                        st.h = rec.h; st.s = rec.s; st.t = rec.t; st.phi = rec.phi;
-                        st.Lhi = rec.Lhi; st.Llo = rec.Llo;
-                        st.bias = (rec.flags & kForceBCBit) ? kForceBC : ((rec.flags & kForceCABit) ? kForceCA : 0.f);
-                        st.par = 0u;
-                        st.ncross = 0;
-                        st.hash = kHash ? fnv_face(14695981039346656037ull, (uint32_t)(rec.h / 3)) : 0ull;
+                        unpack_state(rec, st);
+                        st.hash = kHash ? fnv_face(14695981039346656037ull, (uint32_t)M.order[rec.h / 3]) : 0ull;
                         active = true;
                     }
                 }
@@ -638,11 +646,293 @@ __global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, int64
     }
 }
 
-__global__ __launch_bounds__(256) void k_finish(DevMesh M, ExpArgs a, const StateRec* states) {
+// ---------------------------------------------------------------- partitioned form
+// The mesh is cut into kParts spatial parts (contiguous internal face ranges),
+// one per XCD: blocks are dealt to XCDs round-robin, so block b serves part
+// b % kParts and that part's records stay in its XCD's L2.  A ray is walked by
+// the part that contains its current face; when it crosses into another part
+// its 32-byte state is handed to that part through a queue.  Handoffs between
+// XCDs use agent-scope loads and stores (coherent past the per-XCD L2s).
+struct PartCounters {
+    unsigned long long init_count[kParts];   // rays starting in each part (set by k_init_part)
+    unsigned long long init_head[kParts];    // next unread entry of each part's start queue
+    unsigned long long mig_tail[kParts];     // reservations in each part's handoff queue
+    unsigned long long mig_head[kParts];     // next unread handoff entry
+    unsigned long long finished;             // rays whose walk ended
+    unsigned long long pad[7];
+};
+
+SG_HD __forceinline__ int part_of(const DevMesh& M, int32_t h) {
+    int p = 0;
+#pragma unroll
+    for (int k = 1; k < kParts; ++k) p += h >= M.part_he[k] ? 1 : 0;
+    return p;
+}
+
+template <class T>
+__device__ __forceinline__ T ld_agent(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void st_agent(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_state_agent(StateRec* dst, const StateRec& r) {
+    const uint64_t* w = reinterpret_cast<const uint64_t*>(&r);
+    uint64_t* d = reinterpret_cast<uint64_t*>(dst);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) st_agent(d + k, w[k]);
+}
+__device__ __forceinline__ StateRec ld_state_agent(const StateRec* src) {
+    StateRec r;
+    uint64_t* w = reinterpret_cast<uint64_t*>(&r);
+    const uint64_t* s = reinterpret_cast<const uint64_t*>(src);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = ld_agent(s + k);
+    return r;
+}
+
+// k_part_reset: zero the queue counters and the handoff slots (0 = not yet written).
+__global__ __launch_bounds__(256) void k_part_reset(PartCounters* qc, int32_t* migq, int64_t slots) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (int64_t)(sizeof(PartCounters) / 8)) reinterpret_cast<unsigned long long*>(qc)[i] = 0ull;
+    for (int64_t k = i; k < slots; k += (int64_t)gridDim.x * blockDim.x) migq[k] = 0;
+}
+
+// k_init_part: initial chart state of every ray; walkable rays join the start
+// queue of the part their first face lies in (one atomic per wave and part).
+__global__ __launch_bounds__(256) void k_init_part(DevMesh M, ExpArgs a, StateRec* states, int32_t* initq,
+                                                   PartCounters* qc, int64_t cap) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = (int)(threadIdx.x & 63u);
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int mypart = -1;
+    if (i < a.n) {
+        Ray st;
+        float L = 0.f;
+        const int ir = ray_init(M, a.f[i], a.b + 3 * i, a.v + 3 * i, st, L);
+        StateRec rec;
+        if (ir != kInitOk) {
+            write_unwalked(M, a, i, ir == kInitBad);
+            rec.h = -1;
+            rec.s = rec.t = rec.Lhi = rec.Llo = 0.f;
+            rec.phi = rec.flags = 0u;
+            rec.ncross = 0;
+        } else {
+            rec = pack_state(st);
+            mypart = part_of(M, st.h);
+        }
+        states[i] = rec;
+    }
+#pragma unroll 1
+    for (int p = 0; p < kParts; ++p) {
+        const uint64_t m = __ballot(mypart == p);
+        if (!m) continue;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        unsigned long long base = 0ull;
+        if (lane == leader) base = atomicAdd(&qc->init_count[p], (unsigned long long)__popcll(m));
+        base = __shfl(base, leader);
+        if (mypart == p) initq[(int64_t)p * cap + (int64_t)base + __popcll(m & below)] = (int32_t)i;
+    }
+}
+
+// Take up to `want` entries of part q's handoff queue: returns the first index
+// and the count (lane 0 does the compare-and-swap; the result is broadcast).
+__device__ __forceinline__ int take_handoffs(PartCounters* qc, int q, int want, int64_t cap, unsigned long long& first) {
+    const int lane = (int)(threadIdx.x & 63u);
+    unsigned long long h0 = 0ull;
+    int got = 0;
+    if (lane == 0) {
+        unsigned long long h = ld_agent(&qc->mig_head[q]);
+        for (int tries = 0; tries < 64; ++tries) {
+            unsigned long long t = ld_agent(&qc->mig_tail[q]);
+            if (t > (unsigned long long)cap) t = (unsigned long long)cap;
+            if (h >= t) break;
+            const unsigned long long k = (t - h) < (unsigned long long)want ? (t - h) : (unsigned long long)want;
+            const unsigned long long seen = atomicCAS(&qc->mig_head[q], h, h + k);
+            if (seen == h) { h0 = h; got = (int)k; break; }
+            h = seen;
+        }
+    }
+    first = __shfl(h0, 0);
+    return __shfl(got, 0);
+}
+
+template <bool kHash, bool kFlip>
+__global__ __launch_bounds__(256) void k_walk_part(DevMesh M, StateRec* states, uint64_t* hashes, const int32_t* initq,
+                                                   int32_t* migq, PartCounters* qc, int64_t cap, int32_t max_steps,
+                                                   float snap, int refill_min, int idle_limit) {
+    const int home = (int)(blockIdx.x % kParts);
+    const int lane = (int)(threadIdx.x & 63u);
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    unsigned long long n_walk = 0ull;
+#pragma unroll
+    for (int p = 0; p < kParts; ++p) n_walk += qc->init_count[p];
+    bool active = false;
+    int32_t ray = 0, lo = 0, hi = 0;
+    Ray st;
+    st.h = 0; st.s = st.t = st.Lhi = st.Llo = st.bias = 0.f; st.phi = st.par = 0u; st.ncross = 0; st.hash = 0ull;
+    bool init_left = true;           // wave-uniform: the home start queue may hold rays
+    unsigned long long done_local = 0ull;
+    int idle_spins = 0;
+    int quiet = 0;                   // walk steps to take before polling the queues again
+    for (;;) {
+        uint64_t idle = __ballot(!active);
+        int nidle = __popcll(idle);
+        if (nidle >= refill_min && quiet <= 0) {
+            int got = 0;
+            const int rank = __popcll(idle & below);
+            // (a) rays starting in the home part
+            if (init_left) {
+                unsigned long long base = 0ull;
+                if (lane == 0) base = atomicAdd(&qc->init_head[home], (unsigned long long)nidle);
+                base = __shfl(base, 0);
+                const unsigned long long cnt = qc->init_count[home];
+                const int take = base >= cnt ? 0 : (int)((cnt - base) < (unsigned long long)nidle ? (cnt - base) : nidle);
+                if (base + (unsigned long long)nidle >= cnt) init_left = false;
+                if (!active && rank < take) {
+                    ray = initq[(int64_t)home * cap + (int64_t)base + rank];
+                    unpack_state(states[ray], st);
+                    st.hash = kHash ? fnv_face(14695981039346656037ull, (uint32_t)M.order[st.h / 3]) : 0ull;
+                    lo = M.part_he[home];
+                    hi = M.part_he[home + 1];
+                    active = true;
+                }
+                got += take;
+            }
+            // (b) rays handed over from other parts
+            if (got < nidle) {
+                unsigned long long first = 0ull;
+                const int take = take_handoffs(qc, home, nidle - got, cap, first);
+                if (!active && rank >= got && rank < got + take) {
+                    int32_t* slot = migq + (int64_t)home * cap + (int64_t)(first + (rank - got));
+                    int32_t v = ld_agent(slot);
+                    for (int w = 0; v == 0 && w < (1 << 22); ++w) {   // the producer writes right after reserving
+                        __builtin_amdgcn_s_sleep(1);
+                        v = ld_agent(slot);
+                    }
+                    if (v != 0) {
+                        ray = v - 1;
+                        unpack_state(ld_state_agent(states + ray), st);
+                        if (kHash) st.hash = ld_agent(hashes + ray);
+                        lo = M.part_he[home];
+                        hi = M.part_he[home + 1];
+                        active = true;
+                    }
+                }
+                got += take;
+            }
+            // (c) nothing at home and every lane idle: help another part
+            if (got == 0 && nidle == 64) {
+                for (int k = 1; k < kParts && got == 0; ++k) {
+                    const int q = (home + k) % kParts;
+                    unsigned long long base = 0ull;
+                    if (lane == 0 && ld_agent(&qc->init_head[q]) < qc->init_count[q])
+                        base = atomicAdd(&qc->init_head[q], 64ull);
+                    else if (lane == 0)
+                        base = ~0ull;
+                    base = __shfl(base, 0);
+                    const unsigned long long cnt = qc->init_count[q];
+                    int take = 0;
+                    if (base != ~0ull && base < cnt) take = (int)((cnt - base) < 64ull ? (cnt - base) : 64ull);
+                    if (take > 0) {
+                        if (lane < take) {
+                            ray = initq[(int64_t)q * cap + (int64_t)base + lane];
+                            unpack_state(states[ray], st);
+                            st.hash = kHash ? fnv_face(14695981039346656037ull, (uint32_t)M.order[st.h / 3]) : 0ull;
+                            lo = M.part_he[q];
+                            hi = M.part_he[q + 1];
+                            active = true;
+                        }
+                        got = take;
+                        break;
+                    }
+                    unsigned long long first = 0ull;
+                    take = take_handoffs(qc, q, 64, cap, first);
+                    if (take > 0) {
+                        if (lane < take) {
+                            int32_t* slot = migq + (int64_t)q * cap + (int64_t)(first + lane);
+                            int32_t v = ld_agent(slot);
+                            for (int w = 0; v == 0 && w < (1 << 22); ++w) {
+                                __builtin_amdgcn_s_sleep(1);
+                                v = ld_agent(slot);
+                            }
+                            if (v != 0) {
+                                ray = v - 1;
+                                unpack_state(ld_state_agent(states + ray), st);
+                                if (kHash) st.hash = ld_agent(hashes + ray);
+                                lo = M.part_he[q];
+                                hi = M.part_he[q + 1];
+                                active = true;
+                            }
+                        }
+                        got = take;
+                    }
+                }
+            }
+            if (got == 0 && nidle == 64) {
+                // no work anywhere right now: count this wave's finished rays, then test for the end
+                if (lane == 0 && done_local) atomicAdd(&qc->finished, done_local);
+                done_local = 0ull;
+                if (ld_agent(&qc->finished) >= n_walk) break;
+                if (++idle_spins > idle_limit) break;   // bounded: the kernel always drains
+                __builtin_amdgcn_s_sleep(16);
+                continue;
+            }
+            idle_spins = 0;
+            quiet = got == 0 ? 16 : 0;   // found nothing: walk a while before polling again
+        }
+        // walk until enough lanes are idle to refill
+        for (;;) {
+            bool ended = false;
+            if (active) {
+                Final fin;
+                if (walk_step<kHash, kFlip>(M, st, max_steps, snap, fin) == kStepDone) {
+                    *reinterpret_cast<Final*>(&states[ray]) = fin;
+                    if (kHash) hashes[ray] = fin.hash;
+                    active = false;
+                    ended = true;
+                } else if (st.h < lo || st.h >= hi) {
+                    // entered another part: hand the ray over to it
+                    const int dst = part_of(M, st.h);
+                    const unsigned long long idx = atomicAdd(&qc->mig_tail[dst], 1ull);
+                    if (idx < (unsigned long long)cap) {
+                        st_state_agent(states + ray, pack_state(st));
+                        if (kHash) st_agent(hashes + ray, st.hash);
+                        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // state lands before the slot
+                        st_agent(migq + (int64_t)dst * cap + (int64_t)idx, ray + 1);
+                        active = false;
+                    } else {   // queue full: keep walking here
+                        lo = M.part_he[dst];
+                        hi = M.part_he[dst + 1];
+                    }
+                }
+            }
+            done_local += (unsigned long long)__popcll(__ballot(ended));
+            --quiet;
+            nidle = __popcll(__ballot(!active));
+            if (nidle >= refill_min && quiet <= 0) break;
+            if (nidle == 64) break;
+        }
+    }
+    if (lane == 0 && done_local) atomicAdd(&qc->finished, done_local);
+}
+
+__global__ __launch_bounds__(256) void k_finish(DevMesh M, ExpArgs a, const StateRec* states, const uint64_t* hashes) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
-    const Final fin = *reinterpret_cast<const Final*>(&states[i]);
+    Final fin = *reinterpret_cast<const Final*>(&states[i]);
     if (fin.h < 0) return;
+    if (!(fin.flags & kDoneBit)) {
+        // never reached its end (a walk kernel gave up waiting): report where it is
+        const StateRec rec = states[i];
+        fin.h = rec.h; fin.ex = rec.s; fin.ey = 0.f; fin.phi = rec.phi;
+        fin.flags = (rec.flags & kParity) | ((uint32_t)kRayMaxSteps << 8);
+        fin.ncross = rec.ncross;
+        fin.hash = 0ull;
+    }
+    if (hashes) fin.hash = hashes[i];
     write_final(M, a, i, fin, tangent_length(M, a, i));
 }
 
@@ -682,13 +972,59 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, i
     SG_DISPATCH(k_walk, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)grid_blocks), dim3(block), s, M, states,
                 a.n, counter, a.max_steps, a.snap, refill_min);
     if (ev1) (void)hipEventRecord(ev1, s);
-    hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states);
+    hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)nullptr);
+    return hipGetLastError();
+}
+
+size_t exp_partitioned_workspace(int64_t n, bool hashes) {
+    size_t b = (size_t)n * sizeof(StateRec);          // states
+    b += sizeof(PartCounters);
+    b += 2 * (size_t)kParts * (size_t)n * 4;          // start and handoff queues
+    if (hashes) b += (size_t)n * 8;
+    return b + 1024;
+}
+
+hipError_t launch_exp_partitioned(const DevMesh& M, const ExpArgs& a, void* ws, int grid_blocks, int refill_min,
+                                  hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (a.n <= 0) return hipSuccess;
+    const int block = 256;
+    const int64_t grid = (a.n + block - 1) / block;
+    const int64_t cap = a.n;
+    const bool hash = (a.debug & 2u) != 0u;
+    char* p = reinterpret_cast<char*>(ws);
+    auto* states = reinterpret_cast<StateRec*>(p);
+    p += (size_t)a.n * sizeof(StateRec);
+    auto* qc = reinterpret_cast<PartCounters*>(p);
+    p += sizeof(PartCounters);
+    auto* initq = reinterpret_cast<int32_t*>(p);
+    p += (size_t)kParts * (size_t)cap * 4;
+    auto* migq = reinterpret_cast<int32_t*>(p);
+    p += (size_t)kParts * (size_t)cap * 4;
+    auto* hashes = hash ? reinterpret_cast<uint64_t*>(p) : nullptr;
+    const int64_t slots = (int64_t)kParts * cap;
+    const int64_t rgrid = std::min<int64_t>((slots + block - 1) / block, 4096);
+    hipLaunchKernelGGL(k_part_reset, dim3((unsigned)rgrid), dim3(block), 0, s, qc, migq, slots);
+    hipLaunchKernelGGL(k_init_part, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, initq, qc, cap);
+    if (ev0) (void)hipEventRecord(ev0, s);
+    const int blocks = (grid_blocks + kParts - 1) / kParts * kParts;   // every part gets the same number of blocks
+    const int idle_limit = 1 << 22;
+    SG_DISPATCH(k_walk_part, hash, M.has_flip != 0, dim3((unsigned)blocks), dim3(block), s, M, states, hashes, initq,
+                migq, qc, cap, a.max_steps, a.snap, refill_min, idle_limit);
+    if (ev1) (void)hipEventRecord(ev1, s);
+    hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)hashes);
     return hipGetLastError();
 }
 
 int walk_blocks_per_cu() {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk<false, false>, 256, 0) != hipSuccess || nb <= 0) nb = 1;
+    return nb;
+}
+
+int part_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_part<false, false>, 256, 0) != hipSuccess || nb <= 0)
+        nb = 1;
     return nb;
 }
 

@@ -32,7 +32,10 @@ struct ExpArgs {
 // Host-side result of packing a mesh (float64 work, rounded once).
 struct PackedMesh {
     std::vector<HalfEdgeRec> rec;
-    std::vector<int32_t> F;
+    std::vector<int32_t> F;           // internal (bisection) face order
+    std::vector<int64_t> order;       // internal face id -> user face id
+    std::vector<int32_t> perm;        // user face id -> internal face id
+    int64_t part_start[kParts + 1];   // internal face ranges of the XCD parts
     std::vector<float> X;
     std::vector<int64_t> half;
     int64_t n_verts = 0, n_faces = 0;
@@ -54,5 +57,12 @@ size_t exp_persistent_workspace(int64_t n);
 hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, int grid_blocks, int refill_min,
                                  hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 int walk_blocks_per_cu();
+int part_blocks_per_cu();
+
+// Partitioned forward: the walk runs on the XCD whose L2 holds the ray's
+// current part of the mesh; rays crossing parts are handed over through queues.
+size_t exp_partitioned_workspace(int64_t n, bool hashes);
+hipError_t launch_exp_partitioned(const DevMesh& M, const ExpArgs& a, void* ws, int grid_blocks, int refill_min,
+                                  hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 }  // namespace sg

@@ -16,7 +16,7 @@ from . import build as _build
 SG_OK = 0
 SG_E_ARG, SG_E_NONMANIFOLD, SG_E_DEGENERATE, SG_E_HIP, SG_E_OOM = -1, -2, -3, -4, -5
 RAY_OK, RAY_MAXSTEPS, RAY_BOUNDARY, RAY_BADINPUT = 0, 1, 2, 3
-KERNEL_AUTO, KERNEL_PLAIN, KERNEL_PERSISTENT = 0, 1, 2
+KERNEL_AUTO, KERNEL_PLAIN, KERNEL_PERSISTENT, KERNEL_PARTITIONED = 0, 1, 2, 3
 BWD_EP, BWD_GFD = 0, 1
 
 _lib = None
@@ -109,9 +109,10 @@ class Mesh:
         self.n_verts, self.n_faces = X.shape[0], F.shape[0]
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().sg_mesh_destroy(self._h)
-            self._h = None
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and _lib is not None:
+            _lib.sg_mesh_destroy(h)
 
     __del__ = close
 

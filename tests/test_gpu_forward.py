@@ -48,7 +48,7 @@ def both(torch, X, F, r, **kw):
     return om, gm, o, g
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 def test_config1_parity(torch, kernel):
     X, F = CF.mesh_config(1)
     r = CF.rays_config(1, X, F)
@@ -58,7 +58,7 @@ def test_config1_parity(torch, kernel):
     assert s["hash_mis_far"] == 0
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 @pytest.mark.parametrize("n", [1, 63, 255, 257, 1000, 4097])
 def test_ragged_sizes(torch, n, kernel):
     X, F = CF.mesh_config(1)
@@ -68,7 +68,7 @@ def test_ragged_sizes(torch, n, kernel):
     assert s["bad_not_near"] == 0 and s["face_mis_unexplained"] == 0, s
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 def test_config2_full_batch_sampled(torch, kernel):
     """1,048,576 rays on the 327,680-face displaced icosphere, K = 2, sampled rows vs oracle."""
     X, F = CF.mesh_config(2)
@@ -154,7 +154,7 @@ def test_cube_corner_closed_form(torch, a):
     assert np.abs(g["p"][0] - (c + rr * out)).max() < 1e-5
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 def test_edge_cases(torch, kernel):
     from paper_2603_15780_amd import sg
     X, F = CF.mesh_config(1)
@@ -199,7 +199,7 @@ def test_edge_cases(torch, kernel):
     assert np.abs(g["p"][0] - o["p"][0]).max() < 1e-5
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 def test_boundary_stop(torch, kernel):
     X, F = M.icosphere(3)
     X, F = M.remove_faces(X, F, np.where((F == 0).any(1) | (F == 7).any(1) | (F == 100).any(1))[0])
@@ -242,20 +242,26 @@ def test_deterministic_and_kernels_agree(torch):
     a = run(torch, gm, r, kernel=2)
     b = run(torch, gm, r, kernel=2)
     c = run(torch, gm, r, kernel=1)
+    d = run(torch, gm, r, kernel=3)
+    e = run(torch, gm, r, kernel=3)
     for k in ("f", "b", "p", "v", "W", "status", "n_cross", "hash"):
         assert np.array_equal(a[k], b[k]), k
         assert np.array_equal(a[k], c[k]), k
+        assert np.array_equal(a[k], d[k]), k
+        assert np.array_equal(d[k], e[k]), k
 
 
-@pytest.mark.parametrize("refill_min,walk_blocks", [(1, 0), (64, 0), (16, 3), (8, 1)])
-def test_persistent_schedules(torch, refill_min, walk_blocks):
-    """Every refill threshold and grid size gives the same rays (queue drains fully)."""
+@pytest.mark.parametrize("kernel", [2, 3])
+@pytest.mark.parametrize("refill_min,walk_blocks", [(1, 0), (64, 0), (16, 3), (8, 1), (32, 16)])
+def test_persistent_schedules(torch, kernel, refill_min, walk_blocks):
+    """Every refill threshold and grid size gives the same rays: the queues drain
+    fully, and rays handed between parts (or taken by idle parts) keep their state."""
     from paper_2603_15780_amd import sg
     X, F = CF.mesh_config(1)
     gm = sg.Mesh(X, F)
     r = random_rays(X, F, 5000, np.random.default_rng(9), uniform_len(0.0, 3.0), K=1)
     a = run(torch, gm, r, kernel=1)
-    b = run(torch, gm, r, kernel=2, refill_min=refill_min, walk_blocks=walk_blocks)
+    b = run(torch, gm, r, kernel=kernel, refill_min=refill_min, walk_blocks=walk_blocks)
     for k in ("f", "b", "p", "v", "W", "status", "n_cross", "hash"):
         assert np.array_equal(a[k], b[k]), k
 
@@ -270,6 +276,6 @@ def test_mixed_orientation(torch):
     F2 = F.copy()
     F2[flip] = F2[flip][:, [0, 2, 1]]
     r = random_rays(X, F2, 20000, np.random.default_rng(4), uniform_len(0.0, 2.0), K=2)
-    for kernel in (1, 2):
+    for kernel in (1, 2, 3):
         om, gm, o, g = both(torch, X, F2, r, kernel=kernel)
         assert_parity(o, g, om.mean_edge, K=2, label=f"mixed orientation, kernel {kernel}")
