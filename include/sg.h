@@ -59,10 +59,12 @@ enum {
 
 enum { SG_BWD_EP = 0, SG_BWD_GFD = 1 };
 enum {
-    SG_KERNEL_AUTO = 0,         /* = SG_KERNEL_PARTITIONED */
+    SG_KERNEL_AUTO = 0,         /* = SG_KERNEL_PERSISTENT */
     SG_KERNEL_PLAIN = 1,        /* one ray per lane, run to completion (Alg. gpu_parallel) */
     SG_KERNEL_PERSISTENT = 2,   /* persistent waves refilled from one global ray queue */
-    SG_KERNEL_PARTITIONED = 3   /* persistent waves per XCD, each walking the rays inside its part of the mesh */
+    SG_KERNEL_PARTITIONED = 3   /* persistent waves per XCD, each walking the rays inside its part of the mesh and
+                                   handing rays that leave it to the owning XCD (experimental: correct, but its
+                                   handoff queues are contended and it is far slower than PERSISTENT) */
 };
 
 typedef struct {

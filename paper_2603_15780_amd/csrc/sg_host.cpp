@@ -137,7 +137,7 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     if (!(o.eps_v > 0.f)) o.eps_v = (float)(5e-3 * m->mean_edge);
     if (!(o.eps_p > 0.f)) o.eps_p = (float)(5e-3 * m->mean_edge);
     if (o.kernel < SG_KERNEL_AUTO || o.kernel > SG_KERNEL_PARTITIONED) return fail(SG_E_ARG, "unknown kernel %d", o.kernel);
-    if (o.kernel == SG_KERNEL_AUTO) o.kernel = SG_KERNEL_PARTITIONED;
+    if (o.kernel == SG_KERNEL_AUTO) o.kernel = SG_KERNEL_PERSISTENT;
     if (o.refill_min <= 0) o.refill_min = 16;
     if (o.refill_min > 64) return fail(SG_E_ARG, "refill_min must be at most 64");
     if (o.walk_blocks <= 0)
