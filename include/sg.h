@@ -133,6 +133,33 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
                      const sg_opts* opts, void* stream);
 
 /*
+ * Backward of the exponential map with respect to the query (Sec. 4
+ * "Backpropagation"): given g_p[n,3] = dL/dp' (float32, device) returns
+ *   grad_v[n,3] = dL/dv (tangent to the start face) and
+ *   grad_b[n,3] = dL/db (component k = G . x_k, where G is the in-plane
+ *                 gradient of L with respect to the start point),
+ * for the queries (f, b, v) of an earlier sg_exp call.
+ *   mode SG_BWD_EP  (eq. proxy_func): J^v = R = M_{p'} M_p^T with frames
+ *        [e_par, e_perp, n] at both ends; grad_b = 0.  On meshes whose faces
+ *        agree in orientation it reads the forward's f_out[n] and v_out[n,3]
+ *        and walks nothing; otherwise (those two may be NULL) it re-walks the
+ *        geodesic to find the end normal's orientation.
+ *   mode SG_BWD_GFD (eqs. jv, jp and chain): geodesic finite differences with
+ *        step sizes opts->eps_v, opts->eps_p.  Re-walks seven geodesics per
+ *        query (the base, the e_perp-perturbed one, two short start-point
+ *        steps, then the e_par step from p' and the two start-point-shifted
+ *        geodesics) in two persistent passes; nothing of the forward is read.
+ *        |v_t| = 0 takes e_par = e_u (the start face's x1 - x0 direction).
+ * Queries the forward rejects (SG_RAY_BADINPUT) get NaN gradients.  Uses a
+ * stream-ordered device workspace (224 bytes per query for GFD, 32 for a
+ * re-walked EP).  opts: max_steps, vertex_snap, eps_v, eps_p, refill_min,
+ * walk_blocks are honoured; kernel is ignored (always the persistent walk).
+ */
+int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b, const float* v,
+                    const int32_t* f_out, const float* v_out, const float* g_p,
+                    float* grad_v, float* grad_b, const sg_opts* opts, void* stream);
+
+/*
  * Walk-kernel timing (profiling aid).  Calls made with opts->debug bit 2
  * record a HIP event pair around their walk kernel on the call's stream.
  * This synchronizes those events, returns the summed elapsed milliseconds

@@ -496,6 +496,45 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
     return SG_OK;
 }
 
+int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b, const float* v,
+                    const int32_t* f_out, const float* v_out, const float* g_p, float* grad_v, float* grad_b,
+                    const sg_opts* opts, void* stream) {
+    if (!mesh) return fail(SG_E_ARG, "mesh is NULL");
+    if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
+    if (mode != SG_BWD_EP && mode != SG_BWD_GFD) return fail(SG_E_ARG, "unknown backward mode %d", mode);
+    sg_opts o;
+    int rc = check_opts(opts, o, mesh);
+    if (rc != SG_OK) return rc;
+    if (o.kernel == SG_KERNEL_PARTITIONED) o.walk_blocks = mesh->cu_count * mesh->walk_blocks_per_cu;
+    if (!(std::isfinite(o.eps_v) && std::isfinite(o.eps_p))) return fail(SG_E_ARG, "eps_v and eps_p must be finite");
+    if (n == 0) return SG_OK;
+    if (!f || !b || !v || !g_p || !grad_v || !grad_b) return fail(SG_E_ARG, "a required array is NULL");
+    const bool saved = mode == SG_BWD_EP && !mesh->has_flip;
+    if (saved && (!f_out || !v_out)) return fail(SG_E_ARG, "the extrinsic proxy needs the forward's f_out and v_out");
+    sg::BwdArgs a{};
+    a.n = n;
+    a.mode = mode;
+    a.f = f; a.b = b; a.v = v;
+    a.f_out = f_out; a.v_out = v_out;
+    a.g = g_p;
+    a.grad_v = grad_v; a.grad_b = grad_b;
+    a.eps_v = o.eps_v; a.eps_p = o.eps_p;
+    a.max_steps = o.max_steps;
+    a.snap = o.vertex_snap;
+    const hipStream_t st = (hipStream_t)stream;
+    const size_t wsb = sg::bwd_workspace(n, mode, mesh->has_flip != 0);
+    void* ws = nullptr;
+    if (wsb) {
+        hipError_t e = hipMallocAsync(&ws, wsb, st);
+        if (e != hipSuccess) return fail(SG_E_OOM, "workspace allocation: %s", hipGetErrorString(e));
+    }
+    hipError_t e = sg::launch_backward(mesh->dev(), a, ws, o.walk_blocks, o.refill_min, st);
+    const hipError_t e2 = ws ? hipFreeAsync(ws, st) : hipSuccess;
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    if (e2 != hipSuccess) return hip_fail(e2, "workspace release");
+    return SG_OK;
+}
+
 int sg_exp(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v, int32_t* f_out, float* b_out,
            float* p_out, float* v_out, int32_t* status, int32_t* n_cross, uint64_t* seq_hash, const sg_opts* opts,
            void* stream) {

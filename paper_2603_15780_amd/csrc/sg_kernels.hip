@@ -128,59 +128,59 @@ SG_HD __forceinline__ float3 nrm(float3 a) { return scl(a, 1.0f / sqrtf(dot(a, a
 
 enum InitResult { kInitOk = 0, kInitZero = 1, kInitBad = 2 };
 
-// initialise_trace (Alg. gpu_parallel): project v onto the start face, then
-// extend the ray backwards to the edge it would have entered through, so the
-// walk always starts on an entry edge with remaining length |v_t| + tau.
-SG_HD int ray_init(const DevMesh& M, int32_t fu, const float* bp, const float* vp, Ray& st, float& L) {
-    if (fu < 0 || (int64_t)fu >= M.n_faces) return kInitBad;
-    const int32_t f = M.perm[fu];   // internal face id
-    float b0 = bp[0], b1 = bp[1], b2 = bp[2];
-    if (!(b0 >= 0.f && b1 >= 0.f && b2 >= 0.f)) return kInitBad;
-    const float bs = b0 + b1 + b2;
-    if (!(bs > 0.f) || !__builtin_isfinite(bs)) return kInitBad;
-    const float3 v = ld3(vp);
-    if (!__builtin_isfinite(v.x) || !__builtin_isfinite(v.y) || !__builtin_isfinite(v.z)) return kInitBad;
-    b0 /= bs; b1 /= bs; b2 /= bs;
-    const int64_t f3 = 3 * (int64_t)f;
-    const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
-    const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
-    const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
-    const float3 e1 = sub(x1, x0), e2 = sub(x2, x0);
-    const float l0 = sqrtf(dot(e1, e1));
-    const float3 n = nrm(crs(e1, e2));
-    const float3 ex = scl(e1, 1.0f / l0);
-    const float3 ey = crs(n, ex);
-    const float vx = dot(v, ex), vy = dot(v, ey);
-    L = sqrtf(fmaf(vx, vx, vy * vy));
-    if (!(L > 0.f)) return kInitZero;
-    const HalfEdgeRec r0 = M.rec[f3];
-    const uint32_t phi0 = angle_fx(vx, vy);
-    const float dx = vx / L, dy = vy / L;
-    // barycentric rates of the direction in the chart of edge 0
-    const float icy = 1.0f / r0.cy, il0 = 1.0f / l0;
+// sin and cos of any fixed-point angle (full circle).
+SG_HD __forceinline__ void sincos_full(uint32_t phi, float& sn, float& cs) {
+    const bool upper = phi > kPiFx;
+    sincos_fx(upper ? phi - kPiFx : phi, sn, cs);
+    sn = upper ? -sn : sn;
+    cs = upper ? -cs : cs;
+}
+
+// Rounds an angle in radians (|a| < pi) to fixed point with a split constant.
+SG_HD __forceinline__ uint32_t rad_to_fx(float a) {
+    const float khi = 683565248.0f, klo = 27.576362f;   // 2^32 / (2 pi) as a float pair
+    const float p = a * khi;
+    const float e = fmaf(a, khi, -p) + a * klo;
+    const float pr = rintf(p);
+    return (uint32_t)(int32_t)pr + (uint32_t)(int32_t)rintf((p - pr) + e);
+}
+
+// Starts a walk at a point of face f, given by its barycentrics (bA, bB, bC)
+// in the order of the chart of half-edge h0 = 3 f + k0, moving at fixed-point
+// angle phi0 to that chart's x-axis for length Lhi + Llo.  The ray is extended
+// backwards to the edge it would have entered through, so the walk always
+// starts on an entry edge with remaining length L + tau (initialise_trace).
+// ell0 is the length of the chart's x-axis edge.
+SG_HD int enter_face(const DevMesh& M, int32_t f, int k0, float ell0, float bA, float bB, float bC, uint32_t phi0,
+                     float Lhi, float Llo, Ray& st) {
+    const int32_t h0 = 3 * f + k0;
+    const HalfEdgeRec r0 = rec_at(M, h0);
+    float dy, dx;
+    sincos_full(phi0, dy, dx);
+    // barycentric rates of the direction in the chart
+    const float icy = 1.0f / r0.cy, il0 = 1.0f / ell0;
     const float rc = dy * icy;
     const float rb = fmaf(dx, il0, -dy * r0.cx * icy * il0);
     const float ra = -(rb + rc);
     // a start on a vertex must point into this face's corner there
-    if ((b0 == 0.f) + (b1 == 0.f) + (b2 == 0.f) == 2) {
-        if ((b0 == 0.f && ra < 0.f) || (b1 == 0.f && rb < 0.f) || (b2 == 0.f && rc < 0.f)) return kInitBad;
+    if ((bA == 0.f) + (bB == 0.f) + (bC == 0.f) == 2) {
+        if ((bA == 0.f && ra < 0.f) || (bB == 0.f && rb < 0.f) || (bC == 0.f && rc < 0.f)) return kInitBad;
     }
     // backward exit: the first barycentric that reaches 0 going along -d
     int ie = -1;
     float tau = 0.f;
-    if (ra > 0.f) { tau = b0 / ra; ie = 0; }
-    if (rb > 0.f) { const float ti = b1 / rb; if (ie < 0 || ti < tau) { tau = ti; ie = 1; } }
-    if (rc > 0.f) { const float ti = b2 / rc; if (ie < 0 || ti < tau) { tau = ti; ie = 2; } }
+    if (ra > 0.f) { tau = bA / ra; ie = 0; }
+    if (rb > 0.f) { const float ti = bB / rb; if (ie < 0 || ti < tau) { tau = ti; ie = 1; } }
+    if (rc > 0.f) { const float ti = bC / rc; if (ie < 0 || ti < tau) { tau = ti; ie = 2; } }
     if (ie < 0) return kInitBad;
-    const int k = ie == 2 ? 0 : ie + 1;   // entry edge (F[k], F[k+1]) is opposite vertex ie
-    // barycentrics of the entry point at the two ends of edge k
-    const float bk = k == 0 ? b0 : (k == 1 ? b1 : b2);
+    const int k = ie == 2 ? 0 : ie + 1;   // chart edge (a,b)=0, (b,c)=1, (c,a)=2 opposite vertex ie
+    const float bk = k == 0 ? bA : (k == 1 ? bB : bC);
     const float rk = k == 0 ? ra : (k == 1 ? rb : rc);
-    const float bk1 = k == 0 ? b1 : (k == 1 ? b2 : b0);
+    const float bk1 = k == 0 ? bB : (k == 1 ? bC : bA);
     const float rk1 = k == 0 ? rb : (k == 1 ? rc : ra);
     const float wk = fmaxf(fmaf(-tau, rk, bk), 0.f);
     const float wk1 = fmaxf(fmaf(-tau, rk1, bk1), 0.f);
-    const float ell = k == 0 ? l0 : (k == 1 ? r0.lbc : r0.lac);
+    const float ell = k == 0 ? ell0 : (k == 1 ? r0.lbc : r0.lac);
     const float iw = 1.0f / (wk + wk1);
     st.s = wk1 * iw * ell;
     st.t = wk * iw * ell;
@@ -189,8 +189,8 @@ SG_HD int ray_init(const DevMesh& M, int32_t fu, const float* bp, const float* v
     if (st.s == 0.f || st.t == 0.f) {
         // start on a vertex: the direction must point into this face's corner there
         const uint32_t C0 = kPiFx - r0.A - r0.B;
-        const uint32_t cA = k == 0 ? r0.A : (k == 1 ? r0.B : C0);   // corner at F[k]
-        const uint32_t cB = k == 0 ? r0.B : (k == 1 ? C0 : r0.A);   // corner at F[k+1]
+        const uint32_t cA = k == 0 ? r0.A : (k == 1 ? r0.B : C0);   // corner at the entry edge's start
+        const uint32_t cB = k == 0 ? r0.B : (k == 1 ? C0 : r0.A);   // corner at its end
         if (phi > kPiFx) return kInitBad;
         if (st.s == 0.f && phi > cA) return kInitBad;
         if (st.t == 0.f && phi < kPiFx - cB) return kInitBad;
@@ -199,17 +199,73 @@ SG_HD int ray_init(const DevMesh& M, int32_t fu, const float* bp, const float* v
         phi = phi >= kPiFx + kHalfPiFx ? 0u : kPiFx;
     }
     st.phi = phi;
-    st.h = (int32_t)(f3 + k);
-    // remaining length L + tau as a compensated pair (TwoSum)
-    const float sum = L + tau;
-    const float bv = sum - L;
+    st.h = 3 * f + (k0 + k) % 3;
+    // remaining length (Lhi + tau) + Llo, compensated (TwoSum)
+    const float sum = Lhi + tau;
+    const float bv = sum - Lhi;
     st.Lhi = sum;
-    st.Llo = (L - (sum - bv)) + (tau - bv);
+    st.Llo = ((Lhi - (sum - bv)) + (tau - bv)) + Llo;
     st.par = 0u;
     st.bias = st.s == 0.f ? kForceBC : (st.t == 0.f ? kForceCA : 0.f);
     st.ncross = 0;
-    st.hash = fnv_face(14695981039346656037ull, (uint32_t)fu);
+    st.hash = fnv_face(14695981039346656037ull, (uint32_t)M.order[f]);
     return kInitOk;
+}
+
+// Start-face frame of a query: chart of half-edge 3 f (x-axis along x1 - x0).
+struct StartFrame {
+    int32_t f;              // internal face id
+    float b0, b1, b2;       // normalised barycentrics
+    float l0;               // |x1 - x0|
+    float3 x0, ex, ey, n;   // origin and chart frame in 3D
+};
+
+SG_HD __forceinline__ int start_frame(const DevMesh& M, int32_t fu, const float* bp, StartFrame& S) {
+    if (fu < 0 || (int64_t)fu >= M.n_faces) return kInitBad;
+    S.f = M.perm[fu];
+    float b0 = bp[0], b1 = bp[1], b2 = bp[2];
+    if (!(b0 >= 0.f && b1 >= 0.f && b2 >= 0.f)) return kInitBad;
+    const float bs = b0 + b1 + b2;
+    if (!(bs > 0.f) || !__builtin_isfinite(bs)) return kInitBad;
+    S.b0 = b0 / bs; S.b1 = b1 / bs; S.b2 = b2 / bs;
+    const int64_t f3 = 3 * (int64_t)S.f;
+    S.x0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
+    const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
+    const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+    const float3 e1 = sub(x1, S.x0), e2 = sub(x2, S.x0);
+    S.l0 = sqrtf(dot(e1, e1));
+    S.n = nrm(crs(e1, e2));
+    S.ex = scl(e1, 1.0f / S.l0);
+    S.ey = crs(S.n, S.ex);
+    return kInitOk;
+}
+
+// initialise_trace (Alg. gpu_parallel): v is projected onto the start face;
+// its angle to the chart's x-axis and its length start the walk.
+SG_HD int ray_init(const DevMesh& M, int32_t fu, const float* bp, const float* vp, Ray& st, float& L) {
+    StartFrame S;
+    if (start_frame(M, fu, bp, S) != kInitOk) return kInitBad;
+    const float3 v = ld3(vp);
+    if (!__builtin_isfinite(v.x) || !__builtin_isfinite(v.y) || !__builtin_isfinite(v.z)) return kInitBad;
+    const float vx = dot(v, S.ex), vy = dot(v, S.ey);
+    L = sqrtf(fmaf(vx, vx, vy * vy));
+    if (!(L > 0.f)) return kInitZero;
+    return enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, angle_fx(vx, vy), L, 0.f, st);
+}
+
+// Starts a walk at chart point (ex, ey) of half-edge h (an end point of an
+// earlier walk), direction phi to that chart's x-axis, length Lhi + Llo.
+SG_HD int enter_chart(const DevMesh& M, int32_t h, float ex, float ey, uint32_t phi, float Lhi, float Llo, Ray& st) {
+    const int32_t f = h / 3;
+    const int k0 = h - 3 * f;
+    const HalfEdgeRec r = rec_at(M, h);
+    const float ell = rec_at(M, 3 * f + (k0 + 1) % 3).lac;   // |ab| of this chart
+    float bc = ey / r.cy;
+    float bb = (ex - bc * r.cx) / ell;
+    float ba = 1.0f - bb - bc;
+    ba = fmaxf(ba, 0.f); bb = fmaxf(bb, 0.f); bc = fmaxf(bc, 0.f);
+    const float is = 1.0f / (ba + bb + bc);
+    return enter_face(M, f, k0, ell, ba * is, bb * is, bc * is, phi, Lhi, Llo, st);
 }
 
 enum VertexResult { kVertexDone = 0, kVertexNoSnap = 1, kVertexBoundary = 2 };
@@ -936,6 +992,280 @@ __global__ __launch_bounds__(256) void k_finish(DevMesh M, ExpArgs a, const Stat
     write_final(M, a, i, fin, tangent_length(M, a, i));
 }
 
+
+// ---------------------------------------------------------------- backward
+// Point of a finished walk as an offset from `o` (a vertex near it): the
+// finite differences of the geodesic scheme subtract nearby points, so they
+// are formed from small local vectors rather than from rounded 3D positions.
+SG_HD __forceinline__ float3 final_offset(const DevMesh& M, const Final& fin, float3 o, int32_t& fe_out) {
+    const int32_t fe = fin.h / 3;
+    const int ke = fin.h - 3 * fe;
+    const HalfEdgeRec r = rec_at(M, fin.h);
+    const int64_t f3 = 3 * (int64_t)fe;
+    const float3 y0 = sub(ld3(M.X + 3 * (int64_t)M.F[f3]), o);
+    const float3 y1 = sub(ld3(M.X + 3 * (int64_t)M.F[f3 + 1]), o);
+    const float3 y2 = sub(ld3(M.X + 3 * (int64_t)M.F[f3 + 2]), o);
+    const float ell = rec_at(M, 3 * fe + (ke + 1) % 3).lac;
+    float b0, b1, b2;
+    chart_bary(r, ell, fin.ex, fin.ey, ke, b0, b1, b2);
+    fe_out = fe;
+    return make_float3(fmaf(b0, y0.x, fmaf(b1, y1.x, b2 * y2.x)), fmaf(b0, y0.y, fmaf(b1, y1.y, b2 * y2.y)),
+                       fmaf(b0, y0.z, fmaf(b1, y1.z, b2 * y2.z)));
+}
+
+// Tangent and orientation-consistent normal at the end of a walk.
+SG_HD __forceinline__ void final_frame(const DevMesh& M, const Final& fin, float3& d3, float3& n3) {
+    const int32_t fe = fin.h / 3;
+    const int ke = fin.h - 3 * fe;
+    const int64_t f3 = 3 * (int64_t)fe;
+    const float3 ya = ld3(M.X + 3 * (int64_t)M.F[f3 + ke]);
+    const float3 yb = ld3(M.X + 3 * (int64_t)M.F[f3 + (ke + 1) % 3]);
+    const float3 yc = ld3(M.X + 3 * (int64_t)M.F[f3 + (ke + 2) % 3]);
+    const float3 eab = sub(yb, ya);
+    const float3 ex3 = nrm(eab);
+    n3 = nrm(crs(eab, sub(yc, ya)));
+    const float3 ey3 = crs(n3, ex3);
+    float sn, cs;
+    sincos_fx(fin.phi, sn, cs);
+    d3 = make_float3(fmaf(cs, ex3.x, sn * ey3.x), fmaf(cs, ex3.y, sn * ey3.y), fmaf(cs, ex3.z, sn * ey3.z));
+    if (fin.flags & kParity) n3 = scl(n3, -1.0f);
+}
+
+SG_HD __forceinline__ Final as_final(const StateRec& r) { return *reinterpret_cast<const Final*>(&r); }
+
+SG_HD __forceinline__ StateRec dead_state() {
+    StateRec r;
+    r.h = -1; r.s = r.t = r.Lhi = r.Llo = 0.f; r.phi = r.flags = 0u; r.ncross = 0;
+    return r;
+}
+
+// The query's start frame, direction angle phi0 (chart of half-edge 3 f) and
+// length; |v_t| = 0 takes the chart's x-axis (e_u) as its direction.
+SG_HD __forceinline__ int bwd_query(const DevMesh& M, const BwdArgs& a, int64_t i, StartFrame& S, uint32_t& phi0,
+                                    float& L) {
+    if (start_frame(M, a.f[i], a.b + 3 * i, S) != kInitOk) return kInitBad;
+    const float3 v = ld3(a.v + 3 * i);
+    if (!__builtin_isfinite(v.x) || !__builtin_isfinite(v.y) || !__builtin_isfinite(v.z)) return kInitBad;
+    const float vx = dot(v, S.ex), vy = dot(v, S.ey);
+    L = sqrtf(fmaf(vx, vx, vy * vy));
+    phi0 = L > 0.f ? angle_fx(vx, vy) : 0u;
+    return kInitOk;
+}
+
+SG_HD __forceinline__ void nan_grads(const BwdArgs& a, int64_t i) {
+    const float nan = __builtin_nanf("");
+    for (int c = 0; c < 3; ++c) { a.grad_v[3 * i + c] = nan; a.grad_b[3 * i + c] = nan; }
+}
+
+// Stage 1: the walks that start at p.  Slot 0 recomputes Exp(p, v); for the
+// geodesic finite differences (eqs. jv, jp) slot 1 is Exp(p, v + eps_v e_perp),
+// slots 2 and 3 are the short walks Exp(p, eps_p e_u), Exp(p, eps_p e_v).  The
+// perturbations are applied to the fixed-point angle and the compensated
+// length, so the perturbed walks share the base walk's rounding.
+SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_ray, int64_t i) {
+    StateRec* out = s1 + (int64_t)per_ray * i;
+    StartFrame S;
+    uint32_t phi0;
+    float L;
+    Ray st;
+    if (bwd_query(M, a, i, S, phi0, L) != kInitOk) {
+        for (int j = 0; j < per_ray; ++j) out[j] = dead_state();
+        return;
+    }
+    out[0] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+    if (per_ray == 1) return;
+    const float ev = a.eps_v, ep = a.eps_p;
+    // |v + eps e_perp| = L + eps^2 / (L + sqrt(L^2 + eps^2)), angle + atan(eps / L)
+    const float Lp = sqrtf(fmaf(L, L, ev * ev));
+    const float dl = ev * ev / (L + Lp);
+    const uint32_t dphi = rad_to_fx(atan2f(ev, L));
+    out[1] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0 + dphi, L, dl, st) == kInitOk ? pack_state(st)
+                                                                                                 : dead_state();
+    out[2] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, 0u, ep, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+    const uint32_t Av = rec_at(M, 3 * S.f).A;   // angle of e_v = unit(x2 - x0) in the chart
+    out[3] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, Av, ep, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+}
+
+// Stage 2: the walks that start where stage 1 ended.  Slot 0 is the short
+// walk Exp(p', Pi(eps_v e_par)) along the transported tangent; slots 1 and 2
+// are Exp(p_u, v_u), Exp(p_v, v_v) with v transported along the short walks
+// (it keeps its angle to their tangent).
+SG_HD void bwd_stage2(const DevMesh& M, const BwdArgs& a, const StateRec* s1, StateRec* s2, int64_t i) {
+    StateRec* out = s2 + 3 * i;
+    StartFrame S;
+    uint32_t phi0;
+    float L;
+    Ray st;
+    const Final F0 = as_final(s1[4 * i]), Fu = as_final(s1[4 * i + 2]), Fv = as_final(s1[4 * i + 3]);
+    if (bwd_query(M, a, i, S, phi0, L) != kInitOk || F0.h < 0 || Fu.h < 0 || Fv.h < 0) {
+        out[0] = out[1] = out[2] = dead_state();
+        return;
+    }
+    out[0] = enter_chart(M, F0.h, F0.ex, F0.ey, F0.phi, a.eps_v, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+    const uint32_t psi_u = phi0;                              // v relative to e_u
+    const uint32_t psi_v = phi0 - rec_at(M, 3 * S.f).A;       // v relative to e_v
+    const uint32_t du = (Fu.flags & kParity) ? Fu.phi - psi_u : Fu.phi + psi_u;
+    const uint32_t dv = (Fv.flags & kParity) ? Fv.phi - psi_v : Fv.phi + psi_v;
+    out[1] = enter_chart(M, Fu.h, Fu.ex, Fu.ey, du, L, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+    out[2] = enter_chart(M, Fv.h, Fv.ex, Fv.ey, dv, L, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+}
+
+// Projection of an ambient vector onto the non-orthogonal frame [e_u, e_v]
+// of face f (M^dagger = (M^T M)^-1 M^T, Sec. 4 "Differentiation via GFD").
+SG_HD __forceinline__ float2 pinv_uv(float3 eu, float3 ev, float3 w) {
+    const float a = dot(eu, eu), b = dot(eu, ev), d = dot(ev, ev);
+    const float r1 = dot(eu, w), r2 = dot(ev, w);
+    const float idet = 1.0f / fmaf(a, d, -b * b);
+    return make_float2(fmaf(d, r1, -b * r2) * idet, fmaf(a, r2, -b * r1) * idet);
+}
+
+SG_HD __forceinline__ void face_uv(const DevMesh& M, int32_t f, float3& x0, float3& eu, float3& ev) {
+    const int64_t f3 = 3 * (int64_t)f;
+    x0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
+    eu = nrm(sub(ld3(M.X + 3 * (int64_t)M.F[f3 + 1]), x0));
+    ev = nrm(sub(ld3(M.X + 3 * (int64_t)M.F[f3 + 2]), x0));
+}
+
+// Assembly (eqs. jv, jp, chain): finite-difference columns, projected on the
+// end face's [e_u', e_v'] frame, contracted with the upstream gradient g.
+SG_HD void gfd_assemble(const DevMesh& M, const BwdArgs& a, const StateRec* s1, const StateRec* s2, int64_t i) {
+    StartFrame S;
+    uint32_t phi0;
+    float L;
+    const Final F0 = as_final(s1[4 * i]), Fp = as_final(s1[4 * i + 1]);
+    const Final Fq = as_final(s2[3 * i]), Fu = as_final(s2[3 * i + 1]), Fv = as_final(s2[3 * i + 2]);
+    if (bwd_query(M, a, i, S, phi0, L) != kInitOk || F0.h < 0 || Fp.h < 0 || Fq.h < 0 || Fu.h < 0 || Fv.h < 0) {
+        nan_grads(a, i);
+        return;
+    }
+    float3 o, eu2, ev2;
+    face_uv(M, F0.h / 3, o, eu2, ev2);
+    int32_t ft;
+    const float3 q0 = final_offset(M, F0, o, ft);
+    const float iv = 1.0f / a.eps_v, ip = 1.0f / a.eps_p;
+    const float3 cpar = scl(sub(final_offset(M, Fq, o, ft), q0), iv);
+    const float3 cperp = scl(sub(final_offset(M, Fp, o, ft), q0), iv);
+    const float3 cu = scl(sub(final_offset(M, Fu, o, ft), q0), ip);
+    const float3 cv = scl(sub(final_offset(M, Fv, o, ft), q0), ip);
+    const float2 j0 = pinv_uv(eu2, ev2, cpar), j1 = pinv_uv(eu2, ev2, cperp);   // J^v columns
+    const float2 k0 = pinv_uv(eu2, ev2, cu), k1 = pinv_uv(eu2, ev2, cv);         // J^p columns
+    const float3 g = ld3(a.g + 3 * i);
+    const float h0 = dot(eu2, g), h1 = dot(ev2, g);
+    // J^T (M'^T g)
+    const float c0 = fmaf(j0.x, h0, j0.y * h1), c1 = fmaf(j1.x, h0, j1.y * h1);
+    const float d0 = fmaf(k0.x, h0, k0.y * h1), d1 = fmaf(k1.x, h0, k1.y * h1);
+    float sn, cs;
+    sincos_full(phi0, sn, cs);
+    const float3 epar = make_float3(fmaf(cs, S.ex.x, sn * S.ey.x), fmaf(cs, S.ex.y, sn * S.ey.y),
+                                    fmaf(cs, S.ex.z, sn * S.ey.z));
+    const float3 eperp = crs(S.n, epar);
+    for (int c = 0; c < 3; ++c) {
+        const float ep_c = c == 0 ? epar.x : (c == 1 ? epar.y : epar.z);
+        const float eq_c = c == 0 ? eperp.x : (c == 1 ? eperp.y : eperp.z);
+        a.grad_v[3 * i + c] = fmaf(c0, ep_c, c1 * eq_c);
+    }
+    // start-point gradient G in the face plane with [e_u e_v]^T G = (d0, d1)
+    const float3 su = S.ex;
+    const int64_t f3 = 3 * (int64_t)S.f;
+    const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
+    const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+    const float3 sv = nrm(sub(x2, S.x0));
+    const float ga = dot(su, su), gb = dot(su, sv), gd = dot(sv, sv);
+    const float idet = 1.0f / fmaf(ga, gd, -gb * gb);
+    const float y0 = fmaf(gd, d0, -gb * d1) * idet, y1 = fmaf(ga, d1, -gb * d0) * idet;
+    const float3 G = make_float3(fmaf(y0, su.x, y1 * sv.x), fmaf(y0, su.y, y1 * sv.y), fmaf(y0, su.z, y1 * sv.z));
+    a.grad_b[3 * i] = dot(G, S.x0);
+    a.grad_b[3 * i + 1] = dot(G, x1);
+    a.grad_b[3 * i + 2] = dot(G, x2);
+}
+
+// Extrinsic proxy (eq. proxy_func): J^v = R = M_{p'} M_p^T with frames
+// [e_par, e_perp, n], J^p = 0.  grad_v = R^T g = M_p (M_{p'}^T g).
+SG_HD __forceinline__ void ep_grad(const BwdArgs& a, int64_t i, const StartFrame& S, uint32_t phi0, float3 d3, float3 n3) {
+    const float3 g = ld3(a.g + 3 * i);
+    float sn, cs;
+    sincos_full(phi0, sn, cs);
+    const float3 epar = make_float3(fmaf(cs, S.ex.x, sn * S.ey.x), fmaf(cs, S.ex.y, sn * S.ey.y),
+                                    fmaf(cs, S.ex.z, sn * S.ey.z));
+    const float3 eperp = crs(S.n, epar);
+    const float3 q = crs(n3, d3);
+    const float a0 = dot(d3, g), a1 = dot(q, g), a2 = dot(n3, g);
+    a.grad_v[3 * i] = fmaf(a0, epar.x, fmaf(a1, eperp.x, a2 * S.n.x));
+    a.grad_v[3 * i + 1] = fmaf(a0, epar.y, fmaf(a1, eperp.y, a2 * S.n.y));
+    a.grad_v[3 * i + 2] = fmaf(a0, epar.z, fmaf(a1, eperp.z, a2 * S.n.z));
+    a.grad_b[3 * i] = a.grad_b[3 * i + 1] = a.grad_b[3 * i + 2] = 0.f;
+}
+
+// EP from the saved forward outputs (orientable meshes: the end normal is the
+// end face's own normal).
+SG_HD void ep_saved(const DevMesh& M, const BwdArgs& a, int64_t i) {
+    StartFrame S;
+    uint32_t phi0;
+    float L;
+    const int32_t fo = a.f_out[i];
+    if (bwd_query(M, a, i, S, phi0, L) != kInitOk || fo < 0 || (int64_t)fo >= M.n_faces) {
+        nan_grads(a, i);
+        return;
+    }
+    const float3 vo = ld3(a.v_out + 3 * i);
+    const float lo = sqrtf(dot(vo, vo));
+    if (!(L > 0.f) || !(lo > 0.f)) {   // |v| = 0: R = I
+        for (int c = 0; c < 3; ++c) { a.grad_v[3 * i + c] = a.g[3 * i + c]; a.grad_b[3 * i + c] = 0.f; }
+        return;
+    }
+    const int64_t f3 = 3 * (int64_t)M.perm[fo];
+    const float3 y0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
+    const float3 y1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
+    const float3 y2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+    ep_grad(a, i, S, phi0, scl(vo, 1.0f / lo), nrm(crs(sub(y1, y0), sub(y2, y0))));
+}
+
+// EP from a recomputed walk (meshes whose faces disagree in orientation: the
+// end normal's sign comes from the walk's orientation parity).
+SG_HD void ep_walked(const DevMesh& M, const BwdArgs& a, const StateRec* s1, int64_t i) {
+    StartFrame S;
+    uint32_t phi0;
+    float L;
+    const Final F0 = as_final(s1[i]);
+    if (bwd_query(M, a, i, S, phi0, L) != kInitOk || F0.h < 0) {
+        nan_grads(a, i);
+        return;
+    }
+    if (!(L > 0.f)) {
+        for (int c = 0; c < 3; ++c) { a.grad_v[3 * i + c] = a.g[3 * i + c]; a.grad_b[3 * i + c] = 0.f; }
+        return;
+    }
+    float3 d3, n3;
+    final_frame(M, F0, d3, n3);
+    ep_grad(a, i, S, phi0, d3, n3);
+}
+
+// Walks one chart state to its end in place (sequential form of k_walk).
+template <bool kFlip>
+SG_HD void walk_state(const DevMesh& M, StateRec& r, int32_t max_steps, float snap) {
+    if (r.h < 0) return;
+    Ray st;
+    unpack_state(r, st);
+    st.hash = 0ull;
+    Final fin;
+    walk_to_end<false, kFlip>(M, st, max_steps, snap, fin);
+    r = *reinterpret_cast<const StateRec*>(&fin);
+}
+
+#define SG_ROW_KERNEL(name, body, ...)                                                   \
+    __global__ __launch_bounds__(256) void name(DevMesh M, BwdArgs a, ##__VA_ARGS__) {   \
+        const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;                \
+        if (i < a.n) body;                                                               \
+    }
+SG_ROW_KERNEL(k_bwd_stage1, bwd_stage1(M, a, s1, per_ray, i), StateRec* s1, int per_ray)
+SG_ROW_KERNEL(k_bwd_stage2, bwd_stage2(M, a, s1, s2, i), const StateRec* s1, StateRec* s2)
+SG_ROW_KERNEL(k_gfd_assemble, gfd_assemble(M, a, s1, s2, i), const StateRec* s1, const StateRec* s2)
+SG_ROW_KERNEL(k_ep_saved, ep_saved(M, a, i))
+SG_ROW_KERNEL(k_ep_walked, ep_walked(M, a, s1, i), const StateRec* s1)
+#undef SG_ROW_KERNEL
+
+__global__ __launch_bounds__(64) void k_reset_counter(unsigned long long* c) { *c = 0ull; }
+
 }  // namespace
 
 // Launches the kernel instance for the (hash, orientation-flip) combination in use.
@@ -1012,6 +1342,41 @@ hipError_t launch_exp_partitioned(const DevMesh& M, const ExpArgs& a, void* ws, 
                 migq, qc, cap, a.max_steps, a.snap, refill_min, idle_limit);
     if (ev1) (void)hipEventRecord(ev1, s);
     hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)hashes);
+    return hipGetLastError();
+}
+
+size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip) {
+    if (mode == 0 && !has_flip) return 0;
+    const size_t per = mode == 0 ? 1 : 7;
+    return (size_t)n * per * sizeof(StateRec) + 512;
+}
+
+hipError_t launch_backward(const DevMesh& M, const BwdArgs& a, void* ws, int grid_blocks, int refill_min,
+                           hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    const int block = 256;
+    const int64_t grid = (a.n + block - 1) / block;
+    if (a.mode == 0 && !M.has_flip) {
+        hipLaunchKernelGGL(k_ep_saved, dim3((unsigned)grid), dim3(block), 0, s, M, a);
+        return hipGetLastError();
+    }
+    const int per1 = a.mode == 0 ? 1 : 4;
+    auto* s1 = reinterpret_cast<StateRec*>(ws);
+    auto* s2 = s1 + (int64_t)per1 * a.n;
+    auto* counter = reinterpret_cast<unsigned long long*>(s2 + (a.mode == 0 ? 0 : 3 * a.n));
+    hipLaunchKernelGGL(k_bwd_stage1, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
+    SG_DISPATCH(k_walk, false, M.has_flip != 0, dim3((unsigned)grid_blocks), dim3(block), s, M, s1,
+                (int64_t)per1 * a.n, counter, a.max_steps, a.snap, refill_min);
+    if (a.mode == 0) {
+        hipLaunchKernelGGL(k_ep_walked, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_bwd_stage2, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
+    SG_DISPATCH(k_walk, false, M.has_flip != 0, dim3((unsigned)grid_blocks), dim3(block), s, M, s2, 3 * a.n,
+                counter, a.max_steps, a.snap, refill_min);
+    hipLaunchKernelGGL(k_gfd_assemble, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
     return hipGetLastError();
 }
 

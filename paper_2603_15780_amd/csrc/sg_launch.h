@@ -29,6 +29,22 @@ struct ExpArgs {
     uint32_t debug;
 };
 
+struct BwdArgs {
+    int64_t n;
+    int32_t mode;           // 0 extrinsic proxy, 1 geodesic finite differences
+    const int32_t* f;
+    const float* b;
+    const float* v;
+    const int32_t* f_out;   // saved forward outputs (extrinsic proxy)
+    const float* v_out;
+    const float* g;         // dL/dp'
+    float* grad_v;
+    float* grad_b;
+    float eps_v, eps_p;
+    int32_t max_steps;
+    float snap;
+};
+
 // Host-side result of packing a mesh (float64 work, rounded once).
 struct PackedMesh {
     std::vector<HalfEdgeRec> rec;
@@ -58,6 +74,11 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, i
                                  hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 int walk_blocks_per_cu();
 int part_blocks_per_cu();
+
+// Backward of the exponential map (extrinsic proxy or geodesic finite differences).
+size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip);
+hipError_t launch_backward(const DevMesh& M, const BwdArgs& a, void* ws, int grid_blocks, int refill_min,
+                           hipStream_t s);
 
 // Partitioned forward: the walk runs on the XCD whose L2 holds the ray's
 // current part of the mesh; rays crossing parts are handed over through queues.

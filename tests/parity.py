@@ -69,3 +69,33 @@ def assert_parity(o, g, me, K=0, label=""):
         assert s["W_angle_max"] <= 1e-4, msg
     assert s["v_angle_max"] <= 1e-4, msg
     return s
+
+
+def grad_report(o_exp, og_v, og_b, gg_v, gg_b, me, margin=2e-2, tol=1e-3):
+    """Backward parity: relative errors of grad_v (norm) and of the barycentric
+    gradient differences (grad_b[1] - grad_b[0], grad_b[2] - grad_b[0]), which
+    carry the in-plane start-point gradient (grad_b[k] = G . x_k; its common
+    part G . x_0 is ill-conditioned against |G| |x| on curved meshes and is
+    checked against that scale).  `margin` rays keep at least margin * mean edge
+    from every vertex along the oracle's base walk: finite differences of
+    geodesics that pass a vertex closer than their step are not smooth.
+    """
+    def d(x):
+        return np.stack([x[:, 1] - x[:, 0], x[:, 2] - x[:, 0]], 1)
+
+    def rel(a, b):
+        den = np.linalg.norm(b, axis=1)
+        return np.linalg.norm(a - b, axis=-1 if a.ndim == 2 else (1, 2)) / np.maximum(den, 1e-30)
+
+    ev = rel(gg_v, og_v)
+    zb = np.linalg.norm(og_b, axis=1) == 0
+    eb = np.where(zb, np.linalg.norm(gg_b, axis=1), 0.0)
+    nz = ~zb
+    if nz.any():
+        eb[nz] = np.linalg.norm(d(gg_b[nz]) - d(og_b[nz]), axis=1) / np.maximum(
+            np.linalg.norm(d(og_b[nz]), axis=1), 1e-30)
+    m = o_exp["min_vdist"] > margin * me
+    return dict(n=len(ev), n_margin=int(m.sum()), v_ok=float(np.mean(ev[m] <= tol)) if m.any() else 1.0,
+                b_ok=float(np.mean(eb[m] <= tol)) if m.any() else 1.0, v_med=float(np.median(ev)),
+                b_med=float(np.median(eb)), v_all_ok=float(np.mean(ev <= tol)), finite=bool(
+                    np.isfinite(gg_v).all() and np.isfinite(gg_b).all()))

@@ -1,0 +1,177 @@
+"""GPU parity of the backward (sg_exp_backward) against the oracle.
+
+Extrinsic proxy (eq. proxy_func) and geodesic finite differences (eqs. jv,
+jp, chain) through the C ABI on cuda:0, compared with the float64 oracle at
+the same step sizes.  Gradients are compared on rays that keep a margin from
+every vertex (finite differences of geodesics are not smooth across a vertex);
+the bar is a relative error of 1e-3.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from parity import grad_report
+from workloads import configs as CF
+from workloads import meshes as M
+from workloads.rays import random_rays, uniform_len
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU test needs a HIP device"
+    return T
+
+
+def dev_inputs(torch, r, g):
+    dev = torch.device("cuda:0")
+    t = dict(f=torch.from_numpy(np.ascontiguousarray(r["f"], np.int32)).to(dev),
+             b=torch.from_numpy(np.ascontiguousarray(r["b"], np.float32)).to(dev),
+             v=torch.from_numpy(np.ascontiguousarray(r["v"], np.float32)).to(dev),
+             g=torch.from_numpy(np.ascontiguousarray(g, np.float32)).to(dev))
+    return t
+
+
+def gpu_bwd(torch, gm, mode, r, g, **kw):
+    from paper_2603_15780_amd import sg
+    t = dev_inputs(torch, r, g)
+    fo = vo = None
+    if mode == sg.BWD_EP:
+        out = gm.exp(t["f"], t["b"], t["v"], **{k: v for k, v in kw.items() if k in ("max_steps",)})
+        fo, vo = out["f"], out["v"]
+    gv, gb = gm.backward(mode, t["f"], t["b"], t["v"], t["g"], f_out=fo, v_out=vo, **kw)
+    torch.cuda.synchronize()
+    return gv.cpu().numpy(), gb.cpu().numpy()
+
+
+def check(torch, X, F, r, g, mode, rows=None, min_margin_rays=100, **kw):
+    from paper_2603_15780_amd import sg
+    om = oracle.Mesh(X, F)
+    gm = sg.Mesh(X, F)
+    eps = np.float32(5e-3 * om.mean_edge)
+    gv, gb = gpu_bwd(torch, gm, mode, r, g, eps_v=float(eps), eps_p=float(eps), **kw)
+    sel = slice(None) if rows is None else rows
+    rf, rb, rv, gs = r["f"][sel], r["b"][sel], r["v"][sel], g[sel]
+    o = om.exp(rf, rb, rv)
+    if mode == sg.BWD_EP:
+        ogv, ogb = om.ep(rf, rb, rv, gs)
+    else:
+        od = om.gfd(rf, rb, rv, gs, float(eps), float(eps))
+        ogv, ogb = od["grad_v"], od["grad_b"]
+    s = grad_report(o, ogv, ogb, gv[sel], gb[sel], om.mean_edge)
+    print(s)
+    assert s["finite"], s
+    assert s["n_margin"] >= min_margin_rays, s
+    assert s["v_ok"] >= 0.999 and s["b_ok"] >= 0.999, s
+    return s, gv, gb
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_config1(torch, mode):
+    X, F = CF.mesh_config(1)
+    r = CF.rays_config(1, X, F)
+    g = CF.upstream_grad(1, r["f"].shape[0])
+    s, _, gb = check(torch, X, F, r, g, mode)
+    if mode == 0:
+        assert s["v_all_ok"] >= 0.99 and np.all(gb == 0)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("n", [1, 255, 257, 4097])
+def test_ragged(torch, mode, n):
+    X, F = CF.mesh_config(1)
+    rng = np.random.default_rng(100 + n)
+    r = random_rays(X, F, n, rng, uniform_len(0.0, 1.0))
+    g = rng.standard_normal((n, 3)).astype(np.float32)
+    check(torch, X, F, r, g, mode, min_margin_rays=min(n, 100) // 2)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_config2_full_batch_sampled(torch, mode):
+    """Backward over all 1,048,576 rays on the 327,680-face mesh; 4,096 sampled rows vs the oracle."""
+    X, F = CF.mesh_config(2)
+    r = CF.rays_config(2, X, F)
+    g = CF.upstream_grad(2, r["f"].shape[0])
+    rows = np.arange(0, r["f"].shape[0], 256)
+    check(torch, X, F, r, g, mode, rows=rows)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_torus_and_mixed_orientation(torch, mode):
+    rng = np.random.default_rng(3)
+    X, F = M.torus_grid(40, 20, 0.2, rng)
+    r = random_rays(X, F, 4096, rng, uniform_len(0.0, 1.5))
+    g = rng.standard_normal((4096, 3)).astype(np.float32)
+    check(torch, X, F, r, g, mode)
+    # faces with disagreeing orientation: the extrinsic proxy re-walks the geodesic
+    X, F = CF.mesh_config(1)
+    F2 = F.copy()
+    flip = np.random.default_rng(5).random(F.shape[0]) < 0.3
+    F2[flip] = F2[flip][:, ::-1]
+    r = random_rays(X, F2, 4096, rng, uniform_len(0.0, 1.5))
+    check(torch, X, F2, r, g, mode)
+
+
+def test_zero_length_and_short(torch):
+    """|v| = 0: the extrinsic proxy is the identity; GFD differentiates Exp at 0 (projection)."""
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    rng = np.random.default_rng(9)
+    r = random_rays(X, F, 2048, rng, uniform_len(0.0, 0.0))
+    g = rng.standard_normal((2048, 3)).astype(np.float32)
+    gm = sg.Mesh(X, F)
+    gv, gb = gpu_bwd(torch, gm, sg.BWD_EP, r, g)
+    assert np.array_equal(gv, g) and np.all(gb == 0)
+    s, gv, gb = check(torch, X, F, r, g, sg.BWD_GFD)
+    # Exp_p(w) = p + w for small in-face w: grad_v is g projected on the start face
+    om = oracle.Mesh(X, F)
+    N = np.cross(X[F[r["f"], 1]] - X[F[r["f"], 0]], X[F[r["f"], 2]] - X[F[r["f"], 0]])
+    N /= np.linalg.norm(N, axis=1, keepdims=True)
+    proj = g - (g * N).sum(1, keepdims=True) * N
+    far = r["b"].min(1) > 0.05
+    err = np.linalg.norm(gv - proj, axis=1) / np.linalg.norm(proj, axis=1)
+    assert np.quantile(err[far], 0.999) < 1e-3
+    r = random_rays(X, F, 2048, rng, uniform_len(0.0, 0.02 * om.mean_edge))
+    for mode in (0, 1):
+        check(torch, X, F, r, g, mode)
+
+
+def test_edge_cases(torch):
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    gm = sg.Mesh(X, F)
+    dev = torch.device("cuda:0")
+    e = torch.empty(0, dtype=torch.int32, device=dev)
+    e3 = torch.empty(0, 3, device=dev)
+    for mode in (0, 1):
+        gv, gb = gm.backward(mode, e, e3, e3, e3, f_out=e, v_out=e3)
+        assert gv.shape == (0, 3)
+    f = torch.tensor([0, -1, F.shape[0], 1], dtype=torch.int32, device=dev)
+    b = torch.tensor([[1, 1, 1], [1, 1, 1], [1, 1, 1], [float("nan"), 1, 1]], dtype=torch.float32, device=dev)
+    v = torch.full((4, 3), 0.1, device=dev)
+    g = torch.ones(4, 3, device=dev)
+    for mode in (0, 1):
+        out = gm.exp(f, b, v)
+        gv, gb = gm.backward(mode, f, b, v, g, f_out=out["f"], v_out=out["v"])
+        torch.cuda.synchronize()
+        gv = gv.cpu().numpy()
+        assert np.isfinite(gv[0]).all() and np.isnan(gv[1:]).all()
+    with pytest.raises(sg.SgError):
+        gm.backward(7, f, b, v, g)
+    with pytest.raises(sg.SgError):   # the saved-output extrinsic proxy needs the forward's outputs
+        gm.backward(0, f, b, v, g)
+
+
+def test_deterministic_and_schedules(torch):
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    rng = np.random.default_rng(11)
+    r = random_rays(X, F, 20000, rng, uniform_len(0.0, 1.5))
+    g = rng.standard_normal((20000, 3)).astype(np.float32)
+    gm = sg.Mesh(X, F)
+    ref = gpu_bwd(torch, gm, sg.BWD_GFD, r, g)
+    for kw in ({}, dict(refill_min=1), dict(refill_min=64), dict(walk_blocks=7), dict(walk_blocks=3000, refill_min=32)):
+        out = gpu_bwd(torch, gm, sg.BWD_GFD, r, g, **kw)
+        assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), kw
