@@ -5,6 +5,10 @@ icosphere (level 7, l <= 8, amplitude 0.1), |v| ~ U[0, pi/2], two extra
 vectors transported (K = 2).  Inputs are synthetic and resident in HBM
 before timing.  A step is one sg_exp_transport call over the whole batch.
 
+The forward + backward forms (extrinsic proxy from the saved outputs, and
+geodesic finite differences, which re-walk seven geodesics per query) are
+timed on the same batch and reported beside it.
+
 Prints one JSON line.  `value` is face-crossings per second (the crossing
 count is the float64 oracle's, computed on the same batch in the CPU-baseline
 leg).  The roofline object prices the walk kernel against HBM bandwidth with
@@ -44,6 +48,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain kernel for comparison")
     ap.add_argument("--refill", type=int, default=0, help="persistent kernel refill threshold (0: library default)")
     ap.add_argument("--walk-blocks", type=int, default=0, help="persistent kernel blocks (0: fill the GPU)")
+    ap.add_argument("--no-bwd", action="store_true", help="skip timing the backward (EP and GFD)")
     ap.add_argument("--calib-copy", type=int, default=0, help="MiB copied once to calibrate byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -102,6 +107,31 @@ def main():
         ms_p, ms_pk, _ = timed(1, max(3, args.steps // 4), 1)
         plain = {"ms_per_call": ms_p, "events_ms": ms_pk}
         log(f"plain one-ray-per-lane kernel: {ms_p:.3f} ms/call")
+    bwd = None
+    if not args.no_bwd:
+        # forward + backward on the same batch: the forward's saved outputs feed the extrinsic
+        # proxy; geodesic finite differences re-walk seven geodesics per query (recompute, no paths)
+        g_up = torch.from_numpy(CF.upstream_grad(args.config, n)).to(dev)
+        gv = torch.empty(n, 3, device=dev)
+        gb = torch.empty(n, 3, device=dev)
+        bwd = {}
+        fo = sg.opts(kernel=args.kernel, refill_min=args.refill, walk_blocks=args.walk_blocks)
+        for name, mode in (("ep", sg.BWD_EP), ("gfd", sg.BWD_GFD)):
+            steps = max(3, args.steps // 2)
+            def call():
+                mesh.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=fo)
+                mesh.backward(mode, t["f"], t["b"], t["v"], g_up, f_out=out["f"], v_out=out["v"], out=(gv, gb), o=fo)
+            for _ in range(max(1, args.warmup)):
+                call()
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            for _ in range(steps):
+                call()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - w0) * 1e3 / steps
+            bwd[name] = {"ms_fwd_plus_bwd": ms, "ms_bwd": ms - ms_step, "queries_per_s": n / (ms * 1e-3),
+                         "finite": bool(torch.isfinite(gv).all().item())}
+            log(f"forward + {name} backward: {ms:.3f} ms/step ({n / (ms * 1e-3):.3e} queries/s)")
     if args.calib_copy:
         # a plain copy of known size, profiled beside the walk to scale the HBM byte counters
         src = torch.empty(args.calib_copy << 20, dtype=torch.uint8, device=dev)
@@ -130,6 +160,9 @@ def main():
         log(f"oracle: {ocross} crossings in {c1 - c0:.2f}s on {cores} threads; GPU/oracle crossing ratio "
             f"{gpu_cross / max(ocross, 1) if nc == n else float('nan'):.6f}")
 
+    if bwd:
+        for b in bwd.values():   # forward-path crossings per second of the whole fwd + bwd step
+            b["crossings_per_s"] = cross / (b["ms_fwd_plus_bwd"] * 1e-3)
     # algorithmic bytes: 16 per crossing (next face's shape in the crossed edge's frame and its two
     # onward links); per ray the walk kernel reads and writes a 32-byte chart state, while the whole
     # forward call reads the query and writes the answer (144 + 24 K bytes)
@@ -158,6 +191,7 @@ def main():
             "kernel": ["persistent (auto)", "plain", "persistent"][args.kernel],
         },
         "plain_kernel": plain,
+        "fwd_bwd": bwd,
         "speedup_over_plain": (plain["ms_per_call"] / ms_step) if plain else None,
         "queries_per_s": n / (ms_step * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
