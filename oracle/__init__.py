@@ -29,6 +29,8 @@ def lib():
         P = C.c_void_p
         L.or_mesh_build.argtypes = [P, C.c_int64, P, C.c_int64, C.POINTER(C.c_void_p)]
         L.or_mesh_build.restype = C.c_int
+        L.or_mesh_build64.argtypes = [P, C.c_int64, P, C.c_int64, C.POINTER(C.c_void_p)]
+        L.or_mesh_build64.restype = C.c_int
         L.or_mesh_free.argtypes = [P]
         L.or_mesh_mean_edge.argtypes = [P]
         L.or_mesh_mean_edge.restype = C.c_double
@@ -42,6 +44,8 @@ def lib():
         L.or_ep_batch.restype = C.c_int
         L.or_gfd_batch.argtypes = [P, C.c_int64, P, P, P, P, C.c_double, C.c_double, P, P, P, P, P, C.c_int32]
         L.or_gfd_batch.restype = C.c_int
+        L.or_gradx_batch.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, C.c_int32]
+        L.or_gradx_batch.restype = C.c_int
         _lib = L
     return _lib
 
@@ -61,14 +65,16 @@ class OracleError(RuntimeError):
 
 
 class Mesh:
-    """Oracle mesh built from the canonical float32 (X, F)."""
+    """Oracle mesh built from the canonical float32 (X, F); exact64=True keeps
+    float64 positions as given (used for central differences in X)."""
 
-    def __init__(self, X, F):
+    def __init__(self, X, F, exact64=False):
         L = lib()
-        self.X = np.ascontiguousarray(X, dtype=np.float32)
+        self.X = np.ascontiguousarray(X, dtype=np.float64 if exact64 else np.float32)
         self.F = np.ascontiguousarray(F, dtype=np.int32)
         h = C.c_void_p()
-        rc = L.or_mesh_build(_p(self.X), self.X.shape[0], _p(self.F), self.F.shape[0], C.byref(h))
+        build = L.or_mesh_build64 if exact64 else L.or_mesh_build
+        rc = build(_p(self.X), self.X.shape[0], _p(self.F), self.F.shape[0], C.byref(h))
         if rc != 0:
             raise OracleError(rc, L.or_last_error().decode())
         self._h = h
@@ -163,3 +169,18 @@ class Mesh:
         if rc != 0:
             raise OracleError(rc, lib().or_last_error().decode())
         return dict(grad_v=gv, grad_b=gb, Jv=Jv, Jp=Jp)
+
+    def gradx(self, f, b, v, g, max_steps=1 << 20, vertex_snap=1e-10, nthreads=0):
+        """(dL/dX [nv,3] float64, vertex passages per ray (-1: status not OK)) for L = sum g . p'."""
+        f = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
+        n = f.shape[0]
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(n, 3)
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(n, 3)
+        g = np.ascontiguousarray(g, dtype=np.float64).reshape(n, 3)
+        gx = np.zeros((self.nv, 3))
+        nvx = np.zeros(n, np.int32)
+        o = Opts(max_steps, vertex_snap)
+        rc = lib().or_gradx_batch(self._h, n, _p(f), _p(b), _p(v), C.byref(o), _p(g), _p(gx), _p(nvx), nthreads)
+        if rc != 0:
+            raise OracleError(rc, lib().or_last_error().decode())
+        return gx, nvx

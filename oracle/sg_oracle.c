@@ -112,6 +112,17 @@ void or_mesh_free(or_mesh* m) {
 
 int or_mesh_build(const float* X, int64_t nv, const int32_t* F, int64_t nf, or_mesh** out) {
     *out = NULL;
+    if (!X || nv <= 0) { set_err("empty mesh"); return OR_E_ARG; }
+    double* X64 = malloc(sizeof(double) * 3 * nv);
+    if (!X64) return OR_E_OOM;
+    for (int64_t i = 0; i < 3 * nv; i++) X64[i] = (double)X[i];
+    int rc = or_mesh_build64(X64, nv, F, nf, out);
+    free(X64);
+    return rc;
+}
+
+int or_mesh_build64(const double* X, int64_t nv, const int32_t* F, int64_t nf, or_mesh** out) {
+    *out = NULL;
     if (!X || !F || nv <= 0 || nf <= 0) { set_err("empty mesh"); return OR_E_ARG; }
     or_mesh* m = calloc(1, sizeof *m);
     if (!m) return OR_E_OOM;
@@ -129,7 +140,7 @@ int or_mesh_build(const float* X, int64_t nv, const int32_t* F, int64_t nf, or_m
     }
     for (int64_t i = 0; i < 3 * nv; i++) {
         if (!isfinite(X[i])) { set_err("non-finite vertex coordinate"); free(E); or_mesh_free(m); return OR_E_ARG; }
-        m->X[i] = (double)X[i];
+        m->X[i] = X[i];
     }
     for (int64_t f = 0; f < nf; f++) {
         for (int k = 0; k < 3; k++) {
@@ -771,4 +782,194 @@ int or_gfd_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
     J.eps_v = eps_v; J.eps_p = eps_p;
     J.g = g; J.grad_v = grad_v; J.grad_b = grad_b; J.Jv = Jv; J.Jp = Jp;
     return run_job(&J, nthreads);
+}
+
+/* ------------------------------------------------------------ vertex-position gradient */
+/* Hinge map of an edge crossing (transport_over_edge read as a rigid motion):
+ * H(y) = a + Q (y - a), Q the rotation about the line through a and b that
+ * unfolds the plane of the face left (apex cp) onto the plane of the face
+ * entered (apex cn): Q takes cp's side of the edge to the side opposite cn. */
+static void hinge_apply(const double* a, const double* b, const double* cp, const double* cn, const double* y,
+                        double* r) {
+    double u[3], mf[3], mg[3], cf[3], cg[3], t[3], w[3];
+    sub3(b, a, u); unit3(u);
+    sub3(cp, a, t); perp3(t, u, mf); unit3(mf);
+    sub3(cn, a, t); perp3(t, u, mg); unit3(mg);
+    cross3(u, mf, cf);
+    cross3(u, mg, cg);
+    sub3(y, a, w);
+    double pu = dot3(w, u), pm = dot3(w, mf), pc = dot3(w, cf);
+    for (int c = 0; c < 3; c++) r[c] = a[c] + pu * u[c] - pm * mg[c] - pc * cg[c];
+}
+
+/* y_0 = p + v_t of the start face with vertices x[0..2] (barycentrics b, 3D v). */
+static void start_point(const double* x, const double* b, const double* v, double* y) {
+    double e1[3], e2[3], n[3], vt[3];
+    sub3(x + 3, x, e1);
+    sub3(x + 6, x, e2);
+    cross3(e1, e2, n); unit3(n);
+    perp3(v, n, vt);
+    for (int c = 0; c < 3; c++) y[c] = b[0] * x[c] + b[1] * x[3 + c] + b[2] * x[6 + c] + vt[c];
+}
+
+typedef struct {
+    const or_mesh* m;
+    int64_t n;
+    const int32_t* f; const double* b; const double* v; const double* g; const or_opts* o;
+    double h;
+    int32_t* n_vertex;
+    int64_t next;
+    pthread_mutex_t lock;
+    double* grad;            /* nv*3, summed over threads at the end */
+} gx_job;
+
+/* One ray's contribution to dL/dX for L = g . p'.  Away from vertices
+ * p' = H_m o ... o H_1(y_0) (hinge composition of the edge unfoldings), so
+ * dL = lambda_0 . dy_0 + sum_j lambda_j . dH_j(y_{j-1}) with lambda_m = g and
+ * lambda_{j-1} = Q_j^T lambda_j.  The local derivatives of y_0 and of each H_j
+ * with respect to their (3 or 4) vertices are central differences of these
+ * closed forms with step h.  Rays that pass through a vertex contribute
+ * nothing (the vertex rule is not a hinge): the return value is their number
+ * of vertex passages, or -1 for a ray that did not end with status OK. */
+static int gradx_one(const or_mesh* m, int32_t f0, const double* b0, const double* v0, const double* g,
+                     const or_opts* o, double h, double* grad) {
+    int32_t cap = 1024;
+    trace_buf tb;
+    tb.cap = cap; tb.n = 0;
+    tb.kind = malloc(cap); tb.face = malloc(sizeof(int32_t) * cap);
+    tb.ev0 = malloc(sizeof(int32_t) * cap); tb.ev1 = malloc(sizeof(int32_t) * cap);
+    tb.pt = malloc(sizeof(double) * 3 * cap);
+    ray_out r;
+    for (;;) {
+        exp_one(m, f0, b0, v0, 0, NULL, o, &r, NULL, &tb);
+        if (tb.n < tb.cap) break;
+        cap *= 4;
+        tb.cap = cap; tb.n = 0;
+        tb.kind = realloc(tb.kind, cap); tb.face = realloc(tb.face, sizeof(int32_t) * cap);
+        tb.ev0 = realloc(tb.ev0, sizeof(int32_t) * cap); tb.ev1 = realloc(tb.ev1, sizeof(int32_t) * cap);
+        tb.pt = realloc(tb.pt, sizeof(double) * 3 * cap);
+    }
+    int nvert = 0;
+    for (int32_t j = 0; j < tb.n; j++) nvert += tb.kind[j] == 1;
+    if (r.status != OR_RAY_OK || nvert > 0) {
+        free(tb.kind); free(tb.face); free(tb.ev0); free(tb.ev1); free(tb.pt);
+        return r.status != OR_RAY_OK ? -1 : nvert;
+    }
+    const int32_t nh = tb.n;
+    /* hinge vertices: a, b on the edge, cp apex of the face left, cn apex of the face entered */
+    int32_t* HV = malloc(sizeof(int32_t) * 4 * (nh > 0 ? nh : 1));
+    double* Y = malloc(sizeof(double) * 3 * (nh + 1));
+    double* LAM = malloc(sizeof(double) * 3 * (nh + 1));
+    double bn[3] = {b0[0], b0[1], b0[2]};
+    double bs = bn[0] + bn[1] + bn[2];
+    for (int k = 0; k < 3; k++) bn[k] /= bs;
+    double xs[9];
+    for (int k = 0; k < 3; k++) memcpy(xs + 3 * k, FX(m, f0, k), 3 * sizeof(double));
+    start_point(xs, bn, v0, Y);
+    int64_t prev = f0;
+    for (int32_t j = 0; j < nh; j++) {
+        int32_t a = tb.ev0[j], bb = tb.ev1[j], g2 = tb.face[j];
+        int32_t cp = -1, cn = -1;
+        for (int k = 0; k < 3; k++) {
+            int32_t q = m->F[3 * prev + k];
+            if (q != a && q != bb) cp = q;
+            q = m->F[3 * (int64_t)g2 + k];
+            if (q != a && q != bb) cn = q;
+        }
+        HV[4 * j] = a; HV[4 * j + 1] = bb; HV[4 * j + 2] = cp; HV[4 * j + 3] = cn;
+        hinge_apply(VX(m, a), VX(m, bb), VX(m, cp), VX(m, cn), Y + 3 * j, Y + 3 * (j + 1));
+        prev = g2;
+    }
+    /* lambda_m = g; lambda_{j-1} = Q_j^T lambda_j, Q_j w = H_j(a + w) - a */
+    memcpy(LAM + 3 * nh, g, 3 * sizeof(double));
+    for (int32_t j = nh; j >= 1; j--) {
+        const int32_t* hv = HV + 4 * (j - 1);
+        const double *a = VX(m, hv[0]), *bb = VX(m, hv[1]), *cp = VX(m, hv[2]), *cn = VX(m, hv[3]);
+        double Qt[3][3];   /* rows: Q e_c */
+        for (int c = 0; c < 3; c++) {
+            double y[3] = {a[0], a[1], a[2]}, r2[3];
+            y[c] += 1.0;
+            hinge_apply(a, bb, cp, cn, y, r2);
+            for (int q = 0; q < 3; q++) Qt[c][q] = r2[q] - a[q];
+        }
+        for (int c = 0; c < 3; c++) LAM[3 * (j - 1) + c] = dot3(Qt[c], LAM + 3 * j);
+    }
+    /* start term */
+    for (int k = 0; k < 3; k++)
+        for (int c = 0; c < 3; c++) {
+            double xp[9], xm[9], yp[3], ym[3];
+            memcpy(xp, xs, sizeof xs); memcpy(xm, xs, sizeof xs);
+            xp[3 * k + c] += h; xm[3 * k + c] -= h;
+            start_point(xp, bn, v0, yp);
+            start_point(xm, bn, v0, ym);
+            double dy[3] = {(yp[0] - ym[0]) / (2 * h), (yp[1] - ym[1]) / (2 * h), (yp[2] - ym[2]) / (2 * h)};
+            grad[3 * (int64_t)m->F[3 * (int64_t)f0 + k] + c] += dot3(LAM, dy);
+        }
+    /* hinge terms */
+    for (int32_t j = 1; j <= nh; j++) {
+        const int32_t* hv = HV + 4 * (j - 1);
+        for (int w = 0; w < 4; w++)
+            for (int c = 0; c < 3; c++) {
+                double P[4][3], rp[3], rm[3];
+                for (int q = 0; q < 4; q++) memcpy(P[q], VX(m, hv[q]), 3 * sizeof(double));
+                P[w][c] += h;
+                hinge_apply(P[0], P[1], P[2], P[3], Y + 3 * (j - 1), rp);
+                P[w][c] -= 2 * h;
+                hinge_apply(P[0], P[1], P[2], P[3], Y + 3 * (j - 1), rm);
+                double dy[3] = {(rp[0] - rm[0]) / (2 * h), (rp[1] - rm[1]) / (2 * h), (rp[2] - rm[2]) / (2 * h)};
+                grad[3 * (int64_t)hv[w] + c] += dot3(LAM + 3 * j, dy);
+            }
+    }
+    free(HV); free(Y); free(LAM);
+    free(tb.kind); free(tb.face); free(tb.ev0); free(tb.ev1); free(tb.pt);
+    return 0;
+}
+
+static void* gx_worker(void* arg) {
+    gx_job* J = arg;
+    const or_mesh* m = J->m;
+    double* g = calloc(3 * m->nv, sizeof(double));
+    if (!g) return NULL;
+    for (;;) {
+        pthread_mutex_lock(&J->lock);
+        int64_t s = J->next;
+        J->next += 256;
+        pthread_mutex_unlock(&J->lock);
+        if (s >= J->n) break;
+        int64_t e = s + 256 < J->n ? s + 256 : J->n;
+        for (int64_t i = s; i < e; i++) {
+            int nvx = gradx_one(m, J->f[i], J->b + 3 * i, J->v + 3 * i, J->g + 3 * i, J->o, J->h, g);
+            if (J->n_vertex) J->n_vertex[i] = nvx;
+        }
+    }
+    pthread_mutex_lock(&J->lock);
+    for (int64_t i = 0; i < 3 * m->nv; i++) J->grad[i] += g[i];
+    pthread_mutex_unlock(&J->lock);
+    free(g);
+    return NULL;
+}
+
+int or_gradx_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b, const double* v,
+                   const or_opts* o, const double* g, double* grad_X, int32_t* n_vertex, int32_t nthreads) {
+    if (!m || n < 0 || !grad_X || (n > 0 && (!f || !b || !v || !g))) { set_err("bad arguments"); return OR_E_ARG; }
+    memset(grad_X, 0, sizeof(double) * 3 * m->nv);
+    double scale = 0.0;
+    for (int64_t i = 0; i < 3 * m->nv; i++) scale = fmax(scale, fabs(m->X[i]));
+    gx_job J;
+    J.m = m; J.n = n; J.f = f; J.b = b; J.v = v; J.g = g; J.o = o;
+    J.h = 1e-6 * (scale > 0 ? scale : 1.0);
+    J.n_vertex = n_vertex; J.next = 0; J.grad = grad_X;
+    pthread_mutex_init(&J.lock, NULL);
+    if (nthreads <= 0) nthreads = (int32_t)sysconf(_SC_NPROCESSORS_ONLN);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    int started = 0;
+    for (int t = 0; t < nthreads && n > 256 * t; t++)
+        if (pthread_create(&th[t], NULL, gx_worker, &J) == 0) started++;
+        else break;
+    if (!started) gx_worker(&J);
+    for (int t = 0; t < started; t++) pthread_join(th[t], NULL);
+    pthread_mutex_destroy(&J.lock);
+    return OR_OK;
 }

@@ -30,6 +30,8 @@ typedef struct {
 /* Builds adjacency, normals and vertex total angles from the canonical float32
  * mesh (upcast exactly).  Returns OR_OK or a negative error code. */
 int or_mesh_build(const float* X, int64_t nv, const int32_t* F, int64_t nf, or_mesh** out);
+/* The same from float64 positions (used to take central differences in X). */
+int or_mesh_build64(const double* X, int64_t nv, const int32_t* F, int64_t nf, or_mesh** out);
 void or_mesh_free(or_mesh* m);
 double or_mesh_mean_edge(const or_mesh* m);
 void or_mesh_theta(const or_mesh* m, double* theta /* [nv] */);
@@ -72,6 +74,19 @@ int or_gfd_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
                  const double* v, const or_opts* o, double eps_v, double eps_p,
                  const double* g, double* grad_v, double* grad_b,
                  double* Jv, double* Jp, int32_t nthreads);
+
+/* Gradient of L = sum_i g_i . p'_i with respect to the vertex positions
+ * (an extension: the paper differentiates only in v and p).  Away from
+ * vertices p' = H_m o ... o H_1(p + v_t), a composition of the edge unfoldings
+ * read as rigid hinge motions; the adjoint is taken through that chain in
+ * float64, each hinge's local derivative by a central difference of its
+ * closed form (step 1e-6 of the largest coordinate).  grad_X [nv*3] is
+ * overwritten.  Rays that pass through a vertex, or end with a status other
+ * than OK, contribute nothing; n_vertex [n] (nullable) receives each ray's
+ * number of vertex passages, or -1 for a status other than OK. */
+int or_gradx_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
+                   const double* v, const or_opts* o, const double* g, double* grad_X,
+                   int32_t* n_vertex, int32_t nthreads);
 
 #ifdef __cplusplus
 }

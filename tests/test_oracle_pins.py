@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from workloads import configs as CF
 from workloads import meshes as M
 from workloads.rays import random_rays, uniform_len, face_frames
 from unfold_bruteforce import unfold_path
@@ -493,3 +494,59 @@ def test_orientation_invariance(rng):
     assert np.abs(o2["p"] - o["p"])[far].max() < 1e-12
     assert np.abs(o2["v"] - o["v"])[far].max() < 1e-12
     assert np.abs(o2["W"] - o["W"])[far].max() < 1e-12
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_gradx_matches_central_differences(rng, mixed):
+    """dL/dX for L = sum g . p' against central differences of the float64
+    forward in the vertex positions (h = 1e-6), on rays that keep a margin
+    from every vertex (frozen combinatorics); also with faces of disagreeing
+    orientation (the unfolding is orientation-free)."""
+    X, F = CF.mesh_config(1)
+    if mixed:
+        F = F.copy()
+        flip = rng.random(F.shape[0]) < 0.3
+        F[flip] = F[flip][:, ::-1]
+    X64 = X.astype(np.float64)
+    n = 200
+    r = random_rays(X, F, n, rng, uniform_len(0.0, 1.5))
+    g = rng.standard_normal((n, 3))
+    om = oracle.Mesh(X, F)
+    o = om.exp(r["f"], r["b"], r["v"])
+    keep = (o["min_vdist"] > 1e-2 * om.mean_edge) & (o["status"] == 0)
+    g[~keep] = 0.0
+    gx, nvx = om.gradx(r["f"], r["b"], r["v"], g)
+    assert np.all(nvx[keep] == 0)
+    assert keep.sum() > 100
+
+    def loss(Xp):
+        oo = oracle.Mesh(Xp, F, exact64=True).exp(r["f"], r["b"], r["v"])
+        return float((g * oo["p"]).sum())
+
+    h = 1e-6
+    for _ in range(2):
+        dX = rng.standard_normal(X.shape)
+        dX /= np.linalg.norm(dX, axis=1).max()
+        cd = (loss(X64 + h * dX) - loss(X64 - h * dX)) / (2 * h)
+        assert abs(cd - float((gx * dX).sum())) <= 1e-6 * abs(cd)
+    for vtx in np.argsort(-np.linalg.norm(gx, axis=1))[:2]:
+        for c in range(3):
+            dX = np.zeros_like(X64)
+            dX[vtx, c] = 1.0
+            cd = (loss(X64 + h * dX) - loss(X64 - h * dX)) / (2 * h)
+            assert abs(cd - gx[vtx, c]) <= 1e-6 * np.linalg.norm(gx[vtx])
+
+
+def test_gradx_translation(rng):
+    """Translating the whole mesh (v held fixed) translates every p': the
+    vertex gradients sum to the sum of the upstream gradients."""
+    X, F = CF.mesh_config(1)
+    n = 300
+    r = random_rays(X, F, n, rng, uniform_len(0.0, 1.5))
+    g = rng.standard_normal((n, 3))
+    om = oracle.Mesh(X, F)
+    o = om.exp(r["f"], r["b"], r["v"])
+    keep = (o["min_vdist"] > 1e-2 * om.mean_edge) & (o["status"] == 0)
+    g[~keep] = 0.0
+    gx, _ = om.gradx(r["f"], r["b"], r["v"], g)
+    assert np.allclose(gx.sum(0), g.sum(0), rtol=1e-7, atol=1e-7)
