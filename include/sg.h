@@ -133,12 +133,15 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
                      const sg_opts* opts, void* stream);
 
 /*
- * Backward of the exponential map with respect to the query (Sec. 4
- * "Backpropagation"): given g_p[n,3] = dL/dp' (float32, device) returns
+ * Backward of the exponential map (Sec. 4 "Differentiation").  Given
+ * g_p[n,3] = dL/dp' (float32, device) for the queries (f, b, v) of an earlier
+ * sg_exp call, returns
  *   grad_v[n,3] = dL/dv (tangent to the start face) and
  *   grad_b[n,3] = dL/db (component k = G . x_k, where G is the in-plane
  *                 gradient of L with respect to the start point),
- * for the queries (f, b, v) of an earlier sg_exp call.
+ * both nullable together, and accumulates into grad_X[n_verts,3] (float64,
+ * nullable; the caller zeroes it) dL/dX, the gradient with respect to the
+ * vertex positions (global vertex ids).
  *   mode SG_BWD_EP  (eq. proxy_func): J^v = R = M_{p'} M_p^T with frames
  *        [e_par, e_perp, n] at both ends; grad_b = 0.  On meshes whose faces
  *        agree in orientation it reads the forward's f_out[n] and v_out[n,3]
@@ -150,14 +153,26 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
  *        steps, then the e_par step from p' and the two start-point-shifted
  *        geodesics) in two persistent passes; nothing of the forward is read.
  *        |v_t| = 0 takes e_par = e_u (the start face's x1 - x0 direction).
- * Queries the forward rejects (SG_RAY_BADINPUT) get NaN gradients.  Uses a
- * stream-ordered device workspace (224 bytes per query for GFD, 32 for a
- * re-walked EP).  opts: max_steps, vertex_snap, eps_v, eps_p, refill_min,
- * walk_blocks are honoured; kernel is ignored (always the persistent walk).
+ *   grad_X (an extension; the paper has no vertex gradient): the exact
+ *        derivative of p' = H_m o ... o H_1(p + v_t), the composition of the
+ *        rigid unfoldings about the crossed edges, with the combinatorics
+ *        frozen.  The geodesic is re-walked twice (end frame, then the
+ *        adjoint's per-edge float64 sums), then one pass maps each crossed
+ *        edge's sums to its four hinge vertices with float64 atomics.  Rays
+ *        whose walk ends with a status other than SG_RAY_OK contribute
+ *        nothing.  A vertex passage is not a hinge: such rays contribute their
+ *        edge and start terms with the vertex rule held fixed, which is not
+ *        the derivative of the map (give them g_p = 0 to exclude them).
+ *        Float64 atomics make grad_X's last bits depend on timing.
+ * Queries the forward rejects (SG_RAY_BADINPUT) get NaN in grad_v, grad_b.
+ * Uses a stream-ordered device workspace (GFD 224 bytes per query, a re-walk
+ * 32; grad_X 48 per query plus 120 per face).  opts: max_steps, vertex_snap,
+ * eps_v, eps_p, refill_min, walk_blocks are honoured; kernel is ignored (the
+ * persistent walk always runs).
  */
 int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b, const float* v,
                     const int32_t* f_out, const float* v_out, const float* g_p,
-                    float* grad_v, float* grad_b, const sg_opts* opts, void* stream);
+                    float* grad_v, float* grad_b, double* grad_X, const sg_opts* opts, void* stream);
 
 /*
  * Walk-kernel timing (profiling aid).  Calls made with opts->debug bit 2

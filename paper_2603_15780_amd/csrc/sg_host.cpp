@@ -38,12 +38,13 @@ struct sg_mesh_s {
     int64_t* d_half = nullptr;
     int32_t* d_perm = nullptr;
     int32_t* d_order = nullptr;
+    int32_t* d_twin = nullptr;
     int32_t part_he[sg::kParts + 1] = {};
     int32_t has_flip = 0;
     size_t bytes = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare;   // walk-kernel event pairs
     sg::DevMesh dev() const {
-        sg::DevMesh d{d_rec, d_F, d_X, d_half, d_perm, d_order, n_faces, n_verts, has_flip, {}};
+        sg::DevMesh d{d_rec, d_F, d_X, d_half, d_perm, d_order, n_faces, n_verts, has_flip, {}, d_twin};
         for (int p = 0; p <= sg::kParts; ++p) d.part_he[p] = part_he[p];
         return d;
     }
@@ -125,6 +126,7 @@ void free_mesh(sg_mesh_s* m) {
     (void)hipFree(m->d_half);
     (void)hipFree(m->d_perm);
     (void)hipFree(m->d_order);
+    (void)hipFree(m->d_twin);
     delete m;
 }
 
@@ -342,6 +344,7 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
         out.has_flip = 0;
         for (const HalfEdgeRec& r : rec)
             if ((r.nca >= 0 && (r.nca & 1)) || (r.nbc >= 0 && (r.nbc & 1))) out.has_flip = 1;
+        out.twin.assign(twin.begin(), twin.end());
         out.X.assign(X_host, X_host + 3 * n_verts);
         out.F = std::move(F);
         out.n_verts = n_verts;
@@ -406,6 +409,7 @@ int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, 
     if (rc == SG_OK) rc = upload(&m->d_half, pm.half, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_perm, pm.perm, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_order, order32, m->bytes);
+    if (rc == SG_OK) rc = upload(&m->d_twin, pm.twin, m->bytes);
     if (rc != SG_OK) {
         free_mesh(m);
         return rc;
@@ -498,19 +502,22 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
 
 int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b, const float* v,
                     const int32_t* f_out, const float* v_out, const float* g_p, float* grad_v, float* grad_b,
-                    const sg_opts* opts, void* stream) {
+                    double* grad_X, const sg_opts* opts, void* stream) {
     if (!mesh) return fail(SG_E_ARG, "mesh is NULL");
     if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
     if (mode != SG_BWD_EP && mode != SG_BWD_GFD) return fail(SG_E_ARG, "unknown backward mode %d", mode);
+    if ((grad_v == nullptr) != (grad_b == nullptr)) return fail(SG_E_ARG, "grad_v and grad_b go together");
     sg_opts o;
     int rc = check_opts(opts, o, mesh);
     if (rc != SG_OK) return rc;
     if (o.kernel == SG_KERNEL_PARTITIONED) o.walk_blocks = mesh->cu_count * mesh->walk_blocks_per_cu;
     if (!(std::isfinite(o.eps_v) && std::isfinite(o.eps_p))) return fail(SG_E_ARG, "eps_v and eps_p must be finite");
     if (n == 0) return SG_OK;
-    if (!f || !b || !v || !g_p || !grad_v || !grad_b) return fail(SG_E_ARG, "a required array is NULL");
-    const bool saved = mode == SG_BWD_EP && !mesh->has_flip;
-    if (saved && (!f_out || !v_out)) return fail(SG_E_ARG, "the extrinsic proxy needs the forward's f_out and v_out");
+    if (!f || !b || !v || !g_p) return fail(SG_E_ARG, "a required array is NULL");
+    const bool vjp = grad_v != nullptr;
+    if (!vjp && !grad_X) return SG_OK;
+    if (vjp && mode == SG_BWD_EP && !mesh->has_flip && (!f_out || !v_out))
+        return fail(SG_E_ARG, "the extrinsic proxy needs the forward's f_out and v_out");
     sg::BwdArgs a{};
     a.n = n;
     a.mode = mode;
@@ -518,11 +525,12 @@ int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, con
     a.f_out = f_out; a.v_out = v_out;
     a.g = g_p;
     a.grad_v = grad_v; a.grad_b = grad_b;
+    a.grad_X = grad_X;
     a.eps_v = o.eps_v; a.eps_p = o.eps_p;
     a.max_steps = o.max_steps;
     a.snap = o.vertex_snap;
     const hipStream_t st = (hipStream_t)stream;
-    const size_t wsb = sg::bwd_workspace(n, mode, mesh->has_flip != 0);
+    const size_t wsb = sg::bwd_workspace(n, mode, mesh->has_flip != 0, vjp, grad_X != nullptr, mesh->n_faces);
     void* ws = nullptr;
     if (wsb) {
         hipError_t e = hipMallocAsync(&ws, wsb, st);

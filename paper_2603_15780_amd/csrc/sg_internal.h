@@ -48,6 +48,7 @@ struct DevMesh {
     int64_t n_verts;
     int32_t has_flip;           // some adjacent faces disagree in orientation (non-orientable or mixed)
     int32_t part_he[kParts + 1];// half-edge id ranges of the parts
+    const int32_t* twin;        // [3 n_faces] half-edge on the other side of each edge, -1 on the boundary
 };
 
 enum RayStatus : int32_t { kRayOk = 0, kRayMaxSteps = 1, kRayBoundary = 2, kRayBadInput = 3 };

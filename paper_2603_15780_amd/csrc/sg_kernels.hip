@@ -656,9 +656,57 @@ __global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* st
 // lane ranks), so short and long rays share lanes instead of idling behind
 // the longest ray of a fixed batch.  Between refills the wave runs a tight
 // loop of walk steps and re-ballots only to see whether enough lanes are idle.
-template <bool kHash, bool kFlip>
-__global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
-                                              int32_t max_steps, float snap, int refill_min) {
+// Float64 add into a global sum (the gradient accumulators).  hipMalloc'd
+// memory is coarse-grained, where the hardware float64 atomic is exact.
+SG_HD __forceinline__ void add_f64(double* p, double v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    unsafeAtomicAdd(p, v);
+#else
+    uint64_t* q = reinterpret_cast<uint64_t*>(p);
+    uint64_t old = __atomic_load_n(q, __ATOMIC_RELAXED), nw;
+    do {
+        double d;
+        __builtin_memcpy(&d, &old, 8);
+        d += v;
+        __builtin_memcpy(&nw, &d, 8);
+    } while (!__atomic_compare_exchange_n(q, &old, nw, true, __ATOMIC_RELAXED, __ATOMIC_RELAXED));
+#endif
+}
+
+// Vertex-position gradient, per edge crossing: the adjoint lambda is
+// constant in the development (it keeps its components c = (c_d, c_q, c_n)
+// on the frame [d, nu x d, nu] of the tangent d and the carried normal nu).
+// In the chart of the entered half-edge h, frame (u, m, n) = (x, y, z), it
+// adds to h's sums the normal-and-apex-side components (l_m, l_n) of lambda
+// and T = r x lambda, r = (s + l cos phi, l sin phi, 0) the virtual endpoint
+// relative to the chart origin.
+SG_HD __forceinline__ void gx_cross(double* acc, const Ray& st, const float4& c) {
+    float sn, cs;
+    sincos_fx(st.phi, sn, cs);
+    const float sg = (st.par & kParity) ? -1.f : 1.f;
+    const float lu = fmaf(c.x, cs, -sg * c.y * sn);
+    const float lm = fmaf(c.x, sn, sg * c.y * cs);
+    const float ln = sg * c.z;
+    const float Lr = st.Lhi + st.Llo;
+    const float ru = fmaf(Lr, cs, st.s), rm = Lr * sn;
+    double* q = acc + 5 * (int64_t)st.h;
+    add_f64(q, (double)lm);
+    add_f64(q + 1, (double)ln);
+    add_f64(q + 2, (double)(rm * ln));
+    add_f64(q + 3, (double)(-ru * ln));
+    add_f64(q + 4, (double)fmaf(ru, lm, -rm * lu));
+}
+
+// Persistent walk: each wave keeps 64 rays in flight and refills finished
+// lanes from a global queue (one atomic per wave per refill, ballot for the
+// lane ranks), so short and long rays share lanes instead of idling behind
+// the longest ray of a fixed batch.  Between refills the wave runs a tight
+// loop of walk steps and re-ballots only to see whether enough lanes are idle.
+// With kGX every edge crossing also adds its vertex-gradient terms.
+template <bool kHash, bool kFlip, bool kGX>
+__device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, int64_t n, unsigned long long* counter,
+                                          int32_t max_steps, float snap, int refill_min, const float4* cvec,
+                                          double* acc) {
     const int lane = (int)(threadIdx.x & 63u);
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     bool active = false;
@@ -666,6 +714,7 @@ __global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, int64
     int64_t q = 0;
     Ray st;
     st.h = 0; st.s = st.t = st.Lhi = st.Llo = st.bias = 0.f; st.phi = st.par = 0u; st.ncross = 0; st.hash = 0ull;
+    float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
     for (;;) {
         const uint64_t idle = __ballot(!active);
         const int nidle = __popcll(idle);
@@ -682,6 +731,7 @@ __global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, int64
                     if (rec.h >= 0) {
                         unpack_state(rec, st);
                         st.hash = kHash ? fnv_face(14695981039346656037ull, (uint32_t)M.order[rec.h / 3]) : 0ull;
+                        if (kGX) c = cvec[q];
                         active = true;
                     }
                 }
@@ -695,11 +745,26 @@ __global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, int64
                 if (walk_step<kHash, kFlip>(M, st, max_steps, snap, fin) == kStepDone) {
                     *reinterpret_cast<Final*>(&states[q]) = fin;
                     active = false;
+                } else if (kGX && st.bias == 0.f) {   // an edge crossing (a vertex passage leaves a bias)
+                    gx_cross(acc, st, c);
                 }
             }
             if (__popcll(__ballot(!active)) >= stop_at) break;
         }
     }
+}
+
+template <bool kHash, bool kFlip>
+__global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
+                                              int32_t max_steps, float snap, int refill_min) {
+    walk_loop<kHash, kFlip, false>(M, states, n, counter, max_steps, snap, refill_min, nullptr, nullptr);
+}
+
+template <bool kFlip>
+__global__ __launch_bounds__(256) void k_walk_gx(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
+                                                 int32_t max_steps, float snap, int refill_min, const float4* cvec,
+                                                 double* acc) {
+    walk_loop<false, kFlip, true>(M, states, n, counter, max_steps, snap, refill_min, cvec, acc);
 }
 
 // ---------------------------------------------------------------- partitioned form
@@ -1222,11 +1287,11 @@ SG_HD void ep_saved(const DevMesh& M, const BwdArgs& a, int64_t i) {
 
 // EP from a recomputed walk (meshes whose faces disagree in orientation: the
 // end normal's sign comes from the walk's orientation parity).
-SG_HD void ep_walked(const DevMesh& M, const BwdArgs& a, const StateRec* s1, int64_t i) {
+SG_HD void ep_walked(const DevMesh& M, const BwdArgs& a, const StateRec* s1, int stride, int64_t i) {
     StartFrame S;
     uint32_t phi0;
     float L;
-    const Final F0 = as_final(s1[i]);
+    const Final F0 = as_final(s1[(int64_t)stride * i]);
     if (bwd_query(M, a, i, S, phi0, L) != kInitOk || F0.h < 0) {
         nan_grads(a, i);
         return;
@@ -1238,6 +1303,134 @@ SG_HD void ep_walked(const DevMesh& M, const BwdArgs& a, const StateRec* s1, int
     float3 d3, n3;
     final_frame(M, F0, d3, n3);
     ep_grad(a, i, S, phi0, d3, n3);
+}
+
+// ---------------------------------------------------------------- vertex-position gradient
+// (an extension: the paper differentiates in v and p only).  Away from
+// vertices p' = H_m o ... o H_1(p + v_t), H_j the rigid unfolding about the
+// j-th crossed edge, so for L = g . p'
+//   dL = lambda_0 . d(p + v_t) + sum_j [ ((I - Q_j)^T lambda_j) . da_j
+//                                         + dw_j . ((y_j - a_j) x lambda_j) ],
+// lambda_j = Q_j ... Q_1 R^T g, dw_j the infinitesimal rotation of hinge j
+// (the rotation rate of the entered face's edge frame minus that of the face
+// left, carried over the hinge).  The walk adds each crossing's terms to sums
+// of the entered half-edge; one pass over half-edges then maps the sums to
+// the four hinge vertices in float64.
+
+// Start term and the walk's initial state; c = components of g on the end frame
+// [d', nu' x d', nu'] of the base walk (slot `stride * i` of s1).
+SG_HD void gradx_init(const DevMesh& M, const BwdArgs& a, const StateRec* s1, int stride, StateRec* s3, float4* cvec,
+                      int64_t i) {
+    s3[i] = dead_state();
+    StartFrame S;
+    uint32_t phi0;
+    float L;
+    if (bwd_query(M, a, i, S, phi0, L) != kInitOk) return;
+    const Final F0 = as_final(s1[(int64_t)stride * i]);
+    if (F0.h < 0 || ((F0.flags >> 8) & 0xffu) != (uint32_t)kRayOk) return;
+    float3 d3, n3;
+    final_frame(M, F0, d3, n3);
+    const float3 g = ld3(a.g + 3 * i);
+    const float4 c = make_float4(dot(g, d3), dot(g, crs(n3, d3)), dot(g, n3), 0.f);
+    if (c.x == 0.f && c.y == 0.f && c.z == 0.f) return;   // g = 0: nothing to add
+    float sn, cs;
+    sincos_full(phi0, sn, cs);
+    const float3 d0 = make_float3(fmaf(cs, S.ex.x, sn * S.ey.x), fmaf(cs, S.ex.y, sn * S.ey.y),
+                                  fmaf(cs, S.ex.z, sn * S.ey.z));
+    const float3 q0 = crs(S.n, d0);
+    const float3 lam = make_float3(fmaf(c.x, d0.x, fmaf(c.y, q0.x, c.z * S.n.x)),
+                                   fmaf(c.x, d0.y, fmaf(c.y, q0.y, c.z * S.n.y)),
+                                   fmaf(c.x, d0.z, fmaf(c.y, q0.z, c.z * S.n.z)));
+    // d(p + v_t): p = sum b_k x_k, and v_t = v - (v . n) n turns with the start
+    // face's normal; with w = (lambda . n) v + (v . n) lambda its term is -w . dn,
+    // dn = -alpha u - beta m for the plane tilt alpha = (h1 - h0)/l,
+    // beta = (h2 - h0 - alpha cx)/cy of normal offsets h_k.
+    const float3 v = ld3(a.v + 3 * i);
+    const float vn = dot(v, S.n), ln = dot(lam, S.n);
+    const float3 w = make_float3(fmaf(ln, v.x, vn * lam.x), fmaf(ln, v.y, vn * lam.y), fmaf(ln, v.z, vn * lam.z));
+    const float wu = dot(w, S.ex), wm = dot(w, S.ey);
+    const int64_t f3 = 3 * (int64_t)S.f;
+    const float3 e2 = sub(ld3(M.X + 3 * (int64_t)M.F[f3 + 2]), S.x0);
+    const float cx = dot(e2, S.ex), cy = dot(e2, S.ey);
+    const float dh1 = wu / S.l0 - wm * cx / (S.l0 * cy);
+    const float dh2 = wm / cy;
+    const float dh[3] = {-(dh1 + dh2), dh1, dh2};
+    const float bk[3] = {S.b0, S.b1, S.b2};
+    for (int k = 0; k < 3; ++k) {
+        double* gx = a.grad_X + 3 * (int64_t)M.F[f3 + k];
+        add_f64(gx, (double)fmaf(bk[k], lam.x, dh[k] * S.n.x));
+        add_f64(gx + 1, (double)fmaf(bk[k], lam.y, dh[k] * S.n.y));
+        add_f64(gx + 2, (double)fmaf(bk[k], lam.z, dh[k] * S.n.z));
+    }
+    if (!(L > 0.f)) return;
+    Ray st;
+    if (enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, 0.f, st) != kInitOk) return;
+    s3[i] = pack_state(st);
+    cvec[i] = c;
+}
+
+struct D3 { double x, y, z; };
+SG_HD __forceinline__ D3 dld(const float* p) { return D3{(double)p[0], (double)p[1], (double)p[2]}; }
+SG_HD __forceinline__ D3 dsub(D3 a, D3 b) { return D3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+SG_HD __forceinline__ double ddot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+SG_HD __forceinline__ D3 dcrs(D3 a, D3 b) { return D3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+SG_HD __forceinline__ D3 dscl(D3 a, double s) { return D3{a.x * s, a.y * s, a.z * s}; }
+SG_HD __forceinline__ D3 dmad(D3 a, double s, D3 b) { return D3{a.x + s * b.x, a.y + s * b.y, a.z + s * b.z}; }
+SG_HD __forceinline__ void dadd_atomic(double* g, D3 v) { add_f64(g, v.x); add_f64(g + 1, v.y); add_f64(g + 2, v.z); }
+
+// Edge pass: half-edge h (entered from its twin's face).  The rotation rate of
+// a face's edge frame (u, m toward the apex, n = u x m) under normal offsets
+// h_a, h_b, h_c of its vertices and an in-plane offset of b - a is
+//   w.u = (h_c - h_a - (h_b - h_a) cx / l) / cy,  w.m = -(h_b - h_a) / l,
+//   w.n = m . (db - da) / l,
+// so T . w spreads over a, b and the apex; the face left enters with
+// T' = (-T_u, T_m, T_n) (its frame is the unfolding's image of (u, -m, -n)).
+SG_HD void gradx_edge(const DevMesh& M, const double* acc, double* grad_X, int64_t h) {
+    const double* q = acc + 5 * h;
+    const double slm = q[0], sln = q[1], tu = q[2], tm = q[3], tn = q[4];
+    if (slm == 0.0 && sln == 0.0 && tu == 0.0 && tm == 0.0 && tn == 0.0) return;
+    const int64_t t = M.twin[h];
+    if (t < 0) return;
+    const int64_t f = h / 3, k = h - 3 * f, fg = t / 3, kt = t - 3 * fg;
+    const int32_t ia = M.F[3 * f + k], ib = M.F[3 * f + (k + 1) % 3], ic = M.F[3 * f + (k + 2) % 3];
+    const int32_t ip = M.F[3 * fg + (kt + 2) % 3];
+    const D3 A = dld(M.X + 3 * (int64_t)ia), B = dld(M.X + 3 * (int64_t)ib);
+    const D3 Cn = dld(M.X + 3 * (int64_t)ic), Cp = dld(M.X + 3 * (int64_t)ip);
+    D3 u = dsub(B, A);
+    const double l = sqrt(ddot(u, u));
+    u = dscl(u, 1.0 / l);
+    D3 wj = dsub(Cn, A);
+    const double cx = ddot(wj, u);
+    D3 mj = dmad(wj, -cx, u);
+    const double cy = sqrt(ddot(mj, mj));
+    mj = dscl(mj, 1.0 / cy);
+    const D3 nj = dcrs(u, mj);
+    D3 wp = dsub(Cp, A);
+    const double cxp = ddot(wp, u);
+    D3 mp = dmad(wp, -cxp, u);
+    const double cyp = sqrt(ddot(mp, mp));
+    mp = dscl(mp, 1.0 / cyp);
+    const D3 np = dcrs(u, mp);
+    // (I - Q)^T lambda = l_m (m_j + m') + l_n (n_j + n')
+    D3 ga = D3{slm * (mj.x + mp.x) + sln * (nj.x + np.x), slm * (mj.y + mp.y) + sln * (nj.y + np.y),
+               slm * (mj.z + mp.z) + sln * (nj.z + np.z)};
+    D3 gb = D3{0.0, 0.0, 0.0};
+    // entered face, T = (tu, tm, tn)
+    const D3 gcn = dscl(nj, tu / cy);
+    gb = dmad(gb, -tu * cx / (l * cy) - tm / l, nj);
+    gb = dmad(gb, tn / l, mj);
+    ga = dmad(ga, tu * (cx / l - 1.0) / cy + tm / l, nj);
+    ga = dmad(ga, -tn / l, mj);
+    // face left, T' = (-tu, tm, tn)
+    const D3 gcp = dscl(np, -tu / cyp);
+    gb = dmad(gb, tu * cxp / (l * cyp) - tm / l, np);
+    gb = dmad(gb, tn / l, mp);
+    ga = dmad(ga, -tu * (cxp / l - 1.0) / cyp + tm / l, np);
+    ga = dmad(ga, -tn / l, mp);
+    dadd_atomic(grad_X + 3 * (int64_t)ia, ga);
+    dadd_atomic(grad_X + 3 * (int64_t)ib, gb);
+    dadd_atomic(grad_X + 3 * (int64_t)ic, gcn);
+    dadd_atomic(grad_X + 3 * (int64_t)ip, gcp);
 }
 
 // Walks one chart state to its end in place (sequential form of k_walk).
@@ -1261,10 +1454,22 @@ SG_ROW_KERNEL(k_bwd_stage1, bwd_stage1(M, a, s1, per_ray, i), StateRec* s1, int 
 SG_ROW_KERNEL(k_bwd_stage2, bwd_stage2(M, a, s1, s2, i), const StateRec* s1, StateRec* s2)
 SG_ROW_KERNEL(k_gfd_assemble, gfd_assemble(M, a, s1, s2, i), const StateRec* s1, const StateRec* s2)
 SG_ROW_KERNEL(k_ep_saved, ep_saved(M, a, i))
-SG_ROW_KERNEL(k_ep_walked, ep_walked(M, a, s1, i), const StateRec* s1)
+SG_ROW_KERNEL(k_ep_walked, ep_walked(M, a, s1, stride, i), const StateRec* s1, int stride)
+SG_ROW_KERNEL(k_gradx_init, gradx_init(M, a, s1, stride, s3, cvec, i), const StateRec* s1, int stride, StateRec* s3,
+              float4* cvec)
 #undef SG_ROW_KERNEL
 
 __global__ __launch_bounds__(64) void k_reset_counter(unsigned long long* c) { *c = 0ull; }
+
+__global__ __launch_bounds__(256) void k_zero_f64(double* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_gradx_edges(DevMesh M, const double* acc, double* grad_X) {
+    const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (h < 3 * M.n_faces) gradx_edge(M, acc, grad_X, h);
+}
 
 }  // namespace
 
@@ -1345,10 +1550,33 @@ hipError_t launch_exp_partitioned(const DevMesh& M, const ExpArgs& a, void* ws, 
     return hipGetLastError();
 }
 
-size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip) {
-    if (mode == 0 && !has_flip) return 0;
-    const size_t per = mode == 0 ? 1 : 7;
-    return (size_t)n * per * sizeof(StateRec) + 512;
+// Backward workspace, carved in this order (each part 256-byte aligned):
+// base-walk states (1 or 4 per query), GFD second-pass states (3 per query),
+// grad-X walk states and adjoint coefficients, grad-X half-edge sums, counter.
+struct BwdLayout {
+    size_t s1, s2, s3, cvec, acc, counter, total;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static BwdLayout bwd_layout(int64_t n, int32_t mode, bool has_flip, bool vjp, bool gradx, int64_t n_faces) {
+    const bool gfd = vjp && mode == 1;
+    const bool walk = gradx || gfd || (vjp && has_flip);
+    const size_t per1 = gfd ? 4 : 1;
+    BwdLayout L{};
+    size_t o = 0;
+    L.s1 = o; o = align256(o + (walk ? per1 * (size_t)n * sizeof(StateRec) : 0));
+    L.s2 = o; o = align256(o + (gfd ? 3 * (size_t)n * sizeof(StateRec) : 0));
+    L.s3 = o; o = align256(o + (gradx ? (size_t)n * sizeof(StateRec) : 0));
+    L.cvec = o; o = align256(o + (gradx ? (size_t)n * sizeof(float4) : 0));
+    L.acc = o; o = align256(o + (gradx ? 15 * (size_t)n_faces * sizeof(double) : 0));
+    L.counter = o; o = align256(o + sizeof(unsigned long long));
+    L.total = (walk || gradx) ? o : 0;
+    return L;
+}
+
+size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip, bool vjp, bool gradx, int64_t n_faces) {
+    return bwd_layout(n, mode, has_flip, vjp, gradx, n_faces).total;
 }
 
 hipError_t launch_backward(const DevMesh& M, const BwdArgs& a, void* ws, int grid_blocks, int refill_min,
@@ -1356,27 +1584,51 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a, void* ws, int gri
     if (a.n <= 0) return hipSuccess;
     const int block = 256;
     const int64_t grid = (a.n + block - 1) / block;
-    if (a.mode == 0 && !M.has_flip) {
-        hipLaunchKernelGGL(k_ep_saved, dim3((unsigned)grid), dim3(block), 0, s, M, a);
-        return hipGetLastError();
-    }
-    const int per1 = a.mode == 0 ? 1 : 4;
-    auto* s1 = reinterpret_cast<StateRec*>(ws);
-    auto* s2 = s1 + (int64_t)per1 * a.n;
-    auto* counter = reinterpret_cast<unsigned long long*>(s2 + (a.mode == 0 ? 0 : 3 * a.n));
+    const bool vjp = a.grad_v != nullptr;
+    const bool gfd = vjp && a.mode == 1;
+    const bool gradx = a.grad_X != nullptr;
+    const bool flip = M.has_flip != 0;
+    if (vjp && a.mode == 0 && !flip) hipLaunchKernelGGL(k_ep_saved, dim3((unsigned)grid), dim3(block), 0, s, M, a);
+    if (!(gradx || gfd || (vjp && flip))) return hipGetLastError();
+    const BwdLayout L = bwd_layout(a.n, a.mode, flip, vjp, gradx, M.n_faces);
+    char* base = reinterpret_cast<char*>(ws);
+    auto* s1 = reinterpret_cast<StateRec*>(base + L.s1);
+    auto* s2 = reinterpret_cast<StateRec*>(base + L.s2);
+    auto* s3 = reinterpret_cast<StateRec*>(base + L.s3);
+    auto* cvec = reinterpret_cast<float4*>(base + L.cvec);
+    auto* acc = reinterpret_cast<double*>(base + L.acc);
+    auto* counter = reinterpret_cast<unsigned long long*>(base + L.counter);
+    const int per1 = gfd ? 4 : 1;
+    // base walk (and, for GFD, the three perturbed walks that start at p)
     hipLaunchKernelGGL(k_bwd_stage1, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
-    SG_DISPATCH(k_walk, false, M.has_flip != 0, dim3((unsigned)grid_blocks), dim3(block), s, M, s1,
-                (int64_t)per1 * a.n, counter, a.max_steps, a.snap, refill_min);
-    if (a.mode == 0) {
-        hipLaunchKernelGGL(k_ep_walked, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1);
-        return hipGetLastError();
+    SG_DISPATCH(k_walk, false, flip, dim3((unsigned)grid_blocks), dim3(block), s, M, s1, (int64_t)per1 * a.n, counter,
+                a.max_steps, a.snap, refill_min);
+    if (vjp && a.mode == 0)
+        hipLaunchKernelGGL(k_ep_walked, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
+    if (gfd) {
+        hipLaunchKernelGGL(k_bwd_stage2, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
+        SG_DISPATCH(k_walk, false, flip, dim3((unsigned)grid_blocks), dim3(block), s, M, s2, 3 * a.n, counter,
+                    a.max_steps, a.snap, refill_min);
+        hipLaunchKernelGGL(k_gfd_assemble, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
     }
-    hipLaunchKernelGGL(k_bwd_stage2, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
-    SG_DISPATCH(k_walk, false, M.has_flip != 0, dim3((unsigned)grid_blocks), dim3(block), s, M, s2, 3 * a.n,
-                counter, a.max_steps, a.snap, refill_min);
-    hipLaunchKernelGGL(k_gfd_assemble, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
+    if (gradx) {
+        const int64_t nacc = 15 * M.n_faces;
+        hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)std::min<int64_t>((nacc + block - 1) / block, 8192)), dim3(block),
+                           0, s, acc, nacc);
+        hipLaunchKernelGGL(k_gradx_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1, s3, cvec);
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
+        if (flip)
+            k_walk_gx<true><<<dim3((unsigned)grid_blocks), dim3(block), 0, s>>>(M, s3, a.n, counter, a.max_steps, a.snap,
+                                                                                refill_min, cvec, acc);
+        else
+            k_walk_gx<false><<<dim3((unsigned)grid_blocks), dim3(block), 0, s>>>(M, s3, a.n, counter, a.max_steps,
+                                                                                 a.snap, refill_min, cvec, acc);
+        const int64_t nh = 3 * M.n_faces;
+        hipLaunchKernelGGL(k_gradx_edges, dim3((unsigned)((nh + block - 1) / block)), dim3(block), 0, s, M, acc,
+                           a.grad_X);
+    }
     return hipGetLastError();
 }
 

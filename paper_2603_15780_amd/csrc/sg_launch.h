@@ -43,6 +43,7 @@ struct BwdArgs {
     float eps_v, eps_p;
     int32_t max_steps;
     float snap;
+    double* grad_X;         // [n_verts, 3] accumulated vertex-position gradient, or null
 };
 
 // Host-side result of packing a mesh (float64 work, rounded once).
@@ -54,6 +55,7 @@ struct PackedMesh {
     int64_t part_start[kParts + 1];   // internal face ranges of the XCD parts
     std::vector<float> X;
     std::vector<int64_t> half;
+    std::vector<int32_t> twin;        // half-edge across each edge (internal ids), -1 on the boundary
     int64_t n_verts = 0, n_faces = 0;
     double mean_edge = 0.0;
     int32_t has_flip = 0;
@@ -76,7 +78,7 @@ int walk_blocks_per_cu();
 int part_blocks_per_cu();
 
 // Backward of the exponential map (extrinsic proxy or geodesic finite differences).
-size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip);
+size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip, bool vjp, bool gradx, int64_t n_faces);
 hipError_t launch_backward(const DevMesh& M, const BwdArgs& a, void* ws, int grid_blocks, int refill_min,
                            hipStream_t s);
 

@@ -57,7 +57,7 @@ def lib():
         L.sg_exp.restype = C.c_int
         L.sg_exp_transport.argtypes = [P, I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, C.POINTER(Opts), P]
         L.sg_exp_transport.restype = C.c_int
-        L.sg_exp_backward.argtypes = [P, I32, I64, P, P, P, P, P, P, P, P, C.POINTER(Opts), P]
+        L.sg_exp_backward.argtypes = [P, I32, I64, P, P, P, P, P, P, P, P, P, C.POINTER(Opts), P]
         L.sg_exp_backward.restype = C.c_int
         L.sg_mesh_walk_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.sg_mesh_walk_time.restype = C.c_int
@@ -168,18 +168,27 @@ class Mesh:
         _check(rc)
         return out
 
-    def backward(self, mode, f, b, v, g, *, f_out=None, v_out=None, out=None, o: Opts | None = None, **kw):
-        """(grad_v, grad_b) for upstream g = dL/dp' [n,3]; mode BWD_EP or BWD_GFD."""
+    def backward(self, mode, f, b, v, g, *, f_out=None, v_out=None, out=None, grad_X=None, want_vjp=True,
+                 o: Opts | None = None, **kw):
+        """(grad_v, grad_b) for upstream g = dL/dp' [n,3]; mode BWD_EP or BWD_GFD.
+
+        grad_X: a float64 [n_verts, 3] tensor to accumulate dL/dX into (or None).
+        want_vjp=False skips grad_v / grad_b (returns (None, None)).
+        """
         import torch
         n = f.shape[0]
         dev = f.device
         assert f.dtype == torch.int32 and b.dtype == torch.float32 and v.dtype == torch.float32
         assert g.dtype == torch.float32 and g.is_contiguous() and g.shape == (n, 3)
         assert f.is_contiguous() and b.is_contiguous() and v.is_contiguous()
+        if grad_X is not None:
+            assert grad_X.dtype == torch.float64 and grad_X.is_contiguous() and grad_X.shape == (self.n_verts, 3)
         if o is None:
             o = opts(**kw)
-        if out is None:
+        if not want_vjp:
+            out = (None, None)
+        elif out is None:
             out = (torch.empty(n, 3, dtype=torch.float32, device=dev), torch.empty(n, 3, dtype=torch.float32, device=dev))
         _check(lib().sg_exp_backward(self._h, int(mode), n, _dptr(f), _dptr(b), _dptr(v), _dptr(f_out), _dptr(v_out),
-                                     _dptr(g), _dptr(out[0]), _dptr(out[1]), C.byref(o), _stream()))
+                                     _dptr(g), _dptr(out[0]), _dptr(out[1]), _dptr(grad_X), C.byref(o), _stream()))
         return out

@@ -99,3 +99,19 @@ def grad_report(o_exp, og_v, og_b, gg_v, gg_b, me, margin=2e-2, tol=1e-3):
                 b_ok=float(np.mean(eb[m] <= tol)) if m.any() else 1.0, v_med=float(np.median(ev)),
                 b_med=float(np.median(eb)), v_all_ok=float(np.mean(ev <= tol)), finite=bool(
                     np.isfinite(gg_v).all() and np.isfinite(gg_b).all()))
+
+
+def gradx_report(ref, got, floor=0.1, tol=1e-3):
+    """Vertex-gradient parity: per-vertex error against max(|ref_v|, floor * rms)
+    (each vertex sums float32 per-crossing terms of size ~ |v| |g| / edge that
+    largely cancel between neighbouring hinges, so a vertex whose gradient
+    cancels to near zero is judged against the field's scale) and the global
+    relative error."""
+    nrm = np.linalg.norm(ref, axis=1)
+    err = np.linalg.norm(got - ref, axis=1)
+    nz = nrm > 0
+    rms = float(np.sqrt((nrm[nz] ** 2).mean())) if nz.any() else 0.0
+    rel = err / np.maximum(nrm, max(floor * rms, 1e-300))
+    return dict(n_verts=int(nz.sum()), rms=rms, global_rel=float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)),
+                frac_ok=float(np.mean(rel[nz] <= tol)) if nz.any() else 1.0, max_rel=float(rel.max()),
+                finite=bool(np.isfinite(got).all()))

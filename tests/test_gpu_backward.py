@@ -175,3 +175,108 @@ def test_deterministic_and_schedules(torch):
     for kw in ({}, dict(refill_min=1), dict(refill_min=64), dict(walk_blocks=7), dict(walk_blocks=3000, refill_min=32)):
         out = gpu_bwd(torch, gm, sg.BWD_GFD, r, g, **kw)
         assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), kw
+
+
+# ---------------------------------------------------------------- vertex-position gradient
+def margin_mask(om, r, margin=1e-2):
+    o = om.exp(r["f"], r["b"], r["v"])
+    return (o["min_vdist"] > margin * om.mean_edge) & (o["status"] == 0)
+
+
+def gpu_gradx(torch, gm, r, g, mode=0, want_vjp=False, **kw):
+    from paper_2603_15780_amd import sg
+    t = dev_inputs(torch, r, g)
+    gX = torch.zeros(gm.n_verts, 3, dtype=torch.float64, device=t["f"].device)
+    fo = vo = None
+    if want_vjp and mode == sg.BWD_EP:
+        out = gm.exp(t["f"], t["b"], t["v"])
+        fo, vo = out["f"], out["v"]
+    res = gm.backward(mode, t["f"], t["b"], t["v"], t["g"], f_out=fo, v_out=vo, grad_X=gX, want_vjp=want_vjp, **kw)
+    torch.cuda.synchronize()
+    return gX.cpu().numpy(), res
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_gradx_config1(torch, mixed):
+    from paper_2603_15780_amd import sg
+    from parity import gradx_report
+    X, F = CF.mesh_config(1)
+    if mixed:
+        F = F.copy()
+        flip = np.random.default_rng(5).random(F.shape[0]) < 0.3
+        F[flip] = F[flip][:, ::-1]
+    r = CF.rays_config(1, X, F)
+    g = CF.upstream_grad(1, r["f"].shape[0])
+    om = oracle.Mesh(X, F)
+    keep = margin_mask(om, r)
+    g[~keep] = 0.0
+    ref, nvx = om.gradx(r["f"], r["b"], r["v"], g)
+    assert np.all(nvx[keep] == 0)
+    gm = sg.Mesh(X, F)
+    got, _ = gpu_gradx(torch, gm, r, g)
+    s = gradx_report(ref, got)
+    print(s)
+    assert s["finite"] and s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, s
+    # the same sums come out of the combined calls (base walk shared with EP / GFD)
+    for mode in (sg.BWD_EP, sg.BWD_GFD):
+        got2, (gv, gb) = gpu_gradx(torch, gm, r, g, mode=mode, want_vjp=True)
+        assert gradx_report(ref, got2)["global_rel"] < 1e-4
+        assert np.allclose(got2, got, rtol=1e-9, atol=1e-9 * np.abs(got).max())
+        assert np.isfinite(gv.cpu().numpy()[keep]).all()
+
+
+def test_gradx_config2_full_batch(torch):
+    """All 1,048,576 rays on the 327,680-face mesh.  (1) Upstream g on every
+    margin ray: translating the mesh translates each p', so the vertex
+    gradients sum to sum g.  (2) g on 4,096 sampled margin rays only: the
+    gradient field is compared with the oracle's on those rays."""
+    from paper_2603_15780_amd import sg
+    from parity import gradx_report
+    X, F = CF.mesh_config(2)
+    r = CF.rays_config(2, X, F)
+    n = r["f"].shape[0]
+    g = CF.upstream_grad(2, n)
+    om = oracle.Mesh(X, F)
+    keep = margin_mask(om, r)
+    g[~keep] = 0.0
+    gm = sg.Mesh(X, F)
+    got, _ = gpu_gradx(torch, gm, r, g)
+    assert np.isfinite(got).all()
+    tot = got.sum(0)
+    assert np.allclose(tot, g.astype(np.float64).sum(0), rtol=1e-5, atol=1e-5 * np.abs(g).sum() / np.sqrt(n)), tot
+    idx = np.flatnonzero(keep)[:: max(1, keep.sum() // 4096)][:4096]
+    gs = np.zeros_like(g)
+    gs[idx] = g[idx]
+    got_s, _ = gpu_gradx(torch, gm, r, gs)
+    sub = {k: r[k][idx] for k in ("f", "b", "v")}
+    ref, _ = om.gradx(sub["f"], sub["b"], sub["v"], g[idx])
+    s = gradx_report(ref, got_s)
+    print(s)
+    assert s["finite"] and s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, s
+
+
+def test_gradx_zero_length_and_torus(torch):
+    from paper_2603_15780_amd import sg
+    from parity import gradx_report
+    rng = np.random.default_rng(21)
+    X, F = CF.mesh_config(1)
+    r = random_rays(X, F, 2048, rng, uniform_len(0.0, 0.0))
+    g = rng.standard_normal((2048, 3)).astype(np.float32)
+    om = oracle.Mesh(X, F)
+    keep = margin_mask(om, r)
+    g[~keep] = 0.0
+    ref, _ = om.gradx(r["f"], r["b"], r["v"], g)
+    got, _ = gpu_gradx(torch, sg.Mesh(X, F), r, g)
+    s = gradx_report(ref, got)
+    assert s["global_rel"] < 1e-5 and s["frac_ok"] >= 0.999, s
+    X, F = M.torus_grid(60, 20, 0.2, rng)
+    r = random_rays(X, F, 4096, rng, uniform_len(0.0, 1.5))
+    g = rng.standard_normal((4096, 3)).astype(np.float32)
+    om = oracle.Mesh(X, F)
+    keep = margin_mask(om, r)
+    g[~keep] = 0.0
+    ref, _ = om.gradx(r["f"], r["b"], r["v"], g)
+    got, _ = gpu_gradx(torch, sg.Mesh(X, F), r, g)
+    s = gradx_report(ref, got)
+    print(s)
+    assert s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, s
