@@ -1,18 +1,23 @@
 """Benchmark of the batched exponential map on one MI355X.
 
-Workload (default): 1,048,576 rays on the 327,680-face SH-displaced
-icosphere (level 7, l <= 8, amplitude 0.1), |v| ~ U[0, pi/2], two extra
-vectors transported (K = 2).  Inputs are synthetic and resident in HBM
-before timing.  A step is one sg_exp_transport call over the whole batch.
+Workload (default, --config 2): 1,048,576 rays on the 327,680-face
+SH-displaced icosphere (level 7, l <= 8, amplitude 0.1), |v| ~ U[0, pi/2],
+two extra vectors transported (K = 2).  --config 3: 64 meshes of uneven size
+(displaced spheres and jittered tori, 6.8M faces in all) and 5.6M rays of
+uneven length in one persistent call.  Inputs are synthetic and resident in
+HBM before timing.  A step is one sg_exp_transport call over the whole batch,
+with the schedule the library's autotuner picks for this batch (untimed).
 
-The forward + backward forms (extrinsic proxy from the saved outputs, and
-geodesic finite differences, which re-walk seven geodesics per query) are
-timed on the same batch and reported beside it.
+The forward + backward forms (extrinsic proxy from the saved outputs;
+geodesic finite differences, which re-walk seven geodesics per query; each
+with and without the float64 vertex-position gradient, which re-walks twice)
+are timed on the same batch and reported beside it.
 
 Prints one JSON line.  `value` is face-crossings per second (the crossing
-count is the float64 oracle's, computed on the same batch in the CPU-baseline
-leg).  The roofline object prices the walk kernel against HBM bandwidth with
-16 algorithmic bytes per crossing plus 144 + 24 K bytes per query.
+count is the float64 oracle's when the CPU-baseline leg traces the whole
+batch, else the GPU's).  The roofline object prices the walk kernel against
+HBM bandwidth with 16 algorithmic bytes per crossing plus 64 bytes per ray
+(its 32-byte state in and out).
 """
 from __future__ import annotations
 
@@ -30,6 +35,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CROSSING = 16
 METRIC = "face-crossings/s & queries/s, fwd and fwd+bwd, 327k-face mesh, 1M rays"
+WORKLOADS = {
+    1: "icosphere level 3 (1,280 faces); 8,192 rays, |v|~U[0,pi/2], K=1; forward",
+    2: ("icosphere level 7, SH-displaced (l<=8, amp 0.1), 327,680 faces; 1,048,576 rays, |v|~U[0,pi/2], "
+        "K=2 transported; forward (fwd+bwd forms in fwd_bwd)"),
+    3: ("64 meshes (displaced geodesic spheres and 3:1 jittered tori, faces log-U[5k,500k]) in one handle; "
+        "rays per mesh log-U[16k,256k], |v| log-U[0.01,1] x diameter, K=0; one persistent forward call"),
+}
 
 
 def log(*a):
@@ -41,14 +53,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2])
-    ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 plain, 2 persistent")
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--kernel", type=int, default=0, help="0 autotuned, 1 plain, 2 persistent, 3 partitioned")
+    ap.add_argument("--no-autotune", action="store_true", help="library defaults instead of the autotuner's pick")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=0, help="oracle sample size (0: whole batch)")
+    ap.add_argument("--cpu-rays", type=int, default=0, help="oracle sample size (0: whole batch, or 1/4 for config 3)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain kernel for comparison")
+    ap.add_argument("--no-bwd", action="store_true", help="skip timing the backward forms")
     ap.add_argument("--refill", type=int, default=0, help="persistent kernel refill threshold (0: library default)")
     ap.add_argument("--walk-blocks", type=int, default=0, help="persistent kernel blocks (0: fill the GPU)")
-    ap.add_argument("--no-bwd", action="store_true", help="skip timing the backward (EP and GFD)")
     ap.add_argument("--calib-copy", type=int, default=0, help="MiB copied once to calibrate byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -61,24 +74,48 @@ def main():
     from workloads import configs as CF
 
     t0 = time.time()
-    X, F = CF.mesh_config(args.config)
-    r = CF.rays_config(args.config, X, F)
+    if args.config == 3:
+        B = CF.config3_batch(64)
+        X, F_or, r = B["X"], B["F_global"], B["rays"]
+        mesh_args = (B["X"], B["F_local"], B["vert_offsets"], B["face_offsets"])
+    else:
+        X, F_or = CF.mesh_config(args.config)
+        r = CF.rays_config(args.config, X, F_or)
+        mesh_args = (X, F_or)
     n = r["f"].shape[0]
     K = r["W"].shape[1]
-    log(f"workload ready in {time.time() - t0:.1f}s: {F.shape[0]} faces, {n} rays, K={K}")
+    log(f"workload ready in {time.time() - t0:.1f}s: {F_or.shape[0]} faces, {n} rays, K={K}")
     dev = torch.device("cuda:0")
-    mesh = sg.Mesh(X, F)
+    t1 = time.time()
+    mesh = sg.Mesh(*mesh_args)
+    pack_s = time.time() - t1
     info = mesh.info()
-    t = {k: torch.from_numpy(np.ascontiguousarray(r[k])).to(dev) for k in ("f", "b", "v", "W")}
+    log(f"mesh packed in {pack_s:.2f}s ({info['device_bytes'] / 2**20:.1f} MiB on the device)")
+    t = {k: torch.from_numpy(np.ascontiguousarray(r[k])).to(dev) for k in ("f", "b", "v")}
+    t["W"] = torch.from_numpy(np.ascontiguousarray(r["W"])).to(dev) if K else None
     out = dict(
         f=torch.empty(n, dtype=torch.int32, device=dev), b=torch.empty(n, 3, device=dev),
         p=torch.empty(n, 3, device=dev), v=torch.empty(n, 3, device=dev),
-        W=torch.empty(n, K, 3, device=dev), status=torch.empty(n, dtype=torch.int32, device=dev),
+        W=torch.empty(n, K, 3, device=dev) if K else None, status=torch.empty(n, dtype=torch.int32, device=dev),
         n_cross=torch.empty(n, dtype=torch.int32, device=dev), hash=None)
-    def timed(kernel, steps, warmup):
+
+    base = sg.opts(kernel=args.kernel, refill_min=args.refill, walk_blocks=args.walk_blocks)
+    tuned = None
+    if args.kernel == 0 and not args.no_autotune:
+        t1 = time.time()
+        base, tune_ms = mesh.autotune(t["f"], t["b"], t["v"], t["W"], o=base)
+        tuned = {"kernel": ["auto", "plain", "persistent", "partitioned"][base.kernel], "refill_min": base.refill_min,
+                 "walk_blocks": base.walk_blocks, "tuned_ms": tune_ms, "tuning_s": time.time() - t1}
+        log(f"autotuner: {tuned}")
+
+    def opts_for(kernel=None, debug=0):
+        o = sg.opts(kernel=base.kernel if kernel is None else kernel, refill_min=base.refill_min,
+                    walk_blocks=base.walk_blocks)
+        o.debug = debug
+        return o
+
+    def timed(o, steps, warmup):
         """(wall ms per call, event ms per call, walk-kernel event ms per launch or None)."""
-        o = sg.opts(kernel=kernel, debug=1 | (4 if kernel != 1 else 0), refill_min=args.refill,
-                    walk_blocks=args.walk_blocks)
         for _ in range(warmup):
             mesh.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=o)
         torch.cuda.synchronize()
@@ -95,32 +132,43 @@ def main():
         wms, wn = mesh.walk_time()
         return (w1 - w0) * 1e3 / steps, ev0.elapsed_time(ev1) / steps, (wms / wn if wn else None)
 
-    ms_step, ms_call, ms_walk = timed(args.kernel, args.steps, args.warmup)
+    main_o = opts_for(debug=1 | (4 if base.kernel != sg.KERNEL_PLAIN else 0))
+    ms_step, ms_call, ms_walk = timed(main_o, args.steps, args.warmup)
     # dominant kernel: the persistent walk (events the library records around it), or the plain kernel
     ms_kernel = ms_walk if ms_walk is not None else ms_call
     gpu_cross = int(out["n_cross"].sum().item())
     n_ok = int((out["status"] == 0).sum().item())
-    log(f"timed {args.steps} steps (kernel {args.kernel}): {ms_step:.3f} ms/step (events {ms_kernel:.3f} ms), "
-        f"GPU crossings {gpu_cross}, status ok {n_ok}/{n}")
+    log(f"timed {args.steps} steps ({tuned or 'kernel %d' % base.kernel}): {ms_step:.3f} ms/step "
+        f"(events {ms_kernel:.3f} ms), GPU crossings {gpu_cross}, status ok {n_ok}/{n}")
     plain = None
-    if args.kernel != 1 and not args.no_plain:
-        ms_p, ms_pk, _ = timed(1, max(3, args.steps // 4), 1)
+    if base.kernel != sg.KERNEL_PLAIN and not args.no_plain:
+        ms_p, ms_pk, _ = timed(opts_for(kernel=sg.KERNEL_PLAIN, debug=1), max(3, args.steps // 4), 1)
         plain = {"ms_per_call": ms_p, "events_ms": ms_pk}
         log(f"plain one-ray-per-lane kernel: {ms_p:.3f} ms/call")
+
     bwd = None
-    if not args.no_bwd:
+    if not args.no_bwd and args.config != 3:
         # forward + backward on the same batch: the forward's saved outputs feed the extrinsic
         # proxy; geodesic finite differences re-walk seven geodesics per query (recompute, no paths)
         g_up = torch.from_numpy(CF.upstream_grad(args.config, n)).to(dev)
         gv = torch.empty(n, 3, device=dev)
         gb = torch.empty(n, 3, device=dev)
+        gX = torch.zeros(X.shape[0], 3, dtype=torch.float64, device=dev)
         bwd = {}
-        fo = sg.opts(kernel=args.kernel, refill_min=args.refill, walk_blocks=args.walk_blocks)
-        for name, mode in (("ep", sg.BWD_EP), ("gfd", sg.BWD_GFD)):
+        fo = opts_for()
+        persistent = base.kernel == sg.KERNEL_PERSISTENT
+        bo = sg.opts(refill_min=base.refill_min if persistent else 0, walk_blocks=base.walk_blocks if persistent else 0)
+        forms = (("ep", sg.BWD_EP, False), ("gfd", sg.BWD_GFD, False), ("ep+gradX", sg.BWD_EP, True),
+                 ("gfd+gradX", sg.BWD_GFD, True))
+        for name, mode, with_x in forms:
             steps = max(3, args.steps // 2)
+
             def call():
                 mesh.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=fo)
-                mesh.backward(mode, t["f"], t["b"], t["v"], g_up, f_out=out["f"], v_out=out["v"], out=(gv, gb), o=fo)
+                if with_x:
+                    gX.zero_()
+                mesh.backward(mode, t["f"], t["b"], t["v"], g_up, f_out=out["f"], v_out=out["v"], out=(gv, gb),
+                              grad_X=gX if with_x else None, o=bo)
             for _ in range(max(1, args.warmup)):
                 call()
             torch.cuda.synchronize()
@@ -130,7 +178,7 @@ def main():
             torch.cuda.synchronize()
             ms = (time.perf_counter() - w0) * 1e3 / steps
             bwd[name] = {"ms_fwd_plus_bwd": ms, "ms_bwd": ms - ms_step, "queries_per_s": n / (ms * 1e-3),
-                         "finite": bool(torch.isfinite(gv).all().item())}
+                         "finite": bool(torch.isfinite(gv).all().item()) and bool(torch.isfinite(gX).all().item())}
             log(f"forward + {name} backward: {ms:.3f} ms/step ({n / (ms * 1e-3):.3e} queries/s)")
     if args.calib_copy:
         # a plain copy of known size, profiled beside the walk to scale the HBM byte counters
@@ -141,28 +189,31 @@ def main():
         log(f"calibration copy: {args.calib_copy} MiB read + {args.calib_copy} MiB written")
 
     cross = gpu_cross
+    cross_src = "gpu"
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        nc = args.cpu_rays or n
-        om = oracle.Mesh(X, F)
+        nc = args.cpu_rays or (n if args.config != 3 else n // 4)
+        rows = np.arange(n) if nc >= n else np.linspace(0, n - 1, nc).astype(np.int64)
+        om = oracle.Mesh(X, F_or)
         # the machine's CPU share is given by OMP_NUM_THREADS when set
         cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
         c0 = time.perf_counter()
-        oo = om.exp(r["f"][:nc], r["b"][:nc], r["v"][:nc], r["W"][:nc], nthreads=cores)
+        oo = om.exp(r["f"][rows], r["b"][rows], r["v"][rows], r["W"][rows] if K else None, nthreads=cores)
         c1 = time.perf_counter()
         ocross = int(oo["n_cross"].sum())
-        if nc == n:
-            cross = ocross
+        if rows.shape[0] == n:
+            cross, cross_src = ocross, "oracle"
         cpu = {"value": ocross / (c1 - c0), "unit": "face-crossings/s", "cores": cores, "kind": "oracle",
-               "sample": f"{nc} of the {n} rays (K={K}), float64 C oracle, {cores} threads, {c1 - c0:.2f} s",
-               "queries_per_s": nc / (c1 - c0)}
+               "sample": f"{rows.shape[0]} of the {n} rays (K={K}), float64 C oracle, {cores} threads, "
+                         f"{c1 - c0:.2f} s",
+               "queries_per_s": rows.shape[0] / (c1 - c0)}
         log(f"oracle: {ocross} crossings in {c1 - c0:.2f}s on {cores} threads; GPU/oracle crossing ratio "
-            f"{gpu_cross / max(ocross, 1) if nc == n else float('nan'):.6f}")
-
+            f"{gpu_cross / max(ocross, 1) if rows.shape[0] == n else float('nan'):.6f}")
     if bwd:
         for b in bwd.values():   # forward-path crossings per second of the whole fwd + bwd step
             b["crossings_per_s"] = cross / (b["ms_fwd_plus_bwd"] * 1e-3)
+
     # algorithmic bytes: 16 per crossing (next face's shape in the crossed edge's frame and its two
     # onward links); per ray the walk kernel reads and writes a 32-byte chart state, while the whole
     # forward call reads the query and writes the answer (144 + 24 K bytes)
@@ -184,16 +235,14 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": ("icosphere level 7, SH-displaced (l<=8, amp 0.1), 327,680 faces; 1,048,576 rays, "
-                         "|v|~U[0,pi/2], K=2 transported; forward only" if args.config == 2 else
-                         "icosphere level 3 (1,280 faces); 8,192 rays, |v|~U[0,pi/2], K=1; forward only"),
-            "faces": int(F.shape[0]), "rays": n, "K": K, "crossings": cross,
-            "kernel": ["persistent (auto)", "plain", "persistent"][args.kernel],
+            "workload": WORKLOADS[args.config],
+            "faces": int(F_or.shape[0]), "rays": n, "K": K, "crossings": cross, "crossings_from": cross_src,
+            "schedule": tuned or {"kernel": ["default", "plain", "persistent", "partitioned"][args.kernel]},
         },
         "plain_kernel": plain,
-        "fwd_bwd": bwd,
         "speedup_over_plain": (plain["ms_per_call"] / ms_step) if plain else None,
         "queries_per_s": n / (ms_step * 1e-3),
+        "fwd_bwd": bwd,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_walk (persistent walk)" if ms_walk is not None else "k_exp_plain",
@@ -202,6 +251,7 @@ def main():
                                     "achieved_GBs": call_bytes / (ms_call * 1e-3) / 1e9}},
         "cpu_baseline": cpu,
         "mesh_device_bytes": info["device_bytes"],
+        "mesh_pack_s": pack_s,
     }
     print(json.dumps(res), flush=True)
 

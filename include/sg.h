@@ -78,6 +78,12 @@ typedef struct {
     int32_t refill_min;    /* persistent kernel: a wave refetches rays once this many of its 64 lanes are
                               idle; <= 0: tuned default */
     int32_t walk_blocks;   /* persistent kernel: 256-lane blocks launched; <= 0: fill every CU */
+    void* workspace;       /* optional caller-owned device workspace, 256-byte aligned, at least the size
+                              sg_exp_workspace_size / sg_backward_workspace_size report.  With it a call
+                              allocates nothing, so it can be captured in a HIP graph (debug bit 2 aside).
+                              Calls sharing one workspace must be ordered (same stream).  NULL: the call
+                              takes a stream-ordered allocation (hipMallocAsync) and releases it. */
+    uint64_t workspace_bytes;
 } sg_opts;
 
 /* Fills *o with the defaults above. */
@@ -173,6 +179,31 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
 int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b, const float* v,
                     const int32_t* f_out, const float* v_out, const float* g_p,
                     float* grad_v, float* grad_b, double* grad_X, const sg_opts* opts, void* stream);
+
+/*
+ * Device workspace (bytes, host output) that sg_exp / sg_exp_transport need
+ * for n queries with these options (kernel and debug bits matter), and that
+ * sg_exp_backward needs for n queries in `mode` with grad_v/grad_b
+ * (want_vjp != 0) and/or grad_X (want_grad_X != 0).  0 means none.
+ */
+int sg_exp_workspace_size(sg_mesh mesh, int64_t n, const sg_opts* opts, size_t* bytes);
+int sg_backward_workspace_size(sg_mesh mesh, int32_t mode, int64_t n, int32_t want_vjp, int32_t want_grad_X,
+                               const sg_opts* opts, size_t* bytes);
+
+/*
+ * Autotuner for the forward walk (Sec. 4 "Parallelisation on the GPU"
+ * schedules one ray per thread; this picks the schedule that runs the
+ * caller's batch fastest).  Times sg_exp_transport on the given queries
+ * (device arrays as in sg_exp_transport; a representative sample is enough)
+ * for the plain kernel and for the persistent kernel over refill thresholds
+ * (the compaction period) and resident blocks per CU (waves per SIMD), then
+ * writes the fastest kernel, refill_min and walk_blocks into *opts (its other
+ * fields are kept and used).  Synchronizes `stream`; allocates and frees
+ * its own scratch outputs.  Not capturable.  *best_ms (nullable) receives
+ * the winner's time per call.
+ */
+int sg_autotune(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v, int32_t K,
+                const float* W, sg_opts* opts, double* best_ms, void* stream);
 
 /*
  * Walk-kernel timing (profiling aid).  Calls made with opts->debug bit 2

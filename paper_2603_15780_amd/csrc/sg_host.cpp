@@ -147,6 +147,41 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     return SG_OK;
 }
 
+// Workspace of a call: the caller's (checked) or a stream-ordered allocation.
+struct Workspace {
+    void* p = nullptr;
+    bool own = false;
+};
+
+int take_workspace(const sg_opts& o, size_t need, hipStream_t st, Workspace& w) {
+    w = Workspace{};
+    if (need == 0) return SG_OK;
+    if (o.workspace) {
+        if (o.workspace_bytes < need)
+            return fail(SG_E_ARG, "workspace too small: %llu bytes given, %llu needed",
+                        (unsigned long long)o.workspace_bytes, (unsigned long long)need);
+        if (reinterpret_cast<uintptr_t>(o.workspace) & 255u) return fail(SG_E_ARG, "workspace must be 256-byte aligned");
+        w.p = o.workspace;
+        return SG_OK;
+    }
+    hipError_t e = hipMallocAsync(&w.p, need, st);
+    if (e != hipSuccess) return fail(SG_E_OOM, "workspace allocation: %s", hipGetErrorString(e));
+    w.own = true;
+    return SG_OK;
+}
+
+hipError_t give_workspace(Workspace& w, hipStream_t st) {
+    hipError_t e = w.own ? hipFreeAsync(w.p, st) : hipSuccess;
+    w = Workspace{};
+    return e;
+}
+
+size_t exp_workspace_bytes(const sg_opts& o, int64_t n) {
+    if (o.kernel == SG_KERNEL_PLAIN || n <= 0) return 0;
+    return o.kernel == SG_KERNEL_PARTITIONED ? sg::exp_partitioned_workspace(n, (o.debug & 2u) != 0u)
+                                             : sg::exp_persistent_workspace(n);
+}
+
 }  // namespace
 
 namespace sg {
@@ -375,6 +410,8 @@ void sg_opts_default(sg_opts* o) {
     o->debug = 0u;
     o->refill_min = 0;
     o->walk_blocks = 0;
+    o->workspace = nullptr;
+    o->workspace_bytes = 0;
 }
 
 int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, int64_t n_faces,
@@ -475,26 +512,27 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
         if (e != hipSuccess) return hip_fail(e, "forward launch");
         return SG_OK;
     }
-    // persistent forms: per-ray chart states and queues live in a stream-ordered workspace
+    // persistent forms: per-ray chart states and queues live in a workspace
     const bool part = o.kernel == SG_KERNEL_PARTITIONED;
-    const size_t wsb = part ? sg::exp_partitioned_workspace(n, (o.debug & 2u) != 0u) : sg::exp_persistent_workspace(n);
-    void* ws = nullptr;
-    hipError_t e = hipMallocAsync(&ws, wsb, st);
-    if (e != hipSuccess) return fail(SG_E_OOM, "workspace allocation: %s", hipGetErrorString(e));
+    Workspace ws;
+    rc = take_workspace(o, exp_workspace_bytes(o, n), st, ws);
+    if (rc != SG_OK) return rc;
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     if (o.debug & 4u) {
         if (!mesh->spare.empty()) {
             ev = mesh->spare.back();
             mesh->spare.pop_back();
         } else if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
-            (void)hipFreeAsync(ws, st);
+            (void)give_workspace(ws, st);
             return fail(SG_E_HIP, "hipEventCreate failed");
         }
     }
-    e = part ? sg::launch_exp_partitioned(mesh->dev(), a, ws, o.walk_blocks, o.refill_min, st, ev.first, ev.second)
-             : sg::launch_exp_persistent(mesh->dev(), a, ws, o.walk_blocks, o.refill_min, st, ev.first, ev.second);
+    hipError_t e = part ? sg::launch_exp_partitioned(mesh->dev(), a, ws.p, o.walk_blocks, o.refill_min, st, ev.first,
+                                                     ev.second)
+                        : sg::launch_exp_persistent(mesh->dev(), a, ws.p, o.walk_blocks, o.refill_min, st, ev.first,
+                                                    ev.second);
     if (ev.first) mesh->timed.push_back(ev);
-    const hipError_t e2 = hipFreeAsync(ws, st);
+    const hipError_t e2 = give_workspace(ws, st);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     if (e2 != hipSuccess) return hip_fail(e2, "workspace release");
     return SG_OK;
@@ -530,16 +568,108 @@ int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, con
     a.max_steps = o.max_steps;
     a.snap = o.vertex_snap;
     const hipStream_t st = (hipStream_t)stream;
-    const size_t wsb = sg::bwd_workspace(n, mode, mesh->has_flip != 0, vjp, grad_X != nullptr, mesh->n_faces);
-    void* ws = nullptr;
-    if (wsb) {
-        hipError_t e = hipMallocAsync(&ws, wsb, st);
-        if (e != hipSuccess) return fail(SG_E_OOM, "workspace allocation: %s", hipGetErrorString(e));
-    }
-    hipError_t e = sg::launch_backward(mesh->dev(), a, ws, o.walk_blocks, o.refill_min, st);
-    const hipError_t e2 = ws ? hipFreeAsync(ws, st) : hipSuccess;
+    Workspace ws;
+    rc = take_workspace(o, sg::bwd_workspace(n, mode, mesh->has_flip != 0, vjp, grad_X != nullptr, mesh->n_faces), st,
+                        ws);
+    if (rc != SG_OK) return rc;
+    hipError_t e = sg::launch_backward(mesh->dev(), a, ws.p, o.walk_blocks, o.refill_min, st);
+    const hipError_t e2 = give_workspace(ws, st);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     if (e2 != hipSuccess) return hip_fail(e2, "workspace release");
+    return SG_OK;
+}
+
+int sg_exp_workspace_size(sg_mesh mesh, int64_t n, const sg_opts* opts, size_t* bytes) {
+    if (!mesh || !bytes) return fail(SG_E_ARG, "mesh and bytes are required");
+    if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
+    sg_opts o;
+    int rc = check_opts(opts, o, mesh);
+    if (rc != SG_OK) return rc;
+    *bytes = exp_workspace_bytes(o, n);
+    return SG_OK;
+}
+
+int sg_backward_workspace_size(sg_mesh mesh, int32_t mode, int64_t n, int32_t want_vjp, int32_t want_grad_X,
+                               const sg_opts* opts, size_t* bytes) {
+    if (!mesh || !bytes) return fail(SG_E_ARG, "mesh and bytes are required");
+    if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
+    if (mode != SG_BWD_EP && mode != SG_BWD_GFD) return fail(SG_E_ARG, "unknown backward mode %d", mode);
+    sg_opts o;
+    int rc = check_opts(opts, o, mesh);
+    if (rc != SG_OK) return rc;
+    *bytes = (n == 0 || (!want_vjp && !want_grad_X))
+                 ? 0
+                 : sg::bwd_workspace(n, mode, mesh->has_flip != 0, want_vjp != 0, want_grad_X != 0, mesh->n_faces);
+    return SG_OK;
+}
+
+int sg_autotune(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v, int32_t K, const float* W,
+                sg_opts* opts, double* best_ms, void* stream) {
+    if (!mesh || !opts) return fail(SG_E_ARG, "mesh and opts are required");
+    if (n <= 0 || !f || !b || !v) return fail(SG_E_ARG, "autotuning needs a non-empty batch");
+    if (K < 0 || K > 64 || (K > 0 && !W)) return fail(SG_E_ARG, "bad K or W");
+    sg_opts base;
+    int rc = check_opts(opts, base, mesh);
+    if (rc != SG_OK) return rc;
+    base.debug = 0u;
+    base.workspace = nullptr;
+    base.workspace_bytes = 0;
+    const hipStream_t st = (hipStream_t)stream;
+    // scratch outputs and events
+    void* buf = nullptr;
+    const size_t per = 4 + 3 * 12 + (size_t)K * 12 + 4;
+    if (hipMalloc(&buf, per * (size_t)n + 1024) != hipSuccess) return fail(SG_E_OOM, "autotune scratch allocation");
+    char* q = static_cast<char*>(buf);
+    auto carve = [&](size_t bytes) { char* r = q; q += (bytes + 255) & ~(size_t)255; return r; };
+    auto* fo = reinterpret_cast<int32_t*>(carve(4 * (size_t)n));
+    auto* bo = reinterpret_cast<float*>(carve(12 * (size_t)n));
+    auto* po = reinterpret_cast<float*>(carve(12 * (size_t)n));
+    auto* vo = reinterpret_cast<float*>(carve(12 * (size_t)n));
+    auto* Wo = K ? reinterpret_cast<float*>(carve(12 * (size_t)K * n)) : nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipFree(buf);
+        return fail(SG_E_HIP, "hipEventCreate failed");
+    }
+    struct Cand { int32_t kernel, refill, blocks; };
+    std::vector<Cand> cands;
+    cands.push_back({SG_KERNEL_PLAIN, base.refill_min, base.walk_blocks});
+    const int refills[] = {4, 8, 16, 24, 32, 48};
+    for (int bpc = 1; bpc <= mesh->walk_blocks_per_cu; ++bpc)
+        for (int r : refills) cands.push_back({SG_KERNEL_PERSISTENT, r, bpc * mesh->cu_count});
+    double best = 1e300;
+    Cand win = cands[1 < cands.size() ? 1 : 0];
+    rc = SG_OK;
+    for (const Cand& c : cands) {
+        sg_opts o = base;
+        o.kernel = c.kernel;
+        o.refill_min = c.refill;
+        o.walk_blocks = c.blocks;
+        double t = 1e300;
+        for (int rep = 0; rep < 4 && rc == SG_OK; ++rep) {
+            if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(SG_E_HIP, "hipEventRecord failed"); break; }
+            rc = sg_exp_transport(mesh, n, f, b, v, K, W, fo, bo, po, vo, Wo, nullptr, nullptr, nullptr, &o, stream);
+            if (rc != SG_OK) break;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(SG_E_HIP, "event synchronization failed");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) t = std::min(t, (double)ms);   // the first run warms caches
+        }
+        if (rc != SG_OK) break;
+        if (t < best) { best = t; win = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (rc != SG_OK) return rc;
+    opts->kernel = win.kernel;
+    opts->refill_min = win.refill;
+    opts->walk_blocks = win.blocks;
+    if (best_ms) *best_ms = best;
     return SG_OK;
 }
 

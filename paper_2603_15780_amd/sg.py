@@ -31,7 +31,8 @@ class SgError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("vertex_snap", C.c_float), ("eps_v", C.c_float),
                 ("eps_p", C.c_float), ("kernel", C.c_int32), ("debug", C.c_uint32),
-                ("refill_min", C.c_int32), ("walk_blocks", C.c_int32)]
+                ("refill_min", C.c_int32), ("walk_blocks", C.c_int32), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_uint64)]
 
 
 def lib_path() -> str:
@@ -59,6 +60,12 @@ def lib():
         L.sg_exp_transport.restype = C.c_int
         L.sg_exp_backward.argtypes = [P, I32, I64, P, P, P, P, P, P, P, P, P, C.POINTER(Opts), P]
         L.sg_exp_backward.restype = C.c_int
+        L.sg_exp_workspace_size.argtypes = [P, I64, C.POINTER(Opts), C.POINTER(C.c_size_t)]
+        L.sg_exp_workspace_size.restype = C.c_int
+        L.sg_backward_workspace_size.argtypes = [P, I32, I64, I32, I32, C.POINTER(Opts), C.POINTER(C.c_size_t)]
+        L.sg_backward_workspace_size.restype = C.c_int
+        L.sg_autotune.argtypes = [P, I64, P, P, P, I32, P, C.POINTER(Opts), C.POINTER(C.c_double), P]
+        L.sg_autotune.restype = C.c_int
         L.sg_mesh_walk_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.sg_mesh_walk_time.restype = C.c_int
         _lib = L
@@ -124,6 +131,28 @@ class Mesh:
         nb = C.c_size_t()
         _check(lib().sg_mesh_info(self._h, C.byref(me), C.byref(nh), C.byref(nb)))
         return dict(mean_edge=me.value, n_half_edges=nh.value, device_bytes=nb.value)
+
+    def exp_workspace_size(self, n, o: Opts | None = None, **kw):
+        o = o if o is not None else opts(**kw)
+        nb = C.c_size_t()
+        _check(lib().sg_exp_workspace_size(self._h, n, C.byref(o), C.byref(nb)))
+        return nb.value
+
+    def backward_workspace_size(self, mode, n, want_vjp=True, want_grad_X=False, o: Opts | None = None, **kw):
+        o = o if o is not None else opts(**kw)
+        nb = C.c_size_t()
+        _check(lib().sg_backward_workspace_size(self._h, int(mode), n, int(want_vjp), int(want_grad_X), C.byref(o),
+                                                C.byref(nb)))
+        return nb.value
+
+    def autotune(self, f, b, v, W=None, o: Opts | None = None, **kw):
+        """Opts with the fastest forward schedule for this batch, and its time per call (ms)."""
+        o = o if o is not None else opts(**kw)
+        K = 0 if W is None else W.shape[1]
+        ms = C.c_double()
+        _check(lib().sg_autotune(self._h, f.shape[0], _dptr(f), _dptr(b), _dptr(v), K, _dptr(W), C.byref(o),
+                                 C.byref(ms), _stream()))
+        return o, ms.value
 
     def walk_time(self):
         """(summed ms, launches) of walk kernels timed with debug bit 2 since the last call."""

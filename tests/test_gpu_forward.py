@@ -279,3 +279,119 @@ def test_mixed_orientation(torch):
     for kernel in (1, 2, 3):
         om, gm, o, g = both(torch, X, F2, r, kernel=kernel)
         assert_parity(o, g, om.mean_edge, K=2, label=f"mixed orientation, kernel {kernel}")
+
+
+def test_config3_many_meshes_one_launch(torch):
+    """64 meshes of uneven size (displaced spheres and jittered tori) and rays of
+    uneven length in one persistent call; each mesh's rays against the oracle."""
+    from paper_2603_15780_amd import sg
+    B = CF.config3_batch(64, scale=0.05)
+    gm = sg.Mesh(B["X"], B["F_local"], B["vert_offsets"], B["face_offsets"])
+    r = B["rays"]
+    g = run(torch, gm, r)
+    o = oracle.Mesh(B["X"], B["F_global"]).exp(r["f"], r["b"], r["v"])
+    for i, sl in enumerate(B["slices"]):
+        spec = B["specs"][i]
+        oi = {k: a[sl] for k, a in o.items()}
+        gi = {k: (a[sl] if a is not None else None) for k, a in g.items()}
+        s = report(oi, gi, M.mean_edge(spec["X"], spec["F"]), K=0)
+        assert s["frac_ok"] >= 0.999 and s["bad_not_near"] == 0 and s["face_mis_unexplained"] == 0, (i, s)
+
+
+def test_caller_workspace_and_graph_capture(torch):
+    """With a caller workspace a call allocates nothing, so it can be captured in
+    a HIP graph; every replay (with eager work between them) matches the eager call."""
+    from paper_2603_15780_amd import sg
+    dev = torch.device("cuda:0")
+    X, F = CF.mesh_config(1)
+    r = CF.rays_config(1, X, F)
+    n = r["f"].shape[0]
+    gm = sg.Mesh(X, F)
+    t = {k: torch.from_numpy(np.ascontiguousarray(r[k])).to(dev) for k in ("f", "b", "v", "W")}
+    o = sg.opts()
+    nb = gm.exp_workspace_size(n, o)
+    assert nb > 0 and gm.exp_workspace_size(n, sg.opts(kernel=1)) == 0
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    small = sg.opts(workspace=ws.data_ptr(), workspace_bytes=nb - 1)
+    with pytest.raises(sg.SgError):
+        gm.exp(t["f"], t["b"], t["v"], t["W"], o=small)
+    o.workspace, o.workspace_bytes = ws.data_ptr(), nb
+    ref = gm.exp(t["f"], t["b"], t["v"], t["W"])
+    eager = gm.exp(t["f"], t["b"], t["v"], t["W"], o=o)
+    torch.cuda.synchronize()
+    for k in ("f", "b", "p", "v", "W", "status"):
+        assert torch.equal(ref[k], eager[k]), k
+    out = {k: (torch.empty_like(a) if a is not None else None) for k, a in ref.items()}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        gm.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=o)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gm.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=o)
+    r2 = random_rays(X, F, 5000, np.random.default_rng(77), uniform_len(0.0, 1.0), K=1)
+    t2 = {k: torch.from_numpy(np.ascontiguousarray(r2[k])).to(dev) for k in ("f", "b", "v", "W")}
+    for rep in range(3):
+        for a in out.values():
+            if a is not None:
+                a.fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k in ("f", "b", "p", "v", "W", "status"):
+            assert torch.equal(ref[k], out[k]), (rep, k)
+        gm.exp(t2["f"], t2["b"], t2["v"], t2["W"])   # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_backward_caller_workspace_in_graph(torch):
+    from paper_2603_15780_amd import sg
+    dev = torch.device("cuda:0")
+    X, F = CF.mesh_config(1)
+    r = CF.rays_config(1, X, F)
+    n = r["f"].shape[0]
+    gm = sg.Mesh(X, F)
+    t = {k: torch.from_numpy(np.ascontiguousarray(r[k])).to(dev) for k in ("f", "b", "v")}
+    gup = torch.from_numpy(CF.upstream_grad(1, n)).to(dev)
+    nb = gm.backward_workspace_size(sg.BWD_GFD, n, want_vjp=True, want_grad_X=True)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    o = sg.opts(workspace=ws.data_ptr(), workspace_bytes=nb)
+    gX_ref = torch.zeros(gm.n_verts, 3, dtype=torch.float64, device=dev)
+    ref = gm.backward(sg.BWD_GFD, t["f"], t["b"], t["v"], gup, grad_X=gX_ref)
+    gv, gb = torch.empty(n, 3, device=dev), torch.empty(n, 3, device=dev)
+    gX = torch.zeros_like(gX_ref)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        gm.backward(sg.BWD_GFD, t["f"], t["b"], t["v"], gup, out=(gv, gb), grad_X=gX, o=o)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gm.backward(sg.BWD_GFD, t["f"], t["b"], t["v"], gup, out=(gv, gb), grad_X=gX, o=o)
+    for rep in range(3):
+        gv.fill_(0)
+        gX.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(gv, ref[0]) and torch.equal(gb, ref[1]), rep
+        assert torch.allclose(gX, gX_ref, rtol=1e-9, atol=1e-9 * gX_ref.abs().max().item()), rep
+
+
+def test_autotune(torch):
+    """The tuner returns a valid schedule, and the walk's results do not depend on it."""
+    from paper_2603_15780_amd import sg
+    dev = torch.device("cuda:0")
+    X, F = CF.mesh_config(1)
+    r = CF.rays_config(1, X, F)
+    gm = sg.Mesh(X, F)
+    t = {k: torch.from_numpy(np.ascontiguousarray(r[k])).to(dev) for k in ("f", "b", "v", "W")}
+    o, ms = gm.autotune(t["f"], t["b"], t["v"], t["W"])
+    assert ms > 0 and o.kernel in (sg.KERNEL_PLAIN, sg.KERNEL_PERSISTENT)
+    assert 1 <= o.refill_min <= 64 and o.walk_blocks > 0
+    a = gm.exp(t["f"], t["b"], t["v"], t["W"], o=o)
+    b = gm.exp(t["f"], t["b"], t["v"], t["W"])
+    torch.cuda.synchronize()
+    for k in ("f", "b", "p", "v", "W", "status"):
+        assert torch.equal(a[k], b[k]), k

@@ -88,3 +88,25 @@ def config3_rays(spec, i: int):
     g = np.random.default_rng(1000 * 3 + 1 + 7919 * i)
     D = spec["diameter"]
     return random_rays(spec["X"], spec["F"], spec["n_rays"], g, loguniform_len(0.01 * D, D), K=0)
+
+
+def config3_batch(n_meshes: int = 64, scale: float = 1.0):
+    """Config 3 as one batch: concatenated vertices, faces with local vertex ids,
+    vertex / face offsets (prefix sums), faces with global vertex ids, and the
+    rays of all meshes with global face ids; `slices` gives each mesh's rays."""
+    specs = config3_meshes(n_meshes, scale)
+    vo, fo, ro = [0], [0], [0]
+    for s in specs:
+        vo.append(vo[-1] + s["X"].shape[0])
+        fo.append(fo[-1] + s["F"].shape[0])
+        ro.append(ro[-1] + s["n_rays"])
+    X = np.concatenate([s["X"] for s in specs])
+    F_local = np.concatenate([s["F"] for s in specs])
+    F_global = np.concatenate([s["F"] + vo[i] for i, s in enumerate(specs)]).astype(np.int32)
+    rays = [config3_rays(s, i) for i, s in enumerate(specs)]
+    r = {k: np.concatenate([ri[k] + (fo[i] if k == "f" else 0) for i, ri in enumerate(rays)]).astype(rays[0][k].dtype)
+         for k in ("f", "b", "v")}
+    r["W"] = np.zeros((r["f"].shape[0], 0, 3), np.float32)
+    return dict(specs=specs, X=X, F_local=F_local, F_global=F_global, vert_offsets=np.array(vo, np.int64),
+                face_offsets=np.array(fo, np.int64), rays=r,
+                slices=[slice(ro[i], ro[i + 1]) for i in range(len(specs))])
