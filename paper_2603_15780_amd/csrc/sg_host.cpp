@@ -22,7 +22,7 @@
 #include "sg_internal.h"
 #include "sg_launch.h"
 
-using sg::HalfEdgeRec;
+using sg::FaceRec;
 
 struct sg_mesh_s {
     int device = 0;
@@ -32,7 +32,7 @@ struct sg_mesh_s {
     int64_t n_verts = 0, n_faces = 0;
     int32_t n_meshes = 1;
     double mean_edge = 0.0;
-    HalfEdgeRec* d_rec = nullptr;
+    FaceRec* d_face = nullptr;
     int32_t* d_F = nullptr;
     float* d_X = nullptr;
     int64_t* d_half = nullptr;
@@ -44,7 +44,7 @@ struct sg_mesh_s {
     size_t bytes = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare;   // walk-kernel event pairs
     sg::DevMesh dev() const {
-        sg::DevMesh d{d_rec, d_F, d_X, d_half, d_perm, d_order, n_faces, n_verts, has_flip, {}, d_twin};
+        sg::DevMesh d{d_face, d_F, d_X, d_half, d_perm, d_order, n_faces, n_verts, has_flip, {}, d_twin};
         for (int p = 0; p <= sg::kParts; ++p) d.part_he[p] = part_he[p];
         return d;
     }
@@ -75,7 +75,6 @@ inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
 inline double len(V3 a) { return std::sqrt(dot(a, a)); }
-inline V3 mul(V3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
 
 // angle between two vectors, robust for small angles
 inline double angle_between(V3 a, V3 b) { return std::atan2(len(cross(a, b)), dot(a, b)); }
@@ -120,7 +119,7 @@ void free_mesh(sg_mesh_s* m) {
     if (!m) return;
     for (auto& pr : m->timed) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (auto& pr : m->spare) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
-    (void)hipFree(m->d_rec);
+    (void)hipFree(m->d_face);
     (void)hipFree(m->d_F);
     (void)hipFree(m->d_X);
     (void)hipFree(m->d_half);
@@ -190,9 +189,9 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
               const int64_t* vert_offsets, const int64_t* face_offsets, int32_t n_meshes, PackedMesh& out) {
     try {
         if (!X_host || !F_host || n_verts <= 0 || n_faces <= 0) return fail(SG_E_ARG, "empty mesh");
-        // half-edge records are addressed with 32-bit byte offsets: 3 n_faces * 32 < 2^32
-        if (3 * n_faces * 32 >= ((int64_t)1 << 32))
-            return fail(SG_E_ARG, "mesh too large: %lld faces (at most 44,739,242)", (long long)n_faces);
+        // face records are addressed with 32-bit byte offsets: n_faces * 32 < 2^32
+        if (n_faces >= ((int64_t)1 << 27))
+            return fail(SG_E_ARG, "mesh too large: %lld faces (at most 134,217,727)", (long long)n_faces);
         if (n_verts > ((int64_t)1 << 31) - 1) return fail(SG_E_ARG, "too many vertices");
         if (n_meshes < 1) return fail(SG_E_ARG, "n_meshes must be >= 1");
         if ((vert_offsets == nullptr) != (face_offsets == nullptr))
@@ -337,48 +336,41 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
                 else if (root[v] != r) return fail(SG_E_NONMANIFOLD, "vertex %d: faces do not form one fan", v);
             }
         }
-        // chart records and vertex total angles
-        std::vector<HalfEdgeRec>& rec = out.rec;
-        rec.assign(nh, HalfEdgeRec{});
-        std::vector<double> theta(n_verts, 0.0);
-        for (int64_t h = 0; h < nh; ++h) {
-            const int64_t f = h / 3;
-            const int k = (int)(h % 3);
-            const int32_t ia = F[3 * f + k], ib = F[3 * f + (k + 1) % 3], ic = F[3 * f + (k + 2) % 3];
-            const V3 ab = X[ib] - X[ia], ac = X[ic] - X[ia], bc = X[ic] - X[ib];
-            const double l = len(ab);
-            const V3 ex = mul(ab, 1.0 / l);
-            V3 n = cross(ab, ac);
-            n = mul(n, 1.0 / len(n));
-            const V3 ey = cross(n, ex);
-            const double A = angle_between(ab, ac);
-            const double B = angle_between(mul(ab, -1.0), bc);
-            theta[ia] += A;
-            HalfEdgeRec& r = rec[h];
-            r.cx = (float)dot(ac, ex);
-            r.cy = (float)dot(ac, ey);
-            r.lac = (float)len(ac);
-            r.lbc = (float)len(bc);
-            r.A = to_fx(A);
-            r.B = to_fx(B);
-            auto link = [&](int64_t he) -> int32_t {
-                const int64_t g = twin[he];
-                if (g < 0) return -1;
-                const int32_t start_he = F[he];
-                const int32_t start_g = F[g];
-                const uint32_t flip = start_he == start_g ? 1u : 0u;   // same direction: orientations disagree
-                return (int32_t)(((uint32_t)g << 1) | flip);
-            };
-            r.nca = link(3 * f + (k + 2) % 3);
-            r.nbc = link(3 * f + (k + 1) % 3);
+        // face records; vertex total angles from the same fixed-point corners
+        std::vector<FaceRec>& face = out.face;
+        face.assign(n_faces, FaceRec{});
+        std::vector<int64_t> theta_fx(n_verts, 0);
+        auto link = [&](int64_t he) -> int32_t {
+            const int64_t g = twin[he];
+            if (g < 0) return -1;
+            const uint32_t flip = F[he] == F[g] ? 1u : 0u;   // same start vertex: orientations disagree
+            return (int32_t)(((uint32_t)g << 1) | flip);
+        };
+        for (int64_t f = 0; f < n_faces; ++f) {
+            const int32_t* t = &F[3 * f];
+            FaceRec& q = face[f];
+            uint32_t corner[3];
+            for (int k = 0; k < 3; ++k) {
+                const V3 e = X[t[(k + 1) % 3]] - X[t[k]];
+                q.l[k] = (float)len(e);
+                q.nb[k] = link(3 * f + k);
+            }
+            for (int k = 0; k < 2; ++k) {
+                const V3 p = X[t[(k + 1) % 3]] - X[t[k]], r = X[t[(k + 2) % 3]] - X[t[k]];
+                corner[k] = to_fx(angle_between(p, r));
+            }
+            corner[2] = sg::kPiFx - corner[0] - corner[1];
+            q.c0 = corner[0];
+            q.c1 = corner[1];
+            for (int k = 0; k < 3; ++k) theta_fx[t[k]] += (int64_t)corner[k];
         }
         std::vector<int64_t>& half = out.half;
         half.assign(n_verts, 0);
-        for (int64_t v = 0; v < n_verts; ++v)
-            half[v] = vbnd[v] ? -1 : (int64_t)std::llround(0.5 * theta[v] * sg::kFxPerRad);
+        for (int64_t v = 0; v < n_verts; ++v) half[v] = vbnd[v] ? -1 : theta_fx[v] / 2;
         out.has_flip = 0;
-        for (const HalfEdgeRec& r : rec)
-            if ((r.nca >= 0 && (r.nca & 1)) || (r.nbc >= 0 && (r.nbc & 1))) out.has_flip = 1;
+        for (const FaceRec& q : face)
+            for (int k = 0; k < 3; ++k)
+                if (q.nb[k] >= 0 && (q.nb[k] & 1)) out.has_flip = 1;
         out.twin.assign(twin.begin(), twin.end());
         out.X.assign(X_host, X_host + 3 * n_verts);
         out.F = std::move(F);
@@ -440,7 +432,7 @@ int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, 
     m->has_flip = pm.has_flip;
     for (int p = 0; p <= sg::kParts; ++p) m->part_he[p] = (int32_t)(3 * pm.part_start[p]);
     std::vector<int32_t> order32(pm.order.begin(), pm.order.end());
-    rc = upload(&m->d_rec, pm.rec, m->bytes);
+    rc = upload(&m->d_face, pm.face, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_F, pm.F, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_X, pm.X, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_half, pm.half, m->bytes);

@@ -20,16 +20,26 @@ constexpr uint32_t kHalfPiFx = 0x40000000u;
 constexpr double kFxPerRad = 4294967296.0 / 6.283185307179586476925286766559;
 constexpr float kRadPerFx = 1.4629180792671596e-09f;   // 2 pi / 2^32
 
-// One record per half-edge (32 bytes, one aligned sector): everything a ray
-// entering face f through edge k needs to find its exit and the next chart.
-struct alignas(32) HalfEdgeRec {
+// One record per face (32 bytes, one aligned sector).  Edge k runs from
+// vertex k to vertex k+1 of the face; corner k is the angle at vertex k.
+struct alignas(32) FaceRec {
+    float l[3];       // edge lengths |x_{k+1} - x_k|
+    uint32_t c0, c1;  // corner angles at vertices 0 and 1 (fixed point); corner 2 = pi - c0 - c1
+    int32_t nb[3];    // half-edge entered when crossing edge k: (id << 1) | flip, or -1 (boundary)
+};
+static_assert(sizeof(FaceRec) == 32, "record must be one 32-byte sector");
+
+// The chart of half-edge h = 3 f + k as the walk sees it, rebuilt from the
+// face record: a ray entering face f through edge k needs its exit test and
+// its two onward links.
+struct HalfEdgeRec {
     float cx, cy;     // apex c in the entry chart
     float lac, lbc;   // lengths |ac| and |bc|
+    float lab;        // length |ab| of the entry edge
     uint32_t A, B;    // corner angles at a and b (fixed point)
     int32_t nca;      // half-edge entered when crossing edge c-a: (id << 1) | flip, or -1 (boundary)
     int32_t nbc;      // half-edge entered when crossing edge b-c, same encoding
 };
-static_assert(sizeof(HalfEdgeRec) == 32, "record must be one 32-byte sector");
 
 // Faces are stored in a spatial (bisection) order cut into kParts contiguous
 // parts, one per XCD of the MI355X, so that a part's records fit that XCD's L2.
@@ -38,7 +48,7 @@ constexpr int kParts = 8;
 // Device view of a packed mesh handle.  Face ids inside the library are
 // internal (bisection order); rays name faces by user id.
 struct DevMesh {
-    const HalfEdgeRec* rec;     // [3 n_faces], internal order
+    const FaceRec* face;        // [n_faces], internal order
     const int32_t* F;           // [n_faces, 3] global vertex ids, internal order
     const float* X;             // [n_verts, 3]
     const int64_t* half_theta;  // [n_verts] theta(x)/2 in fixed point, -1 on boundary vertices

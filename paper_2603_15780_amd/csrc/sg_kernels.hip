@@ -103,9 +103,27 @@ struct Ray {
     uint64_t hash;
 };
 
-// Record gather with a 32-bit byte offset from the table base (h < 2^27).
+// Chart of half-edge h = 3 f + k from face f's record (one 32-byte gather
+// with a 32-bit byte offset, f < 2^27): the edges and corners rotated by k,
+// the apex from |ac| and the corner at a.
 SG_HD __forceinline__ HalfEdgeRec rec_at(const DevMesh& M, int32_t h) {
-    return *reinterpret_cast<const HalfEdgeRec*>(reinterpret_cast<const char*>(M.rec) + ((uint32_t)h << 5));
+    const uint32_t f = (uint32_t)h / 3u;
+    const uint32_t k = (uint32_t)h - 3u * f;
+    const FaceRec q = *reinterpret_cast<const FaceRec*>(reinterpret_cast<const char*>(M.face) + (f << 5));
+    const uint32_t c2 = kPiFx - q.c0 - q.c1;
+    HalfEdgeRec r;
+    r.A = k == 0u ? q.c0 : (k == 1u ? q.c1 : c2);
+    r.B = k == 0u ? q.c1 : (k == 1u ? c2 : q.c0);
+    r.lab = k == 0u ? q.l[0] : (k == 1u ? q.l[1] : q.l[2]);
+    r.lbc = k == 0u ? q.l[1] : (k == 1u ? q.l[2] : q.l[0]);
+    r.lac = k == 0u ? q.l[2] : (k == 1u ? q.l[0] : q.l[1]);
+    r.nbc = k == 0u ? q.nb[1] : (k == 1u ? q.nb[2] : q.nb[0]);
+    r.nca = k == 0u ? q.nb[2] : (k == 1u ? q.nb[0] : q.nb[1]);
+    float sn, cs;
+    sincos_fx(r.A, sn, cs);
+    r.cx = r.lac * cs;
+    r.cy = r.lac * sn;
+    return r;
 }
 
 // hardware reciprocal (about 1 ulp); the walk only needs local accuracy
@@ -259,7 +277,7 @@ SG_HD int enter_chart(const DevMesh& M, int32_t h, float ex, float ey, uint32_t 
     const int32_t f = h / 3;
     const int k0 = h - 3 * f;
     const HalfEdgeRec r = rec_at(M, h);
-    const float ell = rec_at(M, 3 * f + (k0 + 1) % 3).lac;   // |ab| of this chart
+    const float ell = r.lab;   // |ab| of this chart
     float bc = ey / r.cy;
     float bb = (ex - bc * r.cx) / ell;
     float ba = 1.0f - bb - bc;
@@ -515,7 +533,7 @@ SG_HD void write_unwalked(const DevMesh& M, const ExpArgs& a, int64_t i, bool ba
 SG_HD void write_final(const DevMesh& M, const ExpArgs& a, int64_t i, const Final& fin, float L) {
     const int32_t fe = fin.h / 3;
     const int ke = fin.h - 3 * fe;
-    const HalfEdgeRec r = M.rec[fin.h];
+    const HalfEdgeRec r = rec_at(M, fin.h);
     const int64_t f3 = 3 * (int64_t)fe;
     const float3 y0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
     const float3 y1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
@@ -1070,7 +1088,7 @@ SG_HD __forceinline__ float3 final_offset(const DevMesh& M, const Final& fin, fl
     const float3 y0 = sub(ld3(M.X + 3 * (int64_t)M.F[f3]), o);
     const float3 y1 = sub(ld3(M.X + 3 * (int64_t)M.F[f3 + 1]), o);
     const float3 y2 = sub(ld3(M.X + 3 * (int64_t)M.F[f3 + 2]), o);
-    const float ell = rec_at(M, 3 * fe + (ke + 1) % 3).lac;
+    const float ell = r.lab;
     float b0, b1, b2;
     chart_bary(r, ell, fin.ex, fin.ey, ke, b0, b1, b2);
     fe_out = fe;

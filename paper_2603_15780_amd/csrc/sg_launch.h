@@ -48,7 +48,7 @@ struct BwdArgs {
 
 // Host-side result of packing a mesh (float64 work, rounded once).
 struct PackedMesh {
-    std::vector<HalfEdgeRec> rec;
+    std::vector<FaceRec> face;
     std::vector<int32_t> F;           // internal (bisection) face order
     std::vector<int64_t> order;       // internal face id -> user face id
     std::vector<int32_t> perm;        // user face id -> internal face id
