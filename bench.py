@@ -5,8 +5,9 @@ SH-displaced icosphere (level 7, l <= 8, amplitude 0.1), |v| ~ U[0, pi/2],
 two extra vectors transported (K = 2).  --config 3: 64 meshes of uneven size
 (displaced spheres and jittered tori, 6.8M faces in all) and 5.6M rays of
 uneven length in one persistent call.  Inputs are synthetic and resident in
-HBM before timing.  A step is one sg_exp_transport call over the whole batch,
-with the schedule the library's autotuner picks for this batch (untimed).
+HBM before timing.  A step is one sg_exp_transport call over the whole batch
+with the library's default schedule (--autotune: the schedule the library's
+autotuner picks for this batch, tuned untimed).
 
 The forward + backward forms (extrinsic proxy from the saved outputs;
 geodesic finite differences, which re-walk seven geodesics per query; each
@@ -54,14 +55,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
-    ap.add_argument("--kernel", type=int, default=0, help="0 autotuned, 1 plain, 2 persistent, 3 partitioned")
-    ap.add_argument("--no-autotune", action="store_true", help="library defaults instead of the autotuner's pick")
+    ap.add_argument("--kernel", type=int, default=0, help="0 library default (persistent), 1 plain, 2 persistent, 3 partitioned")
+    ap.add_argument("--autotune", action="store_true", help="time the autotuner's pick instead of the library defaults")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=0, help="oracle sample size (0: whole batch, or 1/4 for config 3)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain kernel for comparison")
     ap.add_argument("--no-bwd", action="store_true", help="skip timing the backward forms")
     ap.add_argument("--refill", type=int, default=0, help="persistent kernel refill threshold (0: library default)")
-    ap.add_argument("--walk-blocks", type=int, default=0, help="persistent kernel blocks (0: fill the GPU)")
+    ap.add_argument("--walk-blocks", type=int, default=0, help="persistent kernel blocks (0: library default, two per CU)")
     ap.add_argument("--calib-copy", type=int, default=0, help="MiB copied once to calibrate byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -101,7 +102,7 @@ def main():
 
     base = sg.opts(kernel=args.kernel, refill_min=args.refill, walk_blocks=args.walk_blocks)
     tuned = None
-    if args.kernel == 0 and not args.no_autotune:
+    if args.kernel == 0 and args.autotune:
         t1 = time.time()
         base, tune_ms = mesh.autotune(t["f"], t["b"], t["v"], t["W"], o=base)
         tuned = {"kernel": ["auto", "plain", "persistent", "partitioned"][base.kernel], "refill_min": base.refill_min,

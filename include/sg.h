@@ -77,7 +77,7 @@ typedef struct {
                               bit 2: time the walk kernel with HIP events (read with sg_mesh_walk_time) */
     int32_t refill_min;    /* persistent kernel: a wave refetches rays once this many of its 64 lanes are
                               idle; <= 0: tuned default */
-    int32_t walk_blocks;   /* persistent kernel: 256-lane blocks launched; <= 0: fill every CU */
+    int32_t walk_blocks;   /* persistent kernel: 256-lane blocks launched; <= 0: two per CU */
     void* workspace;       /* optional caller-owned device workspace, 256-byte aligned, at least the size
                               sg_exp_workspace_size / sg_backward_workspace_size report.  With it a call
                               allocates nothing, so it can be captured in a HIP graph (debug bit 2 aside).
@@ -182,11 +182,12 @@ int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, con
 
 /*
  * Device workspace (bytes, host output) that sg_exp / sg_exp_transport need
- * for n queries with these options (kernel and debug bits matter), and that
+ * for n queries with K extra vectors (0 for sg_exp) under these options
+ * (kernel and debug bits matter), and that
  * sg_exp_backward needs for n queries in `mode` with grad_v/grad_b
  * (want_vjp != 0) and/or grad_X (want_grad_X != 0).  0 means none.
  */
-int sg_exp_workspace_size(sg_mesh mesh, int64_t n, const sg_opts* opts, size_t* bytes);
+int sg_exp_workspace_size(sg_mesh mesh, int64_t n, int32_t K, const sg_opts* opts, size_t* bytes);
 int sg_backward_workspace_size(sg_mesh mesh, int32_t mode, int64_t n, int32_t want_vjp, int32_t want_grad_X,
                                const sg_opts* opts, size_t* bytes);
 

@@ -141,8 +141,11 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     if (o.kernel == SG_KERNEL_AUTO) o.kernel = SG_KERNEL_PERSISTENT;
     if (o.refill_min <= 0) o.refill_min = 16;
     if (o.refill_min > 64) return fail(SG_E_ARG, "refill_min must be at most 64");
+    // default schedule: two resident 256-lane blocks per CU (what the autotuner picks on the
+    // 327k-face and 64-mesh workloads), or the partitioned walk's full occupancy
     if (o.walk_blocks <= 0)
-        o.walk_blocks = m->cu_count * (o.kernel == SG_KERNEL_PARTITIONED ? m->part_blocks_per_cu : m->walk_blocks_per_cu);
+        o.walk_blocks = m->cu_count * (o.kernel == SG_KERNEL_PARTITIONED ? m->part_blocks_per_cu
+                                                                         : std::min(2, m->walk_blocks_per_cu));
     return SG_OK;
 }
 
@@ -175,10 +178,10 @@ hipError_t give_workspace(Workspace& w, hipStream_t st) {
     return e;
 }
 
-size_t exp_workspace_bytes(const sg_opts& o, int64_t n) {
+size_t exp_workspace_bytes(const sg_opts& o, int64_t n, int32_t K) {
     if (o.kernel == SG_KERNEL_PLAIN || n <= 0) return 0;
     return o.kernel == SG_KERNEL_PARTITIONED ? sg::exp_partitioned_workspace(n, (o.debug & 2u) != 0u)
-                                             : sg::exp_persistent_workspace(n);
+                                             : sg::exp_persistent_workspace(n, K);
 }
 
 }  // namespace
@@ -507,7 +510,7 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
     // persistent forms: per-ray chart states and queues live in a workspace
     const bool part = o.kernel == SG_KERNEL_PARTITIONED;
     Workspace ws;
-    rc = take_workspace(o, exp_workspace_bytes(o, n), st, ws);
+    rc = take_workspace(o, exp_workspace_bytes(o, n, K), st, ws);
     if (rc != SG_OK) return rc;
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     if (o.debug & 4u) {
@@ -571,13 +574,14 @@ int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, con
     return SG_OK;
 }
 
-int sg_exp_workspace_size(sg_mesh mesh, int64_t n, const sg_opts* opts, size_t* bytes) {
+int sg_exp_workspace_size(sg_mesh mesh, int64_t n, int32_t K, const sg_opts* opts, size_t* bytes) {
     if (!mesh || !bytes) return fail(SG_E_ARG, "mesh and bytes are required");
     if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
+    if (K < 0 || K > 64) return fail(SG_E_ARG, "K must be in [0, 64]");
     sg_opts o;
     int rc = check_opts(opts, o, mesh);
     if (rc != SG_OK) return rc;
-    *bytes = exp_workspace_bytes(o, n);
+    *bytes = exp_workspace_bytes(o, n, K);
     return SG_OK;
 }
 

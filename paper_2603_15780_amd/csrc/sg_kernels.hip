@@ -529,8 +529,22 @@ SG_HD void write_unwalked(const DevMesh& M, const ExpArgs& a, int64_t i, bool ba
     if (a.seq_hash) a.seq_hash[i] = bad ? 0ull : fnv_face(14695981039346656037ull, (uint32_t)f0);
 }
 
+// Unit tangent d0 of ray i's projected v on its start face and n0 x d0.
+SG_HD __forceinline__ void start_tangent_frame(const DevMesh& M, const ExpArgs& a, int64_t i, float3& d0, float3& q0) {
+    const int64_t g3 = 3 * (int64_t)M.perm[a.f[i]];
+    const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[g3]);
+    const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[g3 + 1]);
+    const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[g3 + 2]);
+    const float3 n0 = nrm(crs(sub(x1, x0), sub(x2, x0)));
+    const float3 v = ld3(a.v + 3 * i);
+    d0 = nrm(sub(v, scl(n0, dot(v, n0))));
+    q0 = crs(n0, d0);
+}
+
 // Epilogue: end face, barycentrics, 3D point, transported tangent and vectors.
-SG_HD void write_final(const DevMesh& M, const ExpArgs& a, int64_t i, const Final& fin, float L) {
+// aux (nullable): the start-side terms saved at init, [L, (w . d0, w . q0) x K].
+SG_HD void write_final(const DevMesh& M, const ExpArgs& a, int64_t i, const Final& fin, float L,
+                       const float* aux = nullptr) {
     const int32_t fe = fin.h / 3;
     const int ke = fin.h - 3 * fe;
     const HalfEdgeRec r = rec_at(M, fin.h);
@@ -558,20 +572,21 @@ SG_HD void write_final(const DevMesh& M, const ExpArgs& a, int64_t i, const Fina
     const float3 d3 = make_float3(fmaf(cs, ex3.x, sn * ey3.x), fmaf(cs, ex3.y, sn * ey3.y), fmaf(cs, ex3.z, sn * ey3.z));
     a.v_out[3 * i] = L * d3.x; a.v_out[3 * i + 1] = L * d3.y; a.v_out[3 * i + 2] = L * d3.z;
     if (a.K > 0) {
-        // components of each extra vector in the start frame (tangent, normal x tangent)
-        const int64_t g3 = 3 * (int64_t)M.perm[a.f[i]];
-        const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[g3]);
-        const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[g3 + 1]);
-        const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[g3 + 2]);
-        const float3 n0 = nrm(crs(sub(x1, x0), sub(x2, x0)));
-        const float3 v = ld3(a.v + 3 * i);
-        const float3 d0 = nrm(sub(v, scl(n0, dot(v, n0))));
-        const float3 q0 = crs(n0, d0);
+        // each extra vector keeps its components on the frame (tangent, normal x tangent)
+        float3 d0, q0;
+        if (!aux) start_tangent_frame(M, a, i, d0, q0);
         const float sg = (fin.flags & kParity) ? -1.0f : 1.0f;
         const float3 q3 = scl(crs(n3, d3), sg);
         for (int kk = 0; kk < a.K; ++kk) {
-            const float3 w = ld3(a.W + 3 * (i * a.K + kk));
-            const float wx = dot(w, d0), wy = dot(w, q0);
+            float wx, wy;
+            if (aux) {
+                wx = aux[1 + 2 * kk];
+                wy = aux[2 + 2 * kk];
+            } else {
+                const float3 w = ld3(a.W + 3 * (i * a.K + kk));
+                wx = dot(w, d0);
+                wy = dot(w, q0);
+            }
             float* o = a.W_out + 3 * (i * a.K + kk);
             o[0] = fmaf(wx, d3.x, wy * q3.x);
             o[1] = fmaf(wx, d3.y, wy * q3.y);
@@ -649,7 +664,11 @@ SG_HD __forceinline__ void unpack_state(const StateRec& r, Ray& st) {
 }
 static_assert(sizeof(StateRec) == 32, "state record is one 32-byte sector");
 
-__global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* states, unsigned long long* counter) {
+// Initial chart state of every ray; the epilogue's start-side terms (|v_t| and
+// the extra vectors' components on the start frame) go to aux, so the
+// epilogue does not revisit the start face.
+__global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* states, unsigned long long* counter,
+                                              float* aux) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *counter = 0ull;
     if (i >= a.n) return;
@@ -665,6 +684,17 @@ __global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* st
         rec.ncross = 0;
     } else {
         rec = pack_state(st);
+        float* x = aux + i * (1 + 2 * (int64_t)a.K);
+        x[0] = L;
+        if (a.K > 0) {
+            float3 d0, q0;
+            start_tangent_frame(M, a, i, d0, q0);
+            for (int kk = 0; kk < a.K; ++kk) {
+                const float3 w = ld3(a.W + 3 * (i * a.K + kk));
+                x[1 + 2 * kk] = dot(w, d0);
+                x[2 + 2 * kk] = dot(w, q0);
+            }
+        }
     }
     states[i] = rec;
 }
@@ -776,6 +806,14 @@ template <bool kHash, bool kFlip>
 __global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
                                               int32_t max_steps, float snap, int refill_min) {
     walk_loop<kHash, kFlip, false>(M, states, n, counter, max_steps, snap, refill_min, nullptr, nullptr);
+}
+
+// The same walk over the backward's stacked chart states (its own symbol, so
+// profiles keep the forward's walk apart).
+template <bool kHash, bool kFlip>
+__global__ __launch_bounds__(256) void k_walk_bwd(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
+                                                  int32_t max_steps, float snap, int refill_min) {
+    walk_loop<false, kFlip, false>(M, states, n, counter, max_steps, snap, refill_min, nullptr, nullptr);
 }
 
 template <bool kFlip>
@@ -1058,7 +1096,8 @@ __global__ __launch_bounds__(256) void k_walk_part(DevMesh M, StateRec* states, 
     if (lane == 0 && done_local) atomicAdd(&qc->finished, done_local);
 }
 
-__global__ __launch_bounds__(256) void k_finish(DevMesh M, ExpArgs a, const StateRec* states, const uint64_t* hashes) {
+__global__ __launch_bounds__(256) void k_finish(DevMesh M, ExpArgs a, const StateRec* states, const uint64_t* hashes,
+                                                const float* aux) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     Final fin = *reinterpret_cast<const Final*>(&states[i]);
@@ -1072,7 +1111,12 @@ __global__ __launch_bounds__(256) void k_finish(DevMesh M, ExpArgs a, const Stat
         fin.hash = 0ull;
     }
     if (hashes) fin.hash = hashes[i];
-    write_final(M, a, i, fin, tangent_length(M, a, i));
+    if (aux) {
+        const float* x = aux + i * (1 + 2 * (int64_t)a.K);
+        write_final(M, a, i, fin, x[0], x);
+    } else {
+        write_final(M, a, i, fin, tangent_length(M, a, i));
+    }
 }
 
 
@@ -1511,7 +1555,12 @@ hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-size_t exp_persistent_workspace(int64_t n) { return (size_t)n * sizeof(StateRec) + 256; }
+// states [n], then the epilogue's start terms [n, 1 + 2K] (256-byte aligned), then the queue counter
+static size_t persistent_aux_offset(int64_t n) { return ((size_t)n * sizeof(StateRec) + 255) & ~(size_t)255; }
+static size_t persistent_counter_offset(int64_t n, int32_t K) {
+    return (persistent_aux_offset(n) + (size_t)n * (1 + 2 * (size_t)K) * sizeof(float) + 255) & ~(size_t)255;
+}
+size_t exp_persistent_workspace(int64_t n, int32_t K) { return persistent_counter_offset(n, K) + 256; }
 
 hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, int grid_blocks, int refill_min,
                                  hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
@@ -1519,13 +1568,16 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, i
     const int block = 256;
     const int64_t grid = (a.n + block - 1) / block;
     auto* states = reinterpret_cast<StateRec*>(ws);
-    auto* counter = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(ws) + (size_t)a.n * sizeof(StateRec));
-    hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, counter);
+    auto* aux = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + persistent_aux_offset(a.n));
+    auto* counter =
+        reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(ws) + persistent_counter_offset(a.n, a.K));
+    hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, counter, aux);
     if (ev0) (void)hipEventRecord(ev0, s);
     SG_DISPATCH(k_walk, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)grid_blocks), dim3(block), s, M, states,
                 a.n, counter, a.max_steps, a.snap, refill_min);
     if (ev1) (void)hipEventRecord(ev1, s);
-    hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)nullptr);
+    hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)nullptr,
+                       (const float*)aux);
     return hipGetLastError();
 }
 
@@ -1564,7 +1616,8 @@ hipError_t launch_exp_partitioned(const DevMesh& M, const ExpArgs& a, void* ws, 
     SG_DISPATCH(k_walk_part, hash, M.has_flip != 0, dim3((unsigned)blocks), dim3(block), s, M, states, hashes, initq,
                 migq, qc, cap, a.max_steps, a.snap, refill_min, idle_limit);
     if (ev1) (void)hipEventRecord(ev1, s);
-    hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)hashes);
+    hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)hashes,
+                       (const float*)nullptr);
     return hipGetLastError();
 }
 
@@ -1620,14 +1673,14 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a, void* ws, int gri
     // base walk (and, for GFD, the three perturbed walks that start at p)
     hipLaunchKernelGGL(k_bwd_stage1, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
-    SG_DISPATCH(k_walk, false, flip, dim3((unsigned)grid_blocks), dim3(block), s, M, s1, (int64_t)per1 * a.n, counter,
-                a.max_steps, a.snap, refill_min);
+    SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)grid_blocks), dim3(block), s, M, s1, (int64_t)per1 * a.n,
+                counter, a.max_steps, a.snap, refill_min);
     if (vjp && a.mode == 0)
         hipLaunchKernelGGL(k_ep_walked, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
     if (gfd) {
         hipLaunchKernelGGL(k_bwd_stage2, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
-        SG_DISPATCH(k_walk, false, flip, dim3((unsigned)grid_blocks), dim3(block), s, M, s2, 3 * a.n, counter,
+        SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)grid_blocks), dim3(block), s, M, s2, 3 * a.n, counter,
                     a.max_steps, a.snap, refill_min);
         hipLaunchKernelGGL(k_gfd_assemble, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
     }

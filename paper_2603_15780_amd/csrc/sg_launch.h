@@ -69,8 +69,8 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
 hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s);
 
 // Persistent forward: init kernel, persistent work-queue walk, finish kernel.
-// ws must hold exp_persistent_workspace(n) bytes of device memory.
-size_t exp_persistent_workspace(int64_t n);
+// ws must hold exp_persistent_workspace(n, K) bytes of device memory.
+size_t exp_persistent_workspace(int64_t n, int32_t K);
 // ev0/ev1 (nullable) are recorded on s around the walk kernel.
 hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, int grid_blocks, int refill_min,
                                  hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

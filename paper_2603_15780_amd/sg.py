@@ -60,7 +60,7 @@ def lib():
         L.sg_exp_transport.restype = C.c_int
         L.sg_exp_backward.argtypes = [P, I32, I64, P, P, P, P, P, P, P, P, P, C.POINTER(Opts), P]
         L.sg_exp_backward.restype = C.c_int
-        L.sg_exp_workspace_size.argtypes = [P, I64, C.POINTER(Opts), C.POINTER(C.c_size_t)]
+        L.sg_exp_workspace_size.argtypes = [P, I64, I32, C.POINTER(Opts), C.POINTER(C.c_size_t)]
         L.sg_exp_workspace_size.restype = C.c_int
         L.sg_backward_workspace_size.argtypes = [P, I32, I64, I32, I32, C.POINTER(Opts), C.POINTER(C.c_size_t)]
         L.sg_backward_workspace_size.restype = C.c_int
@@ -132,10 +132,10 @@ class Mesh:
         _check(lib().sg_mesh_info(self._h, C.byref(me), C.byref(nh), C.byref(nb)))
         return dict(mean_edge=me.value, n_half_edges=nh.value, device_bytes=nb.value)
 
-    def exp_workspace_size(self, n, o: Opts | None = None, **kw):
+    def exp_workspace_size(self, n, K=0, o: Opts | None = None, **kw):
         o = o if o is not None else opts(**kw)
         nb = C.c_size_t()
-        _check(lib().sg_exp_workspace_size(self._h, n, C.byref(o), C.byref(nb)))
+        _check(lib().sg_exp_workspace_size(self._h, n, int(K), C.byref(o), C.byref(nb)))
         return nb.value
 
     def backward_workspace_size(self, mode, n, want_vjp=True, want_grad_X=False, o: Opts | None = None, **kw):

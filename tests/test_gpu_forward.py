@@ -309,8 +309,9 @@ def test_caller_workspace_and_graph_capture(torch):
     gm = sg.Mesh(X, F)
     t = {k: torch.from_numpy(np.ascontiguousarray(r[k])).to(dev) for k in ("f", "b", "v", "W")}
     o = sg.opts()
-    nb = gm.exp_workspace_size(n, o)
-    assert nb > 0 and gm.exp_workspace_size(n, sg.opts(kernel=1)) == 0
+    K = r["W"].shape[1]
+    nb = gm.exp_workspace_size(n, K, o)
+    assert nb > 0 and gm.exp_workspace_size(n, K, sg.opts(kernel=1)) == 0
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
     small = sg.opts(workspace=ws.data_ptr(), workspace_bytes=nb - 1)
     with pytest.raises(sg.SgError):
