@@ -62,9 +62,10 @@ enum {
     SG_KERNEL_AUTO = 0,         /* = SG_KERNEL_PERSISTENT */
     SG_KERNEL_PLAIN = 1,        /* one ray per lane, run to completion (Alg. gpu_parallel) */
     SG_KERNEL_PERSISTENT = 2,   /* persistent waves refilled from one global ray queue */
-    SG_KERNEL_PARTITIONED = 3   /* persistent waves per XCD, each walking the rays inside its part of the mesh and
-                                   handing rays that leave it to the owning XCD (experimental: correct, but its
-                                   handoff queues are contended and it is far slower than PERSISTENT) */
+    SG_KERNEL_PARTITIONED = 3   /* the mesh cut into 8 spatial parts, one per XCD: the walk runs in rounds (one
+                                   launch each) in which the waves of XCD p walk the rays inside part p until
+                                   they end or leave it, and rays that leave are queued for the next round;
+                                   the last round walks every remaining ray to its end */
 };
 
 typedef struct {

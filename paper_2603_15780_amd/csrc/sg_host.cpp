@@ -142,10 +142,10 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     if (o.refill_min <= 0) o.refill_min = 16;
     if (o.refill_min > 64) return fail(SG_E_ARG, "refill_min must be at most 64");
     // default schedule: two resident 256-lane blocks per CU (what the autotuner picks on the
-    // 327k-face and 64-mesh workloads), or the partitioned walk's full occupancy
+    // 327k-face and 64-mesh workloads)
     if (o.walk_blocks <= 0)
-        o.walk_blocks = m->cu_count * (o.kernel == SG_KERNEL_PARTITIONED ? m->part_blocks_per_cu
-                                                                         : std::min(2, m->walk_blocks_per_cu));
+        o.walk_blocks = m->cu_count * std::min(2, o.kernel == SG_KERNEL_PARTITIONED ? m->part_blocks_per_cu
+                                                                                   : m->walk_blocks_per_cu);
     return SG_OK;
 }
 
@@ -180,7 +180,7 @@ hipError_t give_workspace(Workspace& w, hipStream_t st) {
 
 size_t exp_workspace_bytes(const sg_opts& o, int64_t n, int32_t K) {
     if (o.kernel == SG_KERNEL_PLAIN || n <= 0) return 0;
-    return o.kernel == SG_KERNEL_PARTITIONED ? sg::exp_partitioned_workspace(n, (o.debug & 2u) != 0u)
+    return o.kernel == SG_KERNEL_PARTITIONED ? sg::exp_partitioned_workspace(n, K, (o.debug & 2u) != 0u)
                                              : sg::exp_persistent_workspace(n, K);
 }
 
@@ -492,6 +492,8 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
     if (!f || !b || !v || !f_out || !b_out || !p_out || !v_out) return fail(SG_E_ARG, "a required array is NULL");
     if (K > 0 && (!W || !W_out)) return fail(SG_E_ARG, "W and W_out are required when K > 0");
     if ((o.debug & 2u) && !seq_hash) return fail(SG_E_ARG, "debug bit 1 needs seq_hash");
+    if (o.kernel == SG_KERNEL_PARTITIONED && n >= ((int64_t)1 << 31))
+        return fail(SG_E_ARG, "the partitioned walk takes fewer than 2^31 rays per call");
     sg::ExpArgs a{};
     a.n = n;
     a.f = f; a.b = b; a.v = v;

@@ -824,20 +824,19 @@ __global__ __launch_bounds__(256) void k_walk_gx(DevMesh M, StateRec* states, in
 }
 
 // ---------------------------------------------------------------- partitioned form
-// The mesh is cut into kParts spatial parts (contiguous internal face ranges),
-// one per XCD: blocks are dealt to XCDs round-robin, so block b serves part
-// b % kParts and that part's records stay in its XCD's L2.  A ray is walked by
-// the part that contains its current face; when it crosses into another part
-// its 32-byte state is handed to that part through a queue.  Handoffs between
-// XCDs use agent-scope loads and stores (coherent past the per-XCD L2s).
-struct PartCounters {
-    unsigned long long init_count[kParts];   // rays starting in each part (set by k_init_part)
-    unsigned long long init_head[kParts];    // next unread entry of each part's start queue
-    unsigned long long mig_tail[kParts];     // reservations in each part's handoff queue
-    unsigned long long mig_head[kParts];     // next unread handoff entry
-    unsigned long long finished;             // rays whose walk ended
-    unsigned long long pad[7];
-};
+// The mesh is cut into kParts spatial parts (contiguous internal face
+// ranges).  Blocks are dealt to the XCDs round-robin, so block b runs on XCD
+// b % kParts and serves part b % kParts, whose records then stay in that XCD's
+// L2.  The walk runs in rounds, one launch each.  Every ray carries a one-byte
+// tag, (round << 3) | part of its current chart, or kTagDone.  In round r the
+// waves of part p scan the tags in slices claimed from a per-part counter,
+// collect the rays tagged (r, p) in a per-wave list in LDS, and walk each
+// until it ends or leaves the part; a ray that leaves is tagged (r + 1, its
+// new part).  The round stamp keeps a tag written during a round from being
+// taken in the same round; the next launch sees the ray's state.  The last
+// round walks every remaining ray to its end.
+constexpr uint8_t kTagDone = 0xffu;
+constexpr int kSlice = 2048;   // tags per claimed slice (also the per-wave list capacity)
 
 SG_HD __forceinline__ int part_of(const DevMesh& M, int32_t h) {
     int p = 0;
@@ -846,254 +845,119 @@ SG_HD __forceinline__ int part_of(const DevMesh& M, int32_t h) {
     return p;
 }
 
-template <class T>
-__device__ __forceinline__ T ld_agent(const T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <class T>
-__device__ __forceinline__ void st_agent(T* p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__global__ __launch_bounds__(256) void k_rounds_reset(unsigned long long* ctr, int n) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) ctr[i] = 0ull;
 }
 
-__device__ __forceinline__ void st_state_agent(StateRec* dst, const StateRec& r) {
-    const uint64_t* w = reinterpret_cast<const uint64_t*>(&r);
-    uint64_t* d = reinterpret_cast<uint64_t*>(dst);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) st_agent(d + k, w[k]);
-}
-__device__ __forceinline__ StateRec ld_state_agent(const StateRec* src) {
-    StateRec r;
-    uint64_t* w = reinterpret_cast<uint64_t*>(&r);
-    const uint64_t* s = reinterpret_cast<const uint64_t*>(src);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] = ld_agent(s + k);
-    return r;
-}
-
-// k_part_reset: zero the queue counters and the handoff slots (0 = not yet written).
-__global__ __launch_bounds__(256) void k_part_reset(PartCounters* qc, int32_t* migq, int64_t slots) {
+// Initial chart state of every ray (as k_init), tagged (0, part of its first chart).
+template <bool kHash>
+__global__ __launch_bounds__(256) void k_init_rounds(DevMesh M, ExpArgs a, StateRec* states, float* aux,
+                                                     uint64_t* hashes, uint8_t* tags) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < (int64_t)(sizeof(PartCounters) / 8)) reinterpret_cast<unsigned long long*>(qc)[i] = 0ull;
-    for (int64_t k = i; k < slots; k += (int64_t)gridDim.x * blockDim.x) migq[k] = 0;
-}
-
-// k_init_part: initial chart state of every ray; walkable rays join the start
-// queue of the part their first face lies in (one atomic per wave and part).
-__global__ __launch_bounds__(256) void k_init_part(DevMesh M, ExpArgs a, StateRec* states, int32_t* initq,
-                                                   PartCounters* qc, int64_t cap) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = (int)(threadIdx.x & 63u);
-    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    int mypart = -1;
-    if (i < a.n) {
-        Ray st;
-        float L = 0.f;
-        const int ir = ray_init(M, a.f[i], a.b + 3 * i, a.v + 3 * i, st, L);
-        StateRec rec;
-        if (ir != kInitOk) {
-            write_unwalked(M, a, i, ir == kInitBad);
-            rec.h = -1;
-            rec.s = rec.t = rec.Lhi = rec.Llo = 0.f;
-            rec.phi = rec.flags = 0u;
-            rec.ncross = 0;
-        } else {
-            rec = pack_state(st);
-            mypart = part_of(M, st.h);
+    if (i >= a.n) return;
+    Ray st;
+    float L = 0.f;
+    const int ir = ray_init(M, a.f[i], a.b + 3 * i, a.v + 3 * i, st, L);
+    StateRec rec;
+    uint8_t tag = kTagDone;
+    if (ir != kInitOk) {
+        write_unwalked(M, a, i, ir == kInitBad);
+        rec.h = -1;
+        rec.s = rec.t = rec.Lhi = rec.Llo = 0.f;
+        rec.phi = rec.flags = 0u;
+        rec.ncross = 0;
+    } else {
+        rec = pack_state(st);
+        float* x = aux + i * (1 + 2 * (int64_t)a.K);
+        x[0] = L;
+        if (a.K > 0) {
+            float3 d0, q0;
+            start_tangent_frame(M, a, i, d0, q0);
+            for (int kk = 0; kk < a.K; ++kk) {
+                const float3 w = ld3(a.W + 3 * (i * a.K + kk));
+                x[1 + 2 * kk] = dot(w, d0);
+                x[2 + 2 * kk] = dot(w, q0);
+            }
         }
-        states[i] = rec;
+        if (kHash) hashes[i] = st.hash;
+        tag = (uint8_t)part_of(M, st.h);
     }
-#pragma unroll 1
-    for (int p = 0; p < kParts; ++p) {
-        const uint64_t m = __ballot(mypart == p);
-        if (!m) continue;
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        unsigned long long base = 0ull;
-        if (lane == leader) base = atomicAdd(&qc->init_count[p], (unsigned long long)__popcll(m));
-        base = __shfl(base, leader);
-        if (mypart == p) initq[(int64_t)p * cap + (int64_t)base + __popcll(m & below)] = (int32_t)i;
-    }
+    states[i] = rec;
+    tags[i] = tag;
 }
 
-// Take up to `want` entries of part q's handoff queue: returns the first index
-// and the count (lane 0 does the compare-and-swap; the result is broadcast).
-__device__ __forceinline__ int take_handoffs(PartCounters* qc, int q, int want, int64_t cap, unsigned long long& first) {
-    const int lane = (int)(threadIdx.x & 63u);
-    unsigned long long h0 = 0ull;
-    int got = 0;
-    if (lane == 0) {
-        unsigned long long h = ld_agent(&qc->mig_head[q]);
-        for (int tries = 0; tries < 64; ++tries) {
-            unsigned long long t = ld_agent(&qc->mig_tail[q]);
-            if (t > (unsigned long long)cap) t = (unsigned long long)cap;
-            if (h >= t) break;
-            const unsigned long long k = (t - h) < (unsigned long long)want ? (t - h) : (unsigned long long)want;
-            const unsigned long long seen = atomicCAS(&qc->mig_head[q], h, h + k);
-            if (seen == h) { h0 = h; got = (int)k; break; }
-            h = seen;
-        }
-    }
-    first = __shfl(h0, 0);
-    return __shfl(got, 0);
-}
-
+// One round (see above).  slice_ctr: this round's per-part slice counters.
 template <bool kHash, bool kFlip>
-__global__ __launch_bounds__(256) void k_walk_part(DevMesh M, StateRec* states, uint64_t* hashes, const int32_t* initq,
-                                                   int32_t* migq, PartCounters* qc, int64_t cap, int32_t max_steps,
-                                                   float snap, int refill_min, int idle_limit) {
-    const int home = (int)(blockIdx.x % kParts);
+__global__ __launch_bounds__(256) void k_walk_round(DevMesh M, StateRec* states, uint64_t* hashes, uint8_t* tags,
+                                                    unsigned long long* slice_ctr, int64_t n, int32_t max_steps,
+                                                    float snap, int refill_min, int round, int restrict_part) {
+    __shared__ int32_t lists[4][kSlice];
     const int lane = (int)(threadIdx.x & 63u);
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    unsigned long long n_walk = 0ull;
-#pragma unroll
-    for (int p = 0; p < kParts; ++p) n_walk += qc->init_count[p];
-    bool active = false;
-    int32_t ray = 0, lo = 0, hi = 0;
+    int32_t* list = lists[threadIdx.x >> 6];
+    const int home = (int)(blockIdx.x % kParts);
+    const uint8_t want = (uint8_t)((round << 3) | home);
+    const int32_t lo = M.part_he[home], hi = M.part_he[home + 1];
+    bool active = false, exhausted = false;
+    int list_n = 0, list_pos = 0;
+    int32_t ray = 0;
     Ray st;
     st.h = 0; st.s = st.t = st.Lhi = st.Llo = st.bias = 0.f; st.phi = st.par = 0u; st.ncross = 0; st.hash = 0ull;
-    bool init_left = true;           // wave-uniform: the home start queue may hold rays
-    unsigned long long done_local = 0ull;
-    int idle_spins = 0;
-    int quiet = 0;                   // walk steps to take before polling the queues again
     for (;;) {
-        uint64_t idle = __ballot(!active);
-        int nidle = __popcll(idle);
-        if (nidle >= refill_min && quiet <= 0) {
-            int got = 0;
-            const int rank = __popcll(idle & below);
-            // (a) rays starting in the home part
-            if (init_left) {
+        const uint64_t idle = __ballot(!active);
+        const int nidle = __popcll(idle);
+        const bool drained = exhausted && list_pos == list_n;
+        if (nidle == 64 && drained) break;
+        if (!drained && nidle >= refill_min) {
+            while (list_pos == list_n && !exhausted) {
+                // claim a slice of tags and list the rays of this part and round
                 unsigned long long base = 0ull;
-                if (lane == 0) base = atomicAdd(&qc->init_head[home], (unsigned long long)nidle);
+                if (lane == 0) base = atomicAdd(&slice_ctr[home], (unsigned long long)kSlice);
                 base = __shfl(base, 0);
-                const unsigned long long cnt = qc->init_count[home];
-                const int take = base >= cnt ? 0 : (int)((cnt - base) < (unsigned long long)nidle ? (cnt - base) : nidle);
-                if (base + (unsigned long long)nidle >= cnt) init_left = false;
-                if (!active && rank < take) {
-                    ray = initq[(int64_t)home * cap + (int64_t)base + rank];
+                if (base >= (unsigned long long)n) {
+                    exhausted = true;
+                    break;
+                }
+                list_n = 0;
+                list_pos = 0;
+                for (int j = 0; j < kSlice; j += 64) {
+                    const int64_t idx = (int64_t)base + j + lane;
+                    const bool match = idx < n && tags[idx] == want;
+                    const uint64_t m = __ballot(match);
+                    if (match) list[list_n + __popcll(m & below)] = (int32_t)idx;
+                    list_n += __popcll(m);
+                }
+            }
+            if (!active) {
+                const int k = list_pos + __popcll(idle & below);
+                if (k < list_n) {
+                    ray = list[k];
                     unpack_state(states[ray], st);
-                    st.hash = kHash ? fnv_face(14695981039346656037ull, (uint32_t)M.order[st.h / 3]) : 0ull;
-                    lo = M.part_he[home];
-                    hi = M.part_he[home + 1];
+                    st.hash = kHash ? hashes[ray] : 0ull;
                     active = true;
                 }
-                got += take;
             }
-            // (b) rays handed over from other parts
-            if (got < nidle) {
-                unsigned long long first = 0ull;
-                const int take = take_handoffs(qc, home, nidle - got, cap, first);
-                if (!active && rank >= got && rank < got + take) {
-                    int32_t* slot = migq + (int64_t)home * cap + (int64_t)(first + (rank - got));
-                    int32_t v = ld_agent(slot);
-                    for (int w = 0; v == 0 && w < (1 << 22); ++w) {   // the producer writes right after reserving
-                        __builtin_amdgcn_s_sleep(1);
-                        v = ld_agent(slot);
-                    }
-                    if (v != 0) {
-                        ray = v - 1;
-                        unpack_state(ld_state_agent(states + ray), st);
-                        if (kHash) st.hash = ld_agent(hashes + ray);
-                        lo = M.part_he[home];
-                        hi = M.part_he[home + 1];
-                        active = true;
-                    }
-                }
-                got += take;
-            }
-            // (c) nothing at home and every lane idle: help another part
-            if (got == 0 && nidle == 64) {
-                for (int k = 1; k < kParts && got == 0; ++k) {
-                    const int q = (home + k) % kParts;
-                    unsigned long long base = 0ull;
-                    if (lane == 0 && ld_agent(&qc->init_head[q]) < qc->init_count[q])
-                        base = atomicAdd(&qc->init_head[q], 64ull);
-                    else if (lane == 0)
-                        base = ~0ull;
-                    base = __shfl(base, 0);
-                    const unsigned long long cnt = qc->init_count[q];
-                    int take = 0;
-                    if (base != ~0ull && base < cnt) take = (int)((cnt - base) < 64ull ? (cnt - base) : 64ull);
-                    if (take > 0) {
-                        if (lane < take) {
-                            ray = initq[(int64_t)q * cap + (int64_t)base + lane];
-                            unpack_state(states[ray], st);
-                            st.hash = kHash ? fnv_face(14695981039346656037ull, (uint32_t)M.order[st.h / 3]) : 0ull;
-                            lo = M.part_he[q];
-                            hi = M.part_he[q + 1];
-                            active = true;
-                        }
-                        got = take;
-                        break;
-                    }
-                    unsigned long long first = 0ull;
-                    take = take_handoffs(qc, q, 64, cap, first);
-                    if (take > 0) {
-                        if (lane < take) {
-                            int32_t* slot = migq + (int64_t)q * cap + (int64_t)(first + lane);
-                            int32_t v = ld_agent(slot);
-                            for (int w = 0; v == 0 && w < (1 << 22); ++w) {
-                                __builtin_amdgcn_s_sleep(1);
-                                v = ld_agent(slot);
-                            }
-                            if (v != 0) {
-                                ray = v - 1;
-                                unpack_state(ld_state_agent(states + ray), st);
-                                if (kHash) st.hash = ld_agent(hashes + ray);
-                                lo = M.part_he[q];
-                                hi = M.part_he[q + 1];
-                                active = true;
-                            }
-                        }
-                        got = take;
-                    }
-                }
-            }
-            if (got == 0 && nidle == 64) {
-                // no work anywhere right now: count this wave's finished rays, then test for the end
-                if (lane == 0 && done_local) atomicAdd(&qc->finished, done_local);
-                done_local = 0ull;
-                if (ld_agent(&qc->finished) >= n_walk) break;
-                if (++idle_spins > idle_limit) break;   // bounded: the kernel always drains
-                __builtin_amdgcn_s_sleep(16);
-                continue;
-            }
-            idle_spins = 0;
-            quiet = got == 0 ? 16 : 0;   // found nothing: walk a while before polling again
+            list_pos = min(list_n, list_pos + nidle);
         }
-        // walk until enough lanes are idle to refill
+        const int stop_at = (exhausted && list_pos == list_n) ? 64 : refill_min;
         for (;;) {
-            bool ended = false;
             if (active) {
                 Final fin;
                 if (walk_step<kHash, kFlip>(M, st, max_steps, snap, fin) == kStepDone) {
                     *reinterpret_cast<Final*>(&states[ray]) = fin;
-                    if (kHash) hashes[ray] = fin.hash;
+                    tags[ray] = kTagDone;
                     active = false;
-                    ended = true;
-                } else if (st.h < lo || st.h >= hi) {
-                    // entered another part: hand the ray over to it
-                    const int dst = part_of(M, st.h);
-                    const unsigned long long idx = atomicAdd(&qc->mig_tail[dst], 1ull);
-                    if (idx < (unsigned long long)cap) {
-                        st_state_agent(states + ray, pack_state(st));
-                        if (kHash) st_agent(hashes + ray, st.hash);
-                        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // state lands before the slot
-                        st_agent(migq + (int64_t)dst * cap + (int64_t)idx, ray + 1);
-                        active = false;
-                    } else {   // queue full: keep walking here
-                        lo = M.part_he[dst];
-                        hi = M.part_he[dst + 1];
-                    }
+                } else if (restrict_part && (st.h < lo || st.h >= hi)) {
+                    states[ray] = pack_state(st);
+                    if (kHash) hashes[ray] = st.hash;
+                    tags[ray] = (uint8_t)(((round + 1) << 3) | part_of(M, st.h));
+                    active = false;
                 }
             }
-            done_local += (unsigned long long)__popcll(__ballot(ended));
-            --quiet;
-            nidle = __popcll(__ballot(!active));
-            if (nidle >= refill_min && quiet <= 0) break;
-            if (nidle == 64) break;
+            if (__popcll(__ballot(!active)) >= stop_at) break;
         }
     }
-    if (lane == 0 && done_local) atomicAdd(&qc->finished, done_local);
 }
 
 __global__ __launch_bounds__(256) void k_finish(DevMesh M, ExpArgs a, const StateRec* states, const uint64_t* hashes,
@@ -1581,43 +1445,58 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, i
     return hipGetLastError();
 }
 
-size_t exp_partitioned_workspace(int64_t n, bool hashes) {
-    size_t b = (size_t)n * sizeof(StateRec);          // states
-    b += sizeof(PartCounters);
-    b += 2 * (size_t)kParts * (size_t)n * 4;          // start and handoff queues
-    if (hashes) b += (size_t)n * 8;
-    return b + 1024;
+// Rounds of the partitioned walk: all but the last stop rays at part borders
+// (the round stamp in a tag has 5 bits).
+constexpr int kRounds = 4;
+static_assert(kRounds <= 30, "round stamps must stay below the done tag");
+
+// states [n] | epilogue terms [n, 1 + 2K] | hashes [n] (debug) | tags [n] | slice counters [kRounds, kParts]
+struct RoundsLayout {
+    size_t aux, hashes, tags, ctr, total;
+};
+static RoundsLayout rounds_layout(int64_t n, int32_t K, bool hash) {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    RoundsLayout L{};
+    size_t o = al((size_t)n * sizeof(StateRec));
+    L.aux = o; o = al(o + (size_t)n * (1 + 2 * (size_t)K) * sizeof(float));
+    L.hashes = o; o = al(o + (hash ? (size_t)n * 8 : 0));
+    L.tags = o; o = al(o + (size_t)n);
+    L.ctr = o; o = al(o + (size_t)kRounds * kParts * sizeof(unsigned long long));
+    L.total = o;
+    return L;
 }
+
+size_t exp_partitioned_workspace(int64_t n, int32_t K, bool hashes) { return rounds_layout(n, K, hashes).total; }
 
 hipError_t launch_exp_partitioned(const DevMesh& M, const ExpArgs& a, void* ws, int grid_blocks, int refill_min,
                                   hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (a.n <= 0) return hipSuccess;
     const int block = 256;
     const int64_t grid = (a.n + block - 1) / block;
-    const int64_t cap = a.n;
     const bool hash = (a.debug & 2u) != 0u;
+    const RoundsLayout L = rounds_layout(a.n, a.K, hash);
     char* p = reinterpret_cast<char*>(ws);
     auto* states = reinterpret_cast<StateRec*>(p);
-    p += (size_t)a.n * sizeof(StateRec);
-    auto* qc = reinterpret_cast<PartCounters*>(p);
-    p += sizeof(PartCounters);
-    auto* initq = reinterpret_cast<int32_t*>(p);
-    p += (size_t)kParts * (size_t)cap * 4;
-    auto* migq = reinterpret_cast<int32_t*>(p);
-    p += (size_t)kParts * (size_t)cap * 4;
-    auto* hashes = hash ? reinterpret_cast<uint64_t*>(p) : nullptr;
-    const int64_t slots = (int64_t)kParts * cap;
-    const int64_t rgrid = std::min<int64_t>((slots + block - 1) / block, 4096);
-    hipLaunchKernelGGL(k_part_reset, dim3((unsigned)rgrid), dim3(block), 0, s, qc, migq, slots);
-    hipLaunchKernelGGL(k_init_part, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, initq, qc, cap);
+    auto* aux = reinterpret_cast<float*>(p + L.aux);
+    auto* hashes = hash ? reinterpret_cast<uint64_t*>(p + L.hashes) : nullptr;
+    auto* tags = reinterpret_cast<uint8_t*>(p + L.tags);
+    auto* ctr = reinterpret_cast<unsigned long long*>(p + L.ctr);
+    hipLaunchKernelGGL(k_rounds_reset, dim3(1), dim3(kRounds * kParts), 0, s, ctr, kRounds * kParts);
+    if (hash)
+        hipLaunchKernelGGL(k_init_rounds<true>, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, aux, hashes, tags);
+    else
+        hipLaunchKernelGGL(k_init_rounds<false>, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, aux, hashes,
+                           tags);
     if (ev0) (void)hipEventRecord(ev0, s);
     const int blocks = (grid_blocks + kParts - 1) / kParts * kParts;   // every part gets the same number of blocks
-    const int idle_limit = 1 << 22;
-    SG_DISPATCH(k_walk_part, hash, M.has_flip != 0, dim3((unsigned)blocks), dim3(block), s, M, states, hashes, initq,
-                migq, qc, cap, a.max_steps, a.snap, refill_min, idle_limit);
+    for (int r = 0; r < kRounds; ++r) {
+        SG_DISPATCH(k_walk_round, hash, M.has_flip != 0, dim3((unsigned)blocks), dim3(block), s, M, states, hashes,
+                    tags, ctr + (size_t)r * kParts, (int64_t)a.n, a.max_steps, a.snap, refill_min, r,
+                    r + 1 < kRounds ? 1 : 0);
+    }
     if (ev1) (void)hipEventRecord(ev1, s);
-    hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)hashes,
-                       (const float*)nullptr);
+    hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)nullptr,
+                       (const float*)aux);
     return hipGetLastError();
 }
 
@@ -1711,7 +1590,7 @@ int walk_blocks_per_cu() {
 
 int part_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_part<false, false>, 256, 0) != hipSuccess || nb <= 0)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_round<false, false>, 256, 0) != hipSuccess || nb <= 0)
         nb = 1;
     return nb;
 }

@@ -84,7 +84,7 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a, void* ws, int gri
 
 // Partitioned forward: the walk runs on the XCD whose L2 holds the ray's
 // current part of the mesh; rays crossing parts are handed over through queues.
-size_t exp_partitioned_workspace(int64_t n, bool hashes);
+size_t exp_partitioned_workspace(int64_t n, int32_t K, bool hashes);
 hipError_t launch_exp_partitioned(const DevMesh& M, const ExpArgs& a, void* ws, int grid_blocks, int refill_min,
                                   hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
