@@ -79,6 +79,7 @@ typedef struct {
     int32_t refill_min;    /* persistent kernel: a wave refetches rays once this many of its 64 lanes are
                               idle; <= 0: tuned default */
     int32_t walk_blocks;   /* persistent kernel: 256-lane blocks launched; <= 0: two per CU */
+    int32_t rays_per_lane; /* persistent kernel: rays each lane walks at once, 1 or 2; <= 0: tuned default */
     void* workspace;       /* optional caller-owned device workspace, 256-byte aligned, at least the size
                               sg_exp_workspace_size / sg_backward_workspace_size report.  With it a call
                               allocates nothing, so it can be captured in a HIP graph (debug bit 2 aside).
@@ -197,9 +198,10 @@ int sg_backward_workspace_size(sg_mesh mesh, int32_t mode, int64_t n, int32_t wa
  * schedules one ray per thread; this picks the schedule that runs the
  * caller's batch fastest).  Times sg_exp_transport on the given queries
  * (device arrays as in sg_exp_transport; a representative sample is enough)
- * for the plain kernel and for the persistent kernel over refill thresholds
- * (the compaction period) and resident blocks per CU (waves per SIMD), then
- * writes the fastest kernel, refill_min and walk_blocks into *opts (its other
+ * for the plain kernel and for the persistent kernel over rays per lane,
+ * refill thresholds (the compaction period) and resident blocks per CU (waves
+ * per SIMD), then writes the fastest kernel, rays_per_lane, refill_min and
+ * walk_blocks into *opts (its other
  * fields are kept and used).  Synchronizes `stream`; allocates and frees
  * its own scratch outputs.  Not capturable.  *best_ms (nullable) receives
  * the winner's time per call.

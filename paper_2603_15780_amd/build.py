@@ -20,7 +20,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # and some of their forms are avoided on this target
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-ffp-contract=fast", "-fno-gpu-rdc"]
+             "-ffp-contract=on", "-fno-gpu-rdc"]
 
 
 def build(verbose: bool = False, extra=()) -> str:

@@ -139,8 +139,10 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     if (!(o.eps_p > 0.f)) o.eps_p = (float)(5e-3 * m->mean_edge);
     if (o.kernel < SG_KERNEL_AUTO || o.kernel > SG_KERNEL_PARTITIONED) return fail(SG_E_ARG, "unknown kernel %d", o.kernel);
     if (o.kernel == SG_KERNEL_AUTO) o.kernel = SG_KERNEL_PERSISTENT;
+    if (o.rays_per_lane <= 0) o.rays_per_lane = 1;
+    if (o.rays_per_lane > 2) return fail(SG_E_ARG, "rays_per_lane must be 1 or 2");
     if (o.refill_min <= 0) o.refill_min = 16;
-    if (o.refill_min > 64) return fail(SG_E_ARG, "refill_min must be at most 64");
+    if (o.refill_min > 64 * o.rays_per_lane) return fail(SG_E_ARG, "refill_min must be at most 64 per ray slot");
     // default schedule: two resident 256-lane blocks per CU (what the autotuner picks on the
     // 327k-face and 64-mesh workloads)
     if (o.walk_blocks <= 0)
@@ -405,6 +407,7 @@ void sg_opts_default(sg_opts* o) {
     o->debug = 0u;
     o->refill_min = 0;
     o->walk_blocks = 0;
+    o->rays_per_lane = 0;
     o->workspace = nullptr;
     o->workspace_bytes = 0;
 }
@@ -503,6 +506,7 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
     a.max_steps = o.max_steps;
     a.snap = o.vertex_snap;
     a.debug = o.debug;
+    a.rays_per_lane = o.rays_per_lane;
     const hipStream_t st = (hipStream_t)stream;
     if (o.kernel == SG_KERNEL_PLAIN) {
         hipError_t e = sg::launch_exp_plain(mesh->dev(), a, st);
@@ -629,12 +633,13 @@ int sg_autotune(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const
         (void)hipFree(buf);
         return fail(SG_E_HIP, "hipEventCreate failed");
     }
-    struct Cand { int32_t kernel, refill, blocks; };
+    struct Cand { int32_t kernel, refill, blocks, rpl; };
     std::vector<Cand> cands;
-    cands.push_back({SG_KERNEL_PLAIN, base.refill_min, base.walk_blocks});
+    cands.push_back({SG_KERNEL_PLAIN, base.refill_min, base.walk_blocks, 1});
     const int refills[] = {4, 8, 16, 24, 32, 48};
-    for (int bpc = 1; bpc <= mesh->walk_blocks_per_cu; ++bpc)
-        for (int r : refills) cands.push_back({SG_KERNEL_PERSISTENT, r, bpc * mesh->cu_count});
+    for (int rpl = 1; rpl <= 2; ++rpl)
+        for (int bpc = 1; bpc <= mesh->walk_blocks_per_cu; ++bpc)
+            for (int r : refills) cands.push_back({SG_KERNEL_PERSISTENT, r * rpl, bpc * mesh->cu_count, rpl});
     double best = 1e300;
     Cand win = cands[1 < cands.size() ? 1 : 0];
     rc = SG_OK;
@@ -643,6 +648,7 @@ int sg_autotune(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const
         o.kernel = c.kernel;
         o.refill_min = c.refill;
         o.walk_blocks = c.blocks;
+        o.rays_per_lane = c.rpl;
         double t = 1e300;
         for (int rep = 0; rep < 4 && rc == SG_OK; ++rep) {
             if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(SG_E_HIP, "hipEventRecord failed"); break; }
@@ -667,6 +673,7 @@ int sg_autotune(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const
     opts->kernel = win.kernel;
     opts->refill_min = win.refill;
     opts->walk_blocks = win.blocks;
+    opts->rays_per_lane = win.rpl;
     if (best_ms) *best_ms = best;
     return SG_OK;
 }

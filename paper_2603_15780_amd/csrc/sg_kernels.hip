@@ -395,7 +395,8 @@ SG_HD __forceinline__ void set_final(Final& fin, const Ray& st, float ex, float 
 // for every lane and committed with selects; stopping in the face, at the
 // step cap, at a vertex or on the boundary is one rarely taken branch.
 template <bool kHash, bool kFlip>
-SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps, float snap, Final& fin) {
+SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps, float snap, Final& fin,
+                                   bool alive = true) {
     const HalfEdgeRec r = rec_at(M, st.h);
     float sn, cs;
     sincos_fx(st.phi, sn, cs);
@@ -428,14 +429,15 @@ SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps
     ph = (uint32_t)(phs < 0 ? 0 : phs);
     const float nh = st.Lhi - lam;                    // compensated remaining length
     const float lo = st.Llo + ((st.Lhi - nh) - lam);
-    const bool rare = !(lam < Lr) || (st.ncross >= max_steps) || (mu < snap) || (omu < snap) || (nx < 0);
+    // (a lane slot without a ray steps a dummy state and never takes the rare branch)
+    const bool rare = alive && (!(lam < Lr) || (st.ncross >= max_steps) || (mu < snap) || (omu < snap) || (nx < 0));
     const Ray old = st;
     st.s = rare ? st.s : s2;
     st.t = rare ? st.t : t2;
     st.phi = rare ? st.phi : ph;
     st.Lhi = rare ? st.Lhi : nh;
     st.Llo = rare ? st.Llo : lo;
-    st.h = rare ? st.h : (nx >> 1);
+    st.h = (rare || nx < 0) ? st.h : (nx >> 1);
     st.par = rare ? st.par : par;
     st.bias = rare ? st.bias : 0.f;
     st.ncross += rare ? 0 : 1;
@@ -800,6 +802,77 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, in
             if (__popcll(__ballot(!active)) >= stop_at) break;
         }
     }
+}
+
+// Two rays per lane: both slots are stepped every iteration, branch-free, so
+// each lane carries two independent dependency chains and two gathers in
+// flight (the walk is bound by instruction latency at the occupancy where the
+// memory system is not yet congested).  A slot without a ray steps a dummy
+// state (alive = false) whose results are dropped.
+template <bool kHash, bool kFlip>
+__device__ __forceinline__ void walk_loop2(const DevMesh& M, StateRec* states, int64_t n, unsigned long long* counter,
+                                           int32_t max_steps, float snap, int refill_min) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    bool a0 = false, a1 = false, exhausted = false;
+    int64_t q0 = 0, q1 = 0;
+    Ray s0, s1;
+    s0.h = 0; s0.s = s0.t = s0.Lhi = s0.Llo = s0.bias = 0.f; s0.phi = s0.par = 0u; s0.ncross = 0; s0.hash = 0ull;
+    s1 = s0;
+    for (;;) {
+        const uint64_t i0 = __ballot(!a0), i1 = __ballot(!a1);
+        const int n0 = __popcll(i0), nidle = n0 + __popcll(i1);
+        if (nidle == 128 && exhausted) break;
+        if (!exhausted && nidle >= refill_min) {
+            unsigned long long base = 0ull;
+            if (lane == 0) base = atomicAdd(counter, (unsigned long long)nidle);
+            base = __shfl(base, 0);
+            if (base + (unsigned long long)nidle >= (unsigned long long)n) exhausted = true;
+            if (!a0) {
+                q0 = (int64_t)base + __popcll(i0 & below);
+                if (q0 < n) {
+                    const StateRec rec = states[q0];
+                    if (rec.h >= 0) {
+                        unpack_state(rec, s0);
+                        s0.hash = kHash ? fnv_face(14695981039346656037ull, (uint32_t)M.order[rec.h / 3]) : 0ull;
+                        a0 = true;
+                    }
+                }
+            }
+            if (!a1) {
+                q1 = (int64_t)base + n0 + __popcll(i1 & below);
+                if (q1 < n) {
+                    const StateRec rec = states[q1];
+                    if (rec.h >= 0) {
+                        unpack_state(rec, s1);
+                        s1.hash = kHash ? fnv_face(14695981039346656037ull, (uint32_t)M.order[rec.h / 3]) : 0ull;
+                        a1 = true;
+                    }
+                }
+            }
+        }
+        const int stop_at = exhausted ? 128 : refill_min;
+        for (;;) {
+            Final f0, f1;
+            const int e0 = walk_step<kHash, kFlip>(M, s0, max_steps, snap, f0, a0);
+            const int e1 = walk_step<kHash, kFlip>(M, s1, max_steps, snap, f1, a1);
+            if (a0 && e0 == kStepDone) {
+                *reinterpret_cast<Final*>(&states[q0]) = f0;
+                a0 = false;
+            }
+            if (a1 && e1 == kStepDone) {
+                *reinterpret_cast<Final*>(&states[q1]) = f1;
+                a1 = false;
+            }
+            if (__popcll(__ballot(!a0)) + __popcll(__ballot(!a1)) >= stop_at) break;
+        }
+    }
+}
+
+template <bool kHash, bool kFlip>
+__global__ __launch_bounds__(256) void k_walk2(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
+                                               int32_t max_steps, float snap, int refill_min) {
+    walk_loop2<kHash, kFlip>(M, states, n, counter, max_steps, snap, refill_min);
 }
 
 template <bool kHash, bool kFlip>
@@ -1437,8 +1510,12 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, i
         reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(ws) + persistent_counter_offset(a.n, a.K));
     hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, counter, aux);
     if (ev0) (void)hipEventRecord(ev0, s);
-    SG_DISPATCH(k_walk, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)grid_blocks), dim3(block), s, M, states,
-                a.n, counter, a.max_steps, a.snap, refill_min);
+    if (a.rays_per_lane == 2)
+        SG_DISPATCH(k_walk2, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)grid_blocks), dim3(block), s, M,
+                    states, a.n, counter, a.max_steps, a.snap, refill_min);
+    else
+        SG_DISPATCH(k_walk, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)grid_blocks), dim3(block), s, M,
+                    states, a.n, counter, a.max_steps, a.snap, refill_min);
     if (ev1) (void)hipEventRecord(ev1, s);
     hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)nullptr,
                        (const float*)aux);

@@ -27,6 +27,7 @@ struct ExpArgs {
     int32_t max_steps;
     float snap;
     uint32_t debug;
+    int32_t rays_per_lane;   // persistent walk: 1 or 2 rays per lane
 };
 
 struct BwdArgs {

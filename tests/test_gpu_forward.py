@@ -266,6 +266,24 @@ def test_persistent_schedules(torch, kernel, refill_min, walk_blocks):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("refill_min,walk_blocks", [(1, 0), (16, 0), (64, 7), (128, 3000)])
+@pytest.mark.parametrize("flip", [False, True])
+def test_two_rays_per_lane(torch, refill_min, walk_blocks, flip):
+    """Two rays per lane (both slots stepped branch-free) give the plain kernel's rays bit for bit."""
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    if flip:
+        F = F.copy()
+        sel = np.random.default_rng(5).random(F.shape[0]) < 0.3
+        F[sel] = F[sel][:, ::-1]
+    gm = sg.Mesh(X, F)
+    r = random_rays(X, F, 5000, np.random.default_rng(19), uniform_len(0.0, 3.0), K=1)
+    a = run(torch, gm, r, kernel=1)
+    b = run(torch, gm, r, kernel=2, rays_per_lane=2, refill_min=refill_min, walk_blocks=walk_blocks)
+    for k in ("f", "b", "p", "v", "W", "status", "n_cross", "hash"):
+        assert np.array_equal(a[k], b[k]), k
+
+
 def test_mixed_orientation(torch):
     """Faces listed with inconsistent orientation: the walk only uses adjacency, so the
     orientation-flip charts must give the oracle's answer (Sec. 4, non-orientable meshes)."""
