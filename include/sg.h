@@ -77,8 +77,8 @@ typedef struct {
     uint32_t debug;        /* bit 0: fill n_cross; bit 1: fill seq_hash (FNV-1a 64 of the visited face ids);
                               bit 2: time the walk kernel with HIP events (read with sg_mesh_walk_time) */
     int32_t refill_min;    /* persistent kernel: a wave refetches rays once this many of its 64 lanes are
-                              idle; <= 0: tuned default */
-    int32_t walk_blocks;   /* persistent kernel: 256-lane blocks launched; <= 0: two per CU */
+                              idle (of 128 ray slots with two rays per lane); <= 0: 32 per 64 slots */
+    int32_t walk_blocks;   /* persistent kernel: 256-lane blocks launched; <= 0: three per CU */
     int32_t rays_per_lane; /* persistent kernel: rays each lane walks at once, 1 or 2; <= 0: tuned default */
     void* workspace;       /* optional caller-owned device workspace, 256-byte aligned, at least the size
                               sg_exp_workspace_size / sg_backward_workspace_size report.  With it a call

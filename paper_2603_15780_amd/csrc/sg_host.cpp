@@ -141,12 +141,12 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     if (o.kernel == SG_KERNEL_AUTO) o.kernel = SG_KERNEL_PERSISTENT;
     if (o.rays_per_lane <= 0) o.rays_per_lane = 1;
     if (o.rays_per_lane > 2) return fail(SG_E_ARG, "rays_per_lane must be 1 or 2");
-    if (o.refill_min <= 0) o.refill_min = 16;
+    if (o.refill_min <= 0) o.refill_min = 32 * o.rays_per_lane;
     if (o.refill_min > 64 * o.rays_per_lane) return fail(SG_E_ARG, "refill_min must be at most 64 per ray slot");
-    // default schedule: two resident 256-lane blocks per CU (what the autotuner picks on the
-    // 327k-face and 64-mesh workloads)
+    // default schedule: three resident 256-lane blocks per CU, refill at 32 idle lanes (the
+    // fastest in a sweep on the 327k-face workload)
     if (o.walk_blocks <= 0)
-        o.walk_blocks = m->cu_count * std::min(2, o.kernel == SG_KERNEL_PARTITIONED ? m->part_blocks_per_cu
+        o.walk_blocks = m->cu_count * std::min(3, o.kernel == SG_KERNEL_PARTITIONED ? m->part_blocks_per_cu
                                                                                    : m->walk_blocks_per_cu);
     return SG_OK;
 }

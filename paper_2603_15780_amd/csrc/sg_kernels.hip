@@ -666,14 +666,101 @@ SG_HD __forceinline__ void unpack_state(const StateRec& r, Ray& st) {
 }
 static_assert(sizeof(StateRec) == 32, "state record is one 32-byte sector");
 
-// Initial chart state of every ray; the epilogue's start-side terms (|v_t| and
-// the extra vectors' components on the start frame) go to aux, so the
-// epilogue does not revisit the start face.
+// ---------------------------------------------------------------- spatial ray order
+// The persistent walk takes rays in the order of their start faces (the
+// internal face order is a spatial bisection order), so the rays in flight at
+// any moment start close together and share the records they fetch.  A
+// counting sort by start-face bucket: one atomic per ray on its bucket's
+// counter gives its rank inside the bucket, one block scans the counts, and
+// the ray's walk slot is the bucket's start plus that rank.  Rays with a face
+// id out of range go to a last bucket.
+constexpr int kMaxBuckets = 8192;
+
+int bucket_shift(int64_t n_faces) {
+    int sh = 0;
+    while (((n_faces - 1) >> sh) + 1 > kMaxBuckets) ++sh;
+    return sh;
+}
+
+SG_HD __forceinline__ int ray_bucket(const DevMesh& M, int32_t fu, int shift, int nb) {
+    return (fu >= 0 && (int64_t)fu < M.n_faces) ? (M.perm[fu] >> shift) : nb - 1;
+}
+
+__global__ __launch_bounds__(256) void k_zero_u32(uint32_t* p, int n) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = 0u;
+}
+
+// Rank of each ray inside its bucket: a 1024-thread block counts its
+// kBucketRays rays in LDS (the LDS atomic returns the local rank), then adds
+// each nonzero local count to the bucket's global counter once (returning the
+// block's base in the bucket).
+constexpr int kBucketRays = 16384;
+
+__global__ __launch_bounds__(1024) void k_bucket_count(DevMesh M, ExpArgs a, uint32_t* cnt, int32_t* slot, int shift,
+                                                       int nb) {
+    __shared__ uint32_t local[kMaxBuckets + 1];
+    const int t = (int)threadIdx.x;
+    for (int b = t; b < nb; b += 1024) local[b] = 0u;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * kBucketRays;
+    constexpr int kPer = kBucketRays / 1024;
+    uint32_t rk[kPer];
+    int bk[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = i0 + (int64_t)j * 1024 + t;
+        bk[j] = i < a.n ? ray_bucket(M, a.f[i], shift, nb) : -1;
+        rk[j] = bk[j] >= 0 ? atomicAdd(&local[bk[j]], 1u) : 0u;
+    }
+    __syncthreads();
+    for (int b = t; b < nb; b += 1024) {
+        const uint32_t c = local[b];
+        local[b] = c ? atomicAdd(&cnt[b], c) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int64_t i = i0 + (int64_t)j * 1024 + t;
+        if (bk[j] >= 0) slot[i] = (int32_t)(local[bk[j]] + rk[j]);
+    }
+}
+
+// Exclusive scan of nb counts in place (one block of 1024 threads).
+__global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* cnt, int nb) {
+    __shared__ uint32_t part[1024];
+    const int t = (int)threadIdx.x;
+    const int per = (nb + 1023) / 1024;
+    const int b0 = min(nb, t * per), b1 = min(nb, b0 + per);
+    uint32_t sum = 0u;
+    for (int b = b0; b < b1; ++b) sum += cnt[b];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (int b = b0; b < b1; ++b) {
+        const uint32_t c = cnt[b];
+        cnt[b] = run;
+        run += c;
+    }
+}
+
+// Initial chart state of every ray, stored at its walk slot (slot[i] becomes
+// that slot); the epilogue's start-side terms (|v_t| and the extra vectors'
+// components on the start frame) go to aux, so the epilogue does not revisit
+// the start face.
 __global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* states, unsigned long long* counter,
-                                              float* aux) {
+                                              float* aux, const uint32_t* bstart, int32_t* slot, int shift, int nb) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *counter = 0ull;
     if (i >= a.n) return;
+    const int32_t at = (int32_t)bstart[ray_bucket(M, a.f[i], shift, nb)] + slot[i];
+    slot[i] = at;
     Ray st;
     float L = 0.f;
     const int ir = ray_init(M, a.f[i], a.b + 3 * i, a.v + 3 * i, st, L);
@@ -698,14 +785,9 @@ __global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* st
             }
         }
     }
-    states[i] = rec;
+    states[at] = rec;
 }
 
-// Persistent walk: each wave keeps 64 rays in flight and refills finished
-// lanes from a global queue (one atomic per wave per refill, ballot for the
-// lane ranks), so short and long rays share lanes instead of idling behind
-// the longest ray of a fixed batch.  Between refills the wave runs a tight
-// loop of walk steps and re-ballots only to see whether enough lanes are idle.
 // Float64 add into a global sum (the gradient accumulators).  hipMalloc'd
 // memory is coarse-grained, where the hardware float64 atomic is exact.
 SG_HD __forceinline__ void add_f64(double* p, double v) {
@@ -1034,14 +1116,15 @@ __global__ __launch_bounds__(256) void k_walk_round(DevMesh M, StateRec* states,
 }
 
 __global__ __launch_bounds__(256) void k_finish(DevMesh M, ExpArgs a, const StateRec* states, const uint64_t* hashes,
-                                                const float* aux) {
+                                                const float* aux, const int32_t* slot) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
-    Final fin = *reinterpret_cast<const Final*>(&states[i]);
+    const int64_t at = slot ? (int64_t)slot[i] : i;
+    Final fin = *reinterpret_cast<const Final*>(&states[at]);
     if (fin.h < 0) return;
     if (!(fin.flags & kDoneBit)) {
         // never reached its end (a walk kernel gave up waiting): report where it is
-        const StateRec rec = states[i];
+        const StateRec rec = states[at];
         fin.h = rec.h; fin.ex = rec.s; fin.ey = 0.f; fin.phi = rec.phi;
         fin.flags = (rec.flags & kParity) | ((uint32_t)kRayMaxSteps << 8);
         fin.ncross = rec.ncross;
@@ -1492,23 +1575,43 @@ hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// states [n], then the epilogue's start terms [n, 1 + 2K] (256-byte aligned), then the queue counter
-static size_t persistent_aux_offset(int64_t n) { return ((size_t)n * sizeof(StateRec) + 255) & ~(size_t)255; }
-static size_t persistent_counter_offset(int64_t n, int32_t K) {
-    return (persistent_aux_offset(n) + (size_t)n * (1 + 2 * (size_t)K) * sizeof(float) + 255) & ~(size_t)255;
+// states [n] | epilogue terms [n, 1 + 2K] | walk slots [n] | bucket counts [kMaxBuckets + 1] | queue counter
+struct PersistentLayout {
+    size_t aux, slot, cnt, counter, total;
+};
+static PersistentLayout persistent_layout(int64_t n, int32_t K) {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    PersistentLayout L{};
+    size_t o = al((size_t)n * sizeof(StateRec));
+    L.aux = o; o = al(o + (size_t)n * (1 + 2 * (size_t)K) * sizeof(float));
+    L.slot = o; o = al(o + (size_t)n * sizeof(int32_t));
+    L.cnt = o; o = al(o + (size_t)(kMaxBuckets + 1) * sizeof(uint32_t));
+    L.counter = o; o = al(o + sizeof(unsigned long long));
+    L.total = o;
+    return L;
 }
-size_t exp_persistent_workspace(int64_t n, int32_t K) { return persistent_counter_offset(n, K) + 256; }
+size_t exp_persistent_workspace(int64_t n, int32_t K) { return persistent_layout(n, K).total; }
 
 hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, int grid_blocks, int refill_min,
                                  hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (a.n <= 0) return hipSuccess;
     const int block = 256;
     const int64_t grid = (a.n + block - 1) / block;
-    auto* states = reinterpret_cast<StateRec*>(ws);
-    auto* aux = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + persistent_aux_offset(a.n));
-    auto* counter =
-        reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(ws) + persistent_counter_offset(a.n, a.K));
-    hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, counter, aux);
+    const PersistentLayout L = persistent_layout(a.n, a.K);
+    char* p = reinterpret_cast<char*>(ws);
+    auto* states = reinterpret_cast<StateRec*>(p);
+    auto* aux = reinterpret_cast<float*>(p + L.aux);
+    auto* slot = reinterpret_cast<int32_t*>(p + L.slot);
+    auto* cnt = reinterpret_cast<uint32_t*>(p + L.cnt);
+    auto* counter = reinterpret_cast<unsigned long long*>(p + L.counter);
+    const int shift = bucket_shift(M.n_faces);
+    const int nb = (int)(((M.n_faces - 1) >> shift) + 2);   // start-face buckets + one for bad face ids
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, cnt, nb);
+    hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)((a.n + kBucketRays - 1) / kBucketRays)), dim3(1024), 0, s, M, a,
+                       cnt, slot, shift, nb);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, cnt, nb);
+    hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, counter, aux,
+                       (const uint32_t*)cnt, slot, shift, nb);
     if (ev0) (void)hipEventRecord(ev0, s);
     if (a.rays_per_lane == 2)
         SG_DISPATCH(k_walk2, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)grid_blocks), dim3(block), s, M,
@@ -1518,7 +1621,7 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, i
                     states, a.n, counter, a.max_steps, a.snap, refill_min);
     if (ev1) (void)hipEventRecord(ev1, s);
     hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)nullptr,
-                       (const float*)aux);
+                       (const float*)aux, (const int32_t*)slot);
     return hipGetLastError();
 }
 
@@ -1573,7 +1676,7 @@ hipError_t launch_exp_partitioned(const DevMesh& M, const ExpArgs& a, void* ws, 
     }
     if (ev1) (void)hipEventRecord(ev1, s);
     hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)nullptr,
-                       (const float*)aux);
+                       (const float*)aux, (const int32_t*)nullptr);
     return hipGetLastError();
 }
 
