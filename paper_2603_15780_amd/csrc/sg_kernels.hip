@@ -697,8 +697,8 @@ __global__ __launch_bounds__(256) void k_zero_u32(uint32_t* p, int n) {
 // block's base in the bucket).
 constexpr int kBucketRays = 16384;
 
-__global__ __launch_bounds__(1024) void k_bucket_count(DevMesh M, ExpArgs a, uint32_t* cnt, int32_t* slot, int shift,
-                                                       int nb) {
+__global__ __launch_bounds__(1024) void k_bucket_count(DevMesh M, int64_t n, const int32_t* f, uint32_t* cnt,
+                                                       int32_t* slot, int shift, int nb) {
     __shared__ uint32_t local[kMaxBuckets + 1];
     const int t = (int)threadIdx.x;
     for (int b = t; b < nb; b += 1024) local[b] = 0u;
@@ -710,7 +710,7 @@ __global__ __launch_bounds__(1024) void k_bucket_count(DevMesh M, ExpArgs a, uin
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int64_t i = i0 + (int64_t)j * 1024 + t;
-        bk[j] = i < a.n ? ray_bucket(M, a.f[i], shift, nb) : -1;
+        bk[j] = i < n ? ray_bucket(M, f[i], shift, nb) : -1;
         rk[j] = bk[j] >= 0 ? atomicAdd(&local[bk[j]], 1u) : 0u;
     }
     __syncthreads();
@@ -748,6 +748,13 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* cnt, int nb) {
         cnt[b] = run;
         run += c;
     }
+}
+
+// slot[i] = bucket start + rank inside the bucket.
+__global__ __launch_bounds__(256) void k_slot_place(DevMesh M, int64_t n, const int32_t* f, const uint32_t* bstart,
+                                                    int32_t* slot, int shift, int nb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) slot[i] = (int32_t)bstart[ray_bucket(M, f[i], shift, nb)] + slot[i];
 }
 
 // Initial chart state of every ray, stored at its walk slot (slot[i] becomes
@@ -1209,8 +1216,11 @@ SG_HD __forceinline__ void nan_grads(const BwdArgs& a, int64_t i) {
 // slots 2 and 3 are the short walks Exp(p, eps_p e_u), Exp(p, eps_p e_v).  The
 // perturbations are applied to the fixed-point angle and the compensated
 // length, so the perturbed walks share the base walk's rounding.
+// Position of query i in the backward's walk arrays (spatial order when sorted).
+SG_HD __forceinline__ int64_t bwd_at(const BwdArgs& a, int64_t i) { return a.slot ? (int64_t)a.slot[i] : i; }
+
 SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_ray, int64_t i) {
-    StateRec* out = s1 + (int64_t)per_ray * i;
+    StateRec* out = s1 + (int64_t)per_ray * bwd_at(a, i);
     StartFrame S;
     uint32_t phi0;
     float L;
@@ -1238,12 +1248,13 @@ SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_
 // are Exp(p_u, v_u), Exp(p_v, v_v) with v transported along the short walks
 // (it keeps its angle to their tangent).
 SG_HD void bwd_stage2(const DevMesh& M, const BwdArgs& a, const StateRec* s1, StateRec* s2, int64_t i) {
-    StateRec* out = s2 + 3 * i;
+    const int64_t at = bwd_at(a, i);
+    StateRec* out = s2 + 3 * at;
     StartFrame S;
     uint32_t phi0;
     float L;
     Ray st;
-    const Final F0 = as_final(s1[4 * i]), Fu = as_final(s1[4 * i + 2]), Fv = as_final(s1[4 * i + 3]);
+    const Final F0 = as_final(s1[4 * at]), Fu = as_final(s1[4 * at + 2]), Fv = as_final(s1[4 * at + 3]);
     if (bwd_query(M, a, i, S, phi0, L) != kInitOk || F0.h < 0 || Fu.h < 0 || Fv.h < 0) {
         out[0] = out[1] = out[2] = dead_state();
         return;
@@ -1279,8 +1290,9 @@ SG_HD void gfd_assemble(const DevMesh& M, const BwdArgs& a, const StateRec* s1, 
     StartFrame S;
     uint32_t phi0;
     float L;
-    const Final F0 = as_final(s1[4 * i]), Fp = as_final(s1[4 * i + 1]);
-    const Final Fq = as_final(s2[3 * i]), Fu = as_final(s2[3 * i + 1]), Fv = as_final(s2[3 * i + 2]);
+    const int64_t at = bwd_at(a, i);
+    const Final F0 = as_final(s1[4 * at]), Fp = as_final(s1[4 * at + 1]);
+    const Final Fq = as_final(s2[3 * at]), Fu = as_final(s2[3 * at + 1]), Fv = as_final(s2[3 * at + 2]);
     if (bwd_query(M, a, i, S, phi0, L) != kInitOk || F0.h < 0 || Fp.h < 0 || Fq.h < 0 || Fu.h < 0 || Fv.h < 0) {
         nan_grads(a, i);
         return;
@@ -1373,7 +1385,7 @@ SG_HD void ep_walked(const DevMesh& M, const BwdArgs& a, const StateRec* s1, int
     StartFrame S;
     uint32_t phi0;
     float L;
-    const Final F0 = as_final(s1[(int64_t)stride * i]);
+    const Final F0 = as_final(s1[(int64_t)stride * bwd_at(a, i)]);
     if (bwd_query(M, a, i, S, phi0, L) != kInitOk || F0.h < 0) {
         nan_grads(a, i);
         return;
@@ -1403,12 +1415,13 @@ SG_HD void ep_walked(const DevMesh& M, const BwdArgs& a, const StateRec* s1, int
 // [d', nu' x d', nu'] of the base walk (slot `stride * i` of s1).
 SG_HD void gradx_init(const DevMesh& M, const BwdArgs& a, const StateRec* s1, int stride, StateRec* s3, float4* cvec,
                       int64_t i) {
-    s3[i] = dead_state();
+    const int64_t at = bwd_at(a, i);
+    s3[at] = dead_state();
     StartFrame S;
     uint32_t phi0;
     float L;
     if (bwd_query(M, a, i, S, phi0, L) != kInitOk) return;
-    const Final F0 = as_final(s1[(int64_t)stride * i]);
+    const Final F0 = as_final(s1[(int64_t)stride * at]);
     if (F0.h < 0 || ((F0.flags >> 8) & 0xffu) != (uint32_t)kRayOk) return;
     float3 d3, n3;
     final_frame(M, F0, d3, n3);
@@ -1447,8 +1460,8 @@ SG_HD void gradx_init(const DevMesh& M, const BwdArgs& a, const StateRec* s1, in
     if (!(L > 0.f)) return;
     Ray st;
     if (enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, 0.f, st) != kInitOk) return;
-    s3[i] = pack_state(st);
-    cvec[i] = c;
+    s3[at] = pack_state(st);
+    cvec[at] = c;
 }
 
 struct D3 { double x, y, z; };
@@ -1607,8 +1620,8 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, i
     const int shift = bucket_shift(M.n_faces);
     const int nb = (int)(((M.n_faces - 1) >> shift) + 2);   // start-face buckets + one for bad face ids
     hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, cnt, nb);
-    hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)((a.n + kBucketRays - 1) / kBucketRays)), dim3(1024), 0, s, M, a,
-                       cnt, slot, shift, nb);
+    hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)((a.n + kBucketRays - 1) / kBucketRays)), dim3(1024), 0, s, M, a.n,
+                       a.f, cnt, slot, shift, nb);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, cnt, nb);
     hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, counter, aux,
                        (const uint32_t*)cnt, slot, shift, nb);
@@ -1684,7 +1697,7 @@ hipError_t launch_exp_partitioned(const DevMesh& M, const ExpArgs& a, void* ws, 
 // base-walk states (1 or 4 per query), GFD second-pass states (3 per query),
 // grad-X walk states and adjoint coefficients, grad-X half-edge sums, counter.
 struct BwdLayout {
-    size_t s1, s2, s3, cvec, acc, counter, total;
+    size_t s1, s2, s3, cvec, acc, slot, cnt, counter, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1700,6 +1713,8 @@ static BwdLayout bwd_layout(int64_t n, int32_t mode, bool has_flip, bool vjp, bo
     L.s3 = o; o = align256(o + (gradx ? (size_t)n * sizeof(StateRec) : 0));
     L.cvec = o; o = align256(o + (gradx ? (size_t)n * sizeof(float4) : 0));
     L.acc = o; o = align256(o + (gradx ? 15 * (size_t)n_faces * sizeof(double) : 0));
+    L.slot = o; o = align256(o + (walk ? (size_t)n * sizeof(int32_t) : 0));
+    L.cnt = o; o = align256(o + (walk ? (size_t)(kMaxBuckets + 1) * sizeof(uint32_t) : 0));
     L.counter = o; o = align256(o + sizeof(unsigned long long));
     L.total = (walk || gradx) ? o : 0;
     return L;
@@ -1709,8 +1724,9 @@ size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip, bool vjp, bool grad
     return bwd_layout(n, mode, has_flip, vjp, gradx, n_faces).total;
 }
 
-hipError_t launch_backward(const DevMesh& M, const BwdArgs& a, void* ws, int grid_blocks, int refill_min,
+hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, int grid_blocks, int refill_min,
                            hipStream_t s) {
+    BwdArgs a = a_in;
     if (a.n <= 0) return hipSuccess;
     const int block = 256;
     const int64_t grid = (a.n + block - 1) / block;
@@ -1729,6 +1745,19 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a, void* ws, int gri
     auto* acc = reinterpret_cast<double*>(base + L.acc);
     auto* counter = reinterpret_cast<unsigned long long*>(base + L.counter);
     const int per1 = gfd ? 4 : 1;
+    {   // walk the queries in the spatial order of their start faces
+        auto* slot = reinterpret_cast<int32_t*>(base + L.slot);
+        auto* cnt = reinterpret_cast<uint32_t*>(base + L.cnt);
+        const int shift = bucket_shift(M.n_faces);
+        const int nb = (int)(((M.n_faces - 1) >> shift) + 2);
+        hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, cnt, nb);
+        hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)((a.n + kBucketRays - 1) / kBucketRays)), dim3(1024), 0, s,
+                           M, a.n, a.f, cnt, slot, shift, nb);
+        hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, cnt, nb);
+        hipLaunchKernelGGL(k_slot_place, dim3((unsigned)grid), dim3(block), 0, s, M, a.n, a.f, (const uint32_t*)cnt,
+                           slot, shift, nb);
+        a.slot = slot;
+    }
     // base walk (and, for GFD, the three perturbed walks that start at p)
     hipLaunchKernelGGL(k_bwd_stage1, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);

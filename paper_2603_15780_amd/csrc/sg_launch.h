@@ -45,6 +45,7 @@ struct BwdArgs {
     int32_t max_steps;
     float snap;
     double* grad_X;         // [n_verts, 3] accumulated vertex-position gradient, or null
+    const int32_t* slot;    // position of each query in the walk arrays (set by the launcher), or null
 };
 
 // Host-side result of packing a mesh (float64 work, rounded once).
