@@ -49,6 +49,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+WALK_SOURCES = ("paper_2603_15780_amd/csrc/sg_kernels.hip", "paper_2603_15780_amd/csrc/sg_internal.h",
+                "paper_2603_15780_amd/csrc/sg_launch.h", "paper_2603_15780_amd/csrc/sg_host.cpp",
+                "paper_2603_15780_amd/build.py")
+TRAFFIC_NOTE = "profiles/k_walk_icosphere7_1M_rays.md"
+
+
+def measured_traffic():
+    """HBM bytes per walk launch from the committed counter summary, if it was taken on these sources."""
+    import hashlib
+    try:
+        h = hashlib.sha256()
+        for f in WALK_SOURCES:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        note = open(os.path.join(ROOT, TRAFFIC_NOTE)).read()
+    except OSError:
+        return None
+    vals = dict(line.strip().split(": ", 1) for line in note.splitlines() if line.strip().startswith("walk_"))
+    if vals.get("walk_sources_sha256") != h.hexdigest():
+        return None
+    return int(vals["walk_traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,7 +268,10 @@ def main():
         "queries_per_s": n / (ms_step * 1e-3),
         "fwd_bwd": bwd,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if (args.config == 2 and ms_walk is not None and not tuned
+                                                       and args.kernel in (0, 2) and not args.refill
+                                                       and not args.walk_blocks) else None,
                      "kernel": "k_walk (persistent walk)" if ms_walk is not None else "k_exp_plain",
                      "algorithmic_bytes_per_launch": algo_bytes, "kernel_ms": ms_kernel,
                      "whole_call": {"ms": ms_call, "algorithmic_bytes": call_bytes,
