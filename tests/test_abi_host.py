@@ -81,3 +81,14 @@ def test_null_arguments_fail_before_launch():
     o = sg.opts()
     assert L.sg_exp(None, 1, None, None, None, None, None, None, None, None, None, None, C.byref(o), None) == -1
     assert L.sg_mesh_info(None, None, None, None) == -1
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; asking for more exits with a message before touching a device."""
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "4"], capture_output=True, text=True,
+                       timeout=60)
+    assert p.returncode == 2 and "one GPU" in p.stderr
