@@ -222,3 +222,50 @@ class Mesh:
         _check(lib().sg_exp_backward(self._h, int(mode), n, _dptr(f), _dptr(b), _dptr(v), _dptr(f_out), _dptr(v_out),
                                      _dptr(g), _dptr(out[0]), _dptr(out[1]), _dptr(grad_X), C.byref(o), _stream()))
         return out
+
+
+def _autograd_function():
+    import torch
+
+    class ExpFunction(torch.autograd.Function):
+        """p' = Exp_p(v) with the library's backward (Sec. 4 "Differentiation").
+
+        Inputs: f [n] int32, b [n,3], v [n,3] float32 (cuda); X [V,3] (the
+        mesh's vertex positions as a tensor, or None) receives dL/dX from the
+        float64 vertex-gradient pass.  mode: BWD_EP or BWD_GFD for dL/dv and
+        dL/db.  Only the end point p' is differentiated (dL/dv' and dL/dW' are
+        not part of the backward).
+        """
+
+        @staticmethod
+        def forward(ctx, mesh, mode, f, b, v, X, opts_kw):
+            out = mesh.exp(f.contiguous(), b.contiguous(), v.contiguous(), **(opts_kw or {}))
+            ctx.mesh, ctx.mode, ctx.opts_kw = mesh, mode, opts_kw or {}
+            ctx.want_x = X is not None and X.requires_grad
+            ctx.x_dtype = X.dtype if X is not None else None
+            ctx.save_for_backward(f, b, v, out["f"], out["v"])
+            ctx.mark_non_differentiable(out["f"], out["b"], out["v"], out["status"])
+            return out["p"], out["f"], out["b"], out["v"], out["status"]
+
+        @staticmethod
+        def backward(ctx, g_p, *unused):
+            f, b, v, f_out, v_out = ctx.saved_tensors
+            g = g_p.contiguous().float()
+            gX = torch.zeros(ctx.mesh.n_verts, 3, dtype=torch.float64, device=g.device) if ctx.want_x else None
+            gv, gb = ctx.mesh.backward(ctx.mode, f.contiguous(), b.contiguous(), v.contiguous(), g, f_out=f_out,
+                                       v_out=v_out, grad_X=gX, **ctx.opts_kw)
+            return (None, None, None, gb, gv, gX.to(ctx.x_dtype) if gX is not None else None, None)
+
+    return ExpFunction
+
+
+_ExpFunction = None
+
+
+def exp_with_grad(mesh, f, b, v, X=None, mode=BWD_GFD, **opts_kw):
+    """Differentiable Exp: returns (p', f', b', v', status); p' carries the library's backward
+    to b and v (mode BWD_EP or BWD_GFD) and, when X is a tensor that requires grad, to X."""
+    global _ExpFunction
+    if _ExpFunction is None:
+        _ExpFunction = _autograd_function()
+    return _ExpFunction.apply(mesh, mode, f, b, v, X, opts_kw)

@@ -280,3 +280,59 @@ def test_gradx_zero_length_and_torus(torch):
     s = gradx_report(ref, got)
     print(s)
     assert s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, s
+
+
+def test_autograd_function(torch):
+    """torch.autograd through exp_with_grad gives the library's gradients (and the oracle's)."""
+    from paper_2603_15780_amd import sg
+    from parity import gradx_report, grad_report
+    X, F = CF.mesh_config(1)
+    r = CF.rays_config(1, X, F)
+    n = r["f"].shape[0]
+    gup = CF.upstream_grad(1, n)
+    om = oracle.Mesh(X, F)
+    keep = margin_mask(om, r)
+    gup[~keep] = 0.0
+    gm = sg.Mesh(X, F)
+    dev = torch.device("cuda:0")
+    f = torch.from_numpy(r["f"]).to(dev)
+    b = torch.from_numpy(r["b"]).to(dev).requires_grad_(True)
+    v = torch.from_numpy(r["v"]).to(dev).requires_grad_(True)
+    Xt = torch.from_numpy(X).to(dev).requires_grad_(True)
+    eps = float(np.float32(5e-3 * om.mean_edge))
+    p, fo, bo, vo, st = sg.exp_with_grad(gm, f, b, v, Xt, mode=sg.BWD_GFD, eps_v=eps, eps_p=eps)
+    loss = (p * torch.from_numpy(gup).to(dev)).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    od = om.gfd(r["f"], r["b"], r["v"], gup, eps, eps)
+    o = om.exp(r["f"], r["b"], r["v"])
+    s = grad_report(o, od["grad_v"], od["grad_b"], v.grad.cpu().numpy(), b.grad.cpu().numpy(), om.mean_edge)
+    assert s["v_ok"] >= 0.999 and s["b_ok"] >= 0.999, s
+    ref, _ = om.gradx(r["f"], r["b"], r["v"], gup)
+    sx = gradx_report(ref, Xt.grad.double().cpu().numpy(), tol=1e-3)
+    # the tensor gradient is float32 (the dtype of X): compare at float32's resolution
+    assert sx["frac_ok"] >= 0.999 and sx["global_rel"] < 1e-4, sx
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_backward_mesh_with_holes(torch, mode):
+    """A mesh with holes: rays that stop on the boundary are left out of the
+    vertex gradient (both sides); the others match the oracle."""
+    from paper_2603_15780_amd import sg
+    from parity import gradx_report
+    X, F = M.icosphere(3)
+    X, F = M.remove_faces(X, F, np.where((F == 0).any(1) | (F == 7).any(1) | (F == 100).any(1))[0])
+    X, F = M.canonical(X, F)
+    rng = np.random.default_rng(31)
+    r = random_rays(X, F, 4096, rng, uniform_len(0.0, 2.0))
+    g = rng.standard_normal((4096, 3)).astype(np.float32)
+    om = oracle.Mesh(X, F)
+    o = om.exp(r["f"], r["b"], r["v"])
+    assert np.any(o["status"] == 2)
+    keep = margin_mask(om, r)
+    gk = np.where(keep[:, None], g, 0.0).astype(np.float32)
+    check(torch, X, F, r, gk, mode)
+    ref, nvx = om.gradx(r["f"], r["b"], r["v"], gk)
+    got, _ = gpu_gradx(torch, sg.Mesh(X, F), r, gk)
+    s = gradx_report(ref, got)
+    assert s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, s
