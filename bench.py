@@ -42,6 +42,8 @@ WORKLOADS = {
         "K=2 transported; forward (fwd+bwd forms in fwd_bwd)"),
     3: ("64 meshes (displaced geodesic spheres and 3:1 jittered tori, faces log-U[5k,500k]) in one handle; "
         "rays per mesh log-U[16k,256k], |v| log-U[0.01,1] x diameter, K=0; one persistent forward call"),
+    5: ("icosphere level 8 (1,310,720 faces), SH-displaced (l<=32, amp 0.1) plus N(0, 0.1 mean edge) normal noise; "
+        "16,777,216 rays, |v|~U[0,pi], K=2 (the start frame); forward (fwd+bwd forms in fwd_bwd)"),
 }
 
 
@@ -77,11 +79,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3])
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 5])
     ap.add_argument("--kernel", type=int, default=0, help="0 library default (persistent), 1 plain, 2 persistent, 3 partitioned")
     ap.add_argument("--autotune", action="store_true", help="time the autotuner's pick instead of the library defaults")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=0, help="oracle sample size (0: whole batch, or 1/4 for config 3)")
+    ap.add_argument("--cpu-rays", type=int, default=0,
+                    help="oracle sample size (0: whole batch; 1/4 of it for config 3, 1/64 for config 5)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain kernel for comparison")
     ap.add_argument("--no-bwd", action="store_true", help="skip timing the backward forms")
     ap.add_argument("--refill", type=int, default=0, help="persistent kernel refill threshold (0: library default)")
@@ -184,6 +187,8 @@ def main():
         bo = sg.opts(refill_min=base.refill_min if persistent else 0, walk_blocks=base.walk_blocks if persistent else 0)
         forms = (("ep", sg.BWD_EP, False), ("gfd", sg.BWD_GFD, False), ("ep+gradX", sg.BWD_EP, True),
                  ("gfd+gradX", sg.BWD_GFD, True))
+        if args.config == 5:   # the float64 vertex gradient takes seconds per call at this size
+            forms = forms[:2]
         for name, mode, with_x in forms:
             steps = max(3, args.steps // 2)
 
@@ -217,7 +222,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        nc = args.cpu_rays or (n if args.config != 3 else n // 4)
+        nc = args.cpu_rays or {3: n // 4, 5: n // 64}.get(args.config, n)
         rows = np.arange(n) if nc >= n else np.linspace(0, n - 1, nc).astype(np.int64)
         om = oracle.Mesh(X, F_or)
         # the machine's CPU share is given by OMP_NUM_THREADS when set

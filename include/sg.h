@@ -71,7 +71,7 @@ enum {
 typedef struct {
     int32_t max_steps;     /* cap on crossings per ray (edge crossings + vertex passages); <= 0: 1 << 20 */
     float vertex_snap;     /* an exit point within this edge-parameter distance of an edge endpoint passes
-                              through that vertex (straightest rule at vertices); <= 0: 2^-18 */
+                              through that vertex (straightest rule at vertices); <= 0: 2^-21 */
     float eps_v, eps_p;    /* GFD step sizes (absolute lengths); <= 0: 5e-3 * mean edge of the handle */
     int32_t kernel;        /* SG_KERNEL_*: which forward kernel runs the walk */
     uint32_t debug;        /* bit 0: fill n_cross; bit 1: fill seq_hash (FNV-1a 64 of the visited face ids);

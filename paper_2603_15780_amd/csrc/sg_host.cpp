@@ -133,7 +133,7 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     sg_opts_default(&o);
     if (in) o = *in;
     if (o.max_steps <= 0) o.max_steps = 1 << 20;
-    if (!(o.vertex_snap > 0.f)) o.vertex_snap = 1.0f / 262144.0f;
+    if (!(o.vertex_snap > 0.f)) o.vertex_snap = 1.0f / 2097152.0f;
     if (!(o.vertex_snap < 0.25f)) return fail(SG_E_ARG, "vertex_snap must be below 0.25");
     if (!(o.eps_v > 0.f)) o.eps_v = (float)(5e-3 * m->mean_edge);
     if (!(o.eps_p > 0.f)) o.eps_p = (float)(5e-3 * m->mean_edge);
@@ -400,7 +400,7 @@ const char* sg_last_error(void) { return g_err.c_str(); }
 void sg_opts_default(sg_opts* o) {
     if (!o) return;
     o->max_steps = 1 << 20;
-    o->vertex_snap = 1.0f / 262144.0f;
+    o->vertex_snap = 1.0f / 2097152.0f;
     o->eps_v = 0.f;
     o->eps_p = 0.f;
     o->kernel = SG_KERNEL_AUTO;

@@ -64,25 +64,6 @@ SG_HD __forceinline__ void sincos_fx(uint32_t phi, float& sn, float& cs) {
     cs = -x * poly_sinc(u);
 }
 
-// Full-circle fixed-point angle of the 2D vector (x, y), reduced to one octant
-// so the float32 arctangent only sees [0, 1].
-SG_HD uint32_t angle_fx(float x, float y) {
-    const float ax = fabsf(x), ay = fabsf(y);
-    const bool sw = ay > ax;
-    const float q = sw ? ax / ay : (ax > 0.f ? ay / ax : 0.f);
-    const float a = atanf(q);
-    // a * 2^32 / (2 pi) with the constant split in two floats
-    const float khi = 683565248.0f, klo = 27.576362f;
-    const float p = a * khi;
-    const float e = fmaf(a, khi, -p) + a * klo;
-    const float pr = rintf(p);
-    uint32_t fx = (uint32_t)(int32_t)pr + (uint32_t)(int32_t)rintf((p - pr) + e);
-    if (sw) fx = kHalfPiFx - fx;
-    if (x < 0.f) fx = kPiFx - fx;
-    if (y < 0.f) fx = 0u - fx;
-    return fx;
-}
-
 SG_HD __forceinline__ uint64_t fnv_face(uint64_t h, uint32_t f) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -260,15 +241,44 @@ SG_HD __forceinline__ int start_frame(const DevMesh& M, int32_t fu, const float*
 
 // initialise_trace (Alg. gpu_parallel): v is projected onto the start face;
 // its angle to the chart's x-axis and its length start the walk.
+// v projected onto the start face, in float64 (once per ray): its length as
+// a float pair Lhi + Llo and its angle to the chart's x-axis in fixed point,
+// each rounded once.  In float32 these two would carry relative errors of
+// about 1e-7, i.e. endpoint errors of 3e-7 at |v| = pi, along and across the
+// ray; the walk itself keeps its errors near 1e-8.
+SG_HD __forceinline__ void start_direction(const DevMesh& M, int32_t f, float3 vf, float& Lhi, float& Llo,
+                                           uint32_t& phi0) {
+    const int64_t f3 = 3 * (int64_t)f;
+    const float* p0 = M.X + 3 * (int64_t)M.F[f3];
+    const float* p1 = M.X + 3 * (int64_t)M.F[f3 + 1];
+    const float* p2 = M.X + 3 * (int64_t)M.F[f3 + 2];
+    const double e1x = (double)p1[0] - p0[0], e1y = (double)p1[1] - p0[1], e1z = (double)p1[2] - p0[2];
+    const double e2x = (double)p2[0] - p0[0], e2y = (double)p2[1] - p0[1], e2z = (double)p2[2] - p0[2];
+    const double il = 1.0 / sqrt(e1x * e1x + e1y * e1y + e1z * e1z);
+    const double ux = e1x * il, uy = e1y * il, uz = e1z * il;
+    double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+    const double inn = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
+    nx *= inn; ny *= inn; nz *= inn;
+    const double wx = ny * uz - nz * uy, wy = nz * ux - nx * uz, wz = nx * uy - ny * ux;   // n x u
+    const double vx = vf.x * ux + vf.y * uy + vf.z * uz;
+    const double vy = vf.x * wx + vf.y * wy + vf.z * wz;
+    const double L = sqrt(vx * vx + vy * vy);
+    Lhi = (float)L;
+    Llo = (float)(L - (double)Lhi);
+    const double a = L > 0.0 ? atan2(vy, vx) : 0.0;   // (-pi, pi]
+    phi0 = (uint32_t)(int64_t)__builtin_rint(a * kFxPerRad);
+}
+
 SG_HD int ray_init(const DevMesh& M, int32_t fu, const float* bp, const float* vp, Ray& st, float& L) {
     StartFrame S;
     if (start_frame(M, fu, bp, S) != kInitOk) return kInitBad;
     const float3 v = ld3(vp);
     if (!__builtin_isfinite(v.x) || !__builtin_isfinite(v.y) || !__builtin_isfinite(v.z)) return kInitBad;
-    const float vx = dot(v, S.ex), vy = dot(v, S.ey);
-    L = sqrtf(fmaf(vx, vx, vy * vy));
+    float Llo;
+    uint32_t phi0;
+    start_direction(M, S.f, v, L, Llo, phi0);
     if (!(L > 0.f)) return kInitZero;
-    return enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, angle_fx(vx, vy), L, 0.f, st);
+    return enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, Llo, st);
 }
 
 // Starts a walk at chart point (ex, ey) of half-edge h (an end point of an
@@ -1196,13 +1206,13 @@ SG_HD __forceinline__ StateRec dead_state() {
 // The query's start frame, direction angle phi0 (chart of half-edge 3 f) and
 // length; |v_t| = 0 takes the chart's x-axis (e_u) as its direction.
 SG_HD __forceinline__ int bwd_query(const DevMesh& M, const BwdArgs& a, int64_t i, StartFrame& S, uint32_t& phi0,
-                                    float& L) {
+                                    float& L, float* Llo_out = nullptr) {
     if (start_frame(M, a.f[i], a.b + 3 * i, S) != kInitOk) return kInitBad;
     const float3 v = ld3(a.v + 3 * i);
     if (!__builtin_isfinite(v.x) || !__builtin_isfinite(v.y) || !__builtin_isfinite(v.z)) return kInitBad;
-    const float vx = dot(v, S.ex), vy = dot(v, S.ey);
-    L = sqrtf(fmaf(vx, vx, vy * vy));
-    phi0 = L > 0.f ? angle_fx(vx, vy) : 0u;
+    float Llo;
+    start_direction(M, S.f, v, L, Llo, phi0);
+    if (Llo_out) *Llo_out = Llo;
     return kInitOk;
 }
 
@@ -1225,19 +1235,20 @@ SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_
     uint32_t phi0;
     float L;
     Ray st;
-    if (bwd_query(M, a, i, S, phi0, L) != kInitOk) {
+    float Llo = 0.f;
+    if (bwd_query(M, a, i, S, phi0, L, &Llo) != kInitOk) {
         for (int j = 0; j < per_ray; ++j) out[j] = dead_state();
         return;
     }
-    out[0] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+    out[0] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, Llo, st) == kInitOk ? pack_state(st) : dead_state();
     if (per_ray == 1) return;
     const float ev = a.eps_v, ep = a.eps_p;
     // |v + eps e_perp| = L + eps^2 / (L + sqrt(L^2 + eps^2)), angle + atan(eps / L)
     const float Lp = sqrtf(fmaf(L, L, ev * ev));
     const float dl = ev * ev / (L + Lp);
     const uint32_t dphi = rad_to_fx(atan2f(ev, L));
-    out[1] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0 + dphi, L, dl, st) == kInitOk ? pack_state(st)
-                                                                                                 : dead_state();
+    out[1] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0 + dphi, L, Llo + dl, st) == kInitOk ? pack_state(st)
+                                                                                                       : dead_state();
     out[2] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, 0u, ep, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
     const uint32_t Av = rec_at(M, 3 * S.f).A;   // angle of e_v = unit(x2 - x0) in the chart
     out[3] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, Av, ep, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
@@ -1419,8 +1430,8 @@ SG_HD void gradx_init(const DevMesh& M, const BwdArgs& a, const StateRec* s1, in
     s3[at] = dead_state();
     StartFrame S;
     uint32_t phi0;
-    float L;
-    if (bwd_query(M, a, i, S, phi0, L) != kInitOk) return;
+    float L, Llo = 0.f;
+    if (bwd_query(M, a, i, S, phi0, L, &Llo) != kInitOk) return;
     const Final F0 = as_final(s1[(int64_t)stride * at]);
     if (F0.h < 0 || ((F0.flags >> 8) & 0xffu) != (uint32_t)kRayOk) return;
     float3 d3, n3;
@@ -1459,7 +1470,7 @@ SG_HD void gradx_init(const DevMesh& M, const BwdArgs& a, const StateRec* s1, in
     }
     if (!(L > 0.f)) return;
     Ray st;
-    if (enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, 0.f, st) != kInitOk) return;
+    if (enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, Llo, st) != kInitOk) return;
     s3[at] = pack_state(st);
     cvec[at] = c;
 }

@@ -414,3 +414,21 @@ def test_autotune(torch):
     torch.cuda.synchronize()
     for k in ("f", "b", "p", "v", "W", "status"):
         assert torch.equal(a[k], b[k]), k
+
+
+def test_config5_full_batch_sampled(torch):
+    """16,777,216 rays (|v| up to pi, the start frame transported) on the 1,310,720-face
+    noisy displaced icosphere in one call; every 4096th ray against the oracle."""
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(5)
+    r = CF.rays_config(5, X, F)
+    gm = sg.Mesh(X, F)
+    g = run(torch, gm, r)
+    n = r["f"].shape[0]
+    assert np.all(g["status"] == 0)
+    rows = np.arange(0, n, 4096)
+    om = oracle.Mesh(X, F)
+    o = om.exp(r["f"][rows], r["b"][rows], r["v"][rows], r["W"][rows])
+    gs = {k: (a[rows] if a is not None else None) for k, a in g.items()}
+    s = assert_parity(o, gs, om.mean_edge, K=2, label="config5")
+    assert s["hash_mis_far"] == 0

@@ -157,6 +157,34 @@ def _real_sph_harm(lmax, theta, phi):
     return np.concatenate(out)
 
 
+def _real_sph_harm_rec(lmax, theta, phi):
+    """The same functions as _real_sph_harm (same row order and signs), from the
+    standard three-term recurrences for fully normalised associated Legendre
+    functions; vectorised over points, for high degrees."""
+    x = np.cos(theta)
+    sx = np.sqrt(np.maximum(0.0, 1.0 - x * x))
+    # Pbar[l][m] = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!) P_l^m(x), without the Condon-Shortley phase
+    P = {(0, 0): np.full_like(x, np.sqrt(1.0 / (4.0 * np.pi)))}
+    for m in range(1, lmax + 1):
+        P[(m, m)] = np.sqrt((2.0 * m + 1.0) / (2.0 * m)) * sx * P[(m - 1, m - 1)]
+    for m in range(0, lmax):
+        P[(m + 1, m)] = np.sqrt(2.0 * m + 3.0) * x * P[(m, m)]
+    for m in range(0, lmax + 1):
+        for l in range(m + 2, lmax + 1):
+            a = np.sqrt((4.0 * l * l - 1.0) / (l * l - m * m))
+            b = np.sqrt(((l - 1.0) ** 2 - m * m) / (4.0 * (l - 1.0) ** 2 - 1.0))
+            P[(l, m)] = a * (x * P[(l - 1, m)] - b * P[(l - 2, m)])
+    cm = [np.cos(m * phi) for m in range(lmax + 1)]
+    sm = [np.sin(m * phi) for m in range(lmax + 1)]
+    out = []
+    for l in range(1, lmax + 1):
+        rows = [np.sqrt(2.0) * P[(l, mm)] * sm[mm] for mm in range(l, 0, -1)]
+        rows.append(P[(l, 0)])
+        rows += [np.sqrt(2.0) * P[(l, mm)] * cm[mm] for mm in range(1, l + 1)]
+        out.append(np.stack(rows))
+    return np.concatenate(out)
+
+
 def sh_displace(X, lmax: int, amplitude: float, rng):
     """r = 1 + amplitude * sum_{l=1..lmax} sum_m c_lm Y_lm(x_hat), c_lm ~ N(0, 1/l^2)."""
     X = np.asarray(X, dtype=np.float64)
@@ -167,8 +195,9 @@ def sh_displace(X, lmax: int, amplitude: float, rng):
     c = rng.normal(0.0, 1.0, ls.shape[0]) / ls
     r = np.ones(X.shape[0])
     chunk = 1 << 16
+    sh = _real_sph_harm if lmax <= 8 else _real_sph_harm_rec   # the recurrence for high degrees (speed)
     for s in range(0, X.shape[0], chunk):
-        Y = _real_sph_harm(lmax, theta[s:s + chunk], phi[s:s + chunk])
+        Y = sh(lmax, theta[s:s + chunk], phi[s:s + chunk])
         r[s:s + chunk] += amplitude * (c @ Y)
     return u * r[:, None]
 
