@@ -336,3 +336,22 @@ def test_backward_mesh_with_holes(torch, mode):
     got, _ = gpu_gradx(torch, sg.Mesh(X, F), r, gk)
     s = gradx_report(ref, got)
     assert s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, s
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_backward_klein_bottle(torch, mode):
+    """Extrinsic proxy, GFD and the vertex gradient on a non-orientable surface."""
+    from paper_2603_15780_amd import sg
+    from parity import gradx_report
+    X, F = M.canonical(*M.klein_bottle(96, 48))
+    rng = np.random.default_rng(43)
+    r = random_rays(X, F, 4096, rng, uniform_len(0.0, 3.0))
+    g = rng.standard_normal((4096, 3)).astype(np.float32)
+    check(torch, X, F, r, g, mode)
+    om = oracle.Mesh(X, F)
+    keep = margin_mask(om, r)
+    gk = np.where(keep[:, None], g, 0.0).astype(np.float32)
+    ref, _ = om.gradx(r["f"], r["b"], r["v"], gk)
+    got, _ = gpu_gradx(torch, sg.Mesh(X, F), r, gk, mode=mode, want_vjp=True)
+    s = gradx_report(ref, got)
+    assert s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, s

@@ -432,3 +432,15 @@ def test_config5_full_batch_sampled(torch):
     gs = {k: (a[rows] if a is not None else None) for k, a in g.items()}
     s = assert_parity(o, gs, om.mean_edge, K=2, label="config5")
     assert s["hash_mis_far"] == 0
+
+
+@pytest.mark.parametrize("kernel", [1, 2, 3])
+def test_non_orientable_surfaces(torch, kernel):
+    """Moebius strip (with boundary) and Klein bottle: no consistent orientation exists,
+    so the walk relies on the orientation parity carried across edges."""
+    for X, F in (M.mobius_strip(96, 12), M.klein_bottle(96, 48)):
+        X, F = M.canonical(X, F)
+        r = random_rays(X, F, 6000, np.random.default_rng(41), uniform_len(0.0, 4.0), K=2)
+        om, gm, o, g = both(torch, X, F, r, kernel=kernel)
+        s = assert_parity(o, g, om.mean_edge, K=2, label="non-orientable")
+        assert s["hash_mis_far"] == 0

@@ -166,10 +166,11 @@ def _test_meshes():
     X, F = M.icosphere(3)
     out.append(M.canonical(M.sh_displace(X, 6, 0.15, np.random.default_rng(7)), F))
     out.append(M.canonical(*M.torus_grid(36, 12, 0.2, np.random.default_rng(8))))
+    out.append(M.canonical(*M.klein_bottle(96, 48)))   # non-orientable: the carried normal flips
     return out
 
 
-@pytest.mark.parametrize("mi", [0, 1, 2])
+@pytest.mark.parametrize("mi", [0, 1, 2, 3])
 def test_invariants(mi, rng):
     X, F = _test_meshes()[mi]
     m = oracle.Mesh(X, F)
@@ -202,6 +203,17 @@ def test_invariants(mi, rng):
     p0 = (b0[:, :, None] * X.astype(np.float64)[F[r["f"][sel]]]).sum(1) / b0.sum(1)[:, None]
     assert np.abs(back["p"] - p0).max() < 1e-10
     assert np.all(back["n_cross"] == o["n_cross"][sel])
+
+
+def test_klein_bottle_is_non_orientable():
+    """Walks on the Klein bottle come back with the carried normal reversed
+    (sigma = -1) as often as not: no consistent face orientation exists."""
+    X, F = M.canonical(*M.klein_bottle(96, 48))
+    m = oracle.Mesh(X, F)
+    r = random_rays(X, F, 2000, np.random.default_rng(3), uniform_len(2.0, 8.0))
+    o = m.exp(r["f"], r["b"], r["v"])
+    assert np.all(o["status"] == 0)
+    assert 0.2 < np.mean(o["sigma"] < 0) < 0.8
 
 
 def test_reversal_reverses_face_sequence(rng):

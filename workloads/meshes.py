@@ -13,6 +13,7 @@ accuracy/performance section, F from about 10^3 to 10^6 faces):
   * sh_displace(...)            -- radial displacement by random real spherical harmonics
   * normal_noise(...)           -- i.i.d. offsets along area-weighted vertex normals
   * torus_grid(nu, nv, ...)     -- jittered (u, v) grid torus, R:r = 3:1
+  * mobius_strip, klein_bottle  -- non-orientable surfaces (no consistent face orientation exists)
   * tiny test meshes            -- tetrahedron, octahedron, cube grid, flat grid,
                                    polygonal prism (developable cylinder)
 """
@@ -22,7 +23,7 @@ import numpy as np
 
 __all__ = [
     "icosahedron", "icosphere", "geodesic_sphere", "sh_displace", "normal_noise",
-    "torus_grid", "tetrahedron", "octahedron", "cube_grid", "flat_grid", "prism",
+    "torus_grid", "mobius_strip", "klein_bottle", "tetrahedron", "octahedron", "cube_grid", "flat_grid", "prism",
     "canonical", "mean_edge", "orient_outward", "remove_faces",
 ]
 
@@ -217,6 +218,42 @@ def normal_noise(X, F, sigma_rel_edge: float, rng):
     X = np.asarray(X, dtype=np.float64)
     sig = sigma_rel_edge * mean_edge(X, F)
     return X + rng.normal(0.0, sig, X.shape[0])[:, None] * vertex_normals(X, F)
+
+
+def _twisted_grid(nu, nv, periodic_v):
+    """Faces of an nu x nv grid, periodic in u with the v index reflected across the
+    seam ((u + period, v) ~ (u, -v)); periodic or open in v."""
+    def vid(i, j):
+        if i == nu:
+            i, j = 0, (nv - 1 - j) if not periodic_v else (-j) % nv
+        return i * nv + (j % nv)
+    F = []
+    for i in range(nu):
+        for j in range(nv if periodic_v else nv - 1):
+            a, b, c, d = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
+            F += [(a, b, c), (a, c, d)]
+    return np.array(F, dtype=np.int64)
+
+
+def mobius_strip(nu: int, nw: int, R=1.0, width=0.6):
+    """Moebius strip: centre circle of radius R, a half twist along it, boundary on w = +-1."""
+    u = np.arange(nu) * (2 * np.pi / nu)
+    w = np.linspace(-1.0, 1.0, nw)
+    U, Wg = np.meshgrid(u, w, indexing="ij")
+    h = 0.5 * width * Wg
+    X = np.stack([(R + h * np.cos(U / 2)) * np.cos(U), (R + h * np.cos(U / 2)) * np.sin(U), h * np.sin(U / 2)], -1)
+    return X.reshape(-1, 3), _twisted_grid(nu, nw, periodic_v=False)
+
+
+def klein_bottle(nu: int, nv: int, r=2.0):
+    """Klein bottle, figure-8 immersion in R^3 (self-intersecting in space, a closed
+    non-orientable manifold as a mesh: the walk is intrinsic)."""
+    u = np.arange(nu) * (2 * np.pi / nu)
+    v = np.arange(nv) * (2 * np.pi / nv)
+    U, V = np.meshgrid(u, v, indexing="ij")
+    a = r + np.cos(U / 2) * np.sin(V) - np.sin(U / 2) * np.sin(2 * V)
+    X = np.stack([a * np.cos(U), a * np.sin(U), np.sin(U / 2) * np.sin(V) + np.cos(U / 2) * np.sin(2 * V)], -1)
+    return X.reshape(-1, 3), _twisted_grid(nu, nv, periodic_v=True)
 
 
 def torus_grid(nu: int, nv: int, jitter: float, rng, R=0.75, r=0.25):
