@@ -61,7 +61,7 @@ enum { SG_BWD_EP = 0, SG_BWD_GFD = 1 };
 enum {
     SG_KERNEL_AUTO = 0,         /* = SG_KERNEL_PERSISTENT */
     SG_KERNEL_PLAIN = 1,        /* one ray per lane, run to completion (Alg. gpu_parallel) */
-    SG_KERNEL_PERSISTENT = 2,   /* persistent waves refilled from one global ray queue */
+    SG_KERNEL_PERSISTENT = 2,   /* persistent waves refilled from ray queues (a share per XCD) */
     SG_KERNEL_PARTITIONED = 3   /* the mesh cut into 8 spatial parts, one per XCD: the walk runs in rounds (one
                                    launch each) in which the waves of XCD p walk the rays inside part p until
                                    they end or leave it, and rays that leave are queued for the next round;
@@ -80,6 +80,8 @@ typedef struct {
                               idle (of 128 ray slots with two rays per lane); <= 0: 32 per 64 slots */
     int32_t walk_blocks;   /* persistent kernel: 256-lane blocks launched; <= 0: three per CU */
     int32_t rays_per_lane; /* persistent kernel: rays each lane walks at once, 1 or 2; <= 0: tuned default */
+    int32_t ray_queues;    /* persistent kernel: ray queues the walk claims rays from, a multiple of 8 (an
+                              equal share of each XCD) up to 64; <= 0: 8 */
     void* workspace;       /* optional caller-owned device workspace, 256-byte aligned, at least the size
                               sg_exp_workspace_size / sg_backward_workspace_size report.  With it a call
                               allocates nothing, so it can be captured in a HIP graph (debug bit 2 aside).

@@ -143,6 +143,9 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     if (o.rays_per_lane > 2) return fail(SG_E_ARG, "rays_per_lane must be 1 or 2");
     if (o.refill_min <= 0) o.refill_min = 32 * o.rays_per_lane;
     if (o.refill_min > 64 * o.rays_per_lane) return fail(SG_E_ARG, "refill_min must be at most 64 per ray slot");
+    if (o.ray_queues <= 0) o.ray_queues = 8;
+    if (o.ray_queues % 8 != 0 || o.ray_queues > sg::kMaxQueues)
+        return fail(SG_E_ARG, "ray_queues must be a multiple of 8, at most %d", sg::kMaxQueues);
     // default schedule: three resident 256-lane blocks per CU, refill at 32 idle lanes (the
     // fastest in a sweep on the 327k-face workload)
     if (o.walk_blocks <= 0)
@@ -150,6 +153,8 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
                                                                                    : m->walk_blocks_per_cu);
     return SG_OK;
 }
+
+sg::WalkSched sched(const sg_opts& o) { return sg::WalkSched{o.walk_blocks, o.refill_min, o.ray_queues}; }
 
 // Workspace of a call: the caller's (checked) or a stream-ordered allocation.
 struct Workspace {
@@ -408,6 +413,7 @@ void sg_opts_default(sg_opts* o) {
     o->refill_min = 0;
     o->walk_blocks = 0;
     o->rays_per_lane = 0;
+    o->ray_queues = 0;
     o->workspace = nullptr;
     o->workspace_bytes = 0;
 }
@@ -530,8 +536,7 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
     }
     hipError_t e = part ? sg::launch_exp_partitioned(mesh->dev(), a, ws.p, o.walk_blocks, o.refill_min, st, ev.first,
                                                      ev.second)
-                        : sg::launch_exp_persistent(mesh->dev(), a, ws.p, o.walk_blocks, o.refill_min, st, ev.first,
-                                                    ev.second);
+                        : sg::launch_exp_persistent(mesh->dev(), a, ws.p, sched(o), st, ev.first, ev.second);
     if (ev.first) mesh->timed.push_back(ev);
     const hipError_t e2 = give_workspace(ws, st);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
@@ -573,7 +578,7 @@ int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, con
     rc = take_workspace(o, sg::bwd_workspace(n, mode, mesh->has_flip != 0, vjp, grad_X != nullptr, mesh->n_faces), st,
                         ws);
     if (rc != SG_OK) return rc;
-    hipError_t e = sg::launch_backward(mesh->dev(), a, ws.p, o.walk_blocks, o.refill_min, st);
+    hipError_t e = sg::launch_backward(mesh->dev(), a, ws.p, sched(o), st);
     const hipError_t e2 = give_workspace(ws, st);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     if (e2 != hipSuccess) return hip_fail(e2, "workspace release");

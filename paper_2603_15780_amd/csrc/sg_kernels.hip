@@ -686,6 +686,10 @@ static_assert(sizeof(StateRec) == 32, "state record is one 32-byte sector");
 // id out of range go to a last bucket.
 constexpr int kMaxBuckets = 8192;
 
+// Ray queues of the persistent walk (their use is described at queue_claim).
+constexpr int kQueueStride = 32;   // counters 256 bytes apart
+constexpr size_t kQueueBytes = (size_t)kMaxQueues * kQueueStride * sizeof(unsigned long long);
+
 int bucket_shift(int64_t n_faces) {
     int sh = 0;
     while (((n_faces - 1) >> sh) + 1 > kMaxBuckets) ++sh;
@@ -774,7 +778,7 @@ __global__ __launch_bounds__(256) void k_slot_place(DevMesh M, int64_t n, const 
 __global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* states, unsigned long long* counter,
                                               float* aux, const uint32_t* bstart, int32_t* slot, int shift, int nb) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *counter = 0ull;
+    if (i < kMaxQueues) counter[i * kQueueStride] = 0ull;
     if (i >= a.n) return;
     const int32_t at = (int32_t)bstart[ray_bucket(M, a.f[i], shift, nb)] + slot[i];
     slot[i] = at;
@@ -846,20 +850,66 @@ SG_HD __forceinline__ void gx_cross(double* acc, const Ray& st, const float4& c)
     add_f64(q + 4, (double)fmaf(ru, lm, -rm * lu));
 }
 
+// Ray queues of the persistent walk.  The walk slots (in spatial order) are
+// split into nq equal ranges, nq / 8 per XCD: blocks are dealt to the XCDs
+// round-robin, so block b runs on XCD b % 8 and starts on queue b % nq, one
+// of that XCD's.  Each XCD then works through its own region of the ray
+// order, and the claim atomics spread over nq counters on separate 256-byte
+// lines instead of serializing on one address.  A wave whose queue runs dry
+// moves on to the next one, first through its XCD's other queues, so every
+// queue is drained.  Queue q serves range j = (q % 8) * (nq / 8) + q / 8.
+struct QueueCursor {
+    int q;      // queue this wave claims from
+    int left;   // queues not yet seen empty; 0 once every queue is
+    int nq;
+};
+
+SG_HD __forceinline__ QueueCursor queue_start(int nq) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return QueueCursor{(int)(blockIdx.x % (unsigned)nq), nq, nq};
+#else
+    return QueueCursor{0, nq, nq};
+#endif
+}
+
+SG_HD __forceinline__ int queue_range(int q, int nq) { return (q & 7) * (nq >> 3) + (q >> 3); }
+
+// One claim of `want` consecutive slots by the whole wave (lane 0 does the
+// atomic).  Returns the first slot; slots at or past *hi belong to another
+// queue and are not this claim's.  When the claim reaches the end of its queue
+// the cursor moves on.
+__device__ __forceinline__ int64_t queue_claim(unsigned long long* ctr, int64_t n, int lane, int want, QueueCursor& c,
+                                               int64_t& hi) {
+    const int per = c.nq >> 3;
+    const int j = queue_range(c.q, c.nq);
+    const int64_t lo = n * j / c.nq;
+    hi = n * (j + 1) / c.nq;
+    unsigned long long b = 0ull;
+    if (lane == 0) b = atomicAdd(ctr + (size_t)c.q * kQueueStride, (unsigned long long)want);
+    b = __shfl(b, 0);
+    const int64_t first = lo + (int64_t)b;
+    if (first + want >= hi) {   // on to the next range in XCD-major order
+        const int jn = j + 1 == c.nq ? 0 : j + 1;
+        c.q = (jn % per) * 8 + jn / per;
+        --c.left;
+    }
+    return first;
+}
+
 // Persistent walk: each wave keeps 64 rays in flight and refills finished
-// lanes from a global queue (one atomic per wave per refill, ballot for the
+// lanes from the ray queues (one atomic per wave per refill, ballot for the
 // lane ranks), so short and long rays share lanes instead of idling behind
 // the longest ray of a fixed batch.  Between refills the wave runs a tight
 // loop of walk steps and re-ballots only to see whether enough lanes are idle.
 // With kGX every edge crossing also adds its vertex-gradient terms.
 template <bool kHash, bool kFlip, bool kGX>
 __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, int64_t n, unsigned long long* counter,
-                                          int32_t max_steps, float snap, int refill_min, const float4* cvec,
+                                          int32_t max_steps, float snap, int refill_min, int nq, const float4* cvec,
                                           double* acc) {
     const int lane = (int)(threadIdx.x & 63u);
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     bool active = false;
-    bool exhausted = false;
+    QueueCursor qc = queue_start(nq);
     int64_t q = 0;
     Ray st;
     st.h = 0; st.s = st.t = st.Lhi = st.Llo = st.bias = 0.f; st.phi = st.par = 0u; st.ncross = 0; st.hash = 0ull;
@@ -867,15 +917,13 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, in
     for (;;) {
         const uint64_t idle = __ballot(!active);
         const int nidle = __popcll(idle);
-        if (nidle == 64 && exhausted) break;
-        if (!exhausted && nidle >= refill_min) {
-            unsigned long long base = 0ull;
-            if (lane == 0) base = atomicAdd(counter, (unsigned long long)nidle);
-            base = __shfl(base, 0);
-            if (base + (unsigned long long)nidle >= (unsigned long long)n) exhausted = true;
+        if (nidle == 64 && qc.left == 0) break;
+        if (qc.left > 0 && nidle >= refill_min) {
+            int64_t hi = 0;
+            const int64_t base = queue_claim(counter, n, lane, nidle, qc, hi);
             if (!active) {
-                q = (int64_t)base + __popcll(idle & below);
-                if (q < n) {
+                q = base + __popcll(idle & below);
+                if (q < hi) {
                     const StateRec rec = states[q];
                     if (rec.h >= 0) {
                         unpack_state(rec, st);
@@ -886,8 +934,8 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, in
                 }
             }
         }
-        // walk until enough lanes are idle to refill (all of them once the queue is empty)
-        const int stop_at = exhausted ? 64 : refill_min;
+        // walk until enough lanes are idle to refill (all of them once the queues are empty)
+        const int stop_at = qc.left == 0 ? 64 : refill_min;
         for (;;) {
             if (active) {
                 Final fin;
@@ -910,10 +958,11 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, in
 // state (alive = false) whose results are dropped.
 template <bool kHash, bool kFlip>
 __device__ __forceinline__ void walk_loop2(const DevMesh& M, StateRec* states, int64_t n, unsigned long long* counter,
-                                           int32_t max_steps, float snap, int refill_min) {
+                                           int32_t max_steps, float snap, int refill_min, int nq) {
     const int lane = (int)(threadIdx.x & 63u);
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    bool a0 = false, a1 = false, exhausted = false;
+    bool a0 = false, a1 = false;
+    QueueCursor qc = queue_start(nq);
     int64_t q0 = 0, q1 = 0;
     Ray s0, s1;
     s0.h = 0; s0.s = s0.t = s0.Lhi = s0.Llo = s0.bias = 0.f; s0.phi = s0.par = 0u; s0.ncross = 0; s0.hash = 0ull;
@@ -921,15 +970,13 @@ __device__ __forceinline__ void walk_loop2(const DevMesh& M, StateRec* states, i
     for (;;) {
         const uint64_t i0 = __ballot(!a0), i1 = __ballot(!a1);
         const int n0 = __popcll(i0), nidle = n0 + __popcll(i1);
-        if (nidle == 128 && exhausted) break;
-        if (!exhausted && nidle >= refill_min) {
-            unsigned long long base = 0ull;
-            if (lane == 0) base = atomicAdd(counter, (unsigned long long)nidle);
-            base = __shfl(base, 0);
-            if (base + (unsigned long long)nidle >= (unsigned long long)n) exhausted = true;
+        if (nidle == 128 && qc.left == 0) break;
+        if (qc.left > 0 && nidle >= refill_min) {
+            int64_t hi = 0;
+            const int64_t base = queue_claim(counter, n, lane, nidle, qc, hi);
             if (!a0) {
-                q0 = (int64_t)base + __popcll(i0 & below);
-                if (q0 < n) {
+                q0 = base + __popcll(i0 & below);
+                if (q0 < hi) {
                     const StateRec rec = states[q0];
                     if (rec.h >= 0) {
                         unpack_state(rec, s0);
@@ -939,8 +986,8 @@ __device__ __forceinline__ void walk_loop2(const DevMesh& M, StateRec* states, i
                 }
             }
             if (!a1) {
-                q1 = (int64_t)base + n0 + __popcll(i1 & below);
-                if (q1 < n) {
+                q1 = base + n0 + __popcll(i1 & below);
+                if (q1 < hi) {
                     const StateRec rec = states[q1];
                     if (rec.h >= 0) {
                         unpack_state(rec, s1);
@@ -950,7 +997,7 @@ __device__ __forceinline__ void walk_loop2(const DevMesh& M, StateRec* states, i
                 }
             }
         }
-        const int stop_at = exhausted ? 128 : refill_min;
+        const int stop_at = qc.left == 0 ? 128 : refill_min;
         for (;;) {
             Final f0, f1;
             const int e0 = walk_step<kHash, kFlip>(M, s0, max_steps, snap, f0, a0);
@@ -970,29 +1017,29 @@ __device__ __forceinline__ void walk_loop2(const DevMesh& M, StateRec* states, i
 
 template <bool kHash, bool kFlip>
 __global__ __launch_bounds__(256) void k_walk2(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
-                                               int32_t max_steps, float snap, int refill_min) {
-    walk_loop2<kHash, kFlip>(M, states, n, counter, max_steps, snap, refill_min);
+                                               int32_t max_steps, float snap, int refill_min, int nq) {
+    walk_loop2<kHash, kFlip>(M, states, n, counter, max_steps, snap, refill_min, nq);
 }
 
 template <bool kHash, bool kFlip>
 __global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
-                                              int32_t max_steps, float snap, int refill_min) {
-    walk_loop<kHash, kFlip, false>(M, states, n, counter, max_steps, snap, refill_min, nullptr, nullptr);
+                                              int32_t max_steps, float snap, int refill_min, int nq) {
+    walk_loop<kHash, kFlip, false>(M, states, n, counter, max_steps, snap, refill_min, nq, nullptr, nullptr);
 }
 
 // The same walk over the backward's stacked chart states (its own symbol, so
 // profiles keep the forward's walk apart).
 template <bool kHash, bool kFlip>
 __global__ __launch_bounds__(256) void k_walk_bwd(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
-                                                  int32_t max_steps, float snap, int refill_min) {
-    walk_loop<false, kFlip, false>(M, states, n, counter, max_steps, snap, refill_min, nullptr, nullptr);
+                                                  int32_t max_steps, float snap, int refill_min, int nq) {
+    walk_loop<false, kFlip, false>(M, states, n, counter, max_steps, snap, refill_min, nq, nullptr, nullptr);
 }
 
 template <bool kFlip>
 __global__ __launch_bounds__(256) void k_walk_gx(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
-                                                 int32_t max_steps, float snap, int refill_min, const float4* cvec,
-                                                 double* acc) {
-    walk_loop<false, kFlip, true>(M, states, n, counter, max_steps, snap, refill_min, cvec, acc);
+                                                 int32_t max_steps, float snap, int refill_min, int nq,
+                                                 const float4* cvec, double* acc) {
+    walk_loop<false, kFlip, true>(M, states, n, counter, max_steps, snap, refill_min, nq, cvec, acc);
 }
 
 // ---------------------------------------------------------------- partitioned form
@@ -1565,7 +1612,9 @@ SG_ROW_KERNEL(k_gradx_init, gradx_init(M, a, s1, stride, s3, cvec, i), const Sta
               float4* cvec)
 #undef SG_ROW_KERNEL
 
-__global__ __launch_bounds__(64) void k_reset_counter(unsigned long long* c) { *c = 0ull; }
+__global__ __launch_bounds__(64) void k_reset_counter(unsigned long long* c) {
+    if (threadIdx.x < (unsigned)kMaxQueues) c[threadIdx.x * kQueueStride] = 0ull;
+}
 
 __global__ __launch_bounds__(256) void k_zero_f64(double* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -1599,7 +1648,7 @@ hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// states [n] | epilogue terms [n, 1 + 2K] | walk slots [n] | bucket counts [kMaxBuckets + 1] | queue counter
+// states [n] | epilogue terms [n, 1 + 2K] | walk slots [n] | bucket counts [kMaxBuckets + 1] | ray-queue counters
 struct PersistentLayout {
     size_t aux, slot, cnt, counter, total;
 };
@@ -1610,14 +1659,14 @@ static PersistentLayout persistent_layout(int64_t n, int32_t K) {
     L.aux = o; o = al(o + (size_t)n * (1 + 2 * (size_t)K) * sizeof(float));
     L.slot = o; o = al(o + (size_t)n * sizeof(int32_t));
     L.cnt = o; o = al(o + (size_t)(kMaxBuckets + 1) * sizeof(uint32_t));
-    L.counter = o; o = al(o + sizeof(unsigned long long));
+    L.counter = o; o = al(o + kQueueBytes);
     L.total = o;
     return L;
 }
 size_t exp_persistent_workspace(int64_t n, int32_t K) { return persistent_layout(n, K).total; }
 
-hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, int grid_blocks, int refill_min,
-                                 hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, const WalkSched& w, hipStream_t s,
+                                 hipEvent_t ev0, hipEvent_t ev1) {
     if (a.n <= 0) return hipSuccess;
     const int block = 256;
     const int64_t grid = (a.n + block - 1) / block;
@@ -1638,11 +1687,11 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, i
                        (const uint32_t*)cnt, slot, shift, nb);
     if (ev0) (void)hipEventRecord(ev0, s);
     if (a.rays_per_lane == 2)
-        SG_DISPATCH(k_walk2, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)grid_blocks), dim3(block), s, M,
-                    states, a.n, counter, a.max_steps, a.snap, refill_min);
+        SG_DISPATCH(k_walk2, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)w.blocks), dim3(block), s, M,
+                    states, a.n, counter, a.max_steps, a.snap, w.refill_min, w.queues);
     else
-        SG_DISPATCH(k_walk, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)grid_blocks), dim3(block), s, M,
-                    states, a.n, counter, a.max_steps, a.snap, refill_min);
+        SG_DISPATCH(k_walk, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)w.blocks), dim3(block), s, M,
+                    states, a.n, counter, a.max_steps, a.snap, w.refill_min, w.queues);
     if (ev1) (void)hipEventRecord(ev1, s);
     hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)nullptr,
                        (const float*)aux, (const int32_t*)slot);
@@ -1726,7 +1775,7 @@ static BwdLayout bwd_layout(int64_t n, int32_t mode, bool has_flip, bool vjp, bo
     L.acc = o; o = align256(o + (gradx ? 15 * (size_t)n_faces * sizeof(double) : 0));
     L.slot = o; o = align256(o + (walk ? (size_t)n * sizeof(int32_t) : 0));
     L.cnt = o; o = align256(o + (walk ? (size_t)(kMaxBuckets + 1) * sizeof(uint32_t) : 0));
-    L.counter = o; o = align256(o + sizeof(unsigned long long));
+    L.counter = o; o = align256(o + kQueueBytes);
     L.total = (walk || gradx) ? o : 0;
     return L;
 }
@@ -1735,8 +1784,7 @@ size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip, bool vjp, bool grad
     return bwd_layout(n, mode, has_flip, vjp, gradx, n_faces).total;
 }
 
-hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, int grid_blocks, int refill_min,
-                           hipStream_t s) {
+hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, const WalkSched& w, hipStream_t s) {
     BwdArgs a = a_in;
     if (a.n <= 0) return hipSuccess;
     const int block = 256;
@@ -1771,16 +1819,16 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, int 
     }
     // base walk (and, for GFD, the three perturbed walks that start at p)
     hipLaunchKernelGGL(k_bwd_stage1, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
-    SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)grid_blocks), dim3(block), s, M, s1, (int64_t)per1 * a.n,
-                counter, a.max_steps, a.snap, refill_min);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
+    SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)w.blocks), dim3(block), s, M, s1, (int64_t)per1 * a.n,
+                counter, a.max_steps, a.snap, w.refill_min, w.queues);
     if (vjp && a.mode == 0)
         hipLaunchKernelGGL(k_ep_walked, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
     if (gfd) {
         hipLaunchKernelGGL(k_bwd_stage2, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
-        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
-        SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)grid_blocks), dim3(block), s, M, s2, 3 * a.n, counter,
-                    a.max_steps, a.snap, refill_min);
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
+        SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)w.blocks), dim3(block), s, M, s2, 3 * a.n, counter,
+                    a.max_steps, a.snap, w.refill_min, w.queues);
         hipLaunchKernelGGL(k_gfd_assemble, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
     }
     if (gradx) {
@@ -1788,13 +1836,13 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, int 
         hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)std::min<int64_t>((nacc + block - 1) / block, 8192)), dim3(block),
                            0, s, acc, nacc);
         hipLaunchKernelGGL(k_gradx_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1, s3, cvec);
-        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
         if (flip)
-            k_walk_gx<true><<<dim3((unsigned)grid_blocks), dim3(block), 0, s>>>(M, s3, a.n, counter, a.max_steps, a.snap,
-                                                                                refill_min, cvec, acc);
+            k_walk_gx<true><<<dim3((unsigned)w.blocks), dim3(block), 0, s>>>(M, s3, a.n, counter, a.max_steps, a.snap,
+                                                                             w.refill_min, w.queues, cvec, acc);
         else
-            k_walk_gx<false><<<dim3((unsigned)grid_blocks), dim3(block), 0, s>>>(M, s3, a.n, counter, a.max_steps,
-                                                                                 a.snap, refill_min, cvec, acc);
+            k_walk_gx<false><<<dim3((unsigned)w.blocks), dim3(block), 0, s>>>(M, s3, a.n, counter, a.max_steps, a.snap,
+                                                                              w.refill_min, w.queues, cvec, acc);
         const int64_t nh = 3 * M.n_faces;
         hipLaunchKernelGGL(k_gradx_edges, dim3((unsigned)((nh + block - 1) / block)), dim3(block), 0, s, M, acc,
                            a.grad_X);

@@ -70,19 +70,26 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
 // Plain forward: one ray per lane, run to completion (Alg. gpu_parallel).
 hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s);
 
+// Schedule of a persistent walk launch.
+constexpr int kMaxQueues = 64;
+struct WalkSched {
+    int blocks;       // 256-lane blocks launched
+    int refill_min;   // idle lanes (of 64 per ray slot) that trigger a refill
+    int queues;       // ray queues: a multiple of 8, at most kMaxQueues
+};
+
 // Persistent forward: init kernel, persistent work-queue walk, finish kernel.
 // ws must hold exp_persistent_workspace(n, K) bytes of device memory.
 size_t exp_persistent_workspace(int64_t n, int32_t K);
 // ev0/ev1 (nullable) are recorded on s around the walk kernel.
-hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, int grid_blocks, int refill_min,
-                                 hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, const WalkSched& w, hipStream_t s,
+                                 hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 int walk_blocks_per_cu();
 int part_blocks_per_cu();
 
 // Backward of the exponential map (extrinsic proxy or geodesic finite differences).
 size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip, bool vjp, bool gradx, int64_t n_faces);
-hipError_t launch_backward(const DevMesh& M, const BwdArgs& a, void* ws, int grid_blocks, int refill_min,
-                           hipStream_t s);
+hipError_t launch_backward(const DevMesh& M, const BwdArgs& a, void* ws, const WalkSched& w, hipStream_t s);
 
 // Partitioned forward: the walk runs on the XCD whose L2 holds the ray's
 // current part of the mesh; rays crossing parts are handed over through queues.

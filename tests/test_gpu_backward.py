@@ -172,7 +172,8 @@ def test_deterministic_and_schedules(torch):
     g = rng.standard_normal((20000, 3)).astype(np.float32)
     gm = sg.Mesh(X, F)
     ref = gpu_bwd(torch, gm, sg.BWD_GFD, r, g)
-    for kw in ({}, dict(refill_min=1), dict(refill_min=64), dict(walk_blocks=7), dict(walk_blocks=3000, refill_min=32)):
+    for kw in ({}, dict(refill_min=1), dict(refill_min=64), dict(walk_blocks=7), dict(walk_blocks=3000, refill_min=32),
+               dict(ray_queues=64, walk_blocks=5)):
         out = gpu_bwd(torch, gm, sg.BWD_GFD, r, g, **kw)
         assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), kw
 

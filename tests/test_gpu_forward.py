@@ -252,18 +252,44 @@ def test_deterministic_and_kernels_agree(torch):
 
 
 @pytest.mark.parametrize("kernel", [2, 3])
-@pytest.mark.parametrize("refill_min,walk_blocks", [(1, 0), (64, 0), (16, 3), (8, 1), (32, 16)])
-def test_persistent_schedules(torch, kernel, refill_min, walk_blocks):
-    """Every refill threshold and grid size gives the same rays: the queues drain
-    fully, and rays handed between parts (or taken by idle parts) keep their state."""
+@pytest.mark.parametrize("refill_min,walk_blocks,ray_queues",
+                         [(1, 0, 0), (64, 0, 64), (16, 3, 16), (8, 1, 8), (32, 16, 64), (4, 5, 24)])
+def test_persistent_schedules(torch, kernel, refill_min, walk_blocks, ray_queues):
+    """Every refill threshold, grid size and queue count gives the same rays: the
+    queues drain fully (also those no block starts on), and rays handed between
+    parts (or taken by idle parts) keep their state."""
     from paper_2603_15780_amd import sg
     X, F = CF.mesh_config(1)
     gm = sg.Mesh(X, F)
     r = random_rays(X, F, 5000, np.random.default_rng(9), uniform_len(0.0, 3.0), K=1)
     a = run(torch, gm, r, kernel=1)
-    b = run(torch, gm, r, kernel=kernel, refill_min=refill_min, walk_blocks=walk_blocks)
+    b = run(torch, gm, r, kernel=kernel, refill_min=refill_min, walk_blocks=walk_blocks, ray_queues=ray_queues)
     for k in ("f", "b", "p", "v", "W", "status", "n_cross", "hash"):
         assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("n", [1, 3, 63, 64, 65, 200])
+def test_ray_queues_fewer_rays_than_queues(torch, n):
+    """Fewer rays than queues: most queue ranges are empty and every ray is still walked once."""
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    gm = sg.Mesh(X, F)
+    r = random_rays(X, F, n, np.random.default_rng(n), uniform_len(0.0, 3.0), K=1)
+    a = run(torch, gm, r, kernel=1)
+    for nq in (8, 64):
+        b = run(torch, gm, r, kernel=2, ray_queues=nq, walk_blocks=3, refill_min=1)
+        for k in ("f", "b", "p", "v", "W", "status", "n_cross", "hash"):
+            assert np.array_equal(a[k], b[k]), (nq, k)
+
+
+def test_ray_queues_rejected(torch):
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    gm = sg.Mesh(X, F)
+    r = random_rays(X, F, 64, np.random.default_rng(2), uniform_len(0.0, 1.0))
+    for nq in (12, 72):
+        with pytest.raises(RuntimeError, match="ray_queues"):
+            run(torch, gm, r, kernel=2, ray_queues=nq)
 
 
 @pytest.mark.parametrize("refill_min,walk_blocks", [(1, 0), (16, 0), (64, 7), (128, 3000)])
@@ -279,7 +305,8 @@ def test_two_rays_per_lane(torch, refill_min, walk_blocks, flip):
     gm = sg.Mesh(X, F)
     r = random_rays(X, F, 5000, np.random.default_rng(19), uniform_len(0.0, 3.0), K=1)
     a = run(torch, gm, r, kernel=1)
-    b = run(torch, gm, r, kernel=2, rays_per_lane=2, refill_min=refill_min, walk_blocks=walk_blocks)
+    b = run(torch, gm, r, kernel=2, rays_per_lane=2, refill_min=refill_min, walk_blocks=walk_blocks,
+            ray_queues=16 if flip else 0)
     for k in ("f", "b", "p", "v", "W", "status", "n_cross", "hash"):
         assert np.array_equal(a[k], b[k]), k
 
