@@ -123,7 +123,9 @@ int sg_mesh_info(sg_mesh mesh, double* mean_edge, int64_t* n_half_edges, size_t*
  *        point, v_out[n,3] = |v_t| * end tangent (v transported to p').
  *   optional (NULL to skip): status[n] int32, n_cross[n] int32 (needs
  *        debug bit 0), seq_hash[n] uint64 (needs debug bit 1).
- * opts may be NULL (defaults).  n = 0 is a no-op.
+ * opts may be NULL (defaults).  n = 0 is a no-op.  The persistent and
+ * partitioned kernels take n < 2^31 (SG_E_ARG otherwise); the plain kernel
+ * any n.
  */
 int sg_exp(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v,
            int32_t* f_out, float* b_out, float* p_out, float* v_out,
@@ -177,8 +179,8 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
  * Queries the forward rejects (SG_RAY_BADINPUT) get NaN in grad_v, grad_b.
  * Uses a stream-ordered device workspace (GFD 224 bytes per query, a re-walk
  * 32; grad_X 48 per query plus 120 per face).  opts: max_steps, vertex_snap,
- * eps_v, eps_p, refill_min, walk_blocks are honoured; kernel is ignored (the
- * persistent walk always runs).
+ * eps_v, eps_p, refill_min, walk_blocks, ray_queues are honoured; kernel is
+ * ignored (the persistent walk always runs).  n < 2^31 (SG_E_ARG otherwise).
  */
 int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b, const float* v,
                     const int32_t* f_out, const float* v_out, const float* g_p,

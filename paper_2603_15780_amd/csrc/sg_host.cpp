@@ -501,8 +501,8 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
     if (!f || !b || !v || !f_out || !b_out || !p_out || !v_out) return fail(SG_E_ARG, "a required array is NULL");
     if (K > 0 && (!W || !W_out)) return fail(SG_E_ARG, "W and W_out are required when K > 0");
     if ((o.debug & 2u) && !seq_hash) return fail(SG_E_ARG, "debug bit 1 needs seq_hash");
-    if (o.kernel == SG_KERNEL_PARTITIONED && n >= ((int64_t)1 << 31))
-        return fail(SG_E_ARG, "the partitioned walk takes fewer than 2^31 rays per call");
+    if (o.kernel != SG_KERNEL_PLAIN && n >= ((int64_t)1 << 31))
+        return fail(SG_E_ARG, "the persistent and partitioned walks take fewer than 2^31 rays per call");
     sg::ExpArgs a{};
     a.n = n;
     a.f = f; a.b = b; a.v = v;
@@ -557,6 +557,7 @@ int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, con
     if (o.kernel == SG_KERNEL_PARTITIONED) o.walk_blocks = mesh->cu_count * mesh->walk_blocks_per_cu;
     if (!(std::isfinite(o.eps_v) && std::isfinite(o.eps_p))) return fail(SG_E_ARG, "eps_v and eps_p must be finite");
     if (n == 0) return SG_OK;
+    if (n >= ((int64_t)1 << 31)) return fail(SG_E_ARG, "the backward takes fewer than 2^31 queries per call");
     if (!f || !b || !v || !g_p) return fail(SG_E_ARG, "a required array is NULL");
     const bool vjp = grad_v != nullptr;
     if (!vjp && !grad_X) return SG_OK;

@@ -690,14 +690,59 @@ constexpr int kMaxBuckets = 8192;
 constexpr int kQueueStride = 32;   // counters 256 bytes apart
 constexpr size_t kQueueBytes = (size_t)kMaxQueues * kQueueStride * sizeof(unsigned long long);
 
-int bucket_shift(int64_t n_faces) {
-    int sh = 0;
-    while (((n_faces - 1) >> sh) + 1 > kMaxBuckets) ++sh;
-    return sh;
+// The walk order: queue range j (nq ranges of equal internal-face counts, in
+// the spatial bisection order), then length class c (longest first), then
+// spatial sub-bucket.  Taking the long rays of a range first keeps the last
+// rays in flight short, so the waves drain quickly once the queues are empty.
+// Length classes are octaves of |v|^2 below the longest ray of the call, from
+// the difference of the float bit patterns (integer arithmetic, so every
+// kernel that recomputes a ray's bucket gets the same one).
+constexpr int kLenClasses = 8;
+constexpr int kVmaxWord = kMaxBuckets + 1;   // cnt[kVmaxWord]: float bits of the longest |v|^2
+
+struct RayOrder {
+    int nq;    // queue ranges
+    int sub;   // spatial sub-buckets per (range, class)
+    int nb;    // nq * kLenClasses * sub + 1 buckets (the last: face id out of range)
+};
+
+inline RayOrder ray_order(int nq) {
+    RayOrder o;
+    o.nq = nq;
+    o.sub = kMaxBuckets / (nq * kLenClasses);
+    o.nb = nq * kLenClasses * o.sub + 1;
+    return o;
 }
 
-SG_HD __forceinline__ int ray_bucket(const DevMesh& M, int32_t fu, int shift, int nb) {
-    return (fu >= 0 && (int64_t)fu < M.n_faces) ? (M.perm[fu] >> shift) : nb - 1;
+SG_HD __forceinline__ float len2(const float* v) { return fmaf(v[0], v[0], fmaf(v[1], v[1], v[2] * v[2])); }
+
+SG_HD __forceinline__ int ray_bucket(const DevMesh& M, int32_t fu, const float* v, const RayOrder& o, uint32_t vmax_bits) {
+    if (!(fu >= 0 && (int64_t)fu < M.n_faces)) return o.nb - 1;
+    const int64_t x = (int64_t)M.perm[fu] * o.nq;
+    const int64_t j = x / M.n_faces;
+    const int64_t sb = ((x - j * M.n_faces) * o.sub) / M.n_faces;
+    const float l2 = len2(v);
+    int c = 0;
+    if (l2 <= __uint_as_float(vmax_bits)) {   // (NaN, inf: class 0)
+        const uint32_t d = (vmax_bits - __float_as_uint(l2)) >> 23;
+        c = d < (uint32_t)kLenClasses ? (int)d : kLenClasses - 1;
+    }
+    return (int)((j * kLenClasses + c) * o.sub + sb);
+}
+
+// Longest finite |v|^2 of a call (one atomic per block on the float bits,
+// which order like the values for non-negative floats).
+__global__ __launch_bounds__(256) void k_len_max(int64_t n, const float* v, uint32_t* vmax_bits) {
+    __shared__ uint32_t part[4];
+    uint32_t m = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float l2 = len2(v + 3 * i);
+        if (l2 <= 3.0e38f) m = max(m, __float_as_uint(l2));
+    }
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    if ((threadIdx.x & 63u) == 0u) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(vmax_bits, max(max(part[0], part[1]), max(part[2], part[3])));
 }
 
 __global__ __launch_bounds__(256) void k_zero_u32(uint32_t* p, int n) {
@@ -711,9 +756,11 @@ __global__ __launch_bounds__(256) void k_zero_u32(uint32_t* p, int n) {
 // block's base in the bucket).
 constexpr int kBucketRays = 16384;
 
-__global__ __launch_bounds__(1024) void k_bucket_count(DevMesh M, int64_t n, const int32_t* f, uint32_t* cnt,
-                                                       int32_t* slot, int shift, int nb) {
+__global__ __launch_bounds__(1024) void k_bucket_count(DevMesh M, int64_t n, const int32_t* f, const float* v,
+                                                       uint32_t* cnt, int32_t* slot, RayOrder o) {
     __shared__ uint32_t local[kMaxBuckets + 1];
+    const int nb = o.nb;
+    const uint32_t vmax = cnt[kVmaxWord];
     const int t = (int)threadIdx.x;
     for (int b = t; b < nb; b += 1024) local[b] = 0u;
     __syncthreads();
@@ -724,7 +771,7 @@ __global__ __launch_bounds__(1024) void k_bucket_count(DevMesh M, int64_t n, con
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int64_t i = i0 + (int64_t)j * 1024 + t;
-        bk[j] = i < n ? ray_bucket(M, f[i], shift, nb) : -1;
+        bk[j] = i < n ? ray_bucket(M, f[i], v + 3 * i, o, vmax) : -1;
         rk[j] = bk[j] >= 0 ? atomicAdd(&local[bk[j]], 1u) : 0u;
     }
     __syncthreads();
@@ -765,10 +812,10 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(uint32_t* cnt, int nb) {
 }
 
 // slot[i] = bucket start + rank inside the bucket.
-__global__ __launch_bounds__(256) void k_slot_place(DevMesh M, int64_t n, const int32_t* f, const uint32_t* bstart,
-                                                    int32_t* slot, int shift, int nb) {
+__global__ __launch_bounds__(256) void k_slot_place(DevMesh M, int64_t n, const int32_t* f, const float* v,
+                                                    const uint32_t* bstart, int32_t* slot, RayOrder o) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) slot[i] = (int32_t)bstart[ray_bucket(M, f[i], shift, nb)] + slot[i];
+    if (i < n) slot[i] = (int32_t)bstart[ray_bucket(M, f[i], v + 3 * i, o, bstart[kVmaxWord])] + slot[i];
 }
 
 // Initial chart state of every ray, stored at its walk slot (slot[i] becomes
@@ -776,11 +823,11 @@ __global__ __launch_bounds__(256) void k_slot_place(DevMesh M, int64_t n, const 
 // components on the start frame) go to aux, so the epilogue does not revisit
 // the start face.
 __global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* states, unsigned long long* counter,
-                                              float* aux, const uint32_t* bstart, int32_t* slot, int shift, int nb) {
+                                              float* aux, const uint32_t* bstart, int32_t* slot, RayOrder o) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < kMaxQueues) counter[i * kQueueStride] = 0ull;
     if (i >= a.n) return;
-    const int32_t at = (int32_t)bstart[ray_bucket(M, a.f[i], shift, nb)] + slot[i];
+    const int32_t at = (int32_t)bstart[ray_bucket(M, a.f[i], a.v + 3 * i, o, bstart[kVmaxWord])] + slot[i];
     slot[i] = at;
     Ray st;
     float L = 0.f;
@@ -850,18 +897,26 @@ SG_HD __forceinline__ void gx_cross(double* acc, const Ray& st, const float4& c)
     add_f64(q + 4, (double)fmaf(ru, lm, -rm * lu));
 }
 
-// Ray queues of the persistent walk.  The walk slots (in spatial order) are
-// split into nq equal ranges, nq / 8 per XCD: blocks are dealt to the XCDs
-// round-robin, so block b runs on XCD b % 8 and starts on queue b % nq, one
-// of that XCD's.  Each XCD then works through its own region of the ray
-// order, and the claim atomics spread over nq counters on separate 256-byte
-// lines instead of serializing on one address.  A wave whose queue runs dry
-// moves on to the next one, first through its XCD's other queues, so every
-// queue is drained.  Queue q serves range j = (q % 8) * (nq / 8) + q / 8.
+// Ray queues of the persistent walk.  The walk slots are in the order of
+// ray_bucket, whose nq queue ranges are spatial regions (nq / 8 per XCD):
+// blocks are dealt to the XCDs round-robin, so block b runs on XCD b % 8 and
+// starts on queue b % nq, one of that XCD's.  Each XCD then works through its
+// own region, long rays first, and the claim atomics spread over nq counters
+// on separate 256-byte lines instead of serializing on one address.  A wave
+// whose queue runs dry moves on to the next one, first through its XCD's
+// other queues, so every queue is drained.  Queue q serves range
+// j = (q % 8) * (nq / 8) + q / 8, whose slots run from start[j * stride] to
+// start[(j + 1) * stride] (bucket starts), times `per` states per ray.
 struct QueueCursor {
     int q;      // queue this wave claims from
     int left;   // queues not yet seen empty; 0 once every queue is
     int nq;
+};
+
+struct QueueRanges {
+    const uint32_t* start;   // scanned bucket starts
+    int stride;              // buckets per queue range
+    int per;                 // walk states per ray
 };
 
 SG_HD __forceinline__ QueueCursor queue_start(int nq) {
@@ -878,12 +933,12 @@ SG_HD __forceinline__ int queue_range(int q, int nq) { return (q & 7) * (nq >> 3
 // atomic).  Returns the first slot; slots at or past *hi belong to another
 // queue and are not this claim's.  When the claim reaches the end of its queue
 // the cursor moves on.
-__device__ __forceinline__ int64_t queue_claim(unsigned long long* ctr, int64_t n, int lane, int want, QueueCursor& c,
-                                               int64_t& hi) {
+__device__ __forceinline__ int64_t queue_claim(unsigned long long* ctr, const QueueRanges& R, int lane, int want,
+                                               QueueCursor& c, int64_t& hi) {
     const int per = c.nq >> 3;
     const int j = queue_range(c.q, c.nq);
-    const int64_t lo = n * j / c.nq;
-    hi = n * (j + 1) / c.nq;
+    const int64_t lo = (int64_t)R.start[j * R.stride] * R.per;
+    hi = (int64_t)R.start[(j + 1) * R.stride] * R.per;
     unsigned long long b = 0ull;
     if (lane == 0) b = atomicAdd(ctr + (size_t)c.q * kQueueStride, (unsigned long long)want);
     b = __shfl(b, 0);
@@ -903,7 +958,7 @@ __device__ __forceinline__ int64_t queue_claim(unsigned long long* ctr, int64_t 
 // loop of walk steps and re-ballots only to see whether enough lanes are idle.
 // With kGX every edge crossing also adds its vertex-gradient terms.
 template <bool kHash, bool kFlip, bool kGX>
-__device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, int64_t n, unsigned long long* counter,
+__device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, QueueRanges R, unsigned long long* counter,
                                           int32_t max_steps, float snap, int refill_min, int nq, const float4* cvec,
                                           double* acc) {
     const int lane = (int)(threadIdx.x & 63u);
@@ -920,7 +975,7 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, in
         if (nidle == 64 && qc.left == 0) break;
         if (qc.left > 0 && nidle >= refill_min) {
             int64_t hi = 0;
-            const int64_t base = queue_claim(counter, n, lane, nidle, qc, hi);
+            const int64_t base = queue_claim(counter, R, lane, nidle, qc, hi);
             if (!active) {
                 q = base + __popcll(idle & below);
                 if (q < hi) {
@@ -957,8 +1012,9 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, in
 // memory system is not yet congested).  A slot without a ray steps a dummy
 // state (alive = false) whose results are dropped.
 template <bool kHash, bool kFlip>
-__device__ __forceinline__ void walk_loop2(const DevMesh& M, StateRec* states, int64_t n, unsigned long long* counter,
-                                           int32_t max_steps, float snap, int refill_min, int nq) {
+__device__ __forceinline__ void walk_loop2(const DevMesh& M, StateRec* states, QueueRanges R,
+                                           unsigned long long* counter, int32_t max_steps, float snap, int refill_min,
+                                           int nq) {
     const int lane = (int)(threadIdx.x & 63u);
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     bool a0 = false, a1 = false;
@@ -973,7 +1029,7 @@ __device__ __forceinline__ void walk_loop2(const DevMesh& M, StateRec* states, i
         if (nidle == 128 && qc.left == 0) break;
         if (qc.left > 0 && nidle >= refill_min) {
             int64_t hi = 0;
-            const int64_t base = queue_claim(counter, n, lane, nidle, qc, hi);
+            const int64_t base = queue_claim(counter, R, lane, nidle, qc, hi);
             if (!a0) {
                 q0 = base + __popcll(i0 & below);
                 if (q0 < hi) {
@@ -1016,30 +1072,31 @@ __device__ __forceinline__ void walk_loop2(const DevMesh& M, StateRec* states, i
 }
 
 template <bool kHash, bool kFlip>
-__global__ __launch_bounds__(256) void k_walk2(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
+__global__ __launch_bounds__(256) void k_walk2(DevMesh M, StateRec* states, QueueRanges R, unsigned long long* counter,
                                                int32_t max_steps, float snap, int refill_min, int nq) {
-    walk_loop2<kHash, kFlip>(M, states, n, counter, max_steps, snap, refill_min, nq);
+    walk_loop2<kHash, kFlip>(M, states, R, counter, max_steps, snap, refill_min, nq);
 }
 
 template <bool kHash, bool kFlip>
-__global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
+__global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, QueueRanges R, unsigned long long* counter,
                                               int32_t max_steps, float snap, int refill_min, int nq) {
-    walk_loop<kHash, kFlip, false>(M, states, n, counter, max_steps, snap, refill_min, nq, nullptr, nullptr);
+    walk_loop<kHash, kFlip, false>(M, states, R, counter, max_steps, snap, refill_min, nq, nullptr, nullptr);
 }
 
 // The same walk over the backward's stacked chart states (its own symbol, so
 // profiles keep the forward's walk apart).
 template <bool kHash, bool kFlip>
-__global__ __launch_bounds__(256) void k_walk_bwd(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
-                                                  int32_t max_steps, float snap, int refill_min, int nq) {
-    walk_loop<false, kFlip, false>(M, states, n, counter, max_steps, snap, refill_min, nq, nullptr, nullptr);
+__global__ __launch_bounds__(256) void k_walk_bwd(DevMesh M, StateRec* states, QueueRanges R,
+                                                  unsigned long long* counter, int32_t max_steps, float snap,
+                                                  int refill_min, int nq) {
+    walk_loop<false, kFlip, false>(M, states, R, counter, max_steps, snap, refill_min, nq, nullptr, nullptr);
 }
 
 template <bool kFlip>
-__global__ __launch_bounds__(256) void k_walk_gx(DevMesh M, StateRec* states, int64_t n, unsigned long long* counter,
+__global__ __launch_bounds__(256) void k_walk_gx(DevMesh M, StateRec* states, QueueRanges R, unsigned long long* counter,
                                                  int32_t max_steps, float snap, int refill_min, int nq,
                                                  const float4* cvec, double* acc) {
-    walk_loop<false, kFlip, true>(M, states, n, counter, max_steps, snap, refill_min, nq, cvec, acc);
+    walk_loop<false, kFlip, true>(M, states, R, counter, max_steps, snap, refill_min, nq, cvec, acc);
 }
 
 // ---------------------------------------------------------------- partitioned form
@@ -1648,7 +1705,7 @@ hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// states [n] | epilogue terms [n, 1 + 2K] | walk slots [n] | bucket counts [kMaxBuckets + 1] | ray-queue counters
+// states [n] | epilogue terms [n, 1 + 2K] | walk slots [n] | bucket counts [kMaxBuckets + 2] | ray-queue counters
 struct PersistentLayout {
     size_t aux, slot, cnt, counter, total;
 };
@@ -1658,12 +1715,25 @@ static PersistentLayout persistent_layout(int64_t n, int32_t K) {
     size_t o = al((size_t)n * sizeof(StateRec));
     L.aux = o; o = al(o + (size_t)n * (1 + 2 * (size_t)K) * sizeof(float));
     L.slot = o; o = al(o + (size_t)n * sizeof(int32_t));
-    L.cnt = o; o = al(o + (size_t)(kMaxBuckets + 1) * sizeof(uint32_t));
+    L.cnt = o; o = al(o + (size_t)(kMaxBuckets + 2) * sizeof(uint32_t));
     L.counter = o; o = al(o + kQueueBytes);
     L.total = o;
     return L;
 }
 size_t exp_persistent_workspace(int64_t n, int32_t K) { return persistent_layout(n, K).total; }
+
+// Bucket counts of the walk order (ray_bucket) and each ray's rank in its
+// bucket; cnt (kMaxBuckets + 2 words) ends with the exclusive bucket starts.
+static void order_rays(const DevMesh& M, int64_t n, const int32_t* f, const float* v, uint32_t* cnt, int32_t* slot,
+                       const RayOrder& ord, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((kMaxBuckets + 2 + 255) / 256)), dim3(256), 0, s, cnt,
+                       kMaxBuckets + 2);
+    hipLaunchKernelGGL(k_len_max, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 256)), dim3(256), 0, s, n, v,
+                       cnt + kVmaxWord);
+    hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)((n + kBucketRays - 1) / kBucketRays)), dim3(1024), 0, s, M, n, f,
+                       v, cnt, slot, ord);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, cnt, ord.nb);
+}
 
 hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, const WalkSched& w, hipStream_t s,
                                  hipEvent_t ev0, hipEvent_t ev1) {
@@ -1677,21 +1747,18 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, c
     auto* slot = reinterpret_cast<int32_t*>(p + L.slot);
     auto* cnt = reinterpret_cast<uint32_t*>(p + L.cnt);
     auto* counter = reinterpret_cast<unsigned long long*>(p + L.counter);
-    const int shift = bucket_shift(M.n_faces);
-    const int nb = (int)(((M.n_faces - 1) >> shift) + 2);   // start-face buckets + one for bad face ids
-    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, cnt, nb);
-    hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)((a.n + kBucketRays - 1) / kBucketRays)), dim3(1024), 0, s, M, a.n,
-                       a.f, cnt, slot, shift, nb);
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, cnt, nb);
+    const RayOrder ord = ray_order(w.queues);
+    order_rays(M, a.n, a.f, a.v, cnt, slot, ord, s);
     hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, counter, aux,
-                       (const uint32_t*)cnt, slot, shift, nb);
+                       (const uint32_t*)cnt, slot, ord);
+    const QueueRanges R{cnt, kLenClasses * ord.sub, 1};
     if (ev0) (void)hipEventRecord(ev0, s);
     if (a.rays_per_lane == 2)
         SG_DISPATCH(k_walk2, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)w.blocks), dim3(block), s, M,
-                    states, a.n, counter, a.max_steps, a.snap, w.refill_min, w.queues);
+                    states, R, counter, a.max_steps, a.snap, w.refill_min, w.queues);
     else
         SG_DISPATCH(k_walk, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)w.blocks), dim3(block), s, M,
-                    states, a.n, counter, a.max_steps, a.snap, w.refill_min, w.queues);
+                    states, R, counter, a.max_steps, a.snap, w.refill_min, w.queues);
     if (ev1) (void)hipEventRecord(ev1, s);
     hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)nullptr,
                        (const float*)aux, (const int32_t*)slot);
@@ -1774,7 +1841,7 @@ static BwdLayout bwd_layout(int64_t n, int32_t mode, bool has_flip, bool vjp, bo
     L.cvec = o; o = align256(o + (gradx ? (size_t)n * sizeof(float4) : 0));
     L.acc = o; o = align256(o + (gradx ? 15 * (size_t)n_faces * sizeof(double) : 0));
     L.slot = o; o = align256(o + (walk ? (size_t)n * sizeof(int32_t) : 0));
-    L.cnt = o; o = align256(o + (walk ? (size_t)(kMaxBuckets + 1) * sizeof(uint32_t) : 0));
+    L.cnt = o; o = align256(o + (walk ? (size_t)(kMaxBuckets + 2) * sizeof(uint32_t) : 0));
     L.counter = o; o = align256(o + kQueueBytes);
     L.total = (walk || gradx) ? o : 0;
     return L;
@@ -1804,31 +1871,28 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
     auto* acc = reinterpret_cast<double*>(base + L.acc);
     auto* counter = reinterpret_cast<unsigned long long*>(base + L.counter);
     const int per1 = gfd ? 4 : 1;
-    {   // walk the queries in the spatial order of their start faces
+    auto* cnt = reinterpret_cast<uint32_t*>(base + L.cnt);
+    const RayOrder ord = ray_order(w.queues);
+    {   // walk the queries in the order of ray_bucket (region, longest first, start face)
         auto* slot = reinterpret_cast<int32_t*>(base + L.slot);
-        auto* cnt = reinterpret_cast<uint32_t*>(base + L.cnt);
-        const int shift = bucket_shift(M.n_faces);
-        const int nb = (int)(((M.n_faces - 1) >> shift) + 2);
-        hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, cnt, nb);
-        hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)((a.n + kBucketRays - 1) / kBucketRays)), dim3(1024), 0, s,
-                           M, a.n, a.f, cnt, slot, shift, nb);
-        hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, cnt, nb);
-        hipLaunchKernelGGL(k_slot_place, dim3((unsigned)grid), dim3(block), 0, s, M, a.n, a.f, (const uint32_t*)cnt,
-                           slot, shift, nb);
+        order_rays(M, a.n, a.f, a.v, cnt, slot, ord, s);
+        hipLaunchKernelGGL(k_slot_place, dim3((unsigned)grid), dim3(block), 0, s, M, a.n, a.f, a.v,
+                           (const uint32_t*)cnt, slot, ord);
         a.slot = slot;
     }
     // base walk (and, for GFD, the three perturbed walks that start at p)
     hipLaunchKernelGGL(k_bwd_stage1, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
-    SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)w.blocks), dim3(block), s, M, s1, (int64_t)per1 * a.n,
+    const int stride = kLenClasses * ord.sub;
+    SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)w.blocks), dim3(block), s, M, s1, QueueRanges{cnt, stride, per1},
                 counter, a.max_steps, a.snap, w.refill_min, w.queues);
     if (vjp && a.mode == 0)
         hipLaunchKernelGGL(k_ep_walked, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
     if (gfd) {
         hipLaunchKernelGGL(k_bwd_stage2, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
-        SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)w.blocks), dim3(block), s, M, s2, 3 * a.n, counter,
-                    a.max_steps, a.snap, w.refill_min, w.queues);
+        SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)w.blocks), dim3(block), s, M, s2,
+                    QueueRanges{cnt, stride, 3}, counter, a.max_steps, a.snap, w.refill_min, w.queues);
         hipLaunchKernelGGL(k_gfd_assemble, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
     }
     if (gradx) {
@@ -1838,11 +1902,11 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
         hipLaunchKernelGGL(k_gradx_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1, s3, cvec);
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
         if (flip)
-            k_walk_gx<true><<<dim3((unsigned)w.blocks), dim3(block), 0, s>>>(M, s3, a.n, counter, a.max_steps, a.snap,
-                                                                             w.refill_min, w.queues, cvec, acc);
+            k_walk_gx<true><<<dim3((unsigned)w.blocks), dim3(block), 0, s>>>(
+                M, s3, QueueRanges{cnt, stride, 1}, counter, a.max_steps, a.snap, w.refill_min, w.queues, cvec, acc);
         else
-            k_walk_gx<false><<<dim3((unsigned)w.blocks), dim3(block), 0, s>>>(M, s3, a.n, counter, a.max_steps, a.snap,
-                                                                              w.refill_min, w.queues, cvec, acc);
+            k_walk_gx<false><<<dim3((unsigned)w.blocks), dim3(block), 0, s>>>(
+                M, s3, QueueRanges{cnt, stride, 1}, counter, a.max_steps, a.snap, w.refill_min, w.queues, cvec, acc);
         const int64_t nh = 3 * M.n_faces;
         hipLaunchKernelGGL(k_gradx_edges, dim3((unsigned)((nh + block - 1) / block)), dim3(block), 0, s, M, acc,
                            a.grad_X);
