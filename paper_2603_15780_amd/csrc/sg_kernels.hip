@@ -137,7 +137,7 @@ SG_HD __forceinline__ void sincos_full(uint32_t phi, float& sn, float& cs) {
 
 // Rounds an angle in radians (|a| < pi) to fixed point with a split constant.
 SG_HD __forceinline__ uint32_t rad_to_fx(float a) {
-    const float khi = 683565248.0f, klo = 27.576362f;   // 2^32 / (2 pi) as a float pair
+    const float khi = 683565248.0f, klo = 27.576432f;   // 2^32 / (2 pi) as a float pair
     const float p = a * khi;
     const float e = fmaf(a, khi, -p) + a * klo;
     const float pr = rintf(p);
@@ -239,34 +239,145 @@ SG_HD __forceinline__ int start_frame(const DevMesh& M, int32_t fu, const float*
     return kInitOk;
 }
 
+// ---------------------------------------------------------------- float-float arithmetic
+// A value is an unevaluated sum hi + lo of two floats (about 48 significant
+// bits).  Built from the error-free transformations TwoSum (Knuth) and the
+// FMA-based TwoProd (Ogita, Rump and Oishi, "Accurate sum and dot product",
+// 2005), in the style of Dekker's and Bailey's double-length arithmetic.
+// Used once per ray, where float32 alone would cost the walk 1e-7 of its
+// start angle and length.
+struct ff {
+    float hi, lo;
+};
+
+SG_HD __forceinline__ ff two_sum(float a, float b) {
+    const float s = a + b;
+    const float bb = s - a;
+    return ff{s, (a - (s - bb)) + (b - bb)};
+}
+SG_HD __forceinline__ ff fast_two_sum(float a, float b) {   // |a| >= |b|
+    const float s = a + b;
+    return ff{s, b - (s - a)};
+}
+SG_HD __forceinline__ ff two_prod(float a, float b) {
+    const float p = a * b;
+    return ff{p, fmaf(a, b, -p)};
+}
+SG_HD __forceinline__ ff ff_add(ff x, ff y) {
+    const ff s = two_sum(x.hi, y.hi);
+    return fast_two_sum(s.hi, s.lo + (x.lo + y.lo));
+}
+SG_HD __forceinline__ ff ff_neg(ff x) { return ff{-x.hi, -x.lo}; }
+SG_HD __forceinline__ ff ff_sub(ff x, ff y) { return ff_add(x, ff_neg(y)); }
+SG_HD __forceinline__ ff ff_mul(ff x, ff y) {
+    const ff p = two_prod(x.hi, y.hi);
+    return fast_two_sum(p.hi, fmaf(x.hi, y.lo, fmaf(x.lo, y.hi, p.lo)));
+}
+SG_HD __forceinline__ ff ff_mulf(ff x, float b) {
+    const ff p = two_prod(x.hi, b);
+    return fast_two_sum(p.hi, fmaf(x.lo, b, p.lo));
+}
+SG_HD __forceinline__ ff ff_div(ff x, ff y) {
+    const float q1 = x.hi / y.hi;
+    const ff r = ff_sub(x, ff_mulf(y, q1));
+    return fast_two_sum(q1, r.hi / y.hi);
+}
+SG_HD __forceinline__ ff ff_sqrt(ff x) {   // x >= 0
+    if (!(x.hi > 0.f)) return ff{0.f, 0.f};
+    const float s = sqrtf(x.hi);
+    const ff p = two_prod(s, s);
+    return fast_two_sum(s, (((x.hi - p.hi) - p.lo) + x.lo) / (2.0f * s));
+}
+SG_HD __forceinline__ ff ff_abs(ff x) { return x.hi < 0.f ? ff_neg(x) : x; }
+SG_HD __forceinline__ bool ff_gt(ff x, ff y) { return x.hi > y.hi || (x.hi == y.hi && x.lo > y.lo); }
+
+// atan of t in [0, 1]: atan(t) = atan(c) + atan(r) with c = k / 8 nearest to t,
+// r = (t - c) / (1 + t c) in [-1/16, 1/16], and atan(r) = r (1 - r^2/3 + ...)
+// summed to r^11 (truncation below 3e-16).  atan(k / 8) as float pairs.
+SG_HD __forceinline__ ff ff_atan01(ff t) {
+    constexpr float kAtanHi[9] = {0.0f, 0x1.fd5baap-4f, 0x1.f5b760p-3f, 0x1.6f6194p-2f, 0x1.dac670p-2f,
+                                  0x1.1e00bap-1f, 0x1.4978fap-1f, 0x1.700a7cp-1f, 0x1.921fb6p-1f};
+    constexpr float kAtanLo[9] = {0.0f, -0x1.54f424p-30f, -0x1.b4dfc8p-29f, 0x1.e4def0p-30f, 0x1.586ed4p-28f,
+                                  0x1.7bdfd6p-26f, 0x1.934f70p-28f, 0x1.5e118cp-27f, -0x1.777a5cp-26f};
+    const int k = (int)rintf(t.hi * 8.0f);
+    const float c = 0.125f * (float)k;
+    const ff r = ff_div(ff_add(t, ff{-c, 0.f}), ff_add(ff{1.0f, 0.f}, ff_mulf(t, c)));
+    const float r2 = r.hi * r.hi;
+    float q = -1.0f / 11.0f;
+    q = fmaf(q, r2, 1.0f / 9.0f);
+    q = fmaf(q, r2, -1.0f / 7.0f);
+    q = fmaf(q, r2, 1.0f / 5.0f);
+    q = fmaf(q, r2, -1.0f / 3.0f);
+    q *= r2;   // atan(r) = r + r q, |r q| <= 1.3e-3 |r|
+    const ff at = ff_add(r, two_prod(r.hi, q));
+    return ff_add(ff{kAtanHi[k], kAtanLo[k]}, at);
+}
+
+// atan2(y, x) in (-pi, pi] from octant reduction and ff_atan01.
+SG_HD __forceinline__ ff ff_atan2(ff y, ff x) {
+    const ff kPi{0x1.921fb6p+1f, -0x1.777a5cp-24f}, kHalfPi{0x1.921fb6p+0f, -0x1.777a5cp-25f};
+    const ff ax = ff_abs(x), ay = ff_abs(y);
+    const bool swap = ff_gt(ay, ax);
+    if (!(ax.hi > 0.f) && !(ay.hi > 0.f)) return ff{0.f, 0.f};
+    ff a = ff_atan01(swap ? ff_div(ax, ay) : ff_div(ay, ax));
+    if (swap) a = ff_sub(kHalfPi, a);
+    if (x.hi < 0.f) a = ff_sub(kPi, a);
+    if (y.hi < 0.f) a = ff_neg(a);
+    return a;
+}
+
 // initialise_trace (Alg. gpu_parallel): v is projected onto the start face;
-// its angle to the chart's x-axis and its length start the walk.
-// v projected onto the start face, in float64 (once per ray): its length as
-// a float pair Lhi + Llo and its angle to the chart's x-axis in fixed point,
-// each rounded once.  In float32 these two would carry relative errors of
-// about 1e-7, i.e. endpoint errors of 3e-7 at |v| = pi, along and across the
-// ray; the walk itself keeps its errors near 1e-8.
+// its angle to the chart's x-axis and its length start the walk.  With
+// e1 = x1 - x0, e2 = x2 - x0, n = e1 x e2, D = |n| and w = n x e1, the
+// components of v on the chart frame (e1 / |e1|, w / |w|) are B / |e1| and
+// A / (|e1| D), where B = v.e1 and A = v.w.  They are evaluated in
+// float-float from the float32 positions (the edge vectors exactly; D from
+// the cross product, which keeps slim faces accurate), giving the length as a
+// float pair Lhi + Llo and the angle atan2(A, B D) rounded once to fixed
+// point.  In float32 the two would carry relative errors of about 1e-7, i.e.
+// endpoint errors of 3e-7 at |v| = pi, along and across the ray; the walk
+// itself keeps its errors near 1e-8.
 SG_HD __forceinline__ void start_direction(const DevMesh& M, int32_t f, float3 vf, float& Lhi, float& Llo,
                                            uint32_t& phi0) {
     const int64_t f3 = 3 * (int64_t)f;
     const float* p0 = M.X + 3 * (int64_t)M.F[f3];
     const float* p1 = M.X + 3 * (int64_t)M.F[f3 + 1];
     const float* p2 = M.X + 3 * (int64_t)M.F[f3 + 2];
-    const double e1x = (double)p1[0] - p0[0], e1y = (double)p1[1] - p0[1], e1z = (double)p1[2] - p0[2];
-    const double e2x = (double)p2[0] - p0[0], e2y = (double)p2[1] - p0[1], e2z = (double)p2[2] - p0[2];
-    const double il = 1.0 / sqrt(e1x * e1x + e1y * e1y + e1z * e1z);
-    const double ux = e1x * il, uy = e1y * il, uz = e1z * il;
-    double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
-    const double inn = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
-    nx *= inn; ny *= inn; nz *= inn;
-    const double wx = ny * uz - nz * uy, wy = nz * ux - nx * uz, wz = nx * uy - ny * ux;   // n x u
-    const double vx = vf.x * ux + vf.y * uy + vf.z * uz;
-    const double vy = vf.x * wx + vf.y * wy + vf.z * wz;
-    const double L = sqrt(vx * vx + vy * vy);
-    Lhi = (float)L;
-    Llo = (float)(L - (double)Lhi);
-    const double a = L > 0.0 ? atan2(vy, vx) : 0.0;   // (-pi, pi]
-    phi0 = (uint32_t)(int64_t)__builtin_rint(a * kFxPerRad);
+    const float v[3] = {vf.x, vf.y, vf.z};
+    ff e1[3], e2[3];
+    for (int c = 0; c < 3; ++c) {
+        e1[c] = two_sum(p1[c], -p0[c]);
+        e2[c] = two_sum(p2[c], -p0[c]);
+    }
+    ff n[3], w[3];
+    for (int c = 0; c < 3; ++c) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        n[c] = ff_sub(ff_mul(e1[c1], e2[c2]), ff_mul(e1[c2], e2[c1]));
+    }
+    for (int c = 0; c < 3; ++c) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        w[c] = ff_sub(ff_mul(n[c1], e1[c2]), ff_mul(n[c2], e1[c1]));
+    }
+    ff A{0.f, 0.f}, B{0.f, 0.f}, g11{0.f, 0.f}, D2{0.f, 0.f};
+    for (int c = 0; c < 3; ++c) {
+        A = ff_add(A, ff_mulf(w[c], v[c]));
+        B = ff_add(B, ff_mulf(e1[c], v[c]));
+        g11 = ff_add(g11, ff_mul(e1[c], e1[c]));
+        D2 = ff_add(D2, ff_mul(n[c], n[c]));
+    }
+    const ff D = ff_sqrt(D2);
+    const ff X = ff_mul(B, D);
+    // |v_t|^2 = (B^2 D^2 + A^2) / (|e1|^2 D^2)
+    const ff L = ff_sqrt(ff_div(ff_add(ff_mul(X, X), ff_mul(A, A)), ff_mul(g11, D2)));
+    Lhi = L.hi;
+    Llo = L.lo;
+    phi0 = 0u;
+    if (L.hi > 0.f) {
+        const ff kFxPerRadFF{0x1.45f306p+29f, 0x1.b93910p+4f};   // 2^32 / (2 pi)
+        const ff q = ff_mul(ff_atan2(A, X), kFxPerRadFF);       // in (-2^31, 2^31]
+        const int64_t base = (int64_t)q.hi;                      // q.hi is integral once |q.hi| >= 2^23
+        phi0 = (uint32_t)(base + (int64_t)rintf((q.hi - (float)base) + q.lo));
+    }
 }
 
 SG_HD int ray_init(const DevMesh& M, int32_t fu, const float* bp, const float* vp, Ray& st, float& L) {
