@@ -36,7 +36,7 @@ def lib():
         L.or_mesh_mean_edge.restype = C.c_double
         L.or_mesh_theta.argtypes = [P, P]
         L.or_last_error.restype = C.c_char_p
-        L.or_exp_batch.argtypes = [P, C.c_int64, P, P, P, C.c_int32, P, P] + [P] * 11 + [C.c_int32]
+        L.or_exp_batch.argtypes = [P, C.c_int64, P, P, P, C.c_int32, P, P] + [P] * 12 + [C.c_int32]
         L.or_exp_batch.restype = C.c_int
         L.or_exp_trace.argtypes = [P, C.c_int32, P, P, P, C.c_int32] + [P] * 8
         L.or_exp_trace.restype = C.c_int32
@@ -51,7 +51,7 @@ def lib():
 
 
 class Opts(C.Structure):
-    _fields_ = [("max_steps", C.c_int32), ("vertex_snap", C.c_double)]
+    _fields_ = [("max_steps", C.c_int32), ("vertex_snap", C.c_double), ("boundary_mode", C.c_int32)]
 
 
 def _p(a):
@@ -95,10 +95,10 @@ class Mesh:
         return t
 
     @staticmethod
-    def opts(max_steps=1 << 20, vertex_snap=1e-10):
-        return Opts(max_steps, vertex_snap)
+    def opts(max_steps=1 << 20, vertex_snap=1e-10, boundary_mode=0):
+        return Opts(max_steps, vertex_snap, boundary_mode)
 
-    def exp(self, f, b, v, W=None, max_steps=1 << 20, vertex_snap=1e-10, nthreads=0):
+    def exp(self, f, b, v, W=None, max_steps=1 << 20, vertex_snap=1e-10, boundary_mode=0, nthreads=0):
         f = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
         n = f.shape[0]
         b = np.ascontiguousarray(b, dtype=np.float64).reshape(n, 3)
@@ -111,18 +111,18 @@ class Mesh:
             f=np.zeros(n, np.int32), b=np.zeros((n, 3)), p=np.zeros((n, 3)), v=np.zeros((n, 3)),
             W=np.zeros((n, K, 3)), status=np.zeros(n, np.int32), n_cross=np.zeros(n, np.int32),
             hash=np.zeros(n, np.uint64), min_vdist=np.zeros(n), traced=np.zeros(n),
-            sigma=np.zeros(n, np.int8))
-        o = Opts(max_steps, vertex_snap)
+            sigma=np.zeros(n, np.int8), n_bnd=np.zeros(n, np.int32))
+        o = Opts(max_steps, vertex_snap, boundary_mode)
         rc = lib().or_exp_batch(
             self._h, n, _p(f), _p(b), _p(v), K, _p(W) if K else None, C.byref(o),
             _p(out["f"]), _p(out["b"]), _p(out["p"]), _p(out["v"]), _p(out["W"]) if K else None,
             _p(out["status"]), _p(out["n_cross"]), _p(out["hash"]), _p(out["min_vdist"]),
-            _p(out["traced"]), _p(out["sigma"]), nthreads)
+            _p(out["traced"]), _p(out["sigma"]), _p(out["n_bnd"]), nthreads)
         if rc != 0:
             raise OracleError(rc, lib().or_last_error().decode())
         return out
 
-    def trace(self, f, b, v, cap=100000, max_steps=1 << 20, vertex_snap=1e-10):
+    def trace(self, f, b, v, cap=100000, max_steps=1 << 20, vertex_snap=1e-10, boundary_mode=0):
         kind = np.zeros(cap, np.int8)
         face = np.zeros(cap, np.int32)
         e0 = np.zeros(cap, np.int32)
@@ -133,13 +133,13 @@ class Mesh:
         po = np.zeros(3)
         b = np.ascontiguousarray(b, dtype=np.float64)
         v = np.ascontiguousarray(v, dtype=np.float64)
-        o = Opts(max_steps, vertex_snap)
+        o = Opts(max_steps, vertex_snap, boundary_mode)
         k = lib().or_exp_trace(self._h, int(f), _p(b), _p(v), C.byref(o), cap, _p(kind), _p(face),
                                _p(e0), _p(e1), _p(pt), C.byref(fo), _p(po), C.byref(st))
         return dict(kind=kind[:k], face=face[:k], e0=e0[:k], e1=e1[:k], point=pt[:k],
                     f=fo.value, p=po, status=st.value)
 
-    def ep(self, f, b, v, g, max_steps=1 << 20, vertex_snap=1e-10, nthreads=0):
+    def ep(self, f, b, v, g, max_steps=1 << 20, vertex_snap=1e-10, boundary_mode=0, nthreads=0):
         f = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
         n = f.shape[0]
         b = np.ascontiguousarray(b, dtype=np.float64).reshape(n, 3)
@@ -147,13 +147,13 @@ class Mesh:
         g = np.ascontiguousarray(g, dtype=np.float64).reshape(n, 3)
         gv = np.zeros((n, 3))
         gb = np.zeros((n, 3))
-        o = Opts(max_steps, vertex_snap)
+        o = Opts(max_steps, vertex_snap, boundary_mode)
         rc = lib().or_ep_batch(self._h, n, _p(f), _p(b), _p(v), C.byref(o), _p(g), _p(gv), _p(gb), nthreads)
         if rc != 0:
             raise OracleError(rc, lib().or_last_error().decode())
         return gv, gb
 
-    def gfd(self, f, b, v, g, eps_v, eps_p, max_steps=1 << 20, vertex_snap=1e-10, nthreads=0):
+    def gfd(self, f, b, v, g, eps_v, eps_p, max_steps=1 << 20, vertex_snap=1e-10, boundary_mode=0, nthreads=0):
         f = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
         n = f.shape[0]
         b = np.ascontiguousarray(b, dtype=np.float64).reshape(n, 3)
@@ -163,14 +163,14 @@ class Mesh:
         gb = np.zeros((n, 3))
         Jv = np.zeros((n, 2, 2))
         Jp = np.zeros((n, 2, 2))
-        o = Opts(max_steps, vertex_snap)
+        o = Opts(max_steps, vertex_snap, boundary_mode)
         rc = lib().or_gfd_batch(self._h, n, _p(f), _p(b), _p(v), C.byref(o), float(eps_v), float(eps_p),
                                 _p(g), _p(gv), _p(gb), _p(Jv), _p(Jp), nthreads)
         if rc != 0:
             raise OracleError(rc, lib().or_last_error().decode())
         return dict(grad_v=gv, grad_b=gb, Jv=Jv, Jp=Jp)
 
-    def gradx(self, f, b, v, g, max_steps=1 << 20, vertex_snap=1e-10, nthreads=0):
+    def gradx(self, f, b, v, g, max_steps=1 << 20, vertex_snap=1e-10, boundary_mode=0, nthreads=0):
         """(dL/dX [nv,3] float64, vertex passages per ray (-1: status not OK)) for L = sum g . p'."""
         f = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
         n = f.shape[0]
@@ -179,7 +179,7 @@ class Mesh:
         g = np.ascontiguousarray(g, dtype=np.float64).reshape(n, 3)
         gx = np.zeros((self.nv, 3))
         nvx = np.zeros(n, np.int32)
-        o = Opts(max_steps, vertex_snap)
+        o = Opts(max_steps, vertex_snap, boundary_mode)
         rc = lib().or_gradx_batch(self._h, n, _p(f), _p(b), _p(v), C.byref(o), _p(g), _p(gx), _p(nvx), nthreads)
         if rc != 0:
             raise OracleError(rc, lib().or_last_error().decode())

@@ -37,8 +37,21 @@
  *   - extra vectors keep their signed angle to the tangent through a vertex;
  *   - the proxy's rotation is R = M_{p'} M_p^T (frame axes as columns), so that
  *     R^T carries the upstream gradient back from p' to p;
- *   - the tracer stops at a boundary edge or boundary vertex (Sec. 4, original
- *     behaviour); the hole-avoiding variant is not modelled.
+ *   - by default the tracer stops at a boundary edge or boundary vertex (Sec. 4,
+ *     original behaviour).  With boundary_mode = 1 it avoids holes (Sec. 4 and
+ *     the hole branches of transport_over_edge / transport_over_vertex): a ray
+ *     that reaches a boundary edge slides along it to the end its direction
+ *     leans toward (the paper leaves the choice open; exactly across the edge,
+ *     the end with the smaller vertex id); at a boundary vertex it resumes
+ *     straight in the fan face whose corner holds the projection of the
+ *     direction recorded at the boundary and whose plane deviates least from
+ *     it (the paper's transport_error, read as |d . n_face|), with the
+ *     direction projected onto that face; when no face's corner holds it, the
+ *     ray slides on along the next boundary edge of the hole (after a straight
+ *     arrival, along the boundary edge that leans most toward the direction).
+ *     Each slide and each resumption is one step; extra vectors keep their
+ *     angle to the direction, which is the recorded one projected onto the
+ *     current face.
  */
 #define _GNU_SOURCE
 #include "sg_oracle.h"
@@ -248,6 +261,7 @@ typedef struct {
     uint64_t hash;
     double min_vdist, traced;
     int8_t sigma;
+    int32_t n_bnd;            /* boundary slides and resumptions (hole avoidance) */
     double d0[3], L;          /* start tangent (unit) and length, for the backward */
 } ray_out;
 
@@ -312,6 +326,225 @@ static void trace_push(trace_buf* tb, int8_t kind, int32_t face, int32_t v0, int
     memcpy(tb->pt + 3 * i, p, 3 * sizeof(double));
 }
 
+/* ------------------------------------------------------------ hole avoidance */
+/* The fan of boundary vertex x0 through face f, as the chain of faces between
+ * its two boundary edges: fan[0..n), rel[i] = orientation of fan[i] relative
+ * to f (+1 / -1), y0 / y1 = the far vertex of the boundary edge at x0 of
+ * fan[0] / fan[n-1].  Returns n (0 if x0 is not a boundary vertex). */
+static int other_edge_at(const or_mesh* m, int64_t g, int32_t x0, int not_e) {
+    int lx = local_index(m, g, x0);
+    int ea = lx, eb = (lx + 2) % 3;   /* the two edges of g at x0 */
+    return ea == not_e ? eb : ea;
+}
+
+static int fan_chain(const or_mesh* m, int64_t f, int32_t x0, int64_t* fan, int8_t* rel, int32_t* y0, int32_t* y1,
+                     int cap) {
+    /* walk one way from f to a boundary edge */
+    int64_t cur = f;
+    int e = local_index(m, f, x0);   /* edge x0 -> next */
+    int sig = 1, guard = 0;
+    for (;;) {
+        int64_t g = m->nbr[3 * cur + e];
+        if (g < 0) break;
+        int ge = m->nbr_k[3 * cur + e];
+        if (m->F[3 * g + ge] == m->F[3 * cur + e]) sig = -sig;
+        cur = g;
+        e = other_edge_at(m, g, x0, ge);
+        if (++guard > cap || g == f) return 0;   /* closed fan: not a boundary vertex */
+    }
+    /* cur's edge e is a boundary edge at x0; enumerate back to the other end */
+    int n = 0;
+    int32_t a = m->F[3 * cur + e], bq = m->F[3 * cur + (e + 1) % 3];
+    *y0 = a == x0 ? bq : a;
+    int ein = e;
+    for (;;) {
+        if (n >= cap) return 0;
+        fan[n] = cur;
+        rel[n] = (int8_t)sig;
+        n++;
+        int eo = other_edge_at(m, cur, x0, ein);
+        int64_t g = m->nbr[3 * cur + eo];
+        if (g < 0) {
+            int32_t c0 = m->F[3 * cur + eo], c1 = m->F[3 * cur + (eo + 1) % 3];
+            *y1 = c0 == x0 ? c1 : c0;
+            break;
+        }
+        int ge = m->nbr_k[3 * cur + eo];
+        if (m->F[3 * g + ge] == m->F[3 * cur + eo]) sig = -sig;
+        cur = g;
+        ein = ge;
+    }
+    return n;
+}
+
+/* Is the projection w of d onto face g's plane inside g's corner at x0?
+ * Returns the transport error |d . n_g| (the out-of-plane part), or -1. */
+static double corner_fit(const or_mesh* m, int64_t g, int32_t x0, const double* d, double* w) {
+    const double* n = m->N + 3 * g;
+    perp3(d, n, w);
+    if (!(norm3(w) > 1e-300)) return -1.0;
+    int lx = local_index(m, g, x0);
+    double ea[3], eb[3], c[3];
+    sub3(FX(m, g, (lx + 1) % 3), VX(m, x0), ea);
+    sub3(FX(m, g, (lx + 2) % 3), VX(m, x0), eb);
+    cross3(ea, eb, c);
+    double sab = dot3(c, n);
+    cross3(ea, w, c);
+    double sa = dot3(c, n);
+    cross3(w, eb, c);
+    double sb = dot3(c, n);
+    if (sa * sab < 0.0 || sb * sab < 0.0) return -1.0;
+    return fabs(dot3(d, n));
+}
+
+#define FANCAP 4096
+
+/* The hole-avoiding chain from a boundary event (see the header), run until
+ * the ray resumes straight (returns 1: *f, b = the vertex, d = unit direction
+ * in *f's plane, *sigma and *atv set), or its length is used up or the step
+ * cap is reached (returns 0: *status, *f, b and the reported direction d set).
+ * Entry: the ray is in face *f at point b with unit direction d (recorded as
+ * the straightest direction); kind 0: b lies on the boundary edge (la, lb) of
+ * *f; kind 1: the ray stands at boundary vertex x0 of *f.  The step that
+ * reached the boundary is completed by the chain's first slide or
+ * resumption; every further one is a step of its own. */
+static int hole_chain(const or_mesh* m, int32_t max_steps, int64_t* f, double* b, double* d, int* sigma,
+                      double* rem, double* traced, int32_t* steps, int* status, int* atv, ray_out* out,
+                      trace_buf* tb, int kind, int la, int lb, int32_t x0) {
+    static __thread int64_t fan[FANCAP];
+    static __thread int8_t rel[FANCAP];
+    double drec[3];
+    memcpy(drec, d, sizeof drec);
+    int64_t fc = *f;
+    int32_t from = -1;   /* the vertex the last slide started from */
+    int lt = -1, ls = -1, first = 1;
+    if (kind == 0) {   /* slide along the exit edge toward the end the direction leans to */
+        int32_t va = m->F[3 * fc + la], vb = m->F[3 * fc + lb];
+        double e[3];
+        sub3(VX(m, vb), VX(m, va), e);
+        double dd = dot3(drec, e);
+        int to_b = dd > 0.0 || (dd == 0.0 && vb < va);
+        lt = to_b ? lb : la;
+        ls = to_b ? la : lb;
+    }
+    for (;;) {
+        if (lt >= 0) {   /* sliding in fc from point b toward local vertex lt */
+            double p[3], q[3], e[3];
+            bary_pos(m, fc, b, p);
+            sub3(FX(m, fc, lt), p, q);
+            sub3(FX(m, fc, lt), FX(m, fc, ls), e);
+            double sl = norm3(q), elen = norm3(e);
+            if (*rem <= sl) {
+                double t = *rem / elen;
+                b[lt] += t;
+                b[ls] -= t;
+                clamp_renorm(b);
+                *traced += *rem;
+                *rem = 0.0;
+                perp3(drec, m->N + 3 * fc, d); unit3(d);
+                *f = fc;
+                *status = OR_RAY_OK;
+                return 0;
+            }
+            if (!first) {
+                if (*steps >= max_steps) {
+                    perp3(drec, m->N + 3 * fc, d); unit3(d);
+                    *f = fc;
+                    *status = OR_RAY_MAXSTEPS;
+                    return 0;
+                }
+                (*steps)++;
+            }
+            first = 0;
+            *traced += sl;
+            *rem -= sl;
+            x0 = m->F[3 * fc + lt];
+            from = m->F[3 * fc + ls];
+            b[0] = b[1] = b[2] = 0.0;
+            b[lt] = 1.0;
+            out->n_cross++;
+            out->n_bnd++;
+            out->hash = fnv_face(out->hash, (int32_t)fc);
+            trace_push(tb, 2, (int32_t)fc, from, x0, VX(m, x0));
+            lt = -1;
+        }
+        /* at boundary vertex x0 of face fc */
+        out->min_vdist = 0.0;
+        int32_t y0 = -1, y1 = -1;
+        int nfan = fan_chain(m, fc, x0, fan, rel, &y0, &y1, FANCAP);
+        if (nfan == 0) {   /* not on a boundary (cannot happen on a checked mesh) */
+            perp3(drec, m->N + 3 * fc, d); unit3(d);
+            *f = fc;
+            *status = OR_RAY_BOUNDARY;
+            return 0;
+        }
+        double best = INFINITY, wb[3] = {0, 0, 0};
+        int ib = -1;
+        for (int i = 0; i < nfan; i++) {
+            double w[3];
+            double err = corner_fit(m, fan[i], x0, drec, w);
+            if (err >= 0.0 && err < best) { best = err; ib = i; memcpy(wb, w, sizeof w); }
+        }
+        if (!first && *steps >= max_steps) {
+            perp3(drec, m->N + 3 * fc, d); unit3(d);
+            *f = fc;
+            *status = OR_RAY_MAXSTEPS;
+            return 0;
+        }
+        if (ib >= 0) {   /* resume straight in fan[ib] */
+            if (!first) (*steps)++;
+            *f = fan[ib];
+            *sigma *= rel[ib];
+            memcpy(d, wb, sizeof wb);
+            unit3(d);
+            *atv = local_index(m, *f, x0);
+            b[0] = b[1] = b[2] = 0.0;
+            b[*atv] = 1.0;
+            out->n_cross++;
+            out->n_bnd++;
+            out->hash = fnv_face(out->hash, (int32_t)*f);
+            trace_push(tb, 3, (int32_t)*f, x0, -1, VX(m, x0));
+            return 1;
+        }
+        /* no face holds the direction: slide on along a boundary edge of the hole */
+        int end;
+        if (from >= 0) end = (y0 == from) ? 1 : 0;
+        else {
+            double u0[3], u1[3];
+            sub3(VX(m, y0), VX(m, x0), u0); unit3(u0);
+            sub3(VX(m, y1), VX(m, x0), u1); unit3(u1);
+            double c0 = dot3(drec, u0), c1 = dot3(drec, u1);
+            end = (c1 > c0 || (c1 == c0 && y1 < y0)) ? 1 : 0;
+        }
+        *sigma *= end ? rel[nfan - 1] : rel[0];
+        fc = end ? fan[nfan - 1] : fan[0];
+        int32_t y = end ? y1 : y0;
+        ls = local_index(m, fc, x0);
+        lt = local_index(m, fc, y);
+        b[0] = b[1] = b[2] = 0.0;
+        b[ls] = 1.0;
+    }
+}
+
+/* Signed angles of the extra vectors to direction d about the oriented normal
+ * sigma * n (a transported vector keeps its angle to the tangent). */
+static void vec_angles(const double* n, int sigma, const double* d, int K, const double* W, double* psi) {
+    double ns[3] = {sigma * n[0], sigma * n[1], sigma * n[2]};
+    for (int k = 0; k < K; k++) {
+        double c[3];
+        cross3(d, W + 3 * k, c);
+        psi[k] = atan2(dot3(c, ns), dot3(d, W + 3 * k));
+    }
+}
+
+static void vec_rebuild(const double* n, int sigma, const double* d, int K, const double* psi, const double* wn,
+                        double* W) {
+    double ns[3] = {sigma * n[0], sigma * n[1], sigma * n[2]}, dp[3];
+    cross3(ns, d, dp);
+    for (int k = 0; k < K; k++)
+        for (int c = 0; c < 3; c++) W[3 * k + c] = wn[k] * (cos(psi[k]) * d[c] + sin(psi[k]) * dp[c]);
+}
+
 /* One exponential map.  K extra vectors W (K*3) are transported into Wout. */
 static void exp_one(const or_mesh* m, int32_t f0, const double* b0, const double* v0, int K,
                     const double* W0, const or_opts* o, ray_out* out, double* Wout, trace_buf* tb) {
@@ -323,6 +556,7 @@ static void exp_one(const or_mesh* m, int32_t f0, const double* b0, const double
     double wn[64];
     double snap = o ? o->vertex_snap : 1e-10;
     int32_t max_steps = o ? o->max_steps : (1 << 20);
+    int hole = o ? o->boundary_mode == 1 : 0;
 
     int bad = (f0 < 0 || f0 >= m->nf);
     double b[3] = {0, 0, 0};
@@ -424,6 +658,16 @@ static void exp_one(const or_mesh* m, int32_t f0, const double* b0, const double
         if (vloc < 0) {
             /* ---- transport_over_edge: unfold f' into the plane of f about the shared edge */
             int64_t g = m->nbr[3 * f + e];
+            if (g < 0 && hole) {
+                double psi[64];
+                vec_angles(m->N + 3 * f, sigma, d, K, Wout, psi);
+                int resumed = hole_chain(m, max_steps, &f, b, d, &sigma, &rem, &traced, &steps, &status, &atv, out,
+                                         tb, 0, i, j, -1);
+                vec_rebuild(m->N + 3 * f, sigma, d, K, psi, wn, Wout);
+                if (!resumed) break;
+                skip = -1;
+                continue;
+            }
             if (g < 0) { status = OR_RAY_BOUNDARY; break; }
             int ge = m->nbr_k[3 * f + e];
             const double *xi = FX(m, f, i), *xj = FX(m, f, j), *xk = FX(m, f, ks), *z = FX(m, g, (ge + 2) % 3);
@@ -465,6 +709,17 @@ static void exp_one(const or_mesh* m, int32_t f0, const double* b0, const double
             int32_t x0id = m->F[3 * f + vloc];
             const double* x0 = VX(m, x0id);
             out->min_vdist = 0.0;
+            if (m->vbnd[x0id] && hole) {
+                b[0] = b[1] = b[2] = 0.0; b[vloc] = 1.0;
+                double psi[64];
+                vec_angles(m->N + 3 * f, sigma, d, K, Wout, psi);
+                int resumed = hole_chain(m, max_steps, &f, b, d, &sigma, &rem, &traced, &steps, &status, &atv, out,
+                                         tb, 1, -1, -1, x0id);
+                vec_rebuild(m->N + 3 * f, sigma, d, K, psi, wn, Wout);
+                if (!resumed) break;
+                skip = -1;
+                continue;
+            }
             if (m->vbnd[x0id]) {
                 status = OR_RAY_BOUNDARY;
                 b[0] = b[1] = b[2] = 0.0; b[vloc] = 1.0;
@@ -563,6 +818,7 @@ typedef struct {
     const int32_t* f; const double* b; const double* v; int32_t K; const double* W; const or_opts* o;
     int32_t* f_out; double* b_out; double* p_out; double* v_out; double* W_out;
     int32_t* status; int32_t* n_cross; uint64_t* seq_hash; double* min_vdist; double* traced; int8_t* sigma_end;
+    int32_t* n_bnd;
     /* backward */
     int mode;   /* 0 forward, 1 EP, 2 GFD */
     double eps_v, eps_p;
@@ -588,6 +844,7 @@ static void fwd_one(const job_t* J, int64_t i) {
     if (J->min_vdist) J->min_vdist[i] = r.min_vdist;
     if (J->traced) J->traced[i] = r.traced;
     if (J->sigma_end) J->sigma_end[i] = r.sigma;
+    if (J->n_bnd) J->n_bnd[i] = r.n_bnd;
 }
 
 static void* worker(void* arg) {
@@ -625,7 +882,8 @@ static int run_job(job_t* J, int32_t nthreads) {
 int or_exp_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b, const double* v,
                  int32_t K, const double* W, const or_opts* o, int32_t* f_out, double* b_out,
                  double* p_out, double* v_out, double* W_out, int32_t* status, int32_t* n_cross,
-                 uint64_t* seq_hash, double* min_vdist, double* traced, int8_t* sigma_end, int32_t nthreads) {
+                 uint64_t* seq_hash, double* min_vdist, double* traced, int8_t* sigma_end, int32_t* n_bnd,
+                 int32_t nthreads) {
     if (!m || n < 0 || K < 0 || K > 64 || (n > 0 && (!f || !b || !v || !f_out || !b_out || !p_out || !v_out || !status)) ||
         (K > 0 && n > 0 && (!W || !W_out))) {
         set_err("bad arguments");
@@ -635,7 +893,7 @@ int or_exp_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
     J.m = m; J.n = n; J.f = f; J.b = b; J.v = v; J.K = K; J.W = W; J.o = o;
     J.f_out = f_out; J.b_out = b_out; J.p_out = p_out; J.v_out = v_out; J.W_out = W_out;
     J.status = status; J.n_cross = n_cross; J.seq_hash = seq_hash; J.min_vdist = min_vdist;
-    J.traced = traced; J.sigma_end = sigma_end;
+    J.traced = traced; J.sigma_end = sigma_end; J.n_bnd = n_bnd;
     return run_job(&J, nthreads);
 }
 
@@ -851,9 +1109,9 @@ static int gradx_one(const or_mesh* m, int32_t f0, const double* b0, const doubl
     }
     int nvert = 0;
     for (int32_t j = 0; j < tb.n; j++) nvert += tb.kind[j] == 1;
-    if (r.status != OR_RAY_OK || nvert > 0) {
+    if (r.status != OR_RAY_OK || r.n_bnd > 0 || nvert > 0) {
         free(tb.kind); free(tb.face); free(tb.ev0); free(tb.ev1); free(tb.pt);
-        return r.status != OR_RAY_OK ? -1 : nvert;
+        return (r.status != OR_RAY_OK || r.n_bnd > 0) ? -1 : nvert;
     }
     const int32_t nh = tb.n;
     /* hinge vertices: a, b on the edge, cp apex of the face left, cn apex of the face entered */

@@ -25,6 +25,8 @@ typedef struct {
     int32_t max_steps;     /* cap on edge crossings + vertex passages */
     double vertex_snap;    /* exit point within this edge-parameter distance of an
                               edge endpoint counts as passing through that vertex */
+    int32_t boundary_mode; /* 0: stop at the boundary (status BOUNDARY); 1: avoid
+                              holes by tracing along the boundary (Sec. 4) */
 } or_opts;
 
 /* Builds adjacency, normals and vertex total angles from the canonical float32
@@ -44,17 +46,20 @@ const char* or_last_error(void);
  * n_cross (edge crossings + vertex passages), seq_hash (FNV-1a 64 of the
  * visited face ids), min_vdist (closest approach of the path to a vertex of
  * the face it was in), traced (total traced length), sigma_end (+1/-1, the
- * end face's normal relative to the orientation carried along the path).
+ * end face's normal relative to the orientation carried along the path),
+ * n_bnd (boundary slides and resumptions under hole avoidance).
  * Any output pointer except f_out/b_out/p_out/v_out/status may be NULL.
  * nthreads <= 0 uses every online core. */
 int or_exp_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
                  const double* v, int32_t K, const double* W, const or_opts* o,
                  int32_t* f_out, double* b_out, double* p_out, double* v_out,
                  double* W_out, int32_t* status, int32_t* n_cross, uint64_t* seq_hash,
-                 double* min_vdist, double* traced, int8_t* sigma_end, int32_t nthreads);
+                 double* min_vdist, double* traced, int8_t* sigma_end, int32_t* n_bnd,
+                 int32_t nthreads);
 
 /* One ray with its event list: for each edge crossing or vertex passage,
- * kind (0 edge, 1 vertex), the face entered and the 3D point of the event.
+ * kind (0 edge, 1 vertex, 2 boundary slide, 3 resumption after a slide), the
+ * face entered and the 3D point of the event.
  * Returns the number of events written (at most cap). */
 int32_t or_exp_trace(const or_mesh* m, int32_t f, const double* b, const double* v,
                      const or_opts* o, int32_t cap, int8_t* kind, int32_t* face,
@@ -81,9 +86,10 @@ int or_gfd_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
  * read as rigid hinge motions; the adjoint is taken through that chain in
  * float64, each hinge's local derivative by a central difference of its
  * closed form (step 1e-6 of the largest coordinate).  grad_X [nv*3] is
- * overwritten.  Rays that pass through a vertex, or end with a status other
- * than OK, contribute nothing; n_vertex [n] (nullable) receives each ray's
- * number of vertex passages, or -1 for a status other than OK. */
+ * overwritten.  Rays that pass through a vertex, slide along a boundary, or
+ * end with a status other than OK, contribute nothing; n_vertex [n]
+ * (nullable) receives each ray's number of vertex passages, or -1 for a
+ * status other than OK or a boundary slide. */
 int or_gradx_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
                    const double* v, const or_opts* o, const double* g, double* grad_X,
                    int32_t* n_vertex, int32_t nthreads);

@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "icosahedron", "icosphere", "geodesic_sphere", "sh_displace", "normal_noise",
     "torus_grid", "mobius_strip", "klein_bottle", "tetrahedron", "octahedron", "cube_grid", "flat_grid", "prism",
-    "canonical", "mean_edge", "orient_outward", "remove_faces",
+    "canonical", "mean_edge", "orient_outward", "remove_faces", "plane_with_hole",
 ]
 
 
@@ -333,8 +333,9 @@ def flat_grid(n: int, jitter: float, rng, size: float = 1.0):
     x = i.astype(np.float64)
     y = j.astype(np.float64)
     inner = (i > 0) & (i < n) & (j > 0) & (j < n)
-    x[inner] += rng.uniform(-jitter, jitter, inner.sum())
-    y[inner] += rng.uniform(-jitter, jitter, inner.sum())
+    if jitter > 0:
+        x[inner] += rng.uniform(-jitter, jitter, inner.sum())
+        y[inner] += rng.uniform(-jitter, jitter, inner.sum())
     X = np.stack([x, y, np.zeros_like(x)], -1).reshape(-1, 3) * (size / n)
     idx = lambda a, b: a * (n + 1) + b
     F = []
@@ -374,6 +375,17 @@ def prism(nsides: int, nrings: int, radius: float = 1.0, height: float = 2.0):
     meta = dict(facet=2 * radius * np.sin(np.pi / nsides), dz=height / nrings,
                 nsides=nsides, radius=radius, height=height)
     return X, F, meta
+
+
+def plane_with_hole(n: int, size: float, origin, hole_lo, hole_hi):
+    """Flat n x n grid of split squares over [origin, origin + size]^2 with the
+    faces whose centroids lie inside the square [hole_lo, hole_hi]^2 removed
+    (a square hole when its sides fall on grid lines)."""
+    X, F = flat_grid(n, 0.0, None, size=size)
+    X = X + np.array([origin, origin, 0.0])
+    c = X[F].mean(1)
+    inside = np.all((c[:, :2] > hole_lo) & (c[:, :2] < hole_hi), axis=1)
+    return remove_faces(X, F, np.where(inside)[0])
 
 
 def remove_faces(X, F, faces):
