@@ -59,6 +59,18 @@ enum {
 
 enum { SG_BWD_EP = 0, SG_BWD_GFD = 1 };
 enum {
+    SG_BOUNDARY_STOP = 0,   /* stop at a boundary edge or vertex, status SG_RAY_BOUNDARY (Sec. 4, the original rule) */
+    SG_BOUNDARY_AVOID = 1   /* hole avoidance (Sec. 4; the hole branches of the appendix's transport_over_edge and
+                               transport_over_vertex): a ray that reaches a boundary edge slides along it toward
+                               the end its direction leans to; at a boundary vertex it resumes straight in the fan
+                               face whose corner holds the projection of the direction recorded at the boundary,
+                               choosing the face whose plane deviates least from that direction; when no face's
+                               corner holds it, it slides on along the next boundary edge.  Each slide and
+                               resumption counts as a step (n_cross, max_steps, seq_hash).  The reported end
+                               direction is the recorded one projected onto the end face; extra vectors keep their
+                               angle to it.  Such rays end with SG_RAY_OK when their length is used up. */
+};
+enum {
     SG_KERNEL_AUTO = 0,         /* = SG_KERNEL_PERSISTENT */
     SG_KERNEL_PLAIN = 1,        /* one ray per lane, run to completion (Alg. gpu_parallel) */
     SG_KERNEL_PERSISTENT = 2,   /* persistent waves refilled from ray queues (a share per XCD) */
@@ -82,6 +94,8 @@ typedef struct {
     int32_t rays_per_lane; /* persistent kernel: rays each lane walks at once, 1 or 2; <= 0: tuned default */
     int32_t ray_queues;    /* persistent kernel: ray queues the walk claims rays from, a multiple of 8 (an
                               equal share of each XCD) up to 64; <= 0: 8 */
+    int32_t boundary_mode; /* SG_BOUNDARY_STOP (default) or SG_BOUNDARY_AVOID; honoured by every kernel and
+                              the backward (the vertex gradient leaves out rays that slid) */
     void* workspace;       /* optional caller-owned device workspace, 256-byte aligned, at least the size
                               sg_exp_workspace_size / sg_backward_workspace_size report.  With it a call
                               allocates nothing, so it can be captured in a HIP graph (debug bit 2 aside).

@@ -261,7 +261,7 @@ typedef struct {
     uint64_t hash;
     double min_vdist, traced;
     int8_t sigma;
-    int32_t n_bnd;            /* boundary slides and resumptions (hole avoidance) */
+    int32_t n_bnd;            /* boundary slides (whole or partial) and resumptions (hole avoidance) */
     double d0[3], L;          /* start tangent (unit) and length, for the backward */
 } ray_out;
 
@@ -427,8 +427,10 @@ static int hole_chain(const or_mesh* m, int32_t max_steps, int64_t* f, double* b
         lt = to_b ? lb : la;
         ls = to_b ? la : lb;
     }
+    out->min_vdist = 0.0;   /* a slide runs along an edge: the path touches the boundary */
     for (;;) {
         if (lt >= 0) {   /* sliding in fc from point b toward local vertex lt */
+            out->n_bnd++;
             double p[3], q[3], e[3];
             bary_pos(m, fc, b, p);
             sub3(FX(m, fc, lt), p, q);
@@ -463,7 +465,6 @@ static int hole_chain(const or_mesh* m, int32_t max_steps, int64_t* f, double* b
             b[0] = b[1] = b[2] = 0.0;
             b[lt] = 1.0;
             out->n_cross++;
-            out->n_bnd++;
             out->hash = fnv_face(out->hash, (int32_t)fc);
             trace_push(tb, 2, (int32_t)fc, from, x0, VX(m, x0));
             lt = -1;

@@ -47,7 +47,8 @@ const char* or_last_error(void);
  * visited face ids), min_vdist (closest approach of the path to a vertex of
  * the face it was in), traced (total traced length), sigma_end (+1/-1, the
  * end face's normal relative to the orientation carried along the path),
- * n_bnd (boundary slides and resumptions under hole avoidance).
+ * n_bnd (boundary slides, whole or partial, and resumptions under hole
+ * avoidance).
  * Any output pointer except f_out/b_out/p_out/v_out/status may be NULL.
  * nthreads <= 0 uses every online core. */
 int or_exp_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,

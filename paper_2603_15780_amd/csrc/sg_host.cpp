@@ -43,8 +43,8 @@ struct sg_mesh_s {
     int32_t has_flip = 0;
     size_t bytes = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare;   // walk-kernel event pairs
-    sg::DevMesh dev() const {
-        sg::DevMesh d{d_face, d_F, d_X, d_half, d_perm, d_order, n_faces, n_verts, has_flip, {}, d_twin};
+    sg::DevMesh dev(int32_t hole_avoid = 0) const {
+        sg::DevMesh d{d_face, d_F, d_X, d_half, d_perm, d_order, n_faces, n_verts, has_flip, {}, d_twin, hole_avoid};
         for (int p = 0; p <= sg::kParts; ++p) d.part_he[p] = part_he[p];
         return d;
     }
@@ -143,6 +143,8 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     if (o.rays_per_lane > 2) return fail(SG_E_ARG, "rays_per_lane must be 1 or 2");
     if (o.refill_min <= 0) o.refill_min = 32 * o.rays_per_lane;
     if (o.refill_min > 64 * o.rays_per_lane) return fail(SG_E_ARG, "refill_min must be at most 64 per ray slot");
+    if (o.boundary_mode != SG_BOUNDARY_STOP && o.boundary_mode != SG_BOUNDARY_AVOID)
+        return fail(SG_E_ARG, "unknown boundary_mode %d", o.boundary_mode);
     if (o.ray_queues <= 0) o.ray_queues = 8;
     if (o.ray_queues % 8 != 0 || o.ray_queues > sg::kMaxQueues)
         return fail(SG_E_ARG, "ray_queues must be a multiple of 8, at most %d", sg::kMaxQueues);
@@ -414,6 +416,7 @@ void sg_opts_default(sg_opts* o) {
     o->walk_blocks = 0;
     o->rays_per_lane = 0;
     o->ray_queues = 0;
+    o->boundary_mode = SG_BOUNDARY_STOP;
     o->workspace = nullptr;
     o->workspace_bytes = 0;
 }
@@ -515,7 +518,7 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
     a.rays_per_lane = o.rays_per_lane;
     const hipStream_t st = (hipStream_t)stream;
     if (o.kernel == SG_KERNEL_PLAIN) {
-        hipError_t e = sg::launch_exp_plain(mesh->dev(), a, st);
+        hipError_t e = sg::launch_exp_plain(mesh->dev(o.boundary_mode), a, st);
         if (e != hipSuccess) return hip_fail(e, "forward launch");
         return SG_OK;
     }
@@ -534,9 +537,10 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
             return fail(SG_E_HIP, "hipEventCreate failed");
         }
     }
-    hipError_t e = part ? sg::launch_exp_partitioned(mesh->dev(), a, ws.p, o.walk_blocks, o.refill_min, st, ev.first,
+    hipError_t e = part ? sg::launch_exp_partitioned(mesh->dev(o.boundary_mode), a, ws.p, o.walk_blocks, o.refill_min, st, ev.first,
                                                      ev.second)
-                        : sg::launch_exp_persistent(mesh->dev(), a, ws.p, sched(o), st, ev.first, ev.second);
+                        : sg::launch_exp_persistent(mesh->dev(o.boundary_mode), a, ws.p, sched(o), st, ev.first,
+                                                    ev.second);
     if (ev.first) mesh->timed.push_back(ev);
     const hipError_t e2 = give_workspace(ws, st);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
@@ -579,7 +583,7 @@ int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, con
     rc = take_workspace(o, sg::bwd_workspace(n, mode, mesh->has_flip != 0, vjp, grad_X != nullptr, mesh->n_faces), st,
                         ws);
     if (rc != SG_OK) return rc;
-    hipError_t e = sg::launch_backward(mesh->dev(), a, ws.p, sched(o), st);
+    hipError_t e = sg::launch_backward(mesh->dev(o.boundary_mode), a, ws.p, sched(o), st);
     const hipError_t e2 = give_workspace(ws, st);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     if (e2 != hipSuccess) return hip_fail(e2, "workspace release");

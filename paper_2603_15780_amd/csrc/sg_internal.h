@@ -59,6 +59,7 @@ struct DevMesh {
     int32_t has_flip;           // some adjacent faces disagree in orientation (non-orientable or mixed)
     int32_t part_he[kParts + 1];// half-edge id ranges of the parts
     const int32_t* twin;        // [3 n_faces] half-edge on the other side of each edge, -1 on the boundary
+    int32_t hole_avoid;         // per call: 1 = trace along boundaries instead of stopping (Sec. 4)
 };
 
 enum RayStatus : int32_t { kRayOk = 0, kRayMaxSteps = 1, kRayBoundary = 2, kRayBadInput = 3 };

@@ -36,7 +36,10 @@ constexpr float kForceBC = kBig;    // vertex at a: leave through b-c
 constexpr float kForceCA = -kBig;   // vertex at b: leave through c-a
 constexpr uint32_t kForceBCBit = 2u, kForceCABit = 4u;   // the same, in a stored state record
 constexpr uint32_t kParity = 1u;    // orientation flipped an odd number of times
+constexpr uint32_t kSlidPar = 2u;   // (Ray::par) the walk slid along a boundary and resumed
+constexpr uint32_t kSlidBit = 8u;   // the same, in a stored state record
 constexpr uint32_t kDoneBit = 1u << 16;   // a Final record: the walk reached its end
+constexpr uint32_t kBndBit = 1u << 17;    // a Final record: the walk slid along a boundary (hole avoidance)
 
 // sin(x)/x and cos(x) as polynomials in u = x^2 on |x| <= pi/2 (least-squares
 // minimax fits, max error about 1.4e-7 in float32).
@@ -79,7 +82,7 @@ struct Ray {
     uint32_t phi;
     float Lhi, Llo;
     float bias;      // 0, or kForceBC / kForceCA right after a vertex
-    uint32_t par;    // kParity if the orientation flipped an odd number of times
+    uint32_t par;    // kParity if the orientation flipped an odd number of times; kSlidPar
     int32_t ncross;
     uint64_t hash;
 };
@@ -505,9 +508,244 @@ SG_HD __forceinline__ void set_final(Final& fin, const Ray& st, float ex, float 
     fin.ex = ex;
     fin.ey = ey;
     fin.phi = st.phi;
-    fin.flags = (st.par & kParity) | ((uint32_t)status << 8) | kDoneBit;
+    fin.flags = (st.par & kParity) | ((uint32_t)status << 8) | kDoneBit | ((st.par & kSlidPar) ? kBndBit : 0u);
     fin.ncross = st.ncross;
     fin.hash = st.hash;
+}
+
+// ---------------------------------------------------------------- hole avoidance
+// Sec. 4 and the hole branches of the appendix's transport_over_edge and
+// transport_over_vertex.  A ray that reaches a boundary edge slides along it
+// toward the end its direction leans to (exactly across it: the end with the
+// smaller vertex id); at a boundary vertex it resumes straight in the fan face
+// whose corner holds the projection of the direction recorded at the
+// boundary, taking the face whose plane deviates least from it (|d . n|);
+// when no face's corner holds it, it slides on along the next boundary edge of
+// the hole (after a straight arrival, the boundary edge that leans most toward
+// the direction).  The step that reached the boundary is completed by the
+// first slide or resumption; each further one is a step of its own.  These
+// moves are rare and run in 3D from the vertex positions.
+
+// 3D frame of the chart of half-edge h: origin a, x-axis eu along a->b, ev
+// toward c, and the face normal (b - a) x (c - a), normalised.
+SG_HD __forceinline__ void chart_frame3(const DevMesh& M, int32_t h, float3& xa, float3& eu, float3& ev, float3& n) {
+    const int32_t f = h / 3, k = h - 3 * (h / 3);
+    const int64_t f3 = 3 * (int64_t)f;
+    xa = ld3(M.X + 3 * (int64_t)M.F[f3 + k]);
+    const float3 xb = ld3(M.X + 3 * (int64_t)M.F[f3 + (k + 1) % 3]);
+    const float3 xc = ld3(M.X + 3 * (int64_t)M.F[f3 + (k + 2) % 3]);
+    const float3 ab = sub(xb, xa);
+    eu = nrm(ab);
+    n = nrm(crs(ab, sub(xc, xa)));
+    ev = crs(n, eu);
+}
+
+SG_HD __forceinline__ int32_t chart_vertex(const DevMesh& M, int32_t h, int which) {   // 0 a, 1 b, 2 c
+    const int32_t f = h / 3, k = h - 3 * (h / 3);
+    return M.F[3 * (int64_t)f + (k + which) % 3];
+}
+
+SG_HD __forceinline__ float3 proj_unit(float3 d, float3 n) { return nrm(sub(d, scl(n, dot(d, n)))); }
+
+// Ends the walk at 3D point P of face f, direction d projected onto f: the
+// chart of f in which the direction's angle lies in [0, pi].
+SG_HD __forceinline__ void hole_final(const DevMesh& M, int32_t f, float3 P, float3 d, uint32_t par, int32_t ncross,
+                                      uint64_t hash, int32_t status, Final& fin) {
+    int32_t hb = 3 * f;
+    float best = -2.f;
+    float3 xa, eu, ev, n, bxa, beu, bev;
+    for (int k = 0; k < 3; ++k) {
+        chart_frame3(M, 3 * f + k, xa, eu, ev, n);
+        const float dv = dot(d, ev);
+        if (dv > best) { best = dv; hb = 3 * f + k; bxa = xa; beu = eu; bev = ev; }
+    }
+    chart_frame3(M, hb, xa, eu, ev, n);
+    const float3 w = proj_unit(d, n);
+    const float3 q = sub(P, bxa);
+    const float ang = atan2f(fmaxf(dot(w, bev), 0.f), dot(w, beu));
+    fin.h = hb;
+    fin.ex = dot(q, beu);
+    fin.ey = dot(q, bev);
+    fin.phi = rad_to_fx(ang);
+    fin.flags = (par & kParity) | ((uint32_t)status << 8) | kDoneBit | kBndBit;
+    fin.ncross = ncross;
+    fin.hash = hash;
+}
+
+// Does the projection of d onto the face of chart hv (x0 is its vertex a if
+// roleA, else b) point into the face's corner at x0?  Returns |d . n| (the
+// transport error) or -1, and the projection w.
+SG_HD __forceinline__ float corner_fit(const DevMesh& M, int32_t hv, int roleA, float3 d, float3& w) {
+    const int32_t f = hv / 3, k = hv - 3 * (hv / 3);
+    const int64_t f3 = 3 * (int64_t)f;
+    const int k0 = roleA ? k : (k + 1) % 3;   // x0's local index
+    const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[f3 + k0]);
+    const float3 ea = sub(ld3(M.X + 3 * (int64_t)M.F[f3 + (k0 + 1) % 3]), x0);
+    const float3 eb = sub(ld3(M.X + 3 * (int64_t)M.F[f3 + (k0 + 2) % 3]), x0);
+    const float3 n = nrm(crs(ea, eb));   // here (ea x eb) . n > 0
+    const float dn = dot(d, n);
+    w = sub(d, scl(n, dn));
+    if (!(dot(w, w) > 1e-30f)) return -1.f;
+    if (dot(crs(ea, w), n) < 0.f || dot(crs(w, eb), n) < 0.f) return -1.f;
+    return fabsf(dn);
+}
+
+// Compensated remaining length minus a segment.
+SG_HD __forceinline__ void rem_sub(float& hi, float& lo, float seg) {
+    const float nh = hi - seg;
+    lo = lo + ((hi - nh) - seg);
+    hi = nh;
+}
+
+// The chain from a boundary event: the ray stands at boundary vertex x0 of
+// face fc (from: the vertex the last slide started from, or -1), with the
+// recorded direction d.  Returns kStepContinue with st resumed at a vertex, or
+// kStepDone with fin set.
+SG_HD int hole_vertex_chain(const DevMesh& M, int32_t fc, int32_t x0, int32_t from, float3 d, float Lhi, float Llo,
+                            uint32_t par, int32_t ncross, uint64_t hash, bool first, int32_t max_steps, Ray& st,
+                            Final& fin) {
+    for (int guard = 0; guard < (1 << 20); ++guard) {
+        // the fan of x0 between its two boundary edges: first to one end ...
+        int32_t hv = 3 * fc + (M.F[3 * (int64_t)fc] == x0 ? 0 : (M.F[3 * (int64_t)fc + 1] == x0 ? 1 : 2));
+        int roleA = 1;
+        uint32_t p = 0u;
+        int g = 0;
+        for (; g < 4096; ++g) {
+            const HalfEdgeRec q = rec_at(M, hv);
+            const int32_t nx = roleA ? q.nca : q.nbc;
+            if (nx < 0) break;
+            hv = nx >> 1;
+            roleA ^= nx & 1;
+            p ^= (uint32_t)nx & 1u;
+        }
+        const int32_t he0 = hv, y0 = chart_vertex(M, hv, 2);
+        const uint32_t pe0 = p;
+        // ... then back across the fan to the other end, testing each face
+        {
+            const int32_t f = hv / 3, k = hv - 3 * (hv / 3);
+            hv = roleA ? 3 * f + (k + 2) % 3 : 3 * f + (k + 1) % 3;
+            roleA ^= 1;
+        }
+        float best = 3.0e38f;
+        int32_t hb = -1;
+        int rb = 0;
+        uint32_t pb = 0u;
+        float3 wb = make_float3(0.f, 0.f, 0.f);
+        int32_t he1 = hv, y1 = -1;
+        uint32_t pe1 = p;
+        for (g = 0; g < 4096; ++g) {
+            float3 w;
+            const float err = corner_fit(M, hv, roleA, d, w);
+            if (err >= 0.f && err < best) { best = err; hb = hv; rb = roleA; pb = p; wb = w; }
+            const HalfEdgeRec q = rec_at(M, hv);
+            const int32_t nx = roleA ? q.nca : q.nbc;
+            if (nx < 0) { he1 = hv; y1 = chart_vertex(M, hv, 2); pe1 = p; break; }
+            hv = nx >> 1;
+            roleA ^= nx & 1;
+            p ^= (uint32_t)nx & 1u;
+        }
+        const float3 X0 = ld3(M.X + 3 * (int64_t)x0);
+        if (!first && ncross >= max_steps) {
+            float3 xa, eu, ev, n;
+            chart_frame3(M, 3 * fc, xa, eu, ev, n);
+            hole_final(M, fc, X0, proj_unit(d, n), par, ncross, hash, kRayMaxSteps, fin);
+            return kStepDone;
+        }
+        if (hb >= 0) {   // resume straight in that face, from x0 (its chart with a = x0)
+            const int32_t fb = hb / 3, kb = hb - 3 * (hb / 3);
+            const int32_t hr = rb ? hb : 3 * fb + (kb + 1) % 3;
+            const HalfEdgeRec r = rec_at(M, hr);
+            float3 xa, eu, ev, n;
+            chart_frame3(M, hr, xa, eu, ev, n);
+            float ang = atan2f(dot(wb, ev), dot(wb, eu));
+            uint32_t ph = rad_to_fx(fmaxf(ang, 0.f));
+            ph = ph > r.A ? r.A : ph;
+            st.h = hr;
+            st.s = 0.f;
+            st.t = r.lab;
+            st.phi = ph;
+            st.Lhi = Lhi;
+            st.Llo = Llo;
+            st.bias = kForceBC;
+            st.par = (par ^ pb) | kSlidPar;
+            st.ncross = ncross + 1;
+            st.hash = fnv_face(hash, (uint32_t)M.order[fb]);
+            return kStepContinue;
+        }
+        // no face holds the direction: slide on along a boundary edge of the hole
+        int end;
+        if (from >= 0) {
+            end = y0 == from ? 1 : 0;
+        } else {
+            const float c0 = dot(d, nrm(sub(ld3(M.X + 3 * (int64_t)y0), X0)));
+            const float c1 = dot(d, nrm(sub(ld3(M.X + 3 * (int64_t)y1), X0)));
+            end = (c1 > c0 || (c1 == c0 && y1 < y0)) ? 1 : 0;
+        }
+        const int32_t fe = (end ? he1 : he0) / 3;
+        const int32_t y = end ? y1 : y0;
+        par ^= end ? pe1 : pe0;
+        const float3 Y = ld3(M.X + 3 * (int64_t)y);
+        const float3 e = sub(Y, X0);
+        const float len = sqrtf(dot(e, e));
+        float3 xa, eu, ev, n;
+        chart_frame3(M, 3 * fe, xa, eu, ev, n);
+        if (Lhi + Llo <= len) {   // the length ends on this boundary edge
+            const float3 P = make_float3(fmaf(e.x, (Lhi + Llo) / len, X0.x), fmaf(e.y, (Lhi + Llo) / len, X0.y),
+                                         fmaf(e.z, (Lhi + Llo) / len, X0.z));
+            hole_final(M, fe, P, proj_unit(d, n), par, ncross, hash, kRayOk, fin);
+            return kStepDone;
+        }
+        if (!first && ncross >= max_steps) {
+            hole_final(M, fe, X0, proj_unit(d, n), par, ncross, hash, kRayMaxSteps, fin);
+            return kStepDone;
+        }
+        rem_sub(Lhi, Llo, len);
+        ++ncross;
+        hash = fnv_face(hash, (uint32_t)M.order[fe]);
+        first = false;
+        from = x0;
+        x0 = y;
+        fc = fe;
+    }
+    st.ncross = max_steps;
+    set_final(fin, st, 0.f, 0.f, kRayMaxSteps);
+    return kStepDone;
+}
+
+// The ray in chart `old` (record r) reached the boundary edge it exits
+// through (c-a if via_ca, else b-c) at edge fraction mu from the edge's
+// non-apex end, with remaining length Lhi + Llo.  Slide along it.
+SG_HD int hole_edge(const DevMesh& M, const Ray& old, const HalfEdgeRec& r, bool via_ca, float mu, float omu,
+                    float Lhi, float Llo, int32_t max_steps, Ray& st, Final& fin) {
+    const int32_t f = old.h / 3;
+    // the exit point and the edge's two ends in the chart
+    const float ax = via_ca ? 0.f : old.s + old.t;   // non-apex end (a or b)
+    const float px = fmaf(mu, r.cx - ax, ax), py = mu * r.cy;
+    float sn, cs;
+    sincos_fx(old.phi, sn, cs);
+    const float lean = fmaf(cs, r.cx - ax, sn * r.cy);   // direction . (apex - non-apex end)
+    const int32_t vn = chart_vertex(M, old.h, via_ca ? 0 : 1), vc = chart_vertex(M, old.h, 2);
+    const bool to_c = lean > 0.f || (lean == 0.f && vc < vn);
+    const float len = via_ca ? r.lac : r.lbc;
+    const float sl = (to_c ? omu : mu) * len;
+    const float tx = to_c ? r.cx : ax, ty = to_c ? r.cy : 0.f;
+    if (Lhi + Llo <= sl) {   // the length ends on the edge: the recorded direction is the chart's
+        const float u = (Lhi + Llo) / sl;
+        fin.h = old.h;
+        fin.ex = fmaf(u, tx - px, px);
+        fin.ey = fmaf(u, ty - py, py);
+        fin.phi = old.phi;
+        fin.flags = (old.par & kParity) | ((uint32_t)kRayOk << 8) | kDoneBit | kBndBit;
+        fin.ncross = old.ncross;
+        fin.hash = old.hash;
+        return kStepDone;
+    }
+    rem_sub(Lhi, Llo, sl);
+    float3 xa, eu, ev, n;
+    chart_frame3(M, old.h, xa, eu, ev, n);
+    const float3 d = make_float3(fmaf(cs, eu.x, sn * ev.x), fmaf(cs, eu.y, sn * ev.y), fmaf(cs, eu.z, sn * ev.z));
+    return hole_vertex_chain(M, f, to_c ? vc : vn, to_c ? vn : vc, d, Lhi, Llo, old.par, old.ncross + 1,
+                             fnv_face(old.hash, (uint32_t)M.order[f]), false, max_steps, st, fin);
 }
 
 // One geodesic_step: find the exit of the current face (the smallest positive
@@ -515,7 +753,7 @@ SG_HD __forceinline__ void set_final(Final& fin, const Ray& st, float ex, float 
 // edge into the next chart (transport_over_edge).  The crossing is computed
 // for every lane and committed with selects; stopping in the face, at the
 // step cap, at a vertex or on the boundary is one rarely taken branch.
-template <bool kHash, bool kFlip>
+template <bool kHash, bool kFlip, bool kHole>
 SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps, float snap, Final& fin,
                                    bool alive = true) {
     const HalfEdgeRec r = rec_at(M, st.h);
@@ -580,6 +818,14 @@ SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps
         const bool at_apex = omu < snap;
         const int vr = vertex_rule(M, cand, r, via_ca, at_apex, x0);
         if (vr == kVertexBoundary) {
+            if constexpr (kHole) {   // the vertex lies lam along the ray, like a crossing
+                float3 xa, eu, ev, n;
+                chart_frame3(M, old.h, xa, eu, ev, n);
+                const float3 d = make_float3(fmaf(cs, eu.x, sn * ev.x), fmaf(cs, eu.y, sn * ev.y),
+                                             fmaf(cs, eu.z, sn * ev.z));
+                return hole_vertex_chain(M, old.h / 3, x0, -1, d, nh, lo, old.par, old.ncross, old.hash, true,
+                                         max_steps, st, fin);
+            }
             set_final(fin, old, at_apex ? r.cx : (via_ca ? 0.f : old.s + old.t), at_apex ? r.cy : 0.f, kRayBoundary);
             return kStepDone;
         }
@@ -592,7 +838,8 @@ SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps
             return kStepContinue;
         }
     }
-    if (nx < 0) {   // boundary edge: stop on it (Sec. 4, original behaviour)
+    if (nx < 0) {   // boundary edge: stop on it (Sec. 4, original behaviour), or slide along it
+        if constexpr (kHole) return hole_edge(M, old, r, via_ca, mu, omu, nh, lo, max_steps, st, fin);
         set_final(fin, old, fmaf(lam, cs, old.s), lam * sn, kRayBoundary);
         return kStepDone;
     }
@@ -611,9 +858,9 @@ SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps
     return kStepContinue;
 }
 
-template <bool kHash, bool kFlip>
+template <bool kHash, bool kFlip, bool kHole>
 SG_HD __forceinline__ void walk_to_end(const DevMesh& M, Ray& st, int32_t max_steps, float snap, Final& fin) {
-    while (walk_step<kHash, kFlip>(M, st, max_steps, snap, fin) == kStepContinue) {
+    while (walk_step<kHash, kFlip, kHole>(M, st, max_steps, snap, fin) == kStepContinue) {
     }
 }
 
@@ -738,7 +985,7 @@ SG_HD __forceinline__ float tangent_length(const DevMesh& M, const ExpArgs& a, i
     return sqrtf(fmaf(vx, vx, vy * vy));
 }
 
-template <bool kHash, bool kFlip>
+template <bool kHash, bool kFlip, bool kHole>
 SG_HD void exp_ray(const DevMesh& M, const ExpArgs& a, int64_t i) {
     Ray st;
     float L = 0.f;
@@ -748,15 +995,15 @@ SG_HD void exp_ray(const DevMesh& M, const ExpArgs& a, int64_t i) {
         return;
     }
     Final fin;
-    walk_to_end<kHash, kFlip>(M, st, a.max_steps, a.snap, fin);
+    walk_to_end<kHash, kFlip, kHole>(M, st, a.max_steps, a.snap, fin);
     write_final(M, a, i, fin, L);
 }
 
-template <bool kHash, bool kFlip>
+template <bool kHash, bool kFlip, bool kHole>
 __global__ __launch_bounds__(256) void k_exp_plain(DevMesh M, ExpArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
-    exp_ray<kHash, kFlip>(M, a, i);
+    exp_ray<kHash, kFlip, kHole>(M, a, i);
 }
 
 // ---------------------------------------------------------------- persistent form
@@ -774,7 +1021,8 @@ struct alignas(32) StateRec {
 SG_HD __forceinline__ StateRec pack_state(const Ray& st) {
     StateRec r;
     r.h = st.h; r.s = st.s; r.t = st.t; r.phi = st.phi; r.Lhi = st.Lhi; r.Llo = st.Llo;
-    r.flags = (st.par & kParity) | (st.bias > 0.f ? kForceBCBit : (st.bias < 0.f ? kForceCABit : 0u));
+    r.flags = (st.par & kParity) | (st.bias > 0.f ? kForceBCBit : (st.bias < 0.f ? kForceCABit : 0u)) |
+              ((st.par & kSlidPar) ? kSlidBit : 0u);
     r.ncross = st.ncross;
     return r;
 }
@@ -782,7 +1030,7 @@ SG_HD __forceinline__ StateRec pack_state(const Ray& st) {
 SG_HD __forceinline__ void unpack_state(const StateRec& r, Ray& st) {
     st.h = r.h; st.s = r.s; st.t = r.t; st.phi = r.phi; st.Lhi = r.Lhi; st.Llo = r.Llo;
     st.bias = (r.flags & kForceBCBit) ? kForceBC : ((r.flags & kForceCABit) ? kForceCA : 0.f);
-    st.par = r.flags & kParity;
+    st.par = (r.flags & kParity) | ((r.flags & kSlidBit) ? kSlidPar : 0u);
     st.ncross = r.ncross;
 }
 static_assert(sizeof(StateRec) == 32, "state record is one 32-byte sector");
@@ -1068,7 +1316,7 @@ __device__ __forceinline__ int64_t queue_claim(unsigned long long* ctr, const Qu
 // the longest ray of a fixed batch.  Between refills the wave runs a tight
 // loop of walk steps and re-ballots only to see whether enough lanes are idle.
 // With kGX every edge crossing also adds its vertex-gradient terms.
-template <bool kHash, bool kFlip, bool kGX>
+template <bool kHash, bool kFlip, bool kHole, bool kGX>
 __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, QueueRanges R, unsigned long long* counter,
                                           int32_t max_steps, float snap, int refill_min, int nq, const float4* cvec,
                                           double* acc) {
@@ -1105,7 +1353,7 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, Qu
         for (;;) {
             if (active) {
                 Final fin;
-                if (walk_step<kHash, kFlip>(M, st, max_steps, snap, fin) == kStepDone) {
+                if (walk_step<kHash, kFlip, kHole>(M, st, max_steps, snap, fin) == kStepDone) {
                     *reinterpret_cast<Final*>(&states[q]) = fin;
                     active = false;
                 } else if (kGX && st.bias == 0.f) {   // an edge crossing (a vertex passage leaves a bias)
@@ -1122,7 +1370,7 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, Qu
 // flight (the walk is bound by instruction latency at the occupancy where the
 // memory system is not yet congested).  A slot without a ray steps a dummy
 // state (alive = false) whose results are dropped.
-template <bool kHash, bool kFlip>
+template <bool kHash, bool kFlip, bool kHole>
 __device__ __forceinline__ void walk_loop2(const DevMesh& M, StateRec* states, QueueRanges R,
                                            unsigned long long* counter, int32_t max_steps, float snap, int refill_min,
                                            int nq) {
@@ -1167,8 +1415,8 @@ __device__ __forceinline__ void walk_loop2(const DevMesh& M, StateRec* states, Q
         const int stop_at = qc.left == 0 ? 128 : refill_min;
         for (;;) {
             Final f0, f1;
-            const int e0 = walk_step<kHash, kFlip>(M, s0, max_steps, snap, f0, a0);
-            const int e1 = walk_step<kHash, kFlip>(M, s1, max_steps, snap, f1, a1);
+            const int e0 = walk_step<kHash, kFlip, kHole>(M, s0, max_steps, snap, f0, a0);
+            const int e1 = walk_step<kHash, kFlip, kHole>(M, s1, max_steps, snap, f1, a1);
             if (a0 && e0 == kStepDone) {
                 *reinterpret_cast<Final*>(&states[q0]) = f0;
                 a0 = false;
@@ -1182,32 +1430,32 @@ __device__ __forceinline__ void walk_loop2(const DevMesh& M, StateRec* states, Q
     }
 }
 
-template <bool kHash, bool kFlip>
+template <bool kHash, bool kFlip, bool kHole>
 __global__ __launch_bounds__(256) void k_walk2(DevMesh M, StateRec* states, QueueRanges R, unsigned long long* counter,
                                                int32_t max_steps, float snap, int refill_min, int nq) {
-    walk_loop2<kHash, kFlip>(M, states, R, counter, max_steps, snap, refill_min, nq);
+    walk_loop2<kHash, kFlip, kHole>(M, states, R, counter, max_steps, snap, refill_min, nq);
 }
 
-template <bool kHash, bool kFlip>
+template <bool kHash, bool kFlip, bool kHole>
 __global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, QueueRanges R, unsigned long long* counter,
                                               int32_t max_steps, float snap, int refill_min, int nq) {
-    walk_loop<kHash, kFlip, false>(M, states, R, counter, max_steps, snap, refill_min, nq, nullptr, nullptr);
+    walk_loop<kHash, kFlip, kHole, false>(M, states, R, counter, max_steps, snap, refill_min, nq, nullptr, nullptr);
 }
 
 // The same walk over the backward's stacked chart states (its own symbol, so
 // profiles keep the forward's walk apart).
-template <bool kHash, bool kFlip>
+template <bool kHash, bool kFlip, bool kHole>
 __global__ __launch_bounds__(256) void k_walk_bwd(DevMesh M, StateRec* states, QueueRanges R,
                                                   unsigned long long* counter, int32_t max_steps, float snap,
                                                   int refill_min, int nq) {
-    walk_loop<false, kFlip, false>(M, states, R, counter, max_steps, snap, refill_min, nq, nullptr, nullptr);
+    walk_loop<false, kFlip, kHole, false>(M, states, R, counter, max_steps, snap, refill_min, nq, nullptr, nullptr);
 }
 
-template <bool kFlip>
+template <bool kFlip, bool kHole>
 __global__ __launch_bounds__(256) void k_walk_gx(DevMesh M, StateRec* states, QueueRanges R, unsigned long long* counter,
                                                  int32_t max_steps, float snap, int refill_min, int nq,
                                                  const float4* cvec, double* acc) {
-    walk_loop<false, kFlip, true>(M, states, R, counter, max_steps, snap, refill_min, nq, cvec, acc);
+    walk_loop<false, kFlip, kHole, true>(M, states, R, counter, max_steps, snap, refill_min, nq, cvec, acc);
 }
 
 // ---------------------------------------------------------------- partitioned form
@@ -1275,7 +1523,7 @@ __global__ __launch_bounds__(256) void k_init_rounds(DevMesh M, ExpArgs a, State
 }
 
 // One round (see above).  slice_ctr: this round's per-part slice counters.
-template <bool kHash, bool kFlip>
+template <bool kHash, bool kFlip, bool kHole>
 __global__ __launch_bounds__(256) void k_walk_round(DevMesh M, StateRec* states, uint64_t* hashes, uint8_t* tags,
                                                     unsigned long long* slice_ctr, int64_t n, int32_t max_steps,
                                                     float snap, int refill_min, int round, int restrict_part) {
@@ -1331,7 +1579,7 @@ __global__ __launch_bounds__(256) void k_walk_round(DevMesh M, StateRec* states,
         for (;;) {
             if (active) {
                 Final fin;
-                if (walk_step<kHash, kFlip>(M, st, max_steps, snap, fin) == kStepDone) {
+                if (walk_step<kHash, kFlip, kHole>(M, st, max_steps, snap, fin) == kStepDone) {
                     *reinterpret_cast<Final*>(&states[ray]) = fin;
                     tags[ray] = kTagDone;
                     active = false;
@@ -1649,6 +1897,7 @@ SG_HD void gradx_init(const DevMesh& M, const BwdArgs& a, const StateRec* s1, in
     if (bwd_query(M, a, i, S, phi0, L, &Llo) != kInitOk) return;
     const Final F0 = as_final(s1[(int64_t)stride * at]);
     if (F0.h < 0 || ((F0.flags >> 8) & 0xffu) != (uint32_t)kRayOk) return;
+    if (F0.flags & kBndBit) return;   // slid along a boundary: not a chain of hinges
     float3 d3, n3;
     final_frame(M, F0, d3, n3);
     const float3 g = ld3(a.g + 3 * i);
@@ -1755,14 +2004,14 @@ SG_HD void gradx_edge(const DevMesh& M, const double* acc, double* grad_X, int64
 }
 
 // Walks one chart state to its end in place (sequential form of k_walk).
-template <bool kFlip>
+template <bool kFlip, bool kHole = false>
 SG_HD void walk_state(const DevMesh& M, StateRec& r, int32_t max_steps, float snap) {
     if (r.h < 0) return;
     Ray st;
     unpack_state(r, st);
     st.hash = 0ull;
     Final fin;
-    walk_to_end<false, kFlip>(M, st, max_steps, snap, fin);
+    walk_to_end<false, kFlip, kHole>(M, st, max_steps, snap, fin);
     r = *reinterpret_cast<const StateRec*>(&fin);
 }
 
@@ -1797,15 +2046,23 @@ __global__ __launch_bounds__(256) void k_gradx_edges(DevMesh M, const double* ac
 }  // namespace
 
 // Launches the kernel instance for the (hash, orientation-flip) combination in use.
-#define SG_DISPATCH(KERNEL, HASH, FLIP, GRID, BLOCK, STREAM, ...)                          \
-    do {                                                                                   \
-        if (HASH) {                                                                        \
-            if (FLIP) KERNEL<true, true><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);   \
-            else KERNEL<true, false><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);       \
-        } else {                                                                           \
-            if (FLIP) KERNEL<false, true><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);  \
-            else KERNEL<false, false><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);      \
-        }                                                                                  \
+// Launches the instantiation of KERNEL<kHash, kFlip, kHole> for the runtime
+// flags; the hole-avoiding rare path is compiled only into kHole kernels.
+#define SG_DISPATCH_H(KERNEL, HASH, FLIP, HOLE, GRID, BLOCK, STREAM, ...)                        \
+    do {                                                                                         \
+        if (HOLE) KERNEL<HASH, FLIP, true><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);       \
+        else KERNEL<HASH, FLIP, false><<<(GRID), (BLOCK), 0, (STREAM)>>>(__VA_ARGS__);           \
+    } while (0)
+#define SG_DISPATCH(KERNEL, HASH, FLIP, GRID, BLOCK, STREAM, ...)                                             \
+    do {                                                                                                      \
+        const bool hole_ = M.hole_avoid != 0;                                                                 \
+        if (HASH) {                                                                                           \
+            if (FLIP) SG_DISPATCH_H(KERNEL, true, true, hole_, GRID, BLOCK, STREAM, __VA_ARGS__);             \
+            else SG_DISPATCH_H(KERNEL, true, false, hole_, GRID, BLOCK, STREAM, __VA_ARGS__);                 \
+        } else {                                                                                              \
+            if (FLIP) SG_DISPATCH_H(KERNEL, false, true, hole_, GRID, BLOCK, STREAM, __VA_ARGS__);            \
+            else SG_DISPATCH_H(KERNEL, false, false, hole_, GRID, BLOCK, STREAM, __VA_ARGS__);                \
+        }                                                                                                     \
     } while (0)
 
 hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s) {
@@ -2012,12 +2269,19 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
                            0, s, acc, nacc);
         hipLaunchKernelGGL(k_gradx_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1, s3, cvec);
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
-        if (flip)
-            k_walk_gx<true><<<dim3((unsigned)w.blocks), dim3(block), 0, s>>>(
-                M, s3, QueueRanges{cnt, stride, 1}, counter, a.max_steps, a.snap, w.refill_min, w.queues, cvec, acc);
-        else
-            k_walk_gx<false><<<dim3((unsigned)w.blocks), dim3(block), 0, s>>>(
-                M, s3, QueueRanges{cnt, stride, 1}, counter, a.max_steps, a.snap, w.refill_min, w.queues, cvec, acc);
+        const QueueRanges R3{cnt, stride, 1};
+        const dim3 gw((unsigned)w.blocks), bw(block);
+        if (flip) {
+            if (M.hole_avoid) k_walk_gx<true, true><<<gw, bw, 0, s>>>(M, s3, R3, counter, a.max_steps, a.snap,
+                                                                       w.refill_min, w.queues, cvec, acc);
+            else k_walk_gx<true, false><<<gw, bw, 0, s>>>(M, s3, R3, counter, a.max_steps, a.snap, w.refill_min,
+                                                            w.queues, cvec, acc);
+        } else {
+            if (M.hole_avoid) k_walk_gx<false, true><<<gw, bw, 0, s>>>(M, s3, R3, counter, a.max_steps, a.snap,
+                                                                        w.refill_min, w.queues, cvec, acc);
+            else k_walk_gx<false, false><<<gw, bw, 0, s>>>(M, s3, R3, counter, a.max_steps, a.snap, w.refill_min,
+                                                             w.queues, cvec, acc);
+        }
         const int64_t nh = 3 * M.n_faces;
         hipLaunchKernelGGL(k_gradx_edges, dim3((unsigned)((nh + block - 1) / block)), dim3(block), 0, s, M, acc,
                            a.grad_X);
@@ -2027,13 +2291,13 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
 
 int walk_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk<false, false>, 256, 0) != hipSuccess || nb <= 0) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk<false, false, false>, 256, 0) != hipSuccess || nb <= 0) nb = 1;
     return nb;
 }
 
 int part_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_round<false, false>, 256, 0) != hipSuccess || nb <= 0)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk_round<false, false, false>, 256, 0) != hipSuccess || nb <= 0)
         nb = 1;
     return nb;
 }

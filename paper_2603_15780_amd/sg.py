@@ -18,6 +18,7 @@ SG_E_ARG, SG_E_NONMANIFOLD, SG_E_DEGENERATE, SG_E_HIP, SG_E_OOM = -1, -2, -3, -4
 RAY_OK, RAY_MAXSTEPS, RAY_BOUNDARY, RAY_BADINPUT = 0, 1, 2, 3
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_PERSISTENT, KERNEL_PARTITIONED = 0, 1, 2, 3
 BWD_EP, BWD_GFD = 0, 1
+BOUNDARY_STOP, BOUNDARY_AVOID = 0, 1
 
 _lib = None
 
@@ -32,7 +33,7 @@ class Opts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("vertex_snap", C.c_float), ("eps_v", C.c_float),
                 ("eps_p", C.c_float), ("kernel", C.c_int32), ("debug", C.c_uint32),
                 ("refill_min", C.c_int32), ("walk_blocks", C.c_int32), ("rays_per_lane", C.c_int32),
-                ("ray_queues", C.c_int32),
+                ("ray_queues", C.c_int32), ("boundary_mode", C.c_int32),
                 ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_uint64)]
 

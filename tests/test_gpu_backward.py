@@ -39,7 +39,7 @@ def gpu_bwd(torch, gm, mode, r, g, **kw):
     t = dev_inputs(torch, r, g)
     fo = vo = None
     if mode == sg.BWD_EP:
-        out = gm.exp(t["f"], t["b"], t["v"], **{k: v for k, v in kw.items() if k in ("max_steps",)})
+        out = gm.exp(t["f"], t["b"], t["v"], **{k: v for k, v in kw.items() if k in ("max_steps", "boundary_mode")})
         fo, vo = out["f"], out["v"]
     gv, gb = gm.backward(mode, t["f"], t["b"], t["v"], t["g"], f_out=fo, v_out=vo, **kw)
     torch.cuda.synchronize()
@@ -54,11 +54,12 @@ def check(torch, X, F, r, g, mode, rows=None, min_margin_rays=100, **kw):
     gv, gb = gpu_bwd(torch, gm, mode, r, g, eps_v=float(eps), eps_p=float(eps), **kw)
     sel = slice(None) if rows is None else rows
     rf, rb, rv, gs = r["f"][sel], r["b"][sel], r["v"][sel], g[sel]
-    o = om.exp(rf, rb, rv)
+    okw = dict(boundary_mode=kw["boundary_mode"]) if "boundary_mode" in kw else {}
+    o = om.exp(rf, rb, rv, **okw)
     if mode == sg.BWD_EP:
-        ogv, ogb = om.ep(rf, rb, rv, gs)
+        ogv, ogb = om.ep(rf, rb, rv, gs, **okw)
     else:
-        od = om.gfd(rf, rb, rv, gs, float(eps), float(eps))
+        od = om.gfd(rf, rb, rv, gs, float(eps), float(eps), **okw)
         ogv, ogb = od["grad_v"], od["grad_b"]
     s = grad_report(o, ogv, ogb, gv[sel], gb[sel], om.mean_edge)
     print(s)
@@ -190,7 +191,7 @@ def gpu_gradx(torch, gm, r, g, mode=0, want_vjp=False, **kw):
     gX = torch.zeros(gm.n_verts, 3, dtype=torch.float64, device=t["f"].device)
     fo = vo = None
     if want_vjp and mode == sg.BWD_EP:
-        out = gm.exp(t["f"], t["b"], t["v"])
+        out = gm.exp(t["f"], t["b"], t["v"], **{k: v for k, v in kw.items() if k in ("max_steps", "boundary_mode")})
         fo, vo = out["f"], out["v"]
     res = gm.backward(mode, t["f"], t["b"], t["v"], t["g"], f_out=fo, v_out=vo, grad_X=gX, want_vjp=want_vjp, **kw)
     torch.cuda.synchronize()
@@ -354,5 +355,29 @@ def test_backward_klein_bottle(torch, mode):
     gk = np.where(keep[:, None], g, 0.0).astype(np.float32)
     ref, _ = om.gradx(r["f"], r["b"], r["v"], gk)
     got, _ = gpu_gradx(torch, sg.Mesh(X, F), r, gk, mode=mode, want_vjp=True)
+    s = gradx_report(ref, got)
+    assert s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, s
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_backward_hole_avoidance(torch, mode):
+    """EP and GFD with hole avoidance against the oracle's (same boundary mode);
+    the vertex gradient leaves out rays that slid, on both sides."""
+    from paper_2603_15780_amd import sg
+    from parity import gradx_report
+    from test_oracle_holes import holed_sphere
+    X, F = holed_sphere()
+    rng = np.random.default_rng(61)
+    r = random_rays(X, F, 4096, rng, uniform_len(0.0, 3.0))
+    g = rng.standard_normal((4096, 3)).astype(np.float32)
+    om = oracle.Mesh(X, F)
+    o = om.exp(r["f"], r["b"], r["v"], boundary_mode=1)
+    assert (o["n_bnd"] > 0).sum() > 300
+    check(torch, X, F, r, g, mode, boundary_mode=1)
+    keep = (o["min_vdist"] > 1e-2 * om.mean_edge) & (o["status"] == 0)
+    gk = np.where(keep[:, None], g, 0.0).astype(np.float32)
+    ref, nvx = om.gradx(r["f"], r["b"], r["v"], gk, boundary_mode=1)
+    assert np.all(nvx[o["n_bnd"] > 0] == -1)
+    got, _ = gpu_gradx(torch, sg.Mesh(X, F), r, gk, mode=mode, want_vjp=True, boundary_mode=1)
     s = gradx_report(ref, got)
     assert s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, s

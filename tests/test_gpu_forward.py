@@ -471,3 +471,77 @@ def test_non_orientable_surfaces(torch, kernel):
         om, gm, o, g = both(torch, X, F, r, kernel=kernel)
         s = assert_parity(o, g, om.mean_edge, K=2, label="non-orientable")
         assert s["hash_mis_far"] == 0
+
+
+# ---------------------------------------------------------------- hole avoidance
+def _holed_meshes():
+    from test_oracle_holes import plane, holed_sphere
+    X, F, _ = plane()
+    return [(X, F), holed_sphere()]
+
+
+@pytest.mark.parametrize("kernel", [1, 2, 3])
+def test_hole_avoidance_parity(torch, kernel):
+    """boundary_mode = SG_BOUNDARY_AVOID: rays slide along boundary edges and
+    resume straight (Sec. 4); endpoints, faces, step counts, face-sequence
+    hashes and transported vectors match the oracle's."""
+    from paper_2603_15780_amd import sg
+    for mi, (X, F) in enumerate(_holed_meshes()):
+        r = random_rays(X, F, 6000, np.random.default_rng(50 + mi), uniform_len(0.0, 4.0), K=2)
+        om = oracle.Mesh(X, F)
+        o = om.exp(r["f"], r["b"], r["v"], r["W"], boundary_mode=1)
+        assert (o["n_bnd"] > 0).sum() > 500
+        g = run(torch, sg.Mesh(X, F), r, kernel=kernel, boundary_mode=sg.BOUNDARY_AVOID)
+        s = assert_parity(o, g, om.mean_edge, K=2, label=f"hole avoidance mesh {mi} kernel {kernel}")
+        assert s["hash_mis_far"] == 0
+        assert np.all(g["status"] == 0)
+
+
+def test_hole_avoidance_closed_forms(torch):
+    """The flat-plane closed forms of the oracle pins, on the GPU."""
+    from paper_2603_15780_amd import sg
+    from test_oracle_holes import plane
+    from test_oracle_pins import locate
+    X, F, om = plane()
+    cases = [((-0.5, 0.2), (1.0, 0.2), 2.0), ((-0.5, 0.8), (1.0, -0.4), 1.5), ((2.5, 2.1), (1.0, 0.5), 2.0)]
+    f, b, v, want = [], [], [], []
+    for p0, d, L in cases:
+        fi, bi = locate(X, F, np.array([p0[0], p0[1], 0.0]))
+        dd = np.array(d) / np.hypot(*d)
+        f.append(fi); b.append(bi); v.append([L * dd[0], L * dd[1], 0.0])
+    r = dict(f=np.array(f, np.int32), b=np.array(b, np.float32), v=np.array(v, np.float32), W=np.zeros((3, 0, 3)))
+    d0 = np.array([1.0, 0.2]) / np.hypot(1.0, 0.2)
+    d1 = np.array([1.0, -0.4]) / np.hypot(1.0, -0.4)
+    d2 = np.array([1.0, 0.5]) / np.hypot(1.0, 0.5)
+    want = [np.array([0.0, 1.0]) + (2.0 - 0.5 / d0[0] - 0.7) * d0,
+            np.array([0.0, 0.0]) + (1.5 - 0.5 / d1[0] - 0.6) * d1,
+            np.array([3.0 - (2.0 - 0.5 / d2[0] - 0.65), 3.0])]
+    for kernel in (1, 2):
+        g = run(torch, sg.Mesh(X, F), r, kernel=kernel, boundary_mode=sg.BOUNDARY_AVOID)
+        assert np.all(g["status"] == 0)
+        for i in range(3):
+            assert np.abs(g["p"][i, :2] - want[i]).max() < 1e-4 * om.mean_edge, (kernel, i, g["p"][i], want[i])
+
+
+def test_hole_avoidance_schedules_agree(torch):
+    """Every kernel and schedule gives the same rays, bit for bit, with hole avoidance."""
+    from paper_2603_15780_amd import sg
+    from test_oracle_holes import holed_sphere
+    X, F = holed_sphere()
+    gm = sg.Mesh(X, F)
+    r = random_rays(X, F, 5000, np.random.default_rng(53), uniform_len(0.0, 4.0), K=1)
+    a = run(torch, gm, r, kernel=1, boundary_mode=1)
+    for kw in (dict(kernel=2), dict(kernel=2, refill_min=4, walk_blocks=7, ray_queues=16),
+               dict(kernel=2, rays_per_lane=2), dict(kernel=3)):
+        b = run(torch, gm, r, boundary_mode=1, **kw)
+        for k in ("f", "b", "p", "v", "W", "status", "n_cross", "hash"):
+            assert np.array_equal(a[k], b[k]), (kw, k)
+
+
+def test_boundary_mode_rejected(torch):
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    gm = sg.Mesh(X, F)
+    r = random_rays(X, F, 16, np.random.default_rng(2), uniform_len(0.0, 1.0))
+    with pytest.raises(RuntimeError, match="boundary_mode"):
+        run(torch, gm, r, kernel=2, boundary_mode=2)

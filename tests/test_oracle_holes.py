@@ -75,7 +75,7 @@ def test_length_ends_during_slide():
     assert o["status"][0] == 0
     assert np.abs(o["p"][0, :2] - [0.0, 0.6]).max() < 1e-12
     assert np.abs(o["v"][0] - v).max() < 1e-12     # the recorded direction is reported
-    assert o["n_bnd"][0] == 1                      # one whole slide (to (0, 0.5)), then part of the next
+    assert o["n_bnd"][0] == 2                      # one whole slide (to (0, 0.5)), then part of the next
     assert abs(o["traced"][0] - (seg + 0.3)) < 1e-12
 
 
@@ -91,7 +91,7 @@ def test_slide_around_outer_corner():
     rest = L - seg - 0.65
     assert o["status"][0] == 0
     assert np.abs(o["p"][0, :2] - [3.0 - rest, 3.0]).max() < 1e-12
-    assert o["n_bnd"][0] == 3 + int(rest / 0.25)    # three side slides, then whole top edges
+    assert o["n_bnd"][0] == 3 + int(rest / 0.25) + 1   # three side slides, whole top edges, a partial one
     assert abs(o["traced"][0] - L) < 1e-12
 
 
@@ -145,6 +145,7 @@ def test_invariants_on_sphere_with_holes():
     for k in ("f", "p", "v", "W", "n_cross"):
         assert np.array_equal(o[k][same], o0[k][same]), k
     assert np.all(o["n_bnd"][same] == 0)
+    assert np.all(o["min_vdist"][o["n_bnd"] > 0] == 0.0)   # boundary rays are never in a gradient subset
 
 
 def test_gradx_excludes_boundary_rays():
