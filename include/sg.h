@@ -125,6 +125,19 @@ int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, 
                    sg_mesh* out);
 void sg_mesh_destroy(sg_mesh mesh);
 
+/*
+ * New vertex positions for an existing mesh handle (the same connectivity),
+ * for optimisation loops over X (the vertex gradient of sg_exp_backward is
+ * their gradient).  X_host [n_verts,3] float32 host, n_verts as at creation.
+ * Re-packs the position-dependent parts in float64 on the host (edge lengths,
+ * corner angles, vertex total angles, positions, mean edge) and uploads them;
+ * adjacency, face order and the handle stay.  Synchronous: it waits for the
+ * device to be idle first, since no call may read the mesh while it changes.
+ * A zero-area face or a non-finite position returns SG_E_DEGENERATE /
+ * SG_E_ARG and leaves the mesh unchanged.
+ */
+int sg_mesh_update_vertices(sg_mesh mesh, const float* X_host, int64_t n_verts);
+
 /* Host outputs, each nullable: mean undirected edge length, number of
  * half-edge records, device bytes held by the handle. */
 int sg_mesh_info(sg_mesh mesh, double* mean_edge, int64_t* n_half_edges, size_t* device_bytes);

@@ -43,6 +43,7 @@ struct sg_mesh_s {
     int32_t has_flip = 0;
     size_t bytes = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare;   // walk-kernel event pairs
+    sg::PackedMesh host;   // connectivity, links and face order, for sg_mesh_update_vertices
     sg::DevMesh dev(int32_t hole_avoid = 0) const {
         sg::DevMesh d{d_face, d_F, d_X, d_half, d_perm, d_order, n_faces, n_verts, has_flip, {}, d_twin, hole_avoid};
         for (int p = 0; p <= sg::kParts; ++p) d.part_he[p] = part_he[p];
@@ -304,15 +305,11 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
         std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return key[x] < key[y] || (key[x] == key[y] && x < y); });
         std::vector<int64_t> twin(nh, -1);
         std::vector<uint8_t> vbnd(n_verts, 0);
-        double esum = 0.0;
-        int64_t ecount = 0;
         for (int64_t i = 0; i < nh;) {
             int64_t j = i + 1;
             while (j < nh && key[order[j]] == key[order[i]]) ++j;
             const int64_t h0 = order[i];
             const int32_t a = F[h0], b = F[(h0 / 3) * 3 + (h0 % 3 + 1) % 3];
-            esum += len(X[b] - X[a]);
-            ++ecount;
             if (j - i > 2)
                 return fail(SG_E_NONMANIFOLD, "edge (%d,%d) has %lld faces", std::min(a, b), std::max(a, b), (long long)(j - i));
             if (j - i == 2) {
@@ -348,24 +345,61 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
                 else if (root[v] != r) return fail(SG_E_NONMANIFOLD, "vertex %d: faces do not form one fan", v);
             }
         }
-        // face records; vertex total angles from the same fixed-point corners
-        std::vector<FaceRec>& face = out.face;
-        face.assign(n_faces, FaceRec{});
+        // links across edges; the records' geometry comes from pack_geometry
+        out.face.assign(n_faces, FaceRec{});
+        for (int64_t h = 0; h < nh; ++h) {
+            const int64_t g = twin[h];
+            const uint32_t flip = g >= 0 && F[h] == F[g] ? 1u : 0u;   // same start vertex: orientations disagree
+            out.face[h / 3].nb[h % 3] = g < 0 ? -1 : (int32_t)(((uint32_t)g << 1) | flip);
+        }
+        out.has_flip = 0;
+        for (const FaceRec& q : out.face)
+            for (int k = 0; k < 3; ++k)
+                if (q.nb[k] >= 0 && (q.nb[k] & 1)) out.has_flip = 1;
+        out.vbnd = std::move(vbnd);
+        out.twin.assign(twin.begin(), twin.end());
+        out.F = std::move(F);
+        out.n_verts = n_verts;
+        out.n_faces = n_faces;
+        return pack_geometry(X_host, out);
+
+    } catch (const std::bad_alloc&) {
+        return fail(SG_E_OOM, "out of host memory");
+    } catch (...) {
+        return fail(SG_E_ARG, "unexpected error while packing the mesh");
+    }
+}
+
+int pack_geometry(const float* X_host, PackedMesh& pm) {
+    try {
+        const int64_t n_verts = pm.n_verts, n_faces = pm.n_faces;
+        std::vector<V3> X(n_verts);
+        for (int64_t v = 0; v < n_verts; ++v) {
+            const float* p = X_host + 3 * v;
+            if (!std::isfinite(p[0]) || !std::isfinite(p[1]) || !std::isfinite(p[2]))
+                return fail(SG_E_ARG, "vertex %lld is not finite", (long long)v);
+            X[v] = {(double)p[0], (double)p[1], (double)p[2]};
+        }
+        const std::vector<int32_t>& F = pm.F;
+        // face records (float64 work, rounded once); vertex total angles from
+        // the same fixed-point corners
         std::vector<int64_t> theta_fx(n_verts, 0);
-        auto link = [&](int64_t he) -> int32_t {
-            const int64_t g = twin[he];
-            if (g < 0) return -1;
-            const uint32_t flip = F[he] == F[g] ? 1u : 0u;   // same start vertex: orientations disagree
-            return (int32_t)(((uint32_t)g << 1) | flip);
-        };
+        double esum = 0.0;
+        int64_t ecount = 0;
         for (int64_t f = 0; f < n_faces; ++f) {
             const int32_t* t = &F[3 * f];
-            FaceRec& q = face[f];
+            if (!(len(cross(X[t[1]] - X[t[0]], X[t[2]] - X[t[0]])) > 0.0))
+                return fail(SG_E_DEGENERATE, "face %lld has zero area", (long long)pm.order[f]);
+            FaceRec& q = pm.face[f];
             uint32_t corner[3];
             for (int k = 0; k < 3; ++k) {
-                const V3 e = X[t[(k + 1) % 3]] - X[t[k]];
-                q.l[k] = (float)len(e);
-                q.nb[k] = link(3 * f + k);
+                const double l = len(X[t[(k + 1) % 3]] - X[t[k]]);
+                q.l[k] = (float)l;
+                const int64_t g = pm.twin[3 * f + k];
+                if (g < 0 || g > 3 * f + k) {   // each undirected edge once
+                    esum += l;
+                    ++ecount;
+                }
             }
             for (int k = 0; k < 2; ++k) {
                 const V3 p = X[t[(k + 1) % 3]] - X[t[k]], r = X[t[(k + 2) % 3]] - X[t[k]];
@@ -376,25 +410,13 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
             q.c1 = corner[1];
             for (int k = 0; k < 3; ++k) theta_fx[t[k]] += (int64_t)corner[k];
         }
-        std::vector<int64_t>& half = out.half;
-        half.assign(n_verts, 0);
-        for (int64_t v = 0; v < n_verts; ++v) half[v] = vbnd[v] ? -1 : theta_fx[v] / 2;
-        out.has_flip = 0;
-        for (const FaceRec& q : face)
-            for (int k = 0; k < 3; ++k)
-                if (q.nb[k] >= 0 && (q.nb[k] & 1)) out.has_flip = 1;
-        out.twin.assign(twin.begin(), twin.end());
-        out.X.assign(X_host, X_host + 3 * n_verts);
-        out.F = std::move(F);
-        out.n_verts = n_verts;
-        out.n_faces = n_faces;
-        out.mean_edge = esum / (double)ecount;
+        pm.half.assign(n_verts, 0);
+        for (int64_t v = 0; v < n_verts; ++v) pm.half[v] = pm.vbnd[v] ? -1 : theta_fx[v] / 2;
+        pm.X.assign(X_host, X_host + 3 * n_verts);
+        pm.mean_edge = esum / (double)ecount;
         return SG_OK;
-
     } catch (const std::bad_alloc&) {
         return fail(SG_E_OOM, "out of host memory");
-    } catch (...) {
-        return fail(SG_E_ARG, "unexpected error while packing the mesh");
     }
 }
 
@@ -458,7 +480,37 @@ int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, 
         free_mesh(m);
         return rc;
     }
+    pm.X.clear();
+    pm.X.shrink_to_fit();
+    m->host = std::move(pm);
     *out = m;
+    return SG_OK;
+}
+
+int sg_mesh_update_vertices(sg_mesh mesh, const float* X_host, int64_t n_verts) {
+    if (!mesh) return fail(SG_E_ARG, "mesh is NULL");
+    if (!X_host) return fail(SG_E_ARG, "X_host is NULL");
+    if (n_verts != mesh->n_verts)
+        return fail(SG_E_ARG, "n_verts %lld does not match the mesh's %lld", (long long)n_verts, (long long)mesh->n_verts);
+    sg::PackedMesh& pm = mesh->host;
+    // recompute on copies so that a rejected update leaves the mesh as it was
+    const std::vector<FaceRec> face0 = pm.face;
+    const std::vector<int64_t> half0 = pm.half;
+    const double mean0 = pm.mean_edge;
+    int rc = sg::pack_geometry(X_host, pm);
+    if (rc != SG_OK) {
+        pm.face = face0;
+        pm.half = half0;
+        pm.mean_edge = mean0;
+        return rc;
+    }
+    hipError_t e = hipDeviceSynchronize();   // no walk may read the records while they change
+    if (e == hipSuccess) e = hipMemcpy(mesh->d_face, pm.face.data(), pm.face.size() * sizeof(FaceRec), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(mesh->d_half, pm.half.data(), pm.half.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(mesh->d_X, X_host, (size_t)n_verts * 3 * sizeof(float), hipMemcpyHostToDevice);
+    pm.X.clear();
+    if (e != hipSuccess) return hip_fail(e, "vertex update");
+    mesh->mean_edge = pm.mean_edge;
     return SG_OK;
 }
 

@@ -58,6 +58,7 @@ struct PackedMesh {
     std::vector<float> X;
     std::vector<int64_t> half;
     std::vector<int32_t> twin;        // half-edge across each edge (internal ids), -1 on the boundary
+    std::vector<uint8_t> vbnd;        // vertex lies on a boundary edge
     int64_t n_verts = 0, n_faces = 0;
     double mean_edge = 0.0;
     int32_t has_flip = 0;
@@ -66,6 +67,10 @@ struct PackedMesh {
 // Validates and packs a mesh on the host; returns SG_OK or an SG_E_* code.
 int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64_t n_faces,
               const int64_t* vert_offsets, const int64_t* face_offsets, int32_t n_meshes, PackedMesh& out);
+// Recomputes the position-dependent parts of a packed mesh (face records'
+// lengths and corners, half_theta, X, mean_edge) for new vertex positions,
+// keeping its connectivity, links and face order.
+int pack_geometry(const float* X_host, PackedMesh& pm);
 
 // Plain forward: one ray per lane, run to completion (Alg. gpu_parallel).
 hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s);

@@ -55,6 +55,8 @@ def lib():
         L.sg_mesh_create.argtypes = [P, I64, P, I64, P, P, I32, C.POINTER(C.c_void_p)]
         L.sg_mesh_create.restype = C.c_int
         L.sg_mesh_destroy.argtypes = [P]
+        L.sg_mesh_update_vertices.argtypes = [P, P, I64]
+        L.sg_mesh_update_vertices.restype = C.c_int
         L.sg_mesh_info.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]
         L.sg_mesh_info.restype = C.c_int
         L.sg_exp.argtypes = [P, I64, P, P, P, P, P, P, P, P, P, P, C.POINTER(Opts), P]
@@ -127,6 +129,16 @@ class Mesh:
             _lib.sg_mesh_destroy(h)
 
     __del__ = close
+
+    def update_vertices(self, X):
+        """New vertex positions (numpy or torch [n_verts, 3], same connectivity);
+        synchronous (waits for the device to be idle)."""
+        if hasattr(X, "detach"):
+            X = X.detach().cpu().numpy()
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        if X.shape != (self.n_verts, 3):
+            raise ValueError(f"X must be [{self.n_verts}, 3]")
+        _check(lib().sg_mesh_update_vertices(self._h, _np_ptr(X), X.shape[0]))
 
     def info(self):
         me = C.c_double()

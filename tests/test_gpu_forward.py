@@ -545,3 +545,36 @@ def test_boundary_mode_rejected(torch):
     r = random_rays(X, F, 16, np.random.default_rng(2), uniform_len(0.0, 1.0))
     with pytest.raises(RuntimeError, match="boundary_mode"):
         run(torch, gm, r, kernel=2, boundary_mode=2)
+
+
+def test_update_vertices(torch):
+    """New positions on an existing handle give the rays of a mesh built from
+    them (bit for bit) and the oracle's; a zero-area face is rejected and the
+    handle keeps its previous positions."""
+    from paper_2603_15780_amd import sg
+    X1, F = CF.mesh_config(1)
+    X2 = M.canonical(M.sh_displace(X1.astype(np.float64), 4, 0.15, np.random.default_rng(71)), F)[0]
+    gm = sg.Mesh(X1, F)
+    r = random_rays(X2, F, 4000, np.random.default_rng(72), uniform_len(0.0, 3.0), K=1)
+    before = run(torch, gm, r, kernel=2)
+    gm.update_vertices(X2)
+    a = run(torch, gm, r, kernel=2)
+    b = run(torch, sg.Mesh(X2, F), r, kernel=2)
+    for k in ("f", "b", "p", "v", "W", "status", "n_cross", "hash"):
+        assert np.array_equal(a[k], b[k]), k
+    om = oracle.Mesh(X2, F)
+    o = om.exp(r["f"], r["b"], r["v"], r["W"])
+    assert_parity(o, a, om.mean_edge, K=1, label="updated vertices")
+    assert abs(gm.info()["mean_edge"] - om.mean_edge) < 1e-12 * om.mean_edge
+    bad = X2.copy()
+    bad[F[0, 1]] = bad[F[0, 0]]
+    bad[F[0, 2]] = bad[F[0, 0]]
+    with pytest.raises(RuntimeError, match="zero area"):
+        gm.update_vertices(bad)
+    c = run(torch, gm, r, kernel=2)
+    for k in ("f", "p", "hash"):
+        assert np.array_equal(a[k], c[k]), k
+    gm.update_vertices(X1)
+    d = run(torch, gm, r, kernel=2)
+    for k in ("f", "b", "p", "v", "W", "status", "n_cross", "hash"):
+        assert np.array_equal(before[k], d[k]), k
