@@ -214,6 +214,27 @@ int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, con
                     float* grad_v, float* grad_b, double* grad_X, const sg_opts* opts, void* stream);
 
 /*
+ * sg_exp_backward with cotangents of every output of an earlier
+ * sg_exp_transport call (an extension; the paper's backward takes dL/dp'
+ * only), each float32 [n,3] device and nullable, at least one given:
+ *   g_p = dL/dp';
+ *   g_b = dL/db' (end barycentrics): inside the end face b'_k has the
+ *         in-plane gradient n x (y_{k+2} - y_{k+1}) / (2 A), so it adds to
+ *         dL/dp' and then follows EP or GFD like g_p (this is what chains
+ *         steps of an iterated Exp through their start points);
+ *   g_v = dL/dv' and g_W [n,K,3] = dL/dW': the walk carries the frame
+ *         (d, n x d) from p to p', so W'_k = R W_k and v' = R v_t with R that
+ *         frame map (Sec. 4 "Parallel Transport"), constant wherever the face
+ *         sequence is; grad_v gains R^T g_v and grad_W [n,K,3] (with g_W)
+ *         receives R^T g_W, both in the start face's plane, in either mode.
+ * grad_X takes the g_p and g_b terms.  Other arguments as for sg_exp_backward.
+ */
+int sg_exp_backward_transport(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b,
+                              const float* v, int32_t K, const int32_t* f_out, const float* v_out, const float* g_p,
+                              const float* g_b, const float* g_v, const float* g_W, float* grad_v, float* grad_b,
+                              float* grad_W, double* grad_X, const sg_opts* opts, void* stream);
+
+/*
  * Device workspace (bytes, host output) that sg_exp / sg_exp_transport need
  * for n queries with K extra vectors (0 for sg_exp) under these options
  * (kernel and debug bits matter), and that

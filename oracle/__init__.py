@@ -44,6 +44,8 @@ def lib():
         L.or_ep_batch.restype = C.c_int
         L.or_gfd_batch.argtypes = [P, C.c_int64, P, P, P, P, C.c_double, C.c_double, P, P, P, P, P, C.c_int32]
         L.or_gfd_batch.restype = C.c_int
+        L.or_transport_vjp.argtypes = [P, C.c_int64, P, P, P, P, C.c_int32, P, P, P, P, C.c_int32]
+        L.or_transport_vjp.restype = C.c_int
         L.or_gradx_batch.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, C.c_int32]
         L.or_gradx_batch.restype = C.c_int
         _lib = L
@@ -169,6 +171,25 @@ class Mesh:
         if rc != 0:
             raise OracleError(rc, lib().or_last_error().decode())
         return dict(grad_v=gv, grad_b=gb, Jv=Jv, Jp=Jp)
+
+    def transport_vjp(self, f, b, v, g_v=None, g_W=None, max_steps=1 << 20, vertex_snap=1e-10, boundary_mode=0,
+                      nthreads=0):
+        """(dL/dv from g_v = dL/dv', dL/dW [n,K,3] from g_W = dL/dW') through the transport."""
+        f = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
+        n = f.shape[0]
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(n, 3)
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(n, 3)
+        gv_in = None if g_v is None else np.ascontiguousarray(g_v, dtype=np.float64).reshape(n, 3)
+        gW = np.zeros((n, 0, 3)) if g_W is None else np.ascontiguousarray(g_W, dtype=np.float64).reshape(n, -1, 3)
+        K = gW.shape[1]
+        gv = np.zeros((n, 3))
+        gWo = np.zeros((n, K, 3))
+        o = Opts(max_steps, vertex_snap, boundary_mode)
+        rc = lib().or_transport_vjp(self._h, n, _p(f), _p(b), _p(v), C.byref(o), K, _p(gv_in),
+                                    _p(gW) if K else None, _p(gv), _p(gWo) if K else None, nthreads)
+        if rc != 0:
+            raise OracleError(rc, lib().or_last_error().decode())
+        return gv, gWo
 
     def gradx(self, f, b, v, g, max_steps=1 << 20, vertex_snap=1e-10, boundary_mode=0, nthreads=0):
         """(dL/dX [nv,3] float64, vertex passages per ray (-1: status not OK)) for L = sum g . p'."""

@@ -824,11 +824,13 @@ typedef struct {
     int mode;   /* 0 forward, 1 EP, 2 GFD */
     double eps_v, eps_p;
     const double* g; double* grad_v; double* grad_b; double* Jv; double* Jp;
+    const double* g_vo; const double* g_W; double* grad_W;   /* transport cotangents (mode 3) */
     int64_t next;
 } job_t;
 
 static void ep_one(const job_t* J, int64_t i);
 static void gfd_one(const job_t* J, int64_t i);
+static void tvjp_one(const job_t* J, int64_t i);
 
 static void fwd_one(const job_t* J, int64_t i) {
     ray_out r;
@@ -858,7 +860,8 @@ static void* worker(void* arg) {
         for (int64_t i = s; i < e; i++) {
             if (J->mode == 0) fwd_one(J, i);
             else if (J->mode == 1) ep_one(J, i);
-            else gfd_one(J, i);
+            else if (J->mode == 2) gfd_one(J, i);
+            else tvjp_one(J, i);
         }
     }
     return NULL;
@@ -1018,6 +1021,60 @@ static void gfd_one(const job_t* J, int64_t i) {
     double G[3];
     for (int c = 0; c < 3; c++) G[c] = y0 * eu[c] + y1 * evv[c];
     for (int k = 0; k < 3; k++) gb[k] = dot3(G, FX(m, f, k));
+}
+
+/* Cotangents of the transported outputs (an extension of the backward): the
+ * walk carries the frame (d, sigma n x d) from (d0, n0 x d0) at p to
+ * (d', sigma' n' x d') at p' (Sec. 4 "Parallel Transport": a transported
+ * vector keeps its angle to the tangent), so W'_k = R W_k with R that frame
+ * map, and v' = R v_t.  Hence dL/dv gains P R^T g_v and dL/dW_k = P R^T g_Wk,
+ * P the projection onto the start face's plane (v and W are projected there
+ * first).  |v_t| = 0 transports nothing: R = I. */
+static void tvjp_one(const job_t* J, int64_t i) {
+    const or_mesh* m = J->m;
+    ray_out r;
+    exp_one(m, J->f[i], J->b + 3 * i, J->v + 3 * i, 0, NULL, J->o, &r, NULL, NULL);
+    double* gv = J->grad_v + 3 * i;
+    if (r.status == OR_RAY_BADINPUT) {
+        for (int c = 0; c < 3; c++) gv[c] = NAN;
+        for (int k = 0; k < 3 * J->K; k++) J->grad_W[3 * J->K * i + k] = NAN;
+        return;
+    }
+    const double* n0 = m->N + 3 * (int64_t)J->f[i];
+    double d0[3], q0[3], d1[3], q1[3];
+    int ident = !(r.L > 0.0);
+    if (!ident) {
+        memcpy(d0, r.d0, sizeof d0);
+        cross3(n0, d0, q0);
+        double ns[3];
+        for (int c = 0; c < 3; c++) { d1[c] = r.v[c] / r.L; ns[c] = r.sigma * m->N[3 * (int64_t)r.f + c]; }
+        unit3(d1);
+        cross3(ns, d1, q1);
+    }
+#define TVJP(gin, gout) do {                                                                   \
+        if (ident) { perp3(gin, n0, gout); }                                                    \
+        else {                                                                                  \
+            double a_ = dot3(gin, d1), b_ = dot3(gin, q1);                                      \
+            for (int c = 0; c < 3; c++) (gout)[c] = a_ * d0[c] + b_ * q0[c];                    \
+        }                                                                                       \
+    } while (0)
+    if (J->g_vo) TVJP(J->g_vo + 3 * i, gv);
+    else for (int c = 0; c < 3; c++) gv[c] = 0.0;
+    for (int k = 0; k < J->K; k++) TVJP(J->g_W + 3 * (J->K * i + k), J->grad_W + 3 * (J->K * i + k));
+#undef TVJP
+}
+
+int or_transport_vjp(const or_mesh* m, int64_t n, const int32_t* f, const double* b, const double* v,
+                     const or_opts* o, int32_t K, const double* g_v, const double* g_W, double* grad_v,
+                     double* grad_W, int32_t nthreads) {
+    if (!m || n < 0 || K < 0 || (n > 0 && (!f || !b || !v || !grad_v)) || (K > 0 && n > 0 && (!g_W || !grad_W))) {
+        set_err("bad arguments");
+        return OR_E_ARG;
+    }
+    job_t J = {0};
+    J.m = m; J.n = n; J.f = f; J.b = b; J.v = v; J.o = o; J.mode = 3; J.K = K;
+    J.g_vo = g_v; J.g_W = g_W; J.grad_v = grad_v; J.grad_W = grad_W;
+    return run_job(&J, nthreads);
 }
 
 int or_ep_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b, const double* v,

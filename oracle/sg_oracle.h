@@ -81,6 +81,14 @@ int or_gfd_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
                  const double* g, double* grad_v, double* grad_b,
                  double* Jv, double* Jp, int32_t nthreads);
 
+/* Cotangents of the transported outputs (an extension): W'_k = R W_k and
+ * v' = R v_t with R the walk's frame map from (d0, n0 x d0) to
+ * (d', sigma' n' x d'); returns grad_v [n*3] = P R^T g_v (zero if g_v is NULL)
+ * and grad_W [n*K*3] = P R^T g_W, P the projection onto the start plane. */
+int or_transport_vjp(const or_mesh* m, int64_t n, const int32_t* f, const double* b, const double* v,
+                     const or_opts* o, int32_t K, const double* g_v, const double* g_W, double* grad_v,
+                     double* grad_W, int32_t nthreads);
+
 /* Gradient of L = sum_i g_i . p'_i with respect to the vertex positions
  * (an extension: the paper differentiates only in v and p).  Away from
  * vertices p' = H_m o ... o H_1(p + v_t), a composition of the edge unfoldings

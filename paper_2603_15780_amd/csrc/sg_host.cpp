@@ -600,13 +600,18 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
     return SG_OK;
 }
 
-int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b, const float* v,
-                    const int32_t* f_out, const float* v_out, const float* g_p, float* grad_v, float* grad_b,
-                    double* grad_X, const sg_opts* opts, void* stream) {
+int sg_exp_backward_transport(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b,
+                              const float* v, int32_t K, const int32_t* f_out, const float* v_out, const float* g_p,
+                              const float* g_b, const float* g_v, const float* g_W, float* grad_v, float* grad_b,
+                              float* grad_W, double* grad_X, const sg_opts* opts, void* stream) {
     if (!mesh) return fail(SG_E_ARG, "mesh is NULL");
     if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
     if (mode != SG_BWD_EP && mode != SG_BWD_GFD) return fail(SG_E_ARG, "unknown backward mode %d", mode);
     if ((grad_v == nullptr) != (grad_b == nullptr)) return fail(SG_E_ARG, "grad_v and grad_b go together");
+    if (K < 0 || K > 64) return fail(SG_E_ARG, "K must be in [0, 64]");
+    if ((g_W == nullptr) != (grad_W == nullptr)) return fail(SG_E_ARG, "g_W and grad_W go together");
+    if (g_W && K == 0) return fail(SG_E_ARG, "g_W needs K > 0");
+    if ((g_v || g_W) && !grad_v) return fail(SG_E_ARG, "g_v and g_W need grad_v and grad_b");
     sg_opts o;
     int rc = check_opts(opts, o, mesh);
     if (rc != SG_OK) return rc;
@@ -614,7 +619,8 @@ int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, con
     if (!(std::isfinite(o.eps_v) && std::isfinite(o.eps_p))) return fail(SG_E_ARG, "eps_v and eps_p must be finite");
     if (n == 0) return SG_OK;
     if (n >= ((int64_t)1 << 31)) return fail(SG_E_ARG, "the backward takes fewer than 2^31 queries per call");
-    if (!f || !b || !v || !g_p) return fail(SG_E_ARG, "a required array is NULL");
+    if (!f || !b || !v) return fail(SG_E_ARG, "a required array is NULL");
+    if (!g_p && !g_b && !g_v && !g_W) return fail(SG_E_ARG, "no cotangent given (g_p, g_b, g_v and g_W are NULL)");
     const bool vjp = grad_v != nullptr;
     if (!vjp && !grad_X) return SG_OK;
     if (vjp && mode == SG_BWD_EP && !mesh->has_flip && (!f_out || !v_out))
@@ -625,21 +631,35 @@ int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, con
     a.f = f; a.b = b; a.v = v;
     a.f_out = f_out; a.v_out = v_out;
     a.g = g_p;
+    a.g_bo = g_b;
+    a.g_v = g_v;
+    a.g_W = g_W;
+    a.K = K;
     a.grad_v = grad_v; a.grad_b = grad_b;
-    a.grad_X = grad_X;
+    a.grad_W = grad_W;
+    a.grad_X = (g_p || g_b) ? grad_X : nullptr;
     a.eps_v = o.eps_v; a.eps_p = o.eps_p;
     a.max_steps = o.max_steps;
     a.snap = o.vertex_snap;
+    if (!vjp && !a.grad_X) return SG_OK;
     const hipStream_t st = (hipStream_t)stream;
     Workspace ws;
-    rc = take_workspace(o, sg::bwd_workspace(n, mode, mesh->has_flip != 0, vjp, grad_X != nullptr, mesh->n_faces), st,
-                        ws);
+    rc = take_workspace(o, sg::bwd_workspace(n, mode, mesh->has_flip != 0, vjp, a.grad_X != nullptr, mesh->n_faces),
+                        st, ws);
     if (rc != SG_OK) return rc;
     hipError_t e = sg::launch_backward(mesh->dev(o.boundary_mode), a, ws.p, sched(o), st);
     const hipError_t e2 = give_workspace(ws, st);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     if (e2 != hipSuccess) return hip_fail(e2, "workspace release");
     return SG_OK;
+}
+
+int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b, const float* v,
+                    const int32_t* f_out, const float* v_out, const float* g_p, float* grad_v, float* grad_b,
+                    double* grad_X, const sg_opts* opts, void* stream) {
+    if (n > 0 && !g_p) return fail(SG_E_ARG, "a required array is NULL");
+    return sg_exp_backward_transport(mesh, mode, n, f, b, v, 0, f_out, v_out, g_p, nullptr, nullptr, nullptr, grad_v,
+                                     grad_b, nullptr, grad_X, opts, stream);
 }
 
 int sg_exp_workspace_size(sg_mesh mesh, int64_t n, int32_t K, const sg_opts* opts, size_t* bytes) {

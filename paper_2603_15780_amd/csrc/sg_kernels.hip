@@ -1682,6 +1682,58 @@ SG_HD __forceinline__ int bwd_query(const DevMesh& M, const BwdArgs& a, int64_t 
 SG_HD __forceinline__ void nan_grads(const BwdArgs& a, int64_t i) {
     const float nan = __builtin_nanf("");
     for (int c = 0; c < 3; ++c) { a.grad_v[3 * i + c] = nan; a.grad_b[3 * i + c] = nan; }
+    if (a.g_W)
+        for (int k = 0; k < 3 * a.K; ++k) a.grad_W[3 * (i * a.K) + k] = nan;
+}
+
+// dL/dp' of query i, with the cotangent of the end barycentrics folded in:
+// inside end face fe (internal id; vertices y0, y1, y2), b'_k has the in-plane
+// gradient n x (y_{k+2} - y_{k+1}) / (2 A), n the unit normal of
+// (y1 - y0) x (y2 - y0) and 2 A its length.
+SG_HD __forceinline__ float3 load_g(const DevMesh& M, const BwdArgs& a, int64_t i, int32_t fe) {
+    float3 g = a.g ? ld3(a.g + 3 * i) : make_float3(0.f, 0.f, 0.f);
+    if (a.g_bo && fe >= 0) {
+        const int64_t f3 = 3 * (int64_t)fe;
+        const float3 y0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
+        const float3 y1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
+        const float3 y2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+        const float3 c = crs(sub(y1, y0), sub(y2, y0));
+        const float inv = 1.0f / dot(c, c);   // n / (2A) = c / |c|^2
+        const float3 gb = ld3(a.g_bo + 3 * i);
+        const float3 e = make_float3(gb.x * inv, gb.y * inv, gb.z * inv);
+        const float3 t0 = crs(c, sub(y2, y1)), t1 = crs(c, sub(y0, y2)), t2 = crs(c, sub(y1, y0));
+        g = make_float3(g.x + e.x * t0.x + e.y * t1.x + e.z * t2.x, g.y + e.x * t0.y + e.y * t1.y + e.z * t2.y,
+                        g.z + e.x * t0.z + e.y * t1.z + e.z * t2.z);
+    }
+    return g;
+}
+
+// Cotangents of the transported outputs (an extension of the paper's
+// backward).  The walk carries the frame (d, n x d) from (e_par, e_perp) at p
+// to (d', q' = n' x d') at p' (Sec. 4 "Parallel Transport": a transported
+// vector keeps its angle to the tangent), so W'_k = R W_k and v' = R v_t with
+// R that frame map, constant wherever the face sequence is.  dL/dv gains
+// R^T g_v and dL/dW_k = R^T g_Wk, both in the start face's plane (v and W are
+// projected onto it first).  ident (|v_t| = 0: nothing moves): R = I, and
+// the cotangents are projected with the start normal n0.
+SG_HD __forceinline__ void transport_cot(const BwdArgs& a, int64_t i, bool ident, float3 epar, float3 eperp, float3 d3,
+                                         float3 q3, float3 n0) {
+    auto back = [&](float3 g) {
+        if (ident) return sub(g, scl(n0, dot(g, n0)));
+        const float c0 = dot(g, d3), c1 = dot(g, q3);
+        return make_float3(fmaf(c0, epar.x, c1 * eperp.x), fmaf(c0, epar.y, c1 * eperp.y),
+                           fmaf(c0, epar.z, c1 * eperp.z));
+    };
+    if (a.g_v) {
+        const float3 t = back(ld3(a.g_v + 3 * i));
+        a.grad_v[3 * i] += t.x; a.grad_v[3 * i + 1] += t.y; a.grad_v[3 * i + 2] += t.z;
+    }
+    if (a.g_W)
+        for (int k = 0; k < a.K; ++k) {
+            const int64_t j = 3 * (i * a.K + k);
+            const float3 t = back(ld3(a.g_W + j));
+            a.grad_W[j] = t.x; a.grad_W[j + 1] = t.y; a.grad_W[j + 2] = t.z;
+        }
 }
 
 // Stage 1: the walks that start at p.  Slot 0 recomputes Exp(p, v); for the
@@ -1782,7 +1834,7 @@ SG_HD void gfd_assemble(const DevMesh& M, const BwdArgs& a, const StateRec* s1, 
     const float3 cv = scl(sub(final_offset(M, Fv, o, ft), q0), ip);
     const float2 j0 = pinv_uv(eu2, ev2, cpar), j1 = pinv_uv(eu2, ev2, cperp);   // J^v columns
     const float2 k0 = pinv_uv(eu2, ev2, cu), k1 = pinv_uv(eu2, ev2, cv);         // J^p columns
-    const float3 g = ld3(a.g + 3 * i);
+    const float3 g = load_g(M, a, i, F0.h / 3);
     const float h0 = dot(eu2, g), h1 = dot(ev2, g);
     // J^T (M'^T g)
     const float c0 = fmaf(j0.x, h0, j0.y * h1), c1 = fmaf(j1.x, h0, j1.y * h1);
@@ -1810,12 +1862,18 @@ SG_HD void gfd_assemble(const DevMesh& M, const BwdArgs& a, const StateRec* s1, 
     a.grad_b[3 * i] = dot(G, S.x0);
     a.grad_b[3 * i + 1] = dot(G, x1);
     a.grad_b[3 * i + 2] = dot(G, x2);
+    if (a.g_v || a.g_W) {
+        float3 d3, n3;
+        final_frame(M, F0, d3, n3);
+        transport_cot(a, i, !(L > 0.f), epar, eperp, d3, crs(n3, d3), S.n);
+    }
 }
 
 // Extrinsic proxy (eq. proxy_func): J^v = R = M_{p'} M_p^T with frames
 // [e_par, e_perp, n], J^p = 0.  grad_v = R^T g = M_p (M_{p'}^T g).
-SG_HD __forceinline__ void ep_grad(const BwdArgs& a, int64_t i, const StartFrame& S, uint32_t phi0, float3 d3, float3 n3) {
-    const float3 g = ld3(a.g + 3 * i);
+SG_HD __forceinline__ void ep_grad(const DevMesh& M, const BwdArgs& a, int64_t i, const StartFrame& S, uint32_t phi0,
+                                   float3 d3, float3 n3, int32_t fe) {
+    const float3 g = load_g(M, a, i, fe);
     float sn, cs;
     sincos_full(phi0, sn, cs);
     const float3 epar = make_float3(fmaf(cs, S.ex.x, sn * S.ey.x), fmaf(cs, S.ex.y, sn * S.ey.y),
@@ -1827,6 +1885,16 @@ SG_HD __forceinline__ void ep_grad(const BwdArgs& a, int64_t i, const StartFrame
     a.grad_v[3 * i + 1] = fmaf(a0, epar.y, fmaf(a1, eperp.y, a2 * S.n.y));
     a.grad_v[3 * i + 2] = fmaf(a0, epar.z, fmaf(a1, eperp.z, a2 * S.n.z));
     a.grad_b[3 * i] = a.grad_b[3 * i + 1] = a.grad_b[3 * i + 2] = 0.f;
+    transport_cot(a, i, false, epar, eperp, d3, q, S.n);
+}
+
+// |v_t| = 0: nothing moves (R = I).
+SG_HD __forceinline__ void ep_identity(const DevMesh& M, const BwdArgs& a, int64_t i, const StartFrame& S) {
+    const float3 g = load_g(M, a, i, S.f);
+    a.grad_v[3 * i] = g.x; a.grad_v[3 * i + 1] = g.y; a.grad_v[3 * i + 2] = g.z;
+    a.grad_b[3 * i] = a.grad_b[3 * i + 1] = a.grad_b[3 * i + 2] = 0.f;
+    const float3 z = make_float3(0.f, 0.f, 0.f);
+    transport_cot(a, i, true, z, z, z, z, S.n);
 }
 
 // EP from the saved forward outputs (orientable meshes: the end normal is the
@@ -1843,14 +1911,14 @@ SG_HD void ep_saved(const DevMesh& M, const BwdArgs& a, int64_t i) {
     const float3 vo = ld3(a.v_out + 3 * i);
     const float lo = sqrtf(dot(vo, vo));
     if (!(L > 0.f) || !(lo > 0.f)) {   // |v| = 0: R = I
-        for (int c = 0; c < 3; ++c) { a.grad_v[3 * i + c] = a.g[3 * i + c]; a.grad_b[3 * i + c] = 0.f; }
+        ep_identity(M, a, i, S);
         return;
     }
     const int64_t f3 = 3 * (int64_t)M.perm[fo];
     const float3 y0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
     const float3 y1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
     const float3 y2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
-    ep_grad(a, i, S, phi0, scl(vo, 1.0f / lo), nrm(crs(sub(y1, y0), sub(y2, y0))));
+    ep_grad(M, a, i, S, phi0, scl(vo, 1.0f / lo), nrm(crs(sub(y1, y0), sub(y2, y0))), M.perm[fo]);
 }
 
 // EP from a recomputed walk (meshes whose faces disagree in orientation: the
@@ -1865,12 +1933,12 @@ SG_HD void ep_walked(const DevMesh& M, const BwdArgs& a, const StateRec* s1, int
         return;
     }
     if (!(L > 0.f)) {
-        for (int c = 0; c < 3; ++c) { a.grad_v[3 * i + c] = a.g[3 * i + c]; a.grad_b[3 * i + c] = 0.f; }
+        ep_identity(M, a, i, S);
         return;
     }
     float3 d3, n3;
     final_frame(M, F0, d3, n3);
-    ep_grad(a, i, S, phi0, d3, n3);
+    ep_grad(M, a, i, S, phi0, d3, n3, F0.h / 3);
 }
 
 // ---------------------------------------------------------------- vertex-position gradient
@@ -1900,7 +1968,7 @@ SG_HD void gradx_init(const DevMesh& M, const BwdArgs& a, const StateRec* s1, in
     if (F0.flags & kBndBit) return;   // slid along a boundary: not a chain of hinges
     float3 d3, n3;
     final_frame(M, F0, d3, n3);
-    const float3 g = ld3(a.g + 3 * i);
+    const float3 g = load_g(M, a, i, F0.h / 3);
     const float4 c = make_float4(dot(g, d3), dot(g, crs(n3, d3)), dot(g, n3), 0.f);
     if (c.x == 0.f && c.y == 0.f && c.z == 0.f) return;   // g = 0: nothing to add
     float sn, cs;

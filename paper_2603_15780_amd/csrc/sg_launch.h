@@ -38,9 +38,14 @@ struct BwdArgs {
     const float* v;
     const int32_t* f_out;   // saved forward outputs (extrinsic proxy)
     const float* v_out;
-    const float* g;         // dL/dp'
+    const float* g;         // dL/dp', or null (zero)
+    const float* g_bo;      // dL/db' [n,3] (end barycentrics), or null
+    const float* g_v;       // dL/dv' [n,3], or null
+    const float* g_W;       // dL/dW' [n,K,3], or null
+    int32_t K;              // transported vectors per query (g_W, grad_W)
     float* grad_v;
     float* grad_b;
+    float* grad_W;          // dL/dW [n,K,3] (with g_W)
     float eps_v, eps_p;
     int32_t max_steps;
     float snap;

@@ -65,6 +65,9 @@ def lib():
         L.sg_exp_transport.restype = C.c_int
         L.sg_exp_backward.argtypes = [P, I32, I64, P, P, P, P, P, P, P, P, P, C.POINTER(Opts), P]
         L.sg_exp_backward.restype = C.c_int
+        L.sg_exp_backward_transport.argtypes = [P, I32, I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P,
+                                                C.POINTER(Opts), P]
+        L.sg_exp_backward_transport.restype = C.c_int
         L.sg_exp_workspace_size.argtypes = [P, I64, I32, C.POINTER(Opts), C.POINTER(C.c_size_t)]
         L.sg_exp_workspace_size.restype = C.c_int
         L.sg_backward_workspace_size.argtypes = [P, I32, I64, I32, I32, C.POINTER(Opts), C.POINTER(C.c_size_t)]
@@ -213,18 +216,38 @@ class Mesh:
         return out
 
     def backward(self, mode, f, b, v, g, *, f_out=None, v_out=None, out=None, grad_X=None, want_vjp=True,
-                 o: Opts | None = None, **kw):
+                 g_b=None, g_v=None, g_W=None, o: Opts | None = None, **kw):
         """(grad_v, grad_b) for upstream g = dL/dp' [n,3]; mode BWD_EP or BWD_GFD.
 
         grad_X: a float64 [n_verts, 3] tensor to accumulate dL/dX into (or None).
         want_vjp=False skips grad_v / grad_b (returns (None, None)).
+        g_b = dL/db' [n,3], g_v = dL/dv' [n,3] and g_W = dL/dW' [n,K,3] (optional; g
+        may then be None) add the other outputs' cotangents; with g_W the result
+        is (grad_v, grad_b, grad_W).
         """
         import torch
         n = f.shape[0]
         dev = f.device
         assert f.dtype == torch.int32 and b.dtype == torch.float32 and v.dtype == torch.float32
-        assert g.dtype == torch.float32 and g.is_contiguous() and g.shape == (n, 3)
         assert f.is_contiguous() and b.is_contiguous() and v.is_contiguous()
+        for t, shape in ((g, (n, 3)), (g_b, (n, 3)), (g_v, (n, 3))):
+            assert t is None or (t.dtype == torch.float32 and t.is_contiguous() and t.shape == shape)
+        if g_b is not None or g_v is not None or g_W is not None:
+            K = 0 if g_W is None else g_W.shape[1]
+            assert g_W is None or (g_W.dtype == torch.float32 and g_W.is_contiguous() and g_W.shape == (n, K, 3))
+            if o is None:
+                o = opts(**kw)
+            gv_ = torch.empty(n, 3, dtype=torch.float32, device=dev)
+            gb_ = torch.empty(n, 3, dtype=torch.float32, device=dev)
+            gW_ = torch.empty(n, K, 3, dtype=torch.float32, device=dev) if g_W is not None else None
+            if grad_X is not None:
+                assert grad_X.dtype == torch.float64 and grad_X.is_contiguous() and grad_X.shape == (self.n_verts, 3)
+            _check(lib().sg_exp_backward_transport(
+                self._h, int(mode), n, _dptr(f), _dptr(b), _dptr(v), K, _dptr(f_out), _dptr(v_out), _dptr(g),
+                _dptr(g_b), _dptr(g_v), _dptr(g_W), _dptr(gv_), _dptr(gb_), _dptr(gW_), _dptr(grad_X), C.byref(o),
+                _stream()))
+            return (gv_, gb_, gW_) if g_W is not None else (gv_, gb_)
+        assert g is not None
         if grad_X is not None:
             assert grad_X.dtype == torch.float64 and grad_X.is_contiguous() and grad_X.shape == (self.n_verts, 3)
         if o is None:
@@ -247,28 +270,38 @@ def _autograd_function():
         Inputs: f [n] int32, b [n,3], v [n,3] float32 (cuda); X [V,3] (the
         mesh's vertex positions as a tensor, or None) receives dL/dX from the
         float64 vertex-gradient pass.  mode: BWD_EP or BWD_GFD for dL/dv and
-        dL/db.  Only the end point p' is differentiated (dL/dv' and dL/dW' are
-        not part of the backward).
+        dL/db.  The end point p', its barycentrics b', the end tangent v' and
+        the transported vectors W' (when W [n,K,3] is given) are
+        differentiated; dL/dX takes the p' and b' terms.
         """
 
         @staticmethod
-        def forward(ctx, mesh, mode, f, b, v, X, opts_kw):
-            out = mesh.exp(f.contiguous(), b.contiguous(), v.contiguous(), **(opts_kw or {}))
+        def forward(ctx, mesh, mode, f, b, v, W, X, opts_kw):
+            Wc = None if W is None else W.contiguous().float()
+            out = mesh.exp(f.contiguous(), b.contiguous(), v.contiguous(), Wc, **(opts_kw or {}))
             ctx.mesh, ctx.mode, ctx.opts_kw = mesh, mode, opts_kw or {}
             ctx.want_x = X is not None and X.requires_grad
             ctx.x_dtype = X.dtype if X is not None else None
+            ctx.K = 0 if W is None else W.shape[1]
             ctx.save_for_backward(f, b, v, out["f"], out["v"])
-            ctx.mark_non_differentiable(out["f"], out["b"], out["v"], out["status"])
-            return out["p"], out["f"], out["b"], out["v"], out["status"]
+            ctx.mark_non_differentiable(out["f"], out["status"])
+            if W is None:
+                return out["p"], out["f"], out["b"], out["v"], out["status"]
+            return out["p"], out["f"], out["b"], out["v"], out["W"], out["status"]
 
         @staticmethod
-        def backward(ctx, g_p, *unused):
+        def backward(ctx, g_p, g_f, g_b, g_vo, *rest):
             f, b, v, f_out, v_out = ctx.saved_tensors
+            g_Wo = rest[0] if ctx.K else None
             g = g_p.contiguous().float()
             gX = torch.zeros(ctx.mesh.n_verts, 3, dtype=torch.float64, device=g.device) if ctx.want_x else None
-            gv, gb = ctx.mesh.backward(ctx.mode, f.contiguous(), b.contiguous(), v.contiguous(), g, f_out=f_out,
-                                       v_out=v_out, grad_X=gX, **ctx.opts_kw)
-            return (None, None, None, gb, gv, gX.to(ctx.x_dtype) if gX is not None else None, None)
+            res = ctx.mesh.backward(ctx.mode, f.contiguous(), b.contiguous(), v.contiguous(), g, f_out=f_out,
+                                    v_out=v_out, grad_X=gX, g_b=g_b.contiguous().float(),
+                                    g_v=g_vo.contiguous().float(),
+                                    g_W=None if g_Wo is None else g_Wo.contiguous().float(), **ctx.opts_kw)
+            gv, gb = res[0], res[1]
+            gW = res[2] if g_Wo is not None else None
+            return (None, None, None, gb, gv, gW, gX.to(ctx.x_dtype) if gX is not None else None, None)
 
     return ExpFunction
 
@@ -276,10 +309,41 @@ def _autograd_function():
 _ExpFunction = None
 
 
-def exp_with_grad(mesh, f, b, v, X=None, mode=BWD_GFD, **opts_kw):
-    """Differentiable Exp: returns (p', f', b', v', status); p' carries the library's backward
-    to b and v (mode BWD_EP or BWD_GFD) and, when X is a tensor that requires grad, to X."""
+def exp_with_grad(mesh, f, b, v, X=None, mode=BWD_GFD, W=None, **opts_kw):
+    """Differentiable Exp: returns (p', f', b', v', status), or (p', f', b', v', W', status) when
+    W [n,K,3] is given.  p', v' and W' carry the library's backward to b, v and W (mode BWD_EP
+    or BWD_GFD for p'), and p' to X when X is a tensor that requires grad."""
     global _ExpFunction
     if _ExpFunction is None:
         _ExpFunction = _autograd_function()
-    return _ExpFunction.apply(mesh, mode, f, b, v, X, opts_kw)
+    return _ExpFunction.apply(mesh, mode, f, b, v, W, X, opts_kw)
+
+
+def exp_iterated(mesh, f, b, field, steps, **opts_kw):
+    """Exp applied `steps` times with a vector field re-evaluated at each intermediate point:
+    p_{k+1} = Exp_{p_k}(field(p_k, f_k, b_k) / steps) (the K-step map of the paper's flow
+    matching, Sec. "MeshFlow").  field(p [n,3], f [n], b [n,3]) -> v [n,3] float32 tensor.
+    Differentiable (exp_with_grad, mode BWD_GFD by default): gradients flow through the field's
+    outputs and, step to step, through the start points (the end barycentrics' cotangents).
+    Returns (p, f, b) of the last step and the list of intermediate points."""
+    import torch
+    mode = opts_kw.pop("mode", BWD_GFD)
+    dev = f.device
+    pts = []
+    p = None
+    for _ in range(int(steps)):
+        if p is None:
+            out = mesh.exp(f, b, torch.zeros(f.shape[0], 3, dtype=torch.float32, device=dev), **opts_kw)
+            p = out["p"]
+        v = field(p, f, b) / float(steps)
+        p, f, b, _, _ = exp_with_grad(mesh, f, b.contiguous(), v.contiguous().float(), mode=mode, **opts_kw)
+        pts.append(p)
+    return (p, f, b), pts
+
+
+def transport_back(mesh, f_out, b_out, v_out, W, **opts_kw):
+    """Adjoint (inverse) of the parallel transport of an earlier call: carries vectors W [n,K,3]
+    at p' back along the same geodesic to p, by walking from (f', b') with -v' (a walk reversed
+    from its end retraces its path).  Returns (W at p [n,K,3], status)."""
+    out = mesh.exp(f_out.contiguous(), b_out.contiguous(), (-v_out).contiguous(), W.contiguous(), **opts_kw)
+    return out["W"], out["status"]

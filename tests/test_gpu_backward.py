@@ -381,3 +381,115 @@ def test_backward_hole_avoidance(torch, mode):
     got, _ = gpu_gradx(torch, sg.Mesh(X, F), r, gk, mode=mode, want_vjp=True, boundary_mode=1)
     s = gradx_report(ref, got)
     assert s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, s
+
+
+# ---------------------------------------------------------------- cotangents of b', v', W'; iterated Exp; adjoint transport
+@pytest.mark.parametrize("mode", [0, 1])
+def test_transport_cotangents(torch, mode):
+    """dL/dv' and dL/dW' through the transport (R^T in the start plane) against
+    the oracle's, in both modes (the p' term left out: g_p = None)."""
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    rng = np.random.default_rng(91)
+    r = random_rays(X, F, 4096, rng, uniform_len(0.0, 2.0), K=2)
+    gvo = rng.standard_normal((4096, 3)).astype(np.float32)
+    gWo = rng.standard_normal((4096, 2, 3)).astype(np.float32)
+    om = oracle.Mesh(X, F)
+    o = om.exp(r["f"], r["b"], r["v"])
+    ref_v, ref_W = om.transport_vjp(r["f"], r["b"], r["v"], gvo, gWo)
+    gm = sg.Mesh(X, F)
+    t = dev_inputs(torch, r, gvo)
+    out = gm.exp(t["f"], t["b"], t["v"])
+    gv, gb, gW = gm.backward(mode, t["f"], t["b"], t["v"], None, f_out=out["f"], v_out=out["v"], g_v=t["g"],
+                             g_W=torch.from_numpy(gWo).cuda())
+    torch.cuda.synchronize()
+    gv, gb, gW = gv.cpu().numpy(), gb.cpu().numpy(), gW.cpu().numpy()
+    ok = o["status"] == 0
+    scale = np.linalg.norm(gvo, axis=1)
+    ev = np.linalg.norm(gv - ref_v, axis=1) / scale
+    eW = np.linalg.norm(gW - ref_W, axis=2) / np.linalg.norm(gWo, axis=2)
+    assert np.mean(ev[ok] < 1e-4) >= 0.999 and np.mean(eW[ok] < 1e-4) >= 0.999, (ev.max(), eW.max())
+    assert np.abs(gb).max() == 0.0   # no p' cotangent: nothing for the start point
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_end_barycentric_cotangent(torch, mode):
+    """dL/db' enters as dL/dp' = sum_k g_bk grad b'_k inside the end face."""
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    rng = np.random.default_rng(92)
+    r = random_rays(X, F, 2048, rng, uniform_len(0.0, 2.0))
+    gbo = rng.standard_normal((2048, 3)).astype(np.float32)
+    gm = sg.Mesh(X, F)
+    t = dev_inputs(torch, r, gbo)
+    out = gm.exp(t["f"], t["b"], t["v"])
+    fo = out["f"].cpu().numpy()
+    Xd = X.astype(np.float64)
+    y0, y1, y2 = (Xd[F[fo, k]] for k in range(3))
+    c = np.cross(y1 - y0, y2 - y0)
+    c2 = (c * c).sum(1)[:, None]
+    grads = [np.cross(c, y2 - y1) / c2, np.cross(c, y0 - y2) / c2, np.cross(c, y1 - y0) / c2]
+    gp = sum(gbo[:, k:k + 1] * grads[k] for k in range(3)).astype(np.float32)
+    a = gm.backward(mode, t["f"], t["b"], t["v"], None, f_out=out["f"], v_out=out["v"], g_b=t["g"])
+    b_ = gm.backward(mode, t["f"], t["b"], t["v"], torch.from_numpy(gp).cuda(), f_out=out["f"], v_out=out["v"])
+    torch.cuda.synchronize()
+    for x, y in zip(a, b_):
+        x, y = x.cpu().numpy(), y.cpu().numpy()
+        assert np.abs(x - y).max() <= 1e-4 * np.abs(y).max()
+
+
+def test_autograd_all_outputs_and_iterated(torch):
+    """exp_with_grad differentiates p', b', v' and W' (the library's backward,
+    checked against explicit calls), and exp_iterated chains steps."""
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    rng = np.random.default_rng(93)
+    r = random_rays(X, F, 1024, rng, uniform_len(0.0, 1.0), K=2)
+    gm = sg.Mesh(X, F)
+    dev = torch.device("cuda:0")
+    f = torch.from_numpy(r["f"]).to(dev)
+    b = torch.from_numpy(r["b"].astype(np.float32)).to(dev).requires_grad_(True)
+    v = torch.from_numpy(r["v"].astype(np.float32)).to(dev).requires_grad_(True)
+    W = torch.from_numpy(r["W"].astype(np.float32)).to(dev).requires_grad_(True)
+    cs = [torch.from_numpy(rng.standard_normal(s).astype(np.float32)).to(dev) for s in ((1024, 3), (1024, 3), (1024, 3), (1024, 2, 3))]
+    p, fo, bo, vo, Wo, st = sg.exp_with_grad(gm, f, b, v, mode=sg.BWD_EP, W=W)
+    loss = (p * cs[0]).sum() + (bo * cs[1]).sum() + (vo * cs[2]).sum() + (Wo * cs[3]).sum()
+    loss.backward()
+    out = gm.exp(f, b.detach(), v.detach(), W.detach())
+    gv, gb, gW = gm.backward(sg.BWD_EP, f, b.detach().contiguous(), v.detach().contiguous(), cs[0], f_out=out["f"],
+                             v_out=out["v"], g_b=cs[1], g_v=cs[2], g_W=cs[3])
+    torch.cuda.synchronize()
+    assert torch.allclose(v.grad, gv) and torch.allclose(b.grad, gb) and torch.allclose(W.grad, gW)
+    # iterated: a rotating field, two steps; finite gradients to its parameter
+    theta = torch.tensor(0.3, device=dev, requires_grad=True)
+    axis = torch.tensor([0.0, 0.0, 1.0], device=dev)
+    field = lambda pp, ff, bb: theta * torch.cross(axis.expand_as(pp), pp, dim=1)
+    b0 = torch.from_numpy(r["b"].astype(np.float32)).to(dev)
+    (pK, fK, bK), pts = sg.exp_iterated(gm, f, b0, field, 2)
+    assert len(pts) == 2 and torch.isfinite(pK).all()
+    pK.sum().backward()
+    assert torch.isfinite(theta.grad)
+
+
+def test_transport_back_inverts_transport(torch):
+    """Carrying W' back along the same geodesic (from p' with -v') returns W."""
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    rng = np.random.default_rng(94)
+    r = random_rays(X, F, 4096, rng, uniform_len(0.0, 2.0), K=2)
+    om = oracle.Mesh(X, F)
+    o = om.exp(r["f"], r["b"], r["v"], r["W"])
+    gm = sg.Mesh(X, F)
+    dev = torch.device("cuda:0")
+    t = {k: torch.from_numpy(np.ascontiguousarray(r[k])).to(dev) for k in ("f", "b", "v", "W")}
+    out = gm.exp(t["f"], t["b"], t["v"], t["W"])
+    Wb, st = sg.transport_back(gm, out["f"], out["b"], out["v"], out["W"])
+    torch.cuda.synchronize()
+    Wb = Wb.cpu().numpy()
+    ok = (o["status"] == 0) & (o["min_vdist"] > 1e-3 * om.mean_edge) & (st.cpu().numpy() == 0)
+    Xd = X.astype(np.float64)
+    n0 = np.cross(Xd[F[r["f"], 1]] - Xd[F[r["f"], 0]], Xd[F[r["f"], 2]] - Xd[F[r["f"], 0]])
+    n0 /= np.linalg.norm(n0, axis=1)[:, None]
+    Wt = r["W"] - (r["W"] * n0[:, None, :]).sum(2)[:, :, None] * n0[:, None, :]
+    err = np.linalg.norm(Wb - Wt, axis=2) / np.linalg.norm(Wt, axis=2)
+    assert ok.sum() > 1000 and np.quantile(err[ok], 0.999) < 1e-4, np.quantile(err[ok], 0.999)

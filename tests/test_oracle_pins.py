@@ -562,3 +562,46 @@ def test_gradx_translation(rng):
     g[~keep] = 0.0
     gx, _ = om.gradx(r["f"], r["b"], r["v"], g)
     assert np.allclose(gx.sum(0), g.sum(0), rtol=1e-7, atol=1e-7)
+
+
+# ---------------------------------------------------------------- transported outputs (backward extension)
+def test_transport_vjp_against_central_differences():
+    """dL/dv from dL/dv' and dL/dW from dL/dW' (W'_k = R W_k, v' = R v_t, R the
+    frame the walk carries): directional derivatives of the float64 forward,
+    by central differences in v (margin rays) and in W (linear: every ray)."""
+    X, F = M.canonical(M.sh_displace(M.icosphere(3)[0], 6, 0.1, np.random.default_rng(81)), M.icosphere(3)[1])
+    m = oracle.Mesh(X, F)
+    rng = np.random.default_rng(82)
+    r = random_rays(X, F, 300, rng, uniform_len(0.0, 2.0), K=2)
+    f, b = r["f"], r["b"].astype(np.float64)
+    v, W = r["v"].astype(np.float64), r["W"].astype(np.float64)
+    o = m.exp(f, b, v, W)
+    gv_out = rng.normal(size=(300, 3))
+    gW_out = rng.normal(size=(300, 2, 3))
+    gv, gW = m.transport_vjp(f, b, v, gv_out, gW_out)
+    dv = rng.normal(size=(300, 3))
+    dW = rng.normal(size=(300, 2, 3))
+    h = 1e-6
+    vp = m.exp(f, b, v + h * dv, W)["v"]
+    vm = m.exp(f, b, v - h * dv, W)["v"]
+    fd_v = ((vp - vm) / (2 * h) * gv_out).sum(1)
+    margin = (o["min_vdist"] > 1e-3 * m.mean_edge) & (o["status"] == 0)
+    assert margin.sum() > 150
+    an_v = (dv * gv).sum(1)
+    scale = np.linalg.norm(dv, axis=1) * np.linalg.norm(gv_out, axis=1)
+    assert np.abs(fd_v - an_v)[margin].max() < 1e-6 * scale[margin].max()
+    Wp = m.exp(f, b, v, W + h * dW)["W"]
+    Wm = m.exp(f, b, v, W - h * dW)["W"]
+    fd_W = ((Wp - Wm) / (2 * h) * gW_out).sum((1, 2))
+    ok = o["status"] == 0
+    an_W = (dW * gW).sum((1, 2))
+    assert np.abs(fd_W - an_W)[ok].max() < 1e-7 * np.abs(an_W[ok]).max()
+    # a wrong frame (transposed map, dropped orientation) would fail the checks above;
+    # a zero-length ray transports nothing: the projection onto the start plane
+    z = np.zeros((3, 3))
+    gz, gWz = m.transport_vjp(f[:3], b[:3], z, gv_out[:3], gW_out[:3])
+    Xd = X.astype(np.float64)
+    n0 = np.cross(Xd[F[f[:3], 1]] - Xd[F[f[:3], 0]], Xd[F[f[:3], 2]] - Xd[F[f[:3], 0]])
+    n0 /= np.linalg.norm(n0, axis=1)[:, None]
+    assert np.allclose(gz, gv_out[:3] - (gv_out[:3] * n0).sum(1)[:, None] * n0, atol=1e-15)
+    assert np.allclose(gWz, gW_out[:3] - (gW_out[:3] * n0[:, None, :]).sum(2)[:, :, None] * n0[:, None, :], atol=1e-15)
