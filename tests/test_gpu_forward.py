@@ -578,3 +578,19 @@ def test_update_vertices(torch):
     d = run(torch, gm, r, kernel=2)
     for k in ("f", "b", "p", "v", "W", "status", "n_cross", "hash"):
         assert np.array_equal(before[k], d[k]), k
+
+
+@pytest.mark.parametrize("kind,level", [("noise", 0.05), ("noise", 0.2), ("slim", 0.1), ("slim", 0.33)])
+def test_robustness_noise_and_slim_faces(torch, kind, level):
+    """Mesh-quality sweeps (the paper's robustness study, synthetic): vertex
+    noise along the normals (sigma relative to the mean edge) and slim
+    triangles (slivers with aspect up to ~13); parity with the oracle."""
+    X, F = M.icosphere(4)
+    X = M.sh_displace(X, 6, 0.1, np.random.default_rng(95))
+    rng = np.random.default_rng(96)
+    X = M.normal_noise(X, F, level, rng) if kind == "noise" else M.slim_faces(X, F, level, rng)
+    X, F = M.canonical(X, F)
+    r = random_rays(X, F, 8000, np.random.default_rng(97), uniform_len(0.0, 3.0), K=2)
+    for kernel in (1, 2):
+        om, gm, o, g = both(torch, X, F, r, kernel=kernel)
+        assert_parity(o, g, om.mean_edge, K=2, label=f"{kind} {level} kernel {kernel}")

@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "icosahedron", "icosphere", "geodesic_sphere", "sh_displace", "normal_noise",
     "torus_grid", "mobius_strip", "klein_bottle", "tetrahedron", "octahedron", "cube_grid", "flat_grid", "prism",
-    "canonical", "mean_edge", "orient_outward", "remove_faces", "plane_with_hole",
+    "canonical", "mean_edge", "orient_outward", "remove_faces", "plane_with_hole", "slim_faces",
 ]
 
 
@@ -218,6 +218,26 @@ def normal_noise(X, F, sigma_rel_edge: float, rng):
     X = np.asarray(X, dtype=np.float64)
     sig = sigma_rel_edge * mean_edge(X, F)
     return X + rng.normal(0.0, sig, X.shape[0])[:, None] * vertex_normals(X, F)
+
+
+def slim_faces(X, F, frac: float, rng, lo: float = 0.6, hi: float = 0.9):
+    """Slim triangles: a fraction `frac` of the vertices (no two adjacent) each
+    move a fraction U[lo, hi] of the way toward the midpoint of the opposite
+    edge of one incident face, which becomes a sliver (its height shrinks by
+    that fraction) while the faces around stretch."""
+    X = np.asarray(X, dtype=np.float64).copy()
+    F = np.asarray(F)
+    inc = [[] for _ in range(X.shape[0])]
+    for fi, (a, b, c) in enumerate(F):
+        inc[a].append((b, c)); inc[b].append((c, a)); inc[c].append((a, b))
+    taken = np.zeros(X.shape[0], bool)
+    for v in rng.permutation(X.shape[0]):
+        if rng.uniform() >= frac or taken[v] or any(taken[u] for e in inc[v] for u in e):
+            continue
+        a, b = inc[v][rng.integers(len(inc[v]))]
+        X[v] += rng.uniform(lo, hi) * (0.5 * (X[a] + X[b]) - X[v])
+        taken[v] = True
+    return X
 
 
 def _twisted_grid(nu, nv, periodic_v):
