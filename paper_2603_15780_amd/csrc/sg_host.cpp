@@ -39,13 +39,15 @@ struct sg_mesh_s {
     int32_t* d_perm = nullptr;
     int32_t* d_order = nullptr;
     int32_t* d_twin = nullptr;
+    float* d_geo = nullptr;
     int32_t part_he[sg::kParts + 1] = {};
     int32_t has_flip = 0;
     size_t bytes = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare;   // walk-kernel event pairs
     sg::PackedMesh host;   // connectivity, links and face order, for sg_mesh_update_vertices
     sg::DevMesh dev(int32_t hole_avoid = 0) const {
-        sg::DevMesh d{d_face, d_F, d_X, d_half, d_perm, d_order, n_faces, n_verts, has_flip, {}, d_twin, hole_avoid};
+        sg::DevMesh d{d_face,  d_F,     d_X,     d_half, d_perm,     d_order,
+                      n_faces, n_verts, has_flip, {},   d_twin, hole_avoid, reinterpret_cast<const float4*>(d_geo)};
         for (int p = 0; p <= sg::kParts; ++p) d.part_he[p] = part_he[p];
         return d;
     }
@@ -127,6 +129,7 @@ void free_mesh(sg_mesh_s* m) {
     (void)hipFree(m->d_perm);
     (void)hipFree(m->d_order);
     (void)hipFree(m->d_twin);
+    (void)hipFree(m->d_geo);
     delete m;
 }
 
@@ -414,6 +417,19 @@ int pack_geometry(const float* X_host, PackedMesh& pm) {
         for (int64_t v = 0; v < n_verts; ++v) pm.half[v] = pm.vbnd[v] ? -1 : theta_fx[v] / 2;
         pm.X.assign(X_host, X_host + 3 * n_verts);
         pm.mean_edge = esum / (double)ecount;
+        pm.geo.assign(16 * (size_t)n_faces, 0.f);
+        for (int64_t f = 0; f < n_faces; ++f) {
+            float* g = &pm.geo[16 * (size_t)f];
+            for (int k = 0; k < 3; ++k) {
+                const int32_t v = F[3 * f + k];
+                g[4 * k] = X_host[3 * (int64_t)v];
+                g[4 * k + 1] = X_host[3 * (int64_t)v + 1];
+                g[4 * k + 2] = X_host[3 * (int64_t)v + 2];
+                std::memcpy(&g[4 * k + 3], &v, sizeof v);
+            }
+            const int32_t u = (int32_t)pm.order[f];
+            std::memcpy(&g[12], &u, sizeof u);
+        }
         return SG_OK;
     } catch (const std::bad_alloc&) {
         return fail(SG_E_OOM, "out of host memory");
@@ -476,12 +492,15 @@ int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, 
     if (rc == SG_OK) rc = upload(&m->d_perm, pm.perm, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_order, order32, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_twin, pm.twin, m->bytes);
+    if (rc == SG_OK) rc = upload(&m->d_geo, pm.geo, m->bytes);
     if (rc != SG_OK) {
         free_mesh(m);
         return rc;
     }
     pm.X.clear();
     pm.X.shrink_to_fit();
+    pm.geo.clear();
+    pm.geo.shrink_to_fit();
     m->host = std::move(pm);
     *out = m;
     return SG_OK;
@@ -508,7 +527,9 @@ int sg_mesh_update_vertices(sg_mesh mesh, const float* X_host, int64_t n_verts) 
     if (e == hipSuccess) e = hipMemcpy(mesh->d_face, pm.face.data(), pm.face.size() * sizeof(FaceRec), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(mesh->d_half, pm.half.data(), pm.half.size() * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(mesh->d_X, X_host, (size_t)n_verts * 3 * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(mesh->d_geo, pm.geo.data(), pm.geo.size() * sizeof(float), hipMemcpyHostToDevice);
     pm.X.clear();
+    pm.geo.clear();
     if (e != hipSuccess) return hip_fail(e, "vertex update");
     mesh->mean_edge = pm.mean_edge;
     return SG_OK;

@@ -121,6 +121,14 @@ SG_HD __forceinline__ float rcp(float x) {
 
 SG_HD __forceinline__ float3 ld3(const float* p) { return make_float3(p[0], p[1], p[2]); }
 SG_HD __forceinline__ float3 sub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+// Position of vertex k (0..2, face order) of internal face f: one 64-byte
+// record per face holds the three positions (w: the global vertex id) and the
+// user face id, so an epilogue or a start frame takes one line, not four.
+SG_HD __forceinline__ float3 fvx(const DevMesh& M, int64_t f, int k) {
+    const float4 q = M.geo[4 * f + k];
+    return make_float3(q.x, q.y, q.z);
+}
+SG_HD __forceinline__ int32_t face_user(const DevMesh& M, int64_t f) { return __builtin_bit_cast(int32_t, M.geo[4 * f + 3].x); }
 SG_HD __forceinline__ float dot(float3 a, float3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
 SG_HD __forceinline__ float3 crs(float3 a, float3 b) {
     return make_float3(fmaf(a.y, b.z, -a.z * b.y), fmaf(a.z, b.x, -a.x * b.z), fmaf(a.x, b.y, -a.y * b.x));
@@ -231,9 +239,9 @@ SG_HD __forceinline__ int start_frame(const DevMesh& M, int32_t fu, const float*
     if (!(bs > 0.f) || !__builtin_isfinite(bs)) return kInitBad;
     S.b0 = b0 / bs; S.b1 = b1 / bs; S.b2 = b2 / bs;
     const int64_t f3 = 3 * (int64_t)S.f;
-    S.x0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
-    const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
-    const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+    S.x0 = fvx(M, f3 / 3, 0);
+    const float3 x1 = fvx(M, f3 / 3, 1);
+    const float3 x2 = fvx(M, f3 / 3, 2);
     const float3 e1 = sub(x1, S.x0), e2 = sub(x2, S.x0);
     S.l0 = sqrtf(dot(e1, e1));
     S.n = nrm(crs(e1, e2));
@@ -343,9 +351,8 @@ SG_HD __forceinline__ ff ff_atan2(ff y, ff x) {
 SG_HD __forceinline__ void start_direction(const DevMesh& M, int32_t f, float3 vf, float& Lhi, float& Llo,
                                            uint32_t& phi0) {
     const int64_t f3 = 3 * (int64_t)f;
-    const float* p0 = M.X + 3 * (int64_t)M.F[f3];
-    const float* p1 = M.X + 3 * (int64_t)M.F[f3 + 1];
-    const float* p2 = M.X + 3 * (int64_t)M.F[f3 + 2];
+    const float3 q0 = fvx(M, f3 / 3, 0), q1 = fvx(M, f3 / 3, 1), q2 = fvx(M, f3 / 3, 2);
+    const float p0[3] = {q0.x, q0.y, q0.z}, p1[3] = {q1.x, q1.y, q1.z}, p2[3] = {q2.x, q2.y, q2.z};
     const float v[3] = {vf.x, vf.y, vf.z};
     ff e1[3], e2[3];
     for (int c = 0; c < 3; ++c) {
@@ -531,9 +538,9 @@ SG_HD __forceinline__ void set_final(Final& fin, const Ray& st, float ex, float 
 SG_HD __forceinline__ void chart_frame3(const DevMesh& M, int32_t h, float3& xa, float3& eu, float3& ev, float3& n) {
     const int32_t f = h / 3, k = h - 3 * (h / 3);
     const int64_t f3 = 3 * (int64_t)f;
-    xa = ld3(M.X + 3 * (int64_t)M.F[f3 + k]);
-    const float3 xb = ld3(M.X + 3 * (int64_t)M.F[f3 + (k + 1) % 3]);
-    const float3 xc = ld3(M.X + 3 * (int64_t)M.F[f3 + (k + 2) % 3]);
+    xa = fvx(M, f3 / 3, k);
+    const float3 xb = fvx(M, f3 / 3, (k + 1) % 3);
+    const float3 xc = fvx(M, f3 / 3, (k + 2) % 3);
     const float3 ab = sub(xb, xa);
     eu = nrm(ab);
     n = nrm(crs(ab, sub(xc, xa)));
@@ -579,9 +586,9 @@ SG_HD __forceinline__ float corner_fit(const DevMesh& M, int32_t hv, int roleA, 
     const int32_t f = hv / 3, k = hv - 3 * (hv / 3);
     const int64_t f3 = 3 * (int64_t)f;
     const int k0 = roleA ? k : (k + 1) % 3;   // x0's local index
-    const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[f3 + k0]);
-    const float3 ea = sub(ld3(M.X + 3 * (int64_t)M.F[f3 + (k0 + 1) % 3]), x0);
-    const float3 eb = sub(ld3(M.X + 3 * (int64_t)M.F[f3 + (k0 + 2) % 3]), x0);
+    const float3 x0 = fvx(M, f3 / 3, k0);
+    const float3 ea = sub(fvx(M, f3 / 3, (k0 + 1) % 3), x0);
+    const float3 eb = sub(fvx(M, f3 / 3, (k0 + 2) % 3), x0);
     const float3 n = nrm(crs(ea, eb));   // here (ea x eb) . n > 0
     const float dn = dot(d, n);
     w = sub(d, scl(n, dn));
@@ -877,9 +884,9 @@ SG_HD void write_unwalked(const DevMesh& M, const ExpArgs& a, int64_t i, bool ba
         const float s = bo[0] + bo[1] + bo[2];
         bo[0] /= s; bo[1] /= s; bo[2] /= s;
         const int64_t f3 = 3 * (int64_t)M.perm[f0];
-        const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
-        const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
-        const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+        const float3 x0 = fvx(M, f3 / 3, 0);
+        const float3 x1 = fvx(M, f3 / 3, 1);
+        const float3 x2 = fvx(M, f3 / 3, 2);
         p = make_float3(bo[0] * x0.x + bo[1] * x1.x + bo[2] * x2.x, bo[0] * x0.y + bo[1] * x1.y + bo[2] * x2.y,
                         bo[0] * x0.z + bo[1] * x1.z + bo[2] * x2.z);
         n = nrm(crs(sub(x1, x0), sub(x2, x0)));
@@ -902,9 +909,9 @@ SG_HD void write_unwalked(const DevMesh& M, const ExpArgs& a, int64_t i, bool ba
 // Unit tangent d0 of ray i's projected v on its start face and n0 x d0.
 SG_HD __forceinline__ void start_tangent_frame(const DevMesh& M, const ExpArgs& a, int64_t i, float3& d0, float3& q0) {
     const int64_t g3 = 3 * (int64_t)M.perm[a.f[i]];
-    const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[g3]);
-    const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[g3 + 1]);
-    const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[g3 + 2]);
+    const float3 x0 = fvx(M, g3 / 3, 0);
+    const float3 x1 = fvx(M, g3 / 3, 1);
+    const float3 x2 = fvx(M, g3 / 3, 2);
     const float3 n0 = nrm(crs(sub(x1, x0), sub(x2, x0)));
     const float3 v = ld3(a.v + 3 * i);
     d0 = nrm(sub(v, scl(n0, dot(v, n0))));
@@ -919,9 +926,9 @@ SG_HD void write_final(const DevMesh& M, const ExpArgs& a, int64_t i, const Fina
     const int ke = fin.h - 3 * fe;
     const HalfEdgeRec r = rec_at(M, fin.h);
     const int64_t f3 = 3 * (int64_t)fe;
-    const float3 y0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
-    const float3 y1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
-    const float3 y2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+    const float3 y0 = fvx(M, f3 / 3, 0);
+    const float3 y1 = fvx(M, f3 / 3, 1);
+    const float3 y2 = fvx(M, f3 / 3, 2);
     const float3 ya = ke == 0 ? y0 : (ke == 1 ? y1 : y2);
     const float3 yb = ke == 0 ? y1 : (ke == 1 ? y2 : y0);
     const float3 yc = ke == 0 ? y2 : (ke == 1 ? y0 : y1);
@@ -929,7 +936,7 @@ SG_HD void write_final(const DevMesh& M, const ExpArgs& a, int64_t i, const Fina
     const float ell = sqrtf(dot(eab, eab));
     float bo[3];
     chart_bary(r, ell, fin.ex, fin.ey, ke, bo[0], bo[1], bo[2]);
-    a.f_out[i] = M.order[fe];
+    a.f_out[i] = face_user(M, fe);
     a.b_out[3 * i] = bo[0]; a.b_out[3 * i + 1] = bo[1]; a.b_out[3 * i + 2] = bo[2];
     a.p_out[3 * i] = fmaf(bo[0], y0.x, fmaf(bo[1], y1.x, bo[2] * y2.x));
     a.p_out[3 * i + 1] = fmaf(bo[0], y0.y, fmaf(bo[1], y1.y, bo[2] * y2.y));
@@ -972,9 +979,9 @@ SG_HD void write_final(const DevMesh& M, const ExpArgs& a, int64_t i, const Fina
 // walk state did not keep it.
 SG_HD __forceinline__ float tangent_length(const DevMesh& M, const ExpArgs& a, int64_t i) {
     const int64_t f3 = 3 * (int64_t)M.perm[a.f[i]];
-    const float3 x0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
-    const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
-    const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+    const float3 x0 = fvx(M, f3 / 3, 0);
+    const float3 x1 = fvx(M, f3 / 3, 1);
+    const float3 x2 = fvx(M, f3 / 3, 2);
     const float3 e1 = sub(x1, x0), e2 = sub(x2, x0);
     const float l0 = sqrtf(dot(e1, e1));   // same arithmetic as ray_init
     const float3 n = nrm(crs(e1, e2));
@@ -1629,9 +1636,9 @@ SG_HD __forceinline__ float3 final_offset(const DevMesh& M, const Final& fin, fl
     const int ke = fin.h - 3 * fe;
     const HalfEdgeRec r = rec_at(M, fin.h);
     const int64_t f3 = 3 * (int64_t)fe;
-    const float3 y0 = sub(ld3(M.X + 3 * (int64_t)M.F[f3]), o);
-    const float3 y1 = sub(ld3(M.X + 3 * (int64_t)M.F[f3 + 1]), o);
-    const float3 y2 = sub(ld3(M.X + 3 * (int64_t)M.F[f3 + 2]), o);
+    const float3 y0 = sub(fvx(M, f3 / 3, 0), o);
+    const float3 y1 = sub(fvx(M, f3 / 3, 1), o);
+    const float3 y2 = sub(fvx(M, f3 / 3, 2), o);
     const float ell = r.lab;
     float b0, b1, b2;
     chart_bary(r, ell, fin.ex, fin.ey, ke, b0, b1, b2);
@@ -1645,9 +1652,9 @@ SG_HD __forceinline__ void final_frame(const DevMesh& M, const Final& fin, float
     const int32_t fe = fin.h / 3;
     const int ke = fin.h - 3 * fe;
     const int64_t f3 = 3 * (int64_t)fe;
-    const float3 ya = ld3(M.X + 3 * (int64_t)M.F[f3 + ke]);
-    const float3 yb = ld3(M.X + 3 * (int64_t)M.F[f3 + (ke + 1) % 3]);
-    const float3 yc = ld3(M.X + 3 * (int64_t)M.F[f3 + (ke + 2) % 3]);
+    const float3 ya = fvx(M, f3 / 3, ke);
+    const float3 yb = fvx(M, f3 / 3, (ke + 1) % 3);
+    const float3 yc = fvx(M, f3 / 3, (ke + 2) % 3);
     const float3 eab = sub(yb, ya);
     const float3 ex3 = nrm(eab);
     n3 = nrm(crs(eab, sub(yc, ya)));
@@ -1694,9 +1701,9 @@ SG_HD __forceinline__ float3 load_g(const DevMesh& M, const BwdArgs& a, int64_t 
     float3 g = a.g ? ld3(a.g + 3 * i) : make_float3(0.f, 0.f, 0.f);
     if (a.g_bo && fe >= 0) {
         const int64_t f3 = 3 * (int64_t)fe;
-        const float3 y0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
-        const float3 y1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
-        const float3 y2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+        const float3 y0 = fvx(M, f3 / 3, 0);
+        const float3 y1 = fvx(M, f3 / 3, 1);
+        const float3 y2 = fvx(M, f3 / 3, 2);
         const float3 c = crs(sub(y1, y0), sub(y2, y0));
         const float inv = 1.0f / dot(c, c);   // n / (2A) = c / |c|^2
         const float3 gb = ld3(a.g_bo + 3 * i);
@@ -1805,9 +1812,9 @@ SG_HD __forceinline__ float2 pinv_uv(float3 eu, float3 ev, float3 w) {
 
 SG_HD __forceinline__ void face_uv(const DevMesh& M, int32_t f, float3& x0, float3& eu, float3& ev) {
     const int64_t f3 = 3 * (int64_t)f;
-    x0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
-    eu = nrm(sub(ld3(M.X + 3 * (int64_t)M.F[f3 + 1]), x0));
-    ev = nrm(sub(ld3(M.X + 3 * (int64_t)M.F[f3 + 2]), x0));
+    x0 = fvx(M, f3 / 3, 0);
+    eu = nrm(sub(fvx(M, f3 / 3, 1), x0));
+    ev = nrm(sub(fvx(M, f3 / 3, 2), x0));
 }
 
 // Assembly (eqs. jv, jp, chain): finite-difference columns, projected on the
@@ -1852,8 +1859,8 @@ SG_HD void gfd_assemble(const DevMesh& M, const BwdArgs& a, const StateRec* s1, 
     // start-point gradient G in the face plane with [e_u e_v]^T G = (d0, d1)
     const float3 su = S.ex;
     const int64_t f3 = 3 * (int64_t)S.f;
-    const float3 x1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
-    const float3 x2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+    const float3 x1 = fvx(M, f3 / 3, 1);
+    const float3 x2 = fvx(M, f3 / 3, 2);
     const float3 sv = nrm(sub(x2, S.x0));
     const float ga = dot(su, su), gb = dot(su, sv), gd = dot(sv, sv);
     const float idet = 1.0f / fmaf(ga, gd, -gb * gb);
@@ -1915,9 +1922,9 @@ SG_HD void ep_saved(const DevMesh& M, const BwdArgs& a, int64_t i) {
         return;
     }
     const int64_t f3 = 3 * (int64_t)M.perm[fo];
-    const float3 y0 = ld3(M.X + 3 * (int64_t)M.F[f3]);
-    const float3 y1 = ld3(M.X + 3 * (int64_t)M.F[f3 + 1]);
-    const float3 y2 = ld3(M.X + 3 * (int64_t)M.F[f3 + 2]);
+    const float3 y0 = fvx(M, f3 / 3, 0);
+    const float3 y1 = fvx(M, f3 / 3, 1);
+    const float3 y2 = fvx(M, f3 / 3, 2);
     ep_grad(M, a, i, S, phi0, scl(vo, 1.0f / lo), nrm(crs(sub(y1, y0), sub(y2, y0))), M.perm[fo]);
 }
 
@@ -1988,7 +1995,7 @@ SG_HD void gradx_init(const DevMesh& M, const BwdArgs& a, const StateRec* s1, in
     const float3 w = make_float3(fmaf(ln, v.x, vn * lam.x), fmaf(ln, v.y, vn * lam.y), fmaf(ln, v.z, vn * lam.z));
     const float wu = dot(w, S.ex), wm = dot(w, S.ey);
     const int64_t f3 = 3 * (int64_t)S.f;
-    const float3 e2 = sub(ld3(M.X + 3 * (int64_t)M.F[f3 + 2]), S.x0);
+    const float3 e2 = sub(fvx(M, f3 / 3, 2), S.x0);
     const float cx = dot(e2, S.ex), cy = dot(e2, S.ey);
     const float dh1 = wu / S.l0 - wm * cx / (S.l0 * cy);
     const float dh2 = wm / cy;

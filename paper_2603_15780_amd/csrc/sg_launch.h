@@ -64,6 +64,7 @@ struct PackedMesh {
     std::vector<int64_t> half;
     std::vector<int32_t> twin;        // half-edge across each edge (internal ids), -1 on the boundary
     std::vector<uint8_t> vbnd;        // vertex lies on a boundary edge
+    std::vector<float> geo;           // [n_faces, 16]: per-face vertex positions and user id (DevMesh::geo)
     int64_t n_verts = 0, n_faces = 0;
     double mean_edge = 0.0;
     int32_t has_flip = 0;
