@@ -249,9 +249,10 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
                 return fail(SG_E_DEGENERATE, "face %lld has zero area", (long long)f);
         }
         // Spatial face order: recursive coordinate bisection of the face centroids
-        // (median split along the longest box axis).  The first three levels cut
-        // the faces into 8 contiguous parts of equal count, one per XCD; deeper
-        // levels keep neighbouring faces close in memory.  Everything below works
+        // (median split along the longest box axis), within each mesh of a batch.
+        // For one mesh the first three levels cut the faces into 8 contiguous parts
+        // of equal count, one per XCD; deeper levels keep neighbouring faces close
+        // in memory.  Everything below works
         // on internal ids; perm / order map user ids to internal ids and back.
         {
             std::vector<V3> cen(n_faces);
@@ -263,7 +264,10 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
             order.resize(n_faces);
             std::iota(order.begin(), order.end(), 0);
             struct Span { int64_t lo, hi; };
-            std::vector<Span> stack{{0, n_faces}};
+            // each mesh of a batch keeps its faces contiguous (meshes of one batch may overlap in space)
+            std::vector<Span> stack;
+            for (int32_t m = n_meshes - 1; m >= 0; --m)
+                if (fo[m + 1] > fo[m]) stack.push_back({fo[m], fo[m + 1]});
             while (!stack.empty()) {
                 const Span sp = stack.back();
                 stack.pop_back();
