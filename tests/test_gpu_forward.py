@@ -475,9 +475,16 @@ def test_non_orientable_surfaces(torch, kernel):
 
 # ---------------------------------------------------------------- hole avoidance
 def _holed_meshes():
+    """A plane with a square hole, a sphere with holes, the same with 30% of its
+    faces listed in reverse order, and a Moebius strip (non-orientable, with
+    boundary): slides and resumptions must carry the orientation parity."""
     from test_oracle_holes import plane, holed_sphere
     X, F, _ = plane()
-    return [(X, F), holed_sphere()]
+    Xs, Fs = holed_sphere()
+    Fm = Fs.copy()
+    flip = np.random.default_rng(5).random(Fm.shape[0]) < 0.3
+    Fm[flip] = Fm[flip][:, ::-1]
+    return [(X, F), (Xs, Fs), (Xs, Fm), M.canonical(*M.mobius_strip(96, 12))]
 
 
 @pytest.mark.parametrize("kernel", [1, 2, 3])
