@@ -96,6 +96,9 @@ typedef struct {
                               equal share of each XCD) up to 64; <= 0: 8 */
     int32_t boundary_mode; /* SG_BOUNDARY_STOP (default) or SG_BOUNDARY_AVOID; honoured by every kernel and
                               the backward (the vertex gradient leaves out rays that slid) */
+    int32_t gradx_records; /* vertex gradient: edge crossings per query for which the workspace holds records
+                              (48 bytes each) that are summed per half-edge in LDS; crossings past them add
+                              their sums with float64 atomics (same result, slower).  0: 256; < 0: none */
     void* workspace;       /* optional caller-owned device workspace, 256-byte aligned, at least the size
                               sg_exp_workspace_size / sg_backward_workspace_size report.  With it a call
                               allocates nothing, so it can be captured in a HIP graph (debug bit 2 aside).
@@ -196,8 +199,10 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
  *        derivative of p' = H_m o ... o H_1(p + v_t), the composition of the
  *        rigid unfoldings about the crossed edges, with the combinatorics
  *        frozen.  The geodesic is re-walked twice (end frame, then the
- *        adjoint's per-edge float64 sums), then one pass maps each crossed
- *        edge's sums to its four hinge vertices with float64 atomics.  Rays
+ *        adjoint's per-edge terms, one record per crossing, summed per
+ *        half-edge in float64 after grouping by half-edge range), then one
+ *        pass maps each crossed edge's sums to its four hinge vertices with
+ *        float64 atomics.  Rays
  *        whose walk ends with a status other than SG_RAY_OK contribute
  *        nothing.  A vertex passage is not a hinge: such rays contribute their
  *        edge and start terms with the vertex rule held fixed, which is not
@@ -205,9 +210,10 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
  *        Float64 atomics make grad_X's last bits depend on timing.
  * Queries the forward rejects (SG_RAY_BADINPUT) get NaN in grad_v, grad_b.
  * Uses a stream-ordered device workspace (GFD 224 bytes per query, a re-walk
- * 32; grad_X 48 per query plus 120 per face).  opts: max_steps, vertex_snap,
- * eps_v, eps_p, refill_min, walk_blocks, ray_queues are honoured; kernel is
- * ignored (the persistent walk always runs).  n < 2^31 (SG_E_ARG otherwise).
+ * 32; grad_X 48 per query plus 120 per face plus 48 per record, see
+ * gradx_records).  opts: max_steps, vertex_snap, eps_v, eps_p, refill_min,
+ * walk_blocks, ray_queues, gradx_records are honoured; kernel is ignored (the
+ * persistent walk always runs).  n < 2^31 (SG_E_ARG otherwise).
  */
 int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b, const float* v,
                     const int32_t* f_out, const float* v_out, const float* g_p,

@@ -150,6 +150,7 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     if (o.boundary_mode != SG_BOUNDARY_STOP && o.boundary_mode != SG_BOUNDARY_AVOID)
         return fail(SG_E_ARG, "unknown boundary_mode %d", o.boundary_mode);
     if (o.ray_queues <= 0) o.ray_queues = 8;
+    if (o.gradx_records == 0) o.gradx_records = 256;
     if (o.ray_queues % 8 != 0 || o.ray_queues > sg::kMaxQueues)
         return fail(SG_E_ARG, "ray_queues must be a multiple of 8, at most %d", sg::kMaxQueues);
     // default schedule: three resident 256-lane blocks per CU, refill at 32 idle lanes (the
@@ -189,6 +190,18 @@ hipError_t give_workspace(Workspace& w, hipStream_t st) {
     hipError_t e = w.own ? hipFreeAsync(w.p, st) : hipSuccess;
     w = Workspace{};
     return e;
+}
+
+// The backward always runs the persistent walk: a partitioned choice of
+// kernel takes the persistent walk's block count.
+int check_bwd_opts(const sg_opts* in, sg_opts& o, sg_mesh m) {
+    const int rc = check_opts(in, o, m);
+    if (rc == SG_OK && o.kernel == SG_KERNEL_PARTITIONED) o.walk_blocks = m->cu_count * m->walk_blocks_per_cu;
+    return rc;
+}
+
+size_t bwd_workspace_bytes(const sg_opts& o, sg_mesh m, int64_t n, int32_t mode, bool vjp, bool gradx) {
+    return sg::bwd_workspace(n, mode, m->has_flip != 0, vjp, gradx, m->n_faces, o.gradx_records, o.walk_blocks);
 }
 
 size_t exp_workspace_bytes(const sg_opts& o, int64_t n, int32_t K) {
@@ -459,6 +472,7 @@ void sg_opts_default(sg_opts* o) {
     o->rays_per_lane = 0;
     o->ray_queues = 0;
     o->boundary_mode = SG_BOUNDARY_STOP;
+    o->gradx_records = 0;
     o->workspace = nullptr;
     o->workspace_bytes = 0;
 }
@@ -638,9 +652,8 @@ int sg_exp_backward_transport(sg_mesh mesh, int32_t mode, int64_t n, const int32
     if (g_W && K == 0) return fail(SG_E_ARG, "g_W needs K > 0");
     if ((g_v || g_W) && !grad_v) return fail(SG_E_ARG, "g_v and g_W need grad_v and grad_b");
     sg_opts o;
-    int rc = check_opts(opts, o, mesh);
+    int rc = check_bwd_opts(opts, o, mesh);
     if (rc != SG_OK) return rc;
-    if (o.kernel == SG_KERNEL_PARTITIONED) o.walk_blocks = mesh->cu_count * mesh->walk_blocks_per_cu;
     if (!(std::isfinite(o.eps_v) && std::isfinite(o.eps_p))) return fail(SG_E_ARG, "eps_v and eps_p must be finite");
     if (n == 0) return SG_OK;
     if (n >= ((int64_t)1 << 31)) return fail(SG_E_ARG, "the backward takes fewer than 2^31 queries per call");
@@ -669,8 +682,8 @@ int sg_exp_backward_transport(sg_mesh mesh, int32_t mode, int64_t n, const int32
     if (!vjp && !a.grad_X) return SG_OK;
     const hipStream_t st = (hipStream_t)stream;
     Workspace ws;
-    rc = take_workspace(o, sg::bwd_workspace(n, mode, mesh->has_flip != 0, vjp, a.grad_X != nullptr, mesh->n_faces),
-                        st, ws);
+    a.gx_records = o.gradx_records;
+    rc = take_workspace(o, bwd_workspace_bytes(o, mesh, n, mode, vjp, a.grad_X != nullptr), st, ws);
     if (rc != SG_OK) return rc;
     hipError_t e = sg::launch_backward(mesh->dev(o.boundary_mode), a, ws.p, sched(o), st);
     const hipError_t e2 = give_workspace(ws, st);
@@ -704,11 +717,11 @@ int sg_backward_workspace_size(sg_mesh mesh, int32_t mode, int64_t n, int32_t wa
     if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
     if (mode != SG_BWD_EP && mode != SG_BWD_GFD) return fail(SG_E_ARG, "unknown backward mode %d", mode);
     sg_opts o;
-    int rc = check_opts(opts, o, mesh);
+    int rc = check_bwd_opts(opts, o, mesh);
     if (rc != SG_OK) return rc;
-    *bytes = (n == 0 || (!want_vjp && !want_grad_X))
-                 ? 0
-                 : sg::bwd_workspace(n, mode, mesh->has_flip != 0, want_vjp != 0, want_grad_X != 0, mesh->n_faces);
+    *bytes = (n == 0 || (!want_vjp && !want_grad_X)) ? 0
+                                                     : bwd_workspace_bytes(o, mesh, n, mode, want_vjp != 0,
+                                                                           want_grad_X != 0);
     return SG_OK;
 }
 

@@ -1246,7 +1246,15 @@ SG_HD __forceinline__ void add_f64(double* p, double v) {
 // adds to h's sums the normal-and-apex-side components (l_m, l_n) of lambda
 // and T = r x lambda, r = (s + l cos phi, l sin phi, 0) the virtual endpoint
 // relative to the chart origin.
-SG_HD __forceinline__ void gx_cross(double* acc, const Ray& st, const float4& c) {
+// One crossing's record: the entered half-edge and its five terms
+// (l_m, l_n, T_u, T_m, T_n).
+struct alignas(8) GxRec {
+    int32_t h;
+    float q[5];
+};
+static_assert(sizeof(GxRec) == 24, "grad-X record is 24 bytes");
+
+SG_HD __forceinline__ GxRec gx_terms(const Ray& st, const float4& c) {
     float sn, cs;
     sincos_fx(st.phi, sn, cs);
     const float sg = (st.par & kParity) ? -1.f : 1.f;
@@ -1255,13 +1263,45 @@ SG_HD __forceinline__ void gx_cross(double* acc, const Ray& st, const float4& c)
     const float ln = sg * c.z;
     const float Lr = st.Lhi + st.Llo;
     const float ru = fmaf(Lr, cs, st.s), rm = Lr * sn;
-    double* q = acc + 5 * (int64_t)st.h;
-    add_f64(q, (double)lm);
-    add_f64(q + 1, (double)ln);
-    add_f64(q + 2, (double)(rm * ln));
-    add_f64(q + 3, (double)(-ru * ln));
-    add_f64(q + 4, (double)fmaf(ru, lm, -rm * lu));
+    GxRec r;
+    r.h = st.h;
+    r.q[0] = lm;
+    r.q[1] = ln;
+    r.q[2] = rm * ln;
+    r.q[3] = -ru * ln;
+    r.q[4] = fmaf(ru, lm, -rm * lu);
+    return r;
 }
+
+SG_HD __forceinline__ void gx_cross(double* acc, const Ray& st, const float4& c) {
+    const GxRec r = gx_terms(st, c);
+    double* q = acc + 5 * (int64_t)r.h;
+    for (int k = 0; k < 5; ++k) add_f64(q + k, (double)r.q[k]);
+}
+
+// Binned accumulation of the crossing terms.  Float64 atomics on the
+// half-edge sums run at the memory-side atomic rate, five per crossing, so
+// instead the walk appends each crossing's record to a chunk of a record
+// buffer and counts the records per bin of 2^shift consecutive half-edges in
+// LDS.  Every walk block owns a fixed range of chunks; its waves claim them
+// with an LDS atomic and fill them with coalesced stores.  At its end the
+// block writes its bin counts as one row of a (block, bin) matrix.  A column
+// scan of that matrix gives each (block, bin) pair its place in bin order, so
+// the scatter pass (one block per walk block) moves the records there with
+// LDS cursors only, and a reduce pass sums each bin in LDS (float64) and adds
+// the bin's totals to the half-edge sums once.  Crossings past a block's
+// chunks fall back to the atomics.
+constexpr int kGxChunk = 1024;            // records per chunk
+constexpr int kGxMaxBins = 4096;          // bins (LDS counters of the walk and of the scatter)
+constexpr int kGxWindow = 1024;           // half-edges summed in LDS at once by the reduce pass
+constexpr int64_t kGxMaxRecords = (int64_t)1 << 31;   // bin starts are 32-bit
+
+struct GxSink {
+    GxRec* rec;       // record buffer, gridDim.x * per_block chunks of kGxChunk records; null: atomics only
+    uint32_t* fill;   // records written into each claimed chunk
+    int per_block;    // chunks owned by each walk block
+    int shift;        // a bin is 2^shift consecutive half-edges
+};
 
 // Ray queues of the persistent walk.  The walk slots are in the order of
 // ray_bucket, whose nq queue ranges are spatial regions (nq / 8 per XCD):
@@ -1326,9 +1366,13 @@ __device__ __forceinline__ int64_t queue_claim(unsigned long long* ctr, const Qu
 template <bool kHash, bool kFlip, bool kHole, bool kGX>
 __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, QueueRanges R, unsigned long long* counter,
                                           int32_t max_steps, float snap, int refill_min, int nq, const float4* cvec,
-                                          double* acc) {
+                                          double* acc, const GxSink& sink, uint32_t* lbins) {
     const int lane = (int)(threadIdx.x & 63u);
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    // record chunk of this wave (wave-uniform): index, records written, or spilling to atomics
+    int64_t chunk = -1;
+    int used = kGxChunk;
+    bool spill = sink.rec == nullptr;
     bool active = false;
     QueueCursor qc = queue_start(nq);
     int64_t q = 0;
@@ -1358,18 +1402,49 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, Qu
         // walk until enough lanes are idle to refill (all of them once the queues are empty)
         const int stop_at = qc.left == 0 ? 64 : refill_min;
         for (;;) {
+            bool cross = false;
             if (active) {
                 Final fin;
                 if (walk_step<kHash, kFlip, kHole>(M, st, max_steps, snap, fin) == kStepDone) {
                     *reinterpret_cast<Final*>(&states[q]) = fin;
                     active = false;
                 } else if (kGX && st.bias == 0.f) {   // an edge crossing (a vertex passage leaves a bias)
-                    gx_cross(acc, st, c);
+                    cross = true;
+                }
+            }
+            if constexpr (kGX) {
+                const uint64_t m = __ballot(cross);
+                if (m) {
+                    const int cw = __popcll(m);
+                    if (!spill && used + cw > kGxChunk) {   // close this chunk, claim the block's next
+                        if (chunk >= 0 && lane == 0) sink.fill[chunk] = (uint32_t)used;
+                        uint32_t b = 0u;
+                        if (lane == 0) b = atomicAdd(&lbins[kGxMaxBins], 1u);
+                        b = (uint32_t)__shfl((int)b, 0);
+                        if (b < (uint32_t)sink.per_block) {
+                            chunk = (int64_t)blockIdx.x * sink.per_block + b;
+                            used = 0;
+                        } else {
+                            chunk = -1;
+                            spill = true;
+                        }
+                    }
+                    if (cross) {
+                        if (!spill) {
+                            const GxRec r = gx_terms(st, c);
+                            sink.rec[chunk * kGxChunk + used + __popcll(m & below)] = r;
+                            atomicAdd(&lbins[r.h >> sink.shift], 1u);
+                        } else {
+                            gx_cross(acc, st, c);
+                        }
+                    }
+                    if (!spill) used += cw;
                 }
             }
             if (__popcll(__ballot(!active)) >= stop_at) break;
         }
     }
+    if (kGX && chunk >= 0 && lane == 0) sink.fill[chunk] = (uint32_t)used;
 }
 
 // Two rays per lane: both slots are stepped every iteration, branch-free, so
@@ -1446,7 +1521,8 @@ __global__ __launch_bounds__(256) void k_walk2(DevMesh M, StateRec* states, Queu
 template <bool kHash, bool kFlip, bool kHole>
 __global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, QueueRanges R, unsigned long long* counter,
                                               int32_t max_steps, float snap, int refill_min, int nq) {
-    walk_loop<kHash, kFlip, kHole, false>(M, states, R, counter, max_steps, snap, refill_min, nq, nullptr, nullptr);
+    walk_loop<kHash, kFlip, kHole, false>(M, states, R, counter, max_steps, snap, refill_min, nq, nullptr, nullptr,
+                                          GxSink{}, nullptr);
 }
 
 // The same walk over the backward's stacked chart states (its own symbol, so
@@ -1455,14 +1531,180 @@ template <bool kHash, bool kFlip, bool kHole>
 __global__ __launch_bounds__(256) void k_walk_bwd(DevMesh M, StateRec* states, QueueRanges R,
                                                   unsigned long long* counter, int32_t max_steps, float snap,
                                                   int refill_min, int nq) {
-    walk_loop<false, kFlip, kHole, false>(M, states, R, counter, max_steps, snap, refill_min, nq, nullptr, nullptr);
+    walk_loop<false, kFlip, kHole, false>(M, states, R, counter, max_steps, snap, refill_min, nq, nullptr, nullptr,
+                                          GxSink{}, nullptr);
 }
 
 template <bool kFlip, bool kHole>
 __global__ __launch_bounds__(256) void k_walk_gx(DevMesh M, StateRec* states, QueueRanges R, unsigned long long* counter,
                                                  int32_t max_steps, float snap, int refill_min, int nq,
-                                                 const float4* cvec, double* acc) {
-    walk_loop<false, kFlip, kHole, true>(M, states, R, counter, max_steps, snap, refill_min, nq, cvec, acc);
+                                                 const float4* cvec, double* acc, GxSink sink, uint32_t* counts,
+                                                 uint32_t* used, int nbins) {
+    __shared__ uint32_t lbins[kGxMaxBins + 1];   // bin counts, then the block's chunk counter
+    for (int b = (int)threadIdx.x; b < nbins; b += 256) lbins[b] = 0u;
+    if (threadIdx.x == 0) lbins[kGxMaxBins] = 0u;
+    __syncthreads();
+    walk_loop<false, kFlip, kHole, true>(M, states, R, counter, max_steps, snap, refill_min, nq, cvec, acc, sink,
+                                         lbins);
+    __syncthreads();
+    if (sink.rec == nullptr) return;
+    uint32_t* row = counts + (size_t)blockIdx.x * nbins;
+    for (int b = (int)threadIdx.x; b < nbins; b += 256) row[b] = lbins[b];
+    if (threadIdx.x == 0) used[blockIdx.x] = min(lbins[kGxMaxBins], (uint32_t)sink.per_block);
+}
+
+// Column b of the (walk block, bin) count matrix to exclusive prefix sums
+// over the blocks (in place), and the column total to total[b].
+__global__ __launch_bounds__(1024) void k_gx_colscan(uint32_t* counts, int rows, int nbins, uint32_t* total) {
+    __shared__ uint32_t part[1024];
+    const int b = (int)blockIdx.x, t = (int)threadIdx.x;
+    const int per = (rows + 1023) / 1024;
+    const int r0 = min(rows, t * per), r1 = min(rows, r0 + per);
+    uint32_t sum = 0u;
+    for (int r = r0; r < r1; ++r) sum += counts[(size_t)r * nbins + b];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t x = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (int r = r0; r < r1; ++r) {
+        const uint32_t c = counts[(size_t)r * nbins + b];
+        counts[(size_t)r * nbins + b] = run;
+        run += c;
+    }
+    if (t == 1023) total[b] = part[1023];
+    if (b == 0 && t == 0) total[nbins] = 0u;
+}
+
+// Moves walk block B's records to bin order: bin b's records of block B go
+// to start[b] + (records of bin b in blocks before B) onward.  The block
+// takes its records in tiles of four chunks, sorts each tile by bin in LDS
+// (counting sort), and writes it out so that neighbouring lanes store
+// neighbouring records of one bin: whole runs instead of 24-byte pieces.
+constexpr int kGxTile = 4 * kGxChunk;
+
+// Exclusive prefix sums of x[0, n) in place (n <= 4 * 1024, 1024 threads),
+// visible to the whole block on return; returns the total to every thread.
+__device__ __forceinline__ uint32_t block_scan4096(uint32_t* x, int n, uint32_t* wsum) {
+    const int t = (int)threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint32_t v[4], sum = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = 4 * t + k < n ? x[4 * t + k] : 0u;
+        sum += v[k];
+    }
+    uint32_t inc = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)inc, off);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    uint32_t base = 0u, total = 0u;
+    for (int k = 0; k < 16; ++k) {
+        const uint32_t w = wsum[k];
+        base += k < wv ? w : 0u;
+        total += w;
+    }
+    uint32_t run = base + inc - sum;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (4 * t + k < n) {
+            x[4 * t + k] = run;
+            run += v[k];
+        }
+    __syncthreads();
+    return total;
+}
+
+__global__ __launch_bounds__(1024) void k_gx_scatter(const GxRec* rec, const uint32_t* fill, const uint32_t* used,
+                                                     int per_block, int shift, int nbins, const uint32_t* start,
+                                                     const uint32_t* counts, GxRec* sorted) {
+    __shared__ GxRec tile[kGxTile];
+    __shared__ uint32_t cur[kGxMaxBins];    // next global place of each bin
+    __shared__ uint32_t loff[kGxMaxBins];   // the tile's counts, then their exclusive sums
+    __shared__ uint32_t wsum[16];
+    const int t = (int)threadIdx.x;
+    const uint32_t* row = counts + (size_t)blockIdx.x * nbins;
+    for (int b = t; b < nbins; b += 1024) {
+        cur[b] = start[b] + row[b];
+        loff[b] = 0u;
+    }
+    __syncthreads();
+    const int64_t c0 = (int64_t)blockIdx.x * per_block, c1 = c0 + used[blockIdx.x];
+    for (int64_t c = c0; c < c1; c += 4) {
+        GxRec r[4];
+        uint32_t rk[4];
+        bool ok[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            ok[j] = c + j < c1 && t < (int)fill[c + j];
+            if (ok[j]) {
+                r[j] = rec[(c + j) * kGxChunk + t];
+                rk[j] = atomicAdd(&loff[r[j].h >> shift], 1u);
+            }
+        }
+        __syncthreads();
+        const uint32_t nt = block_scan4096(loff, nbins, wsum);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (ok[j]) tile[loff[r[j].h >> shift] + rk[j]] = r[j];
+        __syncthreads();
+        for (uint32_t i = (uint32_t)t; i < nt; i += 1024u) {
+            const GxRec q = tile[i];
+            const int b = q.h >> shift;
+            sorted[cur[b] + (i - loff[b])] = q;
+        }
+        __syncthreads();
+        uint32_t k4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int b = t + 1024 * k;
+            k4[k] = b < nbins ? (b + 1 < nbins ? loff[b + 1] : nt) - loff[b] : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int b = t + 1024 * k;
+            if (b < nbins) {
+                cur[b] += k4[k];
+                loff[b] = 0u;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Sums the records of one bin (one window of kGxWindow half-edges of it per
+// block) in LDS in float64 and adds the totals to the half-edge sums.  Every
+// bin has one owner here, so the adds need no atomics.
+__global__ __launch_bounds__(256) void k_gx_reduce(const GxRec* sorted, const uint32_t* start, int shift, int64_t nh,
+                                                   double* acc) {
+    __shared__ double s[5 * kGxWindow];
+    const int wpb = (1 << shift) / kGxWindow;
+    const int bin = (int)blockIdx.x / wpb, win = (int)blockIdx.x - bin * wpb;
+    const int64_t h0 = ((int64_t)bin << shift) + (int64_t)win * kGxWindow;
+    if (h0 >= nh) return;
+    const int t = (int)threadIdx.x;
+    for (int k = t; k < 5 * kGxWindow; k += 256) s[k] = 0.0;
+    __syncthreads();
+    const uint32_t lo = start[bin], hi = start[bin + 1];
+    for (uint32_t i = lo + (uint32_t)t; i < hi; i += 256u) {
+        const GxRec r = sorted[i];
+        const int64_t d = (int64_t)r.h - h0;
+        if (d >= 0 && d < kGxWindow)
+            for (int k = 0; k < 5; ++k) atomicAdd(&s[5 * d + k], (double)r.q[k]);
+    }
+    __syncthreads();
+    const int64_t n5 = min((int64_t)5 * kGxWindow, 5 * (nh - h0));
+    for (int64_t k = t; k < n5; k += 256) {
+        const double x = s[k];
+        if (x != 0.0) acc[5 * h0 + k] += x;
+    }
 }
 
 // ---------------------------------------------------------------- partitioned form
@@ -2265,14 +2507,21 @@ hipError_t launch_exp_partitioned(const DevMesh& M, const ExpArgs& a, void* ws, 
 
 // Backward workspace, carved in this order (each part 256-byte aligned):
 // base-walk states (1 or 4 per query), GFD second-pass states (3 per query),
-// grad-X walk states and adjoint coefficients, grad-X half-edge sums, counter.
+// grad-X walk states and adjoint coefficients, grad-X half-edge sums, walk
+// slots and bucket counts, queue counters, then the grad-X records (walk
+// order and bin order), the chunk fills and the bin words (nbins + 1 bin
+// totals scanned into starts, chunks used per walk block, the (walk block,
+// bin) count matrix).
 struct BwdLayout {
-    size_t s1, s2, s3, cvec, acc, slot, cnt, counter, total;
+    size_t s1, s2, s3, cvec, acc, slot, cnt, counter, rec, sorted, fill, bins, total;
+    int per_block;   // record chunks per walk block (0: no records)
+    int shift, nbins;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static BwdLayout bwd_layout(int64_t n, int32_t mode, bool has_flip, bool vjp, bool gradx, int64_t n_faces) {
+static BwdLayout bwd_layout(int64_t n, int32_t mode, bool has_flip, bool vjp, bool gradx, int64_t n_faces,
+                            int32_t gx_records, int walk_blocks) {
     const bool gfd = vjp && mode == 1;
     const bool walk = gradx || gfd || (vjp && has_flip);
     const size_t per1 = gfd ? 4 : 1;
@@ -2286,12 +2535,31 @@ static BwdLayout bwd_layout(int64_t n, int32_t mode, bool has_flip, bool vjp, bo
     L.slot = o; o = align256(o + (walk ? (size_t)n * sizeof(int32_t) : 0));
     L.cnt = o; o = align256(o + (walk ? (size_t)(kMaxBuckets + 2) * sizeof(uint32_t) : 0));
     L.counter = o; o = align256(o + kQueueBytes);
+    const int64_t nh = 3 * n_faces;
+    L.shift = 10;
+    while (((nh + ((int64_t)1 << L.shift) - 1) >> L.shift) > kGxMaxBins) ++L.shift;
+    const int64_t nblk = std::max(walk_blocks, 1);
+    if (gradx && gx_records > 0 && nh > 0) {
+        // about gx_records per query, shared evenly by the walk blocks (the
+        // persistent walk balances crossings across them), plus one partly
+        // filled chunk per wave
+        const int64_t want = ((int64_t)n * gx_records + kGxChunk - 1) / kGxChunk;
+        L.per_block = (int)std::min<int64_t>((want + nblk - 1) / nblk + 4, kGxMaxRecords / kGxChunk / nblk);
+        L.nbins = (int)((nh + ((int64_t)1 << L.shift) - 1) >> L.shift);
+    }
+    const int64_t nchunks = L.per_block * nblk;
+    const size_t recs = (size_t)nchunks * kGxChunk;
+    L.rec = o; o = align256(o + recs * sizeof(GxRec));
+    L.sorted = o; o = align256(o + recs * sizeof(GxRec));
+    L.fill = o; o = align256(o + (size_t)nchunks * sizeof(uint32_t));
+    L.bins = o; o = align256(o + (nchunks ? (size_t)(L.nbins + 1 + nblk + nblk * L.nbins) * sizeof(uint32_t) : 0));
     L.total = (walk || gradx) ? o : 0;
     return L;
 }
 
-size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip, bool vjp, bool gradx, int64_t n_faces) {
-    return bwd_layout(n, mode, has_flip, vjp, gradx, n_faces).total;
+size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip, bool vjp, bool gradx, int64_t n_faces,
+                     int32_t gx_records, int walk_blocks) {
+    return bwd_layout(n, mode, has_flip, vjp, gradx, n_faces, gx_records, walk_blocks).total;
 }
 
 hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, const WalkSched& w, hipStream_t s) {
@@ -2305,7 +2573,7 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
     const bool flip = M.has_flip != 0;
     if (vjp && a.mode == 0 && !flip) hipLaunchKernelGGL(k_ep_saved, dim3((unsigned)grid), dim3(block), 0, s, M, a);
     if (!(gradx || gfd || (vjp && flip))) return hipGetLastError();
-    const BwdLayout L = bwd_layout(a.n, a.mode, flip, vjp, gradx, M.n_faces);
+    const BwdLayout L = bwd_layout(a.n, a.mode, flip, vjp, gradx, M.n_faces, a.gx_records, w.blocks);
     char* base = reinterpret_cast<char*>(ws);
     auto* s1 = reinterpret_cast<StateRec*>(base + L.s1);
     auto* s2 = reinterpret_cast<StateRec*>(base + L.s2);
@@ -2344,20 +2612,44 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
                            0, s, acc, nacc);
         hipLaunchKernelGGL(k_gradx_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1, s3, cvec);
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
+        const int64_t nh = 3 * M.n_faces;
+        GxSink sink{};
+        auto* bins = reinterpret_cast<uint32_t*>(base + L.bins);   // [bin totals / starts, used, count matrix]
+        uint32_t* used = bins + L.nbins + 1;
+        uint32_t* counts = used + w.blocks;
+        if (L.per_block > 0) {
+            sink.rec = reinterpret_cast<GxRec*>(base + L.rec);
+            sink.fill = reinterpret_cast<uint32_t*>(base + L.fill);
+            sink.per_block = L.per_block;
+            sink.shift = L.shift;
+        }
         const QueueRanges R3{cnt, stride, 1};
         const dim3 gw((unsigned)w.blocks), bw(block);
         if (flip) {
             if (M.hole_avoid) k_walk_gx<true, true><<<gw, bw, 0, s>>>(M, s3, R3, counter, a.max_steps, a.snap,
-                                                                       w.refill_min, w.queues, cvec, acc);
+                                                                       w.refill_min, w.queues, cvec, acc, sink,
+                                                                       counts, used, L.nbins);
             else k_walk_gx<true, false><<<gw, bw, 0, s>>>(M, s3, R3, counter, a.max_steps, a.snap, w.refill_min,
-                                                            w.queues, cvec, acc);
+                                                            w.queues, cvec, acc, sink, counts, used, L.nbins);
         } else {
             if (M.hole_avoid) k_walk_gx<false, true><<<gw, bw, 0, s>>>(M, s3, R3, counter, a.max_steps, a.snap,
-                                                                        w.refill_min, w.queues, cvec, acc);
+                                                                        w.refill_min, w.queues, cvec, acc, sink,
+                                                                        counts, used, L.nbins);
             else k_walk_gx<false, false><<<gw, bw, 0, s>>>(M, s3, R3, counter, a.max_steps, a.snap, w.refill_min,
-                                                             w.queues, cvec, acc);
+                                                             w.queues, cvec, acc, sink, counts, used, L.nbins);
         }
-        const int64_t nh = 3 * M.n_faces;
+        if (L.per_block > 0) {
+            hipLaunchKernelGGL(k_gx_colscan, dim3((unsigned)L.nbins), dim3(1024), 0, s, counts, w.blocks, L.nbins,
+                               bins);
+            hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, bins, L.nbins + 1);
+            hipLaunchKernelGGL(k_gx_scatter, dim3((unsigned)w.blocks), dim3(1024), 0, s, (const GxRec*)sink.rec,
+                               (const uint32_t*)sink.fill, (const uint32_t*)used, L.per_block, L.shift, L.nbins,
+                               (const uint32_t*)bins, (const uint32_t*)counts,
+                               reinterpret_cast<GxRec*>(base + L.sorted));
+            const int wpb = (1 << L.shift) / kGxWindow;
+            hipLaunchKernelGGL(k_gx_reduce, dim3((unsigned)(L.nbins * wpb)), dim3(256), 0, s,
+                               (const GxRec*)(base + L.sorted), (const uint32_t*)bins, L.shift, nh, acc);
+        }
         hipLaunchKernelGGL(k_gradx_edges, dim3((unsigned)((nh + block - 1) / block)), dim3(block), 0, s, M, acc,
                            a.grad_X);
     }

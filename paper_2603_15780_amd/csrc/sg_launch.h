@@ -51,6 +51,7 @@ struct BwdArgs {
     float snap;
     double* grad_X;         // [n_verts, 3] accumulated vertex-position gradient, or null
     const int32_t* slot;    // position of each query in the walk arrays (set by the launcher), or null
+    int32_t gx_records;     // grad-X records reserved per query for binned accumulation (<= 0: atomics only)
 };
 
 // Host-side result of packing a mesh (float64 work, rounded once).
@@ -99,7 +100,8 @@ int walk_blocks_per_cu();
 int part_blocks_per_cu();
 
 // Backward of the exponential map (extrinsic proxy or geodesic finite differences).
-size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip, bool vjp, bool gradx, int64_t n_faces);
+size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip, bool vjp, bool gradx, int64_t n_faces,
+                     int32_t gx_records, int walk_blocks);
 hipError_t launch_backward(const DevMesh& M, const BwdArgs& a, void* ws, const WalkSched& w, hipStream_t s);
 
 // Partitioned forward: the walk runs on the XCD whose L2 holds the ray's

@@ -33,7 +33,7 @@ class Opts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("vertex_snap", C.c_float), ("eps_v", C.c_float),
                 ("eps_p", C.c_float), ("kernel", C.c_int32), ("debug", C.c_uint32),
                 ("refill_min", C.c_int32), ("walk_blocks", C.c_int32), ("rays_per_lane", C.c_int32),
-                ("ray_queues", C.c_int32), ("boundary_mode", C.c_int32),
+                ("ray_queues", C.c_int32), ("boundary_mode", C.c_int32), ("gradx_records", C.c_int32),
                 ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_uint64)]
 

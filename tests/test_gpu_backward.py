@@ -284,6 +284,62 @@ def test_gradx_zero_length_and_torus(torch):
     assert s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, s
 
 
+def test_gradx_records_spill_and_atomics_agree(torch):
+    """The per-half-edge sums come out the same whether the crossings go through
+    the binned records (default), partly spill to float64 atomics (a record
+    budget far below the crossings, few walking waves) or all use atomics."""
+    from paper_2603_15780_amd import sg
+    from parity import gradx_report
+    X, F = CF.mesh_config(1)
+    r = CF.rays_config(1, X, F)
+    g = CF.upstream_grad(1, r["f"].shape[0])
+    om = oracle.Mesh(X, F)
+    keep = margin_mask(om, r)
+    g[~keep] = 0.0
+    ref, _ = om.gradx(r["f"], r["b"], r["v"], g)
+    gm = sg.Mesh(X, F)
+    runs = {"records": {}, "spill": dict(gradx_records=1, walk_blocks=2), "atomics": dict(gradx_records=-1)}
+    got = {k: gpu_gradx(torch, gm, r, g, **kw)[0] for k, kw in runs.items()}
+    scale = np.abs(got["atomics"]).max()
+    for k, x in got.items():
+        s = gradx_report(ref, x)
+        print(k, s)
+        assert s["finite"] and s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, (k, s)
+        assert np.allclose(x, got["atomics"], rtol=1e-9, atol=1e-11 * scale), k
+    # sizes: records take 48 bytes each on top of the atomics-only workspace
+    n = r["f"].shape[0]
+    w_rec = gm.backward_workspace_size(sg.BWD_EP, n, want_vjp=False, want_grad_X=True)
+    w_atm = gm.backward_workspace_size(sg.BWD_EP, n, want_vjp=False, want_grad_X=True, gradx_records=-1)
+    assert w_rec - w_atm >= 48 * 256 * n
+
+
+def test_gradx_records_large_mesh(torch):
+    """A mesh of more than 4M half-edges: the record bins span 2048 half-edges
+    and the reduce pass sums each bin in two LDS windows."""
+    from paper_2603_15780_amd import sg
+    from parity import gradx_report
+    rng = np.random.default_rng(31)
+    X, F = M.flat_grid(860, 0.2, rng)
+    assert 3 * F.shape[0] > 4096 * 1024
+    X = (X - np.array([0.5, 0.5, 0.0])).astype(np.float32)
+    # rays in a patch around the origin, where float32 positions resolve the
+    # 1.2e-3 edges as finely as on the other test meshes
+    near = np.flatnonzero(np.linalg.norm(X[F].mean(1)[:, :2], axis=1) < 0.04)
+    r = random_rays(X, F, 8192, rng, uniform_len(0.0, 0.03), faces=near)
+    g = rng.standard_normal((8192, 3)).astype(np.float32)
+    om = oracle.Mesh(X, F)
+    keep = margin_mask(om, r)
+    g[~keep] = 0.0
+    ref, _ = om.gradx(r["f"], r["b"], r["v"], g)
+    gm = sg.Mesh(X, F)
+    got = gpu_gradx(torch, gm, r, g)[0]
+    atm = gpu_gradx(torch, gm, r, g, gradx_records=-1)[0]
+    assert np.allclose(got, atm, rtol=1e-9, atol=1e-11 * np.abs(atm).max())
+    s = gradx_report(ref, got)
+    print(s)
+    assert s["finite"] and s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, s
+
+
 def test_autograd_function(torch):
     """torch.autograd through exp_with_grad gives the library's gradients (and the oracle's)."""
     from paper_2603_15780_amd import sg
