@@ -1587,6 +1587,10 @@ __global__ __launch_bounds__(1024) void k_gx_colscan(uint32_t* counts, int rows,
 // neighbouring records of one bin: whole runs instead of 24-byte pieces.
 constexpr int kGxTile = 4 * kGxChunk;
 
+// Barrier for LDS traffic only: waits for this wave's LDS operations, not for
+// its outstanding global loads and stores (which __syncthreads also drains).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Exclusive prefix sums of x[0, n) in place (n <= 4 * 1024, 1024 threads),
 // visible to the whole block on return; returns the total to every thread.
 __device__ __forceinline__ uint32_t block_scan4096(uint32_t* x, int n, uint32_t* wsum) {
@@ -1603,7 +1607,7 @@ __device__ __forceinline__ uint32_t block_scan4096(uint32_t* x, int n, uint32_t*
         if (lane >= off) inc += y;
     }
     if (lane == 63) wsum[wv] = inc;
-    __syncthreads();
+    lds_barrier();
     uint32_t base = 0u, total = 0u;
     for (int k = 0; k < 16; ++k) {
         const uint32_t w = wsum[k];
@@ -1617,14 +1621,15 @@ __device__ __forceinline__ uint32_t block_scan4096(uint32_t* x, int n, uint32_t*
             x[4 * t + k] = run;
             run += v[k];
         }
-    __syncthreads();
+    lds_barrier();
     return total;
 }
 
-__global__ __launch_bounds__(1024) void k_gx_scatter(const GxRec* rec, const uint32_t* fill, const uint32_t* used,
-                                                     int per_block, int shift, int nbins, const uint32_t* start,
-                                                     const uint32_t* counts, GxRec* sorted) {
-    __shared__ GxRec tile[kGxTile];
+__global__ __launch_bounds__(1024) void k_gx_scatter(const GxRec* __restrict__ rec, const uint32_t* __restrict__ fill,
+                                                     const uint32_t* __restrict__ used, int per_block, int shift,
+                                                     int nbins, const uint32_t* __restrict__ start,
+                                                     const uint32_t* __restrict__ counts, GxRec* __restrict__ sorted) {
+    __shared__ uint2 tile[3 * kGxTile];     // records as three 8-byte words
     __shared__ uint32_t cur[kGxMaxBins];    // next global place of each bin
     __shared__ uint32_t loff[kGxMaxBins];   // the tile's counts, then their exclusive sums
     __shared__ uint32_t wsum[16];
@@ -1636,37 +1641,69 @@ __global__ __launch_bounds__(1024) void k_gx_scatter(const GxRec* rec, const uin
     }
     __syncthreads();
     const int64_t c0 = (int64_t)blockIdx.x * per_block, c1 = c0 + used[blockIdx.x];
+    const uint2* src = reinterpret_cast<const uint2*>(rec);
+    uint2* dst = reinterpret_cast<uint2*>(sorted);
+    // the next tile's records are loaded while this one is sorted and written
+    // (lanes past a chunk's fill load the block's first record and drop it)
+    uint2 n0[4], n1[4], n2[4];
+    bool okn[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        okn[j] = c0 + j < c1 && t < (int)fill[c0 + j];
+        const int64_t at = 3 * (okn[j] ? (c0 + j) * kGxChunk + t : c0 * kGxChunk);
+        n0[j] = src[at];
+        n1[j] = src[at + 1];
+        n2[j] = src[at + 2];
+    }
     for (int64_t c = c0; c < c1; c += 4) {
-        GxRec r[4];
-        uint32_t rk[4];
+        uint2 r0[4], r1[4], r2[4];
         bool ok[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            ok[j] = c + j < c1 && t < (int)fill[c + j];
-            if (ok[j]) {
-                r[j] = rec[(c + j) * kGxChunk + t];
-                rk[j] = atomicAdd(&loff[r[j].h >> shift], 1u);
-            }
+            r0[j] = n0[j];
+            r1[j] = n1[j];
+            r2[j] = n2[j];
+            ok[j] = okn[j];
         }
-        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            okn[j] = c + 4 + j < c1 && t < (int)fill[c + 4 + j];
+            const int64_t at = 3 * (okn[j] ? (c + 4 + j) * kGxChunk + t : c0 * kGxChunk);
+            n0[j] = src[at];
+            n1[j] = src[at + 1];
+            n2[j] = src[at + 2];
+        }
+        uint32_t rk[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (ok[j]) rk[j] = atomicAdd(&loff[(int)r0[j].x >> shift], 1u);
+        lds_barrier();
         const uint32_t nt = block_scan4096(loff, nbins, wsum);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            if (ok[j]) tile[loff[r[j].h >> shift] + rk[j]] = r[j];
-        __syncthreads();
+            if (ok[j]) {
+                const uint32_t k = 3 * (loff[(int)r0[j].x >> shift] + rk[j]);
+                tile[k] = r0[j];
+                tile[k + 1] = r1[j];
+                tile[k + 2] = r2[j];
+            }
+        lds_barrier();
         for (uint32_t i = (uint32_t)t; i < nt; i += 1024u) {
-            const GxRec q = tile[i];
-            const int b = q.h >> shift;
-            sorted[cur[b] + (i - loff[b])] = q;
+            const uint2 q0 = tile[3 * i], q1 = tile[3 * i + 1], q2 = tile[3 * i + 2];
+            const int b = (int)q0.x >> shift;
+            const size_t at = 3 * (size_t)(cur[b] + (i - loff[b]));
+            dst[at] = q0;
+            dst[at + 1] = q1;
+            dst[at + 2] = q2;
         }
-        __syncthreads();
+        lds_barrier();
         uint32_t k4[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int b = t + 1024 * k;
             k4[k] = b < nbins ? (b + 1 < nbins ? loff[b + 1] : nt) - loff[b] : 0u;
         }
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int b = t + 1024 * k;
@@ -1675,7 +1712,7 @@ __global__ __launch_bounds__(1024) void k_gx_scatter(const GxRec* rec, const uin
                 loff[b] = 0u;
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
