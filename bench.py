@@ -187,7 +187,8 @@ def main():
         bo = sg.opts(refill_min=base.refill_min if persistent else 0, walk_blocks=base.walk_blocks if persistent else 0)
         forms = (("ep", sg.BWD_EP, False), ("gfd", sg.BWD_GFD, False), ("ep+gradX", sg.BWD_EP, True),
                  ("gfd+gradX", sg.BWD_GFD, True))
-        if args.config == 5:   # the float64 vertex gradient takes seconds per call at this size
+        if args.config == 5:   # 1.1e10 crossings: most would pass the 2^30 vertex-gradient records and
+            # take the float64 atomics (seconds per call)
             forms = forms[:2]
         for name, mode, with_x in forms:
             steps = max(3, args.steps // 2)

@@ -97,8 +97,9 @@ typedef struct {
     int32_t boundary_mode; /* SG_BOUNDARY_STOP (default) or SG_BOUNDARY_AVOID; honoured by every kernel and
                               the backward (the vertex gradient leaves out rays that slid) */
     int32_t gradx_records; /* vertex gradient: edge crossings per query for which the workspace holds records
-                              (48 bytes each) that are summed per half-edge in LDS; crossings past them add
-                              their sums with float64 atomics (same result, slower).  0: 256; < 0: none */
+                              (48 bytes each, at most 2^30 records per call) that are summed per half-edge in
+                              LDS; crossings past them add their sums with float64 atomics (same result,
+                              slower).  0: 256; < 0: none */
     void* workspace;       /* optional caller-owned device workspace, 256-byte aligned, at least the size
                               sg_exp_workspace_size / sg_backward_workspace_size report.  With it a call
                               allocates nothing, so it can be captured in a HIP graph (debug bit 2 aside).

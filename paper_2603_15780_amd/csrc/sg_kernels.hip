@@ -1294,7 +1294,7 @@ SG_HD __forceinline__ void gx_cross(double* acc, const Ray& st, const float4& c)
 constexpr int kGxChunk = 1024;            // records per chunk
 constexpr int kGxMaxBins = 4096;          // bins (LDS counters of the walk and of the scatter)
 constexpr int kGxWindow = 1024;           // half-edges summed in LDS at once by the reduce pass
-constexpr int64_t kGxMaxRecords = (int64_t)1 << 31;   // bin starts are 32-bit
+constexpr int64_t kGxMaxRecords = (int64_t)1 << 30;   // at most 48 GiB of records (bin starts are 32-bit)
 
 struct GxSink {
     GxRec* rec;       // record buffer, gridDim.x * per_block chunks of kGxChunk records; null: atomics only
