@@ -57,6 +57,18 @@ WALK_SOURCES = ("paper_2603_15780_amd/csrc/sg_kernels.hip", "paper_2603_15780_am
 TRAFFIC_NOTE = "profiles/k_walk_icosphere7_1M_rays.md"
 
 
+def cpu_model():
+    """The host CPU's model name from /proc/cpuinfo (empty if unreadable)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
 def measured_traffic():
     """HBM bytes per walk launch from the committed counter summary, if it was taken on these sources."""
     import hashlib
@@ -237,7 +249,8 @@ def main():
         cpu = {"value": ocross / (c1 - c0), "unit": "face-crossings/s", "cores": cores, "kind": "oracle",
                "sample": f"{rows.shape[0]} of the {n} rays (K={K}), float64 C oracle, {cores} threads, "
                          f"{c1 - c0:.2f} s",
-               "queries_per_s": rows.shape[0] / (c1 - c0)}
+               "queries_per_s": rows.shape[0] / (c1 - c0), "cpu_model": cpu_model(),
+               "host_cpus": os.cpu_count()}
         log(f"oracle: {ocross} crossings in {c1 - c0:.2f}s on {cores} threads; GPU/oracle crossing ratio "
             f"{gpu_cross / max(ocross, 1) if rows.shape[0] == n else float('nan'):.6f}")
     if bwd:

@@ -1120,7 +1120,7 @@ __global__ __launch_bounds__(256) void k_zero_u32(uint32_t* p, int n) {
 // kBucketRays rays in LDS (the LDS atomic returns the local rank), then adds
 // each nonzero local count to the bucket's global counter once (returning the
 // block's base in the bucket).
-constexpr int kBucketRays = 16384;
+constexpr int kBucketRays = 4096;   // 256 blocks for 1M rays, one per CU
 
 __global__ __launch_bounds__(1024) void k_bucket_count(DevMesh M, int64_t n, const int32_t* f, const float* v,
                                                        uint32_t* cnt, int32_t* slot, RayOrder o) {
