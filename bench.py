@@ -199,18 +199,25 @@ def main():
         bo = sg.opts(refill_min=base.refill_min if persistent else 0, walk_blocks=base.walk_blocks if persistent else 0)
         forms = (("ep", sg.BWD_EP, False), ("gfd", sg.BWD_GFD, False), ("ep+gradX", sg.BWD_EP, True),
                  ("gfd+gradX", sg.BWD_GFD, True))
-        if args.config == 5:   # 1.1e10 crossings: most would pass the 2^30 vertex-gradient records and
-            # take the float64 atomics (seconds per call)
-            forms = forms[:2]
+        # The vertex gradient reserves gradx_records records per query (at most 2^30 per call); config 5's
+        # 1.1e10 crossings (641 per ray) go through it in slices of 2^20 queries with 800 records each,
+        # accumulating into one grad_X.
+        gx_slice, gx_records = {5: (1 << 20, 800)}.get(args.config, (n, 0))
+        bo_x = sg.opts(refill_min=bo.refill_min, walk_blocks=bo.walk_blocks, gradx_records=gx_records)
         for name, mode, with_x in forms:
             steps = max(3, args.steps // 2)
 
             def call():
                 mesh.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=fo)
-                if with_x:
-                    gX.zero_()
-                mesh.backward(mode, t["f"], t["b"], t["v"], g_up, f_out=out["f"], v_out=out["v"], out=(gv, gb),
-                              grad_X=gX if with_x else None, o=bo)
+                if not with_x:
+                    mesh.backward(mode, t["f"], t["b"], t["v"], g_up, f_out=out["f"], v_out=out["v"], out=(gv, gb),
+                                  o=bo)
+                    return
+                gX.zero_()
+                for a in range(0, n, gx_slice):
+                    z = slice(a, min(n, a + gx_slice))
+                    mesh.backward(mode, t["f"][z], t["b"][z], t["v"][z], g_up[z], f_out=out["f"][z],
+                                  v_out=out["v"][z], out=(gv[z], gb[z]), grad_X=gX, o=bo_x)
             for _ in range(max(1, args.warmup)):
                 call()
             torch.cuda.synchronize()

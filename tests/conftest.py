@@ -17,3 +17,12 @@ def pytest_configure(config):
 def rng():
     import numpy as np
     return np.random.default_rng(12345)
+
+
+@pytest.fixture(scope="session")
+def config5():
+    """The 1,310,720-face noisy displaced icosphere and its 16,777,216 rays,
+    generated once per session (about a minute of host work)."""
+    from workloads import configs as CF
+    X, F = CF.mesh_config(5)
+    return X, F, CF.rays_config(5, X, F)

@@ -443,12 +443,11 @@ def test_autotune(torch):
         assert torch.equal(a[k], b[k]), k
 
 
-def test_config5_full_batch_sampled(torch):
+def test_config5_full_batch_sampled(torch, config5):
     """16,777,216 rays (|v| up to pi, the start frame transported) on the 1,310,720-face
     noisy displaced icosphere in one call; every 4096th ray against the oracle."""
     from paper_2603_15780_amd import sg
-    X, F = CF.mesh_config(5)
-    r = CF.rays_config(5, X, F)
+    X, F, r = config5
     gm = sg.Mesh(X, F)
     g = run(torch, gm, r)
     n = r["f"].shape[0]
