@@ -1187,9 +1187,12 @@ __global__ __launch_bounds__(256) void k_slot_place(DevMesh M, int64_t n, const 
 // Initial chart state of every ray, stored at its walk slot (slot[i] becomes
 // that slot); the epilogue's start-side terms (|v_t| and the extra vectors'
 // components on the start frame) go to aux, so the epilogue does not revisit
-// the start face.
+// the start face.  With fin (final states by query index), the state's
+// crossing count carries the query index i to the walk, and a query with no
+// walk is marked in fin.
 __global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* states, unsigned long long* counter,
-                                              float* aux, const uint32_t* bstart, int32_t* slot, RayOrder o) {
+                                              float* aux, const uint32_t* bstart, int32_t* slot, RayOrder o,
+                                              Final* fin) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < kMaxQueues) counter[i * kQueueStride] = 0ull;
     if (i >= a.n) return;
@@ -1205,8 +1208,10 @@ __global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* st
         rec.s = rec.t = rec.Lhi = rec.Llo = 0.f;
         rec.phi = rec.flags = 0u;
         rec.ncross = 0;
+        if (fin) fin[i].h = -1;   // the epilogue skips it
     } else {
         rec = pack_state(st);
+        if (fin) rec.ncross = (int32_t)i;   // a start state has crossed nothing: the field carries the query
         float* x = aux + i * (1 + 2 * (int64_t)a.K);
         x[0] = L;
         if (a.K > 0) {
@@ -1366,7 +1371,7 @@ __device__ __forceinline__ int64_t queue_claim(unsigned long long* ctr, const Qu
 template <bool kHash, bool kFlip, bool kHole, bool kGX>
 __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, QueueRanges R, unsigned long long* counter,
                                           int32_t max_steps, float snap, int refill_min, int nq, const float4* cvec,
-                                          double* acc, const GxSink& sink, uint32_t* lbins) {
+                                          double* acc, const GxSink& sink, uint32_t* lbins, Final* fin_out = nullptr) {
     const int lane = (int)(threadIdx.x & 63u);
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     // record chunk of this wave (wave-uniform): index, records written, or spilling to atomics
@@ -1376,6 +1381,7 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, Qu
     bool active = false;
     QueueCursor qc = queue_start(nq);
     int64_t q = 0;
+    int32_t ray = 0;   // with fin_out: the query index, carried in the initial state's crossing count
     Ray st;
     st.h = 0; st.s = st.t = st.Lhi = st.Llo = st.bias = 0.f; st.phi = st.par = 0u; st.ncross = 0; st.hash = 0ull;
     float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1392,6 +1398,10 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, Qu
                     const StateRec rec = states[q];
                     if (rec.h >= 0) {
                         unpack_state(rec, st);
+                        if (fin_out) {
+                            ray = rec.ncross;
+                            st.ncross = 0;
+                        }
                         st.hash = kHash ? fnv_face(14695981039346656037ull, (uint32_t)M.order[rec.h / 3]) : 0ull;
                         if (kGX) c = cvec[q];
                         active = true;
@@ -1406,7 +1416,8 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, Qu
             if (active) {
                 Final fin;
                 if (walk_step<kHash, kFlip, kHole>(M, st, max_steps, snap, fin) == kStepDone) {
-                    *reinterpret_cast<Final*>(&states[q]) = fin;
+                    if (fin_out) fin_out[ray] = fin;
+                    else *reinterpret_cast<Final*>(&states[q]) = fin;
                     active = false;
                 } else if (kGX && st.bias == 0.f) {   // an edge crossing (a vertex passage leaves a bias)
                     cross = true;
@@ -1520,9 +1531,9 @@ __global__ __launch_bounds__(256) void k_walk2(DevMesh M, StateRec* states, Queu
 
 template <bool kHash, bool kFlip, bool kHole>
 __global__ __launch_bounds__(256) void k_walk(DevMesh M, StateRec* states, QueueRanges R, unsigned long long* counter,
-                                              int32_t max_steps, float snap, int refill_min, int nq) {
+                                              int32_t max_steps, float snap, int refill_min, int nq, Final* fin_out) {
     walk_loop<kHash, kFlip, kHole, false>(M, states, R, counter, max_steps, snap, refill_min, nq, nullptr, nullptr,
-                                          GxSink{}, nullptr);
+                                          GxSink{}, nullptr, fin_out);
 }
 
 // The same walk over the backward's stacked chart states (its own symbol, so
@@ -2428,13 +2439,16 @@ hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s) {
 }
 
 // states [n] | epilogue terms [n, 1 + 2K] | walk slots [n] | bucket counts [kMaxBuckets + 2] | ray-queue counters
+// walk states (slot order) | final states (query order) | epilogue terms |
+// slots | bucket counts | queue counters
 struct PersistentLayout {
-    size_t aux, slot, cnt, counter, total;
+    size_t fin, aux, slot, cnt, counter, total;
 };
 static PersistentLayout persistent_layout(int64_t n, int32_t K) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     PersistentLayout L{};
     size_t o = al((size_t)n * sizeof(StateRec));
+    L.fin = o; o = al(o + (size_t)n * sizeof(Final));
     L.aux = o; o = al(o + (size_t)n * (1 + 2 * (size_t)K) * sizeof(float));
     L.slot = o; o = al(o + (size_t)n * sizeof(int32_t));
     L.cnt = o; o = al(o + (size_t)(kMaxBuckets + 2) * sizeof(uint32_t));
@@ -2469,21 +2483,30 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, c
     auto* slot = reinterpret_cast<int32_t*>(p + L.slot);
     auto* cnt = reinterpret_cast<uint32_t*>(p + L.cnt);
     auto* counter = reinterpret_cast<unsigned long long*>(p + L.counter);
+    // the one-ray-per-lane walk writes each final state at its query's index,
+    // so the epilogue streams them; the two-ray form leaves them in the slots
+    const bool by_query = a.rays_per_lane != 2;
+    auto* fin = by_query ? reinterpret_cast<Final*>(p + L.fin) : nullptr;
     const RayOrder ord = ray_order(w.queues);
     order_rays(M, a.n, a.f, a.v, cnt, slot, ord, s);
     hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, counter, aux,
-                       (const uint32_t*)cnt, slot, ord);
+                       (const uint32_t*)cnt, slot, ord, fin);
     const QueueRanges R{cnt, kLenClasses * ord.sub, 1};
     if (ev0) (void)hipEventRecord(ev0, s);
-    if (a.rays_per_lane == 2)
+    if (!by_query)
         SG_DISPATCH(k_walk2, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)w.blocks), dim3(block), s, M,
                     states, R, counter, a.max_steps, a.snap, w.refill_min, w.queues);
     else
         SG_DISPATCH(k_walk, (a.debug & 2u) != 0u, M.has_flip != 0, dim3((unsigned)w.blocks), dim3(block), s, M,
-                    states, R, counter, a.max_steps, a.snap, w.refill_min, w.queues);
+                    states, R, counter, a.max_steps, a.snap, w.refill_min, w.queues, fin);
     if (ev1) (void)hipEventRecord(ev1, s);
-    hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)nullptr,
-                       (const float*)aux, (const int32_t*)slot);
+    if (by_query)
+        hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a,
+                           reinterpret_cast<const StateRec*>(fin), (const uint64_t*)nullptr, (const float*)aux,
+                           (const int32_t*)nullptr);
+    else
+        hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)nullptr,
+                           (const float*)aux, (const int32_t*)slot);
     return hipGetLastError();
 }
 
