@@ -797,7 +797,9 @@ SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps
     const float lo = st.Llo + ((st.Lhi - nh) - lam);
     // (a lane slot without a ray steps a dummy state and never takes the rare branch)
     const bool rare = alive && (!(lam < Lr) || (st.ncross >= max_steps) || (mu < snap) || (omu < snap) || (nx < 0));
-    const Ray old = st;
+    // a lane that takes the rare branch keeps its state unchanged here, so the
+    // branch reads the step's starting state from st itself (no second copy
+    // of the state stays live across the update)
     st.s = rare ? st.s : s2;
     st.t = rare ? st.t : t2;
     st.phi = rare ? st.phi : ph;
@@ -810,48 +812,51 @@ SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps
     if (kHash && !rare) st.hash = fnv_face(st.hash, (uint32_t)M.order[st.h / 3]);
     if (!rare) return kStepContinue;
 
-    // ---- rare events, in priority order
+    // ---- rare events, in priority order (st is the step's starting state)
     if (!(lam < Lr)) {   // the ray ends inside this face (ties stay in the face)
-        set_final(fin, old, fmaf(Lr, cs, old.s), Lr * sn, kRayOk);
+        set_final(fin, st, fmaf(Lr, cs, st.s), Lr * sn, kRayOk);
         return kStepDone;
     }
-    if (old.ncross >= max_steps) {
-        set_final(fin, old, old.s, 0.f, kRayMaxSteps);
+    if (st.ncross >= max_steps) {
+        set_final(fin, st, st.s, 0.f, kRayMaxSteps);
         return kStepDone;
     }
     if (mu < snap || omu < snap) {   // passing a vertex (transport_over_vertex)
         int32_t x0;
-        Ray cand = old;
+        Ray cand = st;
         const bool at_apex = omu < snap;
         const int vr = vertex_rule(M, cand, r, via_ca, at_apex, x0);
         if (vr == kVertexBoundary) {
             if constexpr (kHole) {   // the vertex lies lam along the ray, like a crossing
                 float3 xa, eu, ev, n;
-                chart_frame3(M, old.h, xa, eu, ev, n);
+                chart_frame3(M, st.h, xa, eu, ev, n);
                 const float3 d = make_float3(fmaf(cs, eu.x, sn * ev.x), fmaf(cs, eu.y, sn * ev.y),
                                              fmaf(cs, eu.z, sn * ev.z));
-                return hole_vertex_chain(M, old.h / 3, x0, -1, d, nh, lo, old.par, old.ncross, old.hash, true,
-                                         max_steps, st, fin);
+                const Ray o = st;
+                return hole_vertex_chain(M, o.h / 3, x0, -1, d, nh, lo, o.par, o.ncross, o.hash, true, max_steps, st,
+                                         fin);
             }
-            set_final(fin, old, at_apex ? r.cx : (via_ca ? 0.f : old.s + old.t), at_apex ? r.cy : 0.f, kRayBoundary);
+            set_final(fin, st, at_apex ? r.cx : (via_ca ? 0.f : st.s + st.t), at_apex ? r.cy : 0.f, kRayBoundary);
             return kStepDone;
         }
         if (vr == kVertexDone) {   // the vertex lies lam along the ray: consume it like a crossing
             cand.Lhi = nh;
             cand.Llo = lo;
-            cand.ncross = old.ncross + 1;
-            cand.hash = kHash ? fnv_face(old.hash, (uint32_t)M.order[cand.h / 3]) : 0ull;
+            cand.ncross = st.ncross + 1;
+            cand.hash = kHash ? fnv_face(st.hash, (uint32_t)M.order[cand.h / 3]) : 0ull;
             st = cand;
             return kStepContinue;
         }
     }
     if (nx < 0) {   // boundary edge: stop on it (Sec. 4, original behaviour), or slide along it
-        if constexpr (kHole) return hole_edge(M, old, r, via_ca, mu, omu, nh, lo, max_steps, st, fin);
-        set_final(fin, old, fmaf(lam, cs, old.s), lam * sn, kRayBoundary);
+        if constexpr (kHole) {
+            const Ray o = st;
+            return hole_edge(M, o, r, via_ca, mu, omu, nh, lo, max_steps, st, fin);
+        }
+        set_final(fin, st, fmaf(lam, cs, st.s), lam * sn, kRayBoundary);
         return kStepDone;
     }
     // a vertex passed too far away to snap: an ordinary crossing
-    st = old;
     st.s = s2;
     st.t = t2;
     st.phi = ph;
@@ -860,8 +865,8 @@ SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps
     st.h = nx >> 1;
     st.par = par;
     st.bias = 0.f;
-    st.ncross = old.ncross + 1;
-    if (kHash) st.hash = fnv_face(old.hash, (uint32_t)M.order[st.h / 3]);
+    if (kHash) st.hash = fnv_face(st.hash, (uint32_t)M.order[st.h / 3]);
+    st.ncross = st.ncross + 1;
     return kStepContinue;
 }
 
@@ -1065,6 +1070,8 @@ constexpr size_t kQueueBytes = (size_t)kMaxQueues * kQueueStride * sizeof(unsign
 // kernel that recomputes a ray's bucket gets the same one).
 constexpr int kLenClasses = 8;
 constexpr int kVmaxWord = kMaxBuckets + 1;   // cnt[kVmaxWord]: float bits of the longest |v|^2
+constexpr int kLenBlocks = 256;              // k_len_max blocks; their partial maxima follow kVmaxWord
+constexpr int kCountWords = kMaxBuckets + 2 + kLenBlocks;   // words of the bucket-count array
 
 struct RayOrder {
     int nq;    // queue ranges
@@ -1096,10 +1103,13 @@ SG_HD __forceinline__ int ray_bucket(const DevMesh& M, int32_t fu, const float* 
     return (int)((j * kLenClasses + c) * o.sub + sb);
 }
 
-// Longest finite |v|^2 of a call (one atomic per block on the float bits,
-// which order like the values for non-negative floats).
-__global__ __launch_bounds__(256) void k_len_max(int64_t n, const float* v, uint32_t* vmax_bits) {
+// Longest finite |v|^2 of a call, as float bits (which order like the values
+// for non-negative floats): each block writes its partial maximum after
+// cnt[kVmaxWord], and the blocks clear the bucket counts for k_bucket_count.
+__global__ __launch_bounds__(256) void k_len_max(int64_t n, const float* v, uint32_t* cnt) {
     __shared__ uint32_t part[4];
+    for (int j = (int)(blockIdx.x * blockDim.x + threadIdx.x); j <= kMaxBuckets; j += (int)(gridDim.x * blockDim.x))
+        cnt[j] = 0u;
     uint32_t m = 0u;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const float l2 = len2(v + 3 * i);
@@ -1108,7 +1118,7 @@ __global__ __launch_bounds__(256) void k_len_max(int64_t n, const float* v, uint
     for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
     if ((threadIdx.x & 63u) == 0u) part[threadIdx.x >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0) atomicMax(vmax_bits, max(max(part[0], part[1]), max(part[2], part[3])));
+    if (threadIdx.x == 0) cnt[kVmaxWord + 1 + blockIdx.x] = max(max(part[0], part[1]), max(part[2], part[3]));
 }
 
 __global__ __launch_bounds__(256) void k_zero_u32(uint32_t* p, int n) {
@@ -1123,10 +1133,22 @@ __global__ __launch_bounds__(256) void k_zero_u32(uint32_t* p, int n) {
 constexpr int kBucketRays = 4096;   // 256 blocks for 1M rays, one per CU
 
 __global__ __launch_bounds__(1024) void k_bucket_count(DevMesh M, int64_t n, const int32_t* f, const float* v,
-                                                       uint32_t* cnt, int32_t* slot, RayOrder o) {
+                                                       uint32_t* cnt, int32_t* slot, RayOrder o, int nparts) {
     __shared__ uint32_t local[kMaxBuckets + 1];
     const int nb = o.nb;
-    const uint32_t vmax = cnt[kVmaxWord];
+    // the call's longest |v|^2 from k_len_max's nparts partial maxima (block 0 keeps it for later kernels)
+    __shared__ uint32_t vmax_s;
+    if (threadIdx.x < 64u) {
+        uint32_t m = 0u;
+        for (int j = (int)threadIdx.x; j < nparts; j += 64) m = max(m, cnt[kVmaxWord + 1 + j]);
+        for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+        if (threadIdx.x == 0u) {
+            vmax_s = m;
+            if (blockIdx.x == 0u) cnt[kVmaxWord] = m;
+        }
+    }
+    __syncthreads();
+    const uint32_t vmax = vmax_s;
     const int t = (int)threadIdx.x;
     for (int b = t; b < nb; b += 1024) local[b] = 0u;
     __syncthreads();
@@ -2465,7 +2487,7 @@ hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// states [n] | epilogue terms [n, 1 + 2K] | walk slots [n] | bucket counts [kMaxBuckets + 2] | ray-queue counters
+// states [n] | epilogue terms [n, 1 + 2K] | walk slots [n] | bucket counts [kCountWords] | ray-queue counters
 // walk states (slot order) | final states (query order) | epilogue terms |
 // slots | bucket counts | queue counters
 struct PersistentLayout {
@@ -2478,7 +2500,7 @@ static PersistentLayout persistent_layout(int64_t n, int32_t K) {
     L.fin = o; o = al(o + (size_t)n * sizeof(Final));
     L.aux = o; o = al(o + (size_t)n * (1 + 2 * (size_t)K) * sizeof(float));
     L.slot = o; o = al(o + (size_t)n * sizeof(int32_t));
-    L.cnt = o; o = al(o + (size_t)(kMaxBuckets + 2) * sizeof(uint32_t));
+    L.cnt = o; o = al(o + (size_t)kCountWords * sizeof(uint32_t));
     L.counter = o; o = al(o + kQueueBytes);
     L.total = o;
     return L;
@@ -2486,15 +2508,13 @@ static PersistentLayout persistent_layout(int64_t n, int32_t K) {
 size_t exp_persistent_workspace(int64_t n, int32_t K) { return persistent_layout(n, K).total; }
 
 // Bucket counts of the walk order (ray_bucket) and each ray's rank in its
-// bucket; cnt (kMaxBuckets + 2 words) ends with the exclusive bucket starts.
+// bucket; cnt (kCountWords words) ends with the exclusive bucket starts.
 static void order_rays(const DevMesh& M, int64_t n, const int32_t* f, const float* v, uint32_t* cnt, int32_t* slot,
                        const RayOrder& ord, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((kMaxBuckets + 2 + 255) / 256)), dim3(256), 0, s, cnt,
-                       kMaxBuckets + 2);
-    hipLaunchKernelGGL(k_len_max, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 256)), dim3(256), 0, s, n, v,
-                       cnt + kVmaxWord);
+    const int nparts = (int)std::min<int64_t>((n + 255) / 256, kLenBlocks);
+    hipLaunchKernelGGL(k_len_max, dim3((unsigned)nparts), dim3(256), 0, s, n, v, cnt);
     hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)((n + kBucketRays - 1) / kBucketRays)), dim3(1024), 0, s, M, n, f,
-                       v, cnt, slot, ord);
+                       v, cnt, slot, ord, nparts);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, cnt, ord.nb);
 }
 
@@ -2620,7 +2640,7 @@ static BwdLayout bwd_layout(int64_t n, int32_t mode, bool has_flip, bool vjp, bo
     L.cvec = o; o = align256(o + (gradx ? (size_t)n * sizeof(float4) : 0));
     L.acc = o; o = align256(o + (gradx ? 15 * (size_t)n_faces * sizeof(double) : 0));
     L.slot = o; o = align256(o + (walk ? (size_t)n * sizeof(int32_t) : 0));
-    L.cnt = o; o = align256(o + (walk ? (size_t)(kMaxBuckets + 2) * sizeof(uint32_t) : 0));
+    L.cnt = o; o = align256(o + (walk ? (size_t)kCountWords * sizeof(uint32_t) : 0));
     L.counter = o; o = align256(o + kQueueBytes);
     const int64_t nh = 3 * n_faces;
     L.shift = 10;
