@@ -434,9 +434,14 @@ int pack_geometry(const float* X_host, PackedMesh& pm) {
         for (int64_t v = 0; v < n_verts; ++v) pm.half[v] = pm.vbnd[v] ? -1 : theta_fx[v] / 2;
         pm.X.assign(X_host, X_host + 3 * n_verts);
         pm.mean_edge = esum / (double)ecount;
-        pm.geo.assign(16 * (size_t)n_faces, 0.f);
+        // 128-byte geometry records: the three vertices (w: vertex id), the user
+        // face id, and a copy of the face's walk record, so a start or end
+        // frame takes one line
+        static_assert(sizeof(FaceRec) == 32, "the walk record fills two float4 of the geometry record");
+        pm.geo.assign(32 * (size_t)n_faces, 0.f);
         for (int64_t f = 0; f < n_faces; ++f) {
-            float* g = &pm.geo[16 * (size_t)f];
+            float* g = &pm.geo[32 * (size_t)f];
+            std::memcpy(&g[16], &pm.face[f], sizeof(FaceRec));
             for (int k = 0; k < 3; ++k) {
                 const int32_t v = F[3 * f + k];
                 g[4 * k] = X_host[3 * (int64_t)v];

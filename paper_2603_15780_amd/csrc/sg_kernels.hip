@@ -87,13 +87,9 @@ struct Ray {
     uint64_t hash;
 };
 
-// Chart of half-edge h = 3 f + k from face f's record (one 32-byte gather
-// with a 32-bit byte offset, f < 2^27): the edges and corners rotated by k,
-// the apex from |ac| and the corner at a.
-SG_HD __forceinline__ HalfEdgeRec rec_at(const DevMesh& M, int32_t h) {
-    const uint32_t f = (uint32_t)h / 3u;
-    const uint32_t k = (uint32_t)h - 3u * f;
-    const FaceRec q = *reinterpret_cast<const FaceRec*>(reinterpret_cast<const char*>(M.face) + (f << 5));
+// Chart of half-edge h = 3 f + k from face f's record: the edges and corners
+// rotated by k, the apex from |ac| and the corner at a.
+SG_HD __forceinline__ HalfEdgeRec rec_decode(const FaceRec& q, uint32_t k) {
     const uint32_t c2 = kPiFx - q.c0 - q.c1;
     HalfEdgeRec r;
     r.A = k == 0u ? q.c0 : (k == 1u ? q.c1 : c2);
@@ -110,6 +106,21 @@ SG_HD __forceinline__ HalfEdgeRec rec_at(const DevMesh& M, int32_t h) {
     return r;
 }
 
+// The walk's gather: one 32-byte record with a 32-bit byte offset (f < 2^27).
+SG_HD __forceinline__ HalfEdgeRec rec_at(const DevMesh& M, int32_t h) {
+    const uint32_t f = (uint32_t)h / 3u;
+    const FaceRec q = *reinterpret_cast<const FaceRec*>(reinterpret_cast<const char*>(M.face) + (f << 5));
+    return rec_decode(q, (uint32_t)h - 3u * f);
+}
+
+// The same chart from the copy of the face record inside the 128-byte
+// geometry record (start and end frames read that line anyway).
+SG_HD __forceinline__ HalfEdgeRec rec_geo(const DevMesh& M, int32_t h) {
+    const uint32_t f = (uint32_t)h / 3u;
+    const FaceRec q = *reinterpret_cast<const FaceRec*>(M.geo + 8 * (int64_t)f + 4);
+    return rec_decode(q, (uint32_t)h - 3u * f);
+}
+
 // hardware reciprocal (about 1 ulp); the walk only needs local accuracy
 SG_HD __forceinline__ float rcp(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -121,14 +132,15 @@ SG_HD __forceinline__ float rcp(float x) {
 
 SG_HD __forceinline__ float3 ld3(const float* p) { return make_float3(p[0], p[1], p[2]); }
 SG_HD __forceinline__ float3 sub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
-// Position of vertex k (0..2, face order) of internal face f: one 64-byte
-// record per face holds the three positions (w: the global vertex id) and the
-// user face id, so an epilogue or a start frame takes one line, not four.
+// Position of vertex k (0..2, face order) of internal face f: one 128-byte
+// record per face holds the three positions (w: the global vertex id), the
+// user face id and a copy of the face's walk record, so an epilogue or a
+// start frame takes one line, not five.
 SG_HD __forceinline__ float3 fvx(const DevMesh& M, int64_t f, int k) {
-    const float4 q = M.geo[4 * f + k];
+    const float4 q = M.geo[8 * f + k];
     return make_float3(q.x, q.y, q.z);
 }
-SG_HD __forceinline__ int32_t face_user(const DevMesh& M, int64_t f) { return __builtin_bit_cast(int32_t, M.geo[4 * f + 3].x); }
+SG_HD __forceinline__ int32_t face_user(const DevMesh& M, int64_t f) { return __builtin_bit_cast(int32_t, M.geo[8 * f + 3].x); }
 SG_HD __forceinline__ float dot(float3 a, float3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
 SG_HD __forceinline__ float3 crs(float3 a, float3 b) {
     return make_float3(fmaf(a.y, b.z, -a.z * b.y), fmaf(a.z, b.x, -a.x * b.z), fmaf(a.x, b.y, -a.y * b.x));
@@ -164,7 +176,7 @@ SG_HD __forceinline__ uint32_t rad_to_fx(float a) {
 SG_HD int enter_face(const DevMesh& M, int32_t f, int k0, float ell0, float bA, float bB, float bC, uint32_t phi0,
                      float Lhi, float Llo, Ray& st) {
     const int32_t h0 = 3 * f + k0;
-    const HalfEdgeRec r0 = rec_at(M, h0);
+    const HalfEdgeRec r0 = rec_geo(M, h0);
     float dy, dx;
     sincos_full(phi0, dy, dx);
     // barycentric rates of the direction in the chart
@@ -407,7 +419,7 @@ SG_HD int ray_init(const DevMesh& M, int32_t fu, const float* bp, const float* v
 SG_HD int enter_chart(const DevMesh& M, int32_t h, float ex, float ey, uint32_t phi, float Lhi, float Llo, Ray& st) {
     const int32_t f = h / 3;
     const int k0 = h - 3 * f;
-    const HalfEdgeRec r = rec_at(M, h);
+    const HalfEdgeRec r = rec_geo(M, h);
     const float ell = r.lab;   // |ab| of this chart
     float bc = ey / r.cy;
     float bb = (ex - bc * r.cx) / ell;
@@ -929,7 +941,7 @@ SG_HD void write_final(const DevMesh& M, const ExpArgs& a, int64_t i, const Fina
                        const float* aux = nullptr) {
     const int32_t fe = fin.h / 3;
     const int ke = fin.h - 3 * fe;
-    const HalfEdgeRec r = rec_at(M, fin.h);
+    const HalfEdgeRec r = rec_geo(M, fin.h);
     const int64_t f3 = 3 * (int64_t)fe;
     const float3 y0 = fvx(M, f3 / 3, 0);
     const float3 y1 = fvx(M, f3 / 3, 1);
@@ -1946,7 +1958,7 @@ __global__ __launch_bounds__(256) void k_finish(DevMesh M, ExpArgs a, const Stat
 SG_HD __forceinline__ float3 final_offset(const DevMesh& M, const Final& fin, float3 o, int32_t& fe_out) {
     const int32_t fe = fin.h / 3;
     const int ke = fin.h - 3 * fe;
-    const HalfEdgeRec r = rec_at(M, fin.h);
+    const HalfEdgeRec r = rec_geo(M, fin.h);
     const int64_t f3 = 3 * (int64_t)fe;
     const float3 y0 = sub(fvx(M, f3 / 3, 0), o);
     const float3 y1 = sub(fvx(M, f3 / 3, 1), o);
@@ -2084,7 +2096,7 @@ SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_
     out[1] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0 + dphi, L, Llo + dl, st) == kInitOk ? pack_state(st)
                                                                                                        : dead_state();
     out[2] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, 0u, ep, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
-    const uint32_t Av = rec_at(M, 3 * S.f).A;   // angle of e_v = unit(x2 - x0) in the chart
+    const uint32_t Av = rec_geo(M, 3 * S.f).A;   // angle of e_v = unit(x2 - x0) in the chart
     out[3] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, Av, ep, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
 }
 
@@ -2106,7 +2118,7 @@ SG_HD void bwd_stage2(const DevMesh& M, const BwdArgs& a, const StateRec* s1, St
     }
     out[0] = enter_chart(M, F0.h, F0.ex, F0.ey, F0.phi, a.eps_v, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
     const uint32_t psi_u = phi0;                              // v relative to e_u
-    const uint32_t psi_v = phi0 - rec_at(M, 3 * S.f).A;       // v relative to e_v
+    const uint32_t psi_v = phi0 - rec_geo(M, 3 * S.f).A;       // v relative to e_v
     const uint32_t du = (Fu.flags & kParity) ? Fu.phi - psi_u : Fu.phi + psi_u;
     const uint32_t dv = (Fv.flags & kParity) ? Fv.phi - psi_v : Fv.phi + psi_v;
     out[1] = enter_chart(M, Fu.h, Fu.ex, Fu.ey, du, L, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
