@@ -89,16 +89,19 @@ struct Ray {
 
 // Chart of half-edge h = 3 f + k from face f's record: the edges and corners
 // rotated by k, the apex from |ac| and the corner at a.
-SG_HD __forceinline__ HalfEdgeRec rec_decode(const FaceRec& q, uint32_t k) {
-    const uint32_t c2 = kPiFx - q.c0 - q.c1;
+SG_HD __forceinline__ HalfEdgeRec rec_decode(const FaceRec q, uint32_t k) {
+    // fields as scalars first, so the rotation by k stays selects on registers
+    const float l0 = q.l[0], l1 = q.l[1], l2 = q.l[2];
+    const int32_t n0 = q.nb[0], n1 = q.nb[1], n2 = q.nb[2];
+    const uint32_t c0 = q.c0, c1 = q.c1, c2 = kPiFx - q.c0 - q.c1;
     HalfEdgeRec r;
-    r.A = k == 0u ? q.c0 : (k == 1u ? q.c1 : c2);
-    r.B = k == 0u ? q.c1 : (k == 1u ? c2 : q.c0);
-    r.lab = k == 0u ? q.l[0] : (k == 1u ? q.l[1] : q.l[2]);
-    r.lbc = k == 0u ? q.l[1] : (k == 1u ? q.l[2] : q.l[0]);
-    r.lac = k == 0u ? q.l[2] : (k == 1u ? q.l[0] : q.l[1]);
-    r.nbc = k == 0u ? q.nb[1] : (k == 1u ? q.nb[2] : q.nb[0]);
-    r.nca = k == 0u ? q.nb[2] : (k == 1u ? q.nb[0] : q.nb[1]);
+    r.A = k == 0u ? c0 : (k == 1u ? c1 : c2);
+    r.B = k == 0u ? c1 : (k == 1u ? c2 : c0);
+    r.lab = k == 0u ? l0 : (k == 1u ? l1 : l2);
+    r.lbc = k == 0u ? l1 : (k == 1u ? l2 : l0);
+    r.lac = k == 0u ? l2 : (k == 1u ? l0 : l1);
+    r.nbc = k == 0u ? n1 : (k == 1u ? n2 : n0);
+    r.nca = k == 0u ? n2 : (k == 1u ? n0 : n1);
     float sn, cs;
     sincos_fx(r.A, sn, cs);
     r.cx = r.lac * cs;
@@ -172,11 +175,14 @@ SG_HD __forceinline__ uint32_t rad_to_fx(float a) {
 // angle phi0 to that chart's x-axis for length Lhi + Llo.  The ray is extended
 // backwards to the edge it would have entered through, so the walk always
 // starts on an entry edge with remaining length L + tau (initialise_trace).
-// ell0 is the length of the chart's x-axis edge.
+// ell0 is the length of the chart's x-axis edge.  kGeo: the chart comes from
+// the geometry record (a start frame has read that line), else from the
+// compact walk record.
+template <bool kGeo = true>
 SG_HD int enter_face(const DevMesh& M, int32_t f, int k0, float ell0, float bA, float bB, float bC, uint32_t phi0,
                      float Lhi, float Llo, Ray& st) {
     const int32_t h0 = 3 * f + k0;
-    const HalfEdgeRec r0 = rec_geo(M, h0);
+    const HalfEdgeRec r0 = kGeo ? rec_geo(M, h0) : rec_at(M, h0);
     float dy, dx;
     sincos_full(phi0, dy, dx);
     // barycentric rates of the direction in the chart
@@ -419,14 +425,14 @@ SG_HD int ray_init(const DevMesh& M, int32_t fu, const float* bp, const float* v
 SG_HD int enter_chart(const DevMesh& M, int32_t h, float ex, float ey, uint32_t phi, float Lhi, float Llo, Ray& st) {
     const int32_t f = h / 3;
     const int k0 = h - 3 * f;
-    const HalfEdgeRec r = rec_geo(M, h);
+    const HalfEdgeRec r = rec_at(M, h);
     const float ell = r.lab;   // |ab| of this chart
     float bc = ey / r.cy;
     float bb = (ex - bc * r.cx) / ell;
     float ba = 1.0f - bb - bc;
     ba = fmaxf(ba, 0.f); bb = fmaxf(bb, 0.f); bc = fmaxf(bc, 0.f);
     const float is = 1.0f / (ba + bb + bc);
-    return enter_face(M, f, k0, ell, ba * is, bb * is, bc * is, phi, Lhi, Llo, st);
+    return enter_face<false>(M, f, k0, ell, ba * is, bb * is, bc * is, phi, Lhi, Llo, st);
 }
 
 enum VertexResult { kVertexDone = 0, kVertexNoSnap = 1, kVertexBoundary = 2 };
