@@ -248,9 +248,15 @@ struct StartFrame {
     float3 x0, ex, ey, n;   // origin and chart frame in 3D
 };
 
-SG_HD __forceinline__ int start_frame(const DevMesh& M, int32_t fu, const float* bp, StartFrame& S) {
-    if (fu < 0 || (int64_t)fu >= M.n_faces) return kInitBad;
-    S.f = M.perm[fu];
+// Internal face id of user face fu, or -1 when fu is out of range.
+SG_HD __forceinline__ int32_t internal_face(const DevMesh& M, int32_t fu) {
+    return (fu >= 0 && (int64_t)fu < M.n_faces) ? M.perm[fu] : -1;
+}
+
+// fi: the internal id of the query's face (-1: out of range).
+SG_HD __forceinline__ int start_frame_int(const DevMesh& M, int32_t fi, const float* bp, StartFrame& S) {
+    if (fi < 0) return kInitBad;
+    S.f = fi;
     float b0 = bp[0], b1 = bp[1], b2 = bp[2];
     if (!(b0 >= 0.f && b1 >= 0.f && b2 >= 0.f)) return kInitBad;
     const float bs = b0 + b1 + b2;
@@ -266,6 +272,10 @@ SG_HD __forceinline__ int start_frame(const DevMesh& M, int32_t fu, const float*
     S.ex = scl(e1, 1.0f / S.l0);
     S.ey = crs(S.n, S.ex);
     return kInitOk;
+}
+
+SG_HD __forceinline__ int start_frame(const DevMesh& M, int32_t fu, const float* bp, StartFrame& S) {
+    return start_frame_int(M, internal_face(M, fu), bp, S);
 }
 
 // ---------------------------------------------------------------- float-float arithmetic
@@ -408,9 +418,9 @@ SG_HD __forceinline__ void start_direction(const DevMesh& M, int32_t f, float3 v
     }
 }
 
-SG_HD int ray_init(const DevMesh& M, int32_t fu, const float* bp, const float* vp, Ray& st, float& L) {
+SG_HD int ray_init_int(const DevMesh& M, int32_t fi, const float* bp, const float* vp, Ray& st, float& L) {
     StartFrame S;
-    if (start_frame(M, fu, bp, S) != kInitOk) return kInitBad;
+    if (start_frame_int(M, fi, bp, S) != kInitOk) return kInitBad;
     const float3 v = ld3(vp);
     if (!__builtin_isfinite(v.x) || !__builtin_isfinite(v.y) || !__builtin_isfinite(v.z)) return kInitBad;
     float Llo;
@@ -418,6 +428,10 @@ SG_HD int ray_init(const DevMesh& M, int32_t fu, const float* bp, const float* v
     start_direction(M, S.f, v, L, Llo, phi0);
     if (!(L > 0.f)) return kInitZero;
     return enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, Llo, st);
+}
+
+SG_HD int ray_init(const DevMesh& M, int32_t fu, const float* bp, const float* vp, Ray& st, float& L) {
+    return ray_init_int(M, internal_face(M, fu), bp, vp, st, L);
 }
 
 // Starts a walk at chart point (ex, ey) of half-edge h (an end point of an
@@ -930,8 +944,10 @@ SG_HD void write_unwalked(const DevMesh& M, const ExpArgs& a, int64_t i, bool ba
 }
 
 // Unit tangent d0 of ray i's projected v on its start face and n0 x d0.
-SG_HD __forceinline__ void start_tangent_frame(const DevMesh& M, const ExpArgs& a, int64_t i, float3& d0, float3& q0) {
-    const int64_t g3 = 3 * (int64_t)M.perm[a.f[i]];
+// fi: the internal id of query i's start face.
+SG_HD __forceinline__ void start_tangent_frame_int(const DevMesh& M, const ExpArgs& a, int64_t i, int32_t fi,
+                                                   float3& d0, float3& q0) {
+    const int64_t g3 = 3 * (int64_t)fi;
     const float3 x0 = fvx(M, g3 / 3, 0);
     const float3 x1 = fvx(M, g3 / 3, 1);
     const float3 x2 = fvx(M, g3 / 3, 2);
@@ -939,6 +955,10 @@ SG_HD __forceinline__ void start_tangent_frame(const DevMesh& M, const ExpArgs& 
     const float3 v = ld3(a.v + 3 * i);
     d0 = nrm(sub(v, scl(n0, dot(v, n0))));
     q0 = crs(n0, d0);
+}
+
+SG_HD __forceinline__ void start_tangent_frame(const DevMesh& M, const ExpArgs& a, int64_t i, float3& d0, float3& q0) {
+    start_tangent_frame_int(M, a, i, M.perm[a.f[i]], d0, q0);
 }
 
 // Epilogue: end face, barycentrics, 3D point, transported tangent and vectors.
@@ -1107,9 +1127,11 @@ inline RayOrder ray_order(int nq) {
 
 SG_HD __forceinline__ float len2(const float* v) { return fmaf(v[0], v[0], fmaf(v[1], v[1], v[2] * v[2])); }
 
-SG_HD __forceinline__ int ray_bucket(const DevMesh& M, int32_t fu, const float* v, const RayOrder& o, uint32_t vmax_bits) {
-    if (!(fu >= 0 && (int64_t)fu < M.n_faces)) return o.nb - 1;
-    const int64_t x = (int64_t)M.perm[fu] * o.nq;
+// fi: the internal id of the ray's start face (-1: out of range).
+SG_HD __forceinline__ int ray_bucket_int(const DevMesh& M, int32_t fi, const float* v, const RayOrder& o,
+                                         uint32_t vmax_bits) {
+    if (fi < 0) return o.nb - 1;
+    const int64_t x = (int64_t)fi * o.nq;
     const int64_t j = x / M.n_faces;
     const int64_t sb = ((x - j * M.n_faces) * o.sub) / M.n_faces;
     const float l2 = len2(v);
@@ -1119,6 +1141,10 @@ SG_HD __forceinline__ int ray_bucket(const DevMesh& M, int32_t fu, const float* 
         c = d < (uint32_t)kLenClasses ? (int)d : kLenClasses - 1;
     }
     return (int)((j * kLenClasses + c) * o.sub + sb);
+}
+
+SG_HD __forceinline__ int ray_bucket(const DevMesh& M, int32_t fu, const float* v, const RayOrder& o, uint32_t vmax_bits) {
+    return ray_bucket_int(M, internal_face(M, fu), v, o, vmax_bits);
 }
 
 // Longest finite |v|^2 of a call, as float bits (which order like the values
@@ -1151,7 +1177,8 @@ __global__ __launch_bounds__(256) void k_zero_u32(uint32_t* p, int n) {
 constexpr int kBucketRays = 4096;   // 256 blocks for 1M rays, one per CU
 
 __global__ __launch_bounds__(1024) void k_bucket_count(DevMesh M, int64_t n, const int32_t* f, const float* v,
-                                                       uint32_t* cnt, int32_t* slot, RayOrder o, int nparts) {
+                                                       uint32_t* cnt, int32_t* slot, RayOrder o, int nparts,
+                                                       int32_t* fint) {
     __shared__ uint32_t local[kMaxBuckets + 1];
     const int nb = o.nb;
     // the call's longest |v|^2 from k_len_max's nparts partial maxima (block 0 keeps it for later kernels)
@@ -1177,7 +1204,9 @@ __global__ __launch_bounds__(1024) void k_bucket_count(DevMesh M, int64_t n, con
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int64_t i = i0 + (int64_t)j * 1024 + t;
-        bk[j] = i < n ? ray_bucket(M, f[i], v + 3 * i, o, vmax) : -1;
+        const int32_t fi = i < n ? internal_face(M, f[i]) : -1;
+        if (fint && i < n) fint[i] = fi;
+        bk[j] = i < n ? ray_bucket_int(M, fi, v + 3 * i, o, vmax) : -1;
         rk[j] = bk[j] >= 0 ? atomicAdd(&local[bk[j]], 1u) : 0u;
     }
     __syncthreads();
@@ -1232,15 +1261,17 @@ __global__ __launch_bounds__(256) void k_slot_place(DevMesh M, int64_t n, const 
 // walk is marked in fin.
 __global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* states, unsigned long long* counter,
                                               float* aux, const uint32_t* bstart, int32_t* slot, RayOrder o,
-                                              Final* fin) {
+                                              Final* fin, const int32_t* fint) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < kMaxQueues) counter[i * kQueueStride] = 0ull;
     if (i >= a.n) return;
-    const int32_t at = (int32_t)bstart[ray_bucket(M, a.f[i], a.v + 3 * i, o, bstart[kVmaxWord])] + slot[i];
-    slot[i] = at;
+    // the internal face id from the bucket pass (a stream), not a second random lookup
+    const int32_t fi = fint ? fint[i] : internal_face(M, a.f[i]);
+    const int32_t at = (int32_t)bstart[ray_bucket_int(M, fi, a.v + 3 * i, o, bstart[kVmaxWord])] + slot[i];
+    if (!fin) slot[i] = at;   // the slot-order epilogue needs it
     Ray st;
     float L = 0.f;
-    const int ir = ray_init(M, a.f[i], a.b + 3 * i, a.v + 3 * i, st, L);
+    const int ir = ray_init_int(M, fi, a.b + 3 * i, a.v + 3 * i, st, L);
     StateRec rec;
     if (ir != kInitOk) {
         write_unwalked(M, a, i, ir == kInitBad);
@@ -1256,7 +1287,7 @@ __global__ __launch_bounds__(256) void k_init(DevMesh M, ExpArgs a, StateRec* st
         x[0] = L;
         if (a.K > 0) {
             float3 d0, q0;
-            start_tangent_frame(M, a, i, d0, q0);
+            start_tangent_frame_int(M, a, i, fi, d0, q0);
             for (int kk = 0; kk < a.K; ++kk) {
                 const float3 w = ld3(a.W + 3 * (i * a.K + kk));
                 x[1 + 2 * kk] = dot(w, d0);
@@ -2507,9 +2538,9 @@ hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s) {
 
 // states [n] | epilogue terms [n, 1 + 2K] | walk slots [n] | bucket counts [kCountWords] | ray-queue counters
 // walk states (slot order) | final states (query order) | epilogue terms |
-// slots | bucket counts | queue counters
+// slots | internal start-face ids | bucket counts | queue counters
 struct PersistentLayout {
-    size_t fin, aux, slot, cnt, counter, total;
+    size_t fin, aux, slot, fint, cnt, counter, total;
 };
 static PersistentLayout persistent_layout(int64_t n, int32_t K) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -2518,6 +2549,7 @@ static PersistentLayout persistent_layout(int64_t n, int32_t K) {
     L.fin = o; o = al(o + (size_t)n * sizeof(Final));
     L.aux = o; o = al(o + (size_t)n * (1 + 2 * (size_t)K) * sizeof(float));
     L.slot = o; o = al(o + (size_t)n * sizeof(int32_t));
+    L.fint = o; o = al(o + (size_t)n * sizeof(int32_t));
     L.cnt = o; o = al(o + (size_t)kCountWords * sizeof(uint32_t));
     L.counter = o; o = al(o + kQueueBytes);
     L.total = o;
@@ -2528,11 +2560,11 @@ size_t exp_persistent_workspace(int64_t n, int32_t K) { return persistent_layout
 // Bucket counts of the walk order (ray_bucket) and each ray's rank in its
 // bucket; cnt (kCountWords words) ends with the exclusive bucket starts.
 static void order_rays(const DevMesh& M, int64_t n, const int32_t* f, const float* v, uint32_t* cnt, int32_t* slot,
-                       const RayOrder& ord, hipStream_t s) {
+                       const RayOrder& ord, hipStream_t s, int32_t* fint = nullptr) {
     const int nparts = (int)std::min<int64_t>((n + 255) / 256, kLenBlocks);
     hipLaunchKernelGGL(k_len_max, dim3((unsigned)nparts), dim3(256), 0, s, n, v, cnt);
     hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)((n + kBucketRays - 1) / kBucketRays)), dim3(1024), 0, s, M, n, f,
-                       v, cnt, slot, ord, nparts);
+                       v, cnt, slot, ord, nparts, fint);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, cnt, ord.nb);
 }
 
@@ -2553,9 +2585,10 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, c
     const bool by_query = a.rays_per_lane != 2;
     auto* fin = by_query ? reinterpret_cast<Final*>(p + L.fin) : nullptr;
     const RayOrder ord = ray_order(w.queues);
-    order_rays(M, a.n, a.f, a.v, cnt, slot, ord, s);
+    auto* fint = reinterpret_cast<int32_t*>(p + L.fint);
+    order_rays(M, a.n, a.f, a.v, cnt, slot, ord, s, fint);
     hipLaunchKernelGGL(k_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, counter, aux,
-                       (const uint32_t*)cnt, slot, ord, fin);
+                       (const uint32_t*)cnt, slot, ord, fin, (const int32_t*)fint);
     const QueueRanges R{cnt, kLenClasses * ord.sub, 1};
     if (ev0) (void)hipEventRecord(ev0, s);
     if (!by_query)
