@@ -1372,6 +1372,15 @@ constexpr int kGxMaxBins = 4096;          // bins (LDS counters of the walk and 
 constexpr int kGxWindow = 1024;           // half-edges summed in LDS at once by the reduce pass
 constexpr int64_t kGxMaxRecords = (int64_t)1 << 30;   // at most 48 GiB of records (bin starts are 32-bit)
 
+// A record leaves the walk as a streaming (non-temporal) store, so the 24
+// bytes per crossing do not displace the face records the walk re-reads
+// from L2.
+__device__ __forceinline__ void gx_store(GxRec* p, const GxRec& r) {
+    uint32_t* d = reinterpret_cast<uint32_t*>(p);
+    __builtin_nontemporal_store((uint32_t)r.h, d);
+    for (int k = 0; k < 5; ++k) __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, r.q[k]), d + 1 + k);
+}
+
 struct GxSink {
     GxRec* rec;       // record buffer, gridDim.x * per_block chunks of kGxChunk records; null: atomics only
     uint32_t* fill;   // records written into each claimed chunk
@@ -1514,7 +1523,7 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, Qu
                     if (cross) {
                         if (!spill) {
                             const GxRec r = gx_terms(st, c);
-                            sink.rec[chunk * kGxChunk + used + __popcll(m & below)] = r;
+                            gx_store(sink.rec + chunk * kGxChunk + used + __popcll(m & below), r);
                             atomicAdd(&lbins[r.h >> sink.shift], 1u);
                         } else {
                             gx_cross(acc, st, c);
@@ -1774,7 +1783,7 @@ __global__ __launch_bounds__(1024) void k_gx_scatter(const GxRec* __restrict__ r
             const uint2 q0 = tile[3 * i], q1 = tile[3 * i + 1], q2 = tile[3 * i + 2];
             const int b = (int)q0.x >> shift;
             const size_t at = 3 * (size_t)(cur[b] + (i - loff[b]));
-            dst[at] = q0;
+            dst[at] = q0;   // ordinary stores: L2 merges a run's pieces into whole lines
             dst[at + 1] = q1;
             dst[at + 2] = q2;
         }
