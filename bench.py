@@ -154,25 +154,28 @@ def main():
         return o
 
     def timed(o, steps, warmup):
-        """(wall ms per call, event ms per call, walk-kernel event ms per launch or None)."""
+        """(wall ms per call, event ms per call, walk-kernel event ms per launch or None,
+        median event ms of one call)."""
         for _ in range(warmup):
             mesh.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=o)
         torch.cuda.synchronize()
         mesh.walk_time()   # drop the warm-up launches
         stream = torch.cuda.current_stream()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]   # one between every two calls
         w0 = time.perf_counter()
-        ev0.record(stream)
-        for _ in range(steps):
+        evs[0].record(stream)
+        for j in range(steps):
             mesh.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=o)
-        ev1.record(stream)
+            evs[j + 1].record(stream)
         torch.cuda.synchronize()
         w1 = time.perf_counter()
         wms, wn = mesh.walk_time()
-        return (w1 - w0) * 1e3 / steps, ev0.elapsed_time(ev1) / steps, (wms / wn if wn else None)
+        per = sorted(evs[j].elapsed_time(evs[j + 1]) for j in range(steps))
+        return ((w1 - w0) * 1e3 / steps, evs[0].elapsed_time(evs[-1]) / steps, (wms / wn if wn else None),
+                per[steps // 2] if steps % 2 else 0.5 * (per[steps // 2 - 1] + per[steps // 2]))
 
     main_o = opts_for(debug=1 | (4 if base.kernel != sg.KERNEL_PLAIN else 0))
-    ms_step, ms_call, ms_walk = timed(main_o, args.steps, args.warmup)
+    ms_step, ms_call, ms_walk, ms_call_median = timed(main_o, args.steps, args.warmup)
     # dominant kernel: the persistent walk (events the library records around it), or the plain kernel
     ms_kernel = ms_walk if ms_walk is not None else ms_call
     gpu_cross = int(out["n_cross"].sum().item())
@@ -181,7 +184,7 @@ def main():
         f"(events {ms_kernel:.3f} ms), GPU crossings {gpu_cross}, status ok {n_ok}/{n}")
     plain = None
     if base.kernel != sg.KERNEL_PLAIN and not args.no_plain:
-        ms_p, ms_pk, _ = timed(opts_for(kernel=sg.KERNEL_PLAIN, debug=1), max(3, args.steps // 4), 1)
+        ms_p, ms_pk, _, _ = timed(opts_for(kernel=sg.KERNEL_PLAIN, debug=1), max(3, args.steps // 4), 1)
         plain = {"ms_per_call": ms_p, "events_ms": ms_pk}
         log(f"plain one-ray-per-lane kernel: {ms_p:.3f} ms/call")
 
@@ -279,6 +282,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_median_events": ms_call_median,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
