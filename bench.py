@@ -304,6 +304,9 @@ def main():
                                                        and not args.walk_blocks) else None,
                      "kernel": "k_walk (persistent walk)" if ms_walk is not None else "k_exp_plain",
                      "algorithmic_bytes_per_launch": algo_bytes, "kernel_ms": ms_kernel,
+                     # the same launch counted at the 32-byte face record the walk gathers per crossing
+                     "frac_at_record_size": (32 * cross + (algo_bytes - 16 * cross)) / (ms_kernel * 1e-3) / 1e9
+                                            / HBM_PEAK_GBS,
                      "whole_call": {"ms": ms_call, "algorithmic_bytes": call_bytes,
                                     "achieved_GBs": call_bytes / (ms_call * 1e-3) / 1e9}},
         "cpu_baseline": cpu,
