@@ -36,7 +36,7 @@ def lib():
         L.or_mesh_mean_edge.restype = C.c_double
         L.or_mesh_theta.argtypes = [P, P]
         L.or_last_error.restype = C.c_char_p
-        L.or_exp_batch.argtypes = [P, C.c_int64, P, P, P, C.c_int32, P, P] + [P] * 12 + [C.c_int32]
+        L.or_exp_batch.argtypes = [P, C.c_int64, P, P, P, C.c_int32, P, P] + [P] * 13 + [C.c_int32]
         L.or_exp_batch.restype = C.c_int
         L.or_exp_trace.argtypes = [P, C.c_int32, P, P, P, C.c_int32] + [P] * 8
         L.or_exp_trace.restype = C.c_int32
@@ -113,13 +113,13 @@ class Mesh:
             f=np.zeros(n, np.int32), b=np.zeros((n, 3)), p=np.zeros((n, 3)), v=np.zeros((n, 3)),
             W=np.zeros((n, K, 3)), status=np.zeros(n, np.int32), n_cross=np.zeros(n, np.int32),
             hash=np.zeros(n, np.uint64), min_vdist=np.zeros(n), traced=np.zeros(n),
-            sigma=np.zeros(n, np.int8), n_bnd=np.zeros(n, np.int32))
+            sigma=np.zeros(n, np.int8), n_bnd=np.zeros(n, np.int32), bnd_margin=np.zeros(n))
         o = Opts(max_steps, vertex_snap, boundary_mode)
         rc = lib().or_exp_batch(
             self._h, n, _p(f), _p(b), _p(v), K, _p(W) if K else None, C.byref(o),
             _p(out["f"]), _p(out["b"]), _p(out["p"]), _p(out["v"]), _p(out["W"]) if K else None,
             _p(out["status"]), _p(out["n_cross"]), _p(out["hash"]), _p(out["min_vdist"]),
-            _p(out["traced"]), _p(out["sigma"]), _p(out["n_bnd"]), nthreads)
+            _p(out["traced"]), _p(out["sigma"]), _p(out["n_bnd"]), _p(out["bnd_margin"]), nthreads)
         if rc != 0:
             raise OracleError(rc, lib().or_last_error().decode())
         return out
@@ -205,3 +205,24 @@ class Mesh:
         if rc != 0:
             raise OracleError(rc, lib().or_last_error().decode())
         return gx, nvx
+
+    def exp_iterated(self, f, b, field, steps, **kw):
+        """The K-step exponential map of the paper's flow-matching objective (eq. fmobj, Sec. "MeshFlow"):
+        p^(k+1) = Exp_{p^(k)}(field(p^(k)) / K) for k = 0 .. K-1, the field re-evaluated at every
+        intermediate point.  Composed from `exp` alone; field(p [n,3], f [n], b [n,3]) -> v [n,3]
+        (float64).  Returns the last step's f, b, p, v, status, every intermediate point (`pts`, K of
+        them) and the smallest vertex distance over all steps (`min_vdist`)."""
+        f = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
+        n = f.shape[0]
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(n, 3)
+        o = self.exp(f, b, np.zeros((n, 3)), **kw)   # p^(0) = sum_k b_k x_k
+        p, b = o["p"], o["b"]
+        pts, mvd, status = [], np.full(n, np.inf), np.zeros(n, np.int32)
+        for _ in range(int(steps)):
+            v = np.asarray(field(p, f, b), dtype=np.float64) / float(steps)
+            o = self.exp(f, b, v, **kw)
+            f, b, p = o["f"], o["b"], o["p"]
+            mvd = np.minimum(mvd, o["min_vdist"])
+            status = np.where(status != 0, status, o["status"])
+            pts.append(p)
+        return dict(f=f, b=b, p=p, v=o["v"], status=status, pts=pts, min_vdist=mvd)

@@ -262,6 +262,7 @@ typedef struct {
     double min_vdist, traced;
     int8_t sigma;
     int32_t n_bnd;            /* boundary slides (whole or partial) and resumptions (hole avoidance) */
+    double bnd_margin;        /* smallest margin of a hole-avoidance decision (see hole_chain) */
     double d0[3], L;          /* start tangent (unit) and length, for the backward */
 } ray_out;
 
@@ -307,8 +308,12 @@ static double seg_point_dist(const double* a, const double* c, const double* x) 
     return norm3(q);
 }
 
-static void seg_update(const or_mesh* m, int64_t f, const double* a, const double* c, double* best) {
+/* Closest approach of segment a-c to the vertices of face f, except its
+ * local vertex `skipv` (-1: none), the boundary vertex a resumed segment
+ * starts from. */
+static void seg_update(const or_mesh* m, int64_t f, const double* a, const double* c, double* best, int skipv) {
     for (int k = 0; k < 3; k++) {
+        if (k == skipv) continue;
         double d = seg_point_dist(a, c, FX(m, f, k));
         if (d < *best) *best = d;
     }
@@ -378,11 +383,15 @@ static int fan_chain(const or_mesh* m, int64_t f, int32_t x0, int64_t* fan, int8
 }
 
 /* Is the projection w of d onto face g's plane inside g's corner at x0?
- * Returns the transport error |d . n_g| (the out-of-plane part), or -1. */
-static double corner_fit(const or_mesh* m, int64_t g, int32_t x0, const double* d, double* w) {
+ * Returns the transport error |d . n_g| (the out-of-plane part), or -1.
+ * *qual receives how far w is from the corner's nearer edge, as the sine of
+ * the angle between them (the margin of the inside test). */
+static double corner_fit(const or_mesh* m, int64_t g, int32_t x0, const double* d, double* w, double* qual) {
     const double* n = m->N + 3 * g;
     perp3(d, n, w);
-    if (!(norm3(w) > 1e-300)) return -1.0;
+    *qual = INFINITY;
+    double wl = norm3(w);
+    if (!(wl > 1e-300)) return -1.0;
     int lx = local_index(m, g, x0);
     double ea[3], eb[3], c[3];
     sub3(FX(m, g, (lx + 1) % 3), VX(m, x0), ea);
@@ -393,6 +402,8 @@ static double corner_fit(const or_mesh* m, int64_t g, int32_t x0, const double* 
     double sa = dot3(c, n);
     cross3(w, eb, c);
     double sb = dot3(c, n);
+    double qa = fabs(sa) / (norm3(ea) * wl), qb = fabs(sb) / (norm3(eb) * wl);
+    *qual = qa < qb ? qa : qb;
     if (sa * sab < 0.0 || sb * sab < 0.0) return -1.0;
     return fabs(dot3(d, n));
 }
@@ -424,10 +435,11 @@ static int hole_chain(const or_mesh* m, int32_t max_steps, int64_t* f, double* b
         sub3(VX(m, vb), VX(m, va), e);
         double dd = dot3(drec, e);
         int to_b = dd > 0.0 || (dd == 0.0 && vb < va);
+        double q = fabs(dd) / norm3(e);   /* the slide's end: margin |cos(d, edge)| */
+        if (q < out->bnd_margin) out->bnd_margin = q;
         lt = to_b ? lb : la;
         ls = to_b ? la : lb;
     }
-    out->min_vdist = 0.0;   /* a slide runs along an edge: the path touches the boundary */
     for (;;) {
         if (lt >= 0) {   /* sliding in fc from point b toward local vertex lt */
             out->n_bnd++;
@@ -470,7 +482,6 @@ static int hole_chain(const or_mesh* m, int32_t max_steps, int64_t* f, double* b
             lt = -1;
         }
         /* at boundary vertex x0 of face fc */
-        out->min_vdist = 0.0;
         int32_t y0 = -1, y1 = -1;
         int nfan = fan_chain(m, fc, x0, fan, rel, &y0, &y1, FANCAP);
         if (nfan == 0) {   /* not on a boundary (cannot happen on a checked mesh) */
@@ -479,13 +490,17 @@ static int hole_chain(const or_mesh* m, int32_t max_steps, int64_t* f, double* b
             *status = OR_RAY_BOUNDARY;
             return 0;
         }
-        double best = INFINITY, wb[3] = {0, 0, 0};
+        double best = INFINITY, second = INFINITY, wb[3] = {0, 0, 0};
         int ib = -1;
         for (int i = 0; i < nfan; i++) {
-            double w[3];
-            double err = corner_fit(m, fan[i], x0, drec, w);
-            if (err >= 0.0 && err < best) { best = err; ib = i; memcpy(wb, w, sizeof w); }
+            double w[3], qual;
+            double err = corner_fit(m, fan[i], x0, drec, w, &qual);
+            /* the face choice: margins of every inside test and best against runner-up */
+            if (qual < out->bnd_margin) out->bnd_margin = qual;
+            if (err >= 0.0 && err < best) { second = best; best = err; ib = i; memcpy(wb, w, sizeof w); }
+            else if (err >= 0.0 && err < second) second = err;
         }
+        if (second - best < out->bnd_margin) out->bnd_margin = second - best;
         if (!first && *steps >= max_steps) {
             perp3(drec, m->N + 3 * fc, d); unit3(d);
             *f = fc;
@@ -516,6 +531,7 @@ static int hole_chain(const or_mesh* m, int32_t max_steps, int64_t* f, double* b
             sub3(VX(m, y1), VX(m, x0), u1); unit3(u1);
             double c0 = dot3(drec, u0), c1 = dot3(drec, u1);
             end = (c1 > c0 || (c1 == c0 && y1 < y0)) ? 1 : 0;
+            if (fabs(c1 - c0) < out->bnd_margin) out->bnd_margin = fabs(c1 - c0);
         }
         *sigma *= end ? rel[nfan - 1] : rel[0];
         fc = end ? fan[nfan - 1] : fan[0];
@@ -553,6 +569,7 @@ static void exp_one(const or_mesh* m, int32_t f0, const double* b0, const double
     out->f = f0;
     out->sigma = 1;
     out->min_vdist = INFINITY;
+    out->bnd_margin = INFINITY;
     out->hash = 14695981039346656037ull;
     double wn[64];
     double snap = o ? o->vertex_snap : 1e-10;
@@ -600,6 +617,7 @@ static void exp_one(const or_mesh* m, int32_t f0, const double* b0, const double
     out->L = L;
 
     int atv = -1, skip = -1, sigma = 1;
+    int resume_v = -1;   /* local vertex a hole-avoidance resumption starts from (not a vertex passage) */
     int nz = (b[0] == 0.0) + (b[1] == 0.0) + (b[2] == 0.0);
     double bd[3];
     if (nz == 2) {
@@ -637,7 +655,7 @@ static void exp_one(const or_mesh* m, int32_t f0, const double* b0, const double
             clamp_renorm(b);
             traced += rem;
             bary_pos(m, f, b, p_new);
-            seg_update(m, f, p_prev, p_new, &out->min_vdist);
+            seg_update(m, f, p_prev, p_new, &out->min_vdist, resume_v);
             rem = 0.0;
             break;
         }
@@ -649,7 +667,8 @@ static void exp_one(const or_mesh* m, int32_t f0, const double* b0, const double
         traced += ts;
         steps++;
         bary_pos(m, f, b, p_new);
-        seg_update(m, f, p_prev, p_new, &out->min_vdist);
+        seg_update(m, f, p_prev, p_new, &out->min_vdist, resume_v);
+        resume_v = -1;
         int e = (ks + 1) % 3, i = e, j = (e + 1) % 3;
 
         int vloc = -1;
@@ -666,6 +685,7 @@ static void exp_one(const or_mesh* m, int32_t f0, const double* b0, const double
                                          tb, 0, i, j, -1);
                 vec_rebuild(m->N + 3 * f, sigma, d, K, psi, wn, Wout);
                 if (!resumed) break;
+                resume_v = atv;
                 skip = -1;
                 continue;
             }
@@ -718,6 +738,7 @@ static void exp_one(const or_mesh* m, int32_t f0, const double* b0, const double
                                          tb, 1, -1, -1, x0id);
                 vec_rebuild(m->N + 3 * f, sigma, d, K, psi, wn, Wout);
                 if (!resumed) break;
+                resume_v = atv;
                 skip = -1;
                 continue;
             }
@@ -819,7 +840,7 @@ typedef struct {
     const int32_t* f; const double* b; const double* v; int32_t K; const double* W; const or_opts* o;
     int32_t* f_out; double* b_out; double* p_out; double* v_out; double* W_out;
     int32_t* status; int32_t* n_cross; uint64_t* seq_hash; double* min_vdist; double* traced; int8_t* sigma_end;
-    int32_t* n_bnd;
+    int32_t* n_bnd; double* bnd_margin;
     /* backward */
     int mode;   /* 0 forward, 1 EP, 2 GFD */
     double eps_v, eps_p;
@@ -848,6 +869,7 @@ static void fwd_one(const job_t* J, int64_t i) {
     if (J->traced) J->traced[i] = r.traced;
     if (J->sigma_end) J->sigma_end[i] = r.sigma;
     if (J->n_bnd) J->n_bnd[i] = r.n_bnd;
+    if (J->bnd_margin) J->bnd_margin[i] = r.bnd_margin;
 }
 
 static void* worker(void* arg) {
@@ -887,7 +909,7 @@ int or_exp_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
                  int32_t K, const double* W, const or_opts* o, int32_t* f_out, double* b_out,
                  double* p_out, double* v_out, double* W_out, int32_t* status, int32_t* n_cross,
                  uint64_t* seq_hash, double* min_vdist, double* traced, int8_t* sigma_end, int32_t* n_bnd,
-                 int32_t nthreads) {
+                 double* bnd_margin, int32_t nthreads) {
     if (!m || n < 0 || K < 0 || K > 64 || (n > 0 && (!f || !b || !v || !f_out || !b_out || !p_out || !v_out || !status)) ||
         (K > 0 && n > 0 && (!W || !W_out))) {
         set_err("bad arguments");
@@ -897,7 +919,7 @@ int or_exp_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
     J.m = m; J.n = n; J.f = f; J.b = b; J.v = v; J.K = K; J.W = W; J.o = o;
     J.f_out = f_out; J.b_out = b_out; J.p_out = p_out; J.v_out = v_out; J.W_out = W_out;
     J.status = status; J.n_cross = n_cross; J.seq_hash = seq_hash; J.min_vdist = min_vdist;
-    J.traced = traced; J.sigma_end = sigma_end; J.n_bnd = n_bnd;
+    J.traced = traced; J.sigma_end = sigma_end; J.n_bnd = n_bnd; J.bnd_margin = bnd_margin;
     return run_job(&J, nthreads);
 }
 

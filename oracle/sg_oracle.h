@@ -48,7 +48,13 @@ const char* or_last_error(void);
  * the face it was in), traced (total traced length), sigma_end (+1/-1, the
  * end face's normal relative to the orientation carried along the path),
  * n_bnd (boundary slides, whole or partial, and resumptions under hole
- * avoidance).
+ * avoidance), bnd_margin (the smallest margin of the decisions hole
+ * avoidance took: |cos| of the angle between the recorded direction and an
+ * edge it slid along, the sine margin of each corner test at a boundary
+ * vertex, the gap between the smallest and the next transport error, and
+ * the cosine gap of a slide's end choice; infinity if none).  min_vdist
+ * counts the straight parts of the path only: slides run along boundary
+ * edges, and a resumption starts at its boundary vertex by construction.
  * Any output pointer except f_out/b_out/p_out/v_out/status may be NULL.
  * nthreads <= 0 uses every online core. */
 int or_exp_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
@@ -56,7 +62,7 @@ int or_exp_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b,
                  int32_t* f_out, double* b_out, double* p_out, double* v_out,
                  double* W_out, int32_t* status, int32_t* n_cross, uint64_t* seq_hash,
                  double* min_vdist, double* traced, int8_t* sigma_end, int32_t* n_bnd,
-                 int32_t nthreads);
+                 double* bnd_margin, int32_t nthreads);
 
 /* One ray with its event list: for each edge crossing or vertex passage,
  * kind (0 edge, 1 vertex, 2 boundary slide, 3 resumption after a slide), the

@@ -322,19 +322,19 @@ def exp_with_grad(mesh, f, b, v, X=None, mode=BWD_GFD, W=None, **opts_kw):
 def exp_iterated(mesh, f, b, field, steps, **opts_kw):
     """Exp applied `steps` times with a vector field re-evaluated at each intermediate point:
     p_{k+1} = Exp_{p_k}(field(p_k, f_k, b_k) / steps) (the K-step map of the paper's flow
-    matching, Sec. "MeshFlow").  field(p [n,3], f [n], b [n,3]) -> v [n,3] float32 tensor.
-    Differentiable (exp_with_grad, mode BWD_GFD by default): gradients flow through the field's
-    outputs and, step to step, through the start points (the end barycentrics' cotangents).
+    matching, eq. fmobj in Sec. "MeshFlow").  field(p [n,3], f [n], b [n,3]) -> v [n,3] float32
+    tensor.  Differentiable (exp_with_grad, mode BWD_GFD by default): gradients flow through the
+    field's outputs and, step to step, through the start points (the end barycentrics'
+    cotangents); p_0 = sum_k b_k x_k is itself a library call (a zero-length Exp), so with
+    BWD_GFD the field's dependence on the start point reaches b.
     Returns (p, f, b) of the last step and the list of intermediate points."""
     import torch
     mode = opts_kw.pop("mode", BWD_GFD)
-    dev = f.device
+    n = f.shape[0]
+    zero = torch.zeros(n, 3, dtype=torch.float32, device=f.device)
+    p, f, b, _, _ = exp_with_grad(mesh, f, b.contiguous(), zero, mode=mode, **opts_kw)
     pts = []
-    p = None
     for _ in range(int(steps)):
-        if p is None:
-            out = mesh.exp(f, b, torch.zeros(f.shape[0], 3, dtype=torch.float32, device=dev), **opts_kw)
-            p = out["p"]
         v = field(p, f, b) / float(steps)
         p, f, b, _, _ = exp_with_grad(mesh, f, b.contiguous(), v.contiguous().float(), mode=mode, **opts_kw)
         pts.append(p)

@@ -12,6 +12,10 @@ from __future__ import annotations
 import numpy as np
 
 NEAR_VERTEX = 1e-6
+# A hole-avoidance decision (which end of a boundary edge to slide to, which
+# fan face to resume in) taken with a margin below this may go either way in
+# float32: the float64 oracle reports the smallest margin per ray.
+BOUNDARY_TIE = 1e-5
 
 
 def _angle(a, b):
@@ -20,20 +24,49 @@ def _angle(a, b):
     return np.arctan2(np.linalg.norm(c, axis=-1), np.einsum("...c,...c->...", a, b))
 
 
-def report(o, g, me, K=0):
-    """Returns a dict of parity statistics (o: oracle dict, g: GPU dict of numpy arrays)."""
+def _unfold_about_edge(X, F, fg, fo, w):
+    """Vectors w (K x 3) tangent to face fg, unfolded about the edge fg shares
+    with face fo into fo's plane (the rotation about the edge that takes fg's
+    inward edge normal to fo's outward one); None if the faces share no edge."""
+    common = [v for v in F[fg] if v in F[fo]]
+    if len(common) != 2:
+        return None
+    a, b = X[common[0]].astype(np.float64), X[common[1]].astype(np.float64)
+    u = (b - a) / np.linalg.norm(b - a)
+
+    def inward(f):
+        c = X[[v for v in F[f] if v not in common][0]].astype(np.float64) - a
+        m = c - (c @ u) * u
+        return m / np.linalg.norm(m)
+    mg, mo = inward(fg), -inward(fo)
+    src = np.stack([u, mg, np.cross(u, mg)])
+    dst = np.stack([u, mo, np.cross(u, mo)])
+    return (w @ src.T) @ dst
+
+
+def report(o, g, me, K=0, mesh=None):
+    """Returns a dict of parity statistics (o: oracle dict, g: GPU dict of numpy
+    arrays).  With mesh = (X, F), transported vectors of rays that end in a
+    face next to the oracle's (an endpoint on their shared edge) are compared
+    after unfolding the GPU's vector about that edge."""
     err = np.linalg.norm(g["p"].astype(np.float64) - o["p"], axis=1)
     tol = 1e-4 * me
     near = o["min_vdist"] < NEAR_VERTEX
+    if "bnd_margin" in o:
+        near = near | (o["bnd_margin"] < BOUNDARY_TIE)
     bad = err > tol
     face_mis = g["f"] != o["f"]
     # an endpoint within tolerance of an edge may be reported in either face
     on_edge = (np.min(o["b"], axis=1) * me < 2 * tol) | (np.min(g["b"], axis=1) * me < 2 * tol)
-    out = dict(n=len(err), tol=tol, frac_ok=1.0 - bad.mean(), bad_not_near=int(np.sum(bad & ~near)),
+    out = dict(n=len(err), tol=tol, frac_ok=1.0 - bad.mean(), n_near=int(near.sum()),
+               bad_not_near=int(np.sum(bad & ~near)),
                face_mis_unexplained=int(np.sum(face_mis & ~near & ~(on_edge & ~bad))),
                status_mis=int(np.sum((g["status"] != o["status"]) & ~near)),
                err_max_far=float(err[~near].max()) if np.any(~near) else 0.0,
                err_p999=float(np.percentile(err, 99.9)), err_median=float(np.median(err)))
+    if "n_bnd" in o:
+        out["n_slid"] = int(np.sum(o["n_bnd"] > 0))
+        out["n_slid_compared"] = int(np.sum((o["n_bnd"] > 0) & ~near))
     # an endpoint on an edge may sit in either face: the sequences then differ by that last crossing
     edge_ok = on_edge & ~bad
     if "n_cross" in g and g["n_cross"] is not None:
@@ -42,20 +75,41 @@ def report(o, g, me, K=0):
         edge_ok = edge_ok & (dc <= 1)
     if "hash" in g and g["hash"] is not None:
         out["hash_mis_far"] = int(np.sum((g["hash"].astype(np.uint64) != o["hash"]) & ~near & ~edge_ok))
+    # vectors: same end face, or (with the mesh) the GPU's unfolded into the oracle's face
+    gv = g["v"].astype(np.float64)
+    gw = g["W"].astype(np.float64) if K else None
+    same = (g["f"] == o["f"]) & ~near
+    unfolded = np.zeros(len(err), bool)
+    skipped = 0
+    if mesh is not None:
+        X, F = mesh
+        for i in np.where((g["f"] != o["f"]) & ~near & ~bad)[0]:
+            w = np.concatenate([gv[i:i + 1], gw[i] if K else np.zeros((0, 3))])
+            r = _unfold_about_edge(X, F, g["f"][i], o["f"][i], w)
+            if r is None:
+                skipped += 1
+                continue
+            gv[i] = r[0]
+            if K:
+                gw[i] = r[1:]
+            unfolded[i] = True
+        out["vec_unfolded"] = int(unfolded.sum())
+        out["vec_skipped"] = skipped
+    cmp = same | unfolded
     if K:
-        same = (g["f"] == o["f"]) & ~near
-        gw, ow = g["W"].astype(np.float64), o["W"]
+        ow = o["W"]
         ang = _angle(gw, ow)
-        out["W_angle_max"] = float(ang[same].max()) if same.any() else 0.0
-        out["W_norm_err"] = float(np.abs(np.linalg.norm(gw, axis=2) - np.linalg.norm(ow, axis=2))[same].max()) if same.any() else 0.0
-    vang = _angle(g["v"].astype(np.float64), o["v"])
-    sel = (g["f"] == o["f"]) & ~near & (np.linalg.norm(o["v"], axis=1) > 0)
+        out["W_angle_max"] = float(ang[cmp].max()) if cmp.any() else 0.0
+        out["W_angle_max_unfolded"] = float(ang[unfolded].max()) if unfolded.any() else 0.0
+        out["W_norm_err"] = float(np.abs(np.linalg.norm(gw, axis=2) - np.linalg.norm(ow, axis=2))[cmp].max()) if cmp.any() else 0.0
+    vang = _angle(gv, o["v"])
+    sel = cmp & (np.linalg.norm(o["v"], axis=1) > 0)
     out["v_angle_max"] = float(vang[sel].max()) if sel.any() else 0.0
     return out
 
 
-def assert_parity(o, g, me, K=0, label=""):
-    s = report(o, g, me, K)
+def assert_parity(o, g, me, K=0, label="", mesh=None):
+    s = report(o, g, me, K, mesh)
     msg = f"{label}: {s}"
     assert s["frac_ok"] >= 0.999, msg
     assert s["bad_not_near"] == 0, msg
@@ -68,6 +122,8 @@ def assert_parity(o, g, me, K=0, label=""):
     if K:
         assert s["W_angle_max"] <= 1e-4, msg
     assert s["v_angle_max"] <= 1e-4, msg
+    if mesh is not None:
+        assert s["vec_skipped"] == 0, msg
     return s
 
 
@@ -95,6 +151,8 @@ def grad_report(o_exp, og_v, og_b, gg_v, gg_b, me, margin=2e-2, tol=1e-3):
         eb[nz] = np.linalg.norm(d(gg_b[nz]) - d(og_b[nz]), axis=1) / np.maximum(
             np.linalg.norm(d(og_b[nz]), axis=1), 1e-30)
     m = o_exp["min_vdist"] > margin * me
+    if "n_bnd" in o_exp:   # a boundary slide is not a smooth part of the map
+        m = m & (o_exp["n_bnd"] == 0)
     return dict(n=len(ev), n_margin=int(m.sum()), v_ok=float(np.mean(ev[m] <= tol)) if m.any() else 1.0,
                 b_ok=float(np.mean(eb[m] <= tol)) if m.any() else 1.0, v_med=float(np.median(ev)),
                 b_med=float(np.median(eb)), v_all_ok=float(np.mean(ev <= tol)), finite=bool(

@@ -466,7 +466,7 @@ def test_backward_hole_avoidance(torch, mode):
     o = om.exp(r["f"], r["b"], r["v"], boundary_mode=1)
     assert (o["n_bnd"] > 0).sum() > 300
     check(torch, X, F, r, g, mode, boundary_mode=1)
-    keep = (o["min_vdist"] > 1e-2 * om.mean_edge) & (o["status"] == 0)
+    keep = (o["min_vdist"] > 1e-2 * om.mean_edge) & (o["status"] == 0) & (o["n_bnd"] == 0)
     gk = np.where(keep[:, None], g, 0.0).astype(np.float32)
     ref, nvx = om.gradx(r["f"], r["b"], r["v"], gk, boundary_mode=1)
     assert np.all(nvx[o["n_bnd"] > 0] == -1)
@@ -552,15 +552,76 @@ def test_autograd_all_outputs_and_iterated(torch):
                              v_out=out["v"], g_b=cs[1], g_v=cs[2], g_W=cs[3])
     torch.cuda.synchronize()
     assert torch.allclose(v.grad, gv) and torch.allclose(b.grad, gb) and torch.allclose(W.grad, gW)
-    # iterated: a rotating field, two steps; finite gradients to its parameter
-    theta = torch.tensor(0.3, device=dev, requires_grad=True)
-    axis = torch.tensor([0.0, 0.0, 1.0], device=dev)
-    field = lambda pp, ff, bb: theta * torch.cross(axis.expand_as(pp), pp, dim=1)
-    b0 = torch.from_numpy(r["b"].astype(np.float32)).to(dev)
-    (pK, fK, bK), pts = sg.exp_iterated(gm, f, b0, field, 2)
-    assert len(pts) == 2 and torch.isfinite(pK).all()
-    pK.sum().backward()
-    assert torch.isfinite(theta.grad)
+
+
+def test_iterated_exp_against_oracle(torch):
+    """The K-step map of eq. fmobj (Sec. "MeshFlow"), K = 3, through exp_iterated
+    (GFD): end points against the oracle's composition (tests/test_oracle_iterated.py
+    pins it), and the autograd gradients in the field's per-query parameters and
+    in the start barycentrics against float64 central differences (h = 1e-6) of
+    that composition, at relative error 1e-3 on queries whose paths keep
+    2e-2 mean edges from every vertex at every step."""
+    from paper_2603_15780_amd import sg
+    from test_oracle_iterated import field_factory
+    X, F = CF.mesh_config(1)
+    X, F = M.canonical(M.sh_displace(X.astype(np.float64), 6, 0.15, np.random.default_rng(33)), F)
+    om = oracle.Mesh(X, F)
+    gm = sg.Mesh(X, F)
+    rng = np.random.default_rng(95)
+    n, K, H = 4096, 3, 1e-6
+    r = random_rays(X, F, n, rng, uniform_len(0.0, 1.0))
+    theta = (rng.normal(size=(n, 2)) * [0.5, 0.5]).astype(np.float32).astype(np.float64)
+    c1 = rng.normal(size=3).astype(np.float32).astype(np.float64)
+    c2 = rng.normal(size=3)
+    c2 = (c2 / np.linalg.norm(c2)).astype(np.float32).astype(np.float64)
+    o0 = np.zeros(3)
+    gup = rng.standard_normal((n, 3))
+    db = rng.normal(size=(n, 3))
+    db -= db.mean(1)[:, None]
+    # GPU: loss = sum_i g_i . p_K,i
+    dev = torch.device("cuda:0")
+    th = torch.tensor(theta, dtype=torch.float32, device=dev, requires_grad=True)
+    tc1 = torch.tensor(c1, dtype=torch.float32, device=dev)
+    tc2 = torch.tensor(c2, dtype=torch.float32, device=dev)
+    field = lambda pp, ff, bb: th[:, 0:1] * tc1 + th[:, 1:2] * torch.cross(tc2.expand_as(pp), pp, dim=1)
+    f = torch.from_numpy(r["f"]).to(dev)
+    b = torch.from_numpy(r["b"].astype(np.float32)).to(dev).requires_grad_(True)
+    eps = float(np.float32(5e-3 * om.mean_edge))
+    (pK, fK, bK), pts = sg.exp_iterated(gm, f, b, field, K, eps_v=eps, eps_p=eps)
+    assert len(pts) == K
+    (pK * torch.tensor(gup, dtype=torch.float32, device=dev)).sum().backward()
+    torch.cuda.synchronize()
+    g_theta = th.grad.double().cpu().numpy()
+    g_b = b.grad.double().cpu().numpy()
+    # oracle composition (same float32 start barycentrics, same field)
+    fld = field_factory(theta, c1, c2, o0)
+    it = om.exp_iterated(r["f"], r["b"].astype(np.float32), fld, K)
+    err = np.linalg.norm(pK.detach().double().cpu().numpy() - it["p"], axis=1)
+    far = it["min_vdist"] > 1e-6
+    assert np.mean(err <= 1e-4 * om.mean_edge) >= 0.999 and np.all(err[far] <= 1e-4 * om.mean_edge), err.max()
+    assert np.array_equal(fK.cpu().numpy()[far & (err < 1e-6)], it["f"][far & (err < 1e-6)])
+    keep = (it["status"] == 0) & (it["min_vdist"] > 2e-2 * om.mean_edge) & (r["b"].min(1) > 1e-3)
+    assert keep.sum() > 1000, keep.sum()
+    # central differences of the oracle's composition, per query (queries are independent)
+    fd_theta = np.zeros((n, 2))
+    for q in range(2):
+        tp, tm = theta.copy(), theta.copy()
+        tp[:, q] += H
+        tm[:, q] -= H
+        dp = (om.exp_iterated(r["f"], r["b"].astype(np.float32), field_factory(tp, c1, c2, o0), K)["p"]
+              - om.exp_iterated(r["f"], r["b"].astype(np.float32), field_factory(tm, c1, c2, o0), K)["p"]) / (2 * H)
+        fd_theta[:, q] = (dp * gup).sum(1)
+    b0 = r["b"].astype(np.float32).astype(np.float64)
+    b0 /= b0.sum(1)[:, None]
+    dp = (om.exp_iterated(r["f"], b0 + H * db, fld, K)["p"] - om.exp_iterated(r["f"], b0 - H * db, fld, K)["p"]) / (2 * H)
+    fd_b = (dp * gup).sum(1)
+    rel_t = np.linalg.norm(g_theta - fd_theta, axis=1) / np.maximum(np.linalg.norm(fd_theta, axis=1), 1e-12)
+    got_b = (g_b * db).sum(1)
+    rel_b = np.abs(got_b - fd_b) / np.maximum(np.abs(fd_b), 1e-3 * np.abs(fd_b).max())
+    print(dict(n_keep=int(keep.sum()), t_med=float(np.median(rel_t[keep])), t_ok=float(np.mean(rel_t[keep] <= 1e-3)),
+               b_med=float(np.median(rel_b[keep])), b_ok=float(np.mean(rel_b[keep] <= 1e-3))))
+    assert np.mean(rel_t[keep] <= 1e-3) >= 0.999
+    assert np.mean(rel_b[keep] <= 1e-3) >= 0.999
 
 
 def test_transport_back_inverts_transport(torch):

@@ -54,7 +54,7 @@ def test_config1_parity(torch, kernel):
     r = CF.rays_config(1, X, F)
     om, gm, o, g = both(torch, X, F, r, kernel=kernel)
     assert abs(gm.info()["mean_edge"] - om.mean_edge) < 1e-12
-    s = assert_parity(o, g, om.mean_edge, K=1, label="config1")
+    s = assert_parity(o, g, om.mean_edge, mesh=(X, F), K=1, label="config1")
     assert s["hash_mis_far"] == 0
 
 
@@ -80,7 +80,7 @@ def test_config2_full_batch_sampled(torch, kernel):
     om = oracle.Mesh(X, F)
     o = om.exp(r["f"][rows], r["b"][rows], r["v"][rows], r["W"][rows])
     gs = {k: (a[rows] if a is not None else None) for k, a in g.items()}
-    s = assert_parity(o, gs, om.mean_edge, K=2, label="config2")
+    s = assert_parity(o, gs, om.mean_edge, mesh=(X, F), K=2, label="config2")
     print("config2", s)
     # the rest of the batch: properties that hold at any size
     L = np.linalg.norm(r["v"].astype(np.float64), axis=1)
@@ -96,11 +96,11 @@ def test_displaced_and_torus(torch):
     X, F = M.canonical(M.sh_displace(X, 8, 0.15, np.random.default_rng(11)), F)
     r = random_rays(X, F, 20000, np.random.default_rng(12), uniform_len(0.0, 2.0), K=2)
     om, gm, o, g = both(torch, X, F, r)
-    assert_parity(o, g, om.mean_edge, K=2, label="displaced")
+    assert_parity(o, g, om.mean_edge, mesh=(X, F), K=2, label="displaced")
     X, F = M.canonical(*M.torus_grid(120, 40, 0.2, np.random.default_rng(13)))
     r = random_rays(X, F, 20000, np.random.default_rng(14), uniform_len(0.0, 3.0), K=1)
     om, gm, o, g = both(torch, X, F, r)
-    assert_parity(o, g, om.mean_edge, K=1, label="torus")
+    assert_parity(o, g, om.mean_edge, mesh=(X, F), K=1, label="torus")
 
 
 def test_flat_plane_closed_form(torch):
@@ -207,7 +207,7 @@ def test_boundary_stop(torch, kernel):
     r = random_rays(X, F, 5000, np.random.default_rng(4), uniform_len(0.5, 3.0), K=1)
     om, gm, o, g = both(torch, X, F, r, kernel=kernel)
     assert np.any(o["status"] == 2)
-    assert_parity(o, g, om.mean_edge, K=1, label="holes")
+    assert_parity(o, g, om.mean_edge, mesh=(X, F), K=1, label="holes")
 
 
 def test_multi_mesh_offsets(torch):
@@ -323,7 +323,7 @@ def test_mixed_orientation(torch):
     r = random_rays(X, F2, 20000, np.random.default_rng(4), uniform_len(0.0, 2.0), K=2)
     for kernel in (1, 2, 3):
         om, gm, o, g = both(torch, X, F2, r, kernel=kernel)
-        assert_parity(o, g, om.mean_edge, K=2, label=f"mixed orientation, kernel {kernel}")
+        assert_parity(o, g, om.mean_edge, mesh=(X, F2), K=2, label=f"mixed orientation, kernel {kernel}")
 
 
 def test_config3_many_meshes_one_launch(torch):
@@ -456,7 +456,7 @@ def test_config5_full_batch_sampled(torch, config5):
     om = oracle.Mesh(X, F)
     o = om.exp(r["f"][rows], r["b"][rows], r["v"][rows], r["W"][rows])
     gs = {k: (a[rows] if a is not None else None) for k, a in g.items()}
-    s = assert_parity(o, gs, om.mean_edge, K=2, label="config5")
+    s = assert_parity(o, gs, om.mean_edge, mesh=(X, F), K=2, label="config5")
     assert s["hash_mis_far"] == 0
 
 
@@ -468,7 +468,7 @@ def test_non_orientable_surfaces(torch, kernel):
         X, F = M.canonical(X, F)
         r = random_rays(X, F, 6000, np.random.default_rng(41), uniform_len(0.0, 4.0), K=2)
         om, gm, o, g = both(torch, X, F, r, kernel=kernel)
-        s = assert_parity(o, g, om.mean_edge, K=2, label="non-orientable")
+        s = assert_parity(o, g, om.mean_edge, mesh=(X, F), K=2, label="non-orientable")
         assert s["hash_mis_far"] == 0
 
 
@@ -490,7 +490,10 @@ def _holed_meshes():
 def test_hole_avoidance_parity(torch, kernel):
     """boundary_mode = SG_BOUNDARY_AVOID: rays slide along boundary edges and
     resume straight (Sec. 4); endpoints, faces, step counts, face-sequence
-    hashes and transported vectors match the oracle's."""
+    hashes and transported vectors match the oracle's, rays that slid
+    included.  Excused are only rays whose straight parts pass within 1e-6 of
+    a vertex, or one of whose boundary decisions (slide end, resumption face)
+    the oracle took with a margin below 1e-5 (parity.BOUNDARY_TIE)."""
     from paper_2603_15780_amd import sg
     for mi, (X, F) in enumerate(_holed_meshes()):
         r = random_rays(X, F, 6000, np.random.default_rng(50 + mi), uniform_len(0.0, 4.0), K=2)
@@ -498,7 +501,9 @@ def test_hole_avoidance_parity(torch, kernel):
         o = om.exp(r["f"], r["b"], r["v"], r["W"], boundary_mode=1)
         assert (o["n_bnd"] > 0).sum() > 500
         g = run(torch, sg.Mesh(X, F), r, kernel=kernel, boundary_mode=sg.BOUNDARY_AVOID)
-        s = assert_parity(o, g, om.mean_edge, K=2, label=f"hole avoidance mesh {mi} kernel {kernel}")
+        s = assert_parity(o, g, om.mean_edge, mesh=(X, F), K=2, label=f"hole avoidance mesh {mi} kernel {kernel}")
+        print(mi, kernel, {k: s[k] for k in ("n_slid", "n_slid_compared", "n_near", "vec_unfolded")})
+        assert s["n_slid_compared"] >= 0.9 * s["n_slid"], s   # slid rays are compared, not excused
         assert s["hash_mis_far"] == 0
         assert np.all(g["status"] == 0)
 
@@ -599,4 +604,4 @@ def test_robustness_noise_and_slim_faces(torch, kind, level):
     r = random_rays(X, F, 8000, np.random.default_rng(97), uniform_len(0.0, 3.0), K=2)
     for kernel in (1, 2):
         om, gm, o, g = both(torch, X, F, r, kernel=kernel)
-        assert_parity(o, g, om.mean_edge, K=2, label=f"{kind} {level} kernel {kernel}")
+        assert_parity(o, g, om.mean_edge, mesh=(X, F), K=2, label=f"{kind} {level} kernel {kernel}")

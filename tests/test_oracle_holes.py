@@ -77,6 +77,9 @@ def test_length_ends_during_slide():
     assert np.abs(o["v"][0] - v).max() < 1e-12     # the recorded direction is reported
     assert o["n_bnd"][0] == 2                      # one whole slide (to (0, 0.5)), then part of the next
     assert abs(o["traced"][0] - (seg + 0.3)) < 1e-12
+    # the closest call of its decisions: the slide's end (|cos| of d to the vertical side), which
+    # equals the corner test's margin against the horizontal fan edge at (0, 0.5)
+    assert abs(o["bnd_margin"][0] - 0.2 / np.hypot(1.0, 0.2)) < 1e-12
 
 
 def test_slide_around_outer_corner():
@@ -145,7 +148,12 @@ def test_invariants_on_sphere_with_holes():
     for k in ("f", "p", "v", "W", "n_cross"):
         assert np.array_equal(o[k][same], o0[k][same]), k
     assert np.all(o["n_bnd"][same] == 0)
-    assert np.all(o["min_vdist"][o["n_bnd"] > 0] == 0.0)   # boundary rays are never in a gradient subset
+    # every ray that met the boundary reports the margin of its closest decision, the others none;
+    # the straight parts of slid rays keep their own distance to vertices
+    slid = o["n_bnd"] > 0
+    assert np.all(np.isinf(o["bnd_margin"][~slid])) and np.all(np.isfinite(o["bnd_margin"][slid]))
+    assert np.all(o["bnd_margin"][slid] >= 0.0)
+    assert np.median(o["min_vdist"][slid]) > 1e-4 * m.mean_edge
 
 
 def test_gradx_excludes_boundary_rays():
