@@ -48,12 +48,32 @@ def lib():
         L.or_transport_vjp.restype = C.c_int
         L.or_gradx_batch.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, C.c_int32]
         L.or_gradx_batch.restype = C.c_int
+        L.or_pi_exp_batch.argtypes = [P, C.c_int64, P, P, P, C.c_int32, P, P] + [P] * 9 + [C.c_int32]
+        L.or_pi_exp_batch.restype = C.c_int
+        L.or_pi_project.argtypes = [P, C.c_int64, P, P, P, P, P]
+        L.or_pi_project.restype = C.c_int
+        L.or_pi_ep_batch.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, C.c_int32]
+        L.or_pi_ep_batch.restype = C.c_int
+        L.or_pi_gfd_batch.argtypes = [P, C.c_int64, P, P, P, P, C.c_double, C.c_double, P, P, P, P, P, C.c_int32]
+        L.or_pi_gfd_batch.restype = C.c_int
         _lib = L
     return _lib
 
 
 class Opts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("vertex_snap", C.c_double), ("boundary_mode", C.c_int32)]
+
+
+class PiOpts(C.Structure):
+    _fields_ = [("step", C.c_double), ("max_steps", C.c_int32)]
+
+
+PI_STEP = 0.01   # default s of the projection-integration Exp
+
+
+def pi_max_steps(step):
+    """Default step cap of the projection-integration Exp: 8 / s."""
+    return int(np.ceil(8.0 / step))
 
 
 def _p(a):
@@ -226,3 +246,73 @@ class Mesh:
             status = np.where(status != 0, status, o["status"])
             pts.append(p)
         return dict(f=f, b=b, p=p, v=o["v"], status=status, pts=pts, min_vdist=mvd)
+
+    # ---- projection integration (appendix "Projection Integration Exp Map", Alg. projection-exp)
+    def _pi_opts(self, step, max_steps):
+        return PiOpts(float(step), int(pi_max_steps(step) if max_steps is None else max_steps))
+
+    def pi_exp(self, f, b, v, W=None, step=PI_STEP, max_steps=None, nthreads=0):
+        """The PI exponential map: f, b, p, v, W, status, n_steps, traced, margin (float64)."""
+        f = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
+        n = f.shape[0]
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(n, 3)
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(n, 3)
+        if W is None:
+            W = np.zeros((n, 0, 3))
+        W = np.ascontiguousarray(W, dtype=np.float64).reshape(n, -1, 3)
+        K = W.shape[1]
+        out = dict(f=np.zeros(n, np.int32), b=np.zeros((n, 3)), p=np.zeros((n, 3)), v=np.zeros((n, 3)),
+                   W=np.zeros((n, K, 3)), status=np.zeros(n, np.int32), n_steps=np.zeros(n, np.int32),
+                   traced=np.zeros(n), margin=np.zeros(n))
+        o = self._pi_opts(step, max_steps)
+        rc = lib().or_pi_exp_batch(self._h, n, _p(f), _p(b), _p(v), K, _p(W) if K else None, C.byref(o),
+                                   _p(out["f"]), _p(out["b"]), _p(out["p"]), _p(out["v"]),
+                                   _p(out["W"]) if K else None, _p(out["status"]), _p(out["n_steps"]),
+                                   _p(out["traced"]), _p(out["margin"]), nthreads)
+        if rc != 0:
+            raise OracleError(rc, lib().or_last_error().decode())
+        return out
+
+    def pi_project(self, q):
+        """project_to_mesh of points q [n,3]: (face, nearest point, barycentrics, margin)."""
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+        n = q.shape[0]
+        f = np.zeros(n, np.int32)
+        c = np.zeros((n, 3))
+        bc = np.zeros((n, 3))
+        mg = np.zeros(n)
+        rc = lib().or_pi_project(self._h, n, _p(q), _p(f), _p(c), _p(bc), _p(mg))
+        if rc != 0:
+            raise OracleError(rc, lib().or_last_error().decode())
+        return f, c, bc, mg
+
+    def pi_ep(self, f, b, v, g, step=PI_STEP, max_steps=None, nthreads=0):
+        f = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
+        n = f.shape[0]
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(n, 3)
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(n, 3)
+        g = np.ascontiguousarray(g, dtype=np.float64).reshape(n, 3)
+        gv = np.zeros((n, 3))
+        gb = np.zeros((n, 3))
+        o = self._pi_opts(step, max_steps)
+        rc = lib().or_pi_ep_batch(self._h, n, _p(f), _p(b), _p(v), C.byref(o), _p(g), _p(gv), _p(gb), nthreads)
+        if rc != 0:
+            raise OracleError(rc, lib().or_last_error().decode())
+        return gv, gb
+
+    def pi_gfd(self, f, b, v, g, eps_v, eps_p, step=PI_STEP, max_steps=None, nthreads=0):
+        f = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
+        n = f.shape[0]
+        b = np.ascontiguousarray(b, dtype=np.float64).reshape(n, 3)
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(n, 3)
+        g = np.ascontiguousarray(g, dtype=np.float64).reshape(n, 3)
+        gv = np.zeros((n, 3))
+        gb = np.zeros((n, 3))
+        Jv = np.zeros((n, 2, 2))
+        Jp = np.zeros((n, 2, 2))
+        o = self._pi_opts(step, max_steps)
+        rc = lib().or_pi_gfd_batch(self._h, n, _p(f), _p(b), _p(v), C.byref(o), float(eps_v), float(eps_p),
+                                   _p(g), _p(gv), _p(gb), _p(Jv), _p(Jp), nthreads)
+        if rc != 0:
+            raise OracleError(rc, lib().or_last_error().decode())
+        return dict(grad_v=gv, grad_b=gb, Jv=Jv, Jp=Jp)

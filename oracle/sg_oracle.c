@@ -264,6 +264,7 @@ typedef struct {
     int32_t n_bnd;            /* boundary slides (whole or partial) and resumptions (hole avoidance) */
     double bnd_margin;        /* smallest margin of a hole-avoidance decision (see hole_chain) */
     double d0[3], L;          /* start tangent (unit) and length, for the backward */
+    double pi_margin;         /* projection integration: smallest margin of a projection choice */
 } ray_out;
 
 static inline uint64_t fnv_face(uint64_t h, int32_t f) {
@@ -833,6 +834,215 @@ static void exp_one(const or_mesh* m, int32_t f0, const double* b0, const double
     out->sigma = (int8_t)sigma;
 }
 
+/* ------------------------------------------------------------ projection integration */
+/* The projection-integration (PI) exponential map the paper compares against
+ * (appendix "Projection Integration Exp Map", Alg. projection-exp): step the
+ * point along the current vector in the ambient space, project it back onto
+ * the mesh by scanning every face, rotate the vector from the old face's
+ * normal to the new one's, and add the length actually moved, until that
+ * length reaches |v|.
+ * Readings where the paper is silent or garbled:
+ *   - the step is p + s v with s a fraction of v (the printed formula), and
+ *     the loop runs while the accumulated length is below |v_t| (no clamp of
+ *     the last step, as printed); the algorithm's returned value is garbled
+ *     and read as the final point, face and rotated vector;
+ *   - v (and each extra vector) is first projected onto the start face's
+ *     plane, as for the straightest map;
+ *   - project_to_mesh returns the nearest point of the mesh: the minimiser of
+ *     the distance to each closed triangle, minimised over all faces.  Where
+ *     the nearest point lies inside a face this is the paper's rule (the
+ *     containing face at the smallest distance); where it lies on an edge or a
+ *     vertex, several faces attain it (ties within TIE_ABS of the smallest
+ *     distance, in units of the mesh's largest coordinate), and the face whose
+ *     normal is most nearly parallel to q - c is taken, then the smallest face
+ *     id;
+ *   - rotate_vector by alpha = acos(n . n') about n x n' is the rotation that
+ *     takes n to n' (Rodrigues' formula); parallel normals leave the vectors
+ *     unchanged, and so do opposite normals (the axis is undefined there);
+ *   - a ray still short of |v_t| after max_steps steps ends with status
+ *     MAXSTEPS.
+ * The per-ray margin reports how close the ray came to a different result:
+ * for each projection the gap between the smallest distance and the smallest
+ * distance outside the tie, and the alignment gap inside a tie; for the loop
+ * test, how far the traced length was from |v_t| before and after the last
+ * step (on a plane with 1/s an integer the step count is decided by rounding). */
+#define PI_TIE_ABS 1e-12
+
+/* Closest point c of the closed triangle f to q, its barycentrics bc (face
+ * vertex order) and the distance |q - c|.  Inside the triangle's prism c is
+ * the projection onto the plane; outside, the nearest point of a convex set
+ * lies on its boundary, so it is the nearest of the three edges' closest
+ * points. */
+static double tri_closest(const or_mesh* m, int64_t f, const double* q, double* c, double* bc) {
+    const double *x0 = FX(m, f, 0), *x1 = FX(m, f, 1), *x2 = FX(m, f, 2);
+    double e1[3], e2[3], w[3];
+    sub3(x1, x0, e1);
+    sub3(x2, x0, e2);
+    sub3(q, x0, w);
+    double g11 = dot3(e1, e1), g12 = dot3(e1, e2), g22 = dot3(e2, e2);
+    double r1 = dot3(w, e1), r2 = dot3(w, e2), det = g11 * g22 - g12 * g12;
+    double u = (g22 * r1 - g12 * r2) / det, v = (g11 * r2 - g12 * r1) / det;
+    if (u >= 0.0 && v >= 0.0 && u + v <= 1.0) {
+        bc[0] = 1.0 - u - v; bc[1] = u; bc[2] = v;
+        for (int k = 0; k < 3; k++) c[k] = x0[k] + u * e1[k] + v * e2[k];
+    } else {
+        double best = INFINITY;
+        for (int k = 0; k < 3; k++) {
+            const double* a = FX(m, f, k);
+            const double* b = FX(m, f, (k + 1) % 3);
+            double ab[3], aq[3], pt[3];
+            sub3(b, a, ab);
+            sub3(q, a, aq);
+            double t = dot3(aq, ab) / dot3(ab, ab);
+            if (t < 0.0) t = 0.0;
+            if (t > 1.0) t = 1.0;
+            for (int j = 0; j < 3; j++) pt[j] = a[j] + t * ab[j];
+            double dq[3];
+            sub3(q, pt, dq);
+            double d = norm3(dq);
+            if (d < best) {
+                best = d;
+                memcpy(c, pt, sizeof pt);
+                bc[k] = 1.0 - t; bc[(k + 1) % 3] = t; bc[(k + 2) % 3] = 0.0;
+            }
+        }
+    }
+    double dq[3];
+    sub3(q, c, dq);
+    return norm3(dq);
+}
+
+static double mesh_scale(const or_mesh* m) {
+    double s = 1.0;
+    for (int64_t i = 0; i < 3 * m->nv; i++) if (fabs(m->X[i]) > s) s = fabs(m->X[i]);
+    return s;
+}
+
+/* project_to_mesh: the face holding the nearest point of the mesh to q (a
+ * scan over every face), that point and its barycentrics.  *margin is lowered
+ * to this choice's margin. */
+static int64_t project_to_mesh(const or_mesh* m, double scale, const double* q, double* c, double* bc, double* margin) {
+    double dmin = INFINITY;
+    for (int64_t f = 0; f < m->nf; f++) {
+        double cf[3], bf[3];
+        double d = tri_closest(m, f, q, cf, bf);
+        if (d < dmin) dmin = d;
+    }
+    const double tie = PI_TIE_ABS * scale;
+    int64_t best = -1;
+    double best_al = -1.0, second_al = -1.0, outside = INFINITY;
+    for (int64_t f = 0; f < m->nf; f++) {
+        double cf[3], bf[3];
+        double d = tri_closest(m, f, q, cf, bf);
+        if (d > dmin + tie) {
+            if (d < outside) outside = d;
+            continue;
+        }
+        double dq[3];
+        sub3(q, cf, dq);
+        double al = d > 0.0 ? fabs(dot3(m->N + 3 * f, dq)) / d : 0.0;
+        if (al > best_al) {   /* ties in alignment keep the smaller face id */
+            second_al = best_al;
+            best_al = al; best = f;
+            memcpy(c, cf, sizeof cf);
+            memcpy(bc, bf, sizeof bf);
+        } else if (al > second_al) {
+            second_al = al;
+        }
+    }
+    double mg = outside - dmin;
+    if (second_al >= 0.0 && best_al - second_al < mg) mg = best_al - second_al;
+    if (mg < *margin) *margin = mg;
+    return best;
+}
+
+/* rotate_vector: the rotation taking unit normal n to unit normal n2, by the
+ * angle alpha = acos(n . n2) about the axis n x n2 (Rodrigues' formula). */
+static void rotate_normal_to_normal(const double* n, const double* n2, double* w) {
+    double k[3];
+    cross3(n, n2, k);
+    double sk = norm3(k);
+    if (!(sk > 0.0)) return;
+    scale3(k, 1.0 / sk);
+    double cs = dot3(n, n2);
+    if (cs > 1.0) cs = 1.0;
+    if (cs < -1.0) cs = -1.0;
+    double alpha = acos(cs);
+    double kw[3];
+    cross3(k, w, kw);
+    double kd = dot3(k, w), ca = cos(alpha), sa = sin(alpha);
+    for (int j = 0; j < 3; j++) w[j] = w[j] * ca + kw[j] * sa + k[j] * kd * (1.0 - ca);
+}
+
+static void pi_one(const or_mesh* m, int32_t f0, const double* b0, const double* v0, int K, const double* W0,
+                   const or_pi_opts* o, double scale, ray_out* out, double* Wout) {
+    memset(out, 0, sizeof *out);
+    out->f = f0;
+    out->sigma = 1;
+    out->min_vdist = INFINITY;
+    out->bnd_margin = INFINITY;
+    out->pi_margin = INFINITY;
+    int bad = (f0 < 0 || f0 >= m->nf);
+    double b[3] = {0, 0, 0};
+    if (!bad) {
+        double s = 0.0;
+        for (int k = 0; k < 3; k++) {
+            b[k] = b0[k];
+            if (!isfinite(b[k]) || b[k] < 0.0) bad = 1;
+            s += b[k];
+        }
+        if (!(s > 0.0) || !isfinite(s)) bad = 1;
+        else for (int k = 0; k < 3; k++) b[k] /= s;
+        for (int c = 0; c < 3; c++) if (!isfinite(v0[c])) bad = 1;
+        for (int i = 0; i < 3 * K; i++) if (!isfinite(W0[i])) bad = 1;
+    }
+    if (bad || K > 64) {
+        out->status = OR_RAY_BADINPUT;
+        for (int k = 0; k < 3; k++) { out->b[k] = b0[k]; out->p[k] = NAN; out->v[k] = NAN; }
+        for (int i = 0; i < 3 * K; i++) Wout[i] = NAN;
+        return;
+    }
+    int64_t f = f0;
+    const double* n = m->N + 3 * f;
+    double p[3], v[3];
+    bary_pos(m, f, b, p);
+    perp3(v0, n, v);
+    const double L = norm3(v);
+    for (int k = 0; k < K; k++) perp3(W0 + 3 * k, n, Wout + 3 * k);
+    out->L = L;
+    if (L > 0.0) for (int c = 0; c < 3; c++) out->d0[c] = v[c] / L;
+    double l = 0.0;
+    int32_t steps = 0;
+    int status = OR_RAY_OK;
+    while (l < L) {
+        /* the loop test's margin: how far short of |v_t| the traced length is */
+        if (L - l < out->pi_margin) out->pi_margin = L - l;
+        if (steps >= o->max_steps) { status = OR_RAY_MAXSTEPS; break; }
+        double q[3], c[3], bc[3];
+        for (int j = 0; j < 3; j++) q[j] = p[j] + o->step * v[j];
+        int64_t f2 = project_to_mesh(m, scale, q, c, bc, &out->pi_margin);
+        const double* n2 = m->N + 3 * f2;
+        rotate_normal_to_normal(n, n2, v);
+        for (int k = 0; k < K; k++) rotate_normal_to_normal(n, n2, Wout + 3 * k);
+        double dp[3];
+        sub3(c, p, dp);
+        l += norm3(dp);
+        memcpy(p, c, sizeof c);
+        memcpy(b, bc, sizeof bc);
+        f = f2;
+        n = n2;
+        steps++;
+    }
+    if (status == OR_RAY_OK && L > 0.0 && l - L < out->pi_margin) out->pi_margin = l - L;
+    out->f = (int32_t)f;
+    memcpy(out->b, b, sizeof b);
+    memcpy(out->p, p, sizeof p);
+    memcpy(out->v, v, sizeof v);
+    out->status = status;
+    out->n_cross = steps;
+    out->traced = l;
+}
+
 /* ------------------------------------------------------------ batching */
 typedef struct {
     const or_mesh* m;
@@ -846,8 +1056,18 @@ typedef struct {
     double eps_v, eps_p;
     const double* g; double* grad_v; double* grad_b; double* Jv; double* Jp;
     const double* g_vo; const double* g_W; double* grad_W;   /* transport cotangents (mode 3) */
+    const or_pi_opts* pi;   /* non-NULL: projection integration is the Exp (modes 0, 1, 2) */
+    double pi_scale;        /* largest coordinate magnitude, for the PI tie tolerance */
+    double* pi_margin;
     int64_t next;
 } job_t;
+
+/* The Exp a job runs: the straightest walk, or projection integration. */
+static void exp_any(const job_t* J, int32_t f0, const double* b0, const double* v0, int K, const double* W0,
+                    ray_out* out, double* Wout) {
+    if (J->pi) pi_one(J->m, f0, b0, v0, K, W0, J->pi, J->pi_scale, out, Wout);
+    else exp_one(J->m, f0, b0, v0, K, W0, J->o, out, Wout, NULL);
+}
 
 static void ep_one(const job_t* J, int64_t i);
 static void gfd_one(const job_t* J, int64_t i);
@@ -857,7 +1077,7 @@ static void fwd_one(const job_t* J, int64_t i) {
     ray_out r;
     double Wtmp[3 * 64];
     double* Wo = J->W_out ? J->W_out + 3 * J->K * i : Wtmp;
-    exp_one(J->m, J->f[i], J->b + 3 * i, J->v + 3 * i, J->K, J->W ? J->W + 3 * J->K * i : NULL, J->o, &r, Wo, NULL);
+    exp_any(J, J->f[i], J->b + 3 * i, J->v + 3 * i, J->K, J->W ? J->W + 3 * J->K * i : NULL, &r, Wo);
     J->f_out[i] = r.f;
     memcpy(J->b_out + 3 * i, r.b, sizeof r.b);
     memcpy(J->p_out + 3 * i, r.p, sizeof r.p);
@@ -870,6 +1090,7 @@ static void fwd_one(const job_t* J, int64_t i) {
     if (J->sigma_end) J->sigma_end[i] = r.sigma;
     if (J->n_bnd) J->n_bnd[i] = r.n_bnd;
     if (J->bnd_margin) J->bnd_margin[i] = r.bnd_margin;
+    if (J->pi_margin) J->pi_margin[i] = r.pi_margin;
 }
 
 static void* worker(void* arg) {
@@ -940,7 +1161,7 @@ int32_t or_exp_trace(const or_mesh* m, int32_t f, const double* b, const double*
 static void ep_one(const job_t* J, int64_t i) {
     const or_mesh* m = J->m;
     ray_out r;
-    exp_one(m, J->f[i], J->b + 3 * i, J->v + 3 * i, 0, NULL, J->o, &r, NULL, NULL);
+    exp_any(J, J->f[i], J->b + 3 * i, J->v + 3 * i, 0, NULL, &r, NULL);
     const double* g = J->g + 3 * i;
     double* gv = J->grad_v + 3 * i;
     for (int c = 0; c < 3; c++) J->grad_b[3 * i + c] = 0.0;
@@ -978,7 +1199,7 @@ static void gfd_one(const job_t* J, int64_t i) {
     const double* g = J->g + 3 * i;
     double ev = J->eps_v, ep = J->eps_p;
     ray_out r0, r1, r2, ru, rv, r3, r4;
-    exp_one(m, f, b, J->v + 3 * i, 0, NULL, J->o, &r0, NULL, NULL);
+    exp_any(J, f, b, J->v + 3 * i, 0, NULL, &r0, NULL);
     double* gv = J->grad_v + 3 * i;
     double* gb = J->grad_b + 3 * i;
     if (r0.status == OR_RAY_BADINPUT) {
@@ -1003,18 +1224,18 @@ static void gfd_one(const job_t* J, int64_t i) {
     /* column e_par: short trace from p' along the transported tangent */
     double w[3];
     for (int c = 0; c < 3; c++) w[c] = ev * dend[c];
-    exp_one(m, r0.f, r0.b, w, 0, NULL, J->o, &r1, NULL, NULL);
+    exp_any(J, r0.f, r0.b, w, 0, NULL, &r1, NULL);
     /* column e_perp */
     for (int c = 0; c < 3; c++) w[c] = vt[c] + ev * eperp[c];
-    exp_one(m, f, b, w, 0, NULL, J->o, &r2, NULL, NULL);
+    exp_any(J, f, b, w, 0, NULL, &r2, NULL);
     /* start-point perturbations with v transported along them */
     double vu[3], vv[3];
     for (int c = 0; c < 3; c++) w[c] = ep * eu[c];
-    exp_one(m, f, b, w, 1, vt, J->o, &ru, vu, NULL);
+    exp_any(J, f, b, w, 1, vt, &ru, vu);
     for (int c = 0; c < 3; c++) w[c] = ep * evv[c];
-    exp_one(m, f, b, w, 1, vt, J->o, &rv, vv, NULL);
-    exp_one(m, ru.f, ru.b, vu, 0, NULL, J->o, &r3, NULL, NULL);
-    exp_one(m, rv.f, rv.b, vv, 0, NULL, J->o, &r4, NULL, NULL);
+    exp_any(J, f, b, w, 1, vt, &rv, vv);
+    exp_any(J, ru.f, ru.b, vu, 0, NULL, &r3, NULL);
+    exp_any(J, rv.f, rv.b, vv, 0, NULL, &r4, NULL);
     double col[4][3];
     for (int c = 0; c < 3; c++) {
         col[0][c] = (r1.p[c] - r0.p[c]) / ev;
@@ -1310,4 +1531,64 @@ int or_gradx_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* 
     for (int t = 0; t < started; t++) pthread_join(th[t], NULL);
     pthread_mutex_destroy(&J.lock);
     return OR_OK;
+}
+
+int or_pi_exp_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b, const double* v,
+                    int32_t K, const double* W, const or_pi_opts* o, int32_t* f_out, double* b_out,
+                    double* p_out, double* v_out, double* W_out, int32_t* status, int32_t* n_steps,
+                    double* traced, double* margin, int32_t nthreads) {
+    if (!m || !o || !(o->step > 0.0) || o->max_steps < 0 || n < 0 || K < 0 || K > 64 ||
+        (n > 0 && (!f || !b || !v || !f_out || !b_out || !p_out || !v_out || !status)) ||
+        (K > 0 && n > 0 && (!W || !W_out))) {
+        set_err("bad arguments");
+        return OR_E_ARG;
+    }
+    job_t J;
+    memset(&J, 0, sizeof J);
+    J.m = m; J.n = n; J.f = f; J.b = b; J.v = v; J.K = K; J.W = W;
+    J.f_out = f_out; J.b_out = b_out; J.p_out = p_out; J.v_out = v_out; J.W_out = W_out;
+    J.status = status; J.n_cross = n_steps; J.traced = traced; J.pi_margin = margin;
+    J.pi = o; J.pi_scale = mesh_scale(m);
+    return run_job(&J, nthreads);
+}
+
+int or_pi_project(const or_mesh* m, int64_t n, const double* q, int32_t* f_out, double* c_out, double* b_out,
+                  double* margin) {
+    if (!m || n < 0 || (n > 0 && (!q || !f_out || !c_out || !b_out))) { set_err("bad arguments"); return OR_E_ARG; }
+    const double scale = mesh_scale(m);
+    for (int64_t i = 0; i < n; i++) {
+        double mg = INFINITY;
+        f_out[i] = (int32_t)project_to_mesh(m, scale, q + 3 * i, c_out + 3 * i, b_out + 3 * i, &mg);
+        if (margin) margin[i] = mg;
+    }
+    return OR_OK;
+}
+
+int or_pi_ep_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b, const double* v,
+                   const or_pi_opts* o, const double* g, double* grad_v, double* grad_b, int32_t nthreads) {
+    if (!m || !o || !(o->step > 0.0) || n < 0 || (n > 0 && (!f || !b || !v || !g || !grad_v || !grad_b))) {
+        set_err("bad arguments");
+        return OR_E_ARG;
+    }
+    job_t J;
+    memset(&J, 0, sizeof J);
+    J.m = m; J.n = n; J.f = f; J.b = b; J.v = v; J.g = g; J.grad_v = grad_v; J.grad_b = grad_b; J.mode = 1;
+    J.pi = o; J.pi_scale = mesh_scale(m);
+    return run_job(&J, nthreads);
+}
+
+int or_pi_gfd_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b, const double* v,
+                    const or_pi_opts* o, double eps_v, double eps_p, const double* g, double* grad_v,
+                    double* grad_b, double* Jv, double* Jp, int32_t nthreads) {
+    if (!m || !o || !(o->step > 0.0) || n < 0 || !(eps_v > 0.0) || !(eps_p > 0.0) ||
+        (n > 0 && (!f || !b || !v || !g || !grad_v || !grad_b))) {
+        set_err("bad arguments");
+        return OR_E_ARG;
+    }
+    job_t J;
+    memset(&J, 0, sizeof J);
+    J.m = m; J.n = n; J.f = f; J.b = b; J.v = v; J.g = g; J.grad_v = grad_v; J.grad_b = grad_b; J.mode = 2;
+    J.eps_v = eps_v; J.eps_p = eps_p; J.Jv = Jv; J.Jp = Jp;
+    J.pi = o; J.pi_scale = mesh_scale(m);
+    return run_job(&J, nthreads);
 }

@@ -109,6 +109,42 @@ int or_gradx_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* 
                    const double* v, const or_opts* o, const double* g, double* grad_X,
                    int32_t* n_vertex, int32_t nthreads);
 
+/* ---- projection integration (appendix "Projection Integration Exp Map",
+ * Alg. projection-exp): the comparison Exp of the paper. */
+typedef struct {
+    double step;           /* s: each step moves the point by s v before projecting */
+    int32_t max_steps;     /* cap on projection steps (status MAXSTEPS) */
+} or_pi_opts;
+
+/* Batched PI exponential map with K extra vectors rotated alongside v.
+ * Inputs as for or_exp_batch.  Outputs: f_out, b_out, p_out, v_out (the
+ * rotated v_t), W_out, status (OK or MAXSTEPS, BADINPUT), n_steps
+ * (projection steps), traced (accumulated length), margin (the smallest
+ * margin of a decision over the steps: the distance gap to the nearest face
+ * outside a projection's tie, the alignment gap inside it, and the loop
+ * test's gaps |v_t| - l before and l - |v_t| after the last step).  Any output pointer
+ * except f_out/b_out/p_out/v_out/status may be NULL. */
+int or_pi_exp_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b, const double* v,
+                    int32_t K, const double* W, const or_pi_opts* o, int32_t* f_out, double* b_out,
+                    double* p_out, double* v_out, double* W_out, int32_t* status, int32_t* n_steps,
+                    double* traced, double* margin, int32_t nthreads);
+
+/* project_to_mesh for n ambient points q[n*3]: the face holding the nearest
+ * point of the mesh (ties as in or_pi_exp_batch), that point and its
+ * barycentrics. */
+int or_pi_project(const or_mesh* m, int64_t n, const double* q, int32_t* f_out, double* c_out, double* b_out,
+                  double* margin);
+
+/* The extrinsic proxy and geodesic finite differences with PI as the Exp
+ * (the paper applies both schemes to PI, Fig. PIdiff-acc); arguments as for
+ * or_ep_batch / or_gfd_batch.  The end frame takes the end face's own normal
+ * (PI rotates from face normal to face normal). */
+int or_pi_ep_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b, const double* v,
+                   const or_pi_opts* o, const double* g, double* grad_v, double* grad_b, int32_t nthreads);
+int or_pi_gfd_batch(const or_mesh* m, int64_t n, const int32_t* f, const double* b, const double* v,
+                    const or_pi_opts* o, double eps_v, double eps_p, const double* g, double* grad_v,
+                    double* grad_b, double* Jv, double* Jp, int32_t nthreads);
+
 #ifdef __cplusplus
 }
 #endif
