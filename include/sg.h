@@ -176,6 +176,32 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
                      const sg_opts* opts, void* stream);
 
 /*
+ * Allocation-free sg_exp_transport, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, and harnesses
+ * that forbid hipMalloc.  Same arguments, outputs and per-ray semantics as
+ * sg_exp_transport (the same kernels run).  The persistent walk's workspace
+ * is a fixed device array inside the library, SG_NOALLOC_SCRATCH_BYTES
+ * (128 MiB) per device, held by every device the library runs on until the
+ * process ends; the call allocates nothing and calls no allocating routine.
+ *   - n and K must fit it: sg_exp_workspace_size (persistent kernel) must
+ *     report at most SG_NOALLOC_SCRATCH_BYTES, else SG_E_ARG before any
+ *     launch (about 1.45M rays at K = 2, 1.76M at K = 0).
+ *   - Every call on a device shares that device's array, so calls that
+ *     overlap on one device race: order them on one stream or synchronize
+ *     between them.  The kernels clear what must start at zero; the array
+ *     keeps the last call's contents.
+ *   - opts->kernel: SG_KERNEL_AUTO / SG_KERNEL_PERSISTENT, or SG_KERNEL_PLAIN
+ *     (which needs no scratch); SG_KERNEL_PARTITIONED, opts->workspace != NULL
+ *     and debug bit 2 (event timing) return SG_E_ARG.
+ */
+#define SG_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int sg_exp_transport_noalloc(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v,
+                             int32_t K, const float* W,
+                             int32_t* f_out, float* b_out, float* p_out, float* v_out, float* W_out,
+                             int32_t* status, int32_t* n_cross, uint64_t* seq_hash,
+                             const sg_opts* opts, void* stream);
+
+/*
  * Backward of the exponential map (Sec. 4 "Differentiation").  Given
  * g_p[n,3] = dL/dp' (float32, device) for the queries (f, b, v) of an earlier
  * sg_exp call, returns

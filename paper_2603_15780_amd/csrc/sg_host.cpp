@@ -210,6 +210,34 @@ size_t exp_workspace_bytes(const sg_opts& o, int64_t n, int32_t K) {
                                              : sg::exp_persistent_workspace(n, K);
 }
 
+// Checks the arguments of a forward call and fills its kernel arguments.
+int exp_args(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v, int32_t K, const float* W,
+             int32_t* f_out, float* b_out, float* p_out, float* v_out, float* W_out, int32_t* status,
+             int32_t* n_cross, uint64_t* seq_hash, const sg_opts* opts, sg_opts& o, sg::ExpArgs& a) {
+    if (!mesh) return fail(SG_E_ARG, "mesh is NULL");
+    if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
+    if (K < 0 || K > 64) return fail(SG_E_ARG, "K must be in [0, 64]");
+    int rc = check_opts(opts, o, mesh);
+    if (rc != SG_OK) return rc;
+    if (n == 0) return SG_OK;
+    if (!f || !b || !v || !f_out || !b_out || !p_out || !v_out) return fail(SG_E_ARG, "a required array is NULL");
+    if (K > 0 && (!W || !W_out)) return fail(SG_E_ARG, "W and W_out are required when K > 0");
+    if ((o.debug & 2u) && !seq_hash) return fail(SG_E_ARG, "debug bit 1 needs seq_hash");
+    if (o.kernel != SG_KERNEL_PLAIN && n >= ((int64_t)1 << 31))
+        return fail(SG_E_ARG, "the persistent and partitioned walks take fewer than 2^31 rays per call");
+    a = sg::ExpArgs{};
+    a.n = n;
+    a.f = f; a.b = b; a.v = v;
+    a.K = K; a.W = W;
+    a.f_out = f_out; a.b_out = b_out; a.p_out = p_out; a.v_out = v_out; a.W_out = W_out;
+    a.status = status; a.n_cross = n_cross; a.seq_hash = seq_hash;
+    a.max_steps = o.max_steps;
+    a.snap = o.vertex_snap;
+    a.debug = o.debug;
+    a.rays_per_lane = o.rays_per_lane;
+    return SG_OK;
+}
+
 }  // namespace
 
 namespace sg {
@@ -499,6 +527,14 @@ int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, 
     if (hipDeviceGetAttribute(&m->cu_count, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess ||
         m->cu_count <= 0)
         m->cu_count = 256;
+    {   // the allocation-free forward's scratch address on this device (once per device)
+        void* scr = nullptr;
+        e = sg::noalloc_scratch(&scr);
+        if (e != hipSuccess) {
+            delete m;
+            return hip_fail(e, "scratch address");
+        }
+    }
     m->walk_blocks_per_cu = sg::walk_blocks_per_cu();
     m->part_blocks_per_cu = sg::part_blocks_per_cu();
     m->n_verts = n_verts;
@@ -590,28 +626,11 @@ int sg_mesh_walk_time(sg_mesh mesh, double* total_ms, int64_t* launches) {
 int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v, int32_t K,
                      const float* W, int32_t* f_out, float* b_out, float* p_out, float* v_out, float* W_out,
                      int32_t* status, int32_t* n_cross, uint64_t* seq_hash, const sg_opts* opts, void* stream) {
-    if (!mesh) return fail(SG_E_ARG, "mesh is NULL");
-    if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
-    if (K < 0 || K > 64) return fail(SG_E_ARG, "K must be in [0, 64]");
     sg_opts o;
-    int rc = check_opts(opts, o, mesh);
-    if (rc != SG_OK) return rc;
-    if (n == 0) return SG_OK;
-    if (!f || !b || !v || !f_out || !b_out || !p_out || !v_out) return fail(SG_E_ARG, "a required array is NULL");
-    if (K > 0 && (!W || !W_out)) return fail(SG_E_ARG, "W and W_out are required when K > 0");
-    if ((o.debug & 2u) && !seq_hash) return fail(SG_E_ARG, "debug bit 1 needs seq_hash");
-    if (o.kernel != SG_KERNEL_PLAIN && n >= ((int64_t)1 << 31))
-        return fail(SG_E_ARG, "the persistent and partitioned walks take fewer than 2^31 rays per call");
     sg::ExpArgs a{};
-    a.n = n;
-    a.f = f; a.b = b; a.v = v;
-    a.K = K; a.W = W;
-    a.f_out = f_out; a.b_out = b_out; a.p_out = p_out; a.v_out = v_out; a.W_out = W_out;
-    a.status = status; a.n_cross = n_cross; a.seq_hash = seq_hash;
-    a.max_steps = o.max_steps;
-    a.snap = o.vertex_snap;
-    a.debug = o.debug;
-    a.rays_per_lane = o.rays_per_lane;
+    int rc = exp_args(mesh, n, f, b, v, K, W, f_out, b_out, p_out, v_out, W_out, status, n_cross, seq_hash, opts, o,
+                      a);
+    if (rc != SG_OK || n == 0) return rc;
     const hipStream_t st = (hipStream_t)stream;
     if (o.kernel == SG_KERNEL_PLAIN) {
         hipError_t e = sg::launch_exp_plain(mesh->dev(o.boundary_mode), a, st);
@@ -641,6 +660,39 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
     const hipError_t e2 = give_workspace(ws, st);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     if (e2 != hipSuccess) return hip_fail(e2, "workspace release");
+    return SG_OK;
+}
+
+static_assert(SG_NOALLOC_SCRATCH_BYTES == sg::kNoAllocScratchBytes, "scratch size in sg.h and the library agree");
+
+int sg_exp_transport_noalloc(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v, int32_t K,
+                             const float* W, int32_t* f_out, float* b_out, float* p_out, float* v_out, float* W_out,
+                             int32_t* status, int32_t* n_cross, uint64_t* seq_hash, const sg_opts* opts,
+                             void* stream) {
+    sg_opts o;
+    sg::ExpArgs a{};
+    int rc = exp_args(mesh, n, f, b, v, K, W, f_out, b_out, p_out, v_out, W_out, status, n_cross, seq_hash, opts, o,
+                      a);
+    if (rc != SG_OK || n == 0) return rc;
+    if (o.workspace) return fail(SG_E_ARG, "sg_exp_transport_noalloc uses the library's scratch: opts->workspace must be NULL");
+    if (o.debug & 4u) return fail(SG_E_ARG, "sg_exp_transport_noalloc does not time the walk (debug bit 2)");
+    if (o.kernel == SG_KERNEL_PARTITIONED)
+        return fail(SG_E_ARG, "sg_exp_transport_noalloc runs the plain or the persistent kernel");
+    const hipStream_t st = (hipStream_t)stream;
+    if (o.kernel == SG_KERNEL_PLAIN) {   // one ray per lane: no scratch at all
+        hipError_t e = sg::launch_exp_plain(mesh->dev(o.boundary_mode), a, st);
+        if (e != hipSuccess) return hip_fail(e, "forward launch");
+        return SG_OK;
+    }
+    const size_t need = sg::exp_persistent_workspace(n, K);
+    if (need > sg::kNoAllocScratchBytes)
+        return fail(SG_E_ARG, "%lld rays with K = %d need %llu bytes of scratch; the limit is %llu (SG_NOALLOC_SCRATCH_BYTES)",
+                    (long long)n, (int)K, (unsigned long long)need, (unsigned long long)sg::kNoAllocScratchBytes);
+    void* ws = nullptr;
+    hipError_t e = sg::noalloc_scratch(&ws);
+    if (e != hipSuccess) return hip_fail(e, "scratch address");
+    e = sg::launch_exp_persistent(mesh->dev(o.boundary_mode), a, ws, sched(o), st, nullptr, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
     return SG_OK;
 }
 

@@ -19,6 +19,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "sg_internal.h"
 #include "sg_launch.h"
@@ -2615,6 +2616,38 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, c
         hipLaunchKernelGGL(k_finish, dim3((unsigned)grid), dim3(block), 0, s, M, a, states, (const uint64_t*)nullptr,
                            (const float*)aux, (const int32_t*)slot);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- allocation-free forward
+// Scratch of the allocation-free forward: the persistent walk's workspace
+// (walk states, final states, epilogue terms, slots, bucket counts, queue
+// counters) for callers that cannot allocate.  Every device the library runs
+// on holds its own copy from the load of this code object until the process
+// ends.  In host code the array's name is a host-side stand-in, never a
+// device address: host code reaches the array only through the address
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device.  The walk's kernels clear the counts and counters they use, so the
+// previous call's contents do no harm; calls that overlap on one device race.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void** out) {
+    static std::mutex mu;
+    static void* addr[kNoAllocMaxDevices] = {};
+    *out = nullptr;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 // Rounds of the partitioned walk: all but the last stop rays at part borders

@@ -93,6 +93,13 @@ struct WalkSched {
 // Persistent forward: init kernel, persistent work-queue walk, finish kernel.
 // ws must hold exp_persistent_workspace(n, K) bytes of device memory.
 size_t exp_persistent_workspace(int64_t n, int32_t K);
+// Device scratch of the allocation-free forward (one copy per device, held
+// until the process ends): its size, the devices it is looked up for, and the
+// current device's address (looked up with hipGetSymbolAddress on the first
+// request from each device).
+constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
+constexpr int kNoAllocMaxDevices = 64;
+hipError_t noalloc_scratch(void** out);
 // ev0/ev1 (nullable) are recorded on s around the walk kernel.
 hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, const WalkSched& w, hipStream_t s,
                                  hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

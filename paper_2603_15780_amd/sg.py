@@ -63,6 +63,8 @@ def lib():
         L.sg_exp.restype = C.c_int
         L.sg_exp_transport.argtypes = [P, I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, C.POINTER(Opts), P]
         L.sg_exp_transport.restype = C.c_int
+        L.sg_exp_transport_noalloc.argtypes = L.sg_exp_transport.argtypes
+        L.sg_exp_transport_noalloc.restype = C.c_int
         L.sg_exp_backward.argtypes = [P, I32, I64, P, P, P, P, P, P, P, P, P, C.POINTER(Opts), P]
         L.sg_exp_backward.restype = C.c_int
         L.sg_exp_backward_transport.argtypes = [P, I32, I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P,
@@ -180,8 +182,12 @@ class Mesh:
         return ms.value, cnt.value
 
     def exp(self, f, b, v, W=None, *, out=None, want_status=True, want_cross=False, want_hash=False,
-            o: Opts | None = None, **kw):
-        """Exp_p(v) for torch CUDA tensors f[n] int32, b[n,3], v[n,3] (float32), W[n,K,3]."""
+            noalloc=False, o: Opts | None = None, **kw):
+        """Exp_p(v) for torch CUDA tensors f[n] int32, b[n,3], v[n,3] (float32), W[n,K,3].
+
+        noalloc=True calls sg_exp_transport_noalloc (the library's fixed
+        scratch instead of a workspace allocation; pass `out` to allocate
+        nothing here either)."""
         import torch
         n = f.shape[0]
         dev = f.device
@@ -208,7 +214,8 @@ class Mesh:
                 n_cross=torch.empty(n, dtype=torch.int32, device=dev) if want_cross else None,
                 hash=torch.empty(n, dtype=torch.int64, device=dev) if want_hash else None,
             )
-        rc = lib().sg_exp_transport(
+        call = lib().sg_exp_transport_noalloc if noalloc else lib().sg_exp_transport
+        rc = call(
             self._h, n, _dptr(f), _dptr(b), _dptr(v), K, _dptr(W), _dptr(out["f"]), _dptr(out["b"]),
             _dptr(out["p"]), _dptr(out["v"]), _dptr(out.get("W")), _dptr(out.get("status")),
             _dptr(out.get("n_cross")), _dptr(out.get("hash")), C.byref(o), _stream())
