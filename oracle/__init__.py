@@ -231,13 +231,15 @@ class Mesh:
         p^(k+1) = Exp_{p^(k)}(field(p^(k)) / K) for k = 0 .. K-1, the field re-evaluated at every
         intermediate point.  Composed from `exp` alone; field(p [n,3], f [n], b [n,3]) -> v [n,3]
         (float64).  Returns the last step's f, b, p, v, status, every intermediate point (`pts`, K of
-        them) and the smallest vertex distance over all steps (`min_vdist`)."""
+        them, with their faces `fs` and barycentrics `bs`, and the start point's face and barycentrics
+        first in `fs`, `bs`) and the smallest vertex distance over all steps (`min_vdist`)."""
         f = np.ascontiguousarray(f, dtype=np.int32).reshape(-1)
         n = f.shape[0]
         b = np.ascontiguousarray(b, dtype=np.float64).reshape(n, 3)
         o = self.exp(f, b, np.zeros((n, 3)), **kw)   # p^(0) = sum_k b_k x_k
         p, b = o["p"], o["b"]
         pts, mvd, status = [], np.full(n, np.inf), np.zeros(n, np.int32)
+        fs, bs = [f.copy()], [b.copy()]
         for _ in range(int(steps)):
             v = np.asarray(field(p, f, b), dtype=np.float64) / float(steps)
             o = self.exp(f, b, v, **kw)
@@ -245,7 +247,9 @@ class Mesh:
             mvd = np.minimum(mvd, o["min_vdist"])
             status = np.where(status != 0, status, o["status"])
             pts.append(p)
-        return dict(f=f, b=b, p=p, v=o["v"], status=status, pts=pts, min_vdist=mvd)
+            fs.append(f.copy())
+            bs.append(b.copy())
+        return dict(f=f, b=b, p=p, v=o["v"], status=status, pts=pts, fs=fs, bs=bs, min_vdist=mvd)
 
     # ---- projection integration (appendix "Projection Integration Exp Map", Alg. projection-exp)
     def _pi_opts(self, step, max_steps):

@@ -560,7 +560,13 @@ def test_iterated_exp_against_oracle(torch):
     pins it), and the autograd gradients in the field's per-query parameters and
     in the start barycentrics against float64 central differences (h = 1e-6) of
     that composition, at relative error 1e-3 on queries whose paths keep
-    2e-2 mean edges from every vertex at every step."""
+    2e-2 mean edges from every vertex at every step and whose start and
+    intermediate points lie farther than 2 eps from their faces' edges.
+    The second condition keeps every GFD stencil inside one face: a stencil
+    walk of length eps that crosses an edge makes the difference a chord bent
+    by the dihedral angle (eqs. jv and jp take the literal 3D chord), an error
+    of order dihedral^2 (about 1e-2 on this coarse mesh) that central
+    differences of the map do not have."""
     from paper_2603_15780_amd import sg
     from test_oracle_iterated import field_factory
     X, F = CF.mesh_config(1)
@@ -576,8 +582,6 @@ def test_iterated_exp_against_oracle(torch):
     c2 = (c2 / np.linalg.norm(c2)).astype(np.float32).astype(np.float64)
     o0 = np.zeros(3)
     gup = rng.standard_normal((n, 3))
-    db = rng.normal(size=(n, 3))
-    db -= db.mean(1)[:, None]
     # GPU: loss = sum_i g_i . p_K,i
     dev = torch.device("cuda:0")
     th = torch.tensor(theta, dtype=torch.float32, device=dev, requires_grad=True)
@@ -601,6 +605,13 @@ def test_iterated_exp_against_oracle(torch):
     assert np.mean(err <= 1e-4 * om.mean_edge) >= 0.999 and np.all(err[far] <= 1e-4 * om.mean_edge), err.max()
     assert np.array_equal(fK.cpu().numpy()[far & (err < 1e-6)], it["f"][far & (err < 1e-6)])
     keep = (it["status"] == 0) & (it["min_vdist"] > 2e-2 * om.mean_edge) & (r["b"].min(1) > 1e-3)
+    # distance of each start and intermediate point to its face's edges: b_j times the altitude onto edge j
+    Xd = X.astype(np.float64)
+    for fk, bk in zip(it["fs"], it["bs"]):
+        x = Xd[F[fk]]
+        area2 = np.linalg.norm(np.cross(x[:, 1] - x[:, 0], x[:, 2] - x[:, 0]), axis=1)
+        opp = np.stack([np.linalg.norm(x[:, (j + 2) % 3] - x[:, (j + 1) % 3], axis=1) for j in range(3)], 1)
+        keep &= (bk * (area2[:, None] / opp)).min(1) > 2 * eps
     assert keep.sum() > 1000, keep.sum()
     # central differences of the oracle's composition, per query (queries are independent)
     fd_theta = np.zeros((n, 2))
@@ -611,13 +622,18 @@ def test_iterated_exp_against_oracle(torch):
         dp = (om.exp_iterated(r["f"], r["b"].astype(np.float32), field_factory(tp, c1, c2, o0), K)["p"]
               - om.exp_iterated(r["f"], r["b"].astype(np.float32), field_factory(tm, c1, c2, o0), K)["p"]) / (2 * H)
         fd_theta[:, q] = (dp * gup).sum(1)
+    # the start-point gradient in the face plane, as its components along the
+    # constraint-preserving barycentric directions (-1, 1, 0) and (-1, 0, 1)
     b0 = r["b"].astype(np.float32).astype(np.float64)
     b0 /= b0.sum(1)[:, None]
-    dp = (om.exp_iterated(r["f"], b0 + H * db, fld, K)["p"] - om.exp_iterated(r["f"], b0 - H * db, fld, K)["p"]) / (2 * H)
-    fd_b = (dp * gup).sum(1)
+    fd_b = np.zeros((n, 2))
+    for q, d in enumerate(([-1.0, 1.0, 0.0], [-1.0, 0.0, 1.0])):
+        d = np.asarray(d)[None, :]
+        dp = (om.exp_iterated(r["f"], b0 + H * d, fld, K)["p"] - om.exp_iterated(r["f"], b0 - H * d, fld, K)["p"]) / (2 * H)
+        fd_b[:, q] = (dp * gup).sum(1)
     rel_t = np.linalg.norm(g_theta - fd_theta, axis=1) / np.maximum(np.linalg.norm(fd_theta, axis=1), 1e-12)
-    got_b = (g_b * db).sum(1)
-    rel_b = np.abs(got_b - fd_b) / np.maximum(np.abs(fd_b), 1e-3 * np.abs(fd_b).max())
+    got_b = np.stack([g_b[:, 1] - g_b[:, 0], g_b[:, 2] - g_b[:, 0]], 1)
+    rel_b = np.linalg.norm(got_b - fd_b, axis=1) / np.maximum(np.linalg.norm(fd_b, axis=1), 1e-12)
     print(dict(n_keep=int(keep.sum()), t_med=float(np.median(rel_t[keep])), t_ok=float(np.mean(rel_t[keep] <= 1e-3)),
                b_med=float(np.median(rel_b[keep])), b_ok=float(np.mean(rel_b[keep] <= 1e-3))))
     assert np.mean(rel_t[keep] <= 1e-3) >= 0.999
