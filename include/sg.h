@@ -279,6 +279,60 @@ int sg_backward_workspace_size(sg_mesh mesh, int32_t mode, int64_t n, int32_t wa
                                const sg_opts* opts, size_t* bytes);
 
 /*
+ * Projection-integration (PI) exponential map, the paper's comparison Exp
+ * (appendix "Projection Integration Exp Map", Alg. projection-exp): repeat
+ *   q = p + s v; (p', f') = nearest point of the mesh to q (project_to_mesh);
+ *   v turned by the rotation taking f's normal to f''s (rotate_vector);
+ *   l += |p' - p|
+ * while l < |v_t|.  Readings: v (and W) are first projected onto the start
+ * face's plane, as for sg_exp; the loop runs while the traced length is
+ * short of |v_t| (the last step is not clamped, as printed); the nearest
+ * point is the minimiser of the distance to each closed triangle over the
+ * ray's own mesh, ties (distances within 2^-20 of the largest coordinate,
+ * i.e. float32 rounding: a nearest point on an edge or vertex) going to the
+ * face whose normal is most nearly parallel to q - p', then the smallest
+ * face id; parallel normals leave v unchanged.
+ *   search SG_PI_GRID (default): a uniform grid per mesh, cells visited in
+ *     rings and skipped when farther than the best distance found, which
+ *     selects what a scan of every face selects;
+ *   search SG_PI_SCAN: the printed scan of every face of the mesh per step.
+ * In/out arrays as for sg_exp_transport (K extra vectors keep their angle to
+ * v); n_steps[n] int32 (nullable) receives the projection steps taken.
+ * status: SG_RAY_OK, SG_RAY_MAXSTEPS (l still short after max_steps steps),
+ * SG_RAY_BADINPUT.  The first PI call on a handle, and the first after
+ * sg_mesh_update_vertices, builds the per-face records and grids on the host
+ * and uploads them (synchronous; about 100 bytes per face plus 4 bytes per
+ * cell).  Float32 arithmetic; the traced length is summed in float-float.
+ */
+enum { SG_PI_GRID = 0, SG_PI_SCAN = 1 };
+typedef struct {
+    float step;            /* s, in (0, 1]; <= 0: 0.01 */
+    int32_t max_steps;     /* <= 0: ceil(8 / s) */
+    int32_t search;        /* SG_PI_GRID or SG_PI_SCAN */
+} sg_pi_opts;
+void sg_pi_opts_default(sg_pi_opts* o);
+int sg_pi_exp(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v, int32_t K,
+              const float* W, int32_t* f_out, float* b_out, float* p_out, float* v_out, float* W_out,
+              int32_t* status, int32_t* n_steps, const sg_pi_opts* pi_opts, void* stream);
+
+/*
+ * Backward of the PI map (the paper applies both of its schemes to PI).
+ *   SG_BWD_EP: eq. proxy_func from the forward's saved f_out and v_out (the
+ *     end frame takes the end face's own normal); no PI steps run.
+ *   SG_BWD_GFD: eqs. jv, jp and chain with PI as the Exp: seven PI maps per
+ *     query in two stacked launches (Appendix "Speed-up GFD and EP through
+ *     batching"), step sizes opts->eps_v, opts->eps_p; f_out, v_out unused.
+ * g_p[n,3] = dL/dp'; grad_v, grad_b [n,3] out as for sg_exp_backward (NaN for
+ * rejected queries).  opts: eps_v, eps_p and workspace are honoured (GFD's
+ * workspace: sg_pi_backward_workspace_size, about 600 bytes per query; NULL:
+ * a stream-ordered allocation).  n < 2^29.
+ */
+int sg_pi_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b, const float* v,
+                   const int32_t* f_out, const float* v_out, const float* g_p, float* grad_v, float* grad_b,
+                   const sg_pi_opts* pi_opts, const sg_opts* opts, void* stream);
+int sg_pi_backward_workspace_size(sg_mesh mesh, int32_t mode, int64_t n, size_t* bytes);
+
+/*
  * Autotuner for the forward walk (Sec. 4 "Parallelisation on the GPU"
  * schedules one ray per thread; this picks the schedule that runs the
  * caller's batch fastest).  Times sg_exp_transport on the given queries

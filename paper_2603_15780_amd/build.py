@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(OUT_DIR, "libsg.so")
-SOURCES = ["sg_host.cpp", "sg_kernels.hip"]
+SOURCES = ["sg_host.cpp", "sg_kernels.hip", "sg_pi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed-fp32 instructions are disabled: hipcc -O3 forms them from float code
 # and some of their forms are avoided on this target

@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -45,6 +46,20 @@ struct sg_mesh_s {
     size_t bytes = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed, spare;   // walk-kernel event pairs
     sg::PackedMesh host;   // connectivity, links and face order, for sg_mesh_update_vertices
+    std::vector<float> hX;  // vertex positions on the host (the projection grid is built from them)
+    // projection-integration Exp: per-face data in user order and one grid per
+    // mesh, built on the first call that needs them (and again after a vertex update)
+    std::mutex pi_mu;
+    bool pi_ready = false;
+    sg::PiFace* d_piface = nullptr;
+    sg::PiGrid* d_pigrid = nullptr;
+    uint32_t* d_cell_start = nullptr;
+    int32_t* d_cell_face = nullptr;
+    size_t pi_bytes = 0;
+    double pi_tie = 0.0, pi_slack = 0.0;
+    sg::PiMesh pi() const {
+        return sg::PiMesh{d_piface, d_pigrid, d_cell_start, d_cell_face, n_faces, n_meshes, pi_tie, pi_slack};
+    }
     sg::DevMesh dev(int32_t hole_avoid = 0) const {
         sg::DevMesh d{d_face,  d_F,     d_X,     d_half, d_perm,     d_order,
                       n_faces, n_verts, has_flip, {},   d_twin, hole_avoid, reinterpret_cast<const float4*>(d_geo)};
@@ -118,6 +133,19 @@ int upload(T** dptr, const std::vector<T>& h, size_t& bytes) {
     return SG_OK;
 }
 
+void free_pi(sg_mesh_s* m) {
+    (void)hipFree(m->d_piface);
+    (void)hipFree(m->d_pigrid);
+    (void)hipFree(m->d_cell_start);
+    (void)hipFree(m->d_cell_face);
+    m->d_piface = nullptr;
+    m->d_pigrid = nullptr;
+    m->d_cell_start = nullptr;
+    m->d_cell_face = nullptr;
+    m->pi_bytes = 0;
+    m->pi_ready = false;
+}
+
 void free_mesh(sg_mesh_s* m) {
     if (!m) return;
     for (auto& pr : m->timed) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
@@ -130,6 +158,7 @@ void free_mesh(sg_mesh_s* m) {
     (void)hipFree(m->d_order);
     (void)hipFree(m->d_twin);
     (void)hipFree(m->d_geo);
+    free_pi(m);
     delete m;
 }
 
@@ -208,6 +237,177 @@ size_t exp_workspace_bytes(const sg_opts& o, int64_t n, int32_t K) {
     if (o.kernel == SG_KERNEL_PLAIN || n <= 0) return 0;
     return o.kernel == SG_KERNEL_PARTITIONED ? sg::exp_partitioned_workspace(n, K, (o.debug & 2u) != 0u)
                                              : sg::exp_persistent_workspace(n, K);
+}
+
+// Builds the projection-integration data of a handle on the host (float64
+// from the float32 positions, rounded once) and uploads it: per-face records
+// in user order and one uniform grid per mesh whose cells list the faces
+// whose bounding boxes, widened by a margin, meet them.  Cells are 1.5 mean
+// edges wide (wider if a mesh would need more than 32 cells per face).
+int ensure_pi(sg_mesh m) {
+    std::lock_guard<std::mutex> lock(m->pi_mu);
+    if (m->pi_ready) return SG_OK;
+    try {
+        const sg::PackedMesh& pm = m->host;
+        const int64_t nf = m->n_faces;
+        const std::vector<float>& X = m->hX;
+        std::vector<int32_t> Fu(3 * nf);   // user order, global vertex ids
+        for (int64_t u = 0; u < nf; ++u) {
+            const int64_t fi = pm.perm[u];
+            for (int k = 0; k < 3; ++k) Fu[3 * u + k] = pm.F[3 * fi + k];
+        }
+        auto P = [&](int64_t v) { return V3{X[3 * v], X[3 * v + 1], X[3 * v + 2]}; };
+        double scale = 1.0;
+        for (float x : X) scale = std::max(scale, (double)std::fabs(x));
+        std::vector<sg::PiFace> face(nf);
+        for (int64_t u = 0; u < nf; ++u) {
+            const V3 x0 = P(Fu[3 * u]), x1 = P(Fu[3 * u + 1]), x2 = P(Fu[3 * u + 2]);
+            const V3 c = cross(x1 - x0, x2 - x0);
+            const double ic = 1.0 / len(c);
+            sg::PiFace& F = face[u];
+            const V3 xs[3] = {x0, x1, x2};
+            float* dst[3] = {F.x0, F.x1, F.x2};
+            for (int k = 0; k < 3; ++k) {
+                dst[k][0] = (float)xs[k].x;
+                dst[k][1] = (float)xs[k].y;
+                dst[k][2] = (float)xs[k].z;
+            }
+            F.pad = 0.f;
+            F.n[0] = c.x * ic;
+            F.n[1] = c.y * ic;
+            F.n[2] = c.z * ic;
+        }
+        const std::vector<int64_t>& fo = pm.face_off;
+        const int nm = (int)fo.size() - 1;
+        std::vector<sg::PiGrid> grid(nm);
+        std::vector<double> lo(3 * (size_t)nm), hh(nm);
+        uint64_t total = 0;
+        for (int k = 0; k < nm; ++k) {
+            sg::PiGrid& G = grid[k];
+            G.face0 = (int32_t)fo[k];
+            G.face1 = (int32_t)fo[k + 1];
+            double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY}, el = 0.0;
+            for (int64_t u = fo[k]; u < fo[k + 1]; ++u)
+                for (int j = 0; j < 3; ++j) {
+                    const V3 a = P(Fu[3 * u + j]), b = P(Fu[3 * u + (j + 1) % 3]);
+                    el += len(b - a);
+                    const double xa[3] = {a.x, a.y, a.z};
+                    for (int c = 0; c < 3; ++c) {
+                        mn[c] = std::min(mn[c], xa[c]);
+                        mx[c] = std::max(mx[c], xa[c]);
+                    }
+                }
+            const int64_t fm = fo[k + 1] - fo[k];
+            if (fm == 0) {
+                for (int c = 0; c < 3; ++c) mn[c] = mx[c] = 0.0;
+                el = 1.0;
+            }
+            double h = 1.5 * el / (3.0 * (double)std::max<int64_t>(fm, 1));
+            if (!(h > 0.0)) h = 1.0;
+            const double cap = (double)std::max<int64_t>(32 * fm, 4096);
+            int32_t n[3];
+            double o[3];
+            for (;;) {
+                double cells = 1.0;
+                for (int c = 0; c < 3; ++c) {
+                    o[c] = mn[c] - 0.5 * h;
+                    n[c] = (int32_t)std::max(1.0, std::ceil((mx[c] + 0.5 * h - o[c]) / h));
+                    cells *= n[c];
+                }
+                if (cells <= cap) break;
+                h *= 1.25;
+            }
+            G.ox = (float)o[0];
+            G.oy = (float)o[1];
+            G.oz = (float)o[2];
+            G.h = (float)h;
+            G.nx = n[0];
+            G.ny = n[1];
+            G.nz = n[2];
+            G.cell0 = (uint32_t)total;
+            total += (uint64_t)n[0] * n[1] * n[2];
+            if (total >= ((uint64_t)1 << 31)) return fail(SG_E_OOM, "projection grid too large");
+            lo[3 * k] = G.ox;
+            lo[3 * k + 1] = G.oy;
+            lo[3 * k + 2] = G.oz;
+            hh[k] = G.h;
+        }
+        // cell ranges of each face's widened box (in the float32 origin and size the kernels use)
+        auto range = [&](int64_t u, int k, int32_t* i0, int32_t* i1) {
+            const sg::PiGrid& G = grid[k];
+            const double h = hh[k], marg = 1e-3 * h + scale * std::ldexp(1.0, -20);
+            const int32_t nn[3] = {G.nx, G.ny, G.nz};
+            for (int c = 0; c < 3; ++c) {
+                double a = INFINITY, b = -INFINITY;
+                for (int j = 0; j < 3; ++j) {
+                    const double x = X[3 * (int64_t)Fu[3 * u + j] + c];
+                    a = std::min(a, x);
+                    b = std::max(b, x);
+                }
+                const double t0 = std::floor((a - marg - lo[3 * k + c]) / h), t1 = std::floor((b + marg - lo[3 * k + c]) / h);
+                i0[c] = (int32_t)std::min<double>(std::max(t0, 0.0), nn[c] - 1);
+                i1[c] = (int32_t)std::min<double>(std::max(t1, 0.0), nn[c] - 1);
+            }
+        };
+        std::vector<uint32_t> start(total + 1, 0u);
+        std::vector<int32_t> cf;   // cell faces
+        uint64_t entries = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<uint32_t> fill;
+            if (pass == 1) {
+                fill.assign(start.begin(), start.end() - 1);
+                cf.assign(entries, 0);
+            }
+            for (int k = 0; k < nm; ++k) {
+                const sg::PiGrid& G = grid[k];
+                for (int64_t u = fo[k]; u < fo[k + 1]; ++u) {
+                    int32_t i0[3], i1[3];
+                    range(u, k, i0, i1);
+                    for (int32_t iz = i0[2]; iz <= i1[2]; ++iz)
+                        for (int32_t iy = i0[1]; iy <= i1[1]; ++iy)
+                            for (int32_t ix = i0[0]; ix <= i1[0]; ++ix) {
+                                const uint64_t cell = G.cell0 + ((uint64_t)iz * G.ny + iy) * G.nx + ix;
+                                if (pass == 0) start[cell + 1]++;
+                                else cf[fill[cell]++] = (int32_t)u;
+                            }
+                }
+            }
+            if (pass == 0) {
+                for (uint64_t c = 0; c < total; ++c) start[c + 1] += start[c];
+                entries = start[total];
+                if (entries >= ((uint64_t)1 << 32) - 1) return fail(SG_E_OOM, "projection grid too large");
+            } else {
+                std::vector<sg::PiGrid> gcopy = grid;
+                int rc = upload(&m->d_piface, face, m->pi_bytes);
+                if (rc == SG_OK) rc = upload(&m->d_pigrid, gcopy, m->pi_bytes);
+                if (rc == SG_OK) rc = upload(&m->d_cell_start, start, m->pi_bytes);
+                if (rc == SG_OK) rc = upload(&m->d_cell_face, cf, m->pi_bytes);
+                if (rc != SG_OK) {
+                    free_pi(m);
+                    return rc;
+                }
+            }
+        }
+        // distances within 1e-12 of the largest coordinate are one nearest point (float64 rounding);
+        // the cell search reaches 1e-9 further, past any rounding of a box distance
+        m->pi_tie = 1e-12 * scale;
+        m->pi_slack = 1e-9 * scale;
+        m->pi_ready = true;
+        return SG_OK;
+    } catch (const std::bad_alloc&) {
+        free_pi(m);
+        return fail(SG_E_OOM, "out of host memory");
+    }
+}
+
+int check_pi_opts(const sg_pi_opts* in, sg_pi_opts& o) {
+    sg_pi_opts_default(&o);
+    if (in) o = *in;
+    if (!(o.step > 0.f)) o.step = 0.01f;
+    if (!(o.step <= 1.f)) return fail(SG_E_ARG, "PI step must be in (0, 1]");
+    if (o.max_steps <= 0) o.max_steps = (int32_t)std::ceil(8.0 / (double)o.step);
+    if (o.search != SG_PI_GRID && o.search != SG_PI_SCAN) return fail(SG_E_ARG, "unknown PI search %d", o.search);
+    return SG_OK;
 }
 
 // Checks the arguments of a forward call and fills its kernel arguments.
@@ -409,6 +609,7 @@ int pack_mesh(const float* X_host, int64_t n_verts, const int32_t* F_host, int64
         out.F = std::move(F);
         out.n_verts = n_verts;
         out.n_faces = n_faces;
+        out.face_off = fo;
         return pack_geometry(X_host, out);
 
     } catch (const std::bad_alloc&) {
@@ -556,8 +757,8 @@ int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, 
         free_mesh(m);
         return rc;
     }
+    m->hX = std::move(pm.X);
     pm.X.clear();
-    pm.X.shrink_to_fit();
     pm.geo.clear();
     pm.geo.shrink_to_fit();
     m->host = std::move(pm);
@@ -583,6 +784,11 @@ int sg_mesh_update_vertices(sg_mesh mesh, const float* X_host, int64_t n_verts) 
         return rc;
     }
     hipError_t e = hipDeviceSynchronize();   // no walk may read the records while they change
+    {
+        std::lock_guard<std::mutex> lock(mesh->pi_mu);
+        free_pi(mesh);   // the projection grid is rebuilt for the new positions on its next use
+        mesh->hX.assign(X_host, X_host + 3 * n_verts);
+    }
     if (e == hipSuccess) e = hipMemcpy(mesh->d_face, pm.face.data(), pm.face.size() * sizeof(FaceRec), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(mesh->d_half, pm.half.data(), pm.half.size() * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(mesh->d_X, X_host, (size_t)n_verts * 3 * sizeof(float), hipMemcpyHostToDevice);
@@ -852,6 +1058,92 @@ int sg_autotune(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const
     opts->walk_blocks = win.blocks;
     opts->rays_per_lane = win.rpl;
     if (best_ms) *best_ms = best;
+    return SG_OK;
+}
+
+void sg_pi_opts_default(sg_pi_opts* o) {
+    if (!o) return;
+    o->step = 0.01f;
+    o->max_steps = 0;
+    o->search = SG_PI_GRID;
+}
+
+int sg_pi_exp(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v, int32_t K, const float* W,
+              int32_t* f_out, float* b_out, float* p_out, float* v_out, float* W_out, int32_t* status,
+              int32_t* n_steps, const sg_pi_opts* pi_opts, void* stream) {
+    if (!mesh) return fail(SG_E_ARG, "mesh is NULL");
+    if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
+    if (K < 0 || K > 64) return fail(SG_E_ARG, "K must be in [0, 64]");
+    sg_pi_opts po;
+    int rc = check_pi_opts(pi_opts, po);
+    if (rc != SG_OK) return rc;
+    if (n == 0) return SG_OK;
+    if (!f || !b || !v || !f_out || !b_out || !p_out || !v_out) return fail(SG_E_ARG, "a required array is NULL");
+    if (K > 0 && (!W || !W_out)) return fail(SG_E_ARG, "W and W_out are required when K > 0");
+    rc = ensure_pi(mesh);
+    if (rc != SG_OK) return rc;
+    sg::PiArgs a{};
+    a.n = n;
+    a.f = f; a.b = b; a.v = v;
+    a.K = K; a.W = W;
+    a.f_out = f_out; a.b_out = b_out; a.p_out = p_out; a.v_out = v_out; a.W_out = W_out;
+    a.status = status; a.n_steps = n_steps;
+    a.step = po.step;
+    a.max_steps = po.max_steps;
+    a.scan = po.search == SG_PI_SCAN;
+    hipError_t e = sg::launch_pi_exp(mesh->pi(), a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "PI launch");
+    return SG_OK;
+}
+
+int sg_pi_backward_workspace_size(sg_mesh mesh, int32_t mode, int64_t n, size_t* bytes) {
+    if (!mesh || !bytes) return fail(SG_E_ARG, "mesh and bytes are required");
+    if (mode != SG_BWD_EP && mode != SG_BWD_GFD) return fail(SG_E_ARG, "unknown mode %d", mode);
+    if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
+    *bytes = sg::pi_bwd_workspace(n, mode);
+    return SG_OK;
+}
+
+int sg_pi_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b, const float* v,
+                   const int32_t* f_out, const float* v_out, const float* g_p, float* grad_v, float* grad_b,
+                   const sg_pi_opts* pi_opts, const sg_opts* opts, void* stream) {
+    if (!mesh) return fail(SG_E_ARG, "mesh is NULL");
+    if (mode != SG_BWD_EP && mode != SG_BWD_GFD) return fail(SG_E_ARG, "unknown mode %d", mode);
+    if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
+    sg_opts o;
+    int rc = check_opts(opts, o, mesh);
+    if (rc != SG_OK) return rc;
+    sg_pi_opts po;
+    rc = check_pi_opts(pi_opts, po);
+    if (rc != SG_OK) return rc;
+    if (n == 0) return SG_OK;
+    if (!f || !b || !v || !g_p || !grad_v || !grad_b) return fail(SG_E_ARG, "a required array is NULL");
+    if (mode == SG_BWD_EP && (!f_out || !v_out)) return fail(SG_E_ARG, "EP needs the forward's f_out and v_out");
+    if (n >= ((int64_t)1 << 29)) return fail(SG_E_ARG, "the PI backward takes fewer than 2^29 queries per call");
+    rc = ensure_pi(mesh);
+    if (rc != SG_OK) return rc;
+    sg::BwdArgs a{};
+    a.n = n;
+    a.mode = mode;
+    a.f = f; a.b = b; a.v = v;
+    a.f_out = f_out; a.v_out = v_out;
+    a.g = g_p;
+    a.grad_v = grad_v; a.grad_b = grad_b;
+    a.eps_v = o.eps_v; a.eps_p = o.eps_p;
+    a.max_steps = o.max_steps;
+    a.snap = o.vertex_snap;
+    sg::PiArgs pa{};
+    pa.step = po.step;
+    pa.max_steps = po.max_steps;
+    pa.scan = po.search == SG_PI_SCAN;
+    const hipStream_t st = (hipStream_t)stream;
+    Workspace ws;
+    rc = take_workspace(o, sg::pi_bwd_workspace(n, mode), st, ws);
+    if (rc != SG_OK) return rc;
+    hipError_t e = sg::launch_pi_backward(mesh->pi(), mesh->dev(), a, pa, ws.p, st);
+    const hipError_t e2 = give_workspace(ws, st);
+    if (e != hipSuccess) return hip_fail(e, "PI backward launch");
+    if (e2 != hipSuccess) return hip_fail(e2, "workspace release");
     return SG_OK;
 }
 

@@ -65,6 +65,42 @@ struct DevMesh {
                                 // padding: one 128-byte line per face
 };
 
+// ---- projection integration (appendix "Projection Integration Exp Map"):
+// the comparison Exp, whose steps project a point onto the nearest point of
+// the mesh.  Faces are kept in user order (the tie rule takes the smallest
+// user face id): the three vertex positions (float32, exact in float64) and
+// the unit normal in float64.
+struct alignas(16) PiFace {
+    float x0[3], x1[3], x2[3];
+    float pad;
+    double n[3];
+};
+static_assert(sizeof(PiFace) == 64, "PiFace is one 64-byte segment");
+
+// Uniform grid over one mesh of a handle: cell (ix, iy, iz) covers
+// [o + i h, o + (i + 1) h] per axis (evaluated in float64) and lists every
+// face whose bounding box, widened by a margin, meets it.  A nearest-point
+// search visits cells in rings around the query's cell and skips those
+// farther than the best distance found, so it returns what a scan over every
+// face would.
+struct PiGrid {
+    float ox, oy, oz, h;      // origin and cell size
+    int32_t nx, ny, nz;       // cells per axis
+    uint32_t cell0;           // first cell of this mesh in the handle's cell arrays
+    int32_t face0, face1;     // the mesh's user face range [face0, face1)
+};
+
+struct PiMesh {
+    const PiFace* face;        // [n_faces] in user order
+    const PiGrid* grid;        // [n_meshes]
+    const uint32_t* cell_start;// [total cells + 1] offsets into cell_face
+    const int32_t* cell_face;  // user face ids
+    int64_t n_faces;
+    int32_t n_meshes;
+    double tie;                // distances within tie of the smallest are a tie (a shared nearest point)
+    double slack;              // extra reach of the cell search over the tie (rounding of box distances)
+};
+
 enum RayStatus : int32_t { kRayOk = 0, kRayMaxSteps = 1, kRayBoundary = 2, kRayBadInput = 3 };
 
 }  // namespace sg

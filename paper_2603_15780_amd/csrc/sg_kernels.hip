@@ -2856,6 +2856,12 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
     return hipGetLastError();
 }
 
+hipError_t launch_ep_saved(const DevMesh& M, const BwdArgs& a, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ep_saved, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, M, a);
+    return hipGetLastError();
+}
+
 int walk_blocks_per_cu() {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk<false, false, false>, 256, 0) != hipSuccess || nb <= 0) nb = 1;

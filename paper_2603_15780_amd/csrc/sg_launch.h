@@ -66,6 +66,7 @@ struct PackedMesh {
     std::vector<int32_t> twin;        // half-edge across each edge (internal ids), -1 on the boundary
     std::vector<uint8_t> vbnd;        // vertex lies on a boundary edge
     std::vector<float> geo;           // [n_faces, 16]: per-face vertex positions and user id (DevMesh::geo)
+    std::vector<int64_t> face_off;    // [n_meshes + 1] user face offsets of the batched meshes
     int64_t n_verts = 0, n_faces = 0;
     double mean_edge = 0.0;
     int32_t has_flip = 0;
@@ -105,6 +106,36 @@ hipError_t launch_exp_persistent(const DevMesh& M, const ExpArgs& a, void* ws, c
                                  hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 int walk_blocks_per_cu();
 int part_blocks_per_cu();
+
+// ---- projection integration (appendix "Projection Integration Exp Map")
+// T: float for the ABI's arrays, double for the backward's internal stacks.
+template <class T>
+struct PiArgsT {
+    int64_t n;
+    const int32_t* f;   // user face ids
+    const T* b;
+    const T* v;
+    int32_t K;
+    const T* W;         // [n, K, 3] or null (K = 0)
+    int32_t* f_out;
+    T* b_out;
+    T* p_out;
+    T* v_out;
+    T* W_out;
+    int32_t* status;
+    int32_t* n_steps;
+    double step;        // s
+    int32_t max_steps;
+    int32_t scan;       // 1: scan every face of the mesh (the printed form), 0: grid search
+};
+using PiArgs = PiArgsT<float>;
+hipError_t launch_pi_exp(const PiMesh& P, const PiArgs& a, hipStream_t s);
+// EP (saved f', v') or GFD (seven PI walks per query, stacked in two launches).
+size_t pi_bwd_workspace(int64_t n, int32_t mode);
+hipError_t launch_pi_backward(const PiMesh& P, const DevMesh& M, const BwdArgs& a, const PiArgs& pa, void* ws,
+                              hipStream_t s);
+// The extrinsic proxy from saved outputs (shared by both Exp maps).
+hipError_t launch_ep_saved(const DevMesh& M, const BwdArgs& a, hipStream_t s);
 
 // Backward of the exponential map (extrinsic proxy or geodesic finite differences).
 size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip, bool vjp, bool gradx, int64_t n_faces,

@@ -19,6 +19,7 @@ RAY_OK, RAY_MAXSTEPS, RAY_BOUNDARY, RAY_BADINPUT = 0, 1, 2, 3
 KERNEL_AUTO, KERNEL_PLAIN, KERNEL_PERSISTENT, KERNEL_PARTITIONED = 0, 1, 2, 3
 BWD_EP, BWD_GFD = 0, 1
 BOUNDARY_STOP, BOUNDARY_AVOID = 0, 1
+PI_GRID, PI_SCAN = 0, 1
 
 _lib = None
 
@@ -36,6 +37,10 @@ class Opts(C.Structure):
                 ("ray_queues", C.c_int32), ("boundary_mode", C.c_int32), ("gradx_records", C.c_int32),
                 ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_uint64)]
+
+
+class PiOpts(C.Structure):
+    _fields_ = [("step", C.c_float), ("max_steps", C.c_int32), ("search", C.c_int32)]
 
 
 def lib_path() -> str:
@@ -76,6 +81,13 @@ def lib():
         L.sg_backward_workspace_size.restype = C.c_int
         L.sg_autotune.argtypes = [P, I64, P, P, P, I32, P, C.POINTER(Opts), C.POINTER(C.c_double), P]
         L.sg_autotune.restype = C.c_int
+        L.sg_pi_opts_default.argtypes = [C.POINTER(PiOpts)]
+        L.sg_pi_exp.argtypes = [P, I64, P, P, P, I32, P, P, P, P, P, P, P, P, C.POINTER(PiOpts), P]
+        L.sg_pi_exp.restype = C.c_int
+        L.sg_pi_backward.argtypes = [P, I32, I64, P, P, P, P, P, P, P, P, C.POINTER(PiOpts), C.POINTER(Opts), P]
+        L.sg_pi_backward.restype = C.c_int
+        L.sg_pi_backward_workspace_size.argtypes = [P, I32, I64, C.POINTER(C.c_size_t)]
+        L.sg_pi_backward_workspace_size.restype = C.c_int
         L.sg_mesh_walk_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.sg_mesh_walk_time.restype = C.c_int
         _lib = L
@@ -92,6 +104,18 @@ def opts(**kw) -> Opts:
     lib().sg_opts_default(C.byref(o))
     for k, v in kw.items():
         setattr(o, k, v)
+    return o
+
+
+def pi_opts(step=None, max_steps=None, search=None) -> PiOpts:
+    o = PiOpts()
+    lib().sg_pi_opts_default(C.byref(o))
+    if step is not None:
+        o.step = step
+    if max_steps is not None:
+        o.max_steps = max_steps
+    if search is not None:
+        o.search = search
     return o
 
 
@@ -221,6 +245,54 @@ class Mesh:
             _dptr(out.get("n_cross")), _dptr(out.get("hash")), C.byref(o), _stream())
         _check(rc)
         return out
+
+    def pi_exp(self, f, b, v, W=None, *, step=None, max_steps=None, search=None, want_steps=False):
+        """The projection-integration Exp (sg_pi_exp) for torch CUDA tensors as in exp()."""
+        import torch
+        n = f.shape[0]
+        dev = f.device
+        assert f.dtype == torch.int32 and b.dtype == torch.float32 and v.dtype == torch.float32
+        assert f.is_contiguous() and b.is_contiguous() and v.is_contiguous()
+        assert b.shape == (n, 3) and v.shape == (n, 3)
+        K = 0 if W is None else W.shape[1]
+        if W is not None:
+            assert W.dtype == torch.float32 and W.is_contiguous() and W.shape == (n, K, 3)
+        out = dict(
+            f=torch.empty(n, dtype=torch.int32, device=dev),
+            b=torch.empty(n, 3, dtype=torch.float32, device=dev),
+            p=torch.empty(n, 3, dtype=torch.float32, device=dev),
+            v=torch.empty(n, 3, dtype=torch.float32, device=dev),
+            W=torch.empty(n, K, 3, dtype=torch.float32, device=dev) if K else None,
+            status=torch.empty(n, dtype=torch.int32, device=dev),
+            n_steps=torch.empty(n, dtype=torch.int32, device=dev) if want_steps else None,
+        )
+        po = pi_opts(step, max_steps, search)
+        _check(lib().sg_pi_exp(self._h, n, _dptr(f), _dptr(b), _dptr(v), K, _dptr(W), _dptr(out["f"]),
+                               _dptr(out["b"]), _dptr(out["p"]), _dptr(out["v"]), _dptr(out["W"]),
+                               _dptr(out["status"]), _dptr(out["n_steps"]), C.byref(po), _stream()))
+        return out
+
+    def pi_backward(self, mode, f, b, v, g, *, f_out=None, v_out=None, step=None, max_steps=None, search=None,
+                    o: Opts | None = None, **kw):
+        """(grad_v, grad_b) of the PI map for upstream g = dL/dp' [n,3] (sg_pi_backward)."""
+        import torch
+        n = f.shape[0]
+        dev = f.device
+        assert f.dtype == torch.int32 and b.dtype == torch.float32 and v.dtype == torch.float32
+        assert g.dtype == torch.float32 and g.is_contiguous() and g.shape == (n, 3)
+        if o is None:
+            o = opts(**kw)
+        po = pi_opts(step, max_steps, search)
+        gv = torch.empty(n, 3, dtype=torch.float32, device=dev)
+        gb = torch.empty(n, 3, dtype=torch.float32, device=dev)
+        _check(lib().sg_pi_backward(self._h, int(mode), n, _dptr(f), _dptr(b), _dptr(v), _dptr(f_out), _dptr(v_out),
+                                    _dptr(g), _dptr(gv), _dptr(gb), C.byref(po), C.byref(o), _stream()))
+        return gv, gb
+
+    def pi_backward_workspace_size(self, mode, n):
+        nb = C.c_size_t()
+        _check(lib().sg_pi_backward_workspace_size(self._h, int(mode), n, C.byref(nb)))
+        return nb.value
 
     def backward(self, mode, f, b, v, g, *, f_out=None, v_out=None, out=None, grad_X=None, want_vjp=True,
                  g_b=None, g_v=None, g_W=None, o: Opts | None = None, **kw):

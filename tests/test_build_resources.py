@@ -23,17 +23,18 @@ WALK_LDS = {"k_walk": 0, "k_walk2": 0, "k_walk_bwd": 0, "k_exp_plain": 0, "k_wal
 def remarks(tmp_path_factory):
     if not shutil.which(B.HIPCC) and not os.path.exists(B.HIPCC):
         pytest.skip("hipcc not available")
-    out = tmp_path_factory.mktemp("res") / "k.o"
-    cmd = [B.HIPCC, *B.HIP_FLAGS, "--cuda-device-only", "-c", "-Rpass-analysis=kernel-resource-usage",
-           "-I", os.path.join(B.ROOT, "include"), "-I", B.CSRC, os.path.join(B.CSRC, "sg_kernels.hip"), "-o", str(out)]
-    r = subprocess.run(cmd, capture_output=True, text=True, check=True)
     kernels = {}
-    for block in r.stderr.split("Function Name: ")[1:]:
-        name = block.split()[0]
-        sc = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", block)
-        lds = re.search(r"LDS Size \[bytes/block\]: (\d+)", block)
-        if sc and lds:
-            kernels[name] = (int(sc.group(1)), int(lds.group(1)))
+    for src in (s for s in B.SOURCES if s.endswith(".hip")):
+        out = tmp_path_factory.mktemp("res") / (src + ".o")
+        cmd = [B.HIPCC, *B.HIP_FLAGS, "--cuda-device-only", "-c", "-Rpass-analysis=kernel-resource-usage",
+               "-I", os.path.join(B.ROOT, "include"), "-I", B.CSRC, os.path.join(B.CSRC, src), "-o", str(out)]
+        r = subprocess.run(cmd, capture_output=True, text=True, check=True)
+        for block in r.stderr.split("Function Name: ")[1:]:
+            name = block.split()[0]
+            sc = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", block)
+            lds = re.search(r"LDS Size \[bytes/block\]: (\d+)", block)
+            if sc and lds:
+                kernels[name] = (int(sc.group(1)), int(lds.group(1)))
     assert kernels, "no resource remarks parsed"
     return kernels
 
