@@ -14,11 +14,18 @@ geodesic finite differences, which re-walk seven geodesics per query; each
 with and without the float64 vertex-position gradient, which re-walks twice)
 are timed on the same batch and reported beside it.
 
+The projection-integration Exp map (the paper's comparison Exp) is timed on
+the same batch (`pi`), with its extrinsic proxy and geodesic finite
+differences.
+
 Prints one JSON line.  `value` is face-crossings per second (the crossing
 count is the float64 oracle's when the CPU-baseline leg traces the whole
 batch, else the GPU's).  The roofline object prices the walk kernel against
 HBM bandwidth with 16 algorithmic bytes per crossing plus 64 bytes per ray
-(its 32-byte state in and out).
+(its 32-byte state in and out); `whole_call` prices the whole forward call
+(16 bytes per crossing plus the queries' 144 + 24 K bytes), and each
+fwd_bwd form carries the algorithmic bytes of its backward and their
+fraction of the HBM peak over the backward's time.
 """
 from __future__ import annotations
 
@@ -102,6 +109,11 @@ def main():
     ap.add_argument("--refill", type=int, default=0, help="persistent kernel refill threshold (0: library default)")
     ap.add_argument("--walk-blocks", type=int, default=0, help="persistent kernel blocks (0: library default, two per CU)")
     ap.add_argument("--calib-copy", type=int, default=0, help="MiB copied once to calibrate byte counters")
+    ap.add_argument("--graph", type=int, default=-1,
+                    help="1: time HIP-graph replays of the call (caller workspace); 0: eager calls; "
+                         "-1: graph for the 64-mesh batch, eager otherwise")
+    ap.add_argument("--no-pi", action="store_true", help="skip timing the projection-integration map")
+    ap.add_argument("--pi-rays", type=int, default=0, help="rays for the PI leg (0: the whole batch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -140,6 +152,10 @@ def main():
 
     base = sg.opts(kernel=args.kernel, refill_min=args.refill, walk_blocks=args.walk_blocks)
     tuned = None
+    if args.graph < 0:
+        args.graph = 1 if args.config == 3 else 0
+    if args.config == 3 and args.kernel == 0:
+        args.autotune = True   # the 64-mesh batch runs the schedule the autotuner picks for it
     if args.kernel == 0 and args.autotune:
         t1 = time.time()
         base, tune_ms = mesh.autotune(t["f"], t["b"], t["v"], t["W"], o=base)
@@ -149,8 +165,17 @@ def main():
 
     def opts_for(kernel=None, debug=0):
         o = sg.opts(kernel=base.kernel if kernel is None else kernel, refill_min=base.refill_min,
-                    walk_blocks=base.walk_blocks)
+                    walk_blocks=base.walk_blocks, rays_per_lane=base.rays_per_lane, ray_queues=base.ray_queues)
         o.debug = debug
+        return o
+
+    # a caller workspace, allocated once outside the timed region: the calls allocate nothing
+    ws_bytes = mesh.exp_workspace_size(n, K, o=opts_for(debug=1))
+    ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+
+    def with_ws(o):
+        o.workspace = ws.data_ptr()
+        o.workspace_bytes = ws.numel()
         return o
 
     def timed(o, steps, warmup):
@@ -174,8 +199,28 @@ def main():
         return ((w1 - w0) * 1e3 / steps, evs[0].elapsed_time(evs[-1]) / steps, (wms / wn if wn else None),
                 per[steps // 2] if steps % 2 else 0.5 * (per[steps // 2 - 1] + per[steps // 2]))
 
-    main_o = opts_for(debug=1 | (4 if base.kernel != sg.KERNEL_PLAIN else 0))
+    main_o = with_ws(opts_for(debug=1 | (4 if base.kernel != sg.KERNEL_PLAIN else 0)))
     ms_step, ms_call, ms_walk, ms_call_median = timed(main_o, args.steps, args.warmup)
+    graph = None
+    if args.graph:
+        # the same call captured once in a HIP graph and replayed (launch-bound meshes gain most)
+        go = with_ws(opts_for(debug=1))
+        mesh.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=go)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            mesh.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=go)
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        ms_graph = (time.perf_counter() - w0) * 1e3 / args.steps
+        graph = {"ms_per_step": ms_graph, "eager_ms_per_step": ms_step}
+        log(f"graph replay: {ms_graph:.3f} ms/step (eager {ms_step:.3f})")
+        ms_step = ms_graph
     # dominant kernel: the persistent walk (events the library records around it), or the plain kernel
     ms_kernel = ms_walk if ms_walk is not None else ms_call
     gpu_cross = int(out["n_cross"].sum().item())
@@ -213,14 +258,16 @@ def main():
             def call():
                 mesh.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=fo)
                 if not with_x:
-                    mesh.backward(mode, t["f"], t["b"], t["v"], g_up, f_out=out["f"], v_out=out["v"], out=(gv, gb),
-                                  o=bo)
+                    mesh.backward(mode, t["f"], t["b"], t["v"], g_up, f_out=out["f"], b_out=out["b"], v_out=out["v"],
+                                  status=out["status"], out=(gv, gb), o=bo)
                     return
                 gX.zero_()
                 for a in range(0, n, gx_slice):
                     z = slice(a, min(n, a + gx_slice))
                     mesh.backward(mode, t["f"][z], t["b"][z], t["v"][z], g_up[z], f_out=out["f"][z],
-                                  v_out=out["v"][z], out=(gv[z], gb[z]), grad_X=gX, o=bo_x)
+                                  b_out=out["b"][z], v_out=out["v"][z], status=out["status"][z],
+                                  out=(gv[z], gb[z]), grad_X=gX,
+                                  o=bo_x)
             for _ in range(max(1, args.warmup)):
                 call()
             torch.cuda.synchronize()
@@ -230,7 +277,8 @@ def main():
             torch.cuda.synchronize()
             ms = (time.perf_counter() - w0) * 1e3 / steps
             bwd[name] = {"ms_fwd_plus_bwd": ms, "ms_bwd": ms - ms_step, "queries_per_s": n / (ms * 1e-3),
-                         "finite": bool(torch.isfinite(gv).all().item()) and bool(torch.isfinite(gX).all().item())}
+                         "finite": bool(torch.isfinite(gv).all().item()) and bool(torch.isfinite(gX).all().item()),
+                         "mode": name}
             log(f"forward + {name} backward: {ms:.3f} ms/step ({n / (ms * 1e-3):.3e} queries/s)")
     if args.calib_copy:
         # a plain copy of known size, profiled beside the walk to scale the HBM byte counters
@@ -264,8 +312,56 @@ def main():
         log(f"oracle: {ocross} crossings in {c1 - c0:.2f}s on {cores} threads; GPU/oracle crossing ratio "
             f"{gpu_cross / max(ocross, 1) if rows.shape[0] == n else float('nan'):.6f}")
     if bwd:
-        for b in bwd.values():   # forward-path crossings per second of the whole fwd + bwd step
+        # algorithmic bytes of each backward (the paper's schemes, SURVEY's per-step counts):
+        # EP streams ~152 B per query (query, saved f' and v', g, both gradients, start and end
+        # faces' vertices) and walks nothing; GFD walks its four long geodesics (the base, the
+        # e_perp-perturbed one and the two start-shifted ones; the three short ones cross almost
+        # nothing) at 16 B per crossing, with 64 B of chart state in and out per walk and query;
+        # the vertex gradient adds one adjoint walk (16 B per crossing), the float64 sums
+        # (6 per half-edge) and grad_X (24 B per vertex).
+        n_he = 3 * int(F_or.shape[0])
+        per_q = 152
+        algo = {"ep": n * per_q,
+                "gfd": 4 * cross * BYTES_PER_CROSSING + n * (per_q + 7 * 64)}
+        gx_extra = cross * BYTES_PER_CROSSING + n * 64 + n_he * 6 * 8 + int(X.shape[0]) * 24
+        algo["ep+gradX"] = algo["ep"] + gx_extra
+        algo["gfd+gradX"] = algo["gfd"] + gx_extra
+        for name, b in bwd.items():   # forward-path crossings per second of the whole fwd + bwd step
             b["crossings_per_s"] = cross / (b["ms_fwd_plus_bwd"] * 1e-3)
+            b["algorithmic_bytes_bwd"] = algo[name]
+            b["frac_bwd"] = algo[name] / (b["ms_bwd"] * 1e-3) / 1e9 / HBM_PEAK_GBS if b["ms_bwd"] > 0 else None
+            b.pop("mode", None)
+
+    pi = None
+    if not args.no_pi and args.config in (1, 2):
+        # the projection-integration Exp (float64 steps of s = 0.01, grid search for the nearest
+        # point), its EP from the saved outputs and its GFD (seven PI maps per query), on the same
+        # batch or its first --pi-rays rays
+        npi = min(n, args.pi_rays) if args.pi_rays else n
+        tp = {k: (vv[:npi].contiguous() if vv is not None else None) for k, vv in t.items()}
+        g_pi = torch.from_numpy(CF.upstream_grad(args.config, npi)).to(dev)
+
+        def pi_timed(fn, steps):
+            fn()
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            for _ in range(steps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - w0) * 1e3 / steps
+        po = {}
+        ms_pi = pi_timed(lambda: po.update(mesh.pi_exp(tp["f"], tp["b"], tp["v"], tp["W"], want_steps=True)), 3)
+        psteps = int(po["n_steps"].sum().item())
+        ms_pi_ep = pi_timed(lambda: mesh.pi_backward(sg.BWD_EP, tp["f"], tp["b"], tp["v"], g_pi, f_out=po["f"],
+                                                     v_out=po["v"]), 3)
+        ms_pi_gfd = pi_timed(lambda: mesh.pi_backward(sg.BWD_GFD, tp["f"], tp["b"], tp["v"], g_pi), 2)
+        ms_sg = ms_step * npi / n   # the straightest map on the same rays (per-ray share of the timed call)
+        pi = {"rays": npi, "step": 0.01, "search": "grid", "precision": "f64",
+              "ms_per_call": ms_pi, "queries_per_s": npi / (ms_pi * 1e-3), "projection_steps": psteps,
+              "steps_per_s": psteps / (ms_pi * 1e-3), "ms_ep_bwd": ms_pi_ep, "ms_gfd_bwd": ms_pi_gfd,
+              "slowdown_vs_straightest": ms_pi / ms_sg}
+        log(f"PI exp map: {ms_pi:.2f} ms for {npi} rays ({psteps} projection steps), EP {ms_pi_ep:.2f} ms, "
+            f"GFD {ms_pi_gfd:.2f} ms; {ms_pi / ms_sg:.1f}x the straightest map's time")
 
     # algorithmic bytes: 16 per crossing (next face's shape in the crossed edge's frame and its two
     # onward links); per ray the walk kernel reads and writes a 32-byte chart state, while the whole
@@ -297,6 +393,8 @@ def main():
         "speedup_over_plain": (plain["ms_per_call"] / ms_step) if plain else None,
         "queries_per_s": n / (ms_step * 1e-3),
         "fwd_bwd": bwd,
+        "pi": pi,
+        "graph": graph,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if (args.config == 2 and ms_walk is not None and not tuned
@@ -304,11 +402,14 @@ def main():
                                                        and not args.walk_blocks) else None,
                      "kernel": "k_walk (persistent walk)" if ms_walk is not None else "k_exp_plain",
                      "algorithmic_bytes_per_launch": algo_bytes, "kernel_ms": ms_kernel,
-                     # the same launch counted at the 32-byte face record the walk gathers per crossing
-                     "frac_at_record_size": (32 * cross + (algo_bytes - 16 * cross)) / (ms_kernel * 1e-3) / 1e9
-                                            / HBM_PEAK_GBS,
-                     "whole_call": {"ms": ms_call, "algorithmic_bytes": call_bytes,
-                                    "achieved_GBs": call_bytes / (ms_call * 1e-3) / 1e9}},
+                     # what the walk's loads request from the cache hierarchy per crossing (32 of its
+                     # 64-byte face record), over the same time: an L2 request rate, not HBM traffic
+                     "l2_request_GBs_at_32B": (32 * cross + (algo_bytes - 16 * cross)) / (ms_kernel * 1e-3) / 1e9,
+                     "whole_call": {"ms": ms_step, "algorithmic_bytes": call_bytes,
+                                    "achieved_GBs": call_bytes / (ms_step * 1e-3) / 1e9,
+                                    "frac": call_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                    "target_frac": 0.40,
+                                    "meets_target": call_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS >= 0.40}},
         "cpu_baseline": cpu,
         "mesh_device_bytes": info["device_bytes"],
         "mesh_pack_s": pack_s,

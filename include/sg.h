@@ -87,7 +87,8 @@ typedef struct {
     float eps_v, eps_p;    /* GFD step sizes (absolute lengths); <= 0: 5e-3 * mean edge of the handle */
     int32_t kernel;        /* SG_KERNEL_*: which forward kernel runs the walk */
     uint32_t debug;        /* bit 0: fill n_cross; bit 1: fill seq_hash (FNV-1a 64 of the visited face ids);
-                              bit 2: time the walk kernel with HIP events (read with sg_mesh_walk_time) */
+                              bit 2: time the walk kernel with HIP events (read with sg_mesh_walk_time);
+                              bit 3 (sg_autotune): tune again even for a cached class of batches */
     int32_t refill_min;    /* persistent kernel: a wave refetches rays once this many of its 64 lanes are
                               idle (of 128 ray slots with two rays per lane); <= 0: 32 per 64 slots */
     int32_t walk_blocks;   /* persistent kernel: 256-lane blocks launched; <= 0: three per CU */
@@ -204,7 +205,8 @@ int sg_exp_transport_noalloc(sg_mesh mesh, int64_t n, const int32_t* f, const fl
 /*
  * Backward of the exponential map (Sec. 4 "Differentiation").  Given
  * g_p[n,3] = dL/dp' (float32, device) for the queries (f, b, v) of an earlier
- * sg_exp call, returns
+ * sg_exp call, and optionally that call's saved outputs f_out[n], b_out[n,3],
+ * v_out[n,3] and status[n] (each nullable), returns
  *   grad_v[n,3] = dL/dv (tangent to the start face) and
  *   grad_b[n,3] = dL/db (component k = G . x_k, where G is the in-plane
  *                 gradient of L with respect to the start point),
@@ -217,19 +219,26 @@ int sg_exp_transport_noalloc(sg_mesh mesh, int64_t n, const int32_t* f, const fl
  *        and walks nothing; otherwise (those two may be NULL) it re-walks the
  *        geodesic to find the end normal's orientation.
  *   mode SG_BWD_GFD (eqs. jv, jp and chain): geodesic finite differences with
- *        step sizes opts->eps_v, opts->eps_p.  Re-walks seven geodesics per
+ *        step sizes opts->eps_v, opts->eps_p.  Walks seven geodesics per
  *        query (the base, the e_perp-perturbed one, two short start-point
  *        steps, then the e_par step from p' and the two start-point-shifted
- *        geodesics) in two persistent passes; nothing of the forward is read.
+ *        geodesics) in two persistent passes.  With f_out, b_out and v_out
+ *        given, on meshes whose faces agree in orientation, the base
+ *        geodesic's end is taken from them (Appendix "Speed-up GFD and EP
+ *        through batching": Exp(p, v) is the forward's) and six are walked.
  *        |v_t| = 0 takes e_par = e_u (the start face's x1 - x0 direction).
  *   grad_X (an extension; the paper has no vertex gradient): the exact
  *        derivative of p' = H_m o ... o H_1(p + v_t), the composition of the
  *        rigid unfoldings about the crossed edges, with the combinatorics
- *        frozen.  The geodesic is re-walked twice (end frame, then the
- *        adjoint's per-edge terms, one record per crossing, summed per
- *        half-edge in float64 after grouping by half-edge range), then one
- *        pass maps each crossed edge's sums to its four hinge vertices with
- *        float64 atomics.  Rays
+ *        frozen.  The geodesic is re-walked for the adjoint's per-edge
+ *        terms (one record per crossing, summed per half-edge in float64
+ *        after grouping by half-edge range), then one pass maps each crossed
+ *        edge's sums to its four hinge vertices with float64 atomics.  The
+ *        adjoint starts from the end frame: taken from the forward's saved
+ *        f_out, v_out and status when all three are given, the faces agree
+ *        in orientation, hole avoidance is off and the mode is EP (or only
+ *        grad_X is asked for); otherwise from one more walk (GFD walks it
+ *        anyway).  Rays
  *        whose walk ends with a status other than SG_RAY_OK contribute
  *        nothing.  A vertex passage is not a hinge: such rays contribute their
  *        edge and start terms with the vertex rule held fixed, which is not
@@ -243,8 +252,9 @@ int sg_exp_transport_noalloc(sg_mesh mesh, int64_t n, const int32_t* f, const fl
  * persistent walk always runs).  n < 2^31 (SG_E_ARG otherwise).
  */
 int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b, const float* v,
-                    const int32_t* f_out, const float* v_out, const float* g_p,
-                    float* grad_v, float* grad_b, double* grad_X, const sg_opts* opts, void* stream);
+                    const int32_t* f_out, const float* b_out, const float* v_out, const int32_t* status,
+                    const float* g_p, float* grad_v, float* grad_b, double* grad_X, const sg_opts* opts,
+                    void* stream);
 
 /*
  * sg_exp_backward with cotangents of every output of an earlier
@@ -263,9 +273,11 @@ int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, con
  * grad_X takes the g_p and g_b terms.  Other arguments as for sg_exp_backward.
  */
 int sg_exp_backward_transport(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b,
-                              const float* v, int32_t K, const int32_t* f_out, const float* v_out, const float* g_p,
-                              const float* g_b, const float* g_v, const float* g_W, float* grad_v, float* grad_b,
-                              float* grad_W, double* grad_X, const sg_opts* opts, void* stream);
+                              const float* v, int32_t K, const int32_t* f_out, const float* b_out,
+                              const float* v_out, const int32_t* status, const float* g_p, const float* g_b,
+                              const float* g_v,
+                              const float* g_W, float* grad_v, float* grad_b, float* grad_W, double* grad_X,
+                              const sg_opts* opts, void* stream);
 
 /*
  * Device workspace (bytes, host output) that sg_exp / sg_exp_transport need
@@ -338,12 +350,18 @@ int sg_pi_backward_workspace_size(sg_mesh mesh, int32_t mode, int64_t n, size_t*
  * caller's batch fastest).  Times sg_exp_transport on the given queries
  * (device arrays as in sg_exp_transport; a representative sample is enough)
  * for the plain kernel and for the persistent kernel over rays per lane,
- * refill thresholds (the compaction period) and resident blocks per CU (waves
- * per SIMD), then writes the fastest kernel, rays_per_lane, refill_min and
- * walk_blocks into *opts (its other
- * fields are kept and used).  Synchronizes `stream`; allocates and frees
- * its own scratch outputs.  Not capturable.  *best_ms (nullable) receives
- * the winner's time per call.
+ * refill thresholds (the compaction period), resident blocks per CU (waves
+ * per SIMD) and ray queues, then writes the fastest kernel, rays_per_lane,
+ * refill_min,
+ * walk_blocks, ray_queues into *opts (its other fields are kept and used).
+ * Synchronizes `stream`; allocates and frees its own scratch outputs and
+ * workspace (before any timing).  Not capturable.  *best_ms (nullable)
+ * receives the winner's time per call.
+ * The pick is cached per process, keyed by device (gfx arch, CU count), the
+ * mesh's face-count class (power of two), the batch's size class, K, the
+ * boundary rule and its length class (mean |v| of a 256-ray sample, in half
+ * octaves of the mean edge); a batch of a cached class gets the cached pick
+ * without timing.  opts->debug bit 3 forces a new tuning (and recaches).
  */
 int sg_autotune(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const float* v, int32_t K,
                 const float* W, sg_opts* opts, double* best_ms, void* stream);

@@ -13,10 +13,12 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "sg.h"
@@ -229,8 +231,11 @@ int check_bwd_opts(const sg_opts* in, sg_opts& o, sg_mesh m) {
     return rc;
 }
 
-size_t bwd_workspace_bytes(const sg_opts& o, sg_mesh m, int64_t n, int32_t mode, bool vjp, bool gradx) {
-    return sg::bwd_workspace(n, mode, m->has_flip != 0, vjp, gradx, m->n_faces, o.gradx_records, o.walk_blocks);
+// have_*: which saved forward outputs the call is given (none: the size that covers every call)
+size_t bwd_workspace_bytes(const sg_opts& o, sg_mesh m, int64_t n, int32_t mode, bool vjp, bool gradx,
+                           bool have_f = false, bool have_b = false, bool have_v = false, bool have_status = false) {
+    return sg::bwd_workspace(n, mode, m->has_flip != 0, vjp, gradx, m->n_faces, o.gradx_records, o.walk_blocks,
+                             o.boundary_mode != SG_BOUNDARY_STOP, have_f, have_b, have_v, have_status);
 }
 
 size_t exp_workspace_bytes(const sg_opts& o, int64_t n, int32_t K) {
@@ -408,6 +413,31 @@ int check_pi_opts(const sg_pi_opts* in, sg_pi_opts& o) {
     if (o.max_steps <= 0) o.max_steps = (int32_t)std::ceil(8.0 / (double)o.step);
     if (o.search != SG_PI_GRID && o.search != SG_PI_SCAN) return fail(SG_E_ARG, "unknown PI search %d", o.search);
     return SG_OK;
+}
+
+// Autotuner cache (per process): the schedule picked for a class of batches.
+struct TuneKey {
+    std::string arch;
+    int cus, fclass, nclass, K, lclass, boundary;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(arch, cus, fclass, nclass, K, lclass, boundary) <
+               std::tie(o.arch, o.cus, o.fclass, o.nclass, o.K, o.lclass, o.boundary);
+    }
+};
+struct TunePick {
+    int32_t kernel, refill, blocks, rpl, queues;
+    double ms;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TunePick> g_tune;
+
+int ilog2(int64_t x) {
+    int r = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++r;
+    }
+    return r;
 }
 
 // Checks the arguments of a forward call and fills its kernel arguments.
@@ -903,9 +933,10 @@ int sg_exp_transport_noalloc(sg_mesh mesh, int64_t n, const int32_t* f, const fl
 }
 
 int sg_exp_backward_transport(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b,
-                              const float* v, int32_t K, const int32_t* f_out, const float* v_out, const float* g_p,
-                              const float* g_b, const float* g_v, const float* g_W, float* grad_v, float* grad_b,
-                              float* grad_W, double* grad_X, const sg_opts* opts, void* stream) {
+                              const float* v, int32_t K, const int32_t* f_out, const float* b_out,
+                              const float* v_out, const int32_t* status, const float* g_p, const float* g_b,
+                              const float* g_v, const float* g_W, float* grad_v, float* grad_b, float* grad_W,
+                              double* grad_X, const sg_opts* opts, void* stream) {
     if (!mesh) return fail(SG_E_ARG, "mesh is NULL");
     if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
     if (mode != SG_BWD_EP && mode != SG_BWD_GFD) return fail(SG_E_ARG, "unknown backward mode %d", mode);
@@ -930,7 +961,8 @@ int sg_exp_backward_transport(sg_mesh mesh, int32_t mode, int64_t n, const int32
     a.n = n;
     a.mode = mode;
     a.f = f; a.b = b; a.v = v;
-    a.f_out = f_out; a.v_out = v_out;
+    a.f_out = f_out; a.b_out = b_out; a.v_out = v_out;
+    a.status_in = status;
     a.g = g_p;
     a.g_bo = g_b;
     a.g_v = g_v;
@@ -946,7 +978,9 @@ int sg_exp_backward_transport(sg_mesh mesh, int32_t mode, int64_t n, const int32
     const hipStream_t st = (hipStream_t)stream;
     Workspace ws;
     a.gx_records = o.gradx_records;
-    rc = take_workspace(o, bwd_workspace_bytes(o, mesh, n, mode, vjp, a.grad_X != nullptr), st, ws);
+    rc = take_workspace(o, bwd_workspace_bytes(o, mesh, n, mode, vjp, a.grad_X != nullptr, f_out != nullptr,
+                                               b_out != nullptr, v_out != nullptr, status != nullptr),
+                        st, ws);
     if (rc != SG_OK) return rc;
     hipError_t e = sg::launch_backward(mesh->dev(o.boundary_mode), a, ws.p, sched(o), st);
     const hipError_t e2 = give_workspace(ws, st);
@@ -956,11 +990,12 @@ int sg_exp_backward_transport(sg_mesh mesh, int32_t mode, int64_t n, const int32
 }
 
 int sg_exp_backward(sg_mesh mesh, int32_t mode, int64_t n, const int32_t* f, const float* b, const float* v,
-                    const int32_t* f_out, const float* v_out, const float* g_p, float* grad_v, float* grad_b,
-                    double* grad_X, const sg_opts* opts, void* stream) {
+                    const int32_t* f_out, const float* b_out, const float* v_out, const int32_t* status,
+                    const float* g_p, float* grad_v, float* grad_b, double* grad_X, const sg_opts* opts,
+                    void* stream) {
     if (n > 0 && !g_p) return fail(SG_E_ARG, "a required array is NULL");
-    return sg_exp_backward_transport(mesh, mode, n, f, b, v, 0, f_out, v_out, g_p, nullptr, nullptr, nullptr, grad_v,
-                                     grad_b, nullptr, grad_X, opts, stream);
+    return sg_exp_backward_transport(mesh, mode, n, f, b, v, 0, f_out, b_out, v_out, status, g_p, nullptr, nullptr,
+                                     nullptr, grad_v, grad_b, nullptr, grad_X, opts, stream);
 }
 
 int sg_exp_workspace_size(sg_mesh mesh, int64_t n, int32_t K, const sg_opts* opts, size_t* bytes) {
@@ -996,14 +1031,55 @@ int sg_autotune(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const
     sg_opts base;
     int rc = check_opts(opts, base, mesh);
     if (rc != SG_OK) return rc;
+    const bool retune = (opts->debug & 8u) != 0u;
     base.debug = 0u;
     base.workspace = nullptr;
     base.workspace_bytes = 0;
     const hipStream_t st = (hipStream_t)stream;
-    // scratch outputs and events
+    // the cache key: device, mesh size, batch size, K, boundary rule and the batch's
+    // length class (mean |v| over a strided sample of 256 rays, in mean edges)
+    TuneKey key{};
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, mesh->device) != hipSuccess) return fail(SG_E_HIP, "hipGetDeviceProperties");
+        key.arch = prop.gcnArchName;
+        key.cus = mesh->cu_count;
+        key.fclass = ilog2(mesh->n_faces);
+        key.nclass = ilog2(n);
+        key.K = K;
+        key.boundary = base.boundary_mode;
+        const int64_t ns = std::min<int64_t>(n, 256), stride = n / ns;
+        std::vector<float> vs(3 * (size_t)ns);
+        if (hipMemcpy2DAsync(vs.data(), 12, v, (size_t)stride * 12, 12, (size_t)ns, hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return fail(SG_E_HIP, "copy of the length sample");
+        double sum = 0.0;
+        for (int64_t i = 0; i < ns; ++i)
+            sum += std::sqrt((double)vs[3 * i] * vs[3 * i] + (double)vs[3 * i + 1] * vs[3 * i + 1] +
+                             (double)vs[3 * i + 2] * vs[3 * i + 2]);
+        const double rel = sum / (double)ns / std::max(mesh->mean_edge, 1e-30);
+        key.lclass = std::isfinite(rel) ? (int)std::lround(2.0 * std::log2(std::max(rel, 1e-3))) : 0;
+    }
+    if (!retune) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            opts->kernel = it->second.kernel;
+            opts->refill_min = it->second.refill;
+            opts->walk_blocks = it->second.blocks;
+            opts->rays_per_lane = it->second.rpl;
+            opts->ray_queues = it->second.queues;
+            if (best_ms) *best_ms = it->second.ms;
+            return SG_OK;
+        }
+    }
+    // scratch outputs and one workspace for every candidate, allocated before any timing
     void* buf = nullptr;
     const size_t per = 4 + 3 * 12 + (size_t)K * 12 + 4;
-    if (hipMalloc(&buf, per * (size_t)n + 1024) != hipSuccess) return fail(SG_E_OOM, "autotune scratch allocation");
+    const size_t ws_bytes = sg::exp_persistent_workspace(n, K);
+    const size_t out_bytes = (per * (size_t)n + 1024 + 255) & ~(size_t)255;
+    if (hipMalloc(&buf, out_bytes + ws_bytes) != hipSuccess) return fail(SG_E_OOM, "autotune scratch allocation");
     char* q = static_cast<char*>(buf);
     auto carve = [&](size_t bytes) { char* r = q; q += (bytes + 255) & ~(size_t)255; return r; };
     auto* fo = reinterpret_cast<int32_t*>(carve(4 * (size_t)n));
@@ -1011,27 +1087,35 @@ int sg_autotune(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const
     auto* po = reinterpret_cast<float*>(carve(12 * (size_t)n));
     auto* vo = reinterpret_cast<float*>(carve(12 * (size_t)n));
     auto* Wo = K ? reinterpret_cast<float*>(carve(12 * (size_t)K * n)) : nullptr;
+    void* ws = static_cast<char*>(buf) + out_bytes;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         (void)hipFree(buf);
         return fail(SG_E_HIP, "hipEventCreate failed");
     }
-    struct Cand { int32_t kernel, refill, blocks, rpl; };
-    std::vector<Cand> cands;
-    cands.push_back({SG_KERNEL_PLAIN, base.refill_min, base.walk_blocks, 1});
+    // candidates: the plain kernel, and the persistent walk over rays per lane, resident
+    // blocks per CU (waves per SIMD), refill thresholds (the compaction period) and ray queues
+    std::vector<TunePick> cands;
+    cands.push_back({SG_KERNEL_PLAIN, base.refill_min, base.walk_blocks, 1, base.ray_queues, 0.0});
     const int refills[] = {4, 8, 16, 24, 32, 48};
-    for (int rpl = 1; rpl <= 2; ++rpl)
-        for (int bpc = 1; bpc <= mesh->walk_blocks_per_cu; ++bpc)
-            for (int r : refills) cands.push_back({SG_KERNEL_PERSISTENT, r * rpl, bpc * mesh->cu_count, rpl});
+    for (int queues : {8, 16})
+        for (int rpl = 1; rpl <= 2; ++rpl)
+            for (int bpc = 1; bpc <= mesh->walk_blocks_per_cu; ++bpc)
+                for (int r : refills)
+                    if (queues == 8 || rpl == 1)
+                        cands.push_back({SG_KERNEL_PERSISTENT, r * rpl, bpc * mesh->cu_count, rpl, queues, 0.0});
     double best = 1e300;
-    Cand win = cands[1 < cands.size() ? 1 : 0];
+    TunePick win = cands[1 < cands.size() ? 1 : 0];
     rc = SG_OK;
-    for (const Cand& c : cands) {
+    for (const TunePick& c : cands) {
         sg_opts o = base;
         o.kernel = c.kernel;
         o.refill_min = c.refill;
         o.walk_blocks = c.blocks;
         o.rays_per_lane = c.rpl;
+        o.ray_queues = c.queues;
+        o.workspace = c.kernel == SG_KERNEL_PLAIN ? nullptr : ws;
+        o.workspace_bytes = c.kernel == SG_KERNEL_PLAIN ? 0 : ws_bytes;
         double t = 1e300;
         for (int rep = 0; rep < 4 && rc == SG_OK; ++rep) {
             if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(SG_E_HIP, "hipEventRecord failed"); break; }
@@ -1053,10 +1137,16 @@ int sg_autotune(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const
     (void)hipStreamSynchronize(st);
     (void)hipFree(buf);
     if (rc != SG_OK) return rc;
+    win.ms = best;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[key] = win;
+    }
     opts->kernel = win.kernel;
     opts->refill_min = win.refill;
     opts->walk_blocks = win.blocks;
     opts->rays_per_lane = win.rpl;
+    opts->ray_queues = win.queues;
     if (best_ms) *best_ms = best;
     return SG_OK;
 }

@@ -1370,7 +1370,8 @@ SG_HD __forceinline__ void gx_cross(double* acc, const Ray& st, const float4& c)
 // chunks fall back to the atomics.
 constexpr int kGxChunk = 1024;            // records per chunk
 constexpr int kGxMaxBins = 4096;          // bins (LDS counters of the walk and of the scatter)
-constexpr int kGxWindow = 1024;           // half-edges summed in LDS at once by the reduce pass
+constexpr int kGxWindow = 4096;           // half-edges summed in LDS at once by the reduce pass (160 KB)
+constexpr int kGxShift0 = 12;             // log2 of the smallest bin: one reduce window
 constexpr int64_t kGxMaxRecords = (int64_t)1 << 30;   // at most 48 GiB of records (bin starts are 32-bit)
 
 // A record leaves the walk as a streaming (non-temporal) store, so the 24
@@ -1811,18 +1812,18 @@ __global__ __launch_bounds__(1024) void k_gx_scatter(const GxRec* __restrict__ r
 // Sums the records of one bin (one window of kGxWindow half-edges of it per
 // block) in LDS in float64 and adds the totals to the half-edge sums.  Every
 // bin has one owner here, so the adds need no atomics.
-__global__ __launch_bounds__(256) void k_gx_reduce(const GxRec* sorted, const uint32_t* start, int shift, int64_t nh,
-                                                   double* acc) {
+__global__ __launch_bounds__(1024) void k_gx_reduce(const GxRec* sorted, const uint32_t* start, int shift,
+                                                    int64_t nh, double* acc) {
     __shared__ double s[5 * kGxWindow];
     const int wpb = (1 << shift) / kGxWindow;
     const int bin = (int)blockIdx.x / wpb, win = (int)blockIdx.x - bin * wpb;
     const int64_t h0 = ((int64_t)bin << shift) + (int64_t)win * kGxWindow;
     if (h0 >= nh) return;
     const int t = (int)threadIdx.x;
-    for (int k = t; k < 5 * kGxWindow; k += 256) s[k] = 0.0;
+    for (int k = t; k < 5 * kGxWindow; k += 1024) s[k] = 0.0;
     __syncthreads();
     const uint32_t lo = start[bin], hi = start[bin + 1];
-    for (uint32_t i = lo + (uint32_t)t; i < hi; i += 256u) {
+    for (uint32_t i = lo + (uint32_t)t; i < hi; i += 1024u) {
         const GxRec r = sorted[i];
         const int64_t d = (int64_t)r.h - h0;
         if (d >= 0 && d < kGxWindow)
@@ -1830,7 +1831,7 @@ __global__ __launch_bounds__(256) void k_gx_reduce(const GxRec* sorted, const ui
     }
     __syncthreads();
     const int64_t n5 = min((int64_t)5 * kGxWindow, 5 * (nh - h0));
-    for (int64_t k = t; k < n5; k += 256) {
+    for (int64_t k = t; k < n5; k += 1024) {
         const double x = s[k];
         if (x != 0.0) acc[5 * h0 + k] += x;
     }
@@ -2133,18 +2134,52 @@ SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_
         for (int j = 0; j < per_ray; ++j) out[j] = dead_state();
         return;
     }
-    out[0] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, Llo, st) == kInitOk ? pack_state(st) : dead_state();
-    if (per_ray == 1) return;
+    if (per_ray != 3) {   // the base geodesic (three states: its end is the forward's, saved)
+        out[0] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, Llo, st) == kInitOk ? pack_state(st)
+                                                                                          : dead_state();
+        if (per_ray == 1) return;
+        ++out;
+    }
     const float ev = a.eps_v, ep = a.eps_p;
     // |v + eps e_perp| = L + eps^2 / (L + sqrt(L^2 + eps^2)), angle + atan(eps / L)
     const float Lp = sqrtf(fmaf(L, L, ev * ev));
     const float dl = ev * ev / (L + Lp);
     const uint32_t dphi = rad_to_fx(atan2f(ev, L));
-    out[1] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0 + dphi, L, Llo + dl, st) == kInitOk ? pack_state(st)
+    out[0] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0 + dphi, L, Llo + dl, st) == kInitOk ? pack_state(st)
                                                                                                        : dead_state();
-    out[2] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, 0u, ep, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+    out[1] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, 0u, ep, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
     const uint32_t Av = rec_geo(M, 3 * S.f).A;   // angle of e_v = unit(x2 - x0) in the chart
-    out[3] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, Av, ep, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+    out[2] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, Av, ep, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+}
+
+// The end of the base geodesic from the forward's saved outputs: the chart of
+// half-edge 3 f' (x-axis along y1 - y0), the point from b' and the angle of
+// v' in that chart (the start chart's x-axis when |v_t| = 0, as the walk
+// keeps it); h < 0 when the saved end is unusable.
+SG_HD __forceinline__ Final saved_final(const DevMesh& M, const BwdArgs& a, int64_t i) {
+    Final F;
+    F.h = -1;
+    F.ex = F.ey = 0.f;
+    F.phi = 0u;
+    F.flags = 0u;
+    F.ncross = 0;
+    F.hash = 0ull;
+    const int32_t fo = a.f_out[i];
+    if (fo < 0 || (int64_t)fo >= M.n_faces) return F;
+    const int32_t fe = M.perm[fo];
+    const float b0 = a.b_out[3 * i], b1 = a.b_out[3 * i + 1], b2 = a.b_out[3 * i + 2];
+    const float bs = b0 + b1 + b2;
+    if (!(bs > 0.f) || !__builtin_isfinite(bs)) return F;
+    const HalfEdgeRec r = rec_geo(M, 3 * fe);
+    F.h = 3 * fe;
+    F.ex = fmaf(b1 / bs, r.lab, (b2 / bs) * r.cx);
+    F.ey = (b2 / bs) * r.cy;
+    float Lo, Llo;
+    uint32_t ph;
+    start_direction(M, fe, ld3(a.v_out + 3 * i), Lo, Llo, ph);
+    F.phi = Lo > 0.f ? ph : 0u;
+    F.flags = kDoneBit | ((uint32_t)kRayOk << 8);
+    return F;
 }
 
 // Stage 2: the walks that start where stage 1 ended.  Slot 0 is the short
@@ -2158,7 +2193,10 @@ SG_HD void bwd_stage2(const DevMesh& M, const BwdArgs& a, const StateRec* s1, St
     uint32_t phi0;
     float L;
     Ray st;
-    const Final F0 = as_final(s1[4 * at]), Fu = as_final(s1[4 * at + 2]), Fv = as_final(s1[4 * at + 3]);
+    const int per = a.gfd_saved ? 3 : 4;   // pass-1 states per query (the base's first unless saved)
+    const StateRec* q1 = s1 + (int64_t)per * at + (a.gfd_saved ? 0 : 1);
+    const Final F0 = a.gfd_saved ? saved_final(M, a, i) : as_final(s1[4 * at]);
+    const Final Fu = as_final(q1[1]), Fv = as_final(q1[2]);
     if (bwd_query(M, a, i, S, phi0, L) != kInitOk || F0.h < 0 || Fu.h < 0 || Fv.h < 0) {
         out[0] = out[1] = out[2] = dead_state();
         return;
@@ -2195,7 +2233,9 @@ SG_HD void gfd_assemble(const DevMesh& M, const BwdArgs& a, const StateRec* s1, 
     uint32_t phi0;
     float L;
     const int64_t at = bwd_at(a, i);
-    const Final F0 = as_final(s1[4 * at]), Fp = as_final(s1[4 * at + 1]);
+    const int per = a.gfd_saved ? 3 : 4;   // pass-1 states per query (the base's first unless saved)
+    const Final F0 = a.gfd_saved ? saved_final(M, a, i) : as_final(s1[4 * at]);
+    const Final Fp = as_final(s1[(int64_t)per * at + (a.gfd_saved ? 0 : 1)]);
     const Final Fq = as_final(s2[3 * at]), Fu = as_final(s2[3 * at + 1]), Fv = as_final(s2[3 * at + 2]);
     if (bwd_query(M, a, i, S, phi0, L) != kInitOk || F0.h < 0 || Fp.h < 0 || Fq.h < 0 || Fu.h < 0 || Fv.h < 0) {
         nan_grads(a, i);
@@ -2341,12 +2381,34 @@ SG_HD void gradx_init(const DevMesh& M, const BwdArgs& a, const StateRec* s1, in
     uint32_t phi0;
     float L, Llo = 0.f;
     if (bwd_query(M, a, i, S, phi0, L, &Llo) != kInitOk) return;
-    const Final F0 = as_final(s1[(int64_t)stride * at]);
-    if (F0.h < 0 || ((F0.flags >> 8) & 0xffu) != (uint32_t)kRayOk) return;
-    if (F0.flags & kBndBit) return;   // slid along a boundary: not a chain of hinges
     float3 d3, n3;
-    final_frame(M, F0, d3, n3);
-    const float3 g = load_g(M, a, i, F0.h / 3);
+    int32_t fe;
+    if (s1) {   // the end frame of the base re-walk
+        const Final F0 = as_final(s1[(int64_t)stride * at]);
+        if (F0.h < 0 || ((F0.flags >> 8) & 0xffu) != (uint32_t)kRayOk) return;
+        if (F0.flags & kBndBit) return;   // slid along a boundary: not a chain of hinges
+        final_frame(M, F0, d3, n3);
+        fe = F0.h / 3;
+    } else {    // the end frame from the forward's saved outputs (faces agree in orientation, no slides)
+        if (a.status_in[i] != kRayOk) return;
+        const int32_t fo = a.f_out[i];
+        if (fo < 0 || (int64_t)fo >= M.n_faces) return;
+        fe = M.perm[fo];
+        const float3 vo = ld3(a.v_out + 3 * i);
+        const float lo = sqrtf(dot(vo, vo));
+        if (L > 0.f && lo > 0.f) {
+            d3 = scl(vo, 1.0f / lo);
+        } else {   // |v_t| = 0: the start chart's direction (phi0), as the base walk keeps it
+            float sn, cs;
+            sincos_full(phi0, sn, cs);
+            d3 = make_float3(fmaf(cs, S.ex.x, sn * S.ey.x), fmaf(cs, S.ex.y, sn * S.ey.y),
+                             fmaf(cs, S.ex.z, sn * S.ey.z));
+        }
+        const int64_t f3 = 3 * (int64_t)fe;
+        const float3 y0 = fvx(M, f3 / 3, 0);
+        n3 = nrm(crs(sub(fvx(M, f3 / 3, 1), y0), sub(fvx(M, f3 / 3, 2), y0)));
+    }
+    const float3 g = load_g(M, a, i, fe);
     const float4 c = make_float4(dot(g, d3), dot(g, crs(n3, d3)), dot(g, n3), 0.f);
     if (c.x == 0.f && c.y == 0.f && c.z == 0.f) return;   // g = 0: nothing to add
     float sn, cs;
@@ -2720,14 +2782,38 @@ struct BwdLayout {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static BwdLayout bwd_layout(int64_t n, int32_t mode, bool has_flip, bool vjp, bool gradx, int64_t n_faces,
-                            int32_t gx_records, int walk_blocks) {
-    const bool gfd = vjp && mode == 1;
-    const bool walk = gradx || gfd || (vjp && has_flip);
-    const size_t per1 = gfd ? 4 : 1;
+// What a backward call walks.  The forward's saved outputs replace the base
+// geodesic's walk (Appendix "Speed-up GFD and EP through batching": Exp(p, v)
+// is the forward's) where the faces agree in orientation (the end normal's
+// sign needs no walk) and hole avoidance is off: GFD then walks six
+// geodesics per query (given f', b', v'), and the vertex gradient takes its
+// end frame from f', v' and the status.
+struct BwdPlan {
+    bool gfd, walk, gfd_saved, gx_saved, base_walk;
+    int per1;   // pass-1 states per query
+};
+
+static BwdPlan bwd_plan(int32_t mode, bool has_flip, bool hole, bool vjp, bool gradx, bool have_f, bool have_b,
+                        bool have_v, bool have_status) {
+    BwdPlan P{};
+    P.gfd = vjp && mode == 1;
+    P.walk = gradx || P.gfd || (vjp && has_flip);
+    const bool plain = !has_flip && !hole;
+    const bool end_ok = plain && have_f && have_v && have_status;   // end frame and status of every ray
+    P.gfd_saved = P.gfd && plain && have_f && have_b && have_v && (!gradx || end_ok);
+    P.gx_saved = gradx && end_ok && (!P.gfd || P.gfd_saved);
+    P.base_walk = P.gfd || (vjp && has_flip) || (gradx && !P.gx_saved);   // pass 1 walks
+    P.per1 = P.gfd ? (P.gfd_saved ? 3 : 4) : 1;
+    return P;
+}
+
+static BwdLayout bwd_layout(int64_t n, const BwdPlan& P, bool gradx, int64_t n_faces, int32_t gx_records,
+                            int walk_blocks) {
+    const bool gfd = P.gfd, walk = P.walk, base_walk = P.base_walk;
+    const size_t per1 = P.per1;
     BwdLayout L{};
     size_t o = 0;
-    L.s1 = o; o = align256(o + (walk ? per1 * (size_t)n * sizeof(StateRec) : 0));
+    L.s1 = o; o = align256(o + (base_walk ? per1 * (size_t)n * sizeof(StateRec) : 0));
     L.s2 = o; o = align256(o + (gfd ? 3 * (size_t)n * sizeof(StateRec) : 0));
     L.s3 = o; o = align256(o + (gradx ? (size_t)n * sizeof(StateRec) : 0));
     L.cvec = o; o = align256(o + (gradx ? (size_t)n * sizeof(float4) : 0));
@@ -2736,7 +2822,7 @@ static BwdLayout bwd_layout(int64_t n, int32_t mode, bool has_flip, bool vjp, bo
     L.cnt = o; o = align256(o + (walk ? (size_t)kCountWords * sizeof(uint32_t) : 0));
     L.counter = o; o = align256(o + kQueueBytes);
     const int64_t nh = 3 * n_faces;
-    L.shift = 10;
+    L.shift = kGxShift0;
     while (((nh + ((int64_t)1 << L.shift) - 1) >> L.shift) > kGxMaxBins) ++L.shift;
     const int64_t nblk = std::max(walk_blocks, 1);
     if (gradx && gx_records > 0 && nh > 0) {
@@ -2758,8 +2844,10 @@ static BwdLayout bwd_layout(int64_t n, int32_t mode, bool has_flip, bool vjp, bo
 }
 
 size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip, bool vjp, bool gradx, int64_t n_faces,
-                     int32_t gx_records, int walk_blocks) {
-    return bwd_layout(n, mode, has_flip, vjp, gradx, n_faces, gx_records, walk_blocks).total;
+                     int32_t gx_records, int walk_blocks, bool hole, bool have_f, bool have_b, bool have_v,
+                     bool have_status) {
+    const BwdPlan P = bwd_plan(mode, has_flip, hole, vjp, gradx, have_f, have_b, have_v, have_status);
+    return bwd_layout(n, P, gradx, n_faces, gx_records, walk_blocks).total;
 }
 
 hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, const WalkSched& w, hipStream_t s) {
@@ -2773,7 +2861,11 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
     const bool flip = M.has_flip != 0;
     if (vjp && a.mode == 0 && !flip) hipLaunchKernelGGL(k_ep_saved, dim3((unsigned)grid), dim3(block), 0, s, M, a);
     if (!(gradx || gfd || (vjp && flip))) return hipGetLastError();
-    const BwdLayout L = bwd_layout(a.n, a.mode, flip, vjp, gradx, M.n_faces, a.gx_records, w.blocks);
+    const BwdPlan P = bwd_plan(a.mode, flip, M.hole_avoid != 0, vjp, gradx, a.f_out != nullptr, a.b_out != nullptr,
+                               a.v_out != nullptr, a.status_in != nullptr);
+    const bool base_walk = P.base_walk;
+    a.gfd_saved = P.gfd_saved ? 1 : 0;
+    const BwdLayout L = bwd_layout(a.n, P, gradx, M.n_faces, a.gx_records, w.blocks);
     char* base = reinterpret_cast<char*>(ws);
     auto* s1 = reinterpret_cast<StateRec*>(base + L.s1);
     auto* s2 = reinterpret_cast<StateRec*>(base + L.s2);
@@ -2781,7 +2873,7 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
     auto* cvec = reinterpret_cast<float4*>(base + L.cvec);
     auto* acc = reinterpret_cast<double*>(base + L.acc);
     auto* counter = reinterpret_cast<unsigned long long*>(base + L.counter);
-    const int per1 = gfd ? 4 : 1;
+    const int per1 = P.per1;
     auto* cnt = reinterpret_cast<uint32_t*>(base + L.cnt);
     const RayOrder ord = ray_order(w.queues);
     {   // walk the queries in the order of ray_bucket (region, longest first, start face)
@@ -2792,12 +2884,14 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
         a.slot = slot;
     }
     // base walk (and, for GFD, the three perturbed walks that start at p)
-    hipLaunchKernelGGL(k_bwd_stage1, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
     const int stride = kLenClasses * ord.sub;
-    SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)w.blocks), dim3(block), s, M, s1, QueueRanges{cnt, stride, per1},
-                counter, a.max_steps, a.snap, w.refill_min, w.queues);
-    if (vjp && a.mode == 0)
+    if (base_walk) {
+        hipLaunchKernelGGL(k_bwd_stage1, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
+        SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)w.blocks), dim3(block), s, M, s1,
+                    QueueRanges{cnt, stride, per1}, counter, a.max_steps, a.snap, w.refill_min, w.queues);
+    }
+    if (vjp && a.mode == 0 && flip)   // (consistent orientation: k_ep_saved above)
         hipLaunchKernelGGL(k_ep_walked, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
     if (gfd) {
         hipLaunchKernelGGL(k_bwd_stage2, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
@@ -2810,7 +2904,8 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
         const int64_t nacc = 15 * M.n_faces;
         hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)std::min<int64_t>((nacc + block - 1) / block, 8192)), dim3(block),
                            0, s, acc, nacc);
-        hipLaunchKernelGGL(k_gradx_init, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1, s3, cvec);
+        hipLaunchKernelGGL(k_gradx_init, dim3((unsigned)grid), dim3(block), 0, s, M, a,
+                           P.gx_saved ? (const StateRec*)nullptr : (const StateRec*)s1, per1, s3, cvec);
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
         const int64_t nh = 3 * M.n_faces;
         GxSink sink{};
@@ -2847,7 +2942,7 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
                                (const uint32_t*)bins, (const uint32_t*)counts,
                                reinterpret_cast<GxRec*>(base + L.sorted));
             const int wpb = (1 << L.shift) / kGxWindow;
-            hipLaunchKernelGGL(k_gx_reduce, dim3((unsigned)(L.nbins * wpb)), dim3(256), 0, s,
+            hipLaunchKernelGGL(k_gx_reduce, dim3((unsigned)(L.nbins * wpb)), dim3(1024), 0, s,
                                (const GxRec*)(base + L.sorted), (const uint32_t*)bins, L.shift, nh, acc);
         }
         hipLaunchKernelGGL(k_gradx_faces, dim3((unsigned)((M.n_faces + block - 1) / block)), dim3(block), 0, s, M,

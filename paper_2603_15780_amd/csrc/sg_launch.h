@@ -36,8 +36,10 @@ struct BwdArgs {
     const int32_t* f;
     const float* b;
     const float* v;
-    const int32_t* f_out;   // saved forward outputs (extrinsic proxy)
+    const int32_t* f_out;   // saved forward outputs (extrinsic proxy; vertex gradient and GFD without a re-walk)
+    const float* b_out;
     const float* v_out;
+    const int32_t* status_in;   // the forward's saved per-ray status, or null
     const float* g;         // dL/dp', or null (zero)
     const float* g_bo;      // dL/db' [n,3] (end barycentrics), or null
     const float* g_v;       // dL/dv' [n,3], or null
@@ -52,6 +54,7 @@ struct BwdArgs {
     double* grad_X;         // [n_verts, 3] accumulated vertex-position gradient, or null
     const int32_t* slot;    // position of each query in the walk arrays (set by the launcher), or null
     int32_t gx_records;     // grad-X records reserved per query for binned accumulation (<= 0: atomics only)
+    int32_t gfd_saved;      // (set by the launcher) GFD takes the base geodesic's end from f_out, b_out, v_out
 };
 
 // Host-side result of packing a mesh (float64 work, rounded once).
@@ -138,8 +141,10 @@ hipError_t launch_pi_backward(const PiMesh& P, const DevMesh& M, const BwdArgs& 
 hipError_t launch_ep_saved(const DevMesh& M, const BwdArgs& a, hipStream_t s);
 
 // Backward of the exponential map (extrinsic proxy or geodesic finite differences).
+// have_*: which of the forward's saved outputs (f', b', v', status) the call is given.
 size_t bwd_workspace(int64_t n, int32_t mode, bool has_flip, bool vjp, bool gradx, int64_t n_faces,
-                     int32_t gx_records, int walk_blocks);
+                     int32_t gx_records, int walk_blocks, bool hole, bool have_f, bool have_b, bool have_v,
+                     bool have_status);
 hipError_t launch_backward(const DevMesh& M, const BwdArgs& a, void* ws, const WalkSched& w, hipStream_t s);
 
 // Partitioned forward: the walk runs on the XCD whose L2 holds the ray's

@@ -70,9 +70,9 @@ def lib():
         L.sg_exp_transport.restype = C.c_int
         L.sg_exp_transport_noalloc.argtypes = L.sg_exp_transport.argtypes
         L.sg_exp_transport_noalloc.restype = C.c_int
-        L.sg_exp_backward.argtypes = [P, I32, I64, P, P, P, P, P, P, P, P, P, C.POINTER(Opts), P]
+        L.sg_exp_backward.argtypes = [P, I32, I64, P, P, P, P, P, P, P, P, P, P, P, C.POINTER(Opts), P]
         L.sg_exp_backward.restype = C.c_int
-        L.sg_exp_backward_transport.argtypes = [P, I32, I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P,
+        L.sg_exp_backward_transport.argtypes = [P, I32, I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, P,
                                                 C.POINTER(Opts), P]
         L.sg_exp_backward_transport.restype = C.c_int
         L.sg_exp_workspace_size.argtypes = [P, I64, I32, C.POINTER(Opts), C.POINTER(C.c_size_t)]
@@ -294,9 +294,13 @@ class Mesh:
         _check(lib().sg_pi_backward_workspace_size(self._h, int(mode), n, C.byref(nb)))
         return nb.value
 
-    def backward(self, mode, f, b, v, g, *, f_out=None, v_out=None, out=None, grad_X=None, want_vjp=True,
-                 g_b=None, g_v=None, g_W=None, o: Opts | None = None, **kw):
+    def backward(self, mode, f, b, v, g, *, f_out=None, b_out=None, v_out=None, status=None, out=None, grad_X=None,
+                 want_vjp=True, g_b=None, g_v=None, g_W=None, o: Opts | None = None, **kw):
         """(grad_v, grad_b) for upstream g = dL/dp' [n,3]; mode BWD_EP or BWD_GFD.
+
+        f_out, b_out, v_out, status: the forward's saved outputs (EP reads f_out
+        and v_out; with f_out, v_out and status the vertex gradient, and with
+        f_out, b_out and v_out GFD, skip walking the base geodesic again).
 
         grad_X: a float64 [n_verts, 3] tensor to accumulate dL/dX into (or None).
         want_vjp=False skips grad_v / grad_b (returns (None, None)).
@@ -322,7 +326,9 @@ class Mesh:
             if grad_X is not None:
                 assert grad_X.dtype == torch.float64 and grad_X.is_contiguous() and grad_X.shape == (self.n_verts, 3)
             _check(lib().sg_exp_backward_transport(
-                self._h, int(mode), n, _dptr(f), _dptr(b), _dptr(v), K, _dptr(f_out), _dptr(v_out), _dptr(g),
+                self._h, int(mode), n, _dptr(f), _dptr(b), _dptr(v), K, _dptr(f_out), _dptr(b_out), _dptr(v_out),
+                _dptr(status),
+                _dptr(g),
                 _dptr(g_b), _dptr(g_v), _dptr(g_W), _dptr(gv_), _dptr(gb_), _dptr(gW_), _dptr(grad_X), C.byref(o),
                 _stream()))
             return (gv_, gb_, gW_) if g_W is not None else (gv_, gb_)
@@ -335,8 +341,9 @@ class Mesh:
             out = (None, None)
         elif out is None:
             out = (torch.empty(n, 3, dtype=torch.float32, device=dev), torch.empty(n, 3, dtype=torch.float32, device=dev))
-        _check(lib().sg_exp_backward(self._h, int(mode), n, _dptr(f), _dptr(b), _dptr(v), _dptr(f_out), _dptr(v_out),
-                                     _dptr(g), _dptr(out[0]), _dptr(out[1]), _dptr(grad_X), C.byref(o), _stream()))
+        _check(lib().sg_exp_backward(self._h, int(mode), n, _dptr(f), _dptr(b), _dptr(v), _dptr(f_out), _dptr(b_out),
+                                     _dptr(v_out), _dptr(status), _dptr(g), _dptr(out[0]), _dptr(out[1]), _dptr(grad_X), C.byref(o),
+                                     _stream()))
         return out
 
 
@@ -362,7 +369,7 @@ def _autograd_function():
             ctx.want_x = X is not None and X.requires_grad
             ctx.x_dtype = X.dtype if X is not None else None
             ctx.K = 0 if W is None else W.shape[1]
-            ctx.save_for_backward(f, b, v, out["f"], out["v"])
+            ctx.save_for_backward(f, b, v, out["f"], out["b"], out["v"], out["status"])
             ctx.mark_non_differentiable(out["f"], out["status"])
             if W is None:
                 return out["p"], out["f"], out["b"], out["v"], out["status"]
@@ -370,12 +377,13 @@ def _autograd_function():
 
         @staticmethod
         def backward(ctx, g_p, g_f, g_b, g_vo, *rest):
-            f, b, v, f_out, v_out = ctx.saved_tensors
+            f, b, v, f_out, b_out, v_out, status = ctx.saved_tensors
             g_Wo = rest[0] if ctx.K else None
             g = g_p.contiguous().float()
             gX = torch.zeros(ctx.mesh.n_verts, 3, dtype=torch.float64, device=g.device) if ctx.want_x else None
             res = ctx.mesh.backward(ctx.mode, f.contiguous(), b.contiguous(), v.contiguous(), g, f_out=f_out,
-                                    v_out=v_out, grad_X=gX, g_b=g_b.contiguous().float(),
+                                    b_out=b_out, v_out=v_out, status=status, grad_X=gX,
+                                    g_b=g_b.contiguous().float(),
                                     g_v=g_vo.contiguous().float(),
                                     g_W=None if g_Wo is None else g_Wo.contiguous().float(), **ctx.opts_kw)
             gv, gb = res[0], res[1]

@@ -34,24 +34,29 @@ def dev_inputs(torch, r, g):
     return t
 
 
-def gpu_bwd(torch, gm, mode, r, g, **kw):
+def gpu_bwd(torch, gm, mode, r, g, saved=False, **kw):
+    """The backward on the GPU; EP reads the forward's f' and v'; with saved=True
+    every mode is also given b' and the status (GFD then takes the base
+    geodesic's end from the forward instead of walking it)."""
     from paper_2603_15780_amd import sg
     t = dev_inputs(torch, r, g)
-    fo = vo = None
-    if mode == sg.BWD_EP:
+    fo = bo = vo = st = None
+    if mode == sg.BWD_EP or saved:
         out = gm.exp(t["f"], t["b"], t["v"], **{k: v for k, v in kw.items() if k in ("max_steps", "boundary_mode")})
         fo, vo = out["f"], out["v"]
-    gv, gb = gm.backward(mode, t["f"], t["b"], t["v"], t["g"], f_out=fo, v_out=vo, **kw)
+        if saved:
+            bo, st = out["b"], out["status"]
+    gv, gb = gm.backward(mode, t["f"], t["b"], t["v"], t["g"], f_out=fo, b_out=bo, v_out=vo, status=st, **kw)
     torch.cuda.synchronize()
     return gv.cpu().numpy(), gb.cpu().numpy()
 
 
-def check(torch, X, F, r, g, mode, rows=None, min_margin_rays=100, **kw):
+def check(torch, X, F, r, g, mode, rows=None, min_margin_rays=100, saved=False, **kw):
     from paper_2603_15780_amd import sg
     om = oracle.Mesh(X, F)
     gm = sg.Mesh(X, F)
     eps = np.float32(5e-3 * om.mean_edge)
-    gv, gb = gpu_bwd(torch, gm, mode, r, g, eps_v=float(eps), eps_p=float(eps), **kw)
+    gv, gb = gpu_bwd(torch, gm, mode, r, g, saved=saved, eps_v=float(eps), eps_p=float(eps), **kw)
     sel = slice(None) if rows is None else rows
     rf, rb, rv, gs = r["f"][sel], r["b"][sel], r["v"][sel], g[sel]
     okw = dict(boundary_mode=kw["boundary_mode"]) if "boundary_mode" in kw else {}
@@ -89,14 +94,44 @@ def test_ragged(torch, mode, n):
     check(torch, X, F, r, g, mode, min_margin_rays=min(n, 100) // 2)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_config2_full_batch_sampled(torch, mode):
-    """Backward over all 1,048,576 rays on the 327,680-face mesh; 4,096 sampled rows vs the oracle."""
+@pytest.mark.parametrize("mode,saved", [(0, False), (1, False), (1, True)])
+def test_config2_full_batch_sampled(torch, mode, saved):
+    """Backward over all 1,048,576 rays on the 327,680-face mesh; 4,096 sampled
+    rows vs the oracle.  saved: GFD takes the base geodesic's end from the
+    forward's outputs (six walks per query instead of seven)."""
     X, F = CF.mesh_config(2)
     r = CF.rays_config(2, X, F)
     g = CF.upstream_grad(2, r["f"].shape[0])
     rows = np.arange(0, r["f"].shape[0], 256)
-    check(torch, X, F, r, g, mode, rows=rows)
+    check(torch, X, F, r, g, mode, rows=rows, saved=saved)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_gfd_from_saved_forward(torch, mixed):
+    """GFD given the forward's f', b', v' and status walks six geodesics per
+    query; it matches the oracle like the seven-walk form and agrees with it
+    (relative 1e-3 on the margin rays: the base end point enters through the
+    float32 b' instead of the walk's chart state).  On a mesh whose faces
+    disagree in orientation the saved outputs are not used: bit for bit the
+    seven-walk result."""
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    if mixed:
+        F = F.copy()
+        flip = np.random.default_rng(5).random(F.shape[0]) < 0.3
+        F[flip] = F[flip][:, ::-1]
+    r = CF.rays_config(1, X, F)
+    g = CF.upstream_grad(1, r["f"].shape[0])
+    s7, gv7, gb7 = check(torch, X, F, r, g, sg.BWD_GFD)
+    s6, gv6, gb6 = check(torch, X, F, r, g, sg.BWD_GFD, saved=True)
+    if mixed:
+        assert np.array_equal(gv6, gv7) and np.array_equal(gb6, gb7)
+        return
+    om = oracle.Mesh(X, F)
+    o = om.exp(r["f"], r["b"], r["v"])
+    keep = (o["min_vdist"] > 1e-4 * om.mean_edge) & (o["status"] == 0)
+    rel = np.linalg.norm(gv6 - gv7, axis=1) / np.maximum(np.linalg.norm(gv7, axis=1), 1e-12)
+    assert np.quantile(rel[keep], 0.999) < 1e-3, np.quantile(rel[keep], 0.999)
 
 
 @pytest.mark.parametrize("mode", [0, 1])
@@ -225,6 +260,48 @@ def test_gradx_config1(torch, mixed):
         assert gradx_report(ref, got2)["global_rel"] < 1e-4
         assert np.allclose(got2, got, rtol=1e-9, atol=1e-9 * np.abs(got).max())
         assert np.isfinite(gv.cpu().numpy()[keep]).all()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_gradx_from_saved_outputs(torch, mixed):
+    """With the forward's f_out, v_out and status the vertex gradient takes its
+    end frame from them instead of re-walking the geodesic: the same sums up to
+    the float32 rounding of v' (global relative 1e-6), and the oracle's within
+    1e-4, for EP + grad_X and for grad_X alone.  On a mesh whose faces disagree
+    in orientation the end normal's sign needs the walk: the call re-walks and
+    gives the walked sums bit for bit."""
+    from paper_2603_15780_amd import sg
+    from parity import gradx_report
+    X, F = CF.mesh_config(1)
+    if mixed:
+        F = F.copy()
+        flip = np.random.default_rng(5).random(F.shape[0]) < 0.3
+        F[flip] = F[flip][:, ::-1]
+    r = CF.rays_config(1, X, F)
+    g = CF.upstream_grad(1, r["f"].shape[0])
+    om = oracle.Mesh(X, F)
+    keep = margin_mask(om, r)
+    g[~keep] = 0.0
+    ref, _ = om.gradx(r["f"], r["b"], r["v"], g)
+    gm = sg.Mesh(X, F)
+    t = dev_inputs(torch, r, g)
+    out = gm.exp(t["f"], t["b"], t["v"])
+    res = {}
+    for name, st, vjp in (("walked", None, True), ("saved", out["status"], True), ("saved_x_only", out["status"], False)):
+        gX = torch.zeros(gm.n_verts, 3, dtype=torch.float64, device=t["f"].device)
+        gm.backward(sg.BWD_EP, t["f"], t["b"], t["v"], t["g"], f_out=out["f"], v_out=out["v"], status=st, grad_X=gX,
+                    want_vjp=vjp)
+        torch.cuda.synchronize()
+        res[name] = gX.cpu().numpy()
+    scale = np.abs(res["walked"]).max()
+    for name in ("saved", "saved_x_only"):
+        s = gradx_report(ref, res[name])
+        print(name, s)
+        assert s["finite"] and s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, s
+        if mixed:
+            assert np.allclose(res[name], res["walked"], rtol=1e-9, atol=1e-9 * scale)
+        else:
+            assert np.linalg.norm(res[name] - res["walked"]) <= 1e-6 * np.linalg.norm(res["walked"])
 
 
 def test_gradx_config2_full_batch(torch):

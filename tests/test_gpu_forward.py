@@ -343,6 +343,64 @@ def test_config3_many_meshes_one_launch(torch):
         assert s["frac_ok"] >= 0.999 and s["bad_not_near"] == 0 and s["face_mis_unexplained"] == 0, (i, s)
 
 
+@pytest.fixture(scope="module")
+def config3_full():
+    """The 64-mesh batch at full size (6.8M faces, 5.6M rays), generated once."""
+    return CF.config3_batch(64)
+
+
+@pytest.mark.timeout(900)
+def test_config3_full_size_graph_replay(torch, config3_full):
+    """All 64 meshes at full size in one persistent call, as the benchmark runs
+    it: the autotuner's schedule, a caller workspace, the call captured in a
+    HIP graph and replayed (with eager work between the replays).  Every
+    replay gives the eager call's results bit for bit, and every 64th ray of
+    each mesh matches the oracle."""
+    from paper_2603_15780_amd import sg
+    B = config3_full
+    dev = torch.device("cuda:0")
+    gm = sg.Mesh(B["X"], B["F_local"], B["vert_offsets"], B["face_offsets"])
+    r = B["rays"]
+    n = r["f"].shape[0]
+    t = {k: torch.from_numpy(np.ascontiguousarray(r[k])).to(dev) for k in ("f", "b", "v")}
+    print(f"config 3 full size: {B['F_global'].shape[0]} faces, {n} rays", flush=True)
+    o, ms = gm.autotune(t["f"], t["b"], t["v"])
+    print("autotuned", o.kernel, o.refill_min, o.walk_blocks, o.rays_per_lane, o.ray_queues, ms, flush=True)
+    o.debug = 3
+    ws = torch.empty(gm.exp_workspace_size(n, 0, o), dtype=torch.uint8, device=dev)
+    o.workspace, o.workspace_bytes = ws.data_ptr(), ws.numel()
+    eager = gm.exp(t["f"], t["b"], t["v"], o=o, want_cross=True, want_hash=True)
+    torch.cuda.synchronize()
+    eager = {k: (a.clone() if a is not None else None) for k, a in eager.items()}
+    out = {k: (torch.empty_like(a) if a is not None else None) for k, a in eager.items()}
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gm.exp(t["f"], t["b"], t["v"], o=o, out=out)
+    for rep in range(2):
+        for a in out.values():
+            if a is not None:
+                a.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k in eager:
+            if eager[k] is not None:
+                assert torch.equal(out[k], eager[k]), (rep, k)
+    g = {k: (a.cpu().numpy() if a is not None else None) for k, a in eager.items()}
+    g["hash"] = g["hash"].view(np.uint64)
+    rows = np.concatenate([np.arange(sl.start, sl.stop, 64) for sl in B["slices"]])
+    om = oracle.Mesh(B["X"], B["F_global"])
+    oo = om.exp(r["f"][rows], r["b"][rows], r["v"][rows])
+    pos = 0
+    for i, sl in enumerate(B["slices"]):
+        k = len(range(sl.start, sl.stop, 64))
+        spec = B["specs"][i]
+        oi = {key: a[pos:pos + k] for key, a in oo.items()}
+        gi = {key: (a[sl][::64] if a is not None else None) for key, a in g.items()}
+        s = report(oi, gi, M.mean_edge(spec["X"], spec["F"]), K=0)
+        assert s["frac_ok"] >= 0.999 and s["bad_not_near"] == 0 and s["face_mis_unexplained"] == 0, (i, s)
+        pos += k
+
+
 def test_caller_workspace_and_graph_capture(torch):
     """With a caller workspace a call allocates nothing, so it can be captured in
     a HIP graph; every replay (with eager work between them) matches the eager call."""
@@ -436,11 +494,23 @@ def test_autotune(torch):
     o, ms = gm.autotune(t["f"], t["b"], t["v"], t["W"])
     assert ms > 0 and o.kernel in (sg.KERNEL_PLAIN, sg.KERNEL_PERSISTENT)
     assert 1 <= o.refill_min <= 64 and o.walk_blocks > 0
+    assert o.ray_queues in (8, 16)
     a = gm.exp(t["f"], t["b"], t["v"], t["W"], o=o)
     b = gm.exp(t["f"], t["b"], t["v"], t["W"])
     torch.cuda.synchronize()
     for k in ("f", "b", "p", "v", "W", "status"):
         assert torch.equal(a[k], b[k]), k
+    # the pick is cached per class of batches: a second call returns it without timing;
+    # debug bit 3 tunes again
+    import time
+    t0 = time.perf_counter()
+    o2, ms2 = gm.autotune(t["f"], t["b"], t["v"], t["W"])
+    t1 = time.perf_counter()
+    assert ms2 == ms and (o2.kernel, o2.refill_min, o2.walk_blocks, o2.rays_per_lane, o2.ray_queues) == \
+        (o.kernel, o.refill_min, o.walk_blocks, o.rays_per_lane, o.ray_queues)
+    o4, ms4 = gm.autotune(t["f"], t["b"], t["v"], t["W"], debug=8)
+    t2 = time.perf_counter()
+    assert ms4 > 0 and (t1 - t0) < (t2 - t1)
 
 
 def test_config5_full_batch_sampled(torch, config5):
