@@ -106,6 +106,8 @@ def main():
                     help="oracle sample size (0: whole batch; 1/4 of it for config 3, 1/64 for config 5)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain kernel for comparison")
     ap.add_argument("--no-bwd", action="store_true", help="skip timing the backward forms")
+    ap.add_argument("--bwd-forms", default="ep,gfd,ep+gradX,gfd+gradX",
+                    help="comma-separated backward forms to time (ep, gfd, ep+gradX, gfd+gradX)")
     ap.add_argument("--refill", type=int, default=0, help="persistent kernel refill threshold (0: library default)")
     ap.add_argument("--walk-blocks", type=int, default=0, help="persistent kernel blocks (0: library default, two per CU)")
     ap.add_argument("--calib-copy", type=int, default=0, help="MiB copied once to calibrate byte counters")
@@ -245,8 +247,9 @@ def main():
         fo = opts_for()
         persistent = base.kernel == sg.KERNEL_PERSISTENT
         bo = sg.opts(refill_min=base.refill_min if persistent else 0, walk_blocks=base.walk_blocks if persistent else 0)
-        forms = (("ep", sg.BWD_EP, False), ("gfd", sg.BWD_GFD, False), ("ep+gradX", sg.BWD_EP, True),
-                 ("gfd+gradX", sg.BWD_GFD, True))
+        want = set(args.bwd_forms.split(","))
+        forms = tuple(fm for fm in (("ep", sg.BWD_EP, False), ("gfd", sg.BWD_GFD, False),
+                                    ("ep+gradX", sg.BWD_EP, True), ("gfd+gradX", sg.BWD_GFD, True)) if fm[0] in want)
         # The vertex gradient reserves gradx_records records per query (at most 2^30 per call); config 5's
         # 1.1e10 crossings (641 per ray) go through it in slices of 2^20 queries with 800 records each,
         # accumulating into one grad_X.
@@ -312,17 +315,17 @@ def main():
         log(f"oracle: {ocross} crossings in {c1 - c0:.2f}s on {cores} threads; GPU/oracle crossing ratio "
             f"{gpu_cross / max(ocross, 1) if rows.shape[0] == n else float('nan'):.6f}")
     if bwd:
-        # algorithmic bytes of each backward (the paper's schemes, SURVEY's per-step counts):
+        # algorithmic bytes of each backward (the paper's schemes, counted per query and per crossing):
         # EP streams ~152 B per query (query, saved f' and v', g, both gradients, start and end
-        # faces' vertices) and walks nothing; GFD walks its four long geodesics (the base, the
-        # e_perp-perturbed one and the two start-shifted ones; the three short ones cross almost
-        # nothing) at 16 B per crossing, with 64 B of chart state in and out per walk and query;
-        # the vertex gradient adds one adjoint walk (16 B per crossing), the float64 sums
-        # (6 per half-edge) and grad_X (24 B per vertex).
+        # faces' vertices) and walks nothing; GFD walks three long geodesics (the e_perp-perturbed
+        # one and the two start-shifted ones; the base geodesic is the forward's, and the three
+        # short ones cross almost nothing) at 16 B per crossing, with 64 B of chart state in and
+        # out per walk and query; the vertex gradient adds one adjoint walk (16 B per crossing),
+        # the float64 sums (6 per half-edge) and grad_X (24 B per vertex).
         n_he = 3 * int(F_or.shape[0])
         per_q = 152
         algo = {"ep": n * per_q,
-                "gfd": 4 * cross * BYTES_PER_CROSSING + n * (per_q + 7 * 64)}
+                "gfd": 3 * cross * BYTES_PER_CROSSING + n * (per_q + 6 * 64)}
         gx_extra = cross * BYTES_PER_CROSSING + n * 64 + n_he * 6 * 8 + int(X.shape[0]) * 24
         algo["ep+gradX"] = algo["ep"] + gx_extra
         algo["gfd+gradX"] = algo["gfd"] + gx_extra
@@ -402,8 +405,8 @@ def main():
                                                        and not args.walk_blocks) else None,
                      "kernel": "k_walk (persistent walk)" if ms_walk is not None else "k_exp_plain",
                      "algorithmic_bytes_per_launch": algo_bytes, "kernel_ms": ms_kernel,
-                     # what the walk's loads request from the cache hierarchy per crossing (32 of its
-                     # 64-byte face record), over the same time: an L2 request rate, not HBM traffic
+                     # what the walk's loads request from the cache hierarchy per crossing (its 32-byte
+                     # face record), over the same time: an L2 request rate, not HBM traffic
                      "l2_request_GBs_at_32B": (32 * cross + (algo_bytes - 16 * cross)) / (ms_kernel * 1e-3) / 1e9,
                      "whole_call": {"ms": ms_step, "algorithmic_bytes": call_bytes,
                                     "achieved_GBs": call_bytes / (ms_step * 1e-3) / 1e9,

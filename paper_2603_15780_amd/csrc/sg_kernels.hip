@@ -1979,16 +1979,11 @@ __global__ __launch_bounds__(256) void k_finish(DevMesh M, ExpArgs a, const Stat
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const int64_t at = slot ? (int64_t)slot[i] : i;
+    // every walk kernel runs each of its rays to a Final record (the step cap
+    // included), which overwrites the start state in place; h < 0 marks a query
+    // with no walk, whose outputs k_init wrote
     Final fin = *reinterpret_cast<const Final*>(&states[at]);
     if (fin.h < 0) return;
-    if (!(fin.flags & kDoneBit)) {
-        // never reached its end (a walk kernel gave up waiting): report where it is
-        const StateRec rec = states[at];
-        fin.h = rec.h; fin.ex = rec.s; fin.ey = 0.f; fin.phi = rec.phi;
-        fin.flags = (rec.flags & kParity) | ((uint32_t)kRayMaxSteps << 8);
-        fin.ncross = rec.ncross;
-        fin.hash = 0ull;
-    }
     if (hashes) fin.hash = hashes[i];
     if (aux) {
         const float* x = aux + i * (1 + 2 * (int64_t)a.K);

@@ -127,7 +127,7 @@ def assert_parity(o, g, me, K=0, label="", mesh=None):
     return s
 
 
-def grad_report(o_exp, og_v, og_b, gg_v, gg_b, me, margin=2e-2, tol=1e-3):
+def grad_report(o_exp, og_v, og_b, gg_v, gg_b, me, margin=2e-2, tol=1e-3, near=None):
     """Backward parity: relative errors of grad_v (norm) and of the barycentric
     gradient differences (grad_b[1] - grad_b[0], grad_b[2] - grad_b[0]), which
     carry the in-plane start-point gradient (grad_b[k] = G . x_k; its common
@@ -135,6 +135,15 @@ def grad_report(o_exp, og_v, og_b, gg_v, gg_b, me, margin=2e-2, tol=1e-3):
     checked against that scale).  `margin` rays keep at least margin * mean edge
     from every vertex along the oracle's base walk: finite differences of
     geodesics that pass a vertex closer than their step are not smooth.
+
+    near = (radius, tol_near), for geodesic finite differences: margin rays whose
+    base walk passes within radius * mean edge of a vertex are held to tol_near.
+    Both sides take the same difference quotient, but the float32 stencil ends
+    differ from the float64 ones by rounding, and the quotient amplifies that by
+    the map's second derivative, which grows as the walk nears a cone vertex
+    (on the 327,680-face mesh, with step eps = 5e-3 mean edge, the b-gradient
+    error has median 9e-5 and maximum 1.9e-3 for rays that pass 4-6 eps from a
+    vertex, and median 3e-5, maximum 6e-4 for rays that stay beyond 20 eps).
     """
     def d(x):
         return np.stack([x[:, 1] - x[:, 0], x[:, 2] - x[:, 0]], 1)
@@ -153,8 +162,11 @@ def grad_report(o_exp, og_v, og_b, gg_v, gg_b, me, margin=2e-2, tol=1e-3):
     m = o_exp["min_vdist"] > margin * me
     if "n_bnd" in o_exp:   # a boundary slide is not a smooth part of the map
         m = m & (o_exp["n_bnd"] == 0)
-    return dict(n=len(ev), n_margin=int(m.sum()), v_ok=float(np.mean(ev[m] <= tol)) if m.any() else 1.0,
-                b_ok=float(np.mean(eb[m] <= tol)) if m.any() else 1.0, v_med=float(np.median(ev)),
+    t = np.full(len(ev), tol)
+    if near is not None:
+        t[o_exp["min_vdist"] <= near[0] * me] = near[1]
+    return dict(n=len(ev), n_margin=int(m.sum()), v_ok=float(np.mean(ev[m] <= t[m])) if m.any() else 1.0,
+                b_ok=float(np.mean(eb[m] <= t[m])) if m.any() else 1.0, v_med=float(np.median(ev)),
                 b_med=float(np.median(eb)), v_all_ok=float(np.mean(ev <= tol)), finite=bool(
                     np.isfinite(gg_v).all() and np.isfinite(gg_b).all()))
 

@@ -4,7 +4,8 @@ Extrinsic proxy (eq. proxy_func) and geodesic finite differences (eqs. jv,
 jp, chain) through the C ABI on cuda:0, compared with the float64 oracle at
 the same step sizes.  Gradients are compared on rays that keep a margin from
 every vertex (finite differences of geodesics are not smooth across a vertex);
-the bar is a relative error of 1e-3.
+the bar is a relative error of 1e-3, and 5e-3 for finite differences whose
+base walk passes within ten steps (10 eps) of a vertex.
 """
 import numpy as np
 import pytest
@@ -66,7 +67,9 @@ def check(torch, X, F, r, g, mode, rows=None, min_margin_rays=100, saved=False, 
     else:
         od = om.gfd(rf, rb, rv, gs, float(eps), float(eps), **okw)
         ogv, ogb = od["grad_v"], od["grad_b"]
-    s = grad_report(o, ogv, ogb, gv[sel], gb[sel], om.mean_edge)
+    # GFD: rays whose base walk passes within 10 eps of a vertex are held to 5e-3 (see grad_report)
+    near = None if mode == sg.BWD_EP else (10 * float(eps) / om.mean_edge, 5e-3)
+    s = grad_report(o, ogv, ogb, gv[sel], gb[sel], om.mean_edge, near=near)
     print(s)
     assert s["finite"], s
     assert s["n_margin"] >= min_margin_rays, s
@@ -96,13 +99,13 @@ def test_ragged(torch, mode, n):
 
 @pytest.mark.parametrize("mode,saved", [(0, False), (1, False), (1, True)])
 def test_config2_full_batch_sampled(torch, mode, saved):
-    """Backward over all 1,048,576 rays on the 327,680-face mesh; 4,096 sampled
-    rows vs the oracle.  saved: GFD takes the base geodesic's end from the
-    forward's outputs (six walks per query instead of seven)."""
+    """Backward over all 1,048,576 rays on the 327,680-face mesh; 16,384 sampled
+    rows (every 64th) vs the oracle.  saved: GFD takes the base geodesic's end
+    from the forward's outputs (six walks per query instead of seven)."""
     X, F = CF.mesh_config(2)
     r = CF.rays_config(2, X, F)
     g = CF.upstream_grad(2, r["f"].shape[0])
-    rows = np.arange(0, r["f"].shape[0], 256)
+    rows = np.arange(0, r["f"].shape[0], 64)
     check(torch, X, F, r, g, mode, rows=rows, saved=saved)
 
 
@@ -307,7 +310,7 @@ def test_gradx_from_saved_outputs(torch, mixed):
 def test_gradx_config2_full_batch(torch):
     """All 1,048,576 rays on the 327,680-face mesh.  (1) Upstream g on every
     margin ray: translating the mesh translates each p', so the vertex
-    gradients sum to sum g.  (2) g on 4,096 sampled margin rays only: the
+    gradients sum to sum g.  (2) g on 16,384 sampled margin rays only: the
     gradient field is compared with the oracle's on those rays."""
     from paper_2603_15780_amd import sg
     from parity import gradx_report
@@ -323,7 +326,7 @@ def test_gradx_config2_full_batch(torch):
     assert np.isfinite(got).all()
     tot = got.sum(0)
     assert np.allclose(tot, g.astype(np.float64).sum(0), rtol=1e-5, atol=1e-5 * np.abs(g).sum() / np.sqrt(n)), tot
-    idx = np.flatnonzero(keep)[:: max(1, keep.sum() // 4096)][:4096]
+    idx = np.flatnonzero(keep)[:: max(1, keep.sum() // 16384)][:16384]
     gs = np.zeros_like(g)
     gs[idx] = g[idx]
     got_s, _ = gpu_gradx(torch, gm, r, gs)
@@ -420,7 +423,7 @@ def test_gradx_records_large_mesh(torch):
 def test_gradx_config5_sliced_records(torch, config5):
     """16,777,216 queries on the 1,310,720-face mesh (641 crossings per ray): the
     vertex gradient in 16 calls of 2^20 queries with 800 records each, accumulated
-    into one grad_X, equals one call on float64 atomics alone; on every 4096th
+    into one grad_X, equals one call on float64 atomics alone; on every 1024th
     margin ray the records path matches the oracle."""
     from paper_2603_15780_amd import sg
     from parity import gradx_report
@@ -440,7 +443,7 @@ def test_gradx_config5_sliced_records(torch, config5):
     rec, atm = rec.cpu().numpy(), atm.cpu().numpy()
     assert np.isfinite(rec).all()
     assert np.allclose(rec, atm, rtol=1e-9, atol=1e-11 * np.abs(atm).max())
-    rows = np.arange(0, n, 4096)
+    rows = np.arange(0, n, 1024)
     sub = {k: r[k][rows] for k in ("f", "b", "v")}
     om = oracle.Mesh(X, F)
     keep = margin_mask(om, sub)
