@@ -9,10 +9,15 @@ HBM before timing.  A step is one sg_exp_transport call over the whole batch
 with the library's default schedule (--autotune: the schedule the library's
 autotuner picks for this batch, tuned untimed).
 
-The forward + backward forms (extrinsic proxy from the saved outputs;
-geodesic finite differences, which re-walk seven geodesics per query; each
-with and without the float64 vertex-position gradient, which re-walks twice)
-are timed on the same batch and reported beside it.
+The forward + backward forms are timed on the same batch and reported
+beside it; each backward takes the forward's saved outputs: the extrinsic
+proxy walks nothing, geodesic finite differences walk six geodesics per
+query (the base geodesic's end is the forward's), and the float64
+vertex-position gradient adds one adjoint walk.
+
+With the default config the 64-mesh batch (--config 3) is also run, in a
+child process, as HIP-graph replays of one call with the autotuner's
+schedule, and reported as `config3` (--no-config3 skips it).
 
 The projection-integration Exp map (the paper's comparison Exp) is timed on
 the same batch (`pi`), with its extrinsic proxy and geodesic finite
@@ -109,12 +114,14 @@ def main():
     ap.add_argument("--bwd-forms", default="ep,gfd,ep+gradX,gfd+gradX",
                     help="comma-separated backward forms to time (ep, gfd, ep+gradX, gfd+gradX)")
     ap.add_argument("--refill", type=int, default=0, help="persistent kernel refill threshold (0: library default)")
-    ap.add_argument("--walk-blocks", type=int, default=0, help="persistent kernel blocks (0: library default, two per CU)")
+    ap.add_argument("--walk-blocks", type=int, default=0, help="persistent kernel blocks (0: library default, three per CU)")
+    ap.add_argument("--queues", type=int, default=0, help="persistent kernel ray queues (0: library default, 8)")
     ap.add_argument("--calib-copy", type=int, default=0, help="MiB copied once to calibrate byte counters")
     ap.add_argument("--graph", type=int, default=-1,
                     help="1: time HIP-graph replays of the call (caller workspace); 0: eager calls; "
                          "-1: graph for the 64-mesh batch, eager otherwise")
     ap.add_argument("--no-pi", action="store_true", help="skip timing the projection-integration map")
+    ap.add_argument("--no-config3", action="store_true", help="skip the 64-mesh batch leg of the default run")
     ap.add_argument("--pi-rays", type=int, default=0, help="rays for the PI leg (0: the whole batch)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -152,17 +159,18 @@ def main():
         W=torch.empty(n, K, 3, device=dev) if K else None, status=torch.empty(n, dtype=torch.int32, device=dev),
         n_cross=torch.empty(n, dtype=torch.int32, device=dev), hash=None)
 
-    base = sg.opts(kernel=args.kernel, refill_min=args.refill, walk_blocks=args.walk_blocks)
+    base = sg.opts(kernel=args.kernel, refill_min=args.refill, walk_blocks=args.walk_blocks, ray_queues=args.queues)
     tuned = None
     if args.graph < 0:
         args.graph = 1 if args.config == 3 else 0
-    if args.config == 3 and args.kernel == 0:
+    if args.config == 3 and args.kernel == 0 and not (args.refill or args.walk_blocks or args.queues):
         args.autotune = True   # the 64-mesh batch runs the schedule the autotuner picks for it
     if args.kernel == 0 and args.autotune:
         t1 = time.time()
         base, tune_ms = mesh.autotune(t["f"], t["b"], t["v"], t["W"], o=base)
         tuned = {"kernel": ["auto", "plain", "persistent", "partitioned"][base.kernel], "refill_min": base.refill_min,
-                 "walk_blocks": base.walk_blocks, "tuned_ms": tune_ms, "tuning_s": time.time() - t1}
+                 "walk_blocks": base.walk_blocks, "rays_per_lane": base.rays_per_lane, "ray_queues": base.ray_queues,
+                 "tuned_ms": tune_ms, "tuning_s": time.time() - t1}
         log(f"autotuner: {tuned}")
 
     def opts_for(kernel=None, debug=0):
@@ -402,7 +410,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if (args.config == 2 and ms_walk is not None and not tuned
                                                        and args.kernel in (0, 2) and not args.refill
-                                                       and not args.walk_blocks) else None,
+                                                       and not args.walk_blocks and not args.queues) else None,
                      "kernel": "k_walk (persistent walk)" if ms_walk is not None else "k_exp_plain",
                      "algorithmic_bytes_per_launch": algo_bytes, "kernel_ms": ms_kernel,
                      # what the walk's loads request from the cache hierarchy per crossing (its 32-byte
@@ -416,8 +424,34 @@ def main():
         "cpu_baseline": cpu,
         "mesh_device_bytes": info["device_bytes"],
         "mesh_pack_s": pack_s,
+        "config3": None,
     }
+    if args.config == 2 and not args.no_config3:
+        res["config3"] = config3_leg()
     print(json.dumps(res), flush=True)
+
+
+def config3_leg():
+    """The 64-mesh batch as HIP-graph replays with the autotuner's schedule, run by
+    this script in a child process (its own workload and device memory)."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--config", "3", "--steps", "20", "--warmup", "3",
+           "--no-cpu-baseline", "--no-plain", "--no-bwd", "--no-pi"]
+    log("64-mesh batch leg: " + " ".join(cmd[1:]))
+    try:
+        p = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=600)
+    except subprocess.TimeoutExpired:
+        return {"error": "timed out"}
+    lines = [ln for ln in p.stdout.splitlines() if ln.startswith("{")]
+    if p.returncode != 0 or not lines:
+        return {"error": f"exit status {p.returncode}"}
+    r = json.loads(lines[-1])
+    rf = r["roofline"]
+    return {"workload": r["config"]["workload"], "faces": r["config"]["faces"], "rays": r["config"]["rays"],
+            "crossings": r["config"]["crossings"], "schedule": r["config"]["schedule"],
+            "graph_replay": True, "ms_per_step": r["ms_per_step"], "eager_ms_per_step": r["graph"]["eager_ms_per_step"],
+            "crossings_per_s": r["value"], "queries_per_s": r["queries_per_s"],
+            "walk_ms": rf["kernel_ms"], "walk_frac": rf["frac"], "whole_call_frac": rf["whole_call"]["frac"]}
 
 
 if __name__ == "__main__":

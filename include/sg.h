@@ -94,7 +94,8 @@ typedef struct {
     int32_t walk_blocks;   /* persistent kernel: 256-lane blocks launched; <= 0: three per CU */
     int32_t rays_per_lane; /* persistent kernel: rays each lane walks at once, 1 or 2; <= 0: tuned default */
     int32_t ray_queues;    /* persistent kernel: ray queues the walk claims rays from, a multiple of 8 (an
-                              equal share of each XCD) up to 64; <= 0: 8 */
+                              equal share of each XCD, which drains its queues one after another) up to 64;
+                              <= 0: 8 */
     int32_t boundary_mode; /* SG_BOUNDARY_STOP (default) or SG_BOUNDARY_AVOID; honoured by every kernel and
                               the backward (the vertex gradient leaves out rays that slid) */
     int32_t gradx_records; /* vertex gradient: edge crossings per query for which the workspace holds records

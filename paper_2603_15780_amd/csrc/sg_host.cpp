@@ -1098,7 +1098,7 @@ int sg_autotune(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const
     std::vector<TunePick> cands;
     cands.push_back({SG_KERNEL_PLAIN, base.refill_min, base.walk_blocks, 1, base.ray_queues, 0.0});
     const int refills[] = {4, 8, 16, 24, 32, 48};
-    for (int queues : {8, 16})
+    for (int queues : {8, 16, 64})
         for (int rpl = 1; rpl <= 2; ++rpl)
             for (int bpc = 1; bpc <= mesh->walk_blocks_per_cu; ++bpc)
                 for (int r : refills)

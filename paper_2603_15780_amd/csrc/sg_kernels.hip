@@ -793,12 +793,18 @@ SG_HD int hole_edge(const DevMesh& M, const Ray& old, const HalfEdgeRec& r, bool
 // edge into the next chart (transport_over_edge).  The crossing is computed
 // for every lane and committed with selects; stopping in the face, at the
 // step cap, at a vertex or on the boundary is one rarely taken branch.
-template <bool kHash, bool kFlip, bool kHole>
+// kPre: the caller passes sin and cos of st.phi (psn, pcs), already computed.
+template <bool kHash, bool kFlip, bool kHole, bool kPre = false>
 SG_HD __forceinline__ int walk_step(const DevMesh& M, Ray& st, int32_t max_steps, float snap, Final& fin,
-                                   bool alive = true) {
+                                   bool alive = true, float psn = 0.f, float pcs = 0.f) {
     const HalfEdgeRec r = rec_at(M, st.h);
     float sn, cs;
-    sincos_fx(st.phi, sn, cs);
+    if constexpr (kPre) {
+        sn = psn;
+        cs = pcs;
+    } else {
+        sincos_fx(st.phi, sn, cs);
+    }
     const float cross = fmaf(cs, r.cy, -sn * (r.cx - st.s));   // > 0: apex left of the ray
     const bool via_ca = (cross + st.bias) < 0.f;
     const float w = via_ca ? st.s : st.t;
@@ -1331,9 +1337,8 @@ struct alignas(8) GxRec {
 };
 static_assert(sizeof(GxRec) == 24, "grad-X record is 24 bytes");
 
-SG_HD __forceinline__ GxRec gx_terms(const Ray& st, const float4& c) {
-    float sn, cs;
-    sincos_fx(st.phi, sn, cs);
+// sn, cs: sin and cos of st.phi.
+SG_HD __forceinline__ GxRec gx_terms(const Ray& st, const float4& c, float sn, float cs) {
     const float sg = (st.par & kParity) ? -1.f : 1.f;
     const float lu = fmaf(c.x, cs, -sg * c.y * sn);
     const float lm = fmaf(c.x, sn, sg * c.y * cs);
@@ -1350,8 +1355,8 @@ SG_HD __forceinline__ GxRec gx_terms(const Ray& st, const float4& c) {
     return r;
 }
 
-SG_HD __forceinline__ void gx_cross(double* acc, const Ray& st, const float4& c) {
-    const GxRec r = gx_terms(st, c);
+SG_HD __forceinline__ void gx_cross(double* acc, const Ray& st, const float4& c, float sn, float cs) {
+    const GxRec r = gx_terms(st, c, sn, cs);
     double* q = acc + 5 * (int64_t)r.h;
     for (int k = 0; k < 5; ++k) add_f64(q + k, (double)r.q[k]);
 }
@@ -1378,6 +1383,9 @@ constexpr int64_t kGxMaxRecords = (int64_t)1 << 30;   // at most 48 GiB of recor
 // bytes per crossing do not displace the face records the walk re-reads
 // from L2.
 __device__ __forceinline__ void gx_store(GxRec* p, const GxRec& r) {
+    // six 4-byte stores: three 8-byte ones at the records' 24-byte stride made the
+    // walk 0.35 ms slower, and staging a wave's records in LDS for contiguous
+    // stores gained nothing
     uint32_t* d = reinterpret_cast<uint32_t*>(p);
     __builtin_nontemporal_store((uint32_t)r.h, d);
     for (int k = 0; k < 5; ++k) __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, r.q[k]), d + 1 + k);
@@ -1393,8 +1401,10 @@ struct GxSink {
 // Ray queues of the persistent walk.  The walk slots are in the order of
 // ray_bucket, whose nq queue ranges are spatial regions (nq / 8 per XCD):
 // blocks are dealt to the XCDs round-robin, so block b runs on XCD b % 8 and
-// starts on queue b % nq, one of that XCD's.  Each XCD then works through its
-// own region, long rays first, and the claim atomics spread over nq counters
+// starts on queue b % 8, the first of that XCD's.  Each XCD then works through
+// its own ranges one after another, long rays first within each, so its L2
+// holds the face records of one range at a time (with many meshes in a batch,
+// a range is about one mesh), and the claim atomics spread over eight counters
 // on separate 256-byte lines instead of serializing on one address.  A wave
 // whose queue runs dry moves on to the next one, first through its XCD's
 // other queues, so every queue is drained.  Queue q serves range
@@ -1414,7 +1424,7 @@ struct QueueRanges {
 
 SG_HD __forceinline__ QueueCursor queue_start(int nq) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    return QueueCursor{(int)(blockIdx.x % (unsigned)nq), nq, nq};
+    return QueueCursor{(int)(blockIdx.x & 7u), nq, nq};
 #else
     return QueueCursor{0, nq, nq};
 #endif
@@ -1467,6 +1477,7 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, Qu
     Ray st;
     st.h = 0; st.s = st.t = st.Lhi = st.Llo = st.bias = 0.f; st.phi = st.par = 0u; st.ncross = 0; st.hash = 0ull;
     float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+    float gsn = 0.f, gcs = 0.f;   // with kGX: sin and cos of st.phi, shared by the crossing's terms and the next step
     for (;;) {
         const uint64_t idle = __ballot(!active);
         const int nidle = __popcll(idle);
@@ -1485,7 +1496,10 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, Qu
                             st.ncross = 0;
                         }
                         st.hash = kHash ? fnv_face(14695981039346656037ull, (uint32_t)M.order[rec.h / 3]) : 0ull;
-                        if (kGX) c = cvec[q];
+                        if (kGX) {
+                            c = cvec[q];
+                            sincos_fx(st.phi, gsn, gcs);
+                        }
                         active = true;
                     }
                 }
@@ -1497,12 +1511,13 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, Qu
             bool cross = false;
             if (active) {
                 Final fin;
-                if (walk_step<kHash, kFlip, kHole>(M, st, max_steps, snap, fin) == kStepDone) {
+                if (walk_step<kHash, kFlip, kHole, kGX>(M, st, max_steps, snap, fin, true, gsn, gcs) == kStepDone) {
                     if (fin_out) fin_out[ray] = fin;
                     else *reinterpret_cast<Final*>(&states[q]) = fin;
                     active = false;
-                } else if (kGX && st.bias == 0.f) {   // an edge crossing (a vertex passage leaves a bias)
-                    cross = true;
+                } else if constexpr (kGX) {
+                    sincos_fx(st.phi, gsn, gcs);
+                    cross = st.bias == 0.f;   // an edge crossing (a vertex passage leaves a bias)
                 }
             }
             if constexpr (kGX) {
@@ -1524,11 +1539,11 @@ __device__ __forceinline__ void walk_loop(const DevMesh& M, StateRec* states, Qu
                     }
                     if (cross) {
                         if (!spill) {
-                            const GxRec r = gx_terms(st, c);
+                            const GxRec r = gx_terms(st, c, gsn, gcs);
                             gx_store(sink.rec + chunk * kGxChunk + used + __popcll(m & below), r);
                             atomicAdd(&lbins[r.h >> sink.shift], 1u);
                         } else {
-                            gx_cross(acc, st, c);
+                            gx_cross(acc, st, c, gsn, gcs);
                         }
                     }
                     if (!spill) used += cw;
@@ -1823,7 +1838,20 @@ __global__ __launch_bounds__(1024) void k_gx_reduce(const GxRec* sorted, const u
     for (int k = t; k < 5 * kGxWindow; k += 1024) s[k] = 0.0;
     __syncthreads();
     const uint32_t lo = start[bin], hi = start[bin + 1];
-    for (uint32_t i = lo + (uint32_t)t; i < hi; i += 1024u) {
+    // four records per thread in flight: one at a time leaves the loop bound by load latency
+    uint32_t i = lo + (uint32_t)t;
+    for (; i + 3u * 1024u < hi; i += 4u * 1024u) {
+        GxRec r[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r[j] = sorted[i + (uint32_t)j * 1024u];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t d = (int64_t)r[j].h - h0;
+            if (d >= 0 && d < kGxWindow)
+                for (int k = 0; k < 5; ++k) atomicAdd(&s[5 * d + k], (double)r[j].q[k]);
+        }
+    }
+    for (; i < hi; i += 1024u) {
         const GxRec r = sorted[i];
         const int64_t d = (int64_t)r.h - h0;
         if (d >= 0 && d < kGxWindow)
