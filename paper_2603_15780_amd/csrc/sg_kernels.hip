@@ -1115,7 +1115,7 @@ constexpr size_t kQueueBytes = (size_t)kMaxQueues * kQueueStride * sizeof(unsign
 // kernel that recomputes a ray's bucket gets the same one).
 constexpr int kLenClasses = 8;
 constexpr int kVmaxWord = kMaxBuckets + 1;   // cnt[kVmaxWord]: float bits of the longest |v|^2
-constexpr int kLenBlocks = 256;              // k_len_max blocks; their partial maxima follow kVmaxWord
+constexpr int kLenBlocks = 1024;             // k_len_max blocks; their partial maxima follow kVmaxWord
 constexpr int kCountWords = kMaxBuckets + 2 + kLenBlocks;   // words of the bucket-count array
 
 struct RayOrder {
@@ -1162,7 +1162,17 @@ __global__ __launch_bounds__(256) void k_len_max(int64_t n, const float* v, uint
     for (int j = (int)(blockIdx.x * blockDim.x + threadIdx.x); j <= kMaxBuckets; j += (int)(gridDim.x * blockDim.x))
         cnt[j] = 0u;
     uint32_t m = 0u;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {   // four rays in flight per thread
+        float l2[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) l2[j] = len2(v + 3 * (i + j * stride));
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (l2[j] <= 3.0e38f) m = max(m, __float_as_uint(l2[j]));
+    }
+    for (; i < n; i += stride) {
         const float l2 = len2(v + 3 * i);
         if (l2 <= 3.0e38f) m = max(m, __float_as_uint(l2));
     }
@@ -2631,7 +2641,6 @@ hipError_t launch_exp_plain(const DevMesh& M, const ExpArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// states [n] | epilogue terms [n, 1 + 2K] | walk slots [n] | bucket counts [kCountWords] | ray-queue counters
 // walk states (slot order) | final states (query order) | epilogue terms |
 // slots | internal start-face ids | bucket counts | queue counters
 struct PersistentLayout {
