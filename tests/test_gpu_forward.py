@@ -59,6 +59,20 @@ def test_config1_parity(torch, kernel):
 
 
 @pytest.mark.parametrize("kernel", [1, 2, 3])
+def test_golden_fixture(torch, kernel):
+    """The 64 rays stored in tests/golden/ with the oracle's answers: every
+    kernel matches them by the same criteria as the live oracle."""
+    from paper_2603_15780_amd import sg
+    from golden_io import load
+    ins, ref = load()
+    X, F = CF.mesh_config(1)
+    gm = sg.Mesh(X, F)
+    g = run(torch, gm, ins, kernel=kernel)
+    s = assert_parity(ref, g, gm.info()["mean_edge"], mesh=(X, F), K=1, label="golden")
+    assert s["hash_mis_far"] == 0 and s["n_near"] == 0, s
+
+
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 @pytest.mark.parametrize("n", [1, 63, 255, 257, 1000, 4097])
 def test_ragged_sizes(torch, n, kernel):
     X, F = CF.mesh_config(1)
