@@ -43,6 +43,8 @@ struct sg_mesh_s {
     int32_t* d_order = nullptr;
     int32_t* d_twin = nullptr;
     float* d_geo = nullptr;
+    int32_t* d_vc_off = nullptr;   // vertex -> corner lists (internal faces), for the vertex gradient
+    int32_t* d_vc = nullptr;
     int32_t part_he[sg::kParts + 1] = {};
     int32_t has_flip = 0;
     size_t bytes = 0;
@@ -160,6 +162,8 @@ void free_mesh(sg_mesh_s* m) {
     (void)hipFree(m->d_order);
     (void)hipFree(m->d_twin);
     (void)hipFree(m->d_geo);
+    (void)hipFree(m->d_vc_off);
+    (void)hipFree(m->d_vc);
     free_pi(m);
     delete m;
 }
@@ -775,6 +779,14 @@ int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, 
     m->has_flip = pm.has_flip;
     for (int p = 0; p <= sg::kParts; ++p) m->part_he[p] = (int32_t)(3 * pm.part_start[p]);
     std::vector<int32_t> order32(pm.order.begin(), pm.order.end());
+    // corners of each vertex (3 f + k over internal faces), grouped by vertex
+    std::vector<int32_t> vc_off((size_t)n_verts + 1, 0), vc((size_t)3 * n_faces);
+    for (int64_t c = 0; c < 3 * n_faces; ++c) ++vc_off[(size_t)pm.F[c] + 1];
+    for (int64_t v = 0; v < n_verts; ++v) vc_off[(size_t)v + 1] += vc_off[(size_t)v];
+    {
+        std::vector<int32_t> at(vc_off.begin(), vc_off.end() - 1);
+        for (int64_t c = 0; c < 3 * n_faces; ++c) vc[(size_t)at[(size_t)pm.F[c]]++] = (int32_t)c;
+    }
     rc = upload(&m->d_face, pm.face, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_F, pm.F, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_X, pm.X, m->bytes);
@@ -783,6 +795,8 @@ int sg_mesh_create(const float* X_host, int64_t n_verts, const int32_t* F_host, 
     if (rc == SG_OK) rc = upload(&m->d_order, order32, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_twin, pm.twin, m->bytes);
     if (rc == SG_OK) rc = upload(&m->d_geo, pm.geo, m->bytes);
+    if (rc == SG_OK) rc = upload(&m->d_vc_off, vc_off, m->bytes);
+    if (rc == SG_OK) rc = upload(&m->d_vc, vc, m->bytes);
     if (rc != SG_OK) {
         free_mesh(m);
         return rc;
@@ -978,6 +992,8 @@ int sg_exp_backward_transport(sg_mesh mesh, int32_t mode, int64_t n, const int32
     const hipStream_t st = (hipStream_t)stream;
     Workspace ws;
     a.gx_records = o.gradx_records;
+    a.vc_off = mesh->d_vc_off;
+    a.vc = mesh->d_vc;
     rc = take_workspace(o, bwd_workspace_bytes(o, mesh, n, mode, vjp, a.grad_X != nullptr, f_out != nullptr,
                                                b_out != nullptr, v_out != nullptr, status != nullptr),
                         st, ws);

@@ -1182,11 +1182,6 @@ __global__ __launch_bounds__(256) void k_len_max(int64_t n, const float* v, uint
     if (threadIdx.x == 0) cnt[kVmaxWord + 1 + blockIdx.x] = max(max(part[0], part[1]), max(part[2], part[3]));
 }
 
-__global__ __launch_bounds__(256) void k_zero_u32(uint32_t* p, int n) {
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i < n) p[i] = 0u;
-}
-
 // Rank of each ray inside its bucket: a 1024-thread block counts its
 // kBucketRays rays in LDS (the LDS atomic returns the local rank), then adds
 // each nonzero local count to the bucket's global counter once (returning the
@@ -1741,6 +1736,26 @@ __device__ __forceinline__ uint32_t block_scan4096(uint32_t* x, int n, uint32_t*
         }
     lds_barrier();
     return total;
+}
+
+// Exclusive prefix sums of x[0, n) in place, in three launches: each block
+// scans a tile of 4,096 entries and leaves its total in tile[b]; one block
+// scans the totals; each block adds its tile's offset.
+__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* x, int64_t n, uint32_t* tile) {
+    __shared__ uint32_t v[4096];
+    __shared__ uint32_t wsum[16];
+    const int64_t o = (int64_t)blockIdx.x * 4096;
+    const int m = (int)std::min<int64_t>(4096, n - o);
+    for (int k = (int)threadIdx.x; k < m; k += 1024) v[k] = x[o + k];
+    __syncthreads();
+    const uint32_t total = block_scan4096(v, m, wsum);
+    for (int k = (int)threadIdx.x; k < m; k += 1024) x[o + k] = v[k];
+    if (threadIdx.x == 0) tile[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(uint32_t* x, int64_t n, const uint32_t* tile) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += tile[i >> 12];
 }
 
 __global__ __launch_bounds__(1024) void k_gx_scatter(const GxRec* __restrict__ rec, const uint32_t* __restrict__ fill,
@@ -2406,10 +2421,14 @@ SG_HD void ep_walked(const DevMesh& M, const BwdArgs& a, const StateRec* s1, int
 
 // Start term and the walk's initial state; c = components of g on the end frame
 // [d', nu' x d', nu'] of the base walk (slot `stride * i` of s1).
+// The start term (the query's terms on its start face's three vertices) goes
+// to sterm[i] (nine floats), counted per start face in fcnt with the query's
+// rank in srank[i] (-1: no start term), so the face pass can gather it.
 SG_HD void gradx_init(const DevMesh& M, const BwdArgs& a, const StateRec* s1, int stride, StateRec* s3, float4* cvec,
-                      int64_t i) {
+                      float* sterm, int32_t* srank, uint32_t* fcnt, int64_t i) {
     const int64_t at = bwd_at(a, i);
     s3[at] = dead_state();
+    srank[i] = -1;
     StartFrame S;
     uint32_t phi0;
     float L, Llo = 0.f;
@@ -2467,12 +2486,13 @@ SG_HD void gradx_init(const DevMesh& M, const BwdArgs& a, const StateRec* s1, in
     const float dh2 = wm / cy;
     const float dh[3] = {-(dh1 + dh2), dh1, dh2};
     const float bk[3] = {S.b0, S.b1, S.b2};
+    float* q = sterm + 9 * i;
     for (int k = 0; k < 3; ++k) {
-        double* gx = a.grad_X + 3 * (int64_t)M.F[f3 + k];
-        add_f64(gx, (double)fmaf(bk[k], lam.x, dh[k] * S.n.x));
-        add_f64(gx + 1, (double)fmaf(bk[k], lam.y, dh[k] * S.n.y));
-        add_f64(gx + 2, (double)fmaf(bk[k], lam.z, dh[k] * S.n.z));
+        q[3 * k] = fmaf(bk[k], lam.x, dh[k] * S.n.x);
+        q[3 * k + 1] = fmaf(bk[k], lam.y, dh[k] * S.n.y);
+        q[3 * k + 2] = fmaf(bk[k], lam.z, dh[k] * S.n.z);
     }
+    srank[i] = (int32_t)atomicAdd(&fcnt[S.f], 1u);
     if (!(L > 0.f)) return;
     Ray st;
     if (enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, Llo, st) != kInitOk) return;
@@ -2487,7 +2507,6 @@ SG_HD __forceinline__ double ddot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a
 SG_HD __forceinline__ D3 dcrs(D3 a, D3 b) { return D3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
 SG_HD __forceinline__ D3 dscl(D3 a, double s) { return D3{a.x * s, a.y * s, a.z * s}; }
 SG_HD __forceinline__ D3 dmad(D3 a, double s, D3 b) { return D3{a.x + s * b.x, a.y + s * b.y, a.z + s * b.z}; }
-SG_HD __forceinline__ void dadd_atomic(double* g, D3 v) { add_f64(g, v.x); add_f64(g + 1, v.y); add_f64(g + 2, v.z); }
 
 // Edge pass: half-edge h (entered from its twin's face).  The rotation rate of
 // a face's edge frame (u, m toward the apex, n = u x m) under normal offsets
@@ -2550,25 +2569,56 @@ SG_HD bool gradx_edge(const DevMesh& M, const double* acc, int64_t h, D3& ga_out
     return true;
 }
 
-// Face pass: the terms of face f's three entered half-edges.  Those that fall
-// on f's own vertices (each edge's a and b, and the apex c) are summed per
-// vertex first, so a face adds 9 float64 atomics for them instead of 27.
-SG_HD void gradx_face(const DevMesh& M, const double* acc, double* grad_X, int64_t f) {
+// Face pass: the terms of face f's three entered half-edges.  Those on f's own
+// vertices (each edge's a and b, and the apex c) are summed per corner into
+// own[f, k]; the term on the apex of the face across half-edge 3 f + k goes to
+// far[3 f + k].  Every entry is written, so the buffer needs no clearing, and
+// the vertex pass gathers them without atomics (float64 atomics to random
+// addresses run at a fixed rate of about 2.3e10 per second).
+SG_HD void gradx_face(const DevMesh& M, const BwdArgs& a, const double* acc, double* own, double* far, int64_t f) {
     D3 g[3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-    bool any = false;
-    for (int k = 0; k < 3; ++k) {
-        D3 ga, gb, gc, gp;
-        int32_t ip;
-        if (!gradx_edge(M, acc, 3 * f + k, ga, gb, gc, gp, ip)) continue;
-        any = true;
-        const int kb = k == 2 ? 0 : k + 1, kc = k == 0 ? 2 : k - 1;
-        g[k] = dmad(g[k], 1.0, ga);
-        g[kb] = dmad(g[kb], 1.0, gb);
-        g[kc] = dmad(g[kc], 1.0, gc);
-        dadd_atomic(grad_X + 3 * (int64_t)ip, gp);
+    for (uint32_t j = a.fstart[f]; j < a.fstart[f + 1]; ++j) {   // start terms of the queries that start in f
+        const float* q = a.sterm + 9 * (int64_t)a.qlist[j];
+        for (int k = 0; k < 3; ++k) g[k] = D3{g[k].x + (double)q[3 * k], g[k].y + (double)q[3 * k + 1], g[k].z + (double)q[3 * k + 2]};
     }
-    if (!any) return;
-    for (int k = 0; k < 3; ++k) dadd_atomic(grad_X + 3 * (int64_t)M.F[3 * f + k], g[k]);
+    for (int k = 0; k < 3; ++k) {
+        D3 ga, gb, gc, gp = {0.0, 0.0, 0.0};
+        int32_t ip;
+        if (gradx_edge(M, acc, 3 * f + k, ga, gb, gc, gp, ip)) {
+            const int kb = k == 2 ? 0 : k + 1, kc = k == 0 ? 2 : k - 1;
+            g[k] = dmad(g[k], 1.0, ga);
+            g[kb] = dmad(g[kb], 1.0, gb);
+            g[kc] = dmad(g[kc], 1.0, gc);
+        }
+        double* q = far + 3 * (3 * f + k);
+        q[0] = gp.x; q[1] = gp.y; q[2] = gp.z;
+    }
+    for (int k = 0; k < 3; ++k) {
+        double* q = own + 3 * (3 * f + k);
+        q[0] = g[k].x; q[1] = g[k].y; q[2] = g[k].z;
+    }
+}
+
+// Vertex pass: vertex v sums own[f, k] over its corners (f, k) and far[h] over
+// the half-edges h across the edge opposite each corner (their far apex is v),
+// and adds the total to grad_X once.
+SG_HD void gradx_vertex(const DevMesh& M, const BwdArgs& a, const double* own, const double* far, int64_t v) {
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int32_t j = a.vc_off[v]; j < a.vc_off[v + 1]; ++j) {
+        const int32_t c = a.vc[j];
+        const int32_t f = c / 3, k = c - 3 * f;
+        const double* q = own + 3 * (int64_t)c;
+        sx += q[0]; sy += q[1]; sz += q[2];
+        const int32_t t = M.twin[3 * f + (k == 2 ? 0 : k + 1)];
+        if (t >= 0) {
+            const double* r = far + 3 * (int64_t)t;
+            sx += r[0]; sy += r[1]; sz += r[2];
+        }
+    }
+    if (sx != 0.0 || sy != 0.0 || sz != 0.0) {
+        double* gx = a.grad_X + 3 * v;
+        gx[0] += sx; gx[1] += sy; gx[2] += sz;
+    }
 }
 
 // Walks one chart state to its end in place (sequential form of k_walk).
@@ -2593,12 +2643,19 @@ SG_ROW_KERNEL(k_bwd_stage2, bwd_stage2(M, a, s1, s2, i), const StateRec* s1, Sta
 SG_ROW_KERNEL(k_gfd_assemble, gfd_assemble(M, a, s1, s2, i), const StateRec* s1, const StateRec* s2)
 SG_ROW_KERNEL(k_ep_saved, ep_saved(M, a, i))
 SG_ROW_KERNEL(k_ep_walked, ep_walked(M, a, s1, stride, i), const StateRec* s1, int stride)
-SG_ROW_KERNEL(k_gradx_init, gradx_init(M, a, s1, stride, s3, cvec, i), const StateRec* s1, int stride, StateRec* s3,
-              float4* cvec)
+SG_ROW_KERNEL(k_gradx_init, gradx_init(M, a, s1, stride, s3, cvec, sterm, srank, fcnt, i), const StateRec* s1,
+              int stride, StateRec* s3, float4* cvec, float* sterm, int32_t* srank, uint32_t* fcnt)
+// qlist[fstart[f] + rank] = query: the queries of each start face, in a list
+SG_ROW_KERNEL(k_gradx_start_place, if (a.srank[i] >= 0) a.qlist[a.fstart[M.perm[a.f[i]]] + a.srank[i]] = (int32_t)i)
 #undef SG_ROW_KERNEL
 
 __global__ __launch_bounds__(64) void k_reset_counter(unsigned long long* c) {
     if (threadIdx.x < (unsigned)kMaxQueues) c[threadIdx.x * kQueueStride] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_zero_u32(uint32_t* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_zero_f64(double* p, int64_t n) {
@@ -2606,9 +2663,14 @@ __global__ __launch_bounds__(256) void k_zero_f64(double* p, int64_t n) {
         p[i] = 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_gradx_faces(DevMesh M, const double* acc, double* grad_X) {
+__global__ __launch_bounds__(256) void k_gradx_faces(DevMesh M, BwdArgs a, const double* acc, double* gxv) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < M.n_faces) gradx_face(M, acc, grad_X, f);
+    if (f < M.n_faces) gradx_face(M, a, acc, gxv, gxv + 9 * M.n_faces, f);
+}
+
+__global__ __launch_bounds__(256) void k_gradx_vertices(DevMesh M, BwdArgs a, const double* gxv) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < M.n_verts) gradx_vertex(M, a, gxv, gxv + 9 * M.n_faces, v);
 }
 
 }  // namespace
@@ -2807,7 +2869,8 @@ hipError_t launch_exp_partitioned(const DevMesh& M, const ExpArgs& a, void* ws, 
 // totals scanned into starts, chunks used per walk block, the (walk block,
 // bin) count matrix).
 struct BwdLayout {
-    size_t s1, s2, s3, cvec, acc, slot, cnt, counter, rec, sorted, fill, bins, total;
+    size_t s1, s2, s3, cvec, acc, gxv, sterm, srank, fstart, ftile, qlist, slot, cnt, counter, rec, sorted, fill, bins,
+        total;
     int per_block;   // record chunks per walk block (0: no records)
     int shift, nbins;
 };
@@ -2850,6 +2913,12 @@ static BwdLayout bwd_layout(int64_t n, const BwdPlan& P, bool gradx, int64_t n_f
     L.s3 = o; o = align256(o + (gradx ? (size_t)n * sizeof(StateRec) : 0));
     L.cvec = o; o = align256(o + (gradx ? (size_t)n * sizeof(float4) : 0));
     L.acc = o; o = align256(o + (gradx ? 15 * (size_t)n_faces * sizeof(double) : 0));
+    L.gxv = o; o = align256(o + (gradx ? 18 * (size_t)n_faces * sizeof(double) : 0));
+    L.sterm = o; o = align256(o + (gradx ? 9 * (size_t)n * sizeof(float) : 0));
+    L.srank = o; o = align256(o + (gradx ? (size_t)n * sizeof(int32_t) : 0));
+    L.fstart = o; o = align256(o + (gradx ? ((size_t)n_faces + 1) * sizeof(uint32_t) : 0));
+    L.ftile = o; o = align256(o + (gradx ? (((size_t)n_faces + 1 + 4095) / 4096) * sizeof(uint32_t) : 0));
+    L.qlist = o; o = align256(o + (gradx ? (size_t)n * sizeof(int32_t) : 0));
     L.slot = o; o = align256(o + (walk ? (size_t)n * sizeof(int32_t) : 0));
     L.cnt = o; o = align256(o + (walk ? (size_t)kCountWords * sizeof(uint32_t) : 0));
     L.counter = o; o = align256(o + kQueueBytes);
@@ -2936,8 +3005,27 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
         const int64_t nacc = 15 * M.n_faces;
         hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)std::min<int64_t>((nacc + block - 1) / block, 8192)), dim3(block),
                            0, s, acc, nacc);
+        auto* sterm = reinterpret_cast<float*>(base + L.sterm);
+        auto* srank = reinterpret_cast<int32_t*>(base + L.srank);
+        auto* fstart = reinterpret_cast<uint32_t*>(base + L.fstart);
+        a.sterm = sterm;
+        a.srank = srank;
+        a.fstart = fstart;
+        a.qlist = reinterpret_cast<int32_t*>(base + L.qlist);
+        const int64_t nfs = M.n_faces + 1;
+        hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::min<int64_t>((nfs + block - 1) / block, 8192)), dim3(block),
+                           0, s, fstart, nfs);
         hipLaunchKernelGGL(k_gradx_init, dim3((unsigned)grid), dim3(block), 0, s, M, a,
-                           P.gx_saved ? (const StateRec*)nullptr : (const StateRec*)s1, per1, s3, cvec);
+                           P.gx_saved ? (const StateRec*)nullptr : (const StateRec*)s1, per1, s3, cvec, sterm, srank,
+                           fstart);
+        // each start face's queries as one list (counts to offsets, then the ranks place them)
+        const int64_t ntile = (nfs + 4095) / 4096;
+        auto* tile = reinterpret_cast<uint32_t*>(base + L.ftile);
+        hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntile), dim3(1024), 0, s, fstart, nfs, tile);
+        hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, tile, (int)ntile);
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((nfs + block - 1) / block)), dim3(block), 0, s, fstart, nfs,
+                           (const uint32_t*)tile);
+        hipLaunchKernelGGL(k_gradx_start_place, dim3((unsigned)grid), dim3(block), 0, s, M, a);
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
         const int64_t nh = 3 * M.n_faces;
         GxSink sink{};
@@ -2977,8 +3065,11 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
             hipLaunchKernelGGL(k_gx_reduce, dim3((unsigned)(L.nbins * wpb)), dim3(1024), 0, s,
                                (const GxRec*)(base + L.sorted), (const uint32_t*)bins, L.shift, nh, acc);
         }
-        hipLaunchKernelGGL(k_gradx_faces, dim3((unsigned)((M.n_faces + block - 1) / block)), dim3(block), 0, s, M,
-                           acc, a.grad_X);
+        auto* gxv = reinterpret_cast<double*>(base + L.gxv);
+        hipLaunchKernelGGL(k_gradx_faces, dim3((unsigned)((M.n_faces + block - 1) / block)), dim3(block), 0, s, M, a,
+                           (const double*)acc, gxv);
+        hipLaunchKernelGGL(k_gradx_vertices, dim3((unsigned)((M.n_verts + block - 1) / block)), dim3(block), 0, s,
+                           M, a, (const double*)gxv);
     }
     return hipGetLastError();
 }

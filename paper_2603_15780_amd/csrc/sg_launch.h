@@ -55,6 +55,14 @@ struct BwdArgs {
     const int32_t* slot;    // position of each query in the walk arrays (set by the launcher), or null
     int32_t gx_records;     // grad-X records reserved per query for binned accumulation (<= 0: atomics only)
     int32_t gfd_saved;      // (set by the launcher) GFD takes the base geodesic's end from f_out, b_out, v_out
+    const int32_t* vc_off;  // [n_verts + 1] vertex -> corner list offsets (the vertex gradient's gather)
+    const int32_t* vc;      // [3 n_faces] corners 3 f + k (internal face f, corner k) of each vertex
+    // (set by the launcher) the vertex gradient's start terms: nine floats per query,
+    // each query's rank among those of its start face, the faces' list offsets, the lists
+    const float* sterm;
+    const int32_t* srank;
+    const uint32_t* fstart;
+    int32_t* qlist;
 };
 
 // Host-side result of packing a mesh (float64 work, rounded once).
