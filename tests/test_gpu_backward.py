@@ -488,6 +488,33 @@ def test_autograd_function(torch):
     assert sx["frac_ok"] >= 0.999 and sx["global_rel"] < 1e-4, sx
 
 
+def test_gradx_unreferenced_vertex_and_batched_meshes(torch):
+    """The vertex pass sums per vertex over its corner list: a vertex no face
+    uses gets exactly zero and the others what they get without it; two meshes
+    batched in one handle get each mesh's own gradient (global vertex ids)."""
+    from paper_2603_15780_amd import sg
+    X, F = CF.mesh_config(1)
+    r = CF.rays_config(1, X, F, n=2048)
+    g = CF.upstream_grad(1, 2048)
+    ref, _ = gpu_gradx(torch, sg.Mesh(X, F), r, g)
+    assert np.abs(ref).max() > 0
+    X2 = np.vstack([X, np.array([[2.0, 0.5, -0.25]], np.float32)])
+    got, _ = gpu_gradx(torch, sg.Mesh(X2, F), r, g)
+    assert np.all(got[-1] == 0.0)
+    assert np.allclose(got[:-1], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    # a second, displaced mesh after the first in one handle
+    XB = M.sh_displace(X, 4, 0.05, np.random.default_rng(77)).astype(np.float32)
+    rB = CF.rays_config(1, XB, F, n=2048, seed_offset=1)
+    gB = CF.upstream_grad(1, 4096)[2048:]
+    refB, _ = gpu_gradx(torch, sg.Mesh(XB, F), rB, gB)
+    nv, nf = X.shape[0], F.shape[0]
+    gm = sg.Mesh(np.vstack([X, XB]), np.vstack([F, F]), [0, nv, 2 * nv], [0, nf, 2 * nf])
+    rr = {k: np.concatenate([r[k], rB[k] + (nf if k == "f" else 0)]) for k in ("f", "b", "v")}
+    both, _ = gpu_gradx(torch, gm, rr, np.concatenate([g, gB]))
+    want = np.vstack([ref, refB])
+    assert np.allclose(both, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_backward_mesh_with_holes(torch, mode):
     """A mesh with holes: rays that stop on the boundary are left out of the
