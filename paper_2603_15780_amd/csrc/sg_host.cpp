@@ -697,23 +697,24 @@ int pack_geometry(const float* X_host, PackedMesh& pm) {
         for (int64_t v = 0; v < n_verts; ++v) pm.half[v] = pm.vbnd[v] ? -1 : theta_fx[v] / 2;
         pm.X.assign(X_host, X_host + 3 * n_verts);
         pm.mean_edge = esum / (double)ecount;
-        // 128-byte geometry records: the three vertices (w: vertex id), the user
-        // face id, and a copy of the face's walk record, so a start or end
-        // frame takes one line
-        static_assert(sizeof(FaceRec) == 32, "the walk record fills two float4 of the geometry record");
-        pm.geo.assign(32 * (size_t)n_faces, 0.f);
+        // 64-byte geometry records: the three vertices (w: the walk record's
+        // edge lengths), its two corners and the user face id, so a start or
+        // end frame takes one 64-byte segment
+        pm.geo.assign(16 * (size_t)n_faces, 0.f);
         for (int64_t f = 0; f < n_faces; ++f) {
-            float* g = &pm.geo[32 * (size_t)f];
-            std::memcpy(&g[16], &pm.face[f], sizeof(FaceRec));
+            float* g = &pm.geo[16 * (size_t)f];
+            const FaceRec& q = pm.face[f];
             for (int k = 0; k < 3; ++k) {
                 const int32_t v = F[3 * f + k];
                 g[4 * k] = X_host[3 * (int64_t)v];
                 g[4 * k + 1] = X_host[3 * (int64_t)v + 1];
                 g[4 * k + 2] = X_host[3 * (int64_t)v + 2];
-                std::memcpy(&g[4 * k + 3], &v, sizeof v);
+                g[4 * k + 3] = q.l[k];
             }
             const int32_t u = (int32_t)pm.order[f];
-            std::memcpy(&g[12], &u, sizeof u);
+            std::memcpy(&g[12], &q.c0, sizeof q.c0);
+            std::memcpy(&g[13], &q.c1, sizeof q.c1);
+            std::memcpy(&g[14], &u, sizeof u);
         }
         return SG_OK;
     } catch (const std::bad_alloc&) {

@@ -60,9 +60,9 @@ struct DevMesh {
     int32_t part_he[kParts + 1];// half-edge id ranges of the parts
     const int32_t* twin;        // [3 n_faces] half-edge on the other side of each edge, -1 on the boundary
     int32_t hole_avoid;         // per call: 1 = trace along boundaries instead of stopping (Sec. 4)
-    const float4* geo;          // [n_faces, 8]: the face's three vertex positions (w: global vertex id bits),
-                                // (user face id bits, 0, 0, 0), a copy of its FaceRec (two float4) and
-                                // padding: one 128-byte line per face
+    const float4* geo;          // [n_faces, 4]: the face's three vertex positions (w: its FaceRec's edge
+                                // lengths l[0..2]), then (c0 bits, c1 bits, user face id bits, 0): one
+                                // 64-byte record per face
 };
 
 // ---- projection integration (appendix "Projection Integration Exp Map"):

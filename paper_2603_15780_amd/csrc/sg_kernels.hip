@@ -117,11 +117,18 @@ SG_HD __forceinline__ HalfEdgeRec rec_at(const DevMesh& M, int32_t h) {
     return rec_decode(q, (uint32_t)h - 3u * f);
 }
 
-// The same chart from the copy of the face record inside the 128-byte
-// geometry record (start and end frames read that line anyway).
+// The same chart from the 64-byte geometry record, which holds the walk
+// record's lengths and corners (start and end frames read that record anyway;
+// no caller of this form uses the neighbour links, which it leaves at -1).
 SG_HD __forceinline__ HalfEdgeRec rec_geo(const DevMesh& M, int32_t h) {
     const uint32_t f = (uint32_t)h / 3u;
-    const FaceRec q = *reinterpret_cast<const FaceRec*>(M.geo + 8 * (int64_t)f + 4);
+    const float4* g = M.geo + 4 * (int64_t)f;
+    const float4 g0 = g[0], g1 = g[1], g2 = g[2], g3 = g[3];
+    FaceRec q;
+    q.l[0] = g0.w; q.l[1] = g1.w; q.l[2] = g2.w;
+    q.c0 = __builtin_bit_cast(uint32_t, g3.x);
+    q.c1 = __builtin_bit_cast(uint32_t, g3.y);
+    q.nb[0] = q.nb[1] = q.nb[2] = -1;
     return rec_decode(q, (uint32_t)h - 3u * f);
 }
 
@@ -136,15 +143,15 @@ SG_HD __forceinline__ float rcp(float x) {
 
 SG_HD __forceinline__ float3 ld3(const float* p) { return make_float3(p[0], p[1], p[2]); }
 SG_HD __forceinline__ float3 sub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
-// Position of vertex k (0..2, face order) of internal face f: one 128-byte
-// record per face holds the three positions (w: the global vertex id), the
-// user face id and a copy of the face's walk record, so an epilogue or a
-// start frame takes one line, not five.
+// Position of vertex k (0..2, face order) of internal face f: one 64-byte
+// record per face holds the three positions (w: the walk record's edge
+// lengths), the walk record's two corners and the user face id, so an
+// epilogue or a start frame takes one 64-byte segment.
 SG_HD __forceinline__ float3 fvx(const DevMesh& M, int64_t f, int k) {
-    const float4 q = M.geo[8 * f + k];
+    const float4 q = M.geo[4 * f + k];
     return make_float3(q.x, q.y, q.z);
 }
-SG_HD __forceinline__ int32_t face_user(const DevMesh& M, int64_t f) { return __builtin_bit_cast(int32_t, M.geo[8 * f + 3].x); }
+SG_HD __forceinline__ int32_t face_user(const DevMesh& M, int64_t f) { return __builtin_bit_cast(int32_t, M.geo[4 * f + 3].z); }
 SG_HD __forceinline__ float dot(float3 a, float3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
 SG_HD __forceinline__ float3 crs(float3 a, float3 b) {
     return make_float3(fmaf(a.y, b.z, -a.z * b.y), fmaf(a.z, b.x, -a.x * b.z), fmaf(a.x, b.y, -a.y * b.x));

@@ -76,7 +76,7 @@ struct PackedMesh {
     std::vector<int64_t> half;
     std::vector<int32_t> twin;        // half-edge across each edge (internal ids), -1 on the boundary
     std::vector<uint8_t> vbnd;        // vertex lies on a boundary edge
-    std::vector<float> geo;           // [n_faces, 16]: per-face vertex positions and user id (DevMesh::geo)
+    std::vector<float> geo;           // [n_faces, 16]: per-face positions, lengths, corners, user id (DevMesh::geo)
     std::vector<int64_t> face_off;    // [n_meshes + 1] user face offsets of the batched meshes
     int64_t n_verts = 0, n_faces = 0;
     double mean_edge = 0.0;
