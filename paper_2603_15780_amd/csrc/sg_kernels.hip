@@ -184,7 +184,7 @@ SG_HD __forceinline__ uint32_t rad_to_fx(float a) {
 // backwards to the edge it would have entered through, so the walk always
 // starts on an entry edge with remaining length L + tau (initialise_trace).
 // ell0 is the length of the chart's x-axis edge.  kGeo: the chart comes from
-// the geometry record (a start frame has read that line), else from the
+// the geometry record (a start frame has read that record), else from the
 // compact walk record.
 template <bool kGeo = true>
 SG_HD int enter_face(const DevMesh& M, int32_t f, int k0, float ell0, float bA, float bB, float bC, uint32_t phi0,
