@@ -2,7 +2,7 @@
 
 Tolerances (endpoint 1e-4 x mean edge for at least 99.9% of rays; face and
 face-sequence divergence only where the float64 path passes within 1e-6 of a
-vertex; transported-vector angle 1e-4 rad) are the spec bar for the
+vertex; transported-vector angle 1e-4 rad) are the parity bar for the
 float32 tracer.  Where several answers are correct (an endpoint on a shared
 edge may be reported in either face; paths through a vertex neighbourhood may
 split) the unique part is compared and the rest is checked for validity.
