@@ -90,7 +90,8 @@ typedef struct {
                               bit 2: time the walk kernel with HIP events (read with sg_mesh_walk_time);
                               bit 3 (sg_autotune): tune again even for a cached class of batches */
     int32_t refill_min;    /* persistent kernel: a wave refetches rays once this many of its 64 lanes are
-                              idle (of 128 ray slots with two rays per lane); <= 0: 32 per 64 slots */
+                              idle (of 128 ray slots with two rays per lane); <= 0: 48 per 64 slots in
+                              the forward, 32 in the backward's walks */
     int32_t walk_blocks;   /* persistent kernel: 256-lane blocks launched; <= 0: three per CU */
     int32_t rays_per_lane; /* persistent kernel: rays each lane walks at once, 1 or 2; <= 0: tuned default */
     int32_t ray_queues;    /* persistent kernel: ray queues the walk claims rays from, a multiple of 8 (an

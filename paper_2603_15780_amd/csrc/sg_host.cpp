@@ -180,7 +180,7 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     if (o.kernel == SG_KERNEL_AUTO) o.kernel = SG_KERNEL_PERSISTENT;
     if (o.rays_per_lane <= 0) o.rays_per_lane = 1;
     if (o.rays_per_lane > 2) return fail(SG_E_ARG, "rays_per_lane must be 1 or 2");
-    if (o.refill_min <= 0) o.refill_min = 32 * o.rays_per_lane;
+    if (o.refill_min <= 0) o.refill_min = 48 * o.rays_per_lane;
     if (o.refill_min > 64 * o.rays_per_lane) return fail(SG_E_ARG, "refill_min must be at most 64 per ray slot");
     if (o.boundary_mode != SG_BOUNDARY_STOP && o.boundary_mode != SG_BOUNDARY_AVOID)
         return fail(SG_E_ARG, "unknown boundary_mode %d", o.boundary_mode);
@@ -188,8 +188,8 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     if (o.gradx_records == 0) o.gradx_records = 256;
     if (o.ray_queues % 8 != 0 || o.ray_queues > sg::kMaxQueues)
         return fail(SG_E_ARG, "ray_queues must be a multiple of 8, at most %d", sg::kMaxQueues);
-    // default schedule: three resident 256-lane blocks per CU, refill at 32 idle lanes (the
-    // fastest in a sweep on the 327k-face workload)
+    // default schedule: three resident 256-lane blocks per CU, refill at 48 idle lanes (the
+    // fastest in sweeps of 32-60 on 1M, 5.6M and 16.8M rays; the backward keeps 32)
     if (o.walk_blocks <= 0)
         o.walk_blocks = m->cu_count * std::min(3, o.kernel == SG_KERNEL_PARTITIONED ? m->part_blocks_per_cu
                                                                                    : m->walk_blocks_per_cu);
@@ -228,10 +228,13 @@ hipError_t give_workspace(Workspace& w, hipStream_t st) {
 }
 
 // The backward always runs the persistent walk: a partitioned choice of
-// kernel takes the persistent walk's block count.
+// kernel takes the persistent walk's block count.  Its walks refill at 32 idle
+// lanes by default (the forward's 48 made the finite-difference passes, whose
+// queues interleave several walks per query, 3.3 -> 3.9 ms on 1M queries).
 int check_bwd_opts(const sg_opts* in, sg_opts& o, sg_mesh m) {
     const int rc = check_opts(in, o, m);
     if (rc == SG_OK && o.kernel == SG_KERNEL_PARTITIONED) o.walk_blocks = m->cu_count * m->walk_blocks_per_cu;
+    if (rc == SG_OK && !(in && in->refill_min > 0)) o.refill_min = 32 * o.rays_per_lane;
     return rc;
 }
 
