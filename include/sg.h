@@ -234,8 +234,11 @@ int sg_exp_transport_noalloc(sg_mesh mesh, int64_t n, const int32_t* f, const fl
  *        rigid unfoldings about the crossed edges, with the combinatorics
  *        frozen.  The geodesic is re-walked for the adjoint's per-edge
  *        terms (one record per crossing, summed per half-edge in float64
- *        after grouping by half-edge range), then one pass maps each crossed
- *        edge's sums to its four hinge vertices with float64 atomics.  The
+ *        after grouping by half-edge range); a pass over the faces maps each
+ *        crossed edge's sums to its four hinge vertices, and a pass over the
+ *        vertices adds each vertex's total to grad_X once (no atomics on
+ *        grad_X: calls that accumulate into one grad_X must be ordered, for
+ *        instance by running on one stream).  The
  *        adjoint starts from the end frame: taken from the forward's saved
  *        f_out, v_out and status when all three are given, the faces agree
  *        in orientation, hole avoidance is off and the mode is EP (or only
@@ -245,10 +248,11 @@ int sg_exp_transport_noalloc(sg_mesh mesh, int64_t n, const int32_t* f, const fl
  *        nothing.  A vertex passage is not a hinge: such rays contribute their
  *        edge and start terms with the vertex rule held fixed, which is not
  *        the derivative of the map (give them g_p = 0 to exclude them).
- *        Float64 atomics make grad_X's last bits depend on timing.
+ *        The order of the float64 sums depends on timing, so grad_X's last
+ *        bits may differ between calls.
  * Queries the forward rejects (SG_RAY_BADINPUT) get NaN in grad_v, grad_b.
  * Uses a stream-ordered device workspace (GFD 224 bytes per query, a re-walk
- * 32; grad_X 48 per query plus 120 per face plus 48 per record, see
+ * 32; grad_X 96 per query plus 272 per face plus 48 per record, see
  * gradx_records).  opts: max_steps, vertex_snap, eps_v, eps_p, refill_min,
  * walk_blocks, ray_queues, gradx_records are honoured; kernel is ignored (the
  * persistent walk always runs).  n < 2^31 (SG_E_ARG otherwise).
