@@ -2170,15 +2170,18 @@ SG_HD __forceinline__ void transport_cot(const BwdArgs& a, int64_t i, bool ident
         }
 }
 
-// Stage 1: the walks that start at p.  Slot 0 recomputes Exp(p, v); for the
-// geodesic finite differences (eqs. jv, jp) slot 1 is Exp(p, v + eps_v e_perp),
-// slots 2 and 3 are the short walks Exp(p, eps_p e_u), Exp(p, eps_p e_v).  The
-// perturbations are applied to the fixed-point angle and the compensated
-// length, so the perturbed walks share the base walk's rounding.
+// Stage 1: the walks that start at p.  Slot 0 recomputes Exp(p, v) (unless
+// the base geodesic's end is the forward's); for the geodesic finite
+// differences (eqs. jv, jp) the next slot is Exp(p, v + eps_v e_perp), and the
+// short walks Exp(p, eps_p e_u), Exp(p, eps_p e_v) go to sh[3 i], sh[3 i + 1]
+// (query order), which a one-lane-per-walk kernel finishes: they rarely leave
+// their face, and in the persistent pass each took a refill slot beside the
+// long walks.  The perturbations are applied to the fixed-point angle and the
+// compensated length, so the perturbed walks share the base walk's rounding.
 // Position of query i in the backward's walk arrays (spatial order when sorted).
 SG_HD __forceinline__ int64_t bwd_at(const BwdArgs& a, int64_t i) { return a.slot ? (int64_t)a.slot[i] : i; }
 
-SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_ray, int64_t i) {
+SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_ray, StateRec* sh, int64_t i) {
     StateRec* out = s1 + (int64_t)per_ray * bwd_at(a, i);
     StartFrame S;
     uint32_t phi0;
@@ -2187,12 +2190,13 @@ SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_
     float Llo = 0.f;
     if (bwd_query(M, a, i, S, phi0, L, &Llo) != kInitOk) {
         for (int j = 0; j < per_ray; ++j) out[j] = dead_state();
+        if (sh) sh[3 * i] = sh[3 * i + 1] = dead_state();
         return;
     }
-    if (per_ray != 3) {   // the base geodesic (three states: its end is the forward's, saved)
+    if (!sh || !a.gfd_saved) {   // the base geodesic (with GFD, unless its end is the forward's, saved)
         out[0] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, Llo, st) == kInitOk ? pack_state(st)
                                                                                           : dead_state();
-        if (per_ray == 1) return;
+        if (!sh) return;
         ++out;
     }
     const float ev = a.eps_v, ep = a.eps_p;
@@ -2202,9 +2206,11 @@ SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_
     const uint32_t dphi = rad_to_fx(atan2f(ev, L));
     out[0] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0 + dphi, L, Llo + dl, st) == kInitOk ? pack_state(st)
                                                                                                        : dead_state();
-    out[1] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, 0u, ep, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+    sh[3 * i] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, 0u, ep, 0.f, st) == kInitOk ? pack_state(st)
+                                                                                          : dead_state();
     const uint32_t Av = rec_geo(M, 3 * S.f).A;   // angle of e_v = unit(x2 - x0) in the chart
-    out[2] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, Av, ep, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+    sh[3 * i + 1] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, Av, ep, 0.f, st) == kInitOk ? pack_state(st)
+                                                                                              : dead_state();
 }
 
 // The end of the base geodesic from the forward's saved outputs: the chart of
@@ -2241,28 +2247,29 @@ SG_HD __forceinline__ Final saved_final(const DevMesh& M, const BwdArgs& a, int6
 // walk Exp(p', Pi(eps_v e_par)) along the transported tangent; slots 1 and 2
 // are Exp(p_u, v_u), Exp(p_v, v_v) with v transported along the short walks
 // (it keeps its angle to their tangent).
-SG_HD void bwd_stage2(const DevMesh& M, const BwdArgs& a, const StateRec* s1, StateRec* s2, int64_t i) {
+// Stage 2: the e_par step from p' (to sh[3 i + 2], short) and the two long
+// walks from the shifted start points (to s2, two per query).
+SG_HD void bwd_stage2(const DevMesh& M, const BwdArgs& a, const StateRec* s1, StateRec* s2, StateRec* sh, int64_t i) {
     const int64_t at = bwd_at(a, i);
-    StateRec* out = s2 + 3 * at;
+    StateRec* out = s2 + 2 * at;
     StartFrame S;
     uint32_t phi0;
     float L;
     Ray st;
-    const int per = a.gfd_saved ? 3 : 4;   // pass-1 states per query (the base's first unless saved)
-    const StateRec* q1 = s1 + (int64_t)per * at + (a.gfd_saved ? 0 : 1);
-    const Final F0 = a.gfd_saved ? saved_final(M, a, i) : as_final(s1[4 * at]);
-    const Final Fu = as_final(q1[1]), Fv = as_final(q1[2]);
+    const Final F0 = a.gfd_saved ? saved_final(M, a, i) : as_final(s1[2 * at]);   // (pass 1: base, e_perp)
+    const Final Fu = as_final(sh[3 * i]), Fv = as_final(sh[3 * i + 1]);
     if (bwd_query(M, a, i, S, phi0, L) != kInitOk || F0.h < 0 || Fu.h < 0 || Fv.h < 0) {
-        out[0] = out[1] = out[2] = dead_state();
+        sh[3 * i + 2] = out[0] = out[1] = dead_state();
         return;
     }
-    out[0] = enter_chart(M, F0.h, F0.ex, F0.ey, F0.phi, a.eps_v, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+    sh[3 * i + 2] = enter_chart(M, F0.h, F0.ex, F0.ey, F0.phi, a.eps_v, 0.f, st) == kInitOk ? pack_state(st)
+                                                                                          : dead_state();
     const uint32_t psi_u = phi0;                              // v relative to e_u
     const uint32_t psi_v = phi0 - rec_geo(M, 3 * S.f).A;       // v relative to e_v
     const uint32_t du = (Fu.flags & kParity) ? Fu.phi - psi_u : Fu.phi + psi_u;
     const uint32_t dv = (Fv.flags & kParity) ? Fv.phi - psi_v : Fv.phi + psi_v;
-    out[1] = enter_chart(M, Fu.h, Fu.ex, Fu.ey, du, L, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
-    out[2] = enter_chart(M, Fv.h, Fv.ex, Fv.ey, dv, L, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+    out[0] = enter_chart(M, Fu.h, Fu.ex, Fu.ey, du, L, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
+    out[1] = enter_chart(M, Fv.h, Fv.ex, Fv.ey, dv, L, 0.f, st) == kInitOk ? pack_state(st) : dead_state();
 }
 
 // Projection of an ambient vector onto the non-orthogonal frame [e_u, e_v]
@@ -2283,15 +2290,16 @@ SG_HD __forceinline__ void face_uv(const DevMesh& M, int32_t f, float3& x0, floa
 
 // Assembly (eqs. jv, jp, chain): finite-difference columns, projected on the
 // end face's [e_u', e_v'] frame, contracted with the upstream gradient g.
-SG_HD void gfd_assemble(const DevMesh& M, const BwdArgs& a, const StateRec* s1, const StateRec* s2, int64_t i) {
+SG_HD void gfd_assemble(const DevMesh& M, const BwdArgs& a, const StateRec* s1, const StateRec* s2, const StateRec* sh,
+                        int64_t i) {
     StartFrame S;
     uint32_t phi0;
     float L;
     const int64_t at = bwd_at(a, i);
-    const int per = a.gfd_saved ? 3 : 4;   // pass-1 states per query (the base's first unless saved)
-    const Final F0 = a.gfd_saved ? saved_final(M, a, i) : as_final(s1[4 * at]);
+    const int per = a.gfd_saved ? 1 : 2;   // pass-1 states per query (the base's first unless saved)
+    const Final F0 = a.gfd_saved ? saved_final(M, a, i) : as_final(s1[2 * at]);
     const Final Fp = as_final(s1[(int64_t)per * at + (a.gfd_saved ? 0 : 1)]);
-    const Final Fq = as_final(s2[3 * at]), Fu = as_final(s2[3 * at + 1]), Fv = as_final(s2[3 * at + 2]);
+    const Final Fq = as_final(sh[3 * i + 2]), Fu = as_final(s2[2 * at]), Fv = as_final(s2[2 * at + 1]);
     if (bwd_query(M, a, i, S, phi0, L) != kInitOk || F0.h < 0 || Fp.h < 0 || Fq.h < 0 || Fu.h < 0 || Fv.h < 0) {
         nan_grads(a, i);
         return;
@@ -2640,14 +2648,25 @@ SG_HD void walk_state(const DevMesh& M, StateRec& r, int32_t max_steps, float sn
     r = *reinterpret_cast<const StateRec*>(&fin);
 }
 
+// The short finite-difference walks, one lane each (sh[3 i + first] onward,
+// count per query): most end in their first face.
+template <bool kFlip, bool kHole>
+__global__ __launch_bounds__(256) void k_walk_short(DevMesh M, StateRec* sh, int64_t n, int first, int count,
+                                                    int32_t max_steps, float snap) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int j = 0; j < count; ++j) walk_state<kFlip, kHole>(M, sh[3 * i + first + j], max_steps, snap);
+}
+
 #define SG_ROW_KERNEL(name, body, ...)                                                   \
     __global__ __launch_bounds__(256) void name(DevMesh M, BwdArgs a, ##__VA_ARGS__) {   \
         const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;                \
         if (i < a.n) body;                                                               \
     }
-SG_ROW_KERNEL(k_bwd_stage1, bwd_stage1(M, a, s1, per_ray, i), StateRec* s1, int per_ray)
-SG_ROW_KERNEL(k_bwd_stage2, bwd_stage2(M, a, s1, s2, i), const StateRec* s1, StateRec* s2)
-SG_ROW_KERNEL(k_gfd_assemble, gfd_assemble(M, a, s1, s2, i), const StateRec* s1, const StateRec* s2)
+SG_ROW_KERNEL(k_bwd_stage1, bwd_stage1(M, a, s1, per_ray, sh, i), StateRec* s1, int per_ray, StateRec* sh)
+SG_ROW_KERNEL(k_bwd_stage2, bwd_stage2(M, a, s1, s2, sh, i), const StateRec* s1, StateRec* s2, StateRec* sh)
+SG_ROW_KERNEL(k_gfd_assemble, gfd_assemble(M, a, s1, s2, sh, i), const StateRec* s1, const StateRec* s2,
+              const StateRec* sh)
 SG_ROW_KERNEL(k_ep_saved, ep_saved(M, a, i))
 SG_ROW_KERNEL(k_ep_walked, ep_walked(M, a, s1, stride, i), const StateRec* s1, int stride)
 SG_ROW_KERNEL(k_gradx_init, gradx_init(M, a, s1, stride, s3, cvec, sterm, srank, fcnt, i), const StateRec* s1,
@@ -2876,8 +2895,8 @@ hipError_t launch_exp_partitioned(const DevMesh& M, const ExpArgs& a, void* ws, 
 // totals scanned into starts, chunks used per walk block, the (walk block,
 // bin) count matrix).
 struct BwdLayout {
-    size_t s1, s2, s3, cvec, acc, gxv, sterm, srank, fstart, ftile, qlist, slot, cnt, counter, rec, sorted, fill, bins,
-        total;
+    size_t s1, s2, sh, s3, cvec, acc, gxv, sterm, srank, fstart, ftile, qlist, slot, cnt, counter, rec, sorted, fill,
+        bins, total;
     int per_block;   // record chunks per walk block (0: no records)
     int shift, nbins;
 };
@@ -2905,7 +2924,7 @@ static BwdPlan bwd_plan(int32_t mode, bool has_flip, bool hole, bool vjp, bool g
     P.gfd_saved = P.gfd && plain && have_f && have_b && have_v && (!gradx || end_ok);
     P.gx_saved = gradx && end_ok && (!P.gfd || P.gfd_saved);
     P.base_walk = P.gfd || (vjp && has_flip) || (gradx && !P.gx_saved);   // pass 1 walks
-    P.per1 = P.gfd ? (P.gfd_saved ? 3 : 4) : 1;
+    P.per1 = P.gfd ? (P.gfd_saved ? 1 : 2) : 1;
     return P;
 }
 
@@ -2916,7 +2935,8 @@ static BwdLayout bwd_layout(int64_t n, const BwdPlan& P, bool gradx, int64_t n_f
     BwdLayout L{};
     size_t o = 0;
     L.s1 = o; o = align256(o + (base_walk ? per1 * (size_t)n * sizeof(StateRec) : 0));
-    L.s2 = o; o = align256(o + (gfd ? 3 * (size_t)n * sizeof(StateRec) : 0));
+    L.s2 = o; o = align256(o + (gfd ? 2 * (size_t)n * sizeof(StateRec) : 0));
+    L.sh = o; o = align256(o + (gfd ? 3 * (size_t)n * sizeof(StateRec) : 0));
     L.s3 = o; o = align256(o + (gradx ? (size_t)n * sizeof(StateRec) : 0));
     L.cvec = o; o = align256(o + (gradx ? (size_t)n * sizeof(float4) : 0));
     L.acc = o; o = align256(o + (gradx ? 15 * (size_t)n_faces * sizeof(double) : 0));
@@ -2977,6 +2997,7 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
     char* base = reinterpret_cast<char*>(ws);
     auto* s1 = reinterpret_cast<StateRec*>(base + L.s1);
     auto* s2 = reinterpret_cast<StateRec*>(base + L.s2);
+    auto* sh = gfd ? reinterpret_cast<StateRec*>(base + L.sh) : nullptr;
     auto* s3 = reinterpret_cast<StateRec*>(base + L.s3);
     auto* cvec = reinterpret_cast<float4*>(base + L.cvec);
     auto* acc = reinterpret_cast<double*>(base + L.acc);
@@ -2991,10 +3012,19 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
                            (const uint32_t*)cnt, slot, ord);
         a.slot = slot;
     }
-    // base walk (and, for GFD, the three perturbed walks that start at p)
+    // the short walks, one lane each, in the variant the persistent walks use
+    auto walk_short = [&](int first, int count) {
+        const dim3 g((unsigned)grid), b(block);
+        if (flip && M.hole_avoid) k_walk_short<true, true><<<g, b, 0, s>>>(M, sh, a.n, first, count, a.max_steps, a.snap);
+        else if (flip) k_walk_short<true, false><<<g, b, 0, s>>>(M, sh, a.n, first, count, a.max_steps, a.snap);
+        else if (M.hole_avoid) k_walk_short<false, true><<<g, b, 0, s>>>(M, sh, a.n, first, count, a.max_steps, a.snap);
+        else k_walk_short<false, false><<<g, b, 0, s>>>(M, sh, a.n, first, count, a.max_steps, a.snap);
+    };
+    // base walk (and, for GFD, the e_perp walk; the two short start-point steps walk on their own)
     const int stride = kLenClasses * ord.sub;
     if (base_walk) {
-        hipLaunchKernelGGL(k_bwd_stage1, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
+        hipLaunchKernelGGL(k_bwd_stage1, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1, sh);
+        if (gfd) walk_short(0, 2);
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
         SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)w.blocks), dim3(block), s, M, s1,
                     QueueRanges{cnt, stride, per1}, counter, a.max_steps, a.snap, w.refill_min, w.queues);
@@ -3002,11 +3032,12 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
     if (vjp && a.mode == 0 && flip)   // (consistent orientation: k_ep_saved above)
         hipLaunchKernelGGL(k_ep_walked, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
     if (gfd) {
-        hipLaunchKernelGGL(k_bwd_stage2, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
+        hipLaunchKernelGGL(k_bwd_stage2, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2, sh);
+        walk_short(2, 1);
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
         SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)w.blocks), dim3(block), s, M, s2,
-                    QueueRanges{cnt, stride, 3}, counter, a.max_steps, a.snap, w.refill_min, w.queues);
-        hipLaunchKernelGGL(k_gfd_assemble, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2);
+                    QueueRanges{cnt, stride, 2}, counter, a.max_steps, a.snap, w.refill_min, w.queues);
+        hipLaunchKernelGGL(k_gfd_assemble, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2, (const StateRec*)sh);
     }
     if (gradx) {
         const int64_t nacc = 15 * M.n_faces;
