@@ -2181,8 +2181,12 @@ SG_HD __forceinline__ void transport_cot(const BwdArgs& a, int64_t i, bool ident
 // Position of query i in the backward's walk arrays (spatial order when sorted).
 SG_HD __forceinline__ int64_t bwd_at(const BwdArgs& a, int64_t i) { return a.slot ? (int64_t)a.slot[i] : i; }
 
-SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_ray, StateRec* sh, int64_t i) {
-    StateRec* out = s1 + (int64_t)per_ray * bwd_at(a, i);
+SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_ray, StateRec* sh, StateRec* s2,
+                      int64_t i) {
+    const int64_t at = bwd_at(a, i);
+    StateRec* out = s1 + (int64_t)per_ray * at;
+    // with the base's end saved, GFD's e_perp walk goes to pass 2 (its first of three states)
+    StateRec* perp = sh && a.gfd_saved ? s2 + 3 * at : out + 1;
     StartFrame S;
     uint32_t phi0;
     float L;
@@ -2190,22 +2194,21 @@ SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_
     float Llo = 0.f;
     if (bwd_query(M, a, i, S, phi0, L, &Llo) != kInitOk) {
         for (int j = 0; j < per_ray; ++j) out[j] = dead_state();
-        if (sh) sh[3 * i] = sh[3 * i + 1] = dead_state();
+        if (sh) sh[3 * i] = sh[3 * i + 1] = *perp = dead_state();
         return;
     }
     if (!sh || !a.gfd_saved) {   // the base geodesic (with GFD, unless its end is the forward's, saved)
         out[0] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, Llo, st) == kInitOk ? pack_state(st)
                                                                                           : dead_state();
         if (!sh) return;
-        ++out;
     }
     const float ev = a.eps_v, ep = a.eps_p;
     // |v + eps e_perp| = L + eps^2 / (L + sqrt(L^2 + eps^2)), angle + atan(eps / L)
     const float Lp = sqrtf(fmaf(L, L, ev * ev));
     const float dl = ev * ev / (L + Lp);
     const uint32_t dphi = rad_to_fx(atan2f(ev, L));
-    out[0] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0 + dphi, L, Llo + dl, st) == kInitOk ? pack_state(st)
-                                                                                                       : dead_state();
+    *perp = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0 + dphi, L, Llo + dl, st) == kInitOk ? pack_state(st)
+                                                                                                     : dead_state();
     sh[3 * i] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, 0u, ep, 0.f, st) == kInitOk ? pack_state(st)
                                                                                           : dead_state();
     const uint32_t Av = rec_geo(M, 3 * S.f).A;   // angle of e_v = unit(x2 - x0) in the chart
@@ -2251,7 +2254,7 @@ SG_HD __forceinline__ Final saved_final(const DevMesh& M, const BwdArgs& a, int6
 // walks from the shifted start points (to s2, two per query).
 SG_HD void bwd_stage2(const DevMesh& M, const BwdArgs& a, const StateRec* s1, StateRec* s2, StateRec* sh, int64_t i) {
     const int64_t at = bwd_at(a, i);
-    StateRec* out = s2 + 2 * at;
+    StateRec* out = a.gfd_saved ? s2 + 3 * at + 1 : s2 + 2 * at;   // (saved: after the e_perp walk)
     StartFrame S;
     uint32_t phi0;
     float L;
@@ -2296,10 +2299,12 @@ SG_HD void gfd_assemble(const DevMesh& M, const BwdArgs& a, const StateRec* s1, 
     uint32_t phi0;
     float L;
     const int64_t at = bwd_at(a, i);
-    const int per = a.gfd_saved ? 1 : 2;   // pass-1 states per query (the base's first unless saved)
+    // pass 1: (base, e_perp), pass 2: the two shifted walks; with the base's end
+    // saved, pass 2 holds (e_perp, the two shifted walks)
     const Final F0 = a.gfd_saved ? saved_final(M, a, i) : as_final(s1[2 * at]);
-    const Final Fp = as_final(s1[(int64_t)per * at + (a.gfd_saved ? 0 : 1)]);
-    const Final Fq = as_final(sh[3 * i + 2]), Fu = as_final(s2[2 * at]), Fv = as_final(s2[2 * at + 1]);
+    const StateRec* q2 = a.gfd_saved ? s2 + 3 * at + 1 : s2 + 2 * at;
+    const Final Fp = as_final(a.gfd_saved ? s2[3 * at] : s1[2 * at + 1]);
+    const Final Fq = as_final(sh[3 * i + 2]), Fu = as_final(q2[0]), Fv = as_final(q2[1]);
     if (bwd_query(M, a, i, S, phi0, L) != kInitOk || F0.h < 0 || Fp.h < 0 || Fq.h < 0 || Fu.h < 0 || Fv.h < 0) {
         nan_grads(a, i);
         return;
@@ -2663,7 +2668,8 @@ __global__ __launch_bounds__(256) void k_walk_short(DevMesh M, StateRec* sh, int
         const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;                \
         if (i < a.n) body;                                                               \
     }
-SG_ROW_KERNEL(k_bwd_stage1, bwd_stage1(M, a, s1, per_ray, sh, i), StateRec* s1, int per_ray, StateRec* sh)
+SG_ROW_KERNEL(k_bwd_stage1, bwd_stage1(M, a, s1, per_ray, sh, s2, i), StateRec* s1, int per_ray, StateRec* sh,
+              StateRec* s2)
 SG_ROW_KERNEL(k_bwd_stage2, bwd_stage2(M, a, s1, s2, sh, i), const StateRec* s1, StateRec* s2, StateRec* sh)
 SG_ROW_KERNEL(k_gfd_assemble, gfd_assemble(M, a, s1, s2, sh, i), const StateRec* s1, const StateRec* s2,
               const StateRec* sh)
@@ -2911,7 +2917,8 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // end frame from f', v' and the status.
 struct BwdPlan {
     bool gfd, walk, gfd_saved, gx_saved, base_walk;
-    int per1;   // pass-1 states per query
+    int per1;   // pass-1 states per query (0: no pass 1)
+    int per2;   // GFD: pass-2 states per query
 };
 
 static BwdPlan bwd_plan(int32_t mode, bool has_flip, bool hole, bool vjp, bool gradx, bool have_f, bool have_b,
@@ -2923,8 +2930,11 @@ static BwdPlan bwd_plan(int32_t mode, bool has_flip, bool hole, bool vjp, bool g
     const bool end_ok = plain && have_f && have_v && have_status;   // end frame and status of every ray
     P.gfd_saved = P.gfd && plain && have_f && have_b && have_v && (!gradx || end_ok);
     P.gx_saved = gradx && end_ok && (!P.gfd || P.gfd_saved);
-    P.base_walk = P.gfd || (vjp && has_flip) || (gradx && !P.gx_saved);   // pass 1 walks
-    P.per1 = P.gfd ? (P.gfd_saved ? 1 : 2) : 1;
+    // pass 1 walks the base geodesic (and GFD's e_perp walk beside it); with the
+    // base's end saved, GFD's three long walks all go to pass 2
+    P.base_walk = (P.gfd && !P.gfd_saved) || (vjp && has_flip) || (gradx && !P.gx_saved);
+    P.per1 = !P.base_walk ? 0 : (P.gfd ? 2 : 1);
+    P.per2 = P.gfd_saved ? 3 : 2;
     return P;
 }
 
@@ -2935,7 +2945,7 @@ static BwdLayout bwd_layout(int64_t n, const BwdPlan& P, bool gradx, int64_t n_f
     BwdLayout L{};
     size_t o = 0;
     L.s1 = o; o = align256(o + (base_walk ? per1 * (size_t)n * sizeof(StateRec) : 0));
-    L.s2 = o; o = align256(o + (gfd ? 2 * (size_t)n * sizeof(StateRec) : 0));
+    L.s2 = o; o = align256(o + (gfd ? (size_t)P.per2 * n * sizeof(StateRec) : 0));
     L.sh = o; o = align256(o + (gfd ? 3 * (size_t)n * sizeof(StateRec) : 0));
     L.s3 = o; o = align256(o + (gradx ? (size_t)n * sizeof(StateRec) : 0));
     L.cvec = o; o = align256(o + (gradx ? (size_t)n * sizeof(float4) : 0));
@@ -3020,11 +3030,13 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
         else if (M.hole_avoid) k_walk_short<false, true><<<g, b, 0, s>>>(M, sh, a.n, first, count, a.max_steps, a.snap);
         else k_walk_short<false, false><<<g, b, 0, s>>>(M, sh, a.n, first, count, a.max_steps, a.snap);
     };
-    // base walk (and, for GFD, the e_perp walk; the two short start-point steps walk on their own)
+    // pass 1: the base walk (and, for GFD, the e_perp walk); the two short
+    // start-point steps walk on their own
     const int stride = kLenClasses * ord.sub;
+    if (base_walk || gfd)
+        hipLaunchKernelGGL(k_bwd_stage1, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1, sh, s2);
+    if (gfd) walk_short(0, 2);
     if (base_walk) {
-        hipLaunchKernelGGL(k_bwd_stage1, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1, sh);
-        if (gfd) walk_short(0, 2);
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
         SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)w.blocks), dim3(block), s, M, s1,
                     QueueRanges{cnt, stride, per1}, counter, a.max_steps, a.snap, w.refill_min, w.queues);
@@ -3036,7 +3048,7 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
         walk_short(2, 1);
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
         SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)w.blocks), dim3(block), s, M, s2,
-                    QueueRanges{cnt, stride, 2}, counter, a.max_steps, a.snap, w.refill_min, w.queues);
+                    QueueRanges{cnt, stride, P.per2}, counter, a.max_steps, a.snap, w.refill_min, w.queues);
         hipLaunchKernelGGL(k_gfd_assemble, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2, (const StateRec*)sh);
     }
     if (gradx) {
