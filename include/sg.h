@@ -228,7 +228,8 @@ int sg_exp_transport_noalloc(sg_mesh mesh, int64_t n, const int32_t* f, const fl
  *        short ones (length eps) one lane each.  With f_out, b_out and v_out
  *        given, on meshes whose faces agree in orientation, the base
  *        geodesic's end is taken from them (Appendix "Speed-up GFD and EP
- *        through batching": Exp(p, v) is the forward's) and six are walked.
+ *        through batching": Exp(p, v) is the forward's) and six are walked,
+ *        the three long ones in a single persistent pass.
  *        |v_t| = 0 takes e_par = e_u (the start face's x1 - x0 direction).
  *   grad_X (an extension; the paper has no vertex gradient): the exact
  *        derivative of p' = H_m o ... o H_1(p + v_t), the composition of the
