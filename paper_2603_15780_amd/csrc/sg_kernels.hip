@@ -2172,12 +2172,14 @@ SG_HD __forceinline__ void transport_cot(const BwdArgs& a, int64_t i, bool ident
 
 // Stage 1: the walks that start at p.  Slot 0 recomputes Exp(p, v) (unless
 // the base geodesic's end is the forward's); for the geodesic finite
-// differences (eqs. jv, jp) the next slot is Exp(p, v + eps_v e_perp), and the
-// short walks Exp(p, eps_p e_u), Exp(p, eps_p e_v) go to sh[3 i], sh[3 i + 1]
-// (query order), which a one-lane-per-walk kernel finishes: they rarely leave
-// their face, and in the persistent pass each took a refill slot beside the
-// long walks.  The perturbations are applied to the fixed-point angle and the
-// compensated length, so the perturbed walks share the base walk's rounding.
+// differences (eqs. jv, jp) the next slot is Exp(p, v + eps_v e_perp) (with
+// the base's end saved, the first of pass 2's three slots instead, since it
+// needs nothing from pass 1), and the short walks Exp(p, eps_p e_u),
+// Exp(p, eps_p e_v) go to sh[3 i], sh[3 i + 1] (query order), which a
+// one-lane-per-walk kernel finishes: they rarely leave their face, and in the
+// persistent pass each took a refill slot beside the long walks.  The
+// perturbations are applied to the fixed-point angle and the compensated
+// length, so the perturbed walks share the base walk's rounding.
 // Position of query i in the backward's walk arrays (spatial order when sorted).
 SG_HD __forceinline__ int64_t bwd_at(const BwdArgs& a, int64_t i) { return a.slot ? (int64_t)a.slot[i] : i; }
 
@@ -2246,12 +2248,11 @@ SG_HD __forceinline__ Final saved_final(const DevMesh& M, const BwdArgs& a, int6
     return F;
 }
 
-// Stage 2: the walks that start where stage 1 ended.  Slot 0 is the short
-// walk Exp(p', Pi(eps_v e_par)) along the transported tangent; slots 1 and 2
-// are Exp(p_u, v_u), Exp(p_v, v_v) with v transported along the short walks
-// (it keeps its angle to their tangent).
-// Stage 2: the e_par step from p' (to sh[3 i + 2], short) and the two long
-// walks from the shifted start points (to s2, two per query).
+// Stage 2: the walks that start where stage 1 ended: the short walk
+// Exp(p', Pi(eps_v e_par)) along the transported tangent (to sh[3 i + 2]) and
+// the long Exp(p_u, v_u), Exp(p_v, v_v) with v transported along the short
+// walks (it keeps its angle to their tangent), to s2: two per query, or
+// slots 1 and 2 of three when slot 0 holds the e_perp walk.
 SG_HD void bwd_stage2(const DevMesh& M, const BwdArgs& a, const StateRec* s1, StateRec* s2, StateRec* sh, int64_t i) {
     const int64_t at = bwd_at(a, i);
     StateRec* out = a.gfd_saved ? s2 + 3 * at + 1 : s2 + 2 * at;   // (saved: after the e_perp walk)
