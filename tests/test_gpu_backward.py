@@ -307,6 +307,50 @@ def test_gradx_from_saved_outputs(torch, mixed):
             assert np.linalg.norm(res[name] - res["walked"]) <= 1e-6 * np.linalg.norm(res["walked"])
 
 
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_gfd_gradx_from_saved_outputs(torch, mixed):
+    """GFD and the vertex gradient in one call, given all of the forward's
+    saved outputs (f', b', v', status).  On consistently oriented faces
+    neither walks the base geodesic: GFD's three long walks share one pass and
+    the adjoint walk starts from the saved end frame.  On a mesh whose faces
+    disagree in orientation both re-walk it.  Either way the GFD gradients
+    equal those of the same call without grad_X bit for bit, and grad_X
+    equals EP + grad_X's from the same outputs up to the float64 summation
+    order and the oracle's within 1e-4."""
+    from paper_2603_15780_amd import sg
+    from parity import gradx_report
+    X, F = CF.mesh_config(1)
+    if mixed:
+        F = F.copy()
+        flip = np.random.default_rng(5).random(F.shape[0]) < 0.3
+        F[flip] = F[flip][:, ::-1]
+    r = CF.rays_config(1, X, F)
+    g = CF.upstream_grad(1, r["f"].shape[0])
+    om = oracle.Mesh(X, F)
+    keep = margin_mask(om, r)
+    g[~keep] = 0.0
+    ref, _ = om.gradx(r["f"], r["b"], r["v"], g)
+    gm = sg.Mesh(X, F)
+    t = dev_inputs(torch, r, g)
+    out = gm.exp(t["f"], t["b"], t["v"])
+    eps = float(np.float32(5e-3 * om.mean_edge))
+    kw = dict(f_out=out["f"], b_out=out["b"], v_out=out["v"], status=out["status"])
+    args = (t["f"], t["b"], t["v"], t["g"])
+    gv0, gb0 = gm.backward(sg.BWD_GFD, *args, eps_v=eps, eps_p=eps, **kw)
+    gX = torch.zeros(gm.n_verts, 3, dtype=torch.float64, device=t["f"].device)
+    gv1, gb1 = gm.backward(sg.BWD_GFD, *args, grad_X=gX, want_vjp=True, eps_v=eps, eps_p=eps, **kw)
+    gXe = torch.zeros_like(gX)
+    gm.backward(sg.BWD_EP, *args, grad_X=gXe, want_vjp=True, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(gv0, gv1) and torch.equal(gb0, gb1)
+    assert np.isfinite(gv1.cpu().numpy()[keep]).all()
+    got, got_ep = gX.cpu().numpy(), gXe.cpu().numpy()
+    s = gradx_report(ref, got)
+    print(s)
+    assert s["finite"] and s["global_rel"] < 1e-4 and s["frac_ok"] >= 0.999, s
+    assert np.allclose(got, got_ep, rtol=1e-9, atol=1e-9 * np.abs(got_ep).max())
+
 def test_gradx_config2_full_batch(torch):
     """All 1,048,576 rays on the 327,680-face mesh.  (1) Upstream g on every
     margin ray: translating the mesh translates each p', so the vertex
