@@ -224,12 +224,11 @@ int sg_exp_transport_noalloc(sg_mesh mesh, int64_t n, const int32_t* f, const fl
  *        step sizes opts->eps_v, opts->eps_p.  Walks seven geodesics per
  *        query (the base, the e_perp-perturbed one, two short start-point
  *        steps, then the e_par step from p' and the two start-point-shifted
- *        geodesics): the long ones in two persistent passes, the three
+ *        geodesics): the four long ones in one persistent pass, the three
  *        short ones (length eps) one lane each.  With f_out, b_out and v_out
  *        given, on meshes whose faces agree in orientation, the base
  *        geodesic's end is taken from them (Appendix "Speed-up GFD and EP
- *        through batching": Exp(p, v) is the forward's) and six are walked,
- *        the three long ones in a single persistent pass.
+ *        through batching": Exp(p, v) is the forward's) and six are walked.
  *        |v_t| = 0 takes e_par = e_u (the start face's x1 - x0 direction).
  *   grad_X (an extension; the paper has no vertex gradient): the exact
  *        derivative of p' = H_m o ... o H_1(p + v_t), the composition of the

@@ -2172,23 +2172,17 @@ SG_HD __forceinline__ void transport_cot(const BwdArgs& a, int64_t i, bool ident
 
 // Stage 1: the walks that start at p.  Slot 0 recomputes Exp(p, v) (unless
 // the base geodesic's end is the forward's); for the geodesic finite
-// differences (eqs. jv, jp) the next slot is Exp(p, v + eps_v e_perp) (with
-// the base's end saved, the first of pass 2's three slots instead, since it
-// needs nothing from pass 1), and the short walks Exp(p, eps_p e_u),
-// Exp(p, eps_p e_v) go to sh[3 i], sh[3 i + 1] (query order), which a
-// one-lane-per-walk kernel finishes: they rarely leave their face, and in the
-// persistent pass each took a refill slot beside the long walks.  The
-// perturbations are applied to the fixed-point angle and the compensated
-// length, so the perturbed walks share the base walk's rounding.
+// differences (eqs. jv, jp) the next slot is Exp(p, v + eps_v e_perp), and the
+// short walks Exp(p, eps_p e_u), Exp(p, eps_p e_v) go to sh[3 i], sh[3 i + 1]
+// (query order), which a one-lane-per-walk kernel finishes: they rarely leave
+// their face, and in the persistent pass each took a refill slot beside the
+// long walks.  The perturbations are applied to the fixed-point angle and the
+// compensated length, so the perturbed walks share the base walk's rounding.
 // Position of query i in the backward's walk arrays (spatial order when sorted).
 SG_HD __forceinline__ int64_t bwd_at(const BwdArgs& a, int64_t i) { return a.slot ? (int64_t)a.slot[i] : i; }
 
-SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_ray, StateRec* sh, StateRec* s2,
-                      int64_t i) {
-    const int64_t at = bwd_at(a, i);
-    StateRec* out = s1 + (int64_t)per_ray * at;
-    // with the base's end saved, GFD's e_perp walk goes to pass 2 (its first of three states)
-    StateRec* perp = sh && a.gfd_saved ? s2 + 3 * at : out + 1;
+SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_ray, StateRec* sh, int64_t i) {
+    StateRec* out = s1 + (int64_t)per_ray * bwd_at(a, i);
     StartFrame S;
     uint32_t phi0;
     float L;
@@ -2196,21 +2190,22 @@ SG_HD void bwd_stage1(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_
     float Llo = 0.f;
     if (bwd_query(M, a, i, S, phi0, L, &Llo) != kInitOk) {
         for (int j = 0; j < per_ray; ++j) out[j] = dead_state();
-        if (sh) sh[3 * i] = sh[3 * i + 1] = *perp = dead_state();
+        if (sh) sh[3 * i] = sh[3 * i + 1] = dead_state();
         return;
     }
     if (!sh || !a.gfd_saved) {   // the base geodesic (with GFD, unless its end is the forward's, saved)
         out[0] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0, L, Llo, st) == kInitOk ? pack_state(st)
                                                                                           : dead_state();
         if (!sh) return;
+        ++out;
     }
     const float ev = a.eps_v, ep = a.eps_p;
     // |v + eps e_perp| = L + eps^2 / (L + sqrt(L^2 + eps^2)), angle + atan(eps / L)
     const float Lp = sqrtf(fmaf(L, L, ev * ev));
     const float dl = ev * ev / (L + Lp);
     const uint32_t dphi = rad_to_fx(atan2f(ev, L));
-    *perp = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0 + dphi, L, Llo + dl, st) == kInitOk ? pack_state(st)
-                                                                                                     : dead_state();
+    out[0] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, phi0 + dphi, L, Llo + dl, st) == kInitOk ? pack_state(st)
+                                                                                                       : dead_state();
     sh[3 * i] = enter_face(M, S.f, 0, S.l0, S.b0, S.b1, S.b2, 0u, ep, 0.f, st) == kInitOk ? pack_state(st)
                                                                                           : dead_state();
     const uint32_t Av = rec_geo(M, 3 * S.f).A;   // angle of e_v = unit(x2 - x0) in the chart
@@ -2248,26 +2243,36 @@ SG_HD __forceinline__ Final saved_final(const DevMesh& M, const BwdArgs& a, int6
     return F;
 }
 
-// Stage 2: the walks that start where stage 1 ended: the short walk
-// Exp(p', Pi(eps_v e_par)) along the transported tangent (to sh[3 i + 2]) and
-// the long Exp(p_u, v_u), Exp(p_v, v_v) with v transported along the short
-// walks (it keeps its angle to their tangent), to s2: two per query, or
-// slots 1 and 2 of three when slot 0 holds the e_perp walk.
-SG_HD void bwd_stage2(const DevMesh& M, const BwdArgs& a, const StateRec* s1, StateRec* s2, StateRec* sh, int64_t i) {
+// Stage 2: the walks that start where stage 1's ended.  With do_shift, the
+// long Exp(p_u, v_u), Exp(p_v, v_v) from the ends of the two short start-point
+// walks, with v transported along them (it keeps its angle to their tangent),
+// to the last two of the query's per_ray long-walk slots; they need nothing
+// from the base geodesic, so they join its pass.  With do_par, the short walk
+// Exp(p', Pi(eps_v e_par)) along the transported tangent from the base's end
+// (the forward's, or slot 0 once walked), to sh[3 i + 2].
+SG_HD void bwd_stage2(const DevMesh& M, const BwdArgs& a, StateRec* s1, int per_ray, StateRec* sh, bool do_shift,
+                      bool do_par, int64_t i) {
     const int64_t at = bwd_at(a, i);
-    StateRec* out = a.gfd_saved ? s2 + 3 * at + 1 : s2 + 2 * at;   // (saved: after the e_perp walk)
+    StateRec* out = s1 + (int64_t)per_ray * at + (per_ray - 2);
     StartFrame S;
     uint32_t phi0;
     float L;
     Ray st;
-    const Final F0 = a.gfd_saved ? saved_final(M, a, i) : as_final(s1[2 * at]);   // (pass 1: base, e_perp)
-    const Final Fu = as_final(sh[3 * i]), Fv = as_final(sh[3 * i + 1]);
+    Final F0{}, Fu{}, Fv{};
+    if (do_par) F0 = a.gfd_saved ? saved_final(M, a, i) : as_final(s1[(int64_t)per_ray * at]);
+    if (do_shift) {
+        Fu = as_final(sh[3 * i]);
+        Fv = as_final(sh[3 * i + 1]);
+    }
     if (bwd_query(M, a, i, S, phi0, L) != kInitOk || F0.h < 0 || Fu.h < 0 || Fv.h < 0) {
-        sh[3 * i + 2] = out[0] = out[1] = dead_state();
+        if (do_par) sh[3 * i + 2] = dead_state();
+        if (do_shift) out[0] = out[1] = dead_state();
         return;
     }
-    sh[3 * i + 2] = enter_chart(M, F0.h, F0.ex, F0.ey, F0.phi, a.eps_v, 0.f, st) == kInitOk ? pack_state(st)
-                                                                                          : dead_state();
+    if (do_par)
+        sh[3 * i + 2] = enter_chart(M, F0.h, F0.ex, F0.ey, F0.phi, a.eps_v, 0.f, st) == kInitOk ? pack_state(st)
+                                                                                              : dead_state();
+    if (!do_shift) return;
     const uint32_t psi_u = phi0;                              // v relative to e_u
     const uint32_t psi_v = phi0 - rec_geo(M, 3 * S.f).A;       // v relative to e_v
     const uint32_t du = (Fu.flags & kParity) ? Fu.phi - psi_u : Fu.phi + psi_u;
@@ -2294,18 +2299,18 @@ SG_HD __forceinline__ void face_uv(const DevMesh& M, int32_t f, float3& x0, floa
 
 // Assembly (eqs. jv, jp, chain): finite-difference columns, projected on the
 // end face's [e_u', e_v'] frame, contracted with the upstream gradient g.
-SG_HD void gfd_assemble(const DevMesh& M, const BwdArgs& a, const StateRec* s1, const StateRec* s2, const StateRec* sh,
-                        int64_t i) {
+SG_HD void gfd_assemble(const DevMesh& M, const BwdArgs& a, const StateRec* s1, const StateRec* sh, int64_t i) {
     StartFrame S;
     uint32_t phi0;
     float L;
     const int64_t at = bwd_at(a, i);
-    // pass 1: (base, e_perp), pass 2: the two shifted walks; with the base's end
-    // saved, pass 2 holds (e_perp, the two shifted walks)
-    const Final F0 = a.gfd_saved ? saved_final(M, a, i) : as_final(s1[2 * at]);
-    const StateRec* q2 = a.gfd_saved ? s2 + 3 * at + 1 : s2 + 2 * at;
-    const Final Fp = as_final(a.gfd_saved ? s2[3 * at] : s1[2 * at + 1]);
-    const Final Fq = as_final(sh[3 * i + 2]), Fu = as_final(q2[0]), Fv = as_final(q2[1]);
+    // the long walks of a query: (base,) e_perp, the two shifted ones; the base's
+    // end is the forward's when saved
+    const int per = a.gfd_saved ? 3 : 4;
+    const StateRec* q = s1 + (int64_t)per * at + (per - 3);
+    const Final F0 = a.gfd_saved ? saved_final(M, a, i) : as_final(s1[(int64_t)per * at]);
+    const Final Fp = as_final(q[0]), Fu = as_final(q[1]), Fv = as_final(q[2]);
+    const Final Fq = as_final(sh[3 * i + 2]);
     if (bwd_query(M, a, i, S, phi0, L) != kInitOk || F0.h < 0 || Fp.h < 0 || Fq.h < 0 || Fu.h < 0 || Fv.h < 0) {
         nan_grads(a, i);
         return;
@@ -2669,11 +2674,10 @@ __global__ __launch_bounds__(256) void k_walk_short(DevMesh M, StateRec* sh, int
         const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;                \
         if (i < a.n) body;                                                               \
     }
-SG_ROW_KERNEL(k_bwd_stage1, bwd_stage1(M, a, s1, per_ray, sh, s2, i), StateRec* s1, int per_ray, StateRec* sh,
-              StateRec* s2)
-SG_ROW_KERNEL(k_bwd_stage2, bwd_stage2(M, a, s1, s2, sh, i), const StateRec* s1, StateRec* s2, StateRec* sh)
-SG_ROW_KERNEL(k_gfd_assemble, gfd_assemble(M, a, s1, s2, sh, i), const StateRec* s1, const StateRec* s2,
-              const StateRec* sh)
+SG_ROW_KERNEL(k_bwd_stage1, bwd_stage1(M, a, s1, per_ray, sh, i), StateRec* s1, int per_ray, StateRec* sh)
+SG_ROW_KERNEL(k_bwd_stage2, bwd_stage2(M, a, s1, per_ray, sh, do_shift, do_par, i), StateRec* s1, int per_ray,
+              StateRec* sh, bool do_shift, bool do_par)
+SG_ROW_KERNEL(k_gfd_assemble, gfd_assemble(M, a, s1, sh, i), const StateRec* s1, const StateRec* sh)
 SG_ROW_KERNEL(k_ep_saved, ep_saved(M, a, i))
 SG_ROW_KERNEL(k_ep_walked, ep_walked(M, a, s1, stride, i), const StateRec* s1, int stride)
 SG_ROW_KERNEL(k_gradx_init, gradx_init(M, a, s1, stride, s3, cvec, sterm, srank, fcnt, i), const StateRec* s1,
@@ -2902,7 +2906,7 @@ hipError_t launch_exp_partitioned(const DevMesh& M, const ExpArgs& a, void* ws, 
 // totals scanned into starts, chunks used per walk block, the (walk block,
 // bin) count matrix).
 struct BwdLayout {
-    size_t s1, s2, sh, s3, cvec, acc, gxv, sterm, srank, fstart, ftile, qlist, slot, cnt, counter, rec, sorted, fill,
+    size_t s1, sh, s3, cvec, acc, gxv, sterm, srank, fstart, ftile, qlist, slot, cnt, counter, rec, sorted, fill,
         bins, total;
     int per_block;   // record chunks per walk block (0: no records)
     int shift, nbins;
@@ -2918,8 +2922,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // end frame from f', v' and the status.
 struct BwdPlan {
     bool gfd, walk, gfd_saved, gx_saved, base_walk;
-    int per1;   // pass-1 states per query (0: no pass 1)
-    int per2;   // GFD: pass-2 states per query
+    int per1;   // long-walk states per query (0: no walk pass)
 };
 
 static BwdPlan bwd_plan(int32_t mode, bool has_flip, bool hole, bool vjp, bool gradx, bool have_f, bool have_b,
@@ -2931,22 +2934,20 @@ static BwdPlan bwd_plan(int32_t mode, bool has_flip, bool hole, bool vjp, bool g
     const bool end_ok = plain && have_f && have_v && have_status;   // end frame and status of every ray
     P.gfd_saved = P.gfd && plain && have_f && have_b && have_v && (!gradx || end_ok);
     P.gx_saved = gradx && end_ok && (!P.gfd || P.gfd_saved);
-    // pass 1 walks the base geodesic (and GFD's e_perp walk beside it); with the
-    // base's end saved, GFD's three long walks all go to pass 2
+    // one persistent pass walks the long geodesics: the base (unless its end is
+    // the forward's) and, for GFD, the e_perp one and the two start-shifted ones
     P.base_walk = (P.gfd && !P.gfd_saved) || (vjp && has_flip) || (gradx && !P.gx_saved);
-    P.per1 = !P.base_walk ? 0 : (P.gfd ? 2 : 1);
-    P.per2 = P.gfd_saved ? 3 : 2;
+    P.per1 = P.gfd ? (P.gfd_saved ? 3 : 4) : (P.base_walk ? 1 : 0);
     return P;
 }
 
 static BwdLayout bwd_layout(int64_t n, const BwdPlan& P, bool gradx, int64_t n_faces, int32_t gx_records,
                             int walk_blocks) {
-    const bool gfd = P.gfd, walk = P.walk, base_walk = P.base_walk;
+    const bool gfd = P.gfd, walk = P.walk;
     const size_t per1 = P.per1;
     BwdLayout L{};
     size_t o = 0;
-    L.s1 = o; o = align256(o + (base_walk ? per1 * (size_t)n * sizeof(StateRec) : 0));
-    L.s2 = o; o = align256(o + (gfd ? (size_t)P.per2 * n * sizeof(StateRec) : 0));
+    L.s1 = o; o = align256(o + per1 * (size_t)n * sizeof(StateRec));
     L.sh = o; o = align256(o + (gfd ? 3 * (size_t)n * sizeof(StateRec) : 0));
     L.s3 = o; o = align256(o + (gradx ? (size_t)n * sizeof(StateRec) : 0));
     L.cvec = o; o = align256(o + (gradx ? (size_t)n * sizeof(float4) : 0));
@@ -3002,12 +3003,10 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
     if (!(gradx || gfd || (vjp && flip))) return hipGetLastError();
     const BwdPlan P = bwd_plan(a.mode, flip, M.hole_avoid != 0, vjp, gradx, a.f_out != nullptr, a.b_out != nullptr,
                                a.v_out != nullptr, a.status_in != nullptr);
-    const bool base_walk = P.base_walk;
     a.gfd_saved = P.gfd_saved ? 1 : 0;
     const BwdLayout L = bwd_layout(a.n, P, gradx, M.n_faces, a.gx_records, w.blocks);
     char* base = reinterpret_cast<char*>(ws);
     auto* s1 = reinterpret_cast<StateRec*>(base + L.s1);
-    auto* s2 = reinterpret_cast<StateRec*>(base + L.s2);
     auto* sh = gfd ? reinterpret_cast<StateRec*>(base + L.sh) : nullptr;
     auto* s3 = reinterpret_cast<StateRec*>(base + L.s3);
     auto* cvec = reinterpret_cast<float4*>(base + L.cvec);
@@ -3031,13 +3030,19 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
         else if (M.hole_avoid) k_walk_short<false, true><<<g, b, 0, s>>>(M, sh, a.n, first, count, a.max_steps, a.snap);
         else k_walk_short<false, false><<<g, b, 0, s>>>(M, sh, a.n, first, count, a.max_steps, a.snap);
     };
-    // pass 1: the base walk (and, for GFD, the e_perp walk); the two short
-    // start-point steps walk on their own
+    // the long walks' start states (GFD: the two short start-point steps walk
+    // first, one lane each, and the start-shifted long walks begin at their
+    // ends), then one persistent pass over all of them
     const int stride = kLenClasses * ord.sub;
-    if (base_walk || gfd)
-        hipLaunchKernelGGL(k_bwd_stage1, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1, sh, s2);
-    if (gfd) walk_short(0, 2);
-    if (base_walk) {
+    if (per1 > 0) hipLaunchKernelGGL(k_bwd_stage1, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1, sh);
+    if (gfd) {
+        walk_short(0, 2);
+        // with the base's end saved, the e_par step can start now as well
+        hipLaunchKernelGGL(k_bwd_stage2, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1, sh, true,
+                           P.gfd_saved);
+        if (P.gfd_saved) walk_short(2, 1);
+    }
+    if (per1 > 0) {
         hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
         SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)w.blocks), dim3(block), s, M, s1,
                     QueueRanges{cnt, stride, per1}, counter, a.max_steps, a.snap, w.refill_min, w.queues);
@@ -3045,12 +3050,12 @@ hipError_t launch_backward(const DevMesh& M, const BwdArgs& a_in, void* ws, cons
     if (vjp && a.mode == 0 && flip)   // (consistent orientation: k_ep_saved above)
         hipLaunchKernelGGL(k_ep_walked, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1);
     if (gfd) {
-        hipLaunchKernelGGL(k_bwd_stage2, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2, sh);
-        walk_short(2, 1);
-        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
-        SG_DISPATCH(k_walk_bwd, false, flip, dim3((unsigned)w.blocks), dim3(block), s, M, s2,
-                    QueueRanges{cnt, stride, P.per2}, counter, a.max_steps, a.snap, w.refill_min, w.queues);
-        hipLaunchKernelGGL(k_gfd_assemble, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, s2, (const StateRec*)sh);
+        if (!P.gfd_saved) {   // the e_par step from the walked base's end
+            hipLaunchKernelGGL(k_bwd_stage2, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, per1, sh, false,
+                               true);
+            walk_short(2, 1);
+        }
+        hipLaunchKernelGGL(k_gfd_assemble, dim3((unsigned)grid), dim3(block), 0, s, M, a, s1, (const StateRec*)sh);
     }
     if (gradx) {
         const int64_t nacc = 15 * M.n_faces;
