@@ -2899,9 +2899,11 @@ hipError_t launch_exp_partitioned(const DevMesh& M, const ExpArgs& a, void* ws, 
 }
 
 // Backward workspace, carved in this order (each part 256-byte aligned):
-// base-walk states (1 or 4 per query), GFD second-pass states (3 per query),
-// grad-X walk states and adjoint coefficients, grad-X half-edge sums, walk
-// slots and bucket counts, queue counters, then the grad-X records (walk
+// the long-walk states (per1 per query), GFD's short-walk states (3 per
+// query), grad-X walk states and adjoint coefficients, grad-X half-edge sums
+// (15 per face) and per-face corner terms (18 per face), the start terms,
+// their ranks and the per-face query lists (offsets, tile sums, entries),
+// walk slots and bucket counts, queue counters, then the grad-X records (walk
 // order and bin order), the chunk fills and the bin words (nbins + 1 bin
 // totals scanned into starts, chunks used per walk block, the (walk block,
 // bin) count matrix).
