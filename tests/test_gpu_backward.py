@@ -109,6 +109,18 @@ def test_config2_full_batch_sampled(torch, mode, saved):
     check(torch, X, F, r, g, mode, rows=rows, saved=saved)
 
 
+
+@pytest.mark.parametrize("mode,saved", [(0, False), (1, False), (1, True)])
+def test_config5_full_batch_sampled(torch, config5, mode, saved):
+    """Backward over all 16,777,216 rays on the 1,310,720-face noisy mesh (641
+    crossings per ray on average, lengths up to pi); every 512th row vs the
+    oracle.  GFD runs with and without the forward's outputs (its long walks
+    three or four to a query in one pass)."""
+    X, F, r = config5
+    g = CF.upstream_grad(5, r["f"].shape[0])
+    rows = np.arange(0, r["f"].shape[0], 512)
+    check(torch, X, F, r, g, mode, rows=rows, saved=saved, min_margin_rays=600)
+
 @pytest.mark.parametrize("mixed", [False, True])
 def test_gfd_from_saved_forward(torch, mixed):
     """GFD given the forward's f', b', v' and status walks six geodesics per
