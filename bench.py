@@ -13,7 +13,8 @@ The forward + backward forms are timed on the same batch and reported
 beside it; each backward takes the forward's saved outputs: the extrinsic
 proxy walks nothing, geodesic finite differences walk six geodesics per
 query (the base geodesic's end is the forward's), and the float64
-vertex-position gradient adds one adjoint walk.
+vertex-position gradient adds one adjoint walk.  `gfd-no-outputs` times GFD
+without the forward's outputs (seven walks per query).
 
 With the default config the 64-mesh batch (--config 3) is also run, in a
 child process, as HIP-graph replays of one call with the autotuner's
@@ -111,8 +112,9 @@ def main():
                     help="oracle sample size (0: whole batch; 1/4 of it for config 3, 1/64 for config 5)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain kernel for comparison")
     ap.add_argument("--no-bwd", action="store_true", help="skip timing the backward forms")
-    ap.add_argument("--bwd-forms", default="ep,gfd,ep+gradX,gfd+gradX",
-                    help="comma-separated backward forms to time (ep, gfd, ep+gradX, gfd+gradX)")
+    ap.add_argument("--bwd-forms", default="ep,gfd,gfd-no-outputs,ep+gradX,gfd+gradX",
+                    help="comma-separated backward forms to time (ep, gfd, gfd-no-outputs, ep+gradX, gfd+gradX); "
+                         "gfd-no-outputs is GFD without the forward's outputs (it walks the base geodesic too)")
     ap.add_argument("--refill", type=int, default=0, help="persistent kernel refill threshold (0: library default)")
     ap.add_argument("--walk-blocks", type=int, default=0, help="persistent kernel blocks (0: library default, three per CU)")
     ap.add_argument("--queues", type=int, default=0, help="persistent kernel ray queues (0: library default, 8)")
@@ -257,7 +259,8 @@ def main():
         bo = sg.opts(refill_min=base.refill_min if persistent else 0, walk_blocks=base.walk_blocks if persistent else 0)
         want = set(args.bwd_forms.split(","))
         forms = tuple(fm for fm in (("ep", sg.BWD_EP, False), ("gfd", sg.BWD_GFD, False),
-                                    ("ep+gradX", sg.BWD_EP, True), ("gfd+gradX", sg.BWD_GFD, True)) if fm[0] in want)
+                                    ("gfd-no-outputs", sg.BWD_GFD, False), ("ep+gradX", sg.BWD_EP, True),
+                                    ("gfd+gradX", sg.BWD_GFD, True)) if fm[0] in want)
         # The vertex gradient reserves gradx_records records per query (at most 2^30 per call); config 5's
         # 1.1e10 crossings (641 per ray) go through it in slices of 2^20 queries with 800 records each,
         # accumulating into one grad_X.
@@ -268,6 +271,9 @@ def main():
 
             def call():
                 mesh.exp(t["f"], t["b"], t["v"], t["W"], out=out, o=fo)
+                if name == "gfd-no-outputs":
+                    mesh.backward(mode, t["f"], t["b"], t["v"], g_up, out=(gv, gb), o=bo)
+                    return
                 if not with_x:
                     mesh.backward(mode, t["f"], t["b"], t["v"], g_up, f_out=out["f"], b_out=out["b"], v_out=out["v"],
                                   status=out["status"], out=(gv, gb), o=bo)
@@ -328,12 +334,14 @@ def main():
         # faces' vertices) and walks nothing; GFD walks three long geodesics (the e_perp-perturbed
         # one and the two start-shifted ones; the base geodesic is the forward's, and the three
         # short ones cross almost nothing) at 16 B per crossing, with 64 B of chart state in and
-        # out per walk and query; the vertex gradient adds one adjoint walk (16 B per crossing),
-        # the float64 sums (6 per half-edge) and grad_X (24 B per vertex).
+        # out per walk and query (without the forward's outputs it walks the base geodesic as well);
+        # the vertex gradient adds one adjoint walk (16 B per crossing), the float64 sums (6 per
+        # half-edge) and grad_X (24 B per vertex).
         n_he = 3 * int(F_or.shape[0])
         per_q = 152
         algo = {"ep": n * per_q,
-                "gfd": 3 * cross * BYTES_PER_CROSSING + n * (per_q + 6 * 64)}
+                "gfd": 3 * cross * BYTES_PER_CROSSING + n * (per_q + 6 * 64),
+                "gfd-no-outputs": 4 * cross * BYTES_PER_CROSSING + n * (per_q + 7 * 64)}
         gx_extra = cross * BYTES_PER_CROSSING + n * 64 + n_he * 6 * 8 + int(X.shape[0]) * 24
         algo["ep+gradX"] = algo["ep"] + gx_extra
         algo["gfd+gradX"] = algo["gfd"] + gx_extra
