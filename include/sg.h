@@ -252,8 +252,8 @@ int sg_exp_transport_noalloc(sg_mesh mesh, int64_t n, const int32_t* f, const fl
  *        The order of the float64 sums depends on timing, so grad_X's last
  *        bits may differ between calls.
  * Queries the forward rejects (SG_RAY_BADINPUT) get NaN in grad_v, grad_b.
- * Uses a stream-ordered device workspace (GFD 224 bytes per query, a re-walk
- * 32; grad_X 96 per query plus 272 per face plus 48 per record, see
+ * Uses a stream-ordered device workspace (GFD 224 bytes per query, 192 with
+ * the forward's outputs; a re-walk 32; grad_X 96 per query plus 272 per face plus 48 per record, see
  * gradx_records).  opts: max_steps, vertex_snap, eps_v, eps_p, refill_min,
  * walk_blocks, ray_queues, gradx_records are honoured; kernel is ignored (the
  * persistent walk always runs).  n < 2^31 (SG_E_ARG otherwise).
