@@ -71,7 +71,9 @@ enum {
                                angle to it.  Such rays end with SG_RAY_OK when their length is used up. */
 };
 enum {
-    SG_KERNEL_AUTO = 0,         /* = SG_KERNEL_PERSISTENT */
+    SG_KERNEL_AUTO = 0,         /* forward: SG_KERNEL_PLAIN when n fits the persistent walk's resident lanes
+                                   (walk_blocks x 256 x rays_per_lane, 196,608 by default on 256 CUs), else
+                                   SG_KERNEL_PERSISTENT; the backward's walks are always persistent */
     SG_KERNEL_PLAIN = 1,        /* one ray per lane, run to completion (Alg. gpu_parallel) */
     SG_KERNEL_PERSISTENT = 2,   /* persistent waves refilled from ray queues (a share per XCD) */
     SG_KERNEL_PARTITIONED = 3   /* the mesh cut into 8 spatial parts, one per XCD: the walk runs in rounds (one
@@ -194,7 +196,8 @@ int sg_exp_transport(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, 
  *     between them.  The kernels clear what must start at zero; the array
  *     keeps the last call's contents.
  *   - opts->kernel: SG_KERNEL_AUTO / SG_KERNEL_PERSISTENT, or SG_KERNEL_PLAIN
- *     (which needs no scratch); SG_KERNEL_PARTITIONED, opts->workspace != NULL
+ *     (which needs no scratch, as SG_KERNEL_AUTO for a batch that fits the
+ *     resident lanes); SG_KERNEL_PARTITIONED, opts->workspace != NULL
  *     and debug bit 2 (event timing) return SG_E_ARG.
  */
 #define SG_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
@@ -289,7 +292,8 @@ int sg_exp_backward_transport(sg_mesh mesh, int32_t mode, int64_t n, const int32
 /*
  * Device workspace (bytes, host output) that sg_exp / sg_exp_transport need
  * for n queries with K extra vectors (0 for sg_exp) under these options
- * (kernel and debug bits matter), and that
+ * (kernel and debug bits matter; SG_KERNEL_AUTO resolves with this n, so a
+ * batch that fits the resident lanes needs none), and that
  * sg_exp_backward needs for n queries in `mode` with grad_v/grad_b
  * (want_vjp != 0) and/or grad_X (want_grad_X != 0).  0 means none.
  */

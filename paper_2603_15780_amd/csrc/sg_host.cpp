@@ -168,7 +168,7 @@ void free_mesh(sg_mesh_s* m) {
     delete m;
 }
 
-int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
+int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m, int64_t n = -1) {
     sg_opts_default(&o);
     if (in) o = *in;
     if (o.max_steps <= 0) o.max_steps = 1 << 20;
@@ -177,7 +177,6 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     if (!(o.eps_v > 0.f)) o.eps_v = (float)(5e-3 * m->mean_edge);
     if (!(o.eps_p > 0.f)) o.eps_p = (float)(5e-3 * m->mean_edge);
     if (o.kernel < SG_KERNEL_AUTO || o.kernel > SG_KERNEL_PARTITIONED) return fail(SG_E_ARG, "unknown kernel %d", o.kernel);
-    if (o.kernel == SG_KERNEL_AUTO) o.kernel = SG_KERNEL_PERSISTENT;
     if (o.rays_per_lane <= 0) o.rays_per_lane = 1;
     if (o.rays_per_lane > 2) return fail(SG_E_ARG, "rays_per_lane must be 1 or 2");
     if (o.refill_min <= 0) o.refill_min = 48 * o.rays_per_lane;
@@ -193,6 +192,14 @@ int check_opts(const sg_opts* in, sg_opts& o, const sg_mesh_s* m) {
     if (o.walk_blocks <= 0)
         o.walk_blocks = m->cu_count * std::min(3, o.kernel == SG_KERNEL_PARTITIONED ? m->part_blocks_per_cu
                                                                                    : m->walk_blocks_per_cu);
+    // SG_KERNEL_AUTO: a forward batch (n >= 0) that fits the persistent walk's
+    // resident lanes takes the plain kernel: every ray starts at once either way,
+    // so the ordering passes and the queues only add time (65,536 rays on the
+    // 327,680-face mesh: 0.255 against 0.326 ms); larger batches and every
+    // other caller (n < 0) take the persistent walk
+    if (o.kernel == SG_KERNEL_AUTO)
+        o.kernel = n >= 0 && n <= (int64_t)o.walk_blocks * 256 * o.rays_per_lane ? SG_KERNEL_PLAIN
+                                                                               : SG_KERNEL_PERSISTENT;
     return SG_OK;
 }
 
@@ -454,7 +461,7 @@ int exp_args(sg_mesh mesh, int64_t n, const int32_t* f, const float* b, const fl
     if (!mesh) return fail(SG_E_ARG, "mesh is NULL");
     if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
     if (K < 0 || K > 64) return fail(SG_E_ARG, "K must be in [0, 64]");
-    int rc = check_opts(opts, o, mesh);
+    int rc = check_opts(opts, o, mesh, n);
     if (rc != SG_OK) return rc;
     if (n == 0) return SG_OK;
     if (!f || !b || !v || !f_out || !b_out || !p_out || !v_out) return fail(SG_E_ARG, "a required array is NULL");
@@ -1023,7 +1030,7 @@ int sg_exp_workspace_size(sg_mesh mesh, int64_t n, int32_t K, const sg_opts* opt
     if (n < 0) return fail(SG_E_ARG, "n must be >= 0");
     if (K < 0 || K > 64) return fail(SG_E_ARG, "K must be in [0, 64]");
     sg_opts o;
-    int rc = check_opts(opts, o, mesh);
+    int rc = check_opts(opts, o, mesh, n);
     if (rc != SG_OK) return rc;
     *bytes = exp_workspace_bytes(o, n, K);
     return SG_OK;

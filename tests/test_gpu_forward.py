@@ -425,12 +425,15 @@ def test_caller_workspace_and_graph_capture(torch):
     n = r["f"].shape[0]
     gm = sg.Mesh(X, F)
     t = {k: torch.from_numpy(np.ascontiguousarray(r[k])).to(dev) for k in ("f", "b", "v", "W")}
-    o = sg.opts()
+    o = sg.opts(kernel=sg.KERNEL_PERSISTENT)
     K = r["W"].shape[1]
     nb = gm.exp_workspace_size(n, K, o)
-    assert nb > 0 and gm.exp_workspace_size(n, K, sg.opts(kernel=1)) == 0
+    # the plain kernel needs none, and neither does the default choice for a batch within the
+    # persistent walk's resident lanes; a larger batch takes the persistent walk by default
+    assert nb > 0 and gm.exp_workspace_size(n, K, sg.opts(kernel=1)) == 0 and gm.exp_workspace_size(n, K) == 0
+    assert gm.exp_workspace_size(1 << 20, K) == gm.exp_workspace_size(1 << 20, K, o) > 0
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
-    small = sg.opts(workspace=ws.data_ptr(), workspace_bytes=nb - 1)
+    small = sg.opts(kernel=sg.KERNEL_PERSISTENT, workspace=ws.data_ptr(), workspace_bytes=nb - 1)
     with pytest.raises(sg.SgError):
         gm.exp(t["f"], t["b"], t["v"], t["W"], o=small)
     o.workspace, o.workspace_bytes = ws.data_ptr(), nb

@@ -31,8 +31,10 @@ def test_noalloc_matches_workspace_call(cfg, n1, n2):
     print(f"noalloc parity: config {cfg}, n = {n1} then {n2}", flush=True)
     for n in (n1, n2):
         t = _dev(r, n)
-        ref = mesh.exp(t["f"], t["b"], t["v"], t["W"], want_cross=True, want_hash=True)
-        got = mesh.exp(t["f"], t["b"], t["v"], t["W"], want_cross=True, want_hash=True, noalloc=True)
+        # the persistent walk (the default for batches beyond its resident lanes) runs on the scratch
+        kw = dict(kernel=sg.KERNEL_PERSISTENT, want_cross=True, want_hash=True)
+        ref = mesh.exp(t["f"], t["b"], t["v"], t["W"], **kw)
+        got = mesh.exp(t["f"], t["b"], t["v"], t["W"], noalloc=True, **kw)
         torch.cuda.synchronize()
         _same(ref, got)
         assert (got["status"] == sg.RAY_OK).float().mean().item() > 0.99
@@ -53,7 +55,7 @@ def test_noalloc_limits():
         with pytest.raises(sg.SgError) as e:
             mesh.exp(t["f"], t["b"], t["v"], t["W"], noalloc=True, **kw)
         assert e.value.code == sg.SG_E_ARG
-    ws = torch.empty(mesh.exp_workspace_size(64, 2), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(mesh.exp_workspace_size(64, 2, kernel=sg.KERNEL_PERSISTENT), dtype=torch.uint8, device="cuda")
     with pytest.raises(sg.SgError):
         mesh.exp(t["f"], t["b"], t["v"], t["W"], noalloc=True, workspace=ws.data_ptr(), workspace_bytes=ws.numel())
     # a batch beyond the scratch is refused before any launch: the size check
